@@ -1,0 +1,228 @@
+/*
+ * kgf.h -- C ABI of the Krylov-space Green's-function library (libkgf.so).
+ *
+ * Method: Balzer, Gdaniec & Potthoff, "Krylov-space approach to the
+ * equilibrium and the nonequilibrium single-particle Green's function".
+ * All arithmetic runs in hand-written HIP kernels for gfx950 in FP64
+ * (complex128 state vectors).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Model (Sec. 3 Hubbard model, Sec. 4 Anderson model with the field of
+ * Eq. (hfi), written with site-resolved parameters):
+ *     H = - sum_b t_b sum_s (c+_{i_b s} c_{j_b s} + h.c.)
+ *         + sum_{i s} eps_{i s} n_{i s} + sum_i U_i n_{i up} n_{i dn}
+ * Basis of a sector (N_up, N_dn) (occupation-number basis, Sec. 2; N and
+ * S_z conservation, Sec. 4): per spin the L-bit masks with N bits set in
+ * ascending numeric order; a state vector is a D_up x D_dn row-major matrix
+ * (element (u, d) at index u*D_dn + d).  Fermion order: all up modes
+ * before all down modes, sites ascending, bit i = site i.
+ * Orbital codes: alpha = 2*site + spin (spin 0 = up, 1 = down).
+ *
+ * Memory: pointers named host_* are host memory; every other pointer is
+ * device memory on the context's device.  The caller owns all buffers it
+ * passes; the library never frees them.  Buffers must stay valid until the
+ * context's stream has been synchronised.  Handles returned by *_create
+ * are owned by the caller and released with the matching *_destroy.
+ * Calls that write host_* outputs synchronise the stream; the others are
+ * asynchronous on the context's stream.
+ *
+ * Errors: every int-returning call returns KGF_OK (0) or a negative code;
+ * kgf_last_error() then describes the failure (thread-local, valid until
+ * the next call on the same thread).  No exception crosses the ABI.
+ * Threading: one context per host thread.
+ */
+#ifndef KGF_H
+#define KGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KGF_OK            0
+#define KGF_EINVAL       -1   /* bad argument (size, pointer, range, NaN)   */
+#define KGF_ENOMEM       -2   /* device allocation failed or would not fit */
+#define KGF_EHIP         -3   /* HIP runtime error                          */
+#define KGF_ENOCONV      -4   /* ground-state Lanczos did not converge      */
+#define KGF_EUNSUPPORTED -5   /* size outside the supported range          */
+
+/* complex128, interleaved (re, im); layout-compatible with torch.complex128 */
+typedef struct { double re, im; } kgf_c128;
+
+typedef struct kgf_ctx kgf_ctx;
+typedef struct kgf_model kgf_model;
+typedef struct kgf_sector kgf_sector;
+
+/* ---- context ------------------------------------------------------------
+ * kgf_create: bind a context to HIP device `hip_device` and the stream
+ * `hip_stream` (a hipStream_t, borrowed, may be NULL for the null stream).
+ * All kernels of calls on this context are launched on that stream. */
+int  kgf_create(kgf_ctx** out, int hip_device, void* hip_stream);
+void kgf_destroy(kgf_ctx* ctx);
+int  kgf_set_stream(kgf_ctx* ctx, void* hip_stream);
+const char* kgf_last_error(void);
+int  kgf_version(void);
+
+/* ---- model ----------------------------------------------------------------
+ * Parameters of H (see the header comment).  Bonds are undirected; each
+ * bond contributes both hopping directions (Sec. 3 sum over <ij>, Sec. 4
+ * "+ H.c.").  All arrays are host memory and are copied.
+ * Limits: 1 <= L <= 24, 0 <= n_bonds <= 127, 0 <= bond_i, bond_j < L,
+ * bond_i != bond_j, all values finite (KGF_EINVAL / KGF_EUNSUPPORTED). */
+typedef struct {
+    int L;
+    int n_bonds;
+    const int32_t* bond_i;     /* host [n_bonds] */
+    const int32_t* bond_j;     /* host [n_bonds] */
+    const double*  t_bond;     /* host [n_bonds] hopping amplitudes t_b   */
+    const double*  eps_up;     /* host [L] on-site energies, spin up      */
+    const double*  eps_dn;     /* host [L] on-site energies, spin down    */
+    const double*  U;          /* host [L] Hubbard interaction per site   */
+} kgf_model_desc;
+
+int  kgf_model_create(kgf_ctx* ctx, const kgf_model_desc* desc, kgf_model** out);
+void kgf_model_destroy(kgf_model* model);
+
+/* ---- sector basis (Sec. 2 occupation-number basis; Sec. 4 N, S_z) --------
+ * kgf_sector_create builds, on the device, the ascending mask tables of
+ * the (n_up, n_dn) sector of an L-site cluster by unranking the
+ * combinatorial number system (bit-exact integer work). */
+int  kgf_sector_create(kgf_ctx* ctx, int L, int n_up, int n_dn, kgf_sector** out);
+void kgf_sector_destroy(kgf_sector* sector);
+int  kgf_sector_dims(const kgf_sector* sector, int64_t* d_up, int64_t* d_dn);
+/* copy the mask table of one spin (0 up, 1 down) to host [D_spin] */
+int  kgf_sector_states(kgf_ctx* ctx, const kgf_sector* sector, int spin, uint32_t* host_masks);
+/* combinatorial rank of `n` masks (device uint32 in, device int64 out);
+ * masks whose popcount differs from the sector's N_spin give -1. */
+int  kgf_sector_rank(kgf_ctx* ctx, const kgf_sector* sector, int spin,
+                     const uint32_t* masks, int64_t n, int64_t* ranks);
+
+/* ---- hopping table (the single-species hopping matrix of H) ---------------
+ * For the n-particle masks of an L-site model, row r lists the nonzeros of
+ * <s_r| -sum_b t_b (c+_i c_j + c+_j c_i) |s'> as packed uint32 entries
+ *     bits 0..23 column rank, bits 24..30 bond index, bit 31 sign
+ * (value = -t_bond * (sign ? -1 : +1)); ELL layout entry[k*D + r] for
+ * k < count[r] <= width.  Copies to host: count [D], entries [width*D],
+ * *host_width = width.  Used to check the device-built table bit-exactly. */
+int  kgf_hop_table(kgf_ctx* ctx, const kgf_model* model, int n,
+                   int32_t* host_count, uint32_t* host_entries, int* host_width);
+
+/* ---- H.v (Sec. 3 Hubbard H, Sec. 4 SIAM H) --------------------------------
+ * w[c] = H v[c] for nvec vectors in the sector; vector c starts at
+ * v + c*ld (ld >= D, in elements).  v and w must not overlap. */
+int  kgf_apply_h(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                 const kgf_c128* v, kgf_c128* w, int nvec, int64_t ld);
+
+/* ---- c_alpha / c+_alpha (Eqs. (psit), (glesser); Sec. 4 step (iii)) --------
+ * w[c] = c_alpha v[c] (dagger = 0) or c+_alpha v[c] (dagger = 1); v in
+ * `src`, w in `dst`, which must be the sector with one particle of the
+ * orbital's spin less (more).  Fermion sign: (-1)^(occupied modes before
+ * alpha).  w is fully written (zeros where the operator gives nothing). */
+int  kgf_apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst,
+                 int orbital, int dagger, const kgf_c128* v, kgf_c128* w,
+                 int nvec, int64_t ld_src, int64_t ld_dst);
+
+/* ---- ground state (Sec. 2; Sec. 4 step (i)) --------------------------------
+ * Lanczos recursion (Eq. (recursion)) from the start vector v0 with
+ * Gram-Schmidt reorthogonalisation (reorth: 1 classical GS, 2 twice), T_k
+ * diagonalised on the device (Eq. (tdiag)); stops when the Ritz residual
+ * b_{k+1}|y_k| <= tol * max(1, |E0|) (checked every check_every steps) or
+ * at max_iter.  psi0 (device, D) receives the normalised Ritz vector
+ * (Eq. (eigen)).  Returns KGF_ENOCONV (psi0, E0 still written) when not
+ * converged.  Workspace: (max_iter + 1) vectors of D complex128. */
+typedef struct {
+    double tol;
+    int    max_iter;
+    int    check_every;
+    int    reorth;
+} kgf_gs_opts;
+typedef struct {
+    int    iters;
+    int    converged;
+    double residual;
+} kgf_gs_info;
+int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                      const kgf_gs_opts* opts, const kgf_c128* v0, kgf_c128* psi0,
+                      double* host_E0, kgf_gs_info* host_info);
+
+/* ---- short-iterative-Lanczos propagation (Sec. 3, Eqs. (newstate), (udelta))
+ * Each of nvec vectors psi[c] (at psi + c*ld) is advanced nsteps times by
+ *   direction -1: exp(-i H dt);  +1: exp(+i H dt);  0: exp(-(H - shift) dt)
+ * using a Krylov space of dimension krylov_dim (<= 64) rebuilt at every
+ * step (restart), T diagonalised by implicit QL in one wavefront.  The
+ * vectors of a batch run independent recursions (own a_k, b_k, T).
+ * reorth: 0 none, 1 classical GS, 2 classical GS twice.  A recursion
+ * stops early (exactly) when b_{k+1} <= breakdown_tol * max(|a_j|, b_j).
+ * Workspace: krylov_dim * nvec vectors of D complex128. */
+typedef struct {
+    int    krylov_dim;
+    int    reorth;
+    double dt;
+    int    direction;
+    double shift;
+    double breakdown_tol;
+} kgf_prop_opts;
+int  kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                   kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts);
+
+/* ---- equilibrium Green's function (Sec. 3, Eqs. (psit), (psigreen), eta=0)
+ *   G^>_{ij}(t_k) = -i e^{+i E0 t_k} <c+_i 0| e^{-iH t_k} |c+_j 0>
+ *   G^<_{ij}(t_k) = +i e^{-i E0 t_k} <c_j 0| e^{+iH t_k} |c_i 0>
+ * on t_k = k * steps_per_grid * opts->dt, k = 0..nt-1, for the n_orb
+ * orbital codes in host_orbs.  psi0: ground state in `sector` (device).
+ * batch: number of vectors propagated together (0 = all, 1 = one by one).
+ * Outputs host [nt][n_orb][n_orb]; entries between orbitals of different
+ * spin are zero. */
+int  kgf_greens_eq(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                   const kgf_c128* psi0, double E0, const int32_t* host_orbs, int n_orb,
+                   int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch,
+                   kgf_c128* host_G_greater, kgf_c128* host_G_lesser);
+
+/* ---- nonequilibrium Green's function, four-step procedure (Sec. 4) --------
+ * (i)   |0> = ground state of H_ini in `sector` (kgf_ground_state, from v0)
+ * (ii)  Phi(t_k) = e^{-iH t_k}|0>, t_k = k*steps_per_grid*opts->dt
+ * (iii) Psi_a(t_k) = e^{+iH t_k} c_a Phi(t_k), chi_a(t_k) = e^{+iH t_k} c+_a Phi(t_k)
+ * (iv)  G^<_{ab}(t,t') = i <Psi_b(t')|Psi_a(t)>, G^>_{ab}(t,t') = -i <chi_a(t)|chi_b(t')>
+ * schedule 0 ("plain"): step (iii) literally, one backward run per mesh time;
+ * schedule 1 ("sweep"): one backward sweep whose block grows by one column
+ *   per mesh time, dotting with c_b Phi(t_s) on the way (same steps, batched);
+ *   `batch` caps the block width (0 = automatic from free memory).
+ * Optional zero-temperature Matsubara branch (ntau > 0) with H_ini:
+ *   G^M_{ab}(+tau_j) = -<c+_a 0|e^{-(H_ini-E0)tau_j}|c+_b 0>,
+ *   G^M_{ab}(-tau_j) = +<c_b 0|e^{-(H_ini-E0)tau_j}|c_a 0>,
+ *   G^|_{ab}(t_k, tau_j) = i <e^{-(H_ini-E0)tau_j} c_b 0 | Psi_a(t_k)>,
+ *   tau_j = j * tau_steps_per_grid * dtau.
+ * Outputs (host): G_lesser, G_greater [nt][nt][n_orb][n_orb] indexed (t, t');
+ * G_matsubara [2][ntau][n_orb][n_orb] (+tau, -tau) or NULL; G_mixed
+ * [nt][ntau][n_orb][n_orb] or NULL; *host_E0.  If host_psi0_out is not NULL
+ * the device pointer psi0_out (D) receives |0>. */
+int  kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
+                    const kgf_sector* sector, const kgf_gs_opts* gs_opts, const kgf_c128* v0,
+                    const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
+                    const kgf_prop_opts* opts, int schedule, int batch,
+                    int ntau, int tau_steps_per_grid, double dtau,
+                    kgf_c128* host_G_lesser, kgf_c128* host_G_greater,
+                    kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
+                    double* host_E0, kgf_c128* psi0_out);
+
+/* ---- device-side timing of the library's kernels --------------------------
+ * Between kgf_profile_begin and kgf_profile_end every `sample_every`-th
+ * launch of each kernel class is bracketed by HIP events on the context's
+ * stream.  kgf_profile_end synchronises and fills up to max_classes rows:
+ * class name (<= 31 chars), launches, sampled launches, summed sampled
+ * milliseconds.  Returns the number of classes written (>= 0). */
+typedef struct {
+    char   name[32];
+    int64_t launches;
+    int64_t sampled;
+    double sampled_ms;
+} kgf_kernel_stat;
+int  kgf_profile_begin(kgf_ctx* ctx, int sample_every);
+int  kgf_profile_end(kgf_ctx* ctx, kgf_kernel_stat* host_stats, int max_classes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KGF_H */

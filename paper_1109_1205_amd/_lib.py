@@ -1,0 +1,371 @@
+"""ctypes binding of the C ABI declared in include/kgf.h.
+
+Argument marshalling only.  Tensors must be torch.complex128, contiguous,
+on the context's device; they are passed as raw device pointers and the
+library runs on torch's current stream of that device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libkgf.so"
+
+DIRECTION_FORWARD = -1      # exp(-i H dt)
+DIRECTION_BACKWARD = +1     # exp(+i H dt)
+DIRECTION_IMAGINARY = 0     # exp(-(H - shift) dt)
+
+KGF_OK = 0
+_CODES = {-1: "KGF_EINVAL", -2: "KGF_ENOMEM", -3: "KGF_EHIP", -4: "KGF_ENOCONV", -5: "KGF_EUNSUPPORTED"}
+
+
+class KgfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _C128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class _ModelDesc(C.Structure):
+    _fields_ = [("L", C.c_int), ("n_bonds", C.c_int),
+                ("bond_i", C.POINTER(C.c_int32)), ("bond_j", C.POINTER(C.c_int32)),
+                ("t_bond", C.POINTER(C.c_double)), ("eps_up", C.POINTER(C.c_double)),
+                ("eps_dn", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double))]
+
+
+class _GsOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("reorth", C.c_int)]
+
+
+class _GsInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("residual", C.c_double)]
+
+
+class _PropOpts(C.Structure):
+    _fields_ = [("krylov_dim", C.c_int), ("reorth", C.c_int), ("dt", C.c_double),
+                ("direction", C.c_int), ("shift", C.c_double), ("breakdown_tol", C.c_double)]
+
+
+class _KStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("sampled", C.c_int64),
+                ("sampled_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load libkgf.so from the package directory (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1109_1205_amd.build` "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(path)
+    P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "kgf_create": (I, [C.POINTER(P), I, P]),
+        "kgf_destroy": (None, [P]),
+        "kgf_set_stream": (I, [P, P]),
+        "kgf_last_error": (C.c_char_p, []),
+        "kgf_version": (I, []),
+        "kgf_model_create": (I, [P, C.POINTER(_ModelDesc), C.POINTER(P)]),
+        "kgf_model_destroy": (None, [P]),
+        "kgf_sector_create": (I, [P, I, I, I, C.POINTER(P)]),
+        "kgf_sector_destroy": (None, [P]),
+        "kgf_sector_dims": (I, [P, C.POINTER(I64), C.POINTER(I64)]),
+        "kgf_sector_states": (I, [P, P, I, P]),
+        "kgf_sector_rank": (I, [P, P, I, P, I64, P]),
+        "kgf_hop_table": (I, [P, P, I, P, P, C.POINTER(I)]),
+        "kgf_apply_h": (I, [P, P, P, P, P, I, I64]),
+        "kgf_apply_c": (I, [P, P, P, I, I, P, P, I, I64, I64]),
+        "kgf_ground_state": (I, [P, P, P, C.POINTER(_GsOpts), P, P, C.POINTER(D), C.POINTER(_GsInfo)]),
+        "kgf_propagate": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts)]),
+        "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
+        "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
+                               I, I, D, P, P, P, P, C.POINTER(D), P]),
+        "kgf_profile_begin": (I, [P, I]),
+        "kgf_profile_end": (I, [P, C.POINTER(_KStat), I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols() -> Sequence[str]:
+    return ["kgf_create", "kgf_destroy", "kgf_set_stream", "kgf_last_error", "kgf_version",
+            "kgf_model_create", "kgf_model_destroy", "kgf_sector_create", "kgf_sector_destroy",
+            "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
+            "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
+            "kgf_greens_neq", "kgf_profile_begin", "kgf_profile_end"]
+
+
+def _check(rc: int):
+    if rc < 0:
+        msg = _lib.kgf_last_error()
+        raise KgfError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _host_c128(shape):
+    return np.zeros(shape, dtype=np.complex128)
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Model:
+    """Handle of the model parameters (see include/kgf.h)."""
+
+    def __init__(self, ctx: "Context", L: int, bonds, t, eps_up, eps_dn, U):
+        self.ctx = ctx
+        self.L = int(L)
+        b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 2))
+        self._bi = np.ascontiguousarray(b[:, 0])
+        self._bj = np.ascontiguousarray(b[:, 1])
+        self._t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(-1))
+        self._eu = np.ascontiguousarray(np.asarray(eps_up, dtype=np.float64).reshape(-1))
+        self._ed = np.ascontiguousarray(np.asarray(eps_dn, dtype=np.float64).reshape(-1))
+        self._U = np.ascontiguousarray(np.asarray(U, dtype=np.float64).reshape(-1))
+        if not (len(self._eu) == len(self._ed) == len(self._U) == self.L) or len(self._t) != len(self._bi):
+            raise ValueError("model arrays have inconsistent sizes")
+        d = _ModelDesc(self.L, len(self._bi),
+                       self._bi.ctypes.data_as(C.POINTER(C.c_int32)), self._bj.ctypes.data_as(C.POINTER(C.c_int32)),
+                       self._t.ctypes.data_as(C.POINTER(C.c_double)), self._eu.ctypes.data_as(C.POINTER(C.c_double)),
+                       self._ed.ctypes.data_as(C.POINTER(C.c_double)), self._U.ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        _check(_lib.kgf_model_create(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_spec(cls, ctx: "Context", spec) -> "Model":
+        """From any object with L, bonds, t, eps_up, eps_dn, U attributes."""
+        return cls(ctx, spec.L, spec.bonds if len(spec.bonds) else np.zeros((0, 2)), spec.t,
+                   spec.eps_up, spec.eps_dn, spec.U)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.kgf_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sector:
+    """Handle of a (L, N_up, N_dn) sector basis built on the device."""
+
+    def __init__(self, ctx: "Context", L: int, n_up: int, n_dn: int):
+        self.ctx = ctx
+        self.L, self.n_up, self.n_dn = int(L), int(n_up), int(n_dn)
+        h = C.c_void_p()
+        _check(_lib.kgf_sector_create(ctx.handle, self.L, self.n_up, self.n_dn, C.byref(h)))
+        self.handle = h
+        du, dd = C.c_int64(), C.c_int64()
+        _check(_lib.kgf_sector_dims(h, C.byref(du), C.byref(dd)))
+        self.d_up, self.d_dn = du.value, dd.value
+
+    @property
+    def dim(self) -> int:
+        return self.d_up * self.d_dn
+
+    def states(self, spin: int) -> np.ndarray:
+        n = self.d_up if spin == 0 else self.d_dn
+        out = np.zeros(max(n, 1), dtype=np.uint32)
+        _check(_lib.kgf_sector_states(self.ctx.handle, self.handle, int(spin), _np_ptr(out)))
+        return out[:n]
+
+    def rank(self, spin: int, masks) -> "object":
+        """Combinatorial rank of device uint32 masks (torch.int32 tensor
+        reinterpreted) into a device int64 tensor."""
+        import torch
+        out = torch.empty(masks.numel(), dtype=torch.int64, device=masks.device)
+        _check(_lib.kgf_sector_rank(self.ctx.handle, self.handle, int(spin), _ptr(masks), masks.numel(), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.kgf_sector_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol):
+    return _PropOpts(int(krylov_dim), int(reorth), float(dt), int(direction), float(shift), float(breakdown_tol))
+
+
+class Context:
+    """A libkgf context bound to one HIP device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        load_library()
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._stream = stream
+        h = C.c_void_p()
+        _check(_lib.kgf_create(C.byref(h), self.device, C.c_void_p(stream.cuda_stream)))
+        self.handle = h
+
+    # -- handles ---------------------------------------------------------
+    def model(self, spec=None, **kw) -> Model:
+        return Model.from_spec(self, spec) if spec is not None else Model(self, **kw)
+
+    def sector(self, L: int, n_up: int, n_dn: int) -> Sector:
+        return Sector(self, L, n_up, n_dn)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.kgf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tensors ---------------------------------------------------------
+    def _chk(self, t, n: int, name: str):
+        import torch
+        if t.dtype != torch.complex128 or not t.is_cuda or t.device.index != self.device:
+            raise ValueError(f"{name} must be a complex128 tensor on cuda:{self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() % n:
+            raise ValueError(f"{name} has {t.numel()} elements, not a multiple of {n}")
+        return t.numel() // n
+
+    def empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.complex128, device=f"cuda:{self.device}")
+
+    # -- calls -------------------------------------------------------------
+    def hop_table(self, model: Model, n: int):
+        from math import comb
+        D = comb(model.L, n)
+        width = C.c_int()
+        cnt = np.zeros(max(D, 1), dtype=np.int32)
+        ent = np.zeros(max(D * max(len(model._bi), 1), 1), dtype=np.uint32)
+        _check(_lib.kgf_hop_table(self.handle, model.handle, int(n), _np_ptr(cnt), _np_ptr(ent), C.byref(width)))
+        w = width.value
+        return cnt[:D], ent[:D * w].reshape(w, D), w
+
+    def apply_h(self, model: Model, sec: Sector, v, out=None):
+        nvec = self._chk(v, sec.dim, "v")
+        out = self.empty(*v.shape) if out is None else out
+        self._chk(out, sec.dim, "out")
+        _check(_lib.kgf_apply_h(self.handle, model.handle, sec.handle, _ptr(v), _ptr(out), nvec, sec.dim))
+        return out
+
+    def apply_c(self, src: Sector, dst: Sector, site: int, spin: int, dagger: bool, v, out=None):
+        nvec = self._chk(v, src.dim, "v") if src.dim else (v.shape[0] if v.dim() > 1 else 1)
+        shape = (nvec, dst.dim) if v.dim() > 1 else (dst.dim,)
+        out = self.empty(*shape) if out is None else out
+        self._chk(out, dst.dim, "out")
+        _check(_lib.kgf_apply_c(self.handle, src.handle, dst.handle, 2 * int(site) + int(spin), int(bool(dagger)),
+                                _ptr(v), _ptr(out), nvec, max(src.dim, 1), dst.dim))
+        return out
+
+    def ground_state(self, model: Model, sec: Sector, v0, tol=1e-12, max_iter=300, check_every=1, reorth=2,
+                     out=None, allow_unconverged=False):
+        self._chk(v0, sec.dim, "v0")
+        out = self.empty(sec.dim) if out is None else out
+        E0 = C.c_double()
+        info = _GsInfo()
+        rc = _lib.kgf_ground_state(self.handle, model.handle, sec.handle,
+                                   C.byref(_GsOpts(float(tol), int(max_iter), int(check_every), int(reorth))),
+                                   _ptr(v0), _ptr(out), C.byref(E0), C.byref(info))
+        if rc == -4 and allow_unconverged:
+            pass
+        else:
+            _check(rc)
+        return E0.value, out, {"iters": info.iters, "converged": bool(info.converged), "residual": info.residual}
+
+    def propagate(self, model: Model, sec: Sector, psi, nsteps: int, dt: float, krylov_dim: int = 15,
+                  direction: int = DIRECTION_FORWARD, shift: float = 0.0, reorth: int = 0,
+                  breakdown_tol: float = 1e-13):
+        nvec = self._chk(psi, sec.dim, "psi")
+        o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
+        _check(_lib.kgf_propagate(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
+                                  C.byref(o)))
+        return psi
+
+    def greens_eq(self, model: Model, sec: Sector, psi0, E0: float, orbitals: Sequence[Tuple[int, int]],
+                  nt: int, steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0,
+                  batch: int = 0, breakdown_tol: float = 1e-13):
+        self._chk(psi0, sec.dim, "psi0")
+        orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
+        no = len(orbs)
+        Gg = _host_c128((nt, no, no))
+        Gl = _host_c128((nt, no, no))
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        _check(_lib.kgf_greens_eq(self.handle, model.handle, sec.handle, _ptr(psi0), float(E0), _np_ptr(orbs), no,
+                                  int(nt), int(steps_per_grid), C.byref(o), int(batch), _np_ptr(Gg), _np_ptr(Gl)))
+        return Gg, Gl
+
+    def greens_neq(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
+                   steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0, schedule: int = 1,
+                   batch: int = 0, ntau: int = 0, tau_steps_per_grid: int = 1, dtau: float = 0.0,
+                   gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                   breakdown_tol: float = 1e-13, psi0_out=None):
+        self._chk(v0, sec.dim, "v0")
+        if psi0_out is not None:
+            self._chk(psi0_out, sec.dim, "psi0_out")
+        orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
+        no = len(orbs)
+        Gl = _host_c128((nt, nt, no, no))
+        Gg = _host_c128((nt, nt, no, no))
+        GM = _host_c128((2, ntau, no, no)) if ntau > 0 else None
+        Gx = _host_c128((nt, ntau, no, no)) if ntau > 0 else None
+        E0 = C.c_double()
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        _check(_lib.kgf_greens_neq(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
+                                   _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(schedule),
+                                   int(batch), int(ntau), int(tau_steps_per_grid), float(dtau), _np_ptr(Gl),
+                                   _np_ptr(Gg), _np_ptr(GM), _np_ptr(Gx), C.byref(E0), _ptr(psi0_out)))
+        out = {"G_lesser": Gl, "G_greater": Gg, "E0": E0.value}
+        if ntau > 0:
+            out["G_matsubara"] = GM
+            out["G_mixed"] = Gx
+        return out
+
+    def profile_begin(self, sample_every: int = 1):
+        _check(_lib.kgf_profile_begin(self.handle, int(sample_every)))
+
+    def profile_end(self):
+        arr = (_KStat * 64)()
+        n = _check(_lib.kgf_profile_end(self.handle, arr, 64))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "sampled": arr[i].sampled,
+                                       "sampled_ms": arr[i].sampled_ms} for i in range(n)}

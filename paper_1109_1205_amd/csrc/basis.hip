@@ -1,0 +1,182 @@
+// Sector basis of a fixed (N_up, N_dn): per spin the L-bit masks with N
+// set bits in ascending order (occupation-number basis, Sec. 2; N and S_z
+// conservation, Sec. 4).  The position of a mask in that order is its
+// combinatorial rank  sum_k C(p_k, k)  over its set bits p_1 < p_2 < ...,
+// so the table is built by unranking, in parallel, with integer work only.
+#include "kgf_internal.h"
+
+namespace kgf {
+
+int64_t binom_host(int n, int k) {
+    if (k < 0 || n < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+void build_binomials(kgf_ctx* ctx) {
+    std::vector<uint64_t> c(kBinomN * kBinomN, 0);
+    for (int n = 0; n < kBinomN; ++n) {
+        c[n * kBinomN] = 1;
+        for (int k = 1; k <= n; ++k)
+            c[n * kBinomN + k] = c[(n - 1) * kBinomN + k - 1] + (k <= n - 1 ? c[(n - 1) * kBinomN + k] : 0);
+    }
+    ctx->binom.reserve(sizeof(uint64_t) * c.size());
+    KGF_HIP(hipMemcpy(ctx->binom.p, c.data(), sizeof(uint64_t) * c.size(), hipMemcpyHostToDevice));
+}
+
+__device__ __forceinline__ uint64_t binom_at(const uint64_t* C, int n, int k) {
+    return C[n * kBinomN + k];
+}
+
+// rank of a mask among masks of the same popcount (colex = ascending order)
+__device__ __forceinline__ int64_t mask_rank(uint32_t m, const uint64_t* C) {
+    int64_t r = 0;
+    int k = 1;
+    while (m) {
+        int p = __ffs(m) - 1;
+        r += (int64_t)binom_at(C, p, k);
+        ++k;
+        m &= m - 1u;
+    }
+    return r;
+}
+
+__global__ void k_unrank(uint32_t* __restrict__ masks, int64_t D, int L, int N,
+                         const uint64_t* __restrict__ C) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= D) return;
+    uint64_t rem = (uint64_t)r;
+    uint32_t m = 0;
+    int p = L - 1;
+    for (int k = N; k >= 1; --k) {
+        // largest p with C(p, k) <= rem; C(k-1, k) = 0 bounds the search
+        while (binom_at(C, p, k) > rem) --p;
+        m |= 1u << p;
+        rem -= binom_at(C, p, k);
+        --p;
+    }
+    masks[r] = m;
+}
+
+__global__ void k_rank(const uint32_t* __restrict__ masks, int64_t n, int N,
+                       const uint64_t* __restrict__ C, int64_t* __restrict__ ranks) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t m = masks[i];
+    ranks[i] = (__popc(m) == N) ? mask_rank(m, C) : -1;
+}
+
+void build_masks(kgf_ctx* ctx, int L, int n, uint32_t* masks, int64_t D) {
+    if (D == 0) return;
+    int64_t blocks = (D + kThreads - 1) / kThreads;
+    Prof pr(ctx, "sector_unrank");
+    hipLaunchKernelGGL(k_unrank, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream, masks, D, L,
+                       n, ctx->binom.as<uint64_t>());
+    check_launch("k_unrank");
+}
+
+void rank_masks(kgf_ctx* ctx, const uint32_t* masks, int64_t n, int N, int64_t* ranks) {
+    int64_t blocks = (n + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream, masks, n, N,
+                       ctx->binom.as<uint64_t>(), ranks);
+    check_launch("k_rank");
+}
+
+// ---------------------------------------------------------------------------
+// Hopping table of one spin species.  Row r (mask s) lists the masks s'
+// with <s| c+_i c_j |s'> != 0 for a bond (i, j) in either direction: exactly
+// one of sites i, j is occupied in s, s' = s ^ (1<<i) ^ (1<<j).  Moving one
+// fermion past the occupied sites strictly between i and j gives the sign
+// (-1)^popcount(s & between(i, j)).  Entries keep the bond index so that the
+// amplitude (and, for derivatives, the bond) can be looked up.
+// ---------------------------------------------------------------------------
+__global__ void k_hop_table(const uint32_t* __restrict__ masks, int64_t D, int nb,
+                            const int32_t* __restrict__ bi, const int32_t* __restrict__ bj,
+                            const uint64_t* __restrict__ C, int32_t* __restrict__ count,
+                            uint32_t* __restrict__ ent, int width) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= D) return;
+    uint32_t s = masks[r];
+    int c = 0;
+    for (int b = 0; b < nb; ++b) {
+        int i = bi[b], j = bj[b];
+        if ((((s >> i) ^ (s >> j)) & 1u) == 0u) continue;
+        uint32_t s2 = s ^ (1u << i) ^ (1u << j);
+        int lo = i < j ? i : j, hi = i < j ? j : i;
+        uint32_t between = ((1u << hi) - 1u) & ~((2u << lo) - 1u);
+        uint32_t sign = (uint32_t)(__popc(s & between) & 1);
+        uint32_t col = (uint32_t)mask_rank(s2, C);
+        ent[(int64_t)c * D + r] = col | ((uint32_t)b << 24) | (sign << 31);
+        ++c;
+    }
+    count[r] = c;
+    for (int k = c; k < width; ++k) ent[(int64_t)k * D + r] = 0u;
+}
+
+__global__ void k_onsite(const uint32_t* __restrict__ masks, int64_t D, int L,
+                         const double* __restrict__ eu, const double* __restrict__ ed,
+                         double* __restrict__ out_up, double* __restrict__ out_dn) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= D) return;
+    uint32_t s = masks[r];
+    double su = 0.0, sd = 0.0;
+    for (int i = 0; i < L; ++i)
+        if ((s >> i) & 1u) {
+            su += eu[i];
+            sd += ed[i];
+        }
+    out_up[r] = su;
+    out_dn[r] = sd;
+}
+
+HopTable& hop_table(kgf_model* model, int n) {
+    auto it = model->tables.find(n);
+    if (it != model->tables.end()) return *it->second;
+    kgf_ctx* ctx = model->ctx;
+    std::unique_ptr<HopTable> t(new HopTable());
+    t->n = n;
+    t->D = binom_host(model->L, n);
+    t->width = model->nb;
+    KGF_REQUIRE(t->D < (1ll << 24), KGF_EUNSUPPORTED, "hopping table: dimension exceeds 2^24");
+    int64_t D = t->D;
+    t->masks.reserve(sizeof(uint32_t) * (D ? D : 1));
+    t->count.reserve(sizeof(int32_t) * (D ? D : 1));
+    t->ent.reserve(sizeof(uint32_t) * (D * t->width ? D * t->width : 1));
+    t->e_up.reserve(sizeof(double) * (D ? D : 1));
+    t->e_dn.reserve(sizeof(double) * (D ? D : 1));
+    if (D) {
+        build_masks(ctx, model->L, n, t->masks.as<uint32_t>(), D);
+        DevBuf dbi, dbj, deu, ded;
+        dbi.reserve(sizeof(int32_t) * (model->nb ? model->nb : 1));
+        dbj.reserve(sizeof(int32_t) * (model->nb ? model->nb : 1));
+        deu.reserve(sizeof(double) * model->L);
+        ded.reserve(sizeof(double) * model->L);
+        if (model->nb) {
+            KGF_HIP(hipMemcpyAsync(dbi.p, model->bi.data(), sizeof(int32_t) * model->nb,
+                                   hipMemcpyHostToDevice, ctx->stream));
+            KGF_HIP(hipMemcpyAsync(dbj.p, model->bj.data(), sizeof(int32_t) * model->nb,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        }
+        KGF_HIP(hipMemcpyAsync(deu.p, model->eps_up.data(), sizeof(double) * model->L,
+                               hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(ded.p, model->eps_dn.data(), sizeof(double) * model->L,
+                               hipMemcpyHostToDevice, ctx->stream));
+        int64_t blocks = (D + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_hop_table, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream,
+                           t->masks.as<uint32_t>(), D, model->nb, dbi.as<int32_t>(), dbj.as<int32_t>(),
+                           ctx->binom.as<uint64_t>(), t->count.as<int32_t>(), t->ent.as<uint32_t>(),
+                           t->width);
+        check_launch("k_hop_table");
+        hipLaunchKernelGGL(k_onsite, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream,
+                           t->masks.as<uint32_t>(), D, model->L, deu.as<double>(), ded.as<double>(),
+                           t->e_up.as<double>(), t->e_dn.as<double>());
+        check_launch("k_onsite");
+        sync(ctx);   // the temporaries above are freed on return
+    }
+    HopTable& ref = *t;
+    model->tables[n] = std::move(t);
+    return ref;
+}
+
+}  // namespace kgf

@@ -1,0 +1,524 @@
+// Green's-function drivers.
+//
+// Equilibrium (Sec. 3, Eqs. (psit), (psigreen), eta = 0):
+//   G^>_{ij}(t) = -i e^{+iE0 t} <c+_i 0| e^{-iHt} |c+_j 0>,
+//   G^<_{ij}(t) = +i e^{-iE0 t} <c_j 0| e^{+iHt} |c_i 0>.
+// Nonequilibrium four-step procedure (Sec. 4): ground state of H_ini,
+// forward states Phi(t_k), backward-propagated Psi_a(t_k) = e^{iHt_k} c_a Phi(t_k)
+// for every mesh time, scalar products.  Two schedules of step (iii):
+//   plain : each mesh time gets its own backward run (the paper's order);
+//   sweep : G^<_{ab}(t_j, t_s) = i <c_b Phi_s| e^{iH(t_j - t_s)} |c_a Phi_j>
+//           for j >= s, so one backward sweep from t_max to 0 carries a block
+//           of columns X_{a,j}(s) = e^{iH(t_j - t_s)} c_a Phi_j; a column is
+//           injected when the sweep reaches t_j and dotted with c_b Phi_s at
+//           every later mesh time.  Same number of SIL steps, all columns of
+//           the block share every launch.  t_j < t_s follows from
+//           G^<_{ab}(t,t')* = -G^<_{ba}(t',t) (same for G^>).
+#include <algorithm>
+#include <cmath>
+
+#include "kgf_internal.h"
+
+namespace kgf {
+
+namespace {
+
+// out[oo + sum_d i_d * os_d] = pref * (cj ? conj : id)(in[io + sum_d i_d * is_d])
+struct Map4 {
+    int64_t n[4];
+    int64_t is[4];
+    int64_t os[4];
+};
+
+__global__ void k_scatter4(const double2* __restrict__ in, double2* __restrict__ out, Map4 mp,
+                           double pre, double pim, int cj) {
+    const int64_t total = mp.n[0] * mp.n[1] * mp.n[2] * mp.n[3];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = t;
+        int64_t ii = 0, oi = 0;
+        for (int d = 3; d >= 0; --d) {
+            const int64_t q = r % mp.n[d];
+            r /= mp.n[d];
+            ii += q * mp.is[d];
+            oi += q * mp.os[d];
+        }
+        double2 z = in[ii];
+        if (cj) z.y = -z.y;
+        out[oi] = make_double2(pre * z.x - pim * z.y, pre * z.y + pim * z.x);
+    }
+}
+
+void scatter4(kgf_ctx* ctx, const double2* in, double2* out, const Map4& mp, double pre, double pim, bool cj) {
+    const int64_t total = mp.n[0] * mp.n[1] * mp.n[2] * mp.n[3];
+    if (total == 0) return;
+    int64_t blocks = (total + kThreads - 1) / kThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_scatter4, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream, in, out, mp, pre,
+                       pim, cj ? 1 : 0);
+    check_launch("k_scatter4");
+}
+
+// equilibrium: raw[k][i][j] = <X0_i | X_j(t_k)> ->
+//   greater: G[k][I][J] = -i e^{+iE0 t_k} raw;  lesser: G[k][J][I] = +i e^{-iE0 t_k} raw
+__global__ void k_store_eq(const double2* __restrict__ raw, int nt, int na, int nb_r,
+                           const int* __restrict__ gl, const int* __restrict__ gr, int norb,
+                           double E0, double tstep, int greater, double2* __restrict__ G) {
+    const int64_t total = (int64_t)nt * na * nb_r;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(t % nb_r);
+        const int i = (int)((t / nb_r) % na);
+        const int k = (int)(t / ((int64_t)nb_r * na));
+        const double2 z = raw[t];
+        const double tk = tstep * k;
+        double sn, cs;
+        sincos(E0 * tk, &sn, &cs);
+        double2 o;
+        if (greater) {   // -i (cs + i sn) z
+            const double pr = sn, pi = -cs;
+            o = make_double2(pr * z.x - pi * z.y, pr * z.y + pi * z.x);
+            G[((int64_t)k * norb + gl[i]) * norb + gr[j]] = o;
+        } else {         // +i (cs - i sn) z
+            const double pr = sn, pi = cs;
+            o = make_double2(pr * z.x - pi * z.y, pr * z.y + pi * z.x);
+            G[((int64_t)k * norb + gr[j]) * norb + gl[i]] = o;
+        }
+    }
+}
+
+// four-step: raw(s, b, a, j) = <X_b(s) | X_a(j)> with X = c Phi or c+ Phi
+// propagated so that the product is <c_b Phi_s| e^{iH(t_j - t_s)} |c_a Phi_j>.
+//   lesser : G[j][s][A][B] = +i raw(s, b, a, j)
+//   greater: G[j][s][A][B] = -i conj(raw(s, b, a, j))
+// half = 1: only j >= s is stored in raw; j < s from G_{AB}(t_j,t_s) = -conj G_{BA}(t_s,t_j)
+__global__ void k_store_neq(const double2* __restrict__ raw, int64_t ss, int64_t sb, int64_t sa,
+                            int64_t sj, int nt, int na, const int* __restrict__ gidx, int norb,
+                            int greater, int half, double2* __restrict__ G) {
+    const int64_t total = (int64_t)nt * nt * na * na;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % na);
+        const int a = (int)((t / na) % na);
+        const int s = (int)((t / ((int64_t)na * na)) % nt);
+        const int j = (int)(t / ((int64_t)na * na * nt));
+        bool flip = half && j < s;
+        double2 z;
+        if (!flip)
+            z = raw[s * ss + b * sb + a * sa + j * sj];
+        else
+            z = raw[j * ss + a * sb + b * sa + s * sj];
+        double2 g;
+        if (greater)
+            g = make_double2(-z.y, -z.x);    // -i conj(z)
+        else
+            g = make_double2(-z.y, z.x);     // +i z
+        if (flip) g = make_double2(-g.x, g.y);   // -conj(g)
+        G[(((int64_t)j * nt + s) * norb + gidx[a]) * norb + gidx[b]] = g;
+    }
+}
+
+// sweep bookkeeping: tmp[b][r] for b < nleft, r < ncur, where column
+// r = (jhi - j) * nq + q holds orbital q injected at mesh time j
+//   -> raw[base + b * sb + q * sa + j * sj]
+__global__ void k_place(const double2* __restrict__ tmp, int nleft, int nq, int ncur, int jhi,
+                        double2* __restrict__ raw, int64_t base, int64_t sb, int64_t sa, int64_t sj) {
+    const int64_t total = (int64_t)nleft * ncur;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(t % ncur);
+        const int b = (int)(t / ncur);
+        const int j = jhi - r / nq, q = r % nq;
+        raw[base + b * sb + q * sa + j * sj] = tmp[t];
+    }
+}
+
+void place(kgf_ctx* ctx, const double2* tmp, int nleft, int nq, int ncur, int jhi, double2* raw, int64_t base,
+           int64_t sb, int64_t sa, int64_t sj) {
+    const int64_t total = (int64_t)nleft * ncur;
+    if (!total) return;
+    hipLaunchKernelGGL(k_place, dim3((unsigned)std::min<int64_t>((total + kThreads - 1) / kThreads, 1024)),
+                       dim3(kThreads), 0, ctx->stream, tmp, nleft, nq, ncur, jhi, raw, base, sb, sa, sj);
+    check_launch("k_place");
+}
+
+// mixed component: rawm[(b * ntau + jt) * (na * nt) + a * nt + k] -> Gmix[k][jt][A][B] = i rawm
+void store_mixed(kgf_ctx* ctx, const double2* rawm, const std::vector<int>& loc, int nt, int ntau, int norb,
+                 double2* Gmix) {
+    const int na = (int)loc.size();
+    for (int a = 0; a < na; ++a)
+        for (int b = 0; b < na; ++b) {
+            Map4 m2;
+            m2.n[0] = 1; m2.n[1] = ntau; m2.n[2] = 1; m2.n[3] = nt;
+            m2.is[0] = 0; m2.is[1] = (int64_t)na * nt; m2.is[2] = 0; m2.is[3] = 1;
+            m2.os[0] = 0; m2.os[1] = (int64_t)norb * norb; m2.os[2] = 0; m2.os[3] = (int64_t)ntau * norb * norb;
+            const double2* in = rawm + (int64_t)b * ntau * na * nt + (int64_t)a * nt;
+            double2* out = Gmix + (int64_t)loc[a] * norb + loc[b];
+            scatter4(ctx, in, out, m2, 0.0, 1.0, false);
+        }
+}
+
+std::unique_ptr<kgf_sector> make_sector(kgf_ctx* ctx, int L, int nu, int nd) {
+    if (nu < 0 || nu > L || nd < 0 || nd > L) return nullptr;
+    std::unique_ptr<kgf_sector> s(new kgf_sector());
+    s->ctx = ctx;
+    s->L = L;
+    s->n_up = nu;
+    s->n_dn = nd;
+    s->d_up = binom_host(L, nu);
+    s->d_dn = binom_host(L, nd);
+    s->masks_up.reserve(sizeof(uint32_t) * s->d_up);
+    s->masks_dn.reserve(sizeof(uint32_t) * s->d_dn);
+    build_masks(ctx, L, nu, s->masks_up.as<uint32_t>(), s->d_up);
+    build_masks(ctx, L, nd, s->masks_dn.as<uint32_t>(), s->d_dn);
+    return s;
+}
+
+std::unique_ptr<kgf_sector> shifted(kgf_ctx* ctx, const kgf_sector* sec, int spin, int delta) {
+    return make_sector(ctx, sec->L, sec->n_up + (spin == 0 ? delta : 0), sec->n_dn + (spin == 1 ? delta : 0));
+}
+
+void upload_ints(kgf_ctx* ctx, DevBuf& buf, const std::vector<int>& v) {
+    buf.reserve(sizeof(int) * (v.empty() ? 1 : v.size()));
+    if (!v.empty()) KGF_HIP(hipMemcpy(buf.p, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+}
+
+void release(kgf_ctx* ctx, const char* name) {
+    auto it = ctx->ws.find(name);
+    if (it != ctx->ws.end()) {
+        sync(ctx);
+        ctx->ws.erase(it);
+    }
+}
+
+}  // namespace
+
+void greens_eq(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0, double E0,
+               const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch,
+               double2* Gg_host, double2* Gl_host) {
+    const size_t gsz = sizeof(double2) * (size_t)nt * norb * norb;
+    double2* Gdev = static_cast<double2*>(workspace(ctx, "geq_G", 2 * gsz));
+    KGF_HIP(hipMemsetAsync(Gdev, 0, 2 * gsz, ctx->stream));
+    const double tstep = spg * o.dt;
+    for (int spin = 0; spin < 2; ++spin) {
+        std::vector<int> loc;
+        for (int a = 0; a < norb; ++a)
+            if ((orbs[a] & 1) == spin) loc.push_back(a);
+        const int na = (int)loc.size();
+        if (!na) continue;
+        for (int greater = 1; greater >= 0; --greater) {
+            auto tgt = shifted(ctx, sec, spin, greater ? +1 : -1);
+            if (!tgt || tgt->dim() == 0) continue;
+            const int64_t Dt = tgt->dim();
+            double2* X0 = static_cast<double2*>(workspace(ctx, "geq_X0", sizeof(double2) * na * Dt));
+            double2* Xt = static_cast<double2*>(workspace(ctx, "geq_Xt", sizeof(double2) * na * Dt));
+            double2* raw = static_cast<double2*>(workspace(ctx, "geq_raw", sizeof(double2) * (size_t)nt * na * na));
+            for (int q = 0; q < na; ++q)
+                apply_c(ctx, sec, tgt.get(), orbs[loc[q]], greater, psi0, X0 + q * Dt, 1, sec->dim(), Dt);
+            KGF_HIP(hipMemcpyAsync(Xt, X0, sizeof(double2) * na * Dt, hipMemcpyDeviceToDevice, ctx->stream));
+            SilOpts so = o;
+            so.direction = greater ? -1 : +1;
+            const int B = (batch <= 0 || batch > na) ? na : batch;
+            for (int c0 = 0; c0 < na; c0 += B) {
+                const int nc = std::min(B, na - c0);
+                for (int k = 0; k < nt; ++k) {
+                    if (k > 0) sil_propagate(ctx, model, tgt.get(), Xt + c0 * Dt, nc, Dt, spg, so);
+                    // raw[k][i][c0 + j] = <X0_i | Xt_j>
+                    block_dots(ctx, X0, Dt, na, Xt + c0 * Dt, Dt, nc, Dt, raw + (size_t)k * na * na + c0, na);
+                }
+            }
+            DevBuf gl;
+            upload_ints(ctx, gl, loc);
+            int64_t total = (int64_t)nt * na * na;
+            int64_t blocks = std::min<int64_t>((total + kThreads - 1) / kThreads, 4096);
+            hipLaunchKernelGGL(k_store_eq, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream, raw, nt, na, na,
+                               gl.as<int>(), gl.as<int>(), norb, E0, tstep, greater,
+                               Gdev + (greater ? 0 : (size_t)nt * norb * norb));
+            check_launch("k_store_eq");
+            sync(ctx);
+        }
+    }
+    if (Gg_host) KGF_HIP(hipMemcpyAsync(Gg_host, Gdev, gsz, hipMemcpyDeviceToHost, ctx->stream));
+    if (Gl_host)
+        KGF_HIP(hipMemcpyAsync(Gl_host, Gdev + (size_t)nt * norb * norb, gsz, hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+}
+
+struct NeqArgs {
+    kgf_model* H_ini;
+    kgf_model* H;
+    const kgf_sector* sec;
+    const int32_t* orbs;
+    int norb, nt, spg;
+    SilOpts o;
+    int schedule, batch;
+    int ntau, tspg;
+    double dtau;
+};
+
+// step (iii)+(iv) for one spin group and one operator (c or c+);
+// also the mixed component when `mixed_dev` is given (lesser only).
+static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& loc, int spin, int dagger,
+                       const double2* Phi, double2* Gdev, const double2* hole_states, const kgf_sector* hole_sec,
+                       double2* Gmix_dev) {
+    const kgf_sector* sec = A.sec;
+    auto tgt = shifted(ctx, sec, spin, dagger ? +1 : -1);
+    if (!tgt || tgt->dim() == 0) return;
+    const int64_t D = sec->dim();
+    const int64_t Dt = tgt->dim();
+    const int na = (int)loc.size();
+    const int nt = A.nt;
+    SilOpts so = A.o;
+    so.direction = +1;   // e^{+iH dt}
+    DevBuf gidx;
+    upload_ints(ctx, gidx, loc);
+    double2* raw = static_cast<double2*>(workspace(ctx, "neq_raw", sizeof(double2) * (size_t)nt * nt * na * na));
+    KGF_HIP(hipMemsetAsync(raw, 0, sizeof(double2) * (size_t)nt * nt * na * na, ctx->stream));
+    const bool want_mixed = (Gmix_dev != nullptr && !dagger && A.ntau > 0 && hole_states);
+    double2* rawm = nullptr;
+    if (want_mixed)
+        rawm = static_cast<double2*>(workspace(ctx, "neq_rawm", sizeof(double2) * (size_t)na * A.ntau * na * nt));
+
+    if (A.schedule == 0) {
+        // literal: Psi_a(t_k) for every mesh time, then all scalar products
+        const size_t bytes = sizeof(double2) * (size_t)na * nt * Dt;
+        ensure_device_fits(bytes, "four-step (plain) state mesh");
+        double2* Psi = static_cast<double2*>(workspace(ctx, "neq_psi", bytes));
+        for (int q = 0; q < na; ++q)
+            for (int k = 0; k < nt; ++k) {
+                double2* x = Psi + ((size_t)q * nt + k) * Dt;
+                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, x, 1, D, Dt);
+                if (k > 0) sil_propagate(ctx, A.H, tgt.get(), x, 1, Dt, k * A.spg, so);
+            }
+        // raw layout [b][s][a][j] = <Psi_b(s) | Psi_a(j)>
+        block_dots(ctx, Psi, Dt, na * nt, Psi, Dt, na * nt, Dt, raw, (int64_t)na * nt);
+        const int64_t ss = na * nt, sb = (int64_t)nt * na * nt, sa = nt, sj = 1;
+        int64_t total = (int64_t)nt * nt * na * na;
+        hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(kThreads), 0,
+                           ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), A.norb, dagger, 0, Gdev);
+        check_launch("k_store_neq");
+        if (want_mixed) {
+            // rawm[(b, jt)][(a, k)] = <hole_b(tau_jt) | Psi_a(t_k)>
+            block_dots(ctx, hole_states, Dt, na * A.ntau, Psi, Dt, na * nt, Dt, rawm, (int64_t)na * nt);
+            store_mixed(ctx, rawm, loc, nt, A.ntau, A.norb, Gmix_dev);
+        }
+        sync(ctx);
+        release(ctx, "neq_psi");
+        return;
+    }
+
+    // sweep schedule
+    const size_t per_col = sizeof(double2) * (size_t)(A.o.m + 1) * Dt;
+    int Bcols = A.batch;
+    if (Bcols <= 0) {
+        size_t free_b = 0, total_b = 0;
+        KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+        size_t budget = (size_t)(0.80 * (double)free_b);
+        Bcols = (int)std::max<size_t>(1, budget / per_col);
+    }
+    int jchunk = std::max(1, Bcols / na);
+    jchunk = std::min(jchunk, nt);
+    const int maxcols = jchunk * na;
+    ensure_device_fits(sizeof(double2) * (size_t)maxcols * Dt, "four-step sweep block");
+    double2* S = static_cast<double2*>(workspace(ctx, "neq_cols", sizeof(double2) * (size_t)maxcols * Dt));
+    double2* Lb = static_cast<double2*>(workspace(ctx, "neq_left", sizeof(double2) * (size_t)na * Dt));
+    // raw layout [s][b][a][j]
+    const int64_t ss = (int64_t)na * na * nt, sb = (int64_t)na * nt, sa = nt, sj = 1;
+    double2* tmp = static_cast<double2*>(workspace(ctx, "neq_tmp", sizeof(double2) * (size_t)na * maxcols));
+    for (int jhi = nt - 1; jhi >= 0; jhi -= jchunk) {
+        const int jlo = std::max(0, jhi - jchunk + 1);
+        // column r = (jhi - j) * na + q holds X_{q, j}
+        int ncur = 0;
+        for (int s = jhi; s >= 0; --s) {
+            if (s >= jlo) {
+                for (int q = 0; q < na; ++q)
+                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)s * D, S + (size_t)(ncur + q) * Dt,
+                            1, D, Dt);
+                ncur += na;
+            }
+            for (int q = 0; q < na; ++q)
+                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)s * D, Lb + (size_t)q * Dt, 1, D, Dt);
+            // tmp[b][r] = <c_b Phi_s | X_r>
+            block_dots(ctx, Lb, Dt, na, S, Dt, ncur, Dt, tmp, ncur);
+            place(ctx, tmp, na, na, ncur, jhi, raw, s * ss, sb, sa, sj);
+            if (s > 0) sil_propagate(ctx, A.H, tgt.get(), S, ncur, Dt, A.spg, so);
+        }
+        if (want_mixed) {
+            // columns now hold Psi_a(t_j) for j in [jlo, jhi]; tmpm[(b, jt)][r]
+            double2* tmpm = static_cast<double2*>(workspace(ctx, "neq_tmpm", sizeof(double2) * (size_t)na * A.ntau * ncur));
+            block_dots(ctx, hole_states, Dt, na * A.ntau, S, Dt, ncur, Dt, tmpm, ncur);
+            // rawm layout [(b, jt)][a][k]: treat (b, jt) as the "left" index of place()
+            place(ctx, tmpm, na * A.ntau, na, ncur, jhi, rawm, 0, (int64_t)na * nt, nt, 1);
+        }
+    }
+    int64_t total = (int64_t)nt * nt * na * na;
+    hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(kThreads), 0,
+                       ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), A.norb, dagger, 1, Gdev);
+    check_launch("k_store_neq");
+    if (want_mixed) store_mixed(ctx, rawm, loc, nt, A.ntau, A.norb, Gmix_dev);
+    sync(ctx);
+}
+
+void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso, double* E0_out,
+                double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host) {
+    const kgf_sector* sec = A.sec;
+    const int64_t D = sec->dim();
+    const int nt = A.nt, norb = A.norb;
+    // (i) ground state of H_ini
+    double2* psi0 = static_cast<double2*>(workspace(ctx, "neq_psi0", sizeof(double2) * D));
+    GsResult gs = ground_state(ctx, A.H_ini, sec, v0, psi0, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
+    release(ctx, "gs_V");
+    release(ctx, "gs_partbig");
+    KGF_REQUIRE(gs.converged, KGF_ENOCONV, "four-step: ground state of H_ini did not converge");
+    const double E0 = gs.E0;
+    *E0_out = E0;
+    if (psi0_out)
+        KGF_HIP(hipMemcpyAsync(psi0_out, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    // (ii) forward states on the mesh
+    ensure_device_fits(sizeof(double2) * (size_t)nt * D, "four-step forward mesh");
+    double2* Phi = static_cast<double2*>(workspace(ctx, "neq_phi", sizeof(double2) * (size_t)nt * D));
+    KGF_HIP(hipMemcpyAsync(Phi, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    SilOpts fo = A.o;
+    fo.direction = -1;
+    for (int k = 1; k < nt; ++k) {
+        KGF_HIP(hipMemcpyAsync(Phi + (size_t)k * D, Phi + (size_t)(k - 1) * D, sizeof(double2) * D,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        sil_propagate(ctx, A.H, sec, Phi + (size_t)k * D, 1, D, A.spg, fo);
+    }
+    const size_t gsz = sizeof(double2) * (size_t)nt * nt * norb * norb;
+    double2* Gl = static_cast<double2*>(workspace(ctx, "neq_Gl", gsz));
+    double2* Gg = static_cast<double2*>(workspace(ctx, "neq_Gg", gsz));
+    KGF_HIP(hipMemsetAsync(Gl, 0, gsz, ctx->stream));
+    KGF_HIP(hipMemsetAsync(Gg, 0, gsz, ctx->stream));
+    const bool matsubara = A.ntau > 0 && (GM_host || Gmix_host);
+    const size_t gmsz = sizeof(double2) * 2 * (size_t)std::max(A.ntau, 1) * norb * norb;
+    const size_t gxsz = sizeof(double2) * (size_t)nt * std::max(A.ntau, 1) * norb * norb;
+    double2* GM = static_cast<double2*>(workspace(ctx, "neq_GM", gmsz));
+    double2* Gx = static_cast<double2*>(workspace(ctx, "neq_Gx", gxsz));
+    KGF_HIP(hipMemsetAsync(GM, 0, gmsz, ctx->stream));
+    KGF_HIP(hipMemsetAsync(Gx, 0, gxsz, ctx->stream));
+    SilOpts io = A.o;
+    io.direction = 0;
+    io.shift = E0;
+    io.dt = A.dtau;
+    for (int spin = 0; spin < 2; ++spin) {
+        std::vector<int> loc;
+        for (int a = 0; a < norb; ++a)
+            if ((A.orbs[a] & 1) == spin) loc.push_back(a);
+        const int na = (int)loc.size();
+        if (!na) continue;
+        // Matsubara branch with H_ini: particle (c+) and hole (c) states on the tau mesh
+        std::unique_ptr<kgf_sector> hole_sec;
+        double2* hole = nullptr;
+        if (matsubara) {
+            for (int part = 0; part < 2; ++part) {   // part 0: particle (c+), 1: hole (c)
+                auto ts = shifted(ctx, sec, spin, part == 0 ? +1 : -1);
+                if (!ts || ts->dim() == 0) continue;
+                const int64_t Dt = ts->dim();
+                const size_t bytes = sizeof(double2) * (size_t)na * A.ntau * Dt;
+                ensure_device_fits(bytes, "Matsubara mesh");
+                double2* P = static_cast<double2*>(workspace(ctx, part == 0 ? "neq_mats_p" : "neq_mats_h", bytes));
+                double2* X0 = static_cast<double2*>(workspace(ctx, "neq_mats_x0", sizeof(double2) * na * Dt));
+                for (int q = 0; q < na; ++q) {
+                    apply_c(ctx, sec, ts.get(), A.orbs[loc[q]], part == 0 ? 1 : 0, psi0, X0 + q * Dt, 1, D, Dt);
+                    KGF_HIP(hipMemcpyAsync(P + (size_t)q * A.ntau * Dt, X0 + q * Dt, sizeof(double2) * Dt,
+                                           hipMemcpyDeviceToDevice, ctx->stream));
+                    for (int j = 1; j < A.ntau; ++j) {
+                        double2* x = P + ((size_t)q * A.ntau + j) * Dt;
+                        KGF_HIP(hipMemcpyAsync(x, x - Dt, sizeof(double2) * Dt, hipMemcpyDeviceToDevice, ctx->stream));
+                        sil_propagate(ctx, A.H_ini, ts.get(), x, 1, Dt, A.tspg, io);
+                    }
+                }
+                // rawp[l][(b, j)] = <X0_l | P_b(tau_j)>
+                double2* rawp = static_cast<double2*>(workspace(ctx, "neq_rawp", sizeof(double2) * (size_t)na * na * A.ntau));
+                block_dots(ctx, X0, Dt, na, P, Dt, na * A.ntau, Dt, rawp, (int64_t)na * A.ntau);
+                for (int l = 0; l < na; ++l)
+                    for (int b = 0; b < na; ++b) {
+                        Map4 m2;
+                        m2.n[0] = 1; m2.n[1] = 1; m2.n[2] = 1; m2.n[3] = A.ntau;
+                        m2.is[0] = m2.is[1] = m2.is[2] = 0; m2.is[3] = 1;
+                        m2.os[0] = m2.os[1] = m2.os[2] = 0; m2.os[3] = (int64_t)norb * norb;
+                        const double2* in = rawp + ((size_t)l * na + b) * A.ntau;
+                        if (part == 0) {   // G^M(+tau)[j][A=l][B=b] = -<c+_A 0|P_B>
+                            double2* out = GM + (int64_t)loc[l] * norb + loc[b];
+                            scatter4(ctx, in, out, m2, -1.0, 0.0, false);
+                        } else {           // G^M(-tau)[j][A=b][B=l] = <c_B 0| H_A>
+                            double2* out = GM + (size_t)A.ntau * norb * norb + (int64_t)loc[b] * norb + loc[l];
+                            scatter4(ctx, in, out, m2, 1.0, 0.0, false);
+                        }
+                    }
+                sync(ctx);
+                if (part == 1) {
+                    hole = P;
+                    hole_sec = std::move(ts);
+                }
+            }
+        }
+        for (int dagger = 0; dagger < 2; ++dagger)
+            neq_branch(ctx, A, loc, spin, dagger, Phi, dagger ? Gg : Gl, hole, hole_sec.get(),
+                       (matsubara && Gmix_host) ? Gx : nullptr);
+        release(ctx, "neq_mats_p");
+        release(ctx, "neq_mats_h");
+    }
+    if (Gl_host) KGF_HIP(hipMemcpyAsync(Gl_host, Gl, gsz, hipMemcpyDeviceToHost, ctx->stream));
+    if (Gg_host) KGF_HIP(hipMemcpyAsync(Gg_host, Gg, gsz, hipMemcpyDeviceToHost, ctx->stream));
+    if (matsubara && GM_host)
+        KGF_HIP(hipMemcpyAsync(GM_host, GM, sizeof(double2) * 2 * (size_t)A.ntau * norb * norb,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    if (matsubara && Gmix_host)
+        KGF_HIP(hipMemcpyAsync(Gmix_host, Gx, sizeof(double2) * (size_t)nt * A.ntau * norb * norb,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    release(ctx, "neq_phi");
+    release(ctx, "neq_cols");
+    release(ctx, "sil_X");
+}
+
+}  // namespace kgf
+
+using namespace kgf;
+
+extern "C" int kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
+                              const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
+                              int nt, int steps_per_grid, const kgf_prop_opts* opts, int schedule, int batch,
+                              int ntau, int tau_steps_per_grid, double dtau, kgf_c128* host_G_lesser,
+                              kgf_c128* host_G_greater, kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
+                              double* host_E0, kgf_c128* psi0_out) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(ctx && H_ini && H && sector && gs_opts && v0 && host_orbs && host_E0, KGF_EINVAL,
+                    "kgf_greens_neq: NULL argument");
+        KGF_REQUIRE(H_ini->L == sector->L && H->L == sector->L, KGF_EINVAL,
+                    "kgf_greens_neq: models and sector differ in L");
+        KGF_REQUIRE(sector->dim() > 0, KGF_EINVAL, "kgf_greens_neq: empty sector");
+        kgf::check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && (schedule == 0 || schedule == 1) && batch >= 0,
+                    KGF_EINVAL, "kgf_greens_neq: bad sizes");
+        KGF_REQUIRE(ntau >= 0 && (ntau == 0 || (tau_steps_per_grid >= 1 && std::isfinite(dtau) && dtau >= 0.0)),
+                    KGF_EINVAL, "kgf_greens_neq: bad Matsubara mesh");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                    KGF_EINVAL, "kgf_greens_neq: bad ground-state options");
+        for (int a = 0; a < n_orb; ++a)
+            KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
+                        "kgf_greens_neq: orbital out of range");
+        KGF_HIP(hipSetDevice(ctx->device));
+        NeqArgs A;
+        A.H_ini = const_cast<kgf_model*>(H_ini);
+        A.H = const_cast<kgf_model*>(H);
+        A.sec = sector;
+        A.orbs = host_orbs;
+        A.norb = n_orb;
+        A.nt = nt;
+        A.spg = steps_per_grid;
+        A.o = kgf::to_sil_opts(opts);
+        A.schedule = schedule;
+        A.batch = batch;
+        A.ntau = ntau;
+        A.tspg = tau_steps_per_grid;
+        A.dtau = dtau;
+        greens_neq(ctx, A, reinterpret_cast<const double2*>(v0), gs_opts, host_E0,
+                   reinterpret_cast<double2*>(psi0_out), reinterpret_cast<double2*>(host_G_lesser),
+                   reinterpret_cast<double2*>(host_G_greater), reinterpret_cast<double2*>(host_G_matsubara),
+                   reinterpret_cast<double2*>(host_G_mixed));
+    });
+}

@@ -1,0 +1,210 @@
+// Internal declarations of libkgf (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kgf.h"
+
+namespace kgf {
+
+// Internal failures travel as exceptions and are turned into return codes
+// at the ABI boundary (api.hip); none crosses the C interface.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define KGF_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess)                                                  \
+            ::kgf::fail(KGF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define KGF_REQUIRE(cond, code, msg)                                           \
+    do {                                                                       \
+        if (!(cond)) ::kgf::fail((code), (msg));                               \
+    } while (0)
+
+constexpr int kMaxL = 24;          // masks are uint32; column ranks need 24 bits
+constexpr int kMaxBonds = 127;     // bond index stored in 7 bits
+constexpr int kMaxKrylov = 64;     // SIL Krylov dimension (one wavefront)
+constexpr int kBinomN = 33;        // binomial table C[n][k], n,k < 33
+constexpr int kThreads = 256;      // threads per block of the streaming kernels
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void reserve(size_t n);          // discards contents when it grows
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-spin tables of one particle number n for one model (hopping matrix
+// in ELL layout plus the on-site energy of each mask for either spin).
+struct HopTable {
+    int n = 0;
+    int64_t D = 0;
+    int width = 0;
+    DevBuf masks;    // uint32 [D]
+    DevBuf count;    // int32  [D]
+    DevBuf ent;      // uint32 [width * D]
+    DevBuf e_up;     // double [D]  sum_i eps_up[i] bit_i
+    DevBuf e_dn;     // double [D]  sum_i eps_dn[i] bit_i
+};
+
+struct KernelStat {
+    int64_t launches = 0;
+    int64_t sampled = 0;
+    double ms = 0.0;
+};
+
+}  // namespace kgf
+
+struct kgf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    kgf::DevBuf binom;                       // uint64 [kBinomN * kBinomN]
+    std::map<std::string, std::unique_ptr<kgf::DevBuf>> ws;
+    // profiling
+    bool prof_on = false;
+    int prof_every = 1;
+    std::map<std::string, kgf::KernelStat> prof;
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    // pinned host scratch for scalar readbacks
+    void* host_scratch = nullptr;
+    size_t host_scratch_bytes = 0;
+};
+
+struct kgf_model {
+    kgf_ctx* ctx = nullptr;
+    int L = 0;
+    int nb = 0;
+    std::vector<int32_t> bi, bj;
+    std::vector<double> t, eps_up, eps_dn, U;
+    bool U_uniform = true;
+    kgf::DevBuf d_t;       // double [nb]  hopping amplitudes
+    kgf::DevBuf d_Utab;    // double [3 * 256] sum of U_i over the set bits of each mask byte
+    std::map<int, std::unique_ptr<kgf::HopTable>> tables;
+};
+
+struct kgf_sector {
+    kgf_ctx* ctx = nullptr;
+    int L = 0, n_up = 0, n_dn = 0;
+    int64_t d_up = 0, d_dn = 0;
+    kgf::DevBuf masks_up, masks_dn;   // uint32
+    int64_t dim() const { return d_up * d_dn; }
+};
+
+namespace kgf {
+
+// ---- context helpers (api.hip) -------------------------------------------
+void* workspace(kgf_ctx* ctx, const std::string& name, size_t bytes);
+void* host_scratch(kgf_ctx* ctx, size_t bytes);
+void sync(kgf_ctx* ctx);
+void check_launch(const char* what);
+void ensure_device_fits(size_t bytes, const char* what);
+
+// RAII bracket of one kernel launch for kgf_profile_*.
+struct Prof {
+    kgf_ctx* ctx;
+    const char* name;
+    hipEvent_t a = nullptr, b = nullptr;
+    Prof(kgf_ctx* c, const char* n);
+    ~Prof();
+};
+
+// ---- basis (basis.hip) ----------------------------------------------------
+void build_binomials(kgf_ctx* ctx);
+void build_masks(kgf_ctx* ctx, int L, int n, uint32_t* masks, int64_t D);
+void rank_masks(kgf_ctx* ctx, const uint32_t* masks, int64_t n, int N, int64_t* ranks);
+int64_t binom_host(int n, int k);
+
+// ---- hamiltonian (hamiltonian.hip) ---------------------------------------
+HopTable& hop_table(kgf_model* model, int n);
+void apply_h(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec,
+             const double2* v, double2* w, int nvec, int64_t ld);
+void apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int orbital,
+             int dagger, const double2* v, double2* w, int nvec, int64_t ld_src,
+             int64_t ld_dst);
+
+// Lanczos-fused H.v: for each column c
+//   y_c = s_c[k] * H x_c - b_c[k] * s_c[k-1] * xp_c      (xp may be null)
+//   part[c][blk] = Re <s_c[k] x_c, y_c>   (one partial per block)
+struct LanczosHvArgs {
+    const double2* x; int64_t x_col;       // x_c = x + c * x_col
+    const double2* xp; int64_t xp_col;     // previous vector (nullable)
+    double2* y; int64_t y_col;
+    const double* s_k;                     // scale of x (per column, * stride)
+    const double* b_k;                     // b_k       (per column, * stride)
+    const double* s_km1;                   // scale of xp (per column, * stride)
+    int stride;                            // doubles between columns
+    double* part;                          // [ncol][nblk]
+};
+int hv_lanczos_blocks(const kgf_sector* sec);
+void hv_lanczos(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
+                const LanczosHvArgs& a);
+
+// ---- krylov (krylov.hip) -------------------------------------------------
+struct SilOpts {
+    int m;
+    int reorth;
+    double dt;
+    int direction;
+    double shift;
+    double breakdown_tol;
+};
+
+// Batched short-iterative-Lanczos step(s) on ncol columns psi_c = psi + c*ld.
+void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi,
+                   int ncol, int64_t ld, int nsteps, const SilOpts& o);
+
+struct GsResult {
+    double E0;
+    int iters;
+    bool converged;
+    double residual;
+};
+GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec,
+                      const double2* v0, double2* psi0, double tol, int max_iter,
+                      int check_every, int reorth);
+
+// G[l][r] = <L_l | R_r> for nl left and nr right vectors (complex dots);
+// result in device memory out[l * nr + r] (double2).
+// out[l * out_ld + r]; out_ld = 0 means nr.
+void block_dots(kgf_ctx* ctx, const double2* Lv, int64_t l_col, int nl,
+                const double2* Rv, int64_t r_col, int nr, int64_t D, double2* out,
+                int64_t out_ld = 0);
+
+// ---- ABI helpers (api.hip) -------------------------------------------------
+// Runs f, turning kgf::Error and other exceptions into a return code and the
+// thread-local message of kgf_last_error.
+int abi_guard_impl(void* state, void (*call)(void*));
+template <class F>
+int abi_guard(F&& f) {
+    return abi_guard_impl(&f, [](void* p) { (*static_cast<F*>(p))(); });
+}
+void check_prop_opts(const kgf_prop_opts* o);
+SilOpts to_sil_opts(const kgf_prop_opts* o);
+
+// ---- greens (greens.hip) -------------------------------------------------
+void greens_eq(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,
+               double E0, const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o,
+               int batch, double2* Gg_host, double2* Gl_host);
+
+}  // namespace kgf

@@ -1,0 +1,865 @@
+// Krylov engine: Lanczos recursion (Eq. (recursion)), tridiagonal T
+// (Eq. (tmatrix)) and its eigen-decomposition (Eq. (tdiag)), Ritz vectors
+// (Eq. (eigen)), the ground state (Sec. 2) and the short-iterative-Lanczos
+// step psi -> beta0 V Q exp(-i Lambda dt) Q^T e_1 (Eqs. (newstate),
+// (udelta)).
+//
+// Storage: Lanczos vectors are kept unnormalised, v_k = s_k x_k, with the
+// scale s_k = 1/b_k folded into the next kernel that reads x_k, so no
+// separate normalisation pass over HBM is needed.  Every reduction writes
+// one partial per block; a one-block finaliser sums them in a fixed order
+// (results are reproducible run to run) and updates the per-column
+// scalars.  A batch of ncol independent recursions (own a_k, b_k, T) runs
+// in the same launches.
+#include <cfloat>
+#include <cmath>
+
+#include "kgf_internal.h"
+
+namespace kgf {
+
+namespace {
+
+// per-column scalar block (doubles)
+constexpr int kOffA = 0;                   // a[0..63]
+constexpr int kOffB = 64;                  // b[0..64]
+constexpr int kOffS = 130;                 // s[0..64]
+constexpr int kOffBeta0 = 196;
+constexpr int kOffSmax = 197;
+constexpr int kOffCoef = 200;              // complex coef[0..64] (re, im)
+constexpr int kOffH = 332;                 // complex reorth coefficients [0..64]
+constexpr int kScalStride = 464;
+
+constexpr int kDotChunk = 8;               // vectors per multi-dot chunk
+
+struct Slots {
+    // slot(k, c) = k == 0 ? s0 + c * s0_col : X + (k - 1) * x_slot + c * x_col
+    double2* s0;
+    int64_t s0_col;
+    double2* X;
+    int64_t x_slot;
+    int64_t x_col;
+    __host__ __device__ double2* at(int k, int c) const {
+        return k == 0 ? s0 + c * s0_col : X + (int64_t)(k - 1) * x_slot + c * x_col;
+    }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// block sum in a fixed order; valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    return r;
+}
+
+int red_blocks(int64_t D) {
+    int64_t nb = (D + kThreads * 4 - 1) / (kThreads * 4);
+    if (nb < 1) nb = 1;
+    if (nb > 1024) nb = 1024;
+    return (int)nb;
+}
+
+// ---------------------------------------------------------------------------
+// streaming kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_norm2(const double2* __restrict__ X, int64_t col,
+                                                    int64_t D, double* __restrict__ part) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.y;
+    const double2* x = X + c * col;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 z = x[i];
+        acc = fma(z.x, z.x, acc);
+        acc = fma(z.y, z.y, acc);
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s;
+}
+
+// y_c -= a_k s_k x_c ; part = ||y_c||^2   (a_k, s_k at fa/fs + c * stride)
+__global__ __launch_bounds__(kThreads) void k_update(Slots sl, int k, const double* __restrict__ fa,
+                                                     const double* __restrict__ fs, int stride,
+                                                     int64_t D, double* __restrict__ part) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.y;
+    const double f = fa[(int64_t)c * stride] * fs[(int64_t)c * stride];
+    const double2* x = sl.at(k, c);
+    double2* y = sl.at(k + 1, c);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 z = x[i], w = y[i];
+        w.x = fma(-f, z.x, w.x);
+        w.y = fma(-f, z.y, w.y);
+        y[i] = w;
+        acc = fma(w.x, w.x, acc);
+        acc = fma(w.y, w.y, acc);
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s;
+}
+
+// h_j = <s_j x_j, y> for j in chunk blockIdx.z (Gram-Schmidt coefficients);
+// part layout [c][j][blk] with nj_total coefficient slots per column
+__global__ __launch_bounds__(kThreads) void k_multidot(Slots sl, int ky, int nj,
+                                                       const double* __restrict__ scal,
+                                                       const double* __restrict__ gs_s,
+                                                       int64_t D, double* __restrict__ part) {
+    __shared__ double sh[kThreads / 64][2 * kDotChunk];
+    const int c = blockIdx.y;
+    const int j0 = blockIdx.z * kDotChunk;
+    const int nloc = nj - j0 < kDotChunk ? nj - j0 : kDotChunk;
+    const double2* y = sl.at(ky, c);
+    double ar[kDotChunk], ai[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) ar[q] = ai[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 w = y[i];
+#pragma unroll
+        for (int q = 0; q < kDotChunk; ++q) {
+            if (q < nloc) {
+                const double2 z = sl.at(j0 + q, c)[i];
+                ar[q] = fma(z.x, w.x, fma(z.y, w.y, ar[q]));
+                ai[q] = fma(z.x, w.y, fma(-z.y, w.x, ai[q]));
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) {
+        double r = wave_sum(ar[q]);
+        double im = wave_sum(ai[q]);
+        if (lane == 0) {
+            sh[wv][2 * q] = r;
+            sh[wv][2 * q + 1] = im;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nloc) {
+        const int q = threadIdx.x >> 1, reim = threadIdx.x & 1;
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w][threadIdx.x];
+        const int j = j0 + q;
+        const double scale = gs_s ? gs_s[j] : scal[(int64_t)c * kScalStride + kOffS + j];
+        part[(((int64_t)c * nj + j) * 2 + reim) * gridDim.x + blockIdx.x] = s * scale;
+    }
+}
+
+// y -= sum_j h_j s_j x_j ; part = ||y||^2 .  h from hvec[c][j] (complex).
+__global__ __launch_bounds__(kThreads) void k_multiaxpy(Slots sl, int ky, int nj,
+                                                        const double* __restrict__ scal,
+                                                        const double* __restrict__ gs_s,
+                                                        const double2* __restrict__ hvec,
+                                                        int64_t D, double* __restrict__ part) {
+    extern __shared__ double2 sw[];
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.y;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+        const double s = gs_s ? gs_s[j] : scal[(int64_t)c * kScalStride + kOffS + j];
+        double2 h = hvec[(int64_t)c * nj + j];
+        sw[j] = make_double2(h.x * s, h.y * s);
+    }
+    __syncthreads();
+    double2* y = sl.at(ky, c);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 w = y[i];
+        for (int j = 0; j < nj; ++j) {
+            const double2 z = sl.at(j, c)[i];
+            const double2 h = sw[j];
+            w.x -= h.x * z.x - h.y * z.y;
+            w.y -= h.x * z.y + h.y * z.x;
+        }
+        y[i] = w;
+        acc = fma(w.x, w.x, acc);
+        acc = fma(w.y, w.y, acc);
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s;
+}
+
+// out_c = sum_j coef_j slot(j, c)   (coef complex, already including s_j);
+// out may alias slot 0 (each element is read before it is written).
+__global__ __launch_bounds__(kThreads) void k_combine(Slots sl, int n, const double2* __restrict__ coef,
+                                                      int64_t coef_col, double2* __restrict__ out,
+                                                      int64_t out_col, int64_t D) {
+    extern __shared__ double2 sc[];
+    const int c = blockIdx.y;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) sc[j] = coef[c * coef_col + j];
+    __syncthreads();
+    double2* o = out + c * out_col;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double2 z = sl.at(j, c)[i];
+            const double2 h = sc[j];
+            re = fma(h.x, z.x, fma(-h.y, z.y, re));
+            im = fma(h.x, z.y, fma(h.y, z.x, im));
+        }
+        o[i] = make_double2(re, im);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale(double2* __restrict__ x, int64_t D,
+                                                    const double* __restrict__ fac) {
+    const double f = *fac;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 z = x[i];
+        x[i] = make_double2(z.x * f, z.y * f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// finalisers (one block per column): fixed-order sums of block partials
+// ---------------------------------------------------------------------------
+__device__ double fixed_sum(const double* p, int n, double* sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += p[i];
+    return block_sum(acc, sh);   // thread 0
+}
+
+enum FinMode { FIN_INIT = 0, FIN_A = 1, FIN_B = 2 };
+
+__global__ void k_fin(int mode, int k, const double* __restrict__ part, int nper,
+                      double* __restrict__ scal, double tol) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.x;
+    double v = fixed_sum(part + (int64_t)c * nper, nper, sh);
+    if (threadIdx.x != 0) return;
+    double* sc = scal + (int64_t)c * kScalStride;
+    if (mode == FIN_INIT) {
+        double b0 = sqrt(v);
+        sc[kOffBeta0] = b0;
+        sc[kOffS] = b0 > 0.0 ? 1.0 / b0 : 0.0;
+        sc[kOffB] = 0.0;
+        sc[kOffSmax] = 0.0;
+    } else if (mode == FIN_A) {
+        sc[kOffA + k] = sc[kOffS + k] != 0.0 ? v : 0.0;
+    } else {
+        double smax = fmax(sc[kOffSmax], fmax(fabs(sc[kOffA + k]), sc[kOffB + k]));
+        sc[kOffSmax] = smax;
+        double nb = sqrt(v);
+        if (sc[kOffS + k] == 0.0 || !(nb > tol * smax)) {
+            sc[kOffB + k + 1] = 0.0;
+            sc[kOffS + k + 1] = 0.0;
+        } else {
+            sc[kOffB + k + 1] = nb;
+            sc[kOffS + k + 1] = 1.0 / nb;
+        }
+    }
+}
+
+// sum the multi-dot partials: hvec[c][j] (complex) for j < nj
+__global__ void k_fin_h(const double* __restrict__ part, int nj, int nper, double2* __restrict__ hvec) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.x;
+    for (int j = 0; j < nj; ++j) {
+        double re = fixed_sum(part + (((int64_t)c * nj + j) * 2 + 0) * nper, nper, sh);
+        __syncthreads();
+        double im = fixed_sum(part + (((int64_t)c * nj + j) * 2 + 1) * nper, nper, sh);
+        __syncthreads();
+        if (threadIdx.x == 0) hvec[(int64_t)c * nj + j] = make_double2(re, im);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tridiagonal eigen-decomposition and exponential, one wavefront per column
+// ---------------------------------------------------------------------------
+// Implicit QL iteration with Wilkinson shifts for the symmetric tridiagonal
+// T (diagonal a_0..a_{m-1}, off-diagonal b_1..b_{m-1}).  Lane 0 chases the
+// bulge and records the plane rotations of a sweep; every lane then applies
+// them to its own row of the eigenvector matrix Q held in LDS.  Finally
+//   coef_k = beta0 * sum_j Q[k][j] f(lambda_j) Q[0][j] * s_k,
+// f = exp(-i lambda dt), exp(+i lambda dt) or exp(-(lambda - shift) dt).
+__global__ __launch_bounds__(64) void k_tridiag_exp(double* __restrict__ scal, int m, double dt,
+                                                    int direction, double shift) {
+    __shared__ double Q[kMaxKrylov][kMaxKrylov + 1];
+    __shared__ double d[kMaxKrylov], e[kMaxKrylov];
+    __shared__ double rc[kMaxKrylov], rs[kMaxKrylov];
+    __shared__ int s_mm, s_lo;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    double* sc = scal + (int64_t)c * kScalStride;
+    const double beta0 = sc[kOffBeta0];
+
+    if (lane < m) {
+        d[lane] = sc[kOffA + lane];
+        e[lane] = lane + 1 < m ? sc[kOffB + lane + 1] : 0.0;
+        for (int j = 0; j < m; ++j) Q[lane][j] = (j == lane) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+
+    for (int l = 0; l < m; ++l) {
+        for (int iter = 0; iter < 64; ++iter) {
+            if (lane == 0) {
+                int mm = l;
+                for (; mm < m - 1; ++mm) {
+                    const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+                    if (fabs(e[mm]) <= DBL_EPSILON * dd) break;
+                }
+                s_mm = mm;
+                if (mm != l) {
+                    double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                    double r = hypot(g, 1.0);
+                    g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+                    double s = 1.0, cc = 1.0, p = 0.0;
+                    int i = mm - 1;
+                    bool deflated = false;
+                    for (; i >= l; --i) {
+                        const double f = s * e[i];
+                        const double b = cc * e[i];
+                        r = hypot(f, g);
+                        e[i + 1] = r;
+                        if (r == 0.0) {
+                            d[i + 1] -= p;
+                            e[mm] = 0.0;
+                            deflated = true;
+                            break;
+                        }
+                        s = f / r;
+                        cc = g / r;
+                        g = d[i + 1] - p;
+                        r = (d[i] - g) * s + 2.0 * cc * b;
+                        p = s * r;
+                        d[i + 1] = g + p;
+                        g = cc * r - b;
+                        rc[i] = cc;
+                        rs[i] = s;
+                    }
+                    if (!deflated) {
+                        d[l] -= p;
+                        e[l] = g;
+                        e[mm] = 0.0;
+                        s_lo = l;
+                    } else {
+                        s_lo = i + 1;
+                    }
+                }
+            }
+            __syncthreads();
+            const int mm = s_mm;
+            if (mm == l) break;
+            if (lane < m) {
+                for (int i = mm - 1; i >= s_lo; --i) {
+                    const double f = Q[lane][i + 1];
+                    const double q = Q[lane][i];
+                    Q[lane][i + 1] = rs[i] * q + rc[i] * f;
+                    Q[lane][i] = rc[i] * q - rs[i] * f;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    if (lane < m) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double fr, fi;
+            if (direction == 0) {
+                fr = exp(-(d[j] - shift) * dt);
+                fi = 0.0;
+            } else {
+                double sn, cs;
+                sincos(d[j] * dt, &sn, &cs);
+                fr = cs;
+                fi = direction < 0 ? -sn : sn;
+            }
+            const double w = Q[lane][j] * Q[0][j];
+            re = fma(w, fr, re);
+            im = fma(w, fi, im);
+        }
+        const double f = beta0 * sc[kOffS + lane];
+        sc[kOffCoef + 2 * lane] = re * f;
+        sc[kOffCoef + 2 * lane + 1] = im * f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ground state of T_n: lowest eigenvalue by multisection of Sturm counts
+// (64 lanes), eigenvector by inverse iteration on lane 0.
+// ---------------------------------------------------------------------------
+__device__ int sturm_count(const double* a, const double* b2, int n, double x) {
+    // number of eigenvalues of T below x (LDL^T pivots of T - x I)
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+        if (q == 0.0) q = DBL_MIN;   // perturb an exact zero pivot
+        q = a[i] - x - b2[i] / q;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// gs arrays: a[n], b[n+1] (b[0] = 0, b[k] couples k-1, k), scratch >= 6 n doubles
+// out: res[0] = E0, res[1] = residual, res[2] = n_eff, res[3] = broken flag;
+//      y[0..n_eff-1] eigenvector (unit norm, largest-magnitude entry positive)
+__global__ __launch_bounds__(64) void k_gs_eig(const double* __restrict__ a, const double* __restrict__ b,
+                                               int n, double* __restrict__ scratch,
+                                               double* __restrict__ y, double* __restrict__ res) {
+    __shared__ double s_lo, s_hi;
+    __shared__ int s_n;
+    __shared__ int s_cnt[64];
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        int ne = n;
+        for (int i = 1; i < n; ++i)
+            if (b[i] == 0.0) {
+                ne = i;
+                break;
+            }
+        s_n = ne;
+        double lo = DBL_MAX, hi = -DBL_MAX;
+        double* b2 = scratch;
+        for (int i = 0; i < ne; ++i) {
+            b2[i] = i > 0 ? b[i] * b[i] : 0.0;
+            const double r = (i > 0 ? fabs(b[i]) : 0.0) + (i + 1 < ne ? fabs(b[i + 1]) : 0.0);
+            lo = fmin(lo, a[i] - r);
+            hi = fmax(hi, a[i] + r);
+        }
+        s_lo = lo - 1e-300;
+        s_hi = hi + 1e-300;
+    }
+    __syncthreads();
+    const int ne = s_n;
+    const double* b2 = scratch;
+    for (int round = 0; round < 40; ++round) {
+        const double lo = s_lo, hi = s_hi;
+        if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) || hi - lo <= DBL_MIN) break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        s_cnt[lane] = sturm_count(a, b2, ne, x);
+        __syncthreads();
+        if (lane == 0) {
+            int l = 0;
+            while (l < 64 && s_cnt[l] < 1) ++l;
+            const double nlo = l == 0 ? lo : lo + (hi - lo) * (double)l / 65.0;
+            const double nhi = l == 64 ? hi : lo + (hi - lo) * (double)(l + 1) / 65.0;
+            s_lo = nlo;
+            s_hi = fmin(nhi, hi);
+        }
+        __syncthreads();
+    }
+    if (lane != 0) return;
+    const double lam = 0.5 * (s_lo + s_hi);
+    // inverse iteration: (T - lam I) z = y, LU with partial pivoting
+    double* dl = scratch + ne;        // sub-diagonal multipliers
+    double* du = dl + ne;             // U diagonal
+    double* u1 = du + ne;             // U first super-diagonal
+    double* u2 = u1 + ne;             // U second super-diagonal (fill-in)
+    int* piv = reinterpret_cast<int*>(u2 + ne);
+    double tnorm = 0.0;
+    for (int i = 0; i < ne; ++i) tnorm = fmax(tnorm, fabs(a[i]) + (i > 0 ? fabs(b[i]) : 0.0) + (i + 1 < ne ? fabs(b[i + 1]) : 0.0));
+    const double tiny = DBL_EPSILON * fmax(tnorm, DBL_MIN);
+    // factor
+    for (int i = 0; i < ne; ++i) {
+        du[i] = a[i] - lam;
+        u1[i] = i + 1 < ne ? b[i + 1] : 0.0;
+        u2[i] = 0.0;
+    }
+    for (int i = 0; i < ne - 1; ++i) {
+        const double sub = b[i + 1];
+        if (fabs(du[i]) >= fabs(sub)) {
+            piv[i] = 0;
+            const double piv_v = du[i] != 0.0 ? du[i] : tiny;
+            du[i] = piv_v;
+            const double f = sub / piv_v;
+            dl[i] = f;
+            du[i + 1] -= f * u1[i];
+        } else {
+            piv[i] = 1;
+            const double f = du[i] / sub;
+            dl[i] = f;
+            // swap rows i and i+1
+            const double r_d = sub, r_u1 = du[i + 1], r_u2 = i + 1 < ne - 1 ? u1[i + 1] : 0.0;
+            const double o_u1 = u1[i];
+            du[i] = r_d;
+            u1[i] = r_u1;
+            u2[i] = r_u2;
+            du[i + 1] = o_u1 - f * r_u1;
+            if (i + 1 < ne - 1) u1[i + 1] = -f * r_u2;
+        }
+    }
+    if (du[ne - 1] == 0.0) du[ne - 1] = tiny;
+    for (int i = 0; i < ne; ++i) y[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        // forward (L)
+        for (int i = 0; i < ne - 1; ++i) {
+            if (piv[i]) {
+                const double t = y[i];
+                y[i] = y[i + 1];
+                y[i + 1] = t - dl[i] * y[i];
+            } else {
+                y[i + 1] -= dl[i] * y[i];
+            }
+        }
+        // backward (U)
+        for (int i = ne - 1; i >= 0; --i) {
+            double s = y[i];
+            if (i + 1 < ne) s -= u1[i] * y[i + 1];
+            if (i + 2 < ne) s -= u2[i] * y[i + 2];
+            y[i] = s / du[i];
+        }
+        double nrm = 0.0, big = 0.0;
+        int ib = 0;
+        for (int i = 0; i < ne; ++i) {
+            nrm = fma(y[i], y[i], nrm);
+            if (fabs(y[i]) > big) {
+                big = fabs(y[i]);
+                ib = i;
+            }
+        }
+        nrm = sqrt(nrm);
+        const double f = (y[ib] < 0.0 ? -1.0 : 1.0) / nrm;
+        for (int i = 0; i < ne; ++i) y[i] *= f;
+    }
+    for (int i = ne; i < n; ++i) y[i] = 0.0;
+    res[0] = lam;
+    res[1] = (ne < n) ? 0.0 : fabs(b[n]) * fabs(y[ne - 1]);
+    res[2] = (double)ne;
+    res[3] = ne < n ? 1.0 : (b[n] == 0.0 ? 1.0 : 0.0);
+}
+
+// GS recursion scalars live in plain arrays: a[k], b[k], s[k]
+__global__ void k_gs_fin(int mode, int k, const double* __restrict__ part, int nper,
+                         double* __restrict__ a, double* __restrict__ b, double* __restrict__ s) {
+    __shared__ double sh[kThreads / 64];
+    double v = fixed_sum(part, nper, sh);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_INIT) {
+        double n0 = sqrt(v);
+        s[0] = n0 > 0.0 ? 1.0 / n0 : 0.0;
+        b[0] = 0.0;
+    } else if (mode == FIN_A) {
+        a[k] = s[k] != 0.0 ? v : 0.0;
+    } else {
+        double nb = sqrt(v);
+        if (s[k] == 0.0 || nb == 0.0) {
+            b[k + 1] = 0.0;
+            s[k + 1] = 0.0;
+        } else {
+            b[k + 1] = nb;
+            s[k + 1] = 1.0 / nb;
+        }
+    }
+}
+
+__global__ void k_gs_coef(const double* __restrict__ y, const double* __restrict__ s, int n,
+                          double2* __restrict__ coef) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) coef[j] = make_double2(y[j] * s[j], 0.0);
+}
+
+__global__ void k_inv_sqrt(const double* __restrict__ part, int nper, double* __restrict__ out) {
+    __shared__ double sh[kThreads / 64];
+    double v = fixed_sum(part, nper, sh);
+    if (threadIdx.x == 0) *out = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+}
+
+// block dots: out[l * nr + r] = <L_l | R_r>
+__global__ __launch_bounds__(kThreads) void k_dots(const double2* __restrict__ Lv, int64_t l_col, int nl,
+                                                   const double2* __restrict__ Rv, int64_t r_col,
+                                                   const double2* const* __restrict__ Rptr, int64_t D,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[kThreads / 64][2 * kDotChunk];
+    const int r = blockIdx.y;
+    const int l0 = blockIdx.z * kDotChunk;
+    const int nloc = nl - l0 < kDotChunk ? nl - l0 : kDotChunk;
+    const double2* R = Rptr ? Rptr[r] : Rv + r * r_col;
+    double ar[kDotChunk], ai[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) ar[q] = ai[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 w = R[i];
+#pragma unroll
+        for (int q = 0; q < kDotChunk; ++q) {
+            if (q < nloc) {
+                const double2 z = Lv[(l0 + q) * l_col + i];
+                ar[q] = fma(z.x, w.x, fma(z.y, w.y, ar[q]));
+                ai[q] = fma(z.x, w.y, fma(-z.y, w.x, ai[q]));
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) {
+        double x = wave_sum(ar[q]);
+        double y = wave_sum(ai[q]);
+        if (lane == 0) {
+            sh[wv][2 * q] = x;
+            sh[wv][2 * q + 1] = y;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nloc) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w][threadIdx.x];
+        const int l = l0 + (threadIdx.x >> 1);
+        part[(((int64_t)l * gridDim.y + r) * 2 + (threadIdx.x & 1)) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ void k_dots_fin(const double* __restrict__ part, int nper, int nr, int64_t out_ld,
+                           double2* __restrict__ out) {
+    __shared__ double sh[kThreads / 64];
+    const int idx = blockIdx.x;   // l * nr + r
+    double re = fixed_sum(part + ((int64_t)idx * 2 + 0) * nper, nper, sh);
+    __syncthreads();
+    double im = fixed_sum(part + ((int64_t)idx * 2 + 1) * nper, nper, sh);
+    if (threadIdx.x == 0) out[(int64_t)(idx / nr) * out_ld + idx % nr] = make_double2(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+void launch_fin(kgf_ctx* ctx, int mode, int k, const double* part, int nper, double* scal, int ncol,
+                double tol) {
+    Prof pr(ctx, "fin");
+    hipLaunchKernelGGL(k_fin, dim3(ncol), dim3(kThreads), 0, ctx->stream, mode, k, part, nper, scal, tol);
+    check_launch("k_fin");
+}
+
+// Gram-Schmidt against slots 0..nj-1 (coefficients in hvec), `passes` times.
+// Leaves ||y||^2 partials of the last pass in part (nper = red_blocks(D)).
+void reorthogonalise(kgf_ctx* ctx, const Slots& sl, int ky, int nj, int ncol, int64_t D, int passes,
+                     const double* scal, const double* gs_s, double* part, double* part_big,
+                     double2* hvec) {
+    const int NB = red_blocks(D);
+    const int nchunk = (nj + kDotChunk - 1) / kDotChunk;
+    for (int p = 0; p < passes; ++p) {
+        {
+            Prof pr(ctx, "reorth_dot");
+            hipLaunchKernelGGL(k_multidot, dim3(NB, ncol, nchunk), dim3(kThreads), 0, ctx->stream, sl,
+                               ky, nj, scal, gs_s, D, part_big);
+            check_launch("k_multidot");
+        }
+        {
+            Prof pr(ctx, "fin");
+            hipLaunchKernelGGL(k_fin_h, dim3(ncol), dim3(kThreads), 0, ctx->stream, part_big, nj, NB, hvec);
+            check_launch("k_fin_h");
+        }
+        {
+            Prof pr(ctx, "reorth_axpy");
+            hipLaunchKernelGGL(k_multiaxpy, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * nj,
+                               ctx->stream, sl, ky, nj, scal, gs_s, hvec, D, part);
+            check_launch("k_multiaxpy");
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// short-iterative-Lanczos propagation
+// ---------------------------------------------------------------------------
+void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
+                   int64_t ld, int nsteps, const SilOpts& o) {
+    const int64_t D = sec->dim();
+    const int m = o.m;
+    KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
+    const size_t xbytes = sizeof(double2) * (size_t)m * ncol * D;
+    auto& xs = ctx->ws["sil_X"];
+    if (!xs || xs->bytes < xbytes) ensure_device_fits(xbytes - (xs ? xs->bytes : 0), "SIL Krylov basis");
+    double2* X = static_cast<double2*>(workspace(ctx, "sil_X", xbytes));
+    double* scal = static_cast<double*>(workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol));
+    const int NB = red_blocks(D);
+    const int HB = hv_lanczos_blocks(sec);
+    const int nper_max = NB > HB ? NB : HB;
+    double* part = static_cast<double*>(workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol));
+    double* part_big = nullptr;
+    double2* hvec = nullptr;
+    if (o.reorth > 0) {
+        part_big = static_cast<double*>(workspace(ctx, "sil_partbig", sizeof(double) * (size_t)NB * ncol * (m + 1) * 2));
+        hvec = static_cast<double2*>(workspace(ctx, "sil_hvec", sizeof(double2) * (size_t)ncol * (m + 1)));
+    }
+    Slots sl{psi, ld, X, (int64_t)ncol * D, D};
+
+    for (int step = 0; step < nsteps; ++step) {
+        {
+            Prof pr(ctx, "norm");
+            hipLaunchKernelGGL(k_norm2, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, psi, ld, D, part);
+            check_launch("k_norm2");
+        }
+        launch_fin(ctx, FIN_INIT, 0, part, NB, scal, ncol, 0.0);
+        for (int k = 0; k < m; ++k) {
+            LanczosHvArgs a;
+            a.x = sl.at(k, 0);
+            a.x_col = k == 0 ? ld : D;
+            a.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
+            a.xp_col = k - 1 == 0 ? ld : D;
+            a.y = sl.at(k + 1, 0);
+            a.y_col = D;
+            a.s_k = scal + kOffS + k;
+            a.b_k = scal + kOffB + k;
+            a.s_km1 = scal + kOffS + (k > 0 ? k - 1 : 0);
+            a.stride = kScalStride;
+            a.part = part;
+            hv_lanczos(ctx, model, sec, ncol, a);
+            launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
+            if (k == m - 1) break;
+            {
+                Prof pr(ctx, "lanczos_update");
+                hipLaunchKernelGGL(k_update, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, sl, k,
+                                   scal + kOffA + k, scal + kOffS + k, kScalStride, D, part);
+                check_launch("k_update");
+            }
+            if (o.reorth > 0)
+                reorthogonalise(ctx, sl, k + 1, k + 1, ncol, D, o.reorth, scal, nullptr, part, part_big, hvec);
+            launch_fin(ctx, FIN_B, k, part, NB, scal, ncol, o.breakdown_tol);
+        }
+        {
+            Prof pr(ctx, "tridiag_exp");
+            hipLaunchKernelGGL(k_tridiag_exp, dim3(ncol), dim3(64), 0, ctx->stream, scal, m, o.dt,
+                               o.direction, o.shift);
+            check_launch("k_tridiag_exp");
+        }
+        {
+            Prof pr(ctx, "combine");
+            hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream,
+                               sl, m, reinterpret_cast<const double2*>(scal + kOffCoef),
+                               (int64_t)(kScalStride / 2), psi, ld, D);
+            check_launch("k_combine");
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ground state
+// ---------------------------------------------------------------------------
+GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v0,
+                      double2* psi0, double tol, int max_iter, int check_every, int reorth) {
+    const int64_t D = sec->dim();
+    const int nmax = max_iter + 1;
+    const size_t vbytes = sizeof(double2) * (size_t)nmax * D;
+    auto& xs = ctx->ws["gs_V"];
+    if (!xs || xs->bytes < vbytes) ensure_device_fits(vbytes - (xs ? xs->bytes : 0), "ground-state Lanczos basis");
+    double2* V = static_cast<double2*>(workspace(ctx, "gs_V", vbytes));
+    double* a = static_cast<double*>(workspace(ctx, "gs_a", sizeof(double) * (nmax + 1)));
+    double* b = static_cast<double*>(workspace(ctx, "gs_b", sizeof(double) * (nmax + 1)));
+    double* s = static_cast<double*>(workspace(ctx, "gs_s", sizeof(double) * (nmax + 1)));
+    double* y = static_cast<double*>(workspace(ctx, "gs_y", sizeof(double) * (nmax + 1)));
+    double* scratch = static_cast<double*>(workspace(ctx, "gs_scratch", sizeof(double) * 6 * (nmax + 1)));
+    double* res = static_cast<double*>(workspace(ctx, "gs_res", sizeof(double) * 8));
+    double2* coef = static_cast<double2*>(workspace(ctx, "gs_coef", sizeof(double2) * (nmax + 1)));
+    const int NB = red_blocks(D);
+    const int HB = hv_lanczos_blocks(sec);
+    double* part = static_cast<double*>(workspace(ctx, "gs_part", sizeof(double) * (NB > HB ? NB : HB)));
+    double* part_big = static_cast<double*>(workspace(ctx, "gs_partbig", sizeof(double) * (size_t)NB * 2 * (nmax + 1)));
+    double2* hvec = static_cast<double2*>(workspace(ctx, "gs_hvec", sizeof(double2) * (nmax + 1)));
+    double* host = static_cast<double*>(host_scratch(ctx, sizeof(double) * 8));
+    Slots sl{V, 0, V + D, D, 0};
+
+    KGF_HIP(hipMemcpyAsync(V, v0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    {
+        Prof pr(ctx, "norm");
+        hipLaunchKernelGGL(k_norm2, dim3(NB, 1), dim3(kThreads), 0, ctx->stream, V, D, D, part);
+        check_launch("k_norm2");
+    }
+    hipLaunchKernelGGL(k_gs_fin, dim3(1), dim3(kThreads), 0, ctx->stream, (int)FIN_INIT, 0, part, NB, a, b, s);
+    check_launch("k_gs_fin");
+
+    GsResult out{0.0, 0, false, INFINITY};
+    int n = 0;
+    for (int k = 0; k < max_iter; ++k) {
+        LanczosHvArgs ha;
+        ha.x = sl.at(k, 0);
+        ha.x_col = 0;
+        ha.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
+        ha.xp_col = 0;
+        ha.y = sl.at(k + 1, 0);
+        ha.y_col = 0;
+        ha.s_k = s + k;
+        ha.b_k = b + k;
+        ha.s_km1 = s + (k > 0 ? k - 1 : 0);
+        ha.stride = 0;
+        ha.part = part;
+        hv_lanczos(ctx, model, sec, 1, ha);
+        hipLaunchKernelGGL(k_gs_fin, dim3(1), dim3(kThreads), 0, ctx->stream, (int)FIN_A, k, part, HB, a, b, s);
+        check_launch("k_gs_fin");
+        {
+            Prof pr(ctx, "lanczos_update");
+            hipLaunchKernelGGL(k_update, dim3(NB, 1), dim3(kThreads), 0, ctx->stream, sl, k, a + k, s + k, 0,
+                               D, part);
+            check_launch("k_update");
+        }
+        if (reorth > 0)
+            reorthogonalise(ctx, sl, k + 1, k + 1, 1, D, reorth, nullptr, s, part, part_big, hvec);
+        hipLaunchKernelGGL(k_gs_fin, dim3(1), dim3(kThreads), 0, ctx->stream, (int)FIN_B, k, part, NB, a, b, s);
+        check_launch("k_gs_fin");
+        n = k + 1;
+        if ((k + 1) % check_every == 0 || k == max_iter - 1) {
+            {
+                Prof pr(ctx, "gs_eig");
+                hipLaunchKernelGGL(k_gs_eig, dim3(1), dim3(64), 0, ctx->stream, a, b, n, scratch, y, res);
+                check_launch("k_gs_eig");
+            }
+            KGF_HIP(hipMemcpyAsync(host, res, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            out.E0 = host[0];
+            out.residual = host[1];
+            out.iters = (int)host[2];
+            if (host[3] != 0.0 || host[1] <= tol * fmax(1.0, fabs(host[0]))) {
+                out.converged = true;
+                break;
+            }
+        }
+    }
+    // Ritz vector psi0 = sum_j y_j s_j x_j, then normalise
+    const int ne = out.iters > 0 ? out.iters : n;
+    hipLaunchKernelGGL(k_gs_coef, dim3(1), dim3(kThreads), 0, ctx->stream, y, s, ne, coef);
+    check_launch("k_gs_coef");
+    {
+        Prof pr(ctx, "combine");
+        hipLaunchKernelGGL(k_combine, dim3(NB, 1), dim3(kThreads), sizeof(double2) * ne, ctx->stream, sl, ne,
+                           coef, (int64_t)0, psi0, (int64_t)0, D);
+        check_launch("k_combine");
+    }
+    hipLaunchKernelGGL(k_norm2, dim3(NB, 1), dim3(kThreads), 0, ctx->stream, psi0, D, D, part);
+    check_launch("k_norm2");
+    hipLaunchKernelGGL(k_inv_sqrt, dim3(1), dim3(kThreads), 0, ctx->stream, part, NB, res + 4);
+    check_launch("k_inv_sqrt");
+    hipLaunchKernelGGL(k_scale, dim3(NB), dim3(kThreads), 0, ctx->stream, psi0, D, res + 4);
+    check_launch("k_scale");
+    sync(ctx);
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// block dots
+// ---------------------------------------------------------------------------
+void block_dots(kgf_ctx* ctx, const double2* Lv, int64_t l_col, int nl, const double2* Rv, int64_t r_col,
+                int nr, int64_t D, double2* out, int64_t out_ld) {
+    if (nl == 0 || nr == 0) return;
+    if (out_ld <= 0) out_ld = nr;
+    const int NB = red_blocks(D) < 256 ? red_blocks(D) : 256;
+    double* part = static_cast<double*>(workspace(ctx, "dots_part", sizeof(double) * (size_t)NB * nl * nr * 2));
+    const int nchunk = (nl + kDotChunk - 1) / kDotChunk;
+    KGF_REQUIRE(nr <= 65535 && nchunk <= 65535 && (int64_t)nl * nr <= 0x7fffffff, KGF_EUNSUPPORTED,
+                "dots: too many vectors");
+    {
+        Prof pr(ctx, "dots");
+        hipLaunchKernelGGL(k_dots, dim3(NB, nr, nchunk), dim3(kThreads), 0, ctx->stream, Lv, l_col, nl, Rv,
+                           r_col, (const double2* const*)nullptr, D, part);
+        check_launch("k_dots");
+    }
+    hipLaunchKernelGGL(k_dots_fin, dim3(nl * nr), dim3(kThreads), 0, ctx->stream, part, NB, nr, out_ld, out);
+    check_launch("k_dots_fin");
+}
+
+}  // namespace kgf
