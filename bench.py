@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: four-step nonequilibrium G(t,t') on the 2x7 Hubbard ladder.
+
+Workload (one "step" = one pass of the whole hot path): half-filled open
+2x7 Hubbard ladder (t=1, D = 3432 x 3432 = 11,778,624), sudden quench
+U: 4 -> 8; (i) ground state of H_ini by Lanczos, (ii) forward SIL
+propagation to t_max = 5 (100 steps of dt = 0.05, Krylov dim 20),
+(iii) backward propagation of c Phi(t_k) and c+ Phi(t_k) for every mesh
+time, (iv) G^<_00(t,t') and G^>_00(t,t') on the 101 x 101 mesh.
+Inputs are synthetic and seeded (start vector seed 7); everything is
+resident in HBM when the timed region starts.
+
+value = contour steps/s: single-vector SIL steps (each Krylov dim H.v
+products) completed per second over the whole four-step run.
+roofline: the Lanczos-fused H.v kernel (the dominant kernel), algorithmic
+bytes per launch = 16 B x D x columns x (2 or 3 vector passes), divided by
+its launch durations measured with HIP events on the library's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hv_lanczos_ladder14_traffic.md")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=0)
+    p.add_argument("--schedule", choices=["sweep", "plain"], default="sweep")
+    p.add_argument("--batch", type=int, default=0, help="sweep block width cap (0 = from free memory)")
+    p.add_argument("--reorth", type=int, default=0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--profile-every", type=int, default=1)
+    return p.parse_args()
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("traffic_bytes_per_algorithmic_byte:"):
+                return float(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(q):
+    """The oracle as it stands: one SIL step (Krylov dim 20) of a c-sector
+    vector of the same ladder on the host cores."""
+    import numpy as np
+    import workloads as wl
+    from oracle import basis, hamiltonian, propagate
+    sec = basis.Sector(14, 6, 7)
+    H = hamiltonian.Hamiltonian(q.H, sec)
+    v = wl.complex_vector(sec.dim, 1)
+    t0 = time.perf_counter()
+    propagate.sil_step(H.apply, v, q.dt, q.krylov_dim, +1, reorth="none")
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "vector-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one SIL step (Krylov dim {q.krylov_dim}, dt={q.dt}) of a random D={sec.dim} "
+                       f"c-sector vector of the 2x7 ladder with the NumPy/SciPy oracle, {dt:.1f} s; "
+                       f"scipy.sparse products are single-threaded (host os.cpu_count()={os.cpu_count()})")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "
+              "single-device path in this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+
+    q = wl.ladder14()
+    ctx = kgf.Context(0)
+    last = [time.perf_counter()]
+
+    def report(phase, done, total):
+        now = time.perf_counter()
+        if now - last[0] >= 20.0 or done == total:
+            last[0] = now
+            log(f"  {phase} {done}/{total}")
+    ctx.set_progress(report)
+    m_ini, m_fin = ctx.model(q.H_ini), ctx.model(q.H)
+    sec = ctx.sector(14, q.n_up, q.n_dn)
+    v0 = torch.from_numpy(wl.start_vector(sec.dim, q.gs_seed)).to("cuda:0")
+    schedule = 1 if a.schedule == "sweep" else 0
+    kw = dict(orbitals=q.orbitals, nt=q.nt, steps_per_grid=q.steps_per_grid, dt=q.dt,
+              krylov_dim=q.krylov_dim, reorth=a.reorth, schedule=schedule, batch=a.batch, gs_tol=q.gs_tol)
+    vec_steps = (q.nt - 1) * q.steps_per_grid + 2 * q.steps_per_grid * q.nt * (q.nt - 1) // 2
+
+    for w in range(a.warmup):
+        log(f"warmup {w + 1}/{a.warmup}")
+        ctx.greens_neq(m_ini, m_fin, sec, v0, **kw)
+    torch.cuda.synchronize()
+    log(f"timed: {a.steps} step(s) of {vec_steps} vector-steps each")
+    ctx.profile_begin(a.profile_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for s in range(a.steps):
+        out = ctx.greens_neq(m_ini, m_fin, sec, v0, **kw)
+        log(f"step {s + 1}/{a.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.profile_end()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / a.steps
+
+    # anticommutator on the equal-time diagonal as a cheap live sanity check
+    Gl, Gg = out["G_lesser"][:, :, 0, 0], out["G_greater"][:, :, 0, 0]
+    anti = float(np.abs(np.diag(Gg - Gl) + 1j).max())
+
+    dom = max(stats.items(), key=lambda kv: kv[1]["sampled_ms"] / max(kv[1]["sampled"], 1) * kv[1]["launches"])
+    hv = stats.get("hv_lanczos", dom[1])
+    achieved = hv["sampled_bytes"] / (hv["sampled_ms"] * 1e-3) / 1e9 if hv["sampled_ms"] > 0 else 0.0
+    tb = measured_traffic()
+    avg_launch_bytes = hv["sampled_bytes"] / max(hv["sampled"], 1)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": (round(tb * avg_launch_bytes) if tb is not None else None),
+                "kernel": "hv_lanczos", "avg_launch_ms": round(hv["sampled_ms"] / max(hv["sampled"], 1), 5),
+                "avg_launch_algorithmic_bytes": round(avg_launch_bytes)}
+    kernels = {k: {"launches": v["launches"], "avg_ms": round(v["sampled_ms"] / max(v["sampled"], 1), 5),
+                   "total_ms": round(v["sampled_ms"] * v["launches"] / max(v["sampled"], 1), 1),
+                   "GBps": (round(v["sampled_bytes"] / (v["sampled_ms"] * 1e-3) / 1e9, 1)
+                            if v["sampled_bytes"] and v["sampled_ms"] else None)}
+               for k, v in sorted(stats.items())}
+    cpu = None if a.no_cpu_baseline else cpu_baseline(q)
+    res = {
+        "metric": "G(t,t') contour steps/s at L=14 (four-step, Lanczos-fused H.v GB/s in roofline)",
+        "value": round(vec_steps * a.steps / elapsed, 2),
+        "unit": "vector-steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ("ladder14 quench: 2x7 open Hubbard ladder t=1, half filling, D=11,778,624, "
+                                "U 4->8, G^<_00 and G^>_00 on 101x101, Krylov dim 20, dt=0.05"),
+                   "D": sec.dim, "nt": q.nt, "krylov_dim": q.krylov_dim, "schedule": a.schedule,
+                   "vector_steps_per_step": vec_steps, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "E0": out["E0"],
+        "anticommutator_err": anti,
+        "kernels": kernels,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

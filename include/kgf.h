@@ -207,17 +207,31 @@ int  kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                     kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
                     double* host_E0, kgf_c128* psi0_out);
 
+/* ---- progress reporting ------------------------------------------------------
+ * The drivers (kgf_ground_state, kgf_greens_eq, kgf_greens_neq) call
+ * fn(user, phase, done, total) on the calling host thread after each mesh
+ * time (and at phase boundaries), once the work up to that point has
+ * finished on the device.  `phase` is a short static string.  fn = NULL
+ * disables reporting (the default).  The callback must not call back into
+ * the library. */
+typedef void (*kgf_progress_fn)(void* user, const char* phase, int64_t done, int64_t total);
+int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
+
 /* ---- device-side timing of the library's kernels --------------------------
  * Between kgf_profile_begin and kgf_profile_end every `sample_every`-th
  * launch of each kernel class is bracketed by HIP events on the context's
  * stream.  kgf_profile_end synchronises and fills up to max_classes rows:
  * class name (<= 31 chars), launches, sampled launches, summed sampled
- * milliseconds.  Returns the number of classes written (>= 0). */
+ * milliseconds and the summed algorithmic bytes of the sampled launches
+ * (the minimum HBM traffic of each launch: every input vector read once,
+ * every output vector written once; 0 for classes without a byte model).
+ * Returns the number of classes written (>= 0). */
 typedef struct {
     char   name[32];
     int64_t launches;
     int64_t sampled;
     double sampled_ms;
+    double sampled_bytes;
 } kgf_kernel_stat;
 int  kgf_profile_begin(kgf_ctx* ctx, int sample_every);
 int  kgf_profile_end(kgf_ctx* ctx, kgf_kernel_stat* host_stats, int max_classes);

@@ -55,8 +55,10 @@ class _PropOpts(C.Structure):
 
 class _KStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("sampled", C.c_int64),
-                ("sampled_ms", C.c_double)]
+                ("sampled_ms", C.c_double), ("sampled_bytes", C.c_double)]
 
+
+_PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_char_p, C.c_int64, C.c_int64)
 
 _lib = None
 
@@ -97,6 +99,7 @@ def load_library():
         "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
+        "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
         "kgf_profile_begin": (I, [P, I]),
         "kgf_profile_end": (I, [P, C.POINTER(_KStat), I]),
     }
@@ -113,7 +116,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_model_create", "kgf_model_destroy", "kgf_sector_create", "kgf_sector_destroy",
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
-            "kgf_greens_neq", "kgf_profile_begin", "kgf_profile_end"]
+            "kgf_greens_neq", "kgf_set_progress", "kgf_profile_begin", "kgf_profile_end"]
 
 
 def _check(rc: int):
@@ -361,6 +364,21 @@ class Context:
             out["G_mixed"] = Gx
         return out
 
+    def set_progress(self, fn=None):
+        """fn(phase: str, done: int, total: int) called from the library's
+        drivers as mesh times complete; None disables."""
+        if fn is None:
+            self._progress_cb = None
+            _check(_lib.kgf_set_progress(self.handle, _PROGRESS_FN(), None))
+            return
+        def cb(user, phase, done, total):
+            try:
+                fn(phase.decode(), int(done), int(total))
+            except Exception:
+                pass
+        self._progress_cb = _PROGRESS_FN(cb)
+        _check(_lib.kgf_set_progress(self.handle, self._progress_cb, None))
+
     def profile_begin(self, sample_every: int = 1):
         _check(_lib.kgf_profile_begin(self.handle, int(sample_every)))
 
@@ -368,4 +386,5 @@ class Context:
         arr = (_KStat * 64)()
         n = _check(_lib.kgf_profile_end(self.handle, arr, 64))
         return {arr[i].name.decode(): {"launches": arr[i].launches, "sampled": arr[i].sampled,
-                                       "sampled_ms": arr[i].sampled_ms} for i in range(n)}
+                                       "sampled_ms": arr[i].sampled_ms, "sampled_bytes": arr[i].sampled_bytes}
+                for i in range(n)}

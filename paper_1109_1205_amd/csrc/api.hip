@@ -67,6 +67,12 @@ void ensure_device_fits(size_t bytes, const char* what) {
                              " MiB, " + std::to_string(free_b >> 20) + " MiB free");
 }
 
+void progress(kgf_ctx* ctx, const char* phase, int64_t done, int64_t total) {
+    if (!ctx->progress) return;
+    sync(ctx);
+    ctx->progress(ctx->progress_user, phase, done, total);
+}
+
 static hipEvent_t take_event(kgf_ctx* ctx) {
     if (!ctx->event_pool.empty()) {
         hipEvent_t e = ctx->event_pool.back();
@@ -78,7 +84,7 @@ static hipEvent_t take_event(kgf_ctx* ctx) {
     return e;
 }
 
-Prof::Prof(kgf_ctx* c, const char* n) : ctx(c), name(n) {
+Prof::Prof(kgf_ctx* c, const char* n, double by) : ctx(c), name(n), bytes(by) {
     if (!ctx->prof_on) return;
     auto& st = ctx->prof[name];
     bool take = (st.launches % ctx->prof_every) == 0;
@@ -92,7 +98,7 @@ Prof::Prof(kgf_ctx* c, const char* n) : ctx(c), name(n) {
 Prof::~Prof() {
     if (!a) return;
     if (hipEventRecord(b, ctx->stream) == hipSuccess)
-        ctx->pending.push_back({name, a, b});
+        ctx->pending.push_back({name, a, b, bytes});
 }
 
 }  // namespace kgf
@@ -436,6 +442,14 @@ int kgf_greens_eq(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, con
     });
 }
 
+int kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user) {
+    return guarded([&] {
+        KGF_REQUIRE(ctx, KGF_EINVAL, "kgf_set_progress: ctx is NULL");
+        ctx->progress = fn;
+        ctx->progress_user = user;
+    });
+}
+
 int kgf_profile_begin(kgf_ctx* ctx, int sample_every) {
     return guarded([&] {
         KGF_REQUIRE(ctx && sample_every >= 1, KGF_EINVAL, "kgf_profile_begin: bad argument");
@@ -457,6 +471,7 @@ int kgf_profile_end(kgf_ctx* ctx, kgf_kernel_stat* out, int max_classes) {
             auto& st = ctx->prof[p.name];
             st.sampled++;
             st.ms += ms;
+            st.bytes += p.bytes;
             ctx->event_pool.push_back(p.a);
             ctx->event_pool.push_back(p.b);
         }
@@ -469,6 +484,7 @@ int kgf_profile_end(kgf_ctx* ctx, kgf_kernel_stat* out, int max_classes) {
             out[n].launches = kv.second.launches;
             out[n].sampled = kv.second.sampled;
             out[n].sampled_ms = kv.second.ms;
+            out[n].sampled_bytes = kv.second.bytes;
             ++n;
         }
     });

@@ -225,6 +225,8 @@ void greens_eq(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const doub
                     if (k > 0) sil_propagate(ctx, model, tgt.get(), Xt + c0 * Dt, nc, Dt, spg, so);
                     // raw[k][i][c0 + j] = <X0_i | Xt_j>
                     block_dots(ctx, X0, Dt, na, Xt + c0 * Dt, Dt, nc, Dt, raw + (size_t)k * na * na + c0, na);
+                    progress(ctx, greater ? "eq_greater" : "eq_lesser", (int64_t)c0 * nt + (int64_t)(k + 1) * nc,
+                             (int64_t)na * nt);
                 }
             }
             DevBuf gl;
@@ -289,6 +291,8 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
                 double2* x = Psi + ((size_t)q * nt + k) * Dt;
                 apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, x, 1, D, Dt);
                 if (k > 0) sil_propagate(ctx, A.H, tgt.get(), x, 1, Dt, k * A.spg, so);
+                progress(ctx, dagger ? "backward_greater" : "backward_lesser", (int64_t)q * nt + k + 1,
+                         (int64_t)na * nt);
             }
         // raw layout [b][s][a][j] = <Psi_b(s) | Psi_a(j)>
         block_dots(ctx, Psi, Dt, na * nt, Psi, Dt, na * nt, Dt, raw, (int64_t)na * nt);
@@ -319,6 +323,8 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
     int jchunk = std::max(1, Bcols / na);
     jchunk = std::min(jchunk, nt);
     const int maxcols = jchunk * na;
+    release(ctx, "sil_X");
+    sil_reserve(ctx, tgt.get(), maxcols, A.o.m, A.o.reorth);
     ensure_device_fits(sizeof(double2) * (size_t)maxcols * Dt, "four-step sweep block");
     double2* S = static_cast<double2*>(workspace(ctx, "neq_cols", sizeof(double2) * (size_t)maxcols * Dt));
     double2* Lb = static_cast<double2*>(workspace(ctx, "neq_left", sizeof(double2) * (size_t)na * Dt));
@@ -342,6 +348,7 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
             block_dots(ctx, Lb, Dt, na, S, Dt, ncur, Dt, tmp, ncur);
             place(ctx, tmp, na, na, ncur, jhi, raw, s * ss, sb, sa, sj);
             if (s > 0) sil_propagate(ctx, A.H, tgt.get(), S, ncur, Dt, A.spg, so);
+            progress(ctx, dagger ? "sweep_greater" : "sweep_lesser", jhi - s + 1, jhi + 1);
         }
         if (want_mixed) {
             // columns now hold Psi_a(t_j) for j in [jlo, jhi]; tmpm[(b, jt)][r]
@@ -384,6 +391,7 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
         KGF_HIP(hipMemcpyAsync(Phi + (size_t)k * D, Phi + (size_t)(k - 1) * D, sizeof(double2) * D,
                                hipMemcpyDeviceToDevice, ctx->stream));
         sil_propagate(ctx, A.H, sec, Phi + (size_t)k * D, 1, D, A.spg, fo);
+        progress(ctx, "forward", k, nt - 1);
     }
     const size_t gsz = sizeof(double2) * (size_t)nt * nt * norb * norb;
     double2* Gl = static_cast<double2*>(workspace(ctx, "neq_Gl", gsz));

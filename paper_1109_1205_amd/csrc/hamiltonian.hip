@@ -166,6 +166,127 @@ __global__ __launch_bounds__(kThreads) void k_hv(HvTables T, const double2* __re
     }
 }
 
+// Row-in-LDS variant: the block stages its input row x[u, :] in LDS, so the
+// down-spin gathers (random inside the row) are served by LDS; only the
+// up-spin row reads go to the memory hierarchy.  Blocks are mapped to the
+// 8 XCDs so that each XCD walks a contiguous range of rows (block b runs on
+// XCD b mod 8): most up-spin hops connect rows less than a few hundred
+// apart, so their source rows stay in that XCD's L2.
+constexpr int kHvThreads = 1024;
+constexpr size_t kRowLdsMax = 78 * 1024;
+
+template <int MODE, bool UNIFORM_U>
+__global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_xcd,
+                                                       const double2* __restrict__ X, int64_t x_col,
+                                                       const double2* __restrict__ XP, int64_t xp_col,
+                                                       double2* __restrict__ Y, int64_t y_col,
+                                                       const double* __restrict__ s_k,
+                                                       const double* __restrict__ b_k,
+                                                       const double* __restrict__ s_km1, int stride,
+                                                       double* __restrict__ part) {
+    extern __shared__ double2 srow[];
+    __shared__ double s_negt[kMaxBonds + 1];
+    __shared__ double s_U[UNIFORM_U ? 1 : 3 * 256];
+    __shared__ double s_upval[kMaxBonds + 1];
+    __shared__ int64_t s_uprow[kMaxBonds + 1];
+    __shared__ double s_red[kHvThreads / 64];
+
+    const int blk = blockIdx.x;
+    const int64_t u = (int64_t)(blk & 7) * rows_per_xcd + (blk >> 3);
+    if (u >= T.Dup) return;   // uniform over the block
+    const int c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t Ddn = T.Ddn;
+    const double2* __restrict__ x = X + c * x_col;
+    double2* __restrict__ y = Y + c * y_col;
+    const double2* __restrict__ xrow = x + u * Ddn;
+
+    for (int64_t d = tid; d < Ddn; d += blockDim.x) srow[d] = xrow[d];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    if (!UNIFORM_U)
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[i];
+    __syncthreads();
+    const int cu = T.cnt_up[u];
+    for (int k = tid; k < cu; k += blockDim.x) {
+        uint32_t e = T.ent_up[(int64_t)k * T.Dup + u];
+        double v = s_negt[(e >> 24) & 127u];
+        s_upval[k] = (e >> 31) ? -v : v;
+        s_uprow[k] = (int64_t)(e & 0xFFFFFFu) * Ddn;
+    }
+    __syncthreads();
+
+    double sc = 1.0, bp = 0.0;
+    if (MODE == 1) {
+        sc = s_k[c * stride];
+        if (XP) bp = b_k[c * stride] * s_km1[c * stride];
+    }
+    const uint32_t mu = T.mu[u];
+    const double eu = T.eu[u];
+    double dot = 0.0;
+    // Gathers are issued in predicated batches of kBatch so that many loads
+    // are in flight per thread (the hop counts are data dependent).
+    constexpr int kBatch = 8;
+    for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+        const double2 xv = srow[d];
+        const uint32_t both = mu & T.md[d];
+        const int cd = T.cnt_dn[d];
+        double dg = eu + T.ed[d];
+        if (UNIFORM_U) {
+            dg += T.U0 * (double)__popc(both);
+        } else {
+            dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
+        }
+        double ar = dg * xv.x, ai = dg * xv.y;
+        for (int k0 = 0; k0 < cu; k0 += kBatch) {       // up-spin hops: uniform count
+            double2 z[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) z[j] = x[s_uprow[k0 + j] + d];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) {
+                    const double tv = s_upval[k0 + j];
+                    ar = fma(tv, z[j].x, ar);
+                    ai = fma(tv, z[j].y, ai);
+                }
+        }
+        for (int k0 = 0; k0 < cd; k0 += kBatch) {       // down-spin hops: per-lane count
+            uint32_t e[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) e[j] = (k0 + j < cd) ? T.ent_dn[(int64_t)(k0 + j) * Ddn + d] : 0u;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cd) {
+                    double tv = s_negt[(e[j] >> 24) & 127u];
+                    tv = (e[j] >> 31) ? -tv : tv;
+                    const double2 zz = srow[e[j] & 0xFFFFFFu];
+                    ar = fma(tv, zz.x, ar);
+                    ai = fma(tv, zz.y, ai);
+                }
+        }
+        double2 out;
+        if (MODE == 0) {
+            out.x = ar;
+            out.y = ai;
+        } else {
+            out.x = sc * ar;
+            out.y = sc * ai;
+            if (bp != 0.0) {
+                const double2 p = (XP + c * xp_col)[u * Ddn + d];
+                out.x = fma(-bp, p.x, out.x);
+                out.y = fma(-bp, p.y, out.y);
+            }
+            dot = fma(sc * xv.x, out.x, dot);
+            dot = fma(sc * xv.y, out.y, dot);
+        }
+        y[u * Ddn + d] = out;
+    }
+    if (MODE == 1) {
+        double s = block_sum(dot, s_red);
+        if (tid == 0) part[(int64_t)c * T.Dup + u] = s;
+    }
+}
+
 // c_alpha / c+_alpha between sectors.  For an up-spin orbital the map is a
 // gather of whole rows, for a down-spin orbital a gather inside each row.
 __device__ __forceinline__ int64_t rank_of(uint32_t m, const uint64_t* C) {
@@ -241,9 +362,29 @@ void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
                int64_t y_col, const double* s_k, const double* b_k, const double* s_km1,
                int stride, double* part) {
     HvTables T = make_tables(model, sec);
-    KGF_REQUIRE(sec->d_up <= 0x7fffffff && ncol <= 65535, KGF_EUNSUPPORTED, "H.v: grid too large");
+    KGF_REQUIRE(sec->d_up <= 0x7ffffff0 && ncol <= 65535, KGF_EUNSUPPORTED, "H.v: grid too large");
+    // algorithmic bytes: read x once, write y once, read xp once if present
+    const double vec = 16.0 * (double)sec->dim() * ncol;
+    Prof pr(ctx, MODE == 0 ? "hv" : "hv_lanczos", vec * (xp ? 3.0 : 2.0));
+    const size_t row_bytes = sizeof(double2) * (size_t)sec->d_dn;
+    if (row_bytes <= kRowLdsMax) {
+        const int rpx = (int)((sec->d_up + 7) / 8);
+        dim3 grid((unsigned)(8 * rpx), (unsigned)ncol);
+        // opt in to more than 64 KB of dynamic LDS once per device and kernel
+        static bool opted[2][64] = {};
+        const int ui = model->U_uniform ? 1 : 0;
+        const int dev = ctx->device & 63;
+        auto kern = model->U_uniform ? k_hv_lds<MODE, true> : k_hv_lds<MODE, false>;
+        if (!opted[ui][dev]) {
+            KGF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowLdsMax));
+            opted[ui][dev] = true;
+        }
+        hipLaunchKernelGGL(kern, grid, dim3(kHvThreads), row_bytes, ctx->stream, T, rpx, x, x_col, xp,
+                           xp_col, y, y_col, s_k, b_k, s_km1, stride, part);
+        check_launch("k_hv_lds");
+        return;
+    }
     dim3 grid((unsigned)sec->d_up, (unsigned)ncol);
-    Prof pr(ctx, MODE == 0 ? "hv" : "hv_lanczos");
     if (model->U_uniform)
         hipLaunchKernelGGL((k_hv<MODE, true>), grid, dim3(kThreads), 0, ctx->stream, T, x, x_col, xp,
                            xp_col, y, y_col, s_k, b_k, s_km1, stride, part);

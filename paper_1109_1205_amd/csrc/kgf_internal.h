@@ -70,6 +70,7 @@ struct KernelStat {
     int64_t launches = 0;
     int64_t sampled = 0;
     double ms = 0.0;
+    double bytes = 0.0;
 };
 
 }  // namespace kgf
@@ -83,9 +84,12 @@ struct kgf_ctx {
     bool prof_on = false;
     int prof_every = 1;
     std::map<std::string, kgf::KernelStat> prof;
-    struct Pending { std::string name; hipEvent_t a, b; };
+    struct Pending { std::string name; hipEvent_t a, b; double bytes; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
+    // progress callback
+    kgf_progress_fn progress = nullptr;
+    void* progress_user = nullptr;
     // pinned host scratch for scalar readbacks
     void* host_scratch = nullptr;
     size_t host_scratch_bytes = 0;
@@ -119,13 +123,17 @@ void* host_scratch(kgf_ctx* ctx, size_t bytes);
 void sync(kgf_ctx* ctx);
 void check_launch(const char* what);
 void ensure_device_fits(size_t bytes, const char* what);
+// report progress (synchronises the stream first; no-op without a callback)
+void progress(kgf_ctx* ctx, const char* phase, int64_t done, int64_t total);
 
-// RAII bracket of one kernel launch for kgf_profile_*.
+// RAII bracket of one kernel launch for kgf_profile_*; `bytes` is the
+// launch's algorithmic HBM traffic (0 when not modelled).
 struct Prof {
     kgf_ctx* ctx;
     const char* name;
+    double bytes;
     hipEvent_t a = nullptr, b = nullptr;
-    Prof(kgf_ctx* c, const char* n);
+    Prof(kgf_ctx* c, const char* n, double bytes = 0.0);
     ~Prof();
 };
 
@@ -170,6 +178,9 @@ struct SilOpts {
     double breakdown_tol;
 };
 
+// Reserve the SIL workspaces for batches of up to ncol columns (avoids
+// re-allocation when a caller grows its batch step by step).
+void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth);
 // Batched short-iterative-Lanczos step(s) on ncol columns psi_c = psi + c*ld.
 void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi,
                    int ncol, int64_t ld, int nsteps, const SilOpts& o);

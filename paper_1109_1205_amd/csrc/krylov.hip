@@ -299,6 +299,85 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(double* __restrict__ scal, i
     double* sc = scal + (int64_t)c * kScalStride;
     const double beta0 = sc[kOffBeta0];
 
+    // ---- moderate ||T dt||: exp(A) e_1 by n_sub Taylor substeps of exp(A/n_sub),
+    // with A = -i (T - sigma) dt, +i (T - sigma) dt or -(T - sigma) dt and
+    // the scalar factor of the centre sigma of the Gershgorin interval applied
+    // at the end.  Lane r holds row r; the tridiagonal product uses
+    // neighbour-lane shuffles.  Each substep has x = ||A||/n_sub <= 1 and
+    // K terms with x^(K+1)/(K+1)! e^x < 1e-17.  Large ||T dt|| (few long
+    // steps) takes the eigen-decomposition below instead.
+    {
+        const double a0 = lane < m ? sc[kOffA + lane] : 0.0;
+        const double br = (lane >= 1 && lane < m) ? sc[kOffB + lane] : 0.0;          // couples r-1, r
+        const double bn = (lane + 1 < m) ? sc[kOffB + lane + 1] : 0.0;              // couples r, r+1
+        double glo = lane < m ? a0 - fabs(br) - fabs(bn) : DBL_MAX;
+        double ghi = lane < m ? a0 + fabs(br) + fabs(bn) : -DBL_MAX;
+        for (int off = 32; off > 0; off >>= 1) {
+            glo = fmin(glo, __shfl_xor(glo, off, 64));
+            ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+        }
+        const double sigma = 0.5 * (glo + ghi);
+        const double x = 0.5 * (ghi - glo) * fabs(dt);
+        if (x <= 64.0) {
+            const int n_sub = x <= 1.0 ? 1 : (int)ceil(x);
+            const double xs = x / n_sub;
+            int K = 1;
+            {
+                double term = xs, fact = 1.0;
+                const double ex = exp(xs);
+                while (K < 40) {
+                    fact *= (double)(K + 1);
+                    term *= xs;
+                    if (term / fact * ex < 1e-17) break;
+                    ++K;
+                }
+            }
+            const double ar = a0 - sigma;
+            const double h = dt / n_sub;
+            double cr = lane == 0 ? 1.0 : 0.0, ci = 0.0;   // current state
+            for (int sub = 0; sub < n_sub; ++sub) {
+                double vr = cr, vi = ci;                     // running term
+                for (int k = 1; k <= K; ++k) {
+                    const double pr = __shfl_up(vr, 1, 64), pi = __shfl_up(vi, 1, 64);
+                    const double nr = __shfl_down(vr, 1, 64), ni = __shfl_down(vi, 1, 64);
+                    const double wr = ar * vr + (lane >= 1 ? br * pr : 0.0) + (lane + 1 < m ? bn * nr : 0.0);
+                    const double wi = ar * vi + (lane >= 1 ? br * pi : 0.0) + (lane + 1 < m ? bn * ni : 0.0);
+                    const double f = h / (double)k;
+                    if (direction == 0) {        // -(T - sigma) h
+                        vr = -f * wr;
+                        vi = -f * wi;
+                    } else if (direction < 0) {  // -i (T - sigma) h
+                        vr = f * wi;
+                        vi = -f * wr;
+                    } else {                     // +i (T - sigma) h
+                        vr = -f * wi;
+                        vi = f * wr;
+                    }
+                    if (lane >= m) vr = vi = 0.0;
+                    cr += vr;
+                    ci += vi;
+                }
+            }
+            // scalar factor of the centre: exp(-i sigma dt), exp(+i sigma dt) or exp(-(sigma - shift) dt)
+            double fr, fi;
+            if (direction == 0) {
+                fr = exp(-(sigma - shift) * dt);
+                fi = 0.0;
+            } else {
+                double sn, cs;
+                sincos(sigma * dt, &sn, &cs);
+                fr = cs;
+                fi = direction < 0 ? -sn : sn;
+            }
+            if (lane < m) {
+                const double g = beta0 * sc[kOffS + lane];
+                sc[kOffCoef + 2 * lane] = (cr * fr - ci * fi) * g;
+                sc[kOffCoef + 2 * lane + 1] = (cr * fi + ci * fr) * g;
+            }
+            return;
+        }
+    }
+
     if (lane < m) {
         d[lane] = sc[kOffA + lane];
         e[lane] = lane + 1 < m ? sc[kOffB + lane + 1] : 0.0;
@@ -668,14 +747,36 @@ void reorthogonalise(kgf_ctx* ctx, const Slots& sl, int ky, int nj, int ncol, in
 // ---------------------------------------------------------------------------
 // short-iterative-Lanczos propagation
 // ---------------------------------------------------------------------------
+void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth) {
+    const int64_t D = sec->dim();
+    const size_t xbytes = sizeof(double2) * (size_t)m * ncol * D;
+    auto& xs = ctx->ws["sil_X"];
+    if (!xs || xs->bytes < xbytes) {
+        if (xs) {   // free the smaller buffer first so that the new one fits
+            sync(ctx);
+            xs.reset();
+        }
+        ensure_device_fits(xbytes, "SIL Krylov basis");
+        workspace(ctx, "sil_X", xbytes);
+    }
+    const int NB = red_blocks(D);
+    const int HB = hv_lanczos_blocks(sec);
+    const int nper_max = NB > HB ? NB : HB;
+    workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol);
+    workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol);
+    if (reorth > 0) {
+        workspace(ctx, "sil_partbig", sizeof(double) * (size_t)NB * ncol * (m + 1) * 2);
+        workspace(ctx, "sil_hvec", sizeof(double2) * (size_t)ncol * (m + 1));
+    }
+}
+
 void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
                    int64_t ld, int nsteps, const SilOpts& o) {
     const int64_t D = sec->dim();
     const int m = o.m;
     KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
+    sil_reserve(ctx, sec, ncol, m, o.reorth);
     const size_t xbytes = sizeof(double2) * (size_t)m * ncol * D;
-    auto& xs = ctx->ws["sil_X"];
-    if (!xs || xs->bytes < xbytes) ensure_device_fits(xbytes - (xs ? xs->bytes : 0), "SIL Krylov basis");
     double2* X = static_cast<double2*>(workspace(ctx, "sil_X", xbytes));
     double* scal = static_cast<double*>(workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol));
     const int NB = red_blocks(D);
@@ -692,7 +793,7 @@ void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double
 
     for (int step = 0; step < nsteps; ++step) {
         {
-            Prof pr(ctx, "norm");
+            Prof pr(ctx, "norm", 16.0 * D * ncol);
             hipLaunchKernelGGL(k_norm2, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, psi, ld, D, part);
             check_launch("k_norm2");
         }
@@ -714,7 +815,7 @@ void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double
             launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
             if (k == m - 1) break;
             {
-                Prof pr(ctx, "lanczos_update");
+                Prof pr(ctx, "lanczos_update", 48.0 * D * ncol);
                 hipLaunchKernelGGL(k_update, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, sl, k,
                                    scal + kOffA + k, scal + kOffS + k, kScalStride, D, part);
                 check_launch("k_update");
@@ -730,7 +831,7 @@ void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double
             check_launch("k_tridiag_exp");
         }
         {
-            Prof pr(ctx, "combine");
+            Prof pr(ctx, "combine", 16.0 * (m + 1) * D * ncol);
             hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream,
                                sl, m, reinterpret_cast<const double2*>(scal + kOffCoef),
                                (int64_t)(kScalStride / 2), psi, ld, D);
@@ -814,6 +915,7 @@ GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, con
             out.E0 = host[0];
             out.residual = host[1];
             out.iters = (int)host[2];
+            if (ctx->progress) ctx->progress(ctx->progress_user, "ground_state", k + 1, max_iter);
             if (host[3] != 0.0 || host[1] <= tol * fmax(1.0, fabs(host[0]))) {
                 out.converged = true;
                 break;

@@ -277,3 +277,18 @@ def test_greens_neq_schedules_agree_multi_orbital(ctx):
                            ntau=4, dtau_grid=0.2, tau_steps_per_grid=2)
     for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed"):
         assert rel_err(a[key], ora[key]) < 1e-10, key
+
+
+@pytest.mark.parametrize("dt,m,direction", [(0.4, 40, -1), (3.0, 64, +1), (0.6, 30, 0)])
+def test_propagate_large_norm_uses_eigendecomposition(ctx, dt, m, direction):
+    """Steps with ||T dt|| well above 2 take the implicit-QL eigen-
+    decomposition path (Eq. (udelta) literally); large Krylov spaces,
+    including the single-space (f = 1 style) long step."""
+    say("SIL large step", dt, m, direction)
+    model = wl.ring8().H
+    sec = basis.Sector(8, 5, 4)
+    H = hamiltonian.Hamiltonian(model, sec)
+    X = np.stack([wl.complex_vector(sec.dim, 40 + c) for c in range(2)])
+    ref = np.stack([propagate.propagate(H.apply, X[c], dt, 3, m, direction, -1.0, "cgs2") for c in range(2)])
+    got = ctx.propagate(ctx.model(model), ctx.sector(8, 5, 4), to_dev(X), 3, dt, m, direction, -1.0, 2)
+    assert rel_err(to_host(got), ref) < 1e-10
