@@ -46,19 +46,53 @@ def parse():
     p.add_argument("--reorth", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-every", type=int, default=1)
+    p.add_argument("--probe", action="store_true",
+                   help="short run for hardware counters: one SIL step of a batch of backward-sweep "
+                        "columns of the same workload, then a plain copy of one vector (calibration)")
+    p.add_argument("--probe-cols", type=int, default=8)
     return p.parse_args()
 
 
+def probe(a):
+    """Launch the dominant kernel in its bench configuration a few times
+    (one SIL step, Krylov dim 20, on --probe-cols c-sector columns of the
+    ladder), then one plain vector copy y = 2x whose FETCH_SIZE/WRITE_SIZE
+    calibrate the counters (16 B x D read, 16 B x D written)."""
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    q = wl.ladder14()
+    ctx = kgf.Context(0)
+    m = ctx.model(q.H)
+    sec = ctx.sector(14, q.n_up - 1, q.n_dn)
+    g = torch.Generator(device="cuda:0").manual_seed(11)
+    X = torch.randn(a.probe_cols, sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
+    ctx.propagate(m, sec, X, 1, q.dt, q.krylov_dim, +1)
+    y = torch.empty_like(X[0])
+    torch.mul(X[0], 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "hv_lanczos", "D": sec.dim, "cols": a.probe_cols,
+                      "vector_bytes": 16 * sec.dim}), flush=True)
+
+
 def measured_traffic():
-    """Per-launch HBM bytes of the dominant kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    """HBM bytes per algorithmic byte of the dominant kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each
+    scaled by the plain-copy calibration).  None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1109_1205_amd", "csrc", "hamiltonian.hip")
+    cur = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    ratio, sha = None, None
     try:
         for line in open(TRAFFIC_FILE):
             if line.startswith("traffic_bytes_per_algorithmic_byte:"):
-                return float(line.split(":", 1)[1].strip())
+                ratio = float(line.split(":", 1)[1].strip())
+            if line.startswith("kernel_source_sha1:"):
+                sha = line.split(":", 1)[1].split()[0]
     except OSError:
-        pass
-    return None
+        return None
+    return ratio if sha == cur else None
 
 
 def cpu_baseline(q):
@@ -81,6 +115,9 @@ def cpu_baseline(q):
 
 def main():
     a = parse()
+    if a.probe:
+        probe(a)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "
               "single-device path in this build", file=sys.stderr)
