@@ -207,6 +207,52 @@ int  kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                     kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
                     double* host_E0, kgf_c128* psi0_out);
 
+/* ---- parameter derivatives and the adjoint (reverse mode) ------------------
+ * Parameters of a model: theta = (t_b for b < n_bonds, eps_up_i, eps_dn_i,
+ * U_i for i < L), n_theta = n_bonds + 3 L; dH/dt_b = -sum_s (c+_i c_j + h.c.),
+ * dH/deps_is = n_is, dH/dU_i = n_i,up n_i,dn (the H of the header comment).
+ * Cotangents follow psi_bar = dL/d(psi*) for a real loss L, so that
+ * dL = 2 Re <psi_bar|d psi>; for G, W is the cotangent with
+ * dL = Re sum conj(W) dG (W = 2 dL/dG* for a loss written in G, G*). */
+int  kgf_n_theta(const kgf_model* model);
+
+/* host_grad[theta] = sum_p Re( host_w[p] <lam_p| dH/dtheta |psi_p> ), for npair
+ * vector pairs at lam + p*ld, psi + p*ld (device).  host_grad has n_theta
+ * doubles and is overwritten. */
+int  kgf_dH_expect(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                   const kgf_c128* lam, const kgf_c128* psi, int npair, int64_t ld,
+                   const kgf_c128* host_w, double* host_grad);
+
+/* Adjoint of kgf_propagate for one vector (direction -1 or +1): psi0 is the
+ * initial state (device, D, unchanged); lam enters as the cotangent of the
+ * state after nsteps steps and leaves as the cotangent of psi0.  host_grad
+ * (n_theta doubles, overwritten) receives dL/dtheta of the propagation:
+ * per step 2 Re[ dir i int_0^dt <lam(s)| dH/dtheta |psi(s)> ds ] (derivative of
+ * the propagator, Sec. 3 Eq. (newstate) taken as exact), the integral by
+ * quad_nodes-point Gauss-Legendre with the node states from each step's own
+ * Krylov spaces (fine-grid evaluation, Eq. (udelta)).  Workspace: nsteps
+ * vectors (the recomputed chain) plus 2 quad_nodes node vectors. */
+int  kgf_propagate_vjp(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                       const kgf_c128* psi0, kgf_c128* lam, int nsteps, const kgf_prop_opts* opts,
+                       int quad_nodes, double* host_grad);
+
+/* Gradient of L = Re sum conj(W^<) G^< + Re sum conj(W^>) G^> for the
+ * four-step G of kgf_greens_neq (plain schedule; same arguments and
+ * layouts), with respect to the parameters of H (host_grad) and of H_ini
+ * (host_grad_ini, through the ground state: d|0> = -(H_ini - E0)^+ (1 - P0)
+ * dH_ini |0>, solved by projected conjugate gradients to relative residual
+ * cg_tol).  host_W_lesser / host_W_greater: [nt][nt][n_orb][n_orb] or NULL
+ * (zero).  Optional outputs: G^<, G^> of the forward pass, E0, the number
+ * of CG iterations.  Cost: about four forward passes; memory: the forward
+ * mesh, the backward-propagated states of every mesh time and one chain. */
+int  kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
+                        const kgf_sector* sector, const kgf_gs_opts* gs_opts, const kgf_c128* v0,
+                        const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
+                        const kgf_prop_opts* opts, const kgf_c128* host_W_lesser,
+                        const kgf_c128* host_W_greater, int quad_nodes, double cg_tol,
+                        double* host_grad_ini, double* host_grad, kgf_c128* host_G_lesser,
+                        kgf_c128* host_G_greater, double* host_E0, int* host_cg_iters);
+
 /* ---- progress reporting ------------------------------------------------------
  * The drivers (kgf_ground_state, kgf_greens_eq, kgf_greens_neq) call
  * fn(user, phase, done, total) on the calling host thread after each mesh

@@ -100,6 +100,11 @@ def load_library():
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
+        "kgf_n_theta": (I, [P]),
+        "kgf_dH_expect": (I, [P, P, P, P, P, I, I64, P, P]),
+        "kgf_propagate_vjp": (I, [P, P, P, P, P, I, C.POINTER(_PropOpts), I, P]),
+        "kgf_greens_neq_vjp": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), P, P, I, D,
+                                   P, P, P, P, C.POINTER(D), C.POINTER(I)]),
         "kgf_profile_begin": (I, [P, I]),
         "kgf_profile_end": (I, [P, C.POINTER(_KStat), I]),
     }
@@ -116,7 +121,8 @@ def exported_symbols() -> Sequence[str]:
             "kgf_model_create", "kgf_model_destroy", "kgf_sector_create", "kgf_sector_destroy",
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
-            "kgf_greens_neq", "kgf_set_progress", "kgf_profile_begin", "kgf_profile_end"]
+            "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
+            "kgf_greens_neq_vjp", "kgf_profile_begin", "kgf_profile_end"]
 
 
 def _check(rc: int):
@@ -378,6 +384,62 @@ class Context:
                 pass
         self._progress_cb = _PROGRESS_FN(cb)
         _check(_lib.kgf_set_progress(self.handle, self._progress_cb, None))
+
+    # -- parameter derivatives / adjoint ------------------------------------
+    def n_theta(self, model: Model) -> int:
+        return _check(_lib.kgf_n_theta(model.handle))
+
+    def dH_expect(self, model: Model, sec: Sector, lam, psi, weights):
+        """sum_p Re(w_p <lam_p| dH/dtheta |psi_p>) for theta = (t_b, eps_up, eps_dn, U)."""
+        npair = self._chk(lam, sec.dim, "lam")
+        if self._chk(psi, sec.dim, "psi") != npair:
+            raise ValueError("lam and psi hold different numbers of vectors")
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.complex128).reshape(-1))
+        if len(w) != npair:
+            raise ValueError("one weight per vector pair")
+        g = np.zeros(self.n_theta(model), dtype=np.float64)
+        _check(_lib.kgf_dH_expect(self.handle, model.handle, sec.handle, _ptr(lam), _ptr(psi), npair, sec.dim,
+                                  _np_ptr(w), _np_ptr(g)))
+        return g
+
+    def propagate_vjp(self, model: Model, sec: Sector, psi0, lam, nsteps: int, dt: float, krylov_dim: int = 15,
+                      direction: int = DIRECTION_FORWARD, reorth: int = 0, quad_nodes: int = 12,
+                      breakdown_tol: float = 1e-13):
+        """Adjoint of propagate(): lam (cotangent of the final state) is
+        replaced in place by the cotangent of psi0; returns dL/dtheta."""
+        self._chk(psi0, sec.dim, "psi0")
+        self._chk(lam, sec.dim, "lam")
+        g = np.zeros(self.n_theta(model), dtype=np.float64)
+        o = _prop(krylov_dim, reorth, dt, direction, 0.0, breakdown_tol)
+        _check(_lib.kgf_propagate_vjp(self.handle, model.handle, sec.handle, _ptr(psi0), _ptr(lam), int(nsteps),
+                                      C.byref(o), int(quad_nodes), _np_ptr(g)))
+        return g
+
+    def greens_neq_vjp(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals, nt: int, steps_per_grid: int,
+                       dt: float, W_lesser=None, W_greater=None, krylov_dim: int = 15, reorth: int = 0,
+                       quad_nodes: int = 12, cg_tol: float = 1e-12, gs_tol: float = 1e-12, gs_max_iter: int = 300,
+                       gs_check_every: int = 1, gs_reorth: int = 2, breakdown_tol: float = 1e-13):
+        """dL/dtheta_ini and dL/dtheta for L = Re sum conj(W^<) G^< + Re sum conj(W^>) G^>."""
+        self._chk(v0, sec.dim, "v0")
+        orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
+        no = len(orbs)
+        shape = (nt, nt, no, no)
+        Wl = None if W_lesser is None else np.ascontiguousarray(np.asarray(W_lesser, dtype=np.complex128).reshape(shape))
+        Wg = None if W_greater is None else np.ascontiguousarray(np.asarray(W_greater, dtype=np.complex128).reshape(shape))
+        gi = np.zeros(self.n_theta(H_ini), dtype=np.float64)
+        g = np.zeros(self.n_theta(H), dtype=np.float64)
+        Gl = _host_c128(shape)
+        Gg = _host_c128(shape)
+        E0 = C.c_double()
+        cgi = C.c_int()
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        gso = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        _check(_lib.kgf_greens_neq_vjp(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(gso), _ptr(v0),
+                                       _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), _np_ptr(Wl),
+                                       _np_ptr(Wg), int(quad_nodes), float(cg_tol), _np_ptr(gi), _np_ptr(g),
+                                       _np_ptr(Gl), _np_ptr(Gg), C.byref(E0), C.byref(cgi)))
+        return {"grad_ini": gi, "grad": g, "G_lesser": Gl, "G_greater": Gg, "E0": E0.value,
+                "cg_iters": cgi.value}
 
     def profile_begin(self, sample_every: int = 1):
         _check(_lib.kgf_profile_begin(self.handle, int(sample_every)))

@@ -1,0 +1,476 @@
+// Reverse mode (adjoint) of the short-iterative-Lanczos propagation and of
+// the four-step nonequilibrium Green's function (Sec. 4), with respect to
+// the parameters theta = (t_b, eps_up_i, eps_dn_i, U_i) of H and of H_ini.
+//
+// A real loss L with dL = Re sum conj(W) dG (W = the cotangent of G) is
+// propagated backwards.  Cotangents are psi_bar = dL/d(psi*), so that
+// dL = 2 Re <psi_bar| d psi>.
+//   * One step psi_{n+1} = exp(delta i H dt) psi_n (delta = -1 forward,
+//     +1 backward; each step is numerically exact in its Krylov space):
+//       psi_bar_n = exp(-delta i H dt) psi_bar_{n+1},
+//       dL/dtheta += 2 Re[ delta i int_0^dt <lam(s)| dH/dtheta |psi(s)> ds ],
+//       psi(s) = exp(delta i H s) psi_n, lam(s) = exp(-delta i H (dt - s)) psi_bar_{n+1}
+//     (derivative of the exponential under the integral, Duhamel form).  The
+//     integral uses Gauss-Legendre nodes; the states at the nodes come from
+//     the step's own Krylov spaces (the fine-grid evaluation of Eq. (udelta)).
+//   * c_a and c+_a are parameter free; their adjoints are c+_a and c_a.
+//   * Ground state: d|0> = -(H_ini - E0)^+ (1 - P0) dH_ini |0> gives
+//     dL/dtheta_ini = -2 Re <mu| dH_ini/dtheta |0>, (H_ini - E0) mu = (1 - P0) 0_bar,
+//     mu orthogonal to |0> (projected conjugate gradients).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+
+#include "kgf_internal.h"
+
+namespace kgf {
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// Gauss-Legendre nodes x_q and weights w_q on [-1, 1] (Newton on P_q).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(q, 0.0);
+    w.assign(q, 0.0);
+    for (int i = 0; i < q; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double pq = q == 1 ? z : p1;
+            const double pqm1 = q == 1 ? 1.0 : p0;
+            const double dp = q * (z * pq - pqm1) / (z * z - 1.0);
+            const double dz = pq / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= q; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double pq = q == 1 ? z : p1;
+        const double pqm1 = q == 1 ? 1.0 : p0;
+        const double dp = q * (z * pq - pqm1) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+__global__ void k_axpy(double2* __restrict__ y, const double2* __restrict__ x, double ar, double ai, int64_t D) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = x[i];
+        double2 b = y[i];
+        b.x += ar * a.x - ai * a.y;
+        b.y += ar * a.y + ai * a.x;
+        y[i] = b;
+    }
+}
+
+// p = r + beta p
+__global__ void k_xpby(double2* __restrict__ p, const double2* __restrict__ r, double beta, int64_t D) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = r[i];
+        const double2 b = p[i];
+        p[i] = make_double2(a.x + beta * b.x, a.y + beta * b.y);
+    }
+}
+
+// out[y] = sum_z C[y][z] in[z] for ny outputs (dense complex combination)
+__global__ __launch_bounds__(kThreads) void k_lincomb(const double2* __restrict__ in, int64_t in_col, int nz,
+                                                      const double2* __restrict__ C, double2* __restrict__ out,
+                                                      int64_t out_col, int64_t D) {
+    const int y = blockIdx.y;
+    const double2* c = C + (int64_t)y * nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int z = 0; z < nz; ++z) {
+            const double2 a = in[z * in_col + i];
+            const double2 h = c[z];
+            re = fma(h.x, a.x, fma(-h.y, a.y, re));
+            im = fma(h.x, a.y, fma(h.y, a.x, im));
+        }
+        out[y * out_col + i] = make_double2(re, im);
+    }
+}
+
+int grid_for(int64_t D) {
+    int64_t b = (D + kThreads * 4 - 1) / (kThreads * 4);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+}
+
+void axpy(kgf_ctx* ctx, double2* y, const double2* x, cplx a, int64_t D) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(D)), dim3(kThreads), 0, ctx->stream, y, x, a.real(), a.imag(), D);
+    check_launch("k_axpy");
+}
+
+cplx dot(kgf_ctx* ctx, const double2* a, const double2* b, int64_t D) {
+    double2* d = static_cast<double2*>(workspace(ctx, "adj_dot", sizeof(double2)));
+    block_dots(ctx, a, D, 1, b, D, 1, D, d);
+    double2 h;
+    KGF_HIP(hipMemcpyAsync(&h, d, sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    return cplx(h.x, h.y);
+}
+
+std::unique_ptr<kgf_sector> adj_sector(kgf_ctx* ctx, int L, int nu, int nd) {
+    if (nu < 0 || nu > L || nd < 0 || nd > L) return nullptr;
+    std::unique_ptr<kgf_sector> s(new kgf_sector());
+    s->ctx = ctx;
+    s->L = L;
+    s->n_up = nu;
+    s->n_dn = nd;
+    s->d_up = binom_host(L, nu);
+    s->d_dn = binom_host(L, nd);
+    s->masks_up.reserve(sizeof(uint32_t) * s->d_up);
+    s->masks_dn.reserve(sizeof(uint32_t) * s->d_dn);
+    build_masks(ctx, L, nu, s->masks_up.as<uint32_t>(), s->d_up);
+    build_masks(ctx, L, nd, s->masks_dn.as<uint32_t>(), s->d_dn);
+    return s;
+}
+
+}  // namespace
+
+// One adjoint step of psi_{n+1} = exp(delta i H dt) psi_n (see the file header).
+// lam: on entry psi_bar_{n+1}, on return psi_bar_n.  g (device) accumulates.
+void sil_adjoint_step(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi_n, double2* lam,
+                      double dt, int delta, const SilOpts& o, int nq, double* g) {
+    const int64_t D = sec->dim();
+    const int m = o.m;
+    double2* pair = static_cast<double2*>(workspace(ctx, "adj_pair", sizeof(double2) * 2 * D));
+    KGF_HIP(hipMemcpyAsync(pair, psi_n, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(pair + D, lam, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    sil_build(ctx, model, sec, pair, 2, D, o);
+    std::vector<double> xq, wq;
+    gauss_legendre(nq, xq, wq);
+    const int nreq = 2 * nq + 1;
+    std::vector<int> col(nreq), dir(nreq);
+    std::vector<double> tt(nreq);
+    for (int q = 0; q < nq; ++q) {
+        const double s = 0.5 * dt * (1.0 + xq[q]);
+        col[q] = 0, dir[q] = delta, tt[q] = s;                       // psi(s)
+        col[nq + q] = 1, dir[nq + q] = -delta, tt[nq + q] = dt - s;  // lam(s)
+    }
+    col[2 * nq] = 1, dir[2 * nq] = -delta, tt[2 * nq] = dt;          // new cotangent
+    double2* coef = static_cast<double2*>(workspace(ctx, "adj_coef", sizeof(double2) * nreq * m));
+    sil_coefs(ctx, m, nreq, col.data(), tt.data(), dir.data(), 0.0, coef, m);
+    double2* nodes = static_cast<double2*>(workspace(ctx, "adj_nodes", sizeof(double2) * 2 * nq * D));
+    sil_combine_multi(ctx, sec, pair, D, 2, m, 0, coef, m, nq, nodes, D);
+    sil_combine_multi(ctx, sec, pair, D, 2, m, 1, coef + (size_t)nq * m, m, nq, nodes + (size_t)nq * D, D);
+    sil_combine_multi(ctx, sec, pair, D, 2, m, 1, coef + (size_t)2 * nq * m, m, 1, lam, D);
+    std::vector<double2> om(nq);
+    for (int q = 0; q < nq; ++q) {
+        // 2 Re[delta i (dt/2) w_q <lam|dH|psi>]  ->  weight delta i dt w_q
+        om[q] = make_double2(0.0, delta * dt * wq[q]);
+    }
+    dH_expect(ctx, model, sec, nodes + (size_t)nq * D, D, nodes, D, nq, om.data(), g);
+}
+
+// Adjoint of a chain x_{n+1} = exp(delta i H dt) x_n, n < nsteps, from x_0.
+// lam: in the cotangent of x_nsteps, out the cotangent of x_0.
+void chain_adjoint(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* x0, int nsteps, double dt,
+                   int delta, const SilOpts& o, int nq, double2* lam, double* g) {
+    if (nsteps <= 0) return;
+    const int64_t D = sec->dim();
+    ensure_device_fits(sizeof(double2) * (size_t)nsteps * D, "adjoint chain states");
+    double2* S = static_cast<double2*>(workspace(ctx, "adj_chain", sizeof(double2) * (size_t)nsteps * D));
+    KGF_HIP(hipMemcpyAsync(S, x0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    SilOpts so = o;
+    so.dt = dt;
+    so.direction = delta;
+    for (int n = 1; n < nsteps; ++n) {
+        KGF_HIP(hipMemcpyAsync(S + (size_t)n * D, S + (size_t)(n - 1) * D, sizeof(double2) * D,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        sil_propagate(ctx, model, sec, S + (size_t)n * D, 1, D, 1, so);
+    }
+    for (int n = nsteps - 1; n >= 0; --n) sil_adjoint_step(ctx, model, sec, S + (size_t)n * D, lam, dt, delta, o, nq, g);
+}
+
+// (H - E0) mu = (1 - P0) r, mu orthogonal to psi0 (unit norm), by projected CG.
+static int projected_cg(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0, double E0,
+                        const double2* rhs, double2* mu, double tol, int maxit) {
+    const int64_t D = sec->dim();
+    double2* r = static_cast<double2*>(workspace(ctx, "cg_r", sizeof(double2) * D));
+    double2* p = static_cast<double2*>(workspace(ctx, "cg_p", sizeof(double2) * D));
+    double2* Ap = static_cast<double2*>(workspace(ctx, "cg_Ap", sizeof(double2) * D));
+    KGF_HIP(hipMemsetAsync(mu, 0, sizeof(double2) * D, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(r, rhs, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    axpy(ctx, r, psi0, -dot(ctx, psi0, r, D), D);
+    KGF_HIP(hipMemcpyAsync(p, r, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    double rr = dot(ctx, r, r, D).real();
+    const double bnorm = std::sqrt(rr);
+    if (bnorm == 0.0) return 0;
+    int it = 0;
+    for (; it < maxit; ++it) {
+        apply_h(ctx, model, sec, p, Ap, 1, D);
+        axpy(ctx, Ap, p, cplx(-E0, 0.0), D);
+        axpy(ctx, Ap, psi0, -dot(ctx, psi0, Ap, D), D);
+        const double pAp = dot(ctx, p, Ap, D).real();
+        if (!(pAp > 0.0)) break;
+        const double alpha = rr / pAp;
+        axpy(ctx, mu, p, cplx(alpha, 0.0), D);
+        axpy(ctx, r, Ap, cplx(-alpha, 0.0), D);
+        const double rr2 = dot(ctx, r, r, D).real();
+        if (std::sqrt(rr2) <= tol * bnorm) {
+            ++it;
+            break;
+        }
+        hipLaunchKernelGGL(k_xpby, dim3(grid_for(D)), dim3(kThreads), 0, ctx->stream, p, r, rr2 / rr, D);
+        check_launch("k_xpby");
+        rr = rr2;
+    }
+    axpy(ctx, mu, psi0, -dot(ctx, psi0, mu, D), D);
+    return it;
+}
+
+struct VjpArgs {
+    kgf_model* H_ini;
+    kgf_model* H;
+    const kgf_sector* sec;
+    const int32_t* orbs;
+    int norb, nt, spg;
+    SilOpts o;
+    int nq;
+    double cg_tol;
+    int cg_maxit;
+};
+
+static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const double2* v0, const kgf_gs_opts* gso,
+                          const double2* Wl, const double2* Wg, double* grad_ini_host, double* grad_host,
+                          double2* Gl_host, double2* Gg_host, double* E0_out, int* cg_iters) {
+    const kgf_sector* sec = A.sec;
+    const int64_t D = sec->dim();
+    const int nt = A.nt, norb = A.norb, L = sec->L;
+    const double dt = A.o.dt;
+    // (i) ground state
+    double2* psi0 = static_cast<double2*>(workspace(ctx, "vjp_psi0", sizeof(double2) * D));
+    GsResult gs = ground_state(ctx, A.H_ini, sec, v0, psi0, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
+    ctx->ws.erase("gs_V");
+    KGF_REQUIRE(gs.converged, KGF_ENOCONV, "adjoint: ground state of H_ini did not converge");
+    const double E0 = gs.E0;
+    *E0_out = E0;
+    // (ii) forward mesh
+    ensure_device_fits(sizeof(double2) * (size_t)2 * nt * D, "adjoint forward mesh");
+    double2* Phi = static_cast<double2*>(workspace(ctx, "vjp_phi", sizeof(double2) * (size_t)nt * D));
+    double2* Phib = static_cast<double2*>(workspace(ctx, "vjp_phibar", sizeof(double2) * (size_t)nt * D));
+    KGF_HIP(hipMemsetAsync(Phib, 0, sizeof(double2) * (size_t)nt * D, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(Phi, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    SilOpts fo = A.o;
+    fo.direction = -1;
+    for (int k = 1; k < nt; ++k) {
+        KGF_HIP(hipMemcpyAsync(Phi + (size_t)k * D, Phi + (size_t)(k - 1) * D, sizeof(double2) * D,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        sil_propagate(ctx, A.H, sec, Phi + (size_t)k * D, 1, D, A.spg, fo);
+    }
+    const int nth = n_theta(A.H), nthi = n_theta(A.H_ini);
+    double* g = static_cast<double*>(workspace(ctx, "vjp_g", sizeof(double) * (nth + nthi)));
+    double* gi = g + nth;
+    KGF_HIP(hipMemsetAsync(g, 0, sizeof(double) * (nth + nthi), ctx->stream));
+    const size_t gsz = (size_t)nt * nt * norb * norb;
+    std::vector<double2> Gl(gsz, make_double2(0, 0)), Gg(gsz, make_double2(0, 0));
+    auto Widx = [&](int j, int k, int a, int b) { return (((size_t)j * nt + k) * norb + a) * norb + b; };
+    SilOpts bo = A.o;
+    bo.direction = +1;
+    // (iii)+(iv) and their adjoints, per spin group and operator
+    for (int spin = 0; spin < 2; ++spin) {
+        std::vector<int> loc;
+        for (int a = 0; a < norb; ++a)
+            if ((A.orbs[a] & 1) == spin) loc.push_back(a);
+        const int na = (int)loc.size();
+        if (!na) continue;
+        for (int dagger = 0; dagger < 2; ++dagger) {
+            const double2* W = dagger ? Wg : Wl;
+            auto tgt = adj_sector(ctx, L, sec->n_up + (spin == 0 ? (dagger ? 1 : -1) : 0),
+                                  sec->n_dn + (spin == 1 ? (dagger ? 1 : -1) : 0));
+            if (!tgt || tgt->dim() == 0) continue;
+            const int64_t Dt = tgt->dim();
+            const int N = na * nt;
+            ensure_device_fits(sizeof(double2) * (size_t)2 * N * Dt, "adjoint state mesh");
+            double2* Psi = static_cast<double2*>(workspace(ctx, "vjp_psi", sizeof(double2) * (size_t)N * Dt));
+            double2* Psib = static_cast<double2*>(workspace(ctx, "vjp_psibar", sizeof(double2) * (size_t)N * Dt));
+            for (int q = 0; q < na; ++q)
+                for (int k = 0; k < nt; ++k) {
+                    double2* x = Psi + ((size_t)q * nt + k) * Dt;
+                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, x, 1, D, Dt);
+                    if (k > 0) sil_propagate(ctx, A.H, tgt.get(), x, 1, Dt, k * A.spg, bo);
+                }
+            // Gram matrix raw[(b,s)][(a,j)] = <Psi_b(s)|Psi_a(j)>, then G on the host side of the ABI
+            double2* raw = static_cast<double2*>(workspace(ctx, "vjp_raw", sizeof(double2) * (size_t)N * N));
+            block_dots(ctx, Psi, Dt, N, Psi, Dt, N, Dt, raw);
+            std::vector<double2> rh((size_t)N * N);
+            KGF_HIP(hipMemcpyAsync(rh.data(), raw, sizeof(double2) * rh.size(), hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            for (int a = 0; a < na; ++a)
+                for (int b = 0; b < na; ++b)
+                    for (int j = 0; j < nt; ++j)
+                        for (int s = 0; s < nt; ++s) {
+                            // lesser: G[j][s][A][B] = i <Psi_B(s)|Psi_A(j)>; greater: -i <chi_A(j)|chi_B(s)>
+                            const double2 z = rh[((size_t)b * nt + s) * N + (size_t)a * nt + j];
+                            const double2 zg = rh[((size_t)a * nt + j) * N + (size_t)b * nt + s];
+                            if (!dagger) Gl[Widx(j, s, loc[a], loc[b])] = make_double2(-z.y, z.x);
+                            else Gg[Widx(j, s, loc[a], loc[b])] = make_double2(zg.y, -zg.x);
+                        }
+            if (!W) continue;
+            // cotangents of the mesh states: Psi_bar = C Psi (see the file header)
+            std::vector<double2> C((size_t)N * N);
+            for (int x = 0; x < na; ++x)
+                for (int m = 0; m < nt; ++m)
+                    for (int a = 0; a < na; ++a)
+                        for (int j = 0; j < nt; ++j) {
+                            const double2 w1 = W[Widx(j, m, loc[a], loc[x])];
+                            const double2 w2 = W[Widx(m, j, loc[x], loc[a])];
+                            cplx c;
+                            if (!dagger)   // (i/2)[conj(W[j][m][a][x]) - W[m][j][x][a]]
+                                c = cplx(0.0, 0.5) * (std::conj(cplx(w1.x, w1.y)) - cplx(w2.x, w2.y));
+                            else           // (i/2)[W[j][m][a][x] - conj(W[m][j][x][a])]
+                                c = cplx(0.0, 0.5) * (cplx(w1.x, w1.y) - std::conj(cplx(w2.x, w2.y)));
+                            C[((size_t)x * nt + m) * N + (size_t)a * nt + j] = make_double2(c.real(), c.imag());
+                        }
+            double2* Cd = static_cast<double2*>(workspace(ctx, "vjp_C", sizeof(double2) * C.size()));
+            KGF_HIP(hipMemcpy(Cd, C.data(), sizeof(double2) * C.size(), hipMemcpyHostToDevice));
+            for (int y0 = 0; y0 < N; y0 += 65535) {
+                const int ny = std::min(N - y0, 65535);
+                hipLaunchKernelGGL(k_lincomb, dim3(grid_for(Dt), ny), dim3(kThreads), 0, ctx->stream, Psi, Dt, N,
+                                   Cd + (size_t)y0 * N, Psib + (size_t)y0 * Dt, Dt, Dt);
+                check_launch("k_lincomb");
+            }
+            // back through each chain, then through c_a (adjoint c+_a) or c+_a (adjoint c_a)
+            double2* xs = static_cast<double2*>(workspace(ctx, "vjp_x0", sizeof(double2) * Dt));
+            double2* back = static_cast<double2*>(workspace(ctx, "vjp_back", sizeof(double2) * D));
+            for (int q = 0; q < na; ++q)
+                for (int k = 0; k < nt; ++k) {
+                    double2* lam = Psib + ((size_t)q * nt + k) * Dt;
+                    if (k > 0) {
+                        apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, xs, 1, D, Dt);
+                        chain_adjoint(ctx, A.H, tgt.get(), xs, k * A.spg, dt, +1, A.o, A.nq, lam, g);
+                    }
+                    apply_c(ctx, tgt.get(), sec, A.orbs[loc[q]], dagger ? 0 : 1, lam, back, 1, Dt, D);
+                    axpy(ctx, Phib + (size_t)k * D, back, cplx(1.0, 0.0), D);
+                    progress(ctx, dagger ? "adjoint_greater" : "adjoint_lesser", (int64_t)q * nt + k + 1, N);
+                }
+        }
+    }
+    // adjoint of the forward mesh Phi(t_k) = exp(-iH dt)^(k spg) |0>
+    double2* lam = static_cast<double2*>(workspace(ctx, "vjp_lam", sizeof(double2) * D));
+    KGF_HIP(hipMemcpyAsync(lam, Phib + (size_t)(nt - 1) * D, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    for (int k = nt - 1; k >= 1; --k) {
+        chain_adjoint(ctx, A.H, sec, Phi + (size_t)(k - 1) * D, A.spg, dt, -1, A.o, A.nq, lam, g);
+        axpy(ctx, lam, Phib + (size_t)(k - 1) * D, cplx(1.0, 0.0), D);
+        progress(ctx, "adjoint_forward", nt - k, nt - 1);
+    }
+    // ground state of H_ini
+    if (Wl || Wg) {
+        double2* mu = static_cast<double2*>(workspace(ctx, "vjp_mu", sizeof(double2) * D));
+        *cg_iters = projected_cg(ctx, A.H_ini, sec, psi0, E0, lam, mu, A.cg_tol, A.cg_maxit);
+        const double2 wm = make_double2(-2.0, 0.0);
+        dH_expect(ctx, A.H_ini, sec, mu, D, psi0, D, 1, &wm, gi);
+    }
+    std::vector<double> gh(nth + nthi);
+    KGF_HIP(hipMemcpyAsync(gh.data(), g, sizeof(double) * gh.size(), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    if (grad_host) std::copy(gh.begin(), gh.begin() + nth, grad_host);
+    if (grad_ini_host) std::copy(gh.begin() + nth, gh.end(), grad_ini_host);
+    if (Gl_host) std::copy(Gl.begin(), Gl.end(), Gl_host);
+    if (Gg_host) std::copy(Gg.begin(), Gg.end(), Gg_host);
+    for (const char* n : {"vjp_phi", "vjp_phibar", "vjp_psi", "vjp_psibar", "adj_chain", "sil_X", "adj_nodes"})
+        ctx->ws.erase(n);
+}
+
+}  // namespace kgf
+
+using namespace kgf;
+
+extern "C" {
+
+int kgf_n_theta(const kgf_model* model) { return model ? kgf::n_theta(model) : KGF_EINVAL; }
+
+int kgf_dH_expect(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector, const kgf_c128* lam,
+                  const kgf_c128* psi, int npair, int64_t ld, const kgf_c128* host_w, double* host_grad) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && model && sector && host_grad && host_w, KGF_EINVAL, "kgf_dH_expect: NULL argument");
+        KGF_REQUIRE(model->L == sector->L, KGF_EINVAL, "kgf_dH_expect: model and sector L differ");
+        KGF_REQUIRE(npair >= 0 && ld >= sector->dim(), KGF_EINVAL, "kgf_dH_expect: bad npair / ld");
+        KGF_REQUIRE(npair == 0 || (lam && psi), KGF_EINVAL, "kgf_dH_expect: NULL vector");
+        KGF_HIP(hipSetDevice(ctx->device));
+        const int nth = n_theta(model);
+        double* g = static_cast<double*>(workspace(ctx, "abi_grad", sizeof(double) * nth));
+        KGF_HIP(hipMemsetAsync(g, 0, sizeof(double) * nth, ctx->stream));
+        if (npair > 0 && sector->dim() > 0)
+            dH_expect(ctx, const_cast<kgf_model*>(model), sector, reinterpret_cast<const double2*>(lam), ld,
+                      reinterpret_cast<const double2*>(psi), ld, npair, reinterpret_cast<const double2*>(host_w), g);
+        KGF_HIP(hipMemcpyAsync(host_grad, g, sizeof(double) * nth, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+    });
+}
+
+int kgf_propagate_vjp(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector, const kgf_c128* psi0,
+                      kgf_c128* lam, int nsteps, const kgf_prop_opts* opts, int quad_nodes, double* host_grad) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && model && sector && psi0 && lam && host_grad, KGF_EINVAL,
+                    "kgf_propagate_vjp: NULL argument");
+        KGF_REQUIRE(model->L == sector->L, KGF_EINVAL, "kgf_propagate_vjp: model and sector L differ");
+        check_prop_opts(opts);
+        KGF_REQUIRE(opts->direction == -1 || opts->direction == 1, KGF_EINVAL,
+                    "kgf_propagate_vjp: direction must be -1 or +1");
+        KGF_REQUIRE(nsteps >= 0 && quad_nodes >= 1 && quad_nodes <= 31, KGF_EINVAL,
+                    "kgf_propagate_vjp: bad nsteps / quad_nodes");
+        KGF_HIP(hipSetDevice(ctx->device));
+        const int nth = n_theta(model);
+        double* g = static_cast<double*>(workspace(ctx, "abi_grad", sizeof(double) * nth));
+        KGF_HIP(hipMemsetAsync(g, 0, sizeof(double) * nth, ctx->stream));
+        SilOpts o = to_sil_opts(opts);
+        chain_adjoint(ctx, const_cast<kgf_model*>(model), sector, reinterpret_cast<const double2*>(psi0), nsteps, o.dt,
+                      o.direction, o, quad_nodes, reinterpret_cast<double2*>(lam), g);
+        KGF_HIP(hipMemcpyAsync(host_grad, g, sizeof(double) * nth, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        ctx->ws.erase("adj_chain");
+    });
+}
+
+int kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
+                       const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb, int nt,
+                       int steps_per_grid, const kgf_prop_opts* opts, const kgf_c128* host_W_lesser,
+                       const kgf_c128* host_W_greater, int quad_nodes, double cg_tol, double* host_grad_ini,
+                       double* host_grad, kgf_c128* host_G_lesser, kgf_c128* host_G_greater, double* host_E0,
+                       int* host_cg_iters) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && H_ini && H && sector && gs_opts && v0 && host_orbs && host_E0, KGF_EINVAL,
+                    "kgf_greens_neq_vjp: NULL argument");
+        KGF_REQUIRE(H_ini->L == sector->L && H->L == sector->L, KGF_EINVAL,
+                    "kgf_greens_neq_vjp: models and sector differ in L");
+        check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && quad_nodes >= 1 && quad_nodes <= 31 &&
+                        std::isfinite(cg_tol) && cg_tol > 0.0,
+                    KGF_EINVAL, "kgf_greens_neq_vjp: bad sizes");
+        for (int a = 0; a < n_orb; ++a)
+            KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
+                        "kgf_greens_neq_vjp: orbital out of range");
+        KGF_HIP(hipSetDevice(ctx->device));
+        VjpArgs A;
+        A.H_ini = const_cast<kgf_model*>(H_ini);
+        A.H = const_cast<kgf_model*>(H);
+        A.sec = sector;
+        A.orbs = host_orbs;
+        A.norb = n_orb;
+        A.nt = nt;
+        A.spg = steps_per_grid;
+        A.o = to_sil_opts(opts);
+        A.nq = quad_nodes;
+        A.cg_tol = cg_tol;
+        A.cg_maxit = 20000;
+        int cgi = 0;
+        four_step_vjp(ctx, A, reinterpret_cast<const double2*>(v0), gs_opts,
+                      reinterpret_cast<const double2*>(host_W_lesser), reinterpret_cast<const double2*>(host_W_greater),
+                      host_grad_ini, host_grad, reinterpret_cast<double2*>(host_G_lesser),
+                      reinterpret_cast<double2*>(host_G_greater), host_E0, &cgi);
+        if (host_cg_iters) *host_cg_iters = cgi;
+    });
+}
+
+}  // extern "C"

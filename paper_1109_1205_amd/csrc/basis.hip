@@ -114,6 +114,27 @@ __global__ void k_hop_table(const uint32_t* __restrict__ masks, int64_t D, int n
     for (int k = c; k < width; ++k) ent[(int64_t)k * D + r] = 0u;
 }
 
+// per-bond form of the same table: bond[b * D + r] = target | sign << 31, or ~0u
+__global__ void k_bond_table(const uint32_t* __restrict__ masks, int64_t D, int nb,
+                             const int32_t* __restrict__ bi, const int32_t* __restrict__ bj,
+                             const uint64_t* __restrict__ C, uint32_t* __restrict__ out) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= D) return;
+    uint32_t s = masks[r];
+    for (int b = 0; b < nb; ++b) {
+        int i = bi[b], j = bj[b];
+        uint32_t v = ~0u;
+        if ((((s >> i) ^ (s >> j)) & 1u) != 0u) {
+            uint32_t s2 = s ^ (1u << i) ^ (1u << j);
+            int lo = i < j ? i : j, hi = i < j ? j : i;
+            uint32_t between = ((1u << hi) - 1u) & ~((2u << lo) - 1u);
+            uint32_t sign = (uint32_t)(__popc(s & between) & 1);
+            v = (uint32_t)mask_rank(s2, C) | (sign << 31);
+        }
+        out[(int64_t)b * D + r] = v;
+    }
+}
+
 __global__ void k_onsite(const uint32_t* __restrict__ masks, int64_t D, int L,
                          const double* __restrict__ eu, const double* __restrict__ ed,
                          double* __restrict__ out_up, double* __restrict__ out_dn) {
@@ -145,6 +166,7 @@ HopTable& hop_table(kgf_model* model, int n) {
     t->ent.reserve(sizeof(uint32_t) * (D * t->width ? D * t->width : 1));
     t->e_up.reserve(sizeof(double) * (D ? D : 1));
     t->e_dn.reserve(sizeof(double) * (D ? D : 1));
+    t->bond.reserve(sizeof(uint32_t) * (D * model->nb ? D * model->nb : 1));
     if (D) {
         build_masks(ctx, model->L, n, t->masks.as<uint32_t>(), D);
         DevBuf dbi, dbj, deu, ded;
@@ -168,6 +190,10 @@ HopTable& hop_table(kgf_model* model, int n) {
                            ctx->binom.as<uint64_t>(), t->count.as<int32_t>(), t->ent.as<uint32_t>(),
                            t->width);
         check_launch("k_hop_table");
+        hipLaunchKernelGGL(k_bond_table, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream,
+                           t->masks.as<uint32_t>(), D, model->nb, dbi.as<int32_t>(), dbj.as<int32_t>(),
+                           ctx->binom.as<uint64_t>(), t->bond.as<uint32_t>());
+        check_launch("k_bond_table");
         hipLaunchKernelGGL(k_onsite, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream,
                            t->masks.as<uint32_t>(), D, model->L, deu.as<double>(), ded.as<double>(),
                            t->e_up.as<double>(), t->e_dn.as<double>());

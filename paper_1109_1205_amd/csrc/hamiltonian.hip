@@ -356,6 +356,135 @@ __global__ __launch_bounds__(kThreads) void k_apply_c_dn(
     }
 }
 
+// ---------------------------------------------------------------------------
+// <lam| dH/dtheta |psi> for every parameter in one pass (one block per row u).
+// theta = (t_b [nb], eps_up [L], eps_dn [L], U [L]).  With z = w conj(lam):
+//   dH/dt_b = -K_b:  up part  sum_d z[u,d] sign psi[u', d]   (entries of row u)
+//                    down part sum_d z[u,d] sign psi[u, d'_b(d)]   (per-bond table)
+//   n_{i up}: bit_i(m_u) sum_d z psi;  n_{i dn}: sum_d z psi bit_i(m_d);
+//   n_{i up} n_{i dn}: bit_i(m_u) sum_d z psi bit_i(m_d).
+// Real parts only (the gradient of a real loss).  Per-wave partial sums in
+// LDS, then one value per (row, theta) in part[u][theta] (fixed-order sums).
+// ---------------------------------------------------------------------------
+constexpr int kThetaMax = kMaxBonds + 3 * kMaxL;
+constexpr size_t kDhLdsMax = 112 * 1024;
+
+template <bool STAGE>
+__global__ __launch_bounds__(kHvThreads) void k_dH(HvTables T, const uint32_t* __restrict__ bdn, int rpx,
+                                                   int L, const double2* __restrict__ lam,
+                                                   const double2* __restrict__ psi, double wr, double wi,
+                                                   double* __restrict__ part, int ntheta) {
+    extern __shared__ double2 sm[];
+    __shared__ double s_acc[kHvThreads / 64][kThetaMax];
+    __shared__ int64_t s_uprow[kMaxBonds + 1];
+    __shared__ int s_upb[kMaxBonds + 1];
+    __shared__ double s_ups[kMaxBonds + 1];
+    const int blk = blockIdx.x;
+    const int64_t u = (int64_t)(blk & 7) * rpx + (blk >> 3);
+    if (u >= T.Dup) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nw = blockDim.x >> 6;
+    const int64_t Ddn = T.Ddn;
+    const double2* __restrict__ lrow = lam + u * Ddn;
+    const double2* __restrict__ prow = psi + u * Ddn;
+    for (int i = tid; i < nw * kThetaMax; i += blockDim.x) (&s_acc[0][0])[i] = 0.0;
+    if (STAGE) {
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+            const double2 l = lrow[d];
+            sm[d] = make_double2(wr * l.x + wi * l.y, wi * l.x - wr * l.y);   // w conj(l)
+            sm[Ddn + d] = prow[d];
+        }
+    }
+    const int cu = T.cnt_up[u];
+    for (int k = tid; k < cu; k += blockDim.x) {
+        const uint32_t e = T.ent_up[(int64_t)k * T.Dup + u];
+        s_uprow[k] = (int64_t)(e & 0xFFFFFFu) * Ddn;
+        s_upb[k] = (int)((e >> 24) & 127u);
+        s_ups[k] = (e >> 31) ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    auto zval = [&](int64_t d) -> double2 {
+        if (STAGE) return sm[d];
+        const double2 l = lrow[d];
+        return make_double2(wr * l.x + wi * l.y, wi * l.x - wr * l.y);
+    };
+    auto pown = [&](int64_t d) -> double2 { return STAGE ? sm[Ddn + d] : prow[d]; };
+    auto wave_add = [&](double v, int slot) {
+        v = wave_sum(v);
+        if (lane == 0) s_acc[wv][slot] += v;
+    };
+    const uint32_t mu = T.mu[u];
+    // densities and double occupancy
+    {
+        double R = 0.0, Ri[kMaxL];
+#pragma unroll
+        for (int i = 0; i < kMaxL; ++i) Ri[i] = 0.0;
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+            const double2 z = zval(d), p = pown(d);
+            const double re = z.x * p.x - z.y * p.y;
+            const uint32_t md = T.md[d];
+            R += re;
+#pragma unroll
+            for (int i = 0; i < kMaxL; ++i) Ri[i] += ((md >> i) & 1u) ? re : 0.0;
+        }
+        const int nb = T.nb;
+        for (int i = 0; i < L; ++i) {
+            double r = 0.0;
+#pragma unroll
+            for (int j = 0; j < kMaxL; ++j)
+                if (j == i) r = Ri[j];
+            const double bu = ((mu >> i) & 1u) ? 1.0 : 0.0;
+            const double sRi = wave_sum(r);
+            if (lane == 0) {
+                s_acc[wv][nb + L + i] += sRi;         // eps_dn_i
+                s_acc[wv][nb + 2 * L + i] += bu * sRi; // U_i
+            }
+        }
+        const double sR = wave_sum(R);
+        if (lane == 0)
+            for (int i = 0; i < L; ++i)
+                if ((mu >> i) & 1u) s_acc[wv][nb + i] += sR;   // eps_up_i
+    }
+    // up-spin hops of row u
+    for (int k = 0; k < cu; ++k) {
+        const double2* __restrict__ src = psi + s_uprow[k];
+        double acc = 0.0;
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+            const double2 z = zval(d), p = src[d];
+            acc += z.x * p.x - z.y * p.y;
+        }
+        wave_add(-s_ups[k] * acc, s_upb[k]);
+    }
+    // down-spin hops, one bond at a time
+    for (int b = 0; b < T.nb; ++b) {
+        double acc = 0.0;
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+            const uint32_t e = bdn[(int64_t)b * Ddn + d];
+            if (e == ~0u) continue;
+            const double2 z = zval(d);
+            const double2 p = STAGE ? sm[Ddn + (e & 0x7FFFFFFFu)] : prow[e & 0x7FFFFFFFu];
+            const double v = z.x * p.x - z.y * p.y;
+            acc += (e >> 31) ? -v : v;
+        }
+        wave_add(-acc, b);
+    }
+    __syncthreads();
+    for (int t = tid; t < ntheta; t += blockDim.x) {
+        double sacc = 0.0;
+        for (int w2 = 0; w2 < nw; ++w2) sacc += s_acc[w2][t];
+        part[u * ntheta + t] = sacc;
+    }
+}
+
+__global__ void k_dH_fin(const double* __restrict__ part, int64_t nrow, int ntheta, double* __restrict__ g) {
+    __shared__ double sh[kThreads / 64];
+    const int t = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < nrow; r += blockDim.x) acc += part[r * ntheta + t];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) g[t] += s;
+}
+
 template <int MODE>
 void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
                const double2* x, int64_t x_col, const double2* xp, int64_t xp_col, double2* y,
@@ -411,6 +540,43 @@ void hv_lanczos(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a) {
     launch_hv<1>(ctx, model, sec, ncol, a.x, a.x_col, a.xp, a.xp_col, a.y, a.y_col, a.s_k, a.b_k,
                  a.s_km1, a.stride, a.part);
+}
+
+int n_theta(const kgf_model* model) { return model->nb + 3 * model->L; }
+
+void dH_expect(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* lam, int64_t lam_col,
+               const double2* psi, int64_t psi_col, int npair, const double2* host_w, double* g) {
+    HvTables T = make_tables(model, sec);
+    HopTable& td = hop_table(model, sec->n_dn);
+    const int nth = n_theta(model);
+    KGF_REQUIRE(nth <= kThetaMax, KGF_EUNSUPPORTED, "dH: too many parameters");
+    const int rpx = (int)((sec->d_up + 7) / 8);
+    double* part = static_cast<double*>(workspace(ctx, "dH_part", sizeof(double) * (size_t)sec->d_up * nth));
+    const size_t stage = 2 * sizeof(double2) * (size_t)sec->d_dn;
+    for (int p = 0; p < npair; ++p) {
+        const double2 w = host_w[p];
+        {
+            Prof pr(ctx, "dH_expect", 32.0 * (double)sec->dim());
+            if (stage <= kDhLdsMax) {
+                static bool opted[64] = {};
+                if (!opted[ctx->device & 63]) {
+                    KGF_HIP(hipFuncSetAttribute((const void*)k_dH<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)kDhLdsMax));
+                    opted[ctx->device & 63] = true;
+                }
+                hipLaunchKernelGGL(k_dH<true>, dim3((unsigned)(8 * rpx)), dim3(kHvThreads), stage, ctx->stream, T,
+                                   td.bond.as<uint32_t>(), rpx, model->L, lam + p * lam_col, psi + p * psi_col, w.x,
+                                   w.y, part, nth);
+            } else {
+                hipLaunchKernelGGL(k_dH<false>, dim3((unsigned)(8 * rpx)), dim3(kHvThreads), 0, ctx->stream, T,
+                                   td.bond.as<uint32_t>(), rpx, model->L, lam + p * lam_col, psi + p * psi_col, w.x,
+                                   w.y, part, nth);
+            }
+            check_launch("k_dH");
+        }
+        hipLaunchKernelGGL(k_dH_fin, dim3(nth), dim3(kThreads), 0, ctx->stream, part, (int64_t)sec->d_up, nth, g);
+        check_launch("k_dH_fin");
+    }
 }
 
 void apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int orbital, int dagger,

@@ -64,6 +64,7 @@ struct HopTable {
     DevBuf ent;      // uint32 [width * D]
     DevBuf e_up;     // double [D]  sum_i eps_up[i] bit_i
     DevBuf e_dn;     // double [D]  sum_i eps_dn[i] bit_i
+    DevBuf bond;     // uint32 [nb * D] per bond: target rank | sign << 31, or ~0u
 };
 
 struct KernelStat {
@@ -151,6 +152,15 @@ void apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int orb
              int dagger, const double2* v, double2* w, int nvec, int64_t ld_src,
              int64_t ld_dst);
 
+// Parameter derivatives of H: theta = (t_b [nb], eps_up [L], eps_dn [L], U [L]);
+// dH/dt_b = -K_b (K_b = sum_s c+_i c_j + h.c.), dH/deps_is = n_is,
+// dH/dU_i = n_i,up n_i,dn.  Adds Re(w * <lam| dH/dtheta |psi>) to g[theta]
+// (device, n_theta doubles) for each of npair pairs (lam_p, psi_p, w_p).
+int n_theta(const kgf_model* model);
+void dH_expect(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* lam,
+               int64_t lam_col, const double2* psi, int64_t psi_col, int npair,
+               const double2* host_w, double* g);
+
 // Lanczos-fused H.v: for each column c
 //   y_c = s_c[k] * H x_c - b_c[k] * s_c[k-1] * xp_c      (xp may be null)
 //   part[c][blk] = Re <s_c[k] x_c, y_c>   (one partial per block)
@@ -181,6 +191,28 @@ struct SilOpts {
 // Reserve the SIL workspaces for batches of up to ncol columns (avoids
 // re-allocation when a caller grows its batch step by step).
 void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth);
+// Lanczos bases of ncol columns (slot 0 = psi + c*ld), left in the SIL workspace.
+void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
+               int64_t ld, const SilOpts& o);
+// Coefficients of exp(dir i H t) (or exp(-(H - shift) t) for dir 0) applied to
+// column col[r], in the basis of the last sil_build: coef + r * coef_stride.
+void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, const int* dir,
+               double shift, double2* coef, int coef_stride);
+// out + o * out_col = sum_j coef[o][j] v_j(column c), o < nout (one pass over the basis)
+void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_t ld, int ncol, int m,
+                       int c, const double2* coef, int64_t coef_stride, int nout, double2* out,
+                       int64_t out_col);
+// Lanczos bases of ncol columns (slot 0 = psi + c*ld), left in the SIL workspace.
+void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
+               int64_t ld, const SilOpts& o);
+// Coefficients of exp(dir i H t) (or exp(-(H - shift) t) for dir 0) applied to
+// column col[r], in the basis of the last sil_build: coef + r * coef_stride.
+void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, const int* dir,
+               double shift, double2* coef, int coef_stride);
+// out + o * out_col = sum_j coef[o][j] v_j(column c), o < nout (one pass over the basis)
+void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_t ld, int ncol, int m,
+                       int c, const double2* coef, int64_t coef_stride, int nout, double2* out,
+                       int64_t out_col);
 // Batched short-iterative-Lanczos step(s) on ncol columns psi_c = psi + c*ld.
 void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi,
                    int ncol, int64_t ld, int nsteps, const SilOpts& o);

@@ -11,6 +11,7 @@
 // (results are reproducible run to run) and updates the per-column
 // scalars.  A batch of ncol independent recursions (own a_k, b_k, T) runs
 // in the same launches.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -193,6 +194,36 @@ __global__ __launch_bounds__(kThreads) void k_multiaxpy(Slots sl, int ky, int nj
     if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s;
 }
 
+// Several outputs from one pass over the Krylov slots of column c:
+// out_o = sum_j coef[o][j] slot(j, c) for o < nout (nout <= kMaxOut).
+constexpr int kMaxOut = 8;
+__global__ __launch_bounds__(kThreads) void k_combine_multi(Slots sl, int c, int n, const double2* __restrict__ coef,
+                                                            int64_t coef_stride, int nout, double2* __restrict__ out,
+                                                            int64_t out_col, int64_t D) {
+    extern __shared__ double2 sc2[];
+    for (int t = threadIdx.x; t < n * nout; t += blockDim.x) sc2[t] = coef[(t / n) * coef_stride + t % n];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double re[kMaxOut], im[kMaxOut];
+#pragma unroll
+        for (int o = 0; o < kMaxOut; ++o) re[o] = im[o] = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double2 z = sl.at(j, c)[i];
+#pragma unroll
+            for (int o = 0; o < kMaxOut; ++o)
+                if (o < nout) {
+                    const double2 h = sc2[o * n + j];
+                    re[o] = fma(h.x, z.x, fma(-h.y, z.y, re[o]));
+                    im[o] = fma(h.x, z.y, fma(h.y, z.x, im[o]));
+                }
+        }
+#pragma unroll
+        for (int o = 0; o < kMaxOut; ++o)
+            if (o < nout) out[o * out_col + i] = make_double2(re[o], im[o]);
+    }
+}
+
 // out_c = sum_j coef_j slot(j, c)   (coef complex, already including s_j);
 // out may alias slot 0 (each element is read before it is written).
 __global__ __launch_bounds__(kThreads) void k_combine(Slots sl, int n, const double2* __restrict__ coef,
@@ -288,15 +319,31 @@ __global__ void k_fin_h(const double* __restrict__ part, int nj, int nper, doubl
 // them to its own row of the eigenvector matrix Q held in LDS.  Finally
 //   coef_k = beta0 * sum_j Q[k][j] f(lambda_j) Q[0][j] * s_k,
 // f = exp(-i lambda dt), exp(+i lambda dt) or exp(-(lambda - shift) dt).
-__global__ __launch_bounds__(64) void k_tridiag_exp(double* __restrict__ scal, int m, double dt,
-                                                    int direction, double shift) {
+// Up to kMaxReq coefficient requests per launch: request r evaluates column
+// col[r] at time t[r] with direction dir[r]; its coefficients (including the
+// scales s_k) go to coef_out + r * coef_stride (complex).
+constexpr int kMaxReq = 64;
+struct CoefReq {
+    int n;
+    int col[kMaxReq];
+    int dir[kMaxReq];
+    double t[kMaxReq];
+};
+
+__global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ scal, int m, CoefReq req,
+                                                    double shift, double2* __restrict__ coef_out,
+                                                    int coef_stride) {
     __shared__ double Q[kMaxKrylov][kMaxKrylov + 1];
     __shared__ double d[kMaxKrylov], e[kMaxKrylov];
     __shared__ double rc[kMaxKrylov], rs[kMaxKrylov];
     __shared__ int s_mm, s_lo;
-    const int c = blockIdx.x;
+    const int r = blockIdx.x;
+    const int c = req.col[r];
+    const double dt = req.t[r];
+    const int direction = req.dir[r];
     const int lane = threadIdx.x;
-    double* sc = scal + (int64_t)c * kScalStride;
+    const double* sc = scal + (int64_t)c * kScalStride;
+    double2* co = coef_out + (int64_t)r * coef_stride;
     const double beta0 = sc[kOffBeta0];
 
     // ---- moderate ||T dt||: exp(A) e_1 by n_sub Taylor substeps of exp(A/n_sub),
@@ -371,8 +418,7 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(double* __restrict__ scal, i
             }
             if (lane < m) {
                 const double g = beta0 * sc[kOffS + lane];
-                sc[kOffCoef + 2 * lane] = (cr * fr - ci * fi) * g;
-                sc[kOffCoef + 2 * lane + 1] = (cr * fi + ci * fr) * g;
+                co[lane] = make_double2((cr * fr - ci * fi) * g, (cr * fi + ci * fr) * g);
             }
             return;
         }
@@ -465,8 +511,7 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(double* __restrict__ scal, i
             im = fma(w, fi, im);
         }
         const double f = beta0 * sc[kOffS + lane];
-        sc[kOffCoef + 2 * lane] = re * f;
-        sc[kOffCoef + 2 * lane + 1] = im * f;
+        co[lane] = make_double2(re * f, im * f);
     }
 }
 
@@ -770,8 +815,10 @@ void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reort
     }
 }
 
-void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
-                   int64_t ld, int nsteps, const SilOpts& o) {
+// Lanczos bases of ncol columns psi_c = psi + c * ld (slot 0 = psi itself);
+// leaves the scalars in "sil_scal" and slots 1..m in "sil_X".
+void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+               const SilOpts& o) {
     const int64_t D = sec->dim();
     const int m = o.m;
     KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
@@ -790,51 +837,94 @@ void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double
         hvec = static_cast<double2*>(workspace(ctx, "sil_hvec", sizeof(double2) * (size_t)ncol * (m + 1)));
     }
     Slots sl{psi, ld, X, (int64_t)ncol * D, D};
+    {
+        Prof pr(ctx, "norm", 16.0 * D * ncol);
+        hipLaunchKernelGGL(k_norm2, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, psi, ld, D, part);
+        check_launch("k_norm2");
+    }
+    launch_fin(ctx, FIN_INIT, 0, part, NB, scal, ncol, 0.0);
+    for (int k = 0; k < m; ++k) {
+        LanczosHvArgs a;
+        a.x = sl.at(k, 0);
+        a.x_col = k == 0 ? ld : D;
+        a.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
+        a.xp_col = k - 1 == 0 ? ld : D;
+        a.y = sl.at(k + 1, 0);
+        a.y_col = D;
+        a.s_k = scal + kOffS + k;
+        a.b_k = scal + kOffB + k;
+        a.s_km1 = scal + kOffS + (k > 0 ? k - 1 : 0);
+        a.stride = kScalStride;
+        a.part = part;
+        hv_lanczos(ctx, model, sec, ncol, a);
+        launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
+        if (k == m - 1) break;
+        {
+            Prof pr(ctx, "lanczos_update", 48.0 * D * ncol);
+            hipLaunchKernelGGL(k_update, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, sl, k,
+                               scal + kOffA + k, scal + kOffS + k, kScalStride, D, part);
+            check_launch("k_update");
+        }
+        if (o.reorth > 0)
+            reorthogonalise(ctx, sl, k + 1, k + 1, ncol, D, o.reorth, scal, nullptr, part, part_big, hvec);
+        launch_fin(ctx, FIN_B, k, part, NB, scal, ncol, o.breakdown_tol);
+    }
+}
 
+// coefficient requests against the bases left by sil_build
+void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, const int* dir, double shift,
+               double2* coef, int coef_stride) {
+    const double* scal = static_cast<const double*>(ctx->ws["sil_scal"]->p);
+    for (int r0 = 0; r0 < nreq; r0 += kMaxReq) {
+        CoefReq q;
+        q.n = std::min(kMaxReq, nreq - r0);
+        for (int r = 0; r < q.n; ++r) {
+            q.col[r] = col[r0 + r];
+            q.t[r] = t[r0 + r];
+            q.dir[r] = dir[r0 + r];
+        }
+        Prof pr(ctx, "tridiag_exp");
+        hipLaunchKernelGGL(k_tridiag_exp, dim3(q.n), dim3(64), 0, ctx->stream, scal, m, q, shift,
+                           coef + (int64_t)r0 * coef_stride, coef_stride);
+        check_launch("k_tridiag_exp");
+    }
+}
+
+// out + o * out_col = sum_j coef[o][j] v_j(column c) for nout outputs
+void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_t ld, int ncol, int m, int c,
+                       const double2* coef, int64_t coef_stride, int nout, double2* out, int64_t out_col) {
+    const int64_t D = sec->dim();
+    double2* X = static_cast<double2*>(ctx->ws["sil_X"]->p);
+    Slots sl{psi, ld, X, (int64_t)ncol * D, D};
+    const int NB = red_blocks(D);
+    for (int o0 = 0; o0 < nout; o0 += kMaxOut) {
+        const int no = std::min(kMaxOut, nout - o0);
+        Prof pr(ctx, "combine", 16.0 * (m + no) * D);
+        hipLaunchKernelGGL(k_combine_multi, dim3(NB), dim3(kThreads), sizeof(double2) * m * no, ctx->stream, sl, c,
+                           m, coef + o0 * coef_stride, coef_stride, no, out + o0 * out_col, out_col, D);
+        check_launch("k_combine_multi");
+    }
+}
+
+void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                   int nsteps, const SilOpts& o) {
+    const int64_t D = sec->dim();
+    const int m = o.m;
+    std::vector<int> col(ncol), dir(ncol, o.direction);
+    std::vector<double> tt(ncol, o.dt);
+    for (int c = 0; c < ncol; ++c) col[c] = c;
     for (int step = 0; step < nsteps; ++step) {
-        {
-            Prof pr(ctx, "norm", 16.0 * D * ncol);
-            hipLaunchKernelGGL(k_norm2, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, psi, ld, D, part);
-            check_launch("k_norm2");
-        }
-        launch_fin(ctx, FIN_INIT, 0, part, NB, scal, ncol, 0.0);
-        for (int k = 0; k < m; ++k) {
-            LanczosHvArgs a;
-            a.x = sl.at(k, 0);
-            a.x_col = k == 0 ? ld : D;
-            a.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
-            a.xp_col = k - 1 == 0 ? ld : D;
-            a.y = sl.at(k + 1, 0);
-            a.y_col = D;
-            a.s_k = scal + kOffS + k;
-            a.b_k = scal + kOffB + k;
-            a.s_km1 = scal + kOffS + (k > 0 ? k - 1 : 0);
-            a.stride = kScalStride;
-            a.part = part;
-            hv_lanczos(ctx, model, sec, ncol, a);
-            launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
-            if (k == m - 1) break;
-            {
-                Prof pr(ctx, "lanczos_update", 48.0 * D * ncol);
-                hipLaunchKernelGGL(k_update, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, sl, k,
-                                   scal + kOffA + k, scal + kOffS + k, kScalStride, D, part);
-                check_launch("k_update");
-            }
-            if (o.reorth > 0)
-                reorthogonalise(ctx, sl, k + 1, k + 1, ncol, D, o.reorth, scal, nullptr, part, part_big, hvec);
-            launch_fin(ctx, FIN_B, k, part, NB, scal, ncol, o.breakdown_tol);
-        }
-        {
-            Prof pr(ctx, "tridiag_exp");
-            hipLaunchKernelGGL(k_tridiag_exp, dim3(ncol), dim3(64), 0, ctx->stream, scal, m, o.dt,
-                               o.direction, o.shift);
-            check_launch("k_tridiag_exp");
-        }
+        sil_build(ctx, model, sec, psi, ncol, ld, o);
+        double* scal = static_cast<double*>(ctx->ws["sil_scal"]->p);
+        double2* coef = reinterpret_cast<double2*>(scal + kOffCoef);
+        sil_coefs(ctx, m, ncol, col.data(), tt.data(), dir.data(), o.shift, coef, kScalStride / 2);
+        double2* X = static_cast<double2*>(ctx->ws["sil_X"]->p);
+        Slots sl{psi, ld, X, (int64_t)ncol * D, D};
+        const int NB = red_blocks(D);
         {
             Prof pr(ctx, "combine", 16.0 * (m + 1) * D * ncol);
-            hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream,
-                               sl, m, reinterpret_cast<const double2*>(scal + kOffCoef),
-                               (int64_t)(kScalStride / 2), psi, ld, D);
+            hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream, sl, m,
+                               reinterpret_cast<const double2*>(coef), (int64_t)(kScalStride / 2), psi, ld, D);
             check_launch("k_combine");
         }
     }

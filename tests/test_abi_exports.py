@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1109_1205_amd", "libkgf.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(kgf_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(kgf_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
