@@ -292,3 +292,62 @@ def test_propagate_large_norm_uses_eigendecomposition(ctx, dt, m, direction):
     ref = np.stack([propagate.propagate(H.apply, X[c], dt, 3, m, direction, -1.0, "cgs2") for c in range(2)])
     got = ctx.propagate(ctx.model(model), ctx.sector(8, 5, 4), to_dev(X), 3, dt, m, direction, -1.0, 2)
     assert rel_err(to_host(got), ref) < 1e-10
+
+
+def test_hub4x3_batched_equals_sequential_and_oracle_head():
+    """4x3 cluster, t'=-0.3, U=8 (dim 853,776): the 24 components (12 c_i,
+    12 c_i^+) propagated as one block for all 400 steps of dt=0.025 equal the
+    24 one-by-one runs; the first steps of G_00 match the oracle (ground
+    state of the oracle's sparse H by ARPACK)."""
+    import scipy.sparse.linalg as spla
+    import paper_1109_1205_amd as kgf
+    ctx = kgf.Context(0)
+    q = wl.hub4x3()
+    say("hub4x3 G eq full")
+    sec = basis.Sector(12, 6, 6)
+    m = ctx.model(q.H)
+    s = ctx.sector(12, 6, 6)
+    E0, psi, info = ctx.ground_state(m, s, to_dev(wl.start_vector(sec.dim, q.gs_seed)), tol=1e-12, max_iter=400)
+    assert info["converged"]
+    gb, lb = ctx.greens_eq(m, s, psi, E0, q.orbitals, q.nt, 1, q.dt_grid, q.krylov_dim, batch=0)
+    gs_, ls_ = ctx.greens_eq(m, s, psi, E0, q.orbitals, q.nt, 1, q.dt_grid, q.krylov_dim, batch=1)
+    assert rel_err(gb, gs_) < 1e-12 and rel_err(lb, ls_) < 1e-12
+    # anticommutator for every site at t = 0 and Hermiticity G_ij(0) = -conj(G_ji(0))
+    np.testing.assert_allclose(np.diag(gb[0] - lb[0]), -1j, atol=1e-11)
+    H = hamiltonian.Hamiltonian(q.H, sec)
+    ev, vec = spla.eigsh(H.sparse(), k=1, which="SA", tol=1e-14)
+    assert abs(ev[0] - E0) <= 1e-12 * abs(E0)
+    nh = 6
+    Gg, Gl = greens.equilibrium(q.H, 6, 6, [(0, 0)], nh, q.dt_grid, 1, q.krylov_dim, vec[:, 0].astype(complex),
+                                float(ev[0]), reorth="none")
+    assert rel_err(gb[:nh, :1, :1], Gg) < 1e-10 and rel_err(lb[:nh, :1, :1], Gl) < 1e-10
+
+
+def test_siam10_full_grid_sampled_against_oracle():
+    """Anderson quench on its full mesh (100 x 100 real times, 101 Matsubara
+    times) on the GPU; the oracle computes the rows t_k for a sample of k
+    (all t') plus the whole Matsubara branch and the mixed rows."""
+    import paper_1109_1205_amd as kgf
+    ctx = kgf.Context(0)
+    q = wl.siam10()
+    say("siam10 full grid")
+    sec = basis.Sector(10, 5, 5)
+    v0 = wl.start_vector(sec.dim, q.gs_seed)
+    got = ctx.greens_neq(ctx.model(q.H_ini), ctx.model(q.H), ctx.sector(10, 5, 5), to_dev(v0), q.orbitals, q.nt,
+                         q.steps_per_grid, q.dt, q.krylov_dim, schedule=1, ntau=q.ntau,
+                         tau_steps_per_grid=q.tau_steps_per_grid, dtau=q.dtau_grid / q.tau_steps_per_grid,
+                         gs_tol=q.gs_tol)
+    Gl, Gg = got["G_lesser"][:, :, 0, 0], got["G_greater"][:, :, 0, 0]
+    np.testing.assert_allclose(np.diag(Gg - Gl), -1j, atol=1e-11)
+    np.testing.assert_allclose(Gl.conj(), -Gl.T, atol=1e-12)
+    ks = [0, 41, 99]
+    ora = greens.four_step(q.H_ini, q.H, 5, 5, q.orbitals, q.nt, q.dt_grid, q.steps_per_grid, q.krylov_dim, v0,
+                           gs_tol=q.gs_tol, reorth="none", ntau=q.ntau, dtau_grid=q.dtau_grid,
+                           tau_steps_per_grid=q.tau_steps_per_grid, times=ks)
+    scale = np.abs(ora["G_lesser"]).max()
+    for k in ks:
+        for kp in ks:
+            assert abs(got["G_lesser"][k, kp] - ora["G_lesser"][k, kp]).max() < 1e-10 * scale
+            assert abs(got["G_greater"][k, kp] - ora["G_greater"][k, kp]).max() < 1e-10 * scale
+        assert rel_err(got["G_mixed"][k], ora["G_mixed"][k]) < 1e-10
+    assert rel_err(got["G_matsubara"], ora["G_matsubara"]) < 1e-10
