@@ -50,7 +50,56 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
+    p.add_argument("--hv", default="",
+                   help="H.v micro-benchmark instead of the four-step run: comma-separated ladder sizes "
+                        "(14, 16); each is timed for every --hv-passes variant")
+    p.add_argument("--hv-passes", default="0", help="comma-separated kgf_set_option HV_PASSES values")
+    p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
+    p.add_argument("--hv-reps", type=int, default=10)
     return p.parse_args()
+
+
+def hv_bench(a):
+    """Time H.v (y = H x) and the Lanczos-fused H.v (one SIL step, Krylov
+    dim 20) on the half-filled 2xL/2 ladder's c-sector (N_up - 1, N_dn), for
+    each requested kernel variant.  One JSON line per (L, variant)."""
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    ctx = kgf.Context(0)
+    for L in [int(v) for v in a.hv.split(",") if v]:
+        q = wl.ladder14() if L == 14 else wl.ladder16()
+        m = ctx.model(q.H)
+        sec = ctx.sector(L, q.n_up - 1, q.n_dn)
+        g = torch.Generator(device="cuda:0").manual_seed(11)
+        x = torch.randn(sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
+        y = torch.empty_like(x)
+        variants = [(int(p_), int(s_)) for p_ in a.hv_passes.split(",") if p_ for s_ in a.hv_strip.split(",") if s_]
+        for passes, strip in variants:
+            ctx.set_option(ctx.HV_PASSES, passes)
+            ctx.set_option(ctx.HV_STRIP, strip)
+            ctx.apply_h(m, sec, x, y)      # warm-up (tables, LDS opt-in)
+            torch.cuda.synchronize()
+            log(f"L={L} D={sec.dim} passes={passes} strip={strip}: timing")
+            ctx.profile_begin(1)
+            for _ in range(a.hv_reps):
+                ctx.apply_h(m, sec, x, y)
+            xs = x.clone().reshape(1, -1)
+            ctx.propagate(m, sec, xs, 1, q.dt, q.krylov_dim, +1)
+            torch.cuda.synchronize()
+            st = ctx.profile_end()
+            out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip}
+            for k in ("hv", "hv_lanczos", "lanczos_update", "combine"):
+                if k in st and st[k]["sampled"]:
+                    ms = st[k]["sampled_ms"] / st[k]["sampled"]
+                    gbs = st[k]["sampled_bytes"] / (st[k]["sampled_ms"] * 1e-3) / 1e9
+                    out[k] = {"avg_ms": round(ms, 4), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBPS, 4)}
+            print(json.dumps(out), flush=True)
+            del xs
+        ctx.set_option(ctx.HV_PASSES, 0)
+        ctx.set_option(ctx.HV_STRIP, 0)
+        del x, y
+        torch.cuda.empty_cache()
 
 
 def probe(a):
@@ -117,6 +166,9 @@ def main():
     a = parse()
     if a.probe:
         probe(a)
+        return
+    if a.hv:
+        hv_bench(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "

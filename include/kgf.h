@@ -263,6 +263,21 @@ int  kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H
 typedef void (*kgf_progress_fn)(void* user, const char* phase, int64_t done, int64_t total);
 int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
 
+/* ---- kernel-variant options ---------------------------------------------------
+ * Choices between equivalent kernels (results agree to rounding).  By default
+ * the library picks by the sector's sizes.
+ *   KGF_OPT_HV_PASSES: 0 by size; 1 single-pass H.v (source row staged in LDS,
+ *                      rows up to 78 KB only); 2 two-pass H.v (pass 1: row in
+ *                      LDS, down-spin hops and diagonal; pass 2: up-spin hops on
+ *                      L2-sized column strips); 3 two-pass with rows staged as
+ *                      real and imaginary halves (the mode used for rows above
+ *                      78 KB).
+ *   KGF_OPT_HV_STRIP:  0 by size, or 8, 16, 32, 64 columns per strip (pass 2).
+ * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
+ * work issued by this context is in flight. */
+enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2 };
+int  kgf_set_option(kgf_ctx* ctx, int option, int value);
+
 /* ---- device-side timing of the library's kernels --------------------------
  * Between kgf_profile_begin and kgf_profile_end every `sample_every`-th
  * launch of each kernel class is bracketed by HIP events on the context's

@@ -133,6 +133,14 @@ class Hamiltonian:
         W = self.T_up @ V + (self.T_dn @ V.T).T + self.diag * V
         return W.reshape(-1)
 
+    def apply_rows(self, v: np.ndarray, rows) -> np.ndarray:
+        """Rows u (up-spin indices) of H.v viewed as the D_up x D_dn matrix,
+        from the same three terms as apply(): for checking a product at
+        sizes where the full one is too slow."""
+        V = np.asarray(v).reshape(self.sector.d_up, self.sector.d_dn)
+        rows = np.asarray(rows, dtype=np.int64)
+        return self.T_up[rows] @ V + V[rows] @ self.T_dn.T + self.diag[rows] * V[rows]
+
     def sparse(self) -> sp.csr_matrix:
         Iu = sp.identity(self.sector.d_up, format="csr")
         Id = sp.identity(self.sector.d_dn, format="csr")

@@ -100,6 +100,7 @@ def load_library():
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
+        "kgf_set_option": (I, [P, I, I]),
         "kgf_n_theta": (I, [P]),
         "kgf_dH_expect": (I, [P, P, P, P, P, I, I64, P, P]),
         "kgf_propagate_vjp": (I, [P, P, P, P, P, I, C.POINTER(_PropOpts), I, P]),
@@ -122,7 +123,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
-            "kgf_greens_neq_vjp", "kgf_profile_begin", "kgf_profile_end"]
+            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_profile_begin", "kgf_profile_end"]
 
 
 def _check(rc: int):
@@ -369,6 +370,12 @@ class Context:
             out["G_matsubara"] = GM
             out["G_mixed"] = Gx
         return out
+
+    HV_PASSES, HV_STRIP = 1, 2
+
+    def set_option(self, option: int, value: int) -> None:
+        """Kernel-variant choice (kgf_set_option): HV_PASSES 0..3, HV_STRIP 0/8/16/32/64."""
+        _check(_lib.kgf_set_option(self.handle, int(option), int(value)))
 
     def set_progress(self, fn=None):
         """fn(phase: str, done: int, total: int) called from the library's

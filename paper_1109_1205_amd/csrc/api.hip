@@ -450,6 +450,22 @@ int kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user) {
     });
 }
 
+int kgf_set_option(kgf_ctx* ctx, int option, int value) {
+    return guarded([&] {
+        KGF_REQUIRE(ctx, KGF_EINVAL, "kgf_set_option: ctx is NULL");
+        if (option == KGF_OPT_HV_PASSES) {
+            KGF_REQUIRE(value >= 0 && value <= 3, KGF_EINVAL, "kgf_set_option: HV_PASSES must be 0..3");
+            ctx->hv_passes = value;
+        } else if (option == KGF_OPT_HV_STRIP) {
+            KGF_REQUIRE(value == 0 || value == 8 || value == 16 || value == 32 || value == 64, KGF_EINVAL,
+                        "kgf_set_option: HV_STRIP must be 0, 8, 16, 32 or 64");
+            ctx->hv_strip = value;
+        } else {
+            fail(KGF_EINVAL, "kgf_set_option: unknown option");
+        }
+    });
+}
+
 int kgf_profile_begin(kgf_ctx* ctx, int sample_every) {
     return guarded([&] {
         KGF_REQUIRE(ctx && sample_every >= 1, KGF_EINVAL, "kgf_profile_begin: bad argument");

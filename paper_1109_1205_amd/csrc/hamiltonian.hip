@@ -287,6 +287,232 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-pass H.v for rows too large to share an XCD's L2 with their up-spin
+// neighbours (and, at L = 16, too large for LDS as complex numbers):
+//   pass 1 (rows):   y = (down-spin hops + diagonal) x, one block per row;
+//                    the row is staged in LDS (as double2, or as its real
+//                    then its imaginary parts with the other half held in
+//                    registers) and the random in-row gathers are LDS reads.
+//   pass 2 (strips): y += up-spin hops, on column strips of C columns; XCD x
+//                    (block id mod 8) takes strips x, x+8, ... one after the
+//                    other, and all its CUs sweep the rows of one strip, so
+//                    the strip (D_up x C x 16 bytes, sized to fit in L2) is
+//                    read from HBM once and re-read by the ~n_hop source
+//                    rows of each output row from L2.  The Lanczos epilogue
+//                    (scale, - b v_{k-1}, <v_k, y>) is fused into pass 2.
+// HBM traffic 5 vectors per H.v (6 with the previous Lanczos vector) against
+// the single-pass kernel's 2 (3) plus its L2 misses of whole source rows.
+// ---------------------------------------------------------------------------
+constexpr size_t kSplitLdsMax = 150 * 1024;      // one real component of a row
+constexpr int kRowsJSplit = 16;                  // row elements per thread, split rows (D_dn <= 16,384)
+
+// Pass 1.  One block per row u; threads own d = tid + j * 1024.
+template <bool SPLIT, bool UNIFORM_U>
+__global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double2* __restrict__ X, int64_t x_col,
+                                                        double2* __restrict__ Y, int64_t y_col) {
+    extern __shared__ double2 srow[];
+    __shared__ double s_negt[kMaxBonds + 1];
+    __shared__ double s_U[UNIFORM_U ? 1 : 3 * 256];
+    const int64_t u = blockIdx.x;
+    const int c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t Ddn = T.Ddn;
+    const double2* __restrict__ xrow = X + c * x_col + u * Ddn;
+    double2* __restrict__ yrow = Y + c * y_col + u * Ddn;
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    if (!UNIFORM_U)
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[i];
+    const uint32_t mu = T.mu[u];
+    const double eu = T.eu[u];
+    auto diag = [&](int64_t d) -> double {
+        const uint32_t both = mu & T.md[d];
+        double dg = eu + T.ed[d];
+        if (UNIFORM_U) dg += T.U0 * (double)__popc(both);
+        else dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
+        return dg;
+    };
+    constexpr int kBatch = 8;
+    if (!SPLIT) {
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) srow[d] = xrow[d];
+        __syncthreads();
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+            const double2 xv = srow[d];
+            const double dg = diag(d);
+            double ar = dg * xv.x, ai = dg * xv.y;
+            const int cd = T.cnt_dn[d];
+            for (int k0 = 0; k0 < cd; k0 += kBatch) {
+                uint32_t e[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) e[j] = (k0 + j < cd) ? T.ent_dn[(int64_t)(k0 + j) * Ddn + d] : 0u;
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    if (k0 + j < cd) {
+                        double tv = s_negt[(e[j] >> 24) & 127u];
+                        tv = (e[j] >> 31) ? -tv : tv;
+                        const double2 z = srow[e[j] & 0xFFFFFFu];
+                        ar = fma(tv, z.x, ar);
+                        ai = fma(tv, z.y, ai);
+                    }
+            }
+            yrow[d] = make_double2(ar, ai);
+        }
+        return;
+    }
+    // split: real parts in LDS while the imaginary parts wait in registers
+    double* sh = reinterpret_cast<double*>(srow);
+    double xim[kRowsJSplit], are[kRowsJSplit];
+#pragma unroll
+    for (int j = 0; j < kRowsJSplit; ++j) {
+        const int64_t d = tid + (int64_t)j * kHvThreads;
+        xim[j] = 0.0;
+        if (d < Ddn) {
+            const double2 v = xrow[d];
+            sh[d] = v.x;
+            xim[j] = v.y;
+        }
+    }
+    __syncthreads();
+    auto gather = [&](int64_t d, double self) -> double {
+        double acc = diag(d) * self;
+        const int cd = T.cnt_dn[d];
+        for (int k0 = 0; k0 < cd; k0 += kBatch) {
+            uint32_t e[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) e[j] = (k0 + j < cd) ? T.ent_dn[(int64_t)(k0 + j) * Ddn + d] : 0u;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cd) {
+                    double tv = s_negt[(e[j] >> 24) & 127u];
+                    tv = (e[j] >> 31) ? -tv : tv;
+                    acc = fma(tv, sh[e[j] & 0xFFFFFFu], acc);
+                }
+        }
+        return acc;
+    };
+#pragma unroll
+    for (int j = 0; j < kRowsJSplit; ++j) {
+        const int64_t d = tid + (int64_t)j * kHvThreads;
+        are[j] = d < Ddn ? gather(d, sh[d]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRowsJSplit; ++j) {
+        const int64_t d = tid + (int64_t)j * kHvThreads;
+        if (d < Ddn) sh[d] = xim[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRowsJSplit; ++j) {
+        const int64_t d = tid + (int64_t)j * kHvThreads;
+        if (d < Ddn) yrow[d] = make_double2(are[j], gather(d, xim[j]));
+    }
+}
+
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+    const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(double2* p, double2 a) {
+    dbl2v v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<dbl2v*>(p));
+}
+
+constexpr int kUpThreads = 256;
+
+// Pass 2.  A block covers R = 256 / C rows of one strip; the packed hop
+// entries of its rows are staged in LDS first, so that each thread's source
+// gathers (rows x[u', strip]) are issued back to back.  With one row group
+// per block, the blocks an XCD holds at a time span about one strip.
+// MODE 0: y += T_up x.   MODE 1: y = s (y + T_up x) - bp xp, part = Re <s x, y>.
+template <int MODE, int C>
+__global__ __launch_bounds__(kUpThreads) void k_hv_up(HvTables T, int nstrip, int ntile, int width,
+                                                      const double2* __restrict__ X, int64_t x_col,
+                                                      const double2* __restrict__ XP, int64_t xp_col,
+                                                      double2* __restrict__ Y, int64_t y_col,
+                                                      const double* __restrict__ s_k, const double* __restrict__ b_k,
+                                                      const double* __restrict__ s_km1, int stride,
+                                                      double* __restrict__ part) {
+    constexpr int R = kUpThreads / C;
+    extern __shared__ uint32_t s_ent[];            // [R][width]
+    __shared__ int s_cnt[R];
+    __shared__ double s_negt[kMaxBonds + 1];
+    __shared__ double s_red[kUpThreads / 64];
+    const int blk = blockIdx.x;
+    const int q = blk >> 3;
+    const int strip = (q / ntile) * 8 + (blk & 7);
+    const int tile = q % ntile;
+    const int c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t Ddn = T.Ddn, Dup = T.Dup;
+    const int64_t u0 = (int64_t)tile * R;
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    for (int i = tid; i < R * width; i += blockDim.x) {
+        const int r = i % R, k = i / R;
+        const int64_t u = u0 + r;
+        s_ent[r * width + k] = u < Dup ? T.ent_up[(int64_t)k * Dup + u] : 0u;
+    }
+    if (tid < R) s_cnt[tid] = u0 + tid < Dup ? T.cnt_up[u0 + tid] : 0;
+    __syncthreads();
+    double sc = 1.0, bp = 0.0;
+    if (MODE == 1) {
+        sc = s_k[c * stride];
+        if (XP) bp = b_k[c * stride] * s_km1[c * stride];
+    }
+    const int r = tid / C;
+    const int64_t u = u0 + r;
+    const int64_t d = (int64_t)strip * C + (tid % C);
+    const double2* __restrict__ x = X + c * x_col;
+    double2* __restrict__ y = Y + c * y_col;
+    double dot = 0.0;
+    constexpr int kBatch = 8;
+    if (strip < nstrip && u < Dup && d < Ddn) {
+        const int cu = s_cnt[r];
+        const uint32_t* er = s_ent + r * width;
+        double ar = 0.0, ai = 0.0;
+        for (int k0 = 0; k0 < cu; k0 += kBatch) {
+            double2 z[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) z[j] = x[(int64_t)(er[k0 + j] & 0xFFFFFFu) * Ddn + d];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) {
+                    const uint32_t e = er[k0 + j];
+                    const double v = s_negt[(e >> 24) & 127u];
+                    const double tv = (e >> 31) ? -v : v;
+                    ar = fma(tv, z[j].x, ar);
+                    ai = fma(tv, z[j].y, ai);
+                }
+        }
+        const int64_t i = u * Ddn + d;
+        double2 w = ld_stream(y + i);
+        w.x += ar;
+        w.y += ai;
+        if (MODE == 1) {
+            w.x *= sc;
+            w.y *= sc;
+            if (bp != 0.0) {
+                const double2 p = ld_stream(XP + c * xp_col + i);
+                w.x = fma(-bp, p.x, w.x);
+                w.y = fma(-bp, p.y, w.y);
+            }
+            const double2 xv = x[i];
+            dot = fma(sc * xv.x, w.x, dot);
+            dot = fma(sc * xv.y, w.y, dot);
+        }
+        st_stream(y + i, w);
+    }
+    if (MODE == 1) {
+        const double s = block_sum(dot, s_red);
+        if (tid == 0) part[(int64_t)c * gridDim.x + blk] = s;
+    }
+}
+
 // c_alpha / c+_alpha between sectors.  For an up-spin orbital the map is a
 // gather of whole rows, for a down-spin orbital a gather inside each row.
 __device__ __forceinline__ int64_t rank_of(uint32_t m, const uint64_t* C) {
@@ -485,6 +711,71 @@ __global__ void k_dH_fin(const double* __restrict__ part, int64_t nrow, int nthe
     if (threadIdx.x == 0) g[t] += s;
 }
 
+// Which H.v kernels a sector uses (a function of the sector's sizes, so that
+// the number of partial sums a Lanczos H.v leaves is known in advance).
+//   passes 1: single pass, row in LDS (rows up to kRowLdsMax bytes);
+//   passes 2: two passes (rows up to kSplitLdsMax bytes per component);
+//   passes 0: single pass without LDS staging (anything larger).
+// kgf_set_option can force a variant where the row fits (results agree to
+// rounding): ctx->hv_passes 1 = single pass, 2 = two passes, 3 = two passes
+// with split rows; ctx->hv_strip = strip width of pass 2 (8, 16, 32, 64).
+struct HvPlan {
+    int passes = 0;
+    bool split = false;
+    int C = 8;
+    int nstrip = 0, ntile = 0;
+    int64_t up_blocks = 0;
+};
+
+constexpr size_t kStripL2Bytes = 6 * 1024 * 1024;   // widest strip up to this slab size (measured)
+
+HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec) {
+    HvPlan p;
+    const int64_t Dup = sec->d_up, Ddn = sec->d_dn;
+    const size_t row = sizeof(double2) * (size_t)Ddn;
+    const bool fits1 = row <= kRowLdsMax;
+    const bool fits_split = sizeof(double) * (size_t)Ddn <= kSplitLdsMax && Ddn <= (int64_t)kRowsJSplit * kHvThreads;
+    const int ov = ctx->hv_passes;
+    if (fits1 && (ov == 0 || ov == 1)) p.passes = 1;
+    else if (fits1 || fits_split) p.passes = 2;
+    else p.passes = 0;
+    if (p.passes == 2) {
+        p.split = !fits1 || (ov == 3 && fits_split);
+        p.C = 8;
+        for (int c : {64, 32, 16})
+            if ((size_t)Dup * c * sizeof(double2) <= kStripL2Bytes) {
+                p.C = c;
+                break;
+            }
+        if (ctx->hv_strip) p.C = ctx->hv_strip;
+        const int R = kUpThreads / p.C;
+        p.nstrip = (int)((Ddn + p.C - 1) / p.C);
+        p.ntile = (int)((Dup + R - 1) / R);
+        p.up_blocks = 8 * (int64_t)((p.nstrip + 7) / 8) * p.ntile;
+    }
+    return p;
+}
+
+template <int MODE, int C>
+void launch_up(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int width, int ncol, const double2* x,
+               int64_t x_col, const double2* xp, int64_t xp_col, double2* y, int64_t y_col, const double* s_k,
+               const double* b_k, const double* s_km1, int stride, double* part) {
+    const size_t lds = sizeof(uint32_t) * (size_t)(kUpThreads / C) * width;
+    hipLaunchKernelGGL((k_hv_up<MODE, C>), dim3((unsigned)P.up_blocks, (unsigned)ncol), dim3(kUpThreads), lds,
+                       ctx->stream, T, P.nstrip, P.ntile, width, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1,
+                       stride, part);
+}
+
+// opt in to more than 64 KB of dynamic LDS once per device and kernel
+void opt_in_lds(kgf_ctx* ctx, const void* kern, int slot, size_t bytes) {
+    static bool opted[16][64] = {};
+    const int dev = ctx->device & 63;
+    if (!opted[slot][dev]) {
+        KGF_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        opted[slot][dev] = true;
+    }
+}
+
 template <int MODE>
 void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
                const double2* x, int64_t x_col, const double2* xp, int64_t xp_col, double2* y,
@@ -495,26 +786,46 @@ void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
     // algorithmic bytes: read x once, write y once, read xp once if present
     const double vec = 16.0 * (double)sec->dim() * ncol;
     Prof pr(ctx, MODE == 0 ? "hv" : "hv_lanczos", vec * (xp ? 3.0 : 2.0));
-    const size_t row_bytes = sizeof(double2) * (size_t)sec->d_dn;
-    if (row_bytes <= kRowLdsMax) {
+    const HvPlan P = hv_plan(ctx, sec);
+    const bool uu = model->U_uniform;
+    if (P.passes == 1) {
+        const size_t row_bytes = sizeof(double2) * (size_t)sec->d_dn;
         const int rpx = (int)((sec->d_up + 7) / 8);
         dim3 grid((unsigned)(8 * rpx), (unsigned)ncol);
-        // opt in to more than 64 KB of dynamic LDS once per device and kernel
-        static bool opted[2][64] = {};
-        const int ui = model->U_uniform ? 1 : 0;
-        const int dev = ctx->device & 63;
-        auto kern = model->U_uniform ? k_hv_lds<MODE, true> : k_hv_lds<MODE, false>;
-        if (!opted[ui][dev]) {
-            KGF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowLdsMax));
-            opted[ui][dev] = true;
-        }
+        auto kern = uu ? k_hv_lds<MODE, true> : k_hv_lds<MODE, false>;
+        opt_in_lds(ctx, (const void*)kern, 2 * MODE + (uu ? 1 : 0), kRowLdsMax);
         hipLaunchKernelGGL(kern, grid, dim3(kHvThreads), row_bytes, ctx->stream, T, rpx, x, x_col, xp,
                            xp_col, y, y_col, s_k, b_k, s_km1, stride, part);
         check_launch("k_hv_lds");
         return;
     }
+    if (P.passes == 2) {
+        KGF_REQUIRE(P.up_blocks <= 0x7fffffff && (int64_t)model->nb * sec->d_dn < ((int64_t)1 << 32),
+                    KGF_EUNSUPPORTED, "H.v: strip grid or hop table too large");
+        const size_t lds = P.split ? sizeof(double) * (size_t)sec->d_dn : sizeof(double2) * (size_t)sec->d_dn;
+        dim3 rg((unsigned)sec->d_up, (unsigned)ncol);
+        if (P.split) {
+            auto rows = uu ? k_hv_rows<true, true> : k_hv_rows<true, false>;
+            opt_in_lds(ctx, (const void*)rows, 4 + (uu ? 1 : 0), kSplitLdsMax);
+            hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
+        } else {
+            auto rows = uu ? k_hv_rows<false, true> : k_hv_rows<false, false>;
+            opt_in_lds(ctx, (const void*)rows, 6 + (uu ? 1 : 0), kRowLdsMax);
+            hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
+        }
+        check_launch("k_hv_rows");
+        const int w = model->nb;
+        switch (P.C) {
+            case 64: launch_up<MODE, 64>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+            case 32: launch_up<MODE, 32>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+            case 16: launch_up<MODE, 16>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+            default: launch_up<MODE, 8>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+        }
+        check_launch("k_hv_up");
+        return;
+    }
     dim3 grid((unsigned)sec->d_up, (unsigned)ncol);
-    if (model->U_uniform)
+    if (uu)
         hipLaunchKernelGGL((k_hv<MODE, true>), grid, dim3(kThreads), 0, ctx->stream, T, x, x_col, xp,
                            xp_col, y, y_col, s_k, b_k, s_km1, stride, part);
     else
@@ -534,7 +845,10 @@ void apply_h(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double
     }
 }
 
-int hv_lanczos_blocks(const kgf_sector* sec) { return (int)sec->d_up; }
+int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec) {
+    const HvPlan P = hv_plan(ctx, sec);
+    return P.passes == 2 ? (int)P.up_blocks : (int)sec->d_up;
+}
 
 void hv_lanczos(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a) {

@@ -88,6 +88,9 @@ struct kgf_ctx {
     struct Pending { std::string name; hipEvent_t a, b; double bytes; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
+    // H.v variant knobs (kgf_set_option)
+    int hv_passes = 0;
+    int hv_strip = 0;
     // progress callback
     kgf_progress_fn progress = nullptr;
     void* progress_user = nullptr;
@@ -174,7 +177,7 @@ struct LanczosHvArgs {
     int stride;                            // doubles between columns
     double* part;                          // [ncol][nblk]
 };
-int hv_lanczos_blocks(const kgf_sector* sec);
+int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec);
 void hv_lanczos(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a);
 

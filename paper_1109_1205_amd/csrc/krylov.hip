@@ -805,7 +805,7 @@ void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reort
         workspace(ctx, "sil_X", xbytes);
     }
     const int NB = red_blocks(D);
-    const int HB = hv_lanczos_blocks(sec);
+    const int HB = hv_lanczos_blocks(ctx, sec);
     const int nper_max = NB > HB ? NB : HB;
     workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol);
     workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol);
@@ -827,7 +827,7 @@ void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* p
     double2* X = static_cast<double2*>(workspace(ctx, "sil_X", xbytes));
     double* scal = static_cast<double*>(workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol));
     const int NB = red_blocks(D);
-    const int HB = hv_lanczos_blocks(sec);
+    const int HB = hv_lanczos_blocks(ctx, sec);
     const int nper_max = NB > HB ? NB : HB;
     double* part = static_cast<double*>(workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol));
     double* part_big = nullptr;
@@ -949,7 +949,7 @@ GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, con
     double* res = static_cast<double*>(workspace(ctx, "gs_res", sizeof(double) * 8));
     double2* coef = static_cast<double2*>(workspace(ctx, "gs_coef", sizeof(double2) * (nmax + 1)));
     const int NB = red_blocks(D);
-    const int HB = hv_lanczos_blocks(sec);
+    const int HB = hv_lanczos_blocks(ctx, sec);
     double* part = static_cast<double*>(workspace(ctx, "gs_part", sizeof(double) * (NB > HB ? NB : HB)));
     double* part_big = static_cast<double*>(workspace(ctx, "gs_partbig", sizeof(double) * (size_t)NB * 2 * (nmax + 1)));
     double2* hvec = static_cast<double2*>(workspace(ctx, "gs_hvec", sizeof(double2) * (nmax + 1)));

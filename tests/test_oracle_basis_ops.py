@@ -87,6 +87,18 @@ def test_hermitian_and_apply_consistency():
     np.testing.assert_allclose(H.apply(y), H.sparse() @ y, atol=1e-13)
 
 
+def test_apply_rows_matches_assembled_matrix():
+    """Row-sampled H.v equals the same rows of the Kronecker-assembled
+    sparse matrix times the vector (non-square sector, site-dependent U)."""
+    model = wl.siam10().H_ini
+    sec = basis.Sector(model.L, 4, 6)
+    H = hamiltonian.Hamiltonian(model, sec)
+    y = wl.complex_vector(sec.dim, 3)
+    full = (H.sparse() @ y).reshape(sec.d_up, sec.d_dn)
+    rows = [0, 1, sec.d_up // 2, sec.d_up - 1]
+    np.testing.assert_allclose(H.apply_rows(y, rows), full[rows], atol=1e-13)
+
+
 @pytest.mark.parametrize("U", [0.0, 1.0, 4.0, 8.0])
 def test_dimer_closed_form(U):
     t = 1.3
