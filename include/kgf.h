@@ -273,9 +273,19 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      real and imaginary halves (the mode used for rows above
  *                      78 KB).
  *   KGF_OPT_HV_STRIP:  0 by size, or 8, 16, 32, 64 columns per strip (pass 2).
+ *   KGF_OPT_GS_MAX_BASIS: 0 = the ground-state Lanczos basis holds up to
+ *                      max_iter + 1 vectors if they fit in 70% of free device
+ *                      memory; n >= 8 caps it at n vectors.  Below max_iter + 1
+ *                      the recursion restarts from the current Ritz vector every
+ *                      n - 1 steps (same stopping rule, more iterations).
+ *   KGF_OPT_PHI_EVERY: 0 = kgf_greens_neq stores the forward mesh Phi(t_k) whole
+ *                      if it takes at most 35% of free device memory, else keeps
+ *                      every K-th state (smallest K whose checkpoints and one
+ *                      recomputed segment take at most 30%); n >= 1 fixes K = n.
+ *                      Recomputed states are bitwise equal to stored ones.
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
-enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2 };
+enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

@@ -371,10 +371,10 @@ class Context:
             out["G_mixed"] = Gx
         return out
 
-    HV_PASSES, HV_STRIP = 1, 2
+    HV_PASSES, HV_STRIP, GS_MAX_BASIS, PHI_EVERY = 1, 2, 3, 4
 
     def set_option(self, option: int, value: int) -> None:
-        """Kernel-variant choice (kgf_set_option): HV_PASSES 0..3, HV_STRIP 0/8/16/32/64."""
+        """kgf_set_option: HV_PASSES 0..3, HV_STRIP 0/8/16/32/64, GS_MAX_BASIS 0 or >= 8, PHI_EVERY >= 0."""
         _check(_lib.kgf_set_option(self.handle, int(option), int(value)))
 
     def set_progress(self, fn=None):

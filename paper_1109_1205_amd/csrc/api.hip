@@ -460,6 +460,12 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
             KGF_REQUIRE(value == 0 || value == 8 || value == 16 || value == 32 || value == 64, KGF_EINVAL,
                         "kgf_set_option: HV_STRIP must be 0, 8, 16, 32 or 64");
             ctx->hv_strip = value;
+        } else if (option == KGF_OPT_GS_MAX_BASIS) {
+            KGF_REQUIRE(value == 0 || value >= 8, KGF_EINVAL, "kgf_set_option: GS_MAX_BASIS must be 0 or >= 8");
+            ctx->gs_max_basis = value;
+        } else if (option == KGF_OPT_PHI_EVERY) {
+            KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: PHI_EVERY must be >= 0");
+            ctx->phi_every = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

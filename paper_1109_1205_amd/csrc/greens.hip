@@ -246,6 +246,39 @@ void greens_eq(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const doub
     sync(ctx);
 }
 
+// The forward mesh Phi(t_k) = exp(-iH t_k)|0>, k < nt.  Stored whole when it
+// fits; otherwise only every K-th state is kept (checkpoints) and the states
+// in between are recomputed, one segment of K - 1 states at a time, by the
+// same forward steps (so every Phi(t_k) is bitwise the stored-mesh value).
+// Accesses that walk k monotonically recompute each segment once.
+struct PhiMesh {
+    kgf_ctx* ctx = nullptr;
+    kgf_model* H = nullptr;
+    const kgf_sector* sec = nullptr;
+    SilOpts fo;
+    int spg = 1, nt = 0, K = 1;
+    int64_t D = 0;
+    double2* ck = nullptr;    // K == 1: all nt states; else ceil(nt / K) checkpoints
+    double2* seg = nullptr;   // K - 1 states after the current checkpoint
+    int seg_id = -1;
+
+    const double2* at(int k) {
+        if (K == 1) return ck + (size_t)k * D;
+        const int c = k / K, i = k % K;
+        if (i == 0) return ck + (size_t)c * D;
+        if (seg_id != c) {
+            for (int r = 1; r < K && c * K + r < nt; ++r) {
+                double2* dst = seg + (size_t)(r - 1) * D;
+                const double2* src = r == 1 ? ck + (size_t)c * D : dst - D;
+                KGF_HIP(hipMemcpyAsync(dst, src, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+                sil_propagate(ctx, H, sec, dst, 1, D, spg, fo);
+            }
+            seg_id = c;
+        }
+        return seg + (size_t)(i - 1) * D;
+    }
+};
+
 struct NeqArgs {
     kgf_model* H_ini;
     kgf_model* H;
@@ -261,7 +294,7 @@ struct NeqArgs {
 // step (iii)+(iv) for one spin group and one operator (c or c+);
 // also the mixed component when `mixed_dev` is given (lesser only).
 static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& loc, int spin, int dagger,
-                       const double2* Phi, double2* Gdev, const double2* hole_states, const kgf_sector* hole_sec,
+                       PhiMesh& Phi, double2* Gdev, const double2* hole_states, const kgf_sector* hole_sec,
                        double2* Gmix_dev) {
     const kgf_sector* sec = A.sec;
     auto tgt = shifted(ctx, sec, spin, dagger ? +1 : -1);
@@ -289,7 +322,7 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
         for (int q = 0; q < na; ++q)
             for (int k = 0; k < nt; ++k) {
                 double2* x = Psi + ((size_t)q * nt + k) * Dt;
-                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, x, 1, D, Dt);
+                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi.at(k), x, 1, D, Dt);
                 if (k > 0) sil_propagate(ctx, A.H, tgt.get(), x, 1, Dt, k * A.spg, so);
                 progress(ctx, dagger ? "backward_greater" : "backward_lesser", (int64_t)q * nt + k + 1,
                          (int64_t)na * nt);
@@ -338,12 +371,12 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
         for (int s = jhi; s >= 0; --s) {
             if (s >= jlo) {
                 for (int q = 0; q < na; ++q)
-                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)s * D, S + (size_t)(ncur + q) * Dt,
+                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi.at(s), S + (size_t)(ncur + q) * Dt,
                             1, D, Dt);
                 ncur += na;
             }
             for (int q = 0; q < na; ++q)
-                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)s * D, Lb + (size_t)q * Dt, 1, D, Dt);
+                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi.at(s), Lb + (size_t)q * Dt, 1, D, Dt);
             // tmp[b][r] = <c_b Phi_s | X_r>
             block_dots(ctx, Lb, Dt, na, S, Dt, ncur, Dt, tmp, ncur);
             place(ctx, tmp, na, na, ncur, jhi, raw, s * ss, sb, sa, sj);
@@ -366,6 +399,22 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
     sync(ctx);
 }
 
+// Grid points between stored forward states: 1 (store all) when the mesh
+// takes at most 35% of free device memory, else the smallest K whose
+// checkpoints plus one segment take at most 30%; kgf_set_option can fix K.
+static int phi_checkpoint_interval(kgf_ctx* ctx, int nt, int64_t D) {
+    if (ctx->phi_every > 0) return std::min(ctx->phi_every, std::max(nt, 1));
+    size_t free_b = 0, total_b = 0;
+    KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+    const double vb = 16.0 * (double)D;
+    if (vb * nt <= 0.35 * (double)free_b) return 1;
+    for (int K = 2; K <= nt; ++K) {
+        const int nck = (nt + K - 1) / K;
+        if (vb * (nck + K - 1) <= 0.30 * (double)free_b) return K;
+    }
+    return std::max(nt, 1);
+}
+
 void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso, double* E0_out,
                 double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host) {
     const kgf_sector* sec = A.sec;
@@ -381,17 +430,40 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
     *E0_out = E0;
     if (psi0_out)
         KGF_HIP(hipMemcpyAsync(psi0_out, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
-    // (ii) forward states on the mesh
-    ensure_device_fits(sizeof(double2) * (size_t)nt * D, "four-step forward mesh");
-    double2* Phi = static_cast<double2*>(workspace(ctx, "neq_phi", sizeof(double2) * (size_t)nt * D));
-    KGF_HIP(hipMemcpyAsync(Phi, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
-    SilOpts fo = A.o;
-    fo.direction = -1;
-    for (int k = 1; k < nt; ++k) {
-        KGF_HIP(hipMemcpyAsync(Phi + (size_t)k * D, Phi + (size_t)(k - 1) * D, sizeof(double2) * D,
-                               hipMemcpyDeviceToDevice, ctx->stream));
-        sil_propagate(ctx, A.H, sec, Phi + (size_t)k * D, 1, D, A.spg, fo);
-        progress(ctx, "forward", k, nt - 1);
+    // (ii) forward states on the mesh (whole, or checkpoints every K)
+    PhiMesh Phi;
+    Phi.ctx = ctx;
+    Phi.H = A.H;
+    Phi.sec = sec;
+    Phi.fo = A.o;
+    Phi.fo.direction = -1;
+    Phi.spg = A.spg;
+    Phi.nt = nt;
+    Phi.D = D;
+    Phi.K = phi_checkpoint_interval(ctx, nt, D);
+    const int nck = (nt + Phi.K - 1) / Phi.K;
+    const size_t vb = sizeof(double2) * (size_t)D;
+    ensure_device_fits(vb * (size_t)(nck + (Phi.K > 1 ? Phi.K - 1 : 0)), "four-step forward mesh");
+    Phi.ck = static_cast<double2*>(workspace(ctx, "neq_phi", vb * (size_t)nck));
+    if (Phi.K > 1) Phi.seg = static_cast<double2*>(workspace(ctx, "neq_phiseg", vb * (size_t)(Phi.K - 1)));
+    KGF_HIP(hipMemcpyAsync(Phi.ck, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    {
+        // running state: the mesh itself (K == 1) or the first segment slot
+        double2* run = Phi.K == 1 ? Phi.ck : Phi.seg;
+        if (Phi.K > 1) KGF_HIP(hipMemcpyAsync(run, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int k = 1; k < nt; ++k) {
+            if (Phi.K == 1) {
+                KGF_HIP(hipMemcpyAsync(Phi.ck + (size_t)k * D, Phi.ck + (size_t)(k - 1) * D, vb,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+                sil_propagate(ctx, A.H, sec, Phi.ck + (size_t)k * D, 1, D, A.spg, Phi.fo);
+            } else {
+                sil_propagate(ctx, A.H, sec, run, 1, D, A.spg, Phi.fo);
+                if (k % Phi.K == 0)
+                    KGF_HIP(hipMemcpyAsync(Phi.ck + (size_t)(k / Phi.K) * D, run, vb, hipMemcpyDeviceToDevice,
+                                           ctx->stream));
+            }
+            progress(ctx, "forward", k, nt - 1);
+        }
     }
     const size_t gsz = sizeof(double2) * (size_t)nt * nt * norb * norb;
     double2* Gl = static_cast<double2*>(workspace(ctx, "neq_Gl", gsz));
@@ -478,6 +550,7 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
                                hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
     release(ctx, "neq_phi");
+    release(ctx, "neq_phiseg");
     release(ctx, "neq_cols");
     release(ctx, "sil_X");
 }

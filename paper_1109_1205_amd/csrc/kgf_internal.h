@@ -91,6 +91,8 @@ struct kgf_ctx {
     // H.v variant knobs (kgf_set_option)
     int hv_passes = 0;
     int hv_strip = 0;
+    int gs_max_basis = 0;                    // 0: as many Lanczos vectors as fit
+    int phi_every = 0;                       // 0: forward mesh stored whole when it fits
     // progress callback
     kgf_progress_fn progress = nullptr;
     void* progress_user = nullptr;

@@ -933,8 +933,10 @@ void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double
 // ---------------------------------------------------------------------------
 // ground state
 // ---------------------------------------------------------------------------
-GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v0,
-                      double2* psi0, double tol, int max_iter, int check_every, int reorth) {
+// One Lanczos run of at most max_iter steps from v0; the Ritz vector of the
+// lowest Ritz value goes to psi0 (normalised).  psi0 may alias v0.
+static GsResult gs_cycle(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v0,
+                         double2* psi0, double tol, int max_iter, int check_every, int reorth) {
     const int64_t D = sec->dim();
     const int nmax = max_iter + 1;
     const size_t vbytes = sizeof(double2) * (size_t)nmax * D;
@@ -1029,6 +1031,43 @@ GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, con
     hipLaunchKernelGGL(k_scale, dim3(NB), dim3(kThreads), 0, ctx->stream, psi0, D, res + 4);
     check_launch("k_scale");
     sync(ctx);
+    return out;
+}
+
+// Ground state of H in the sector.  When the Lanczos basis of max_iter + 1
+// vectors does not fit in device memory (large sectors), the recursion is
+// restarted from the current Ritz vector every `cap` vectors (explicit
+// restart); the iteration count and the stopping rule are unchanged.
+GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v0,
+                      double2* psi0, double tol, int max_iter, int check_every, int reorth) {
+    const int64_t D = sec->dim();
+    const size_t vbytes = sizeof(double2) * (size_t)D;
+    size_t free_b = 0, total_b = 0;
+    KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+    auto it = ctx->ws.find("gs_V");
+    const size_t have = it != ctx->ws.end() && it->second ? it->second->bytes : 0;
+    const size_t budget = have + (size_t)(0.7 * (double)free_b);
+    int64_t cap = (int64_t)(budget / std::max<size_t>(vbytes, 1));
+    if (ctx->gs_max_basis > 0) cap = std::min<int64_t>(cap, ctx->gs_max_basis);
+    if (cap >= max_iter + 1) return gs_cycle(ctx, model, sec, v0, psi0, tol, max_iter, check_every, reorth);
+    KGF_REQUIRE(cap >= 8, KGF_ENOMEM, "ground state: fewer than 8 Lanczos vectors fit in device memory");
+    const int len = (int)std::min<int64_t>(cap - 1, 4096);
+    GsResult out{0.0, 0, false, INFINITY};
+    const double2* start = v0;
+    int done = 0;
+    while (done < max_iter) {
+        const int k = std::min(len, max_iter - done);
+        GsResult r = gs_cycle(ctx, model, sec, start, psi0, tol, k, std::min(check_every, k), reorth);
+        done += r.iters > 0 ? r.iters : k;
+        out.E0 = r.E0;
+        out.residual = r.residual;
+        out.iters = done;
+        if (r.converged) {
+            out.converged = true;
+            break;
+        }
+        start = psi0;
+    }
     return out;
 }
 
