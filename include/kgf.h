@@ -207,6 +207,25 @@ int  kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                     kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
                     double* host_E0, kgf_c128* psi0_out);
 
+/* Four-step G^< and G^> (Sec. 4 steps (i)-(iv), sweep schedule) of n_inst
+ * independent instances in one call.  Instances whose sectors have equal
+ * (L, N_up, N_dn) and whose H have the same bond list form a group that runs
+ * as one batch: every Lanczos / SIL launch of the forward meshes and the
+ * backward sweeps serves all members, column c carrying the parameters of
+ * member c mod n (different hoppings, on-site energies and U per instance);
+ * ground states are found one instance at a time.  Results equal
+ * kgf_greens_neq on each instance up to rounding.
+ * Per-instance inputs: H_ini[i], H[i], sectors[i], v0[i] (device, D_i).
+ * Outputs (host): host_G_lesser, host_G_greater [n_inst][nt][nt][n_orb][n_orb]
+ * (NULL to skip); host_E0 [n_inst].  `batch` caps the columns of one sweep
+ * block (0 = from free memory).  No Matsubara branch.  Errors as kgf_greens_neq. */
+int  kgf_greens_neq_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H_ini,
+                          const kgf_model* const* H, const kgf_sector* const* sectors,
+                          const kgf_c128* const* v0, const kgf_gs_opts* gs_opts,
+                          const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
+                          const kgf_prop_opts* opts, int batch, kgf_c128* host_G_lesser,
+                          kgf_c128* host_G_greater, double* host_E0);
+
 /* ---- parameter derivatives and the adjoint (reverse mode) ------------------
  * Parameters of a model: theta = (t_b for b < n_bonds, eps_up_i, eps_dn_i,
  * U_i for i < L), n_theta = n_bonds + 3 L; dH/dt_b = -sum_s (c+_i c_j + h.c.),

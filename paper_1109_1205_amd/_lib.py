@@ -101,6 +101,8 @@ def load_library():
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
         "kgf_set_option": (I, [P, I, I]),
+        "kgf_greens_neq_multi": (I, [P, I, P, P, P, P, C.POINTER(_GsOpts), P, I, I, I, C.POINTER(_PropOpts), I, P, P,
+                                     P]),
         "kgf_n_theta": (I, [P]),
         "kgf_dH_expect": (I, [P, P, P, P, P, I, I64, P, P]),
         "kgf_propagate_vjp": (I, [P, P, P, P, P, I, C.POINTER(_PropOpts), I, P]),
@@ -123,7 +125,8 @@ def exported_symbols() -> Sequence[str]:
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
-            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_profile_begin", "kgf_profile_end"]
+            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_profile_begin",
+            "kgf_profile_end"]
 
 
 def _check(rc: int):
@@ -370,6 +373,33 @@ class Context:
             out["G_matsubara"] = GM
             out["G_mixed"] = Gx
         return out
+
+    def greens_neq_multi(self, H_ini: Sequence[Model], H: Sequence[Model], secs: Sequence[Sector], v0s,
+                         orbitals: Sequence[Tuple[int, int]], nt: int, steps_per_grid: int, dt: float,
+                         krylov_dim: int = 15, reorth: int = 0, batch: int = 0, gs_tol: float = 1e-12,
+                         gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                         breakdown_tol: float = 1e-13):
+        """kgf_greens_neq_multi: four-step G^<, G^> of many instances in one call
+        (same-sector, same-topology instances batched).  Returns G_lesser,
+        G_greater [n][nt][nt][n_orb][n_orb] and E0 [n]."""
+        n = len(H)
+        assert len(H_ini) == n and len(secs) == n and len(v0s) == n
+        for v, s_ in zip(v0s, secs):
+            self._chk(v, s_.dim, "v0")
+        orbs = np.ascontiguousarray([2 * s_ + sp for s_, sp in orbitals], dtype=np.int32)
+        no = len(orbs)
+        Gl = _host_c128((n, nt, nt, no, no))
+        Gg = _host_c128((n, nt, nt, no, no))
+        E0 = np.zeros(n)
+        def arr(xs):
+            return (C.c_void_p * n)(*[(x.value if isinstance(x, C.c_void_p) else int(x)) for x in xs])
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        _check(_lib.kgf_greens_neq_multi(self.handle, n, arr(m.handle for m in H_ini), arr(m.handle for m in H),
+                                         arr(s_.handle for s_ in secs), arr(_ptr(v) for v in v0s), C.byref(g),
+                                         _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(batch),
+                                         _np_ptr(Gl), _np_ptr(Gg), _np_ptr(E0)))
+        return {"G_lesser": Gl, "G_greater": Gg, "E0": E0}
 
     HV_PASSES, HV_STRIP, GS_MAX_BASIS, PHI_EVERY = 1, 2, 3, 4
 

@@ -555,6 +555,139 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
     release(ctx, "sil_X");
 }
 
+// Four-step G^<, G^> (sweep schedule) for several instances at once.
+// Instances with equal sectors and bond topologies form a group; a group's
+// forward meshes and backward sweeps run as one multi-column batch in which
+// column c carries the Hamiltonian of member c mod n (ModelSet), so every
+// launch serves all members.  Ground states are found per instance.
+// Gl_host / Gg_host: [ninst][nt][nt][norb][norb]; E0_host: [ninst].
+void greens_neq_multi(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* const* Hf,
+                      const kgf_sector* const* secs, const double2* const* v0, const kgf_gs_opts* gso,
+                      const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch, double2* Gl_host,
+                      double2* Gg_host, double* E0_host) {
+    std::vector<int> done(ninst, 0);
+    const size_t gsz = (size_t)nt * nt * norb * norb;
+    for (int i0 = 0; i0 < ninst; ++i0) {
+        if (done[i0]) continue;
+        std::vector<int> mem;
+        for (int i = i0; i < ninst; ++i)
+            if (!done[i] && secs[i]->L == secs[i0]->L && secs[i]->n_up == secs[i0]->n_up &&
+                secs[i]->n_dn == secs[i0]->n_dn && same_topology(Hf[i], Hf[i0])) {
+                mem.push_back(i);
+                done[i] = 1;
+            }
+        const int n = (int)mem.size();
+        const kgf_sector* sec = secs[i0];
+        const int64_t D = sec->dim();
+        const size_t vb = sizeof(double2) * (size_t)D;
+        ModelSet Sf;
+        for (int i : mem) Sf.models.push_back(Hf[i]);
+        model_set_init(ctx, Sf);
+        // (i) ground states, (ii) forward meshes Phi[k][member]
+        ensure_device_fits(vb * (size_t)nt * n, "batched four-step forward meshes");
+        double2* Phi = static_cast<double2*>(workspace(ctx, "mneq_phi", vb * (size_t)nt * n));
+        for (int k = 0; k < n; ++k) {
+            GsResult gs = ground_state(ctx, Hi[mem[k]], sec, v0[mem[k]], Phi + (size_t)k * D, gso->tol, gso->max_iter,
+                                       gso->check_every, gso->reorth);
+            KGF_REQUIRE(gs.converged, KGF_ENOCONV, "batched four-step: a ground state of H_ini did not converge");
+            E0_host[mem[k]] = gs.E0;
+            progress(ctx, "ground_states", k + 1, n);
+        }
+        release(ctx, "gs_V");
+        release(ctx, "gs_partbig");
+        SilOpts fo = o;
+        fo.direction = -1;
+        for (int t = 1; t < nt; ++t) {
+            double2* cur = Phi + (size_t)t * n * D;
+            KGF_HIP(hipMemcpyAsync(cur, cur - (size_t)n * D, vb * n, hipMemcpyDeviceToDevice, ctx->stream));
+            sil_propagate(ctx, HModel(&Sf), sec, cur, n, D, spg, fo);
+            progress(ctx, "forward", t, nt - 1);
+        }
+        auto phi = [&](int t) { return Phi + (size_t)t * n * D; };
+        std::vector<double2> Gl((size_t)n * gsz, make_double2(0, 0)), Gg((size_t)n * gsz, make_double2(0, 0));
+        SilOpts so = o;
+        so.direction = +1;
+        for (int spin = 0; spin < 2; ++spin) {
+            std::vector<int> loc;
+            for (int a = 0; a < norb; ++a)
+                if ((orbs[a] & 1) == spin) loc.push_back(a);
+            const int na = (int)loc.size();
+            if (!na) continue;
+            DevBuf gidx;
+            upload_ints(ctx, gidx, loc);
+            for (int dagger = 0; dagger < 2; ++dagger) {
+                auto tgt = shifted(ctx, sec, spin, dagger ? +1 : -1);
+                if (!tgt || tgt->dim() == 0) continue;
+                const int64_t Dt = tgt->dim();
+                const size_t rsz = (size_t)nt * nt * na * na;
+                double2* raw = static_cast<double2*>(workspace(ctx, "mneq_raw", sizeof(double2) * rsz * n));
+                KGF_HIP(hipMemsetAsync(raw, 0, sizeof(double2) * rsz * n, ctx->stream));
+                const size_t per_col = sizeof(double2) * (size_t)(o.m + 1) * Dt;
+                int Bcols = batch;
+                if (Bcols <= 0) {
+                    size_t free_b = 0, total_b = 0;
+                    KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+                    Bcols = (int)std::max<size_t>(1, (size_t)(0.8 * (double)free_b) / per_col);
+                }
+                const int jchunk = std::min(nt, std::max(1, Bcols / (na * n)));
+                const int maxcols = jchunk * na * n;
+                release(ctx, "sil_X");
+                sil_reserve(ctx, tgt.get(), maxcols, o.m, o.reorth);
+                ensure_device_fits(sizeof(double2) * (size_t)maxcols * Dt, "batched four-step sweep block");
+                double2* S = static_cast<double2*>(workspace(ctx, "mneq_cols", sizeof(double2) * (size_t)maxcols * Dt));
+                double2* Lb = static_cast<double2*>(workspace(ctx, "mneq_left", sizeof(double2) * (size_t)na * n * Dt));
+                double2* tmp = static_cast<double2*>(workspace(ctx, "mneq_tmp", sizeof(double2) * (size_t)na * jchunk * na));
+                const int64_t ss = (int64_t)na * na * nt, sb = (int64_t)na * nt, sa = nt, sj = 1;
+                for (int jhi = nt - 1; jhi >= 0; jhi -= jchunk) {
+                    const int jlo = std::max(0, jhi - jchunk + 1);
+                    int ncur = 0;   // columns per member; column (r, member) at S + (r * n + member) * Dt
+                    for (int s2 = jhi; s2 >= 0; --s2) {
+                        if (s2 >= jlo) {
+                            for (int q = 0; q < na; ++q)
+                                apply_c(ctx, sec, tgt.get(), orbs[loc[q]], dagger, phi(s2),
+                                        S + (size_t)(ncur + q) * n * Dt, n, D, Dt);
+                            ncur += na;
+                        }
+                        for (int q = 0; q < na; ++q)
+                            apply_c(ctx, sec, tgt.get(), orbs[loc[q]], dagger, phi(s2), Lb + (size_t)q * n * Dt, n, D,
+                                    Dt);
+                        for (int k = 0; k < n; ++k) {
+                            block_dots(ctx, Lb + (size_t)k * Dt, (int64_t)n * Dt, na, S + (size_t)k * Dt,
+                                       (int64_t)n * Dt, ncur, Dt, tmp, ncur);
+                            place(ctx, tmp, na, na, ncur, jhi, raw + (size_t)k * rsz, s2 * ss, sb, sa, sj);
+                        }
+                        if (s2 > 0) sil_propagate(ctx, HModel(&Sf), tgt.get(), S, ncur * n, Dt, spg, so);
+                        progress(ctx, dagger ? "batch_sweep_greater" : "batch_sweep_lesser", jhi - s2 + 1, jhi + 1);
+                    }
+                }
+                double2* Gdev = static_cast<double2*>(workspace(ctx, "mneq_G", sizeof(double2) * gsz * n));
+                KGF_HIP(hipMemsetAsync(Gdev, 0, sizeof(double2) * gsz * n, ctx->stream));
+                const int64_t total = (int64_t)nt * nt * na * na;
+                for (int k = 0; k < n; ++k) {
+                    hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)),
+                                       dim3(kThreads), 0, ctx->stream, raw + (size_t)k * rsz, ss, sb, sa, sj, nt, na,
+                                       gidx.as<int>(), norb, dagger, 1, Gdev + (size_t)k * gsz);
+                    check_launch("k_store_neq");
+                }
+                std::vector<double2> h((size_t)n * gsz);
+                KGF_HIP(hipMemcpyAsync(h.data(), Gdev, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+                sync(ctx);
+                // only the entries of this spin group were written (the rest are zero)
+                std::vector<double2>& dst = dagger ? Gg : Gl;
+                for (size_t e = 0; e < h.size(); ++e)
+                    if (h[e].x != 0.0 || h[e].y != 0.0) dst[e] = h[e];
+            }
+        }
+        for (int k = 0; k < n; ++k) {
+            if (Gl_host) std::copy(Gl.begin() + (size_t)k * gsz, Gl.begin() + (size_t)(k + 1) * gsz,
+                                   Gl_host + (size_t)mem[k] * gsz);
+            if (Gg_host) std::copy(Gg.begin() + (size_t)k * gsz, Gg.begin() + (size_t)(k + 1) * gsz,
+                                   Gg_host + (size_t)mem[k] * gsz);
+        }
+        for (const char* nm : {"mneq_phi", "mneq_cols", "mneq_left", "mneq_raw", "mneq_G", "sil_X"}) release(ctx, nm);
+    }
+}
+
 }  // namespace kgf
 
 using namespace kgf;
@@ -601,5 +734,35 @@ extern "C" int kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_mo
                    reinterpret_cast<double2*>(psi0_out), reinterpret_cast<double2*>(host_G_lesser),
                    reinterpret_cast<double2*>(host_G_greater), reinterpret_cast<double2*>(host_G_matsubara),
                    reinterpret_cast<double2*>(host_G_mixed));
+    });
+}
+
+extern "C" int kgf_greens_neq_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H_ini,
+                                    const kgf_model* const* H, const kgf_sector* const* sectors,
+                                    const kgf_c128* const* v0, const kgf_gs_opts* gs_opts, const int32_t* host_orbs,
+                                    int n_orb, int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch,
+                                    kgf_c128* host_G_lesser, kgf_c128* host_G_greater, double* host_E0) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(ctx && n_inst >= 1 && H_ini && H && sectors && v0 && gs_opts && host_orbs && host_E0, KGF_EINVAL,
+                    "kgf_greens_neq_multi: NULL argument");
+        kgf::check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && batch >= 0, KGF_EINVAL,
+                    "kgf_greens_neq_multi: bad sizes");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                    KGF_EINVAL, "kgf_greens_neq_multi: bad ground-state options");
+        for (int i = 0; i < n_inst; ++i) {
+            KGF_REQUIRE(H_ini[i] && H[i] && sectors[i] && v0[i], KGF_EINVAL, "kgf_greens_neq_multi: NULL instance");
+            KGF_REQUIRE(H_ini[i]->L == sectors[i]->L && H[i]->L == sectors[i]->L && sectors[i]->dim() > 0,
+                        KGF_EINVAL, "kgf_greens_neq_multi: model / sector mismatch or empty sector");
+            for (int a = 0; a < n_orb; ++a)
+                KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sectors[i]->L, KGF_EINVAL,
+                            "kgf_greens_neq_multi: orbital out of range");
+        }
+        KGF_HIP(hipSetDevice(ctx->device));
+        greens_neq_multi(ctx, n_inst, const_cast<kgf_model* const*>(H_ini), const_cast<kgf_model* const*>(H), sectors,
+                         reinterpret_cast<const double2* const*>(v0), gs_opts, host_orbs, n_orb, nt, steps_per_grid,
+                         kgf::to_sil_opts(opts), batch, reinterpret_cast<double2*>(host_G_lesser),
+                         reinterpret_cast<double2*>(host_G_greater), host_E0);
     });
 }

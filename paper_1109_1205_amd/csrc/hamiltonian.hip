@@ -31,9 +31,71 @@ struct HvTables {
     const double* Utab;   // [3 * 256]
     double U0;
     int nb;
+    // parameter sets (ModelSet): column c uses set (cbase + c) mod npar
+    int npar;
+    int cbase;
+    const double* U0s;    // [npar] or null (then U0)
 };
 
-HvTables make_tables(kgf_model* model, const kgf_sector* sec) {
+__device__ __forceinline__ int par_index(const HvTables& T, int c) { return T.npar > 1 ? (T.cbase + c) % T.npar : 0; }
+__device__ __forceinline__ double par_U0(const HvTables& T, int pm) { return T.U0s ? T.U0s[pm] : T.U0; }
+
+}  // namespace
+
+bool same_topology(const kgf_model* a, const kgf_model* b) {
+    return a->L == b->L && a->nb == b->nb && a->bi == b->bi && a->bj == b->bj;
+}
+
+void model_set_init(kgf_ctx* ctx, ModelSet& S) {
+    const int n = (int)S.models.size();
+    KGF_REQUIRE(n >= 1, KGF_EINVAL, "model set: no models");
+    kgf_model* m0 = S.models[0];
+    S.U_uniform = true;
+    for (kgf_model* m : S.models) {
+        KGF_REQUIRE(m && same_topology(m0, m), KGF_EINVAL, "model set: models differ in L or bonds");
+        S.U_uniform = S.U_uniform && m->U_uniform;
+    }
+    const int nb = std::max(m0->nb, 1);
+    std::vector<double> t((size_t)n * nb, 0.0), U0(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        for (int b = 0; b < S.models[i]->nb; ++b) t[(size_t)i * nb + b] = S.models[i]->t[b];
+        U0[i] = S.models[i]->U.empty() ? 0.0 : S.models[i]->U[0];
+    }
+    S.t.reserve(sizeof(double) * t.size());
+    S.U0.reserve(sizeof(double) * n);
+    S.Utab.reserve(sizeof(double) * 768 * n);
+    KGF_HIP(hipMemcpy(S.t.p, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    KGF_HIP(hipMemcpy(S.U0.p, U0.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    for (int i = 0; i < n; ++i)
+        KGF_HIP(hipMemcpy(S.Utab.as<double>() + (size_t)768 * i, S.models[i]->d_Utab.p, sizeof(double) * 768,
+                          hipMemcpyDeviceToDevice));
+    S.eu.clear();
+    S.ed.clear();
+}
+
+namespace {
+
+// on-site energies of every member for the masks of n particles (up or down)
+const double* set_onsite(ModelSet& S, int n, bool up) {
+    auto& mp = up ? S.eu : S.ed;
+    auto it = mp.find(n);
+    if (it != mp.end()) return it->second->as<double>();
+    const int nm = (int)S.models.size();
+    HopTable& t0 = hop_table(S.models[0], n);
+    auto buf = std::make_unique<DevBuf>();
+    buf->reserve(sizeof(double) * (size_t)nm * std::max<int64_t>(t0.D, 1));
+    for (int i = 0; i < nm; ++i) {
+        HopTable& ti = hop_table(S.models[i], n);
+        KGF_HIP(hipMemcpy(buf->as<double>() + (size_t)i * t0.D, (up ? ti.e_up : ti.e_dn).p, sizeof(double) * t0.D,
+                          hipMemcpyDeviceToDevice));
+    }
+    const double* p = buf->as<double>();
+    mp[n] = std::move(buf);
+    return p;
+}
+
+HvTables make_tables(HModel hm, const kgf_sector* sec) {
+    kgf_model* model = hm.m;
     HopTable& tu = hop_table(model, sec->n_up);
     HopTable& td = hop_table(model, sec->n_dn);
     HvTables T;
@@ -51,8 +113,22 @@ HvTables make_tables(kgf_model* model, const kgf_sector* sec) {
     T.Utab = model->d_Utab.as<double>();
     T.U0 = model->U.empty() ? 0.0 : model->U[0];
     T.nb = model->nb;
+    T.npar = 1;
+    T.cbase = 0;
+    T.U0s = nullptr;
+    if (hm.set) {
+        ModelSet& S = *hm.set;
+        T.npar = (int)S.models.size();
+        T.t = S.t.as<double>();
+        T.Utab = S.Utab.as<double>();
+        T.U0s = S.U0.as<double>();
+        T.eu = set_onsite(S, sec->n_up, true);
+        T.ed = set_onsite(S, sec->n_dn, false);
+    }
     return T;
 }
+
+bool uniform_U(HModel hm) { return hm.set ? hm.set->U_uniform : hm.m->U_uniform; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -95,9 +171,9 @@ __global__ __launch_bounds__(kThreads) void k_hv(HvTables T, const double2* __re
     const double2* __restrict__ x = X + c * x_col;
     double2* __restrict__ y = Y + c * y_col;
 
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
     if (!UNIFORM_U)
-        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[i];
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par_index(T, blockIdx.y) * 768 + i];
     __syncthreads();
     const int cu = T.cnt_up[u];
     for (int k = tid; k < cu; k += blockDim.x) {
@@ -114,16 +190,16 @@ __global__ __launch_bounds__(kThreads) void k_hv(HvTables T, const double2* __re
         if (XP) bp = b_k[c * stride] * s_km1[c * stride];
     }
     const uint32_t mu = T.mu[u];
-    const double eu = T.eu[u];
+    const double eu = T.eu[par_index(T, blockIdx.y) * T.Dup + u];
     const double2* __restrict__ xrow = x + u * Ddn;
     double dot = 0.0;
 
     for (int64_t d = tid; d < Ddn; d += blockDim.x) {
         const double2 xv = xrow[d];
         const uint32_t both = mu & T.md[d];
-        double dg = eu + T.ed[d];
+        double dg = eu + T.ed[par_index(T, blockIdx.y) * T.Ddn + d];
         if (UNIFORM_U) {
-            dg += T.U0 * (double)__popc(both);
+            dg += par_U0(T, par_index(T, blockIdx.y)) * (double)__popc(both);
         } else {
             dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
         }
@@ -202,9 +278,9 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_
     const double2* __restrict__ xrow = x + u * Ddn;
 
     for (int64_t d = tid; d < Ddn; d += blockDim.x) srow[d] = xrow[d];
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
     if (!UNIFORM_U)
-        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[i];
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par_index(T, blockIdx.y) * 768 + i];
     __syncthreads();
     const int cu = T.cnt_up[u];
     for (int k = tid; k < cu; k += blockDim.x) {
@@ -221,7 +297,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_
         if (XP) bp = b_k[c * stride] * s_km1[c * stride];
     }
     const uint32_t mu = T.mu[u];
-    const double eu = T.eu[u];
+    const double eu = T.eu[par_index(T, blockIdx.y) * T.Dup + u];
     double dot = 0.0;
     // Gathers are issued in predicated batches of kBatch so that many loads
     // are in flight per thread (the hop counts are data dependent).
@@ -230,9 +306,9 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_
         const double2 xv = srow[d];
         const uint32_t both = mu & T.md[d];
         const int cd = T.cnt_dn[d];
-        double dg = eu + T.ed[d];
+        double dg = eu + T.ed[par_index(T, blockIdx.y) * T.Ddn + d];
         if (UNIFORM_U) {
-            dg += T.U0 * (double)__popc(both);
+            dg += par_U0(T, par_index(T, blockIdx.y)) * (double)__popc(both);
         } else {
             dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
         }
@@ -320,15 +396,15 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
     const int64_t Ddn = T.Ddn;
     const double2* __restrict__ xrow = X + c * x_col + u * Ddn;
     double2* __restrict__ yrow = Y + c * y_col + u * Ddn;
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
     if (!UNIFORM_U)
-        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[i];
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par_index(T, blockIdx.y) * 768 + i];
     const uint32_t mu = T.mu[u];
-    const double eu = T.eu[u];
+    const double eu = T.eu[par_index(T, blockIdx.y) * T.Dup + u];
     auto diag = [&](int64_t d) -> double {
         const uint32_t both = mu & T.md[d];
-        double dg = eu + T.ed[d];
-        if (UNIFORM_U) dg += T.U0 * (double)__popc(both);
+        double dg = eu + T.ed[par_index(T, blockIdx.y) * T.Ddn + d];
+        if (UNIFORM_U) dg += par_U0(T, par_index(T, blockIdx.y)) * (double)__popc(both);
         else dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
         return dg;
     };
@@ -450,7 +526,7 @@ __global__ __launch_bounds__(kUpThreads) void k_hv_up(HvTables T, int nstrip, in
     const int tid = threadIdx.x;
     const int64_t Ddn = T.Ddn, Dup = T.Dup;
     const int64_t u0 = (int64_t)tile * R;
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[b];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
     for (int i = tid; i < R * width; i += blockDim.x) {
         const int r = i % R, k = i / R;
         const int64_t u = u0 + r;
@@ -777,17 +853,18 @@ void opt_in_lds(kgf_ctx* ctx, const void* kern, int slot, size_t bytes) {
 }
 
 template <int MODE>
-void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
+void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int cbase,
                const double2* x, int64_t x_col, const double2* xp, int64_t xp_col, double2* y,
                int64_t y_col, const double* s_k, const double* b_k, const double* s_km1,
                int stride, double* part) {
     HvTables T = make_tables(model, sec);
+    T.cbase = cbase;
     KGF_REQUIRE(sec->d_up <= 0x7ffffff0 && ncol <= 65535, KGF_EUNSUPPORTED, "H.v: grid too large");
     // algorithmic bytes: read x once, write y once, read xp once if present
     const double vec = 16.0 * (double)sec->dim() * ncol;
     Prof pr(ctx, MODE == 0 ? "hv" : "hv_lanczos", vec * (xp ? 3.0 : 2.0));
     const HvPlan P = hv_plan(ctx, sec);
-    const bool uu = model->U_uniform;
+    const bool uu = uniform_U(model);
     if (P.passes == 1) {
         const size_t row_bytes = sizeof(double2) * (size_t)sec->d_dn;
         const int rpx = (int)((sec->d_up + 7) / 8);
@@ -800,7 +877,7 @@ void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
         return;
     }
     if (P.passes == 2) {
-        KGF_REQUIRE(P.up_blocks <= 0x7fffffff && (int64_t)model->nb * sec->d_dn < ((int64_t)1 << 32),
+        KGF_REQUIRE(P.up_blocks <= 0x7fffffff && (int64_t)model.m->nb * sec->d_dn < ((int64_t)1 << 32),
                     KGF_EUNSUPPORTED, "H.v: strip grid or hop table too large");
         const size_t lds = P.split ? sizeof(double) * (size_t)sec->d_dn : sizeof(double2) * (size_t)sec->d_dn;
         dim3 rg((unsigned)sec->d_up, (unsigned)ncol);
@@ -814,7 +891,7 @@ void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
             hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
         }
         check_launch("k_hv_rows");
-        const int w = model->nb;
+        const int w = model.m->nb;
         switch (P.C) {
             case 64: launch_up<MODE, 64>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
             case 32: launch_up<MODE, 32>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
@@ -836,11 +913,11 @@ void launch_hv(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
 
 }  // namespace
 
-void apply_h(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v, double2* w,
+void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec, const double2* v, double2* w,
              int nvec, int64_t ld) {
     for (int c0 = 0; c0 < nvec; c0 += 65535) {
         int nc = nvec - c0 < 65535 ? nvec - c0 : 65535;
-        launch_hv<0>(ctx, model, sec, nc, v + c0 * ld, ld, nullptr, 0, w + c0 * ld, ld, nullptr,
+        launch_hv<0>(ctx, model, sec, nc, c0, v + c0 * ld, ld, nullptr, 0, w + c0 * ld, ld, nullptr,
                      nullptr, nullptr, 0, nullptr);
     }
 }
@@ -850,9 +927,9 @@ int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec) {
     return P.passes == 2 ? (int)P.up_blocks : (int)sec->d_up;
 }
 
-void hv_lanczos(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
+void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a) {
-    launch_hv<1>(ctx, model, sec, ncol, a.x, a.x_col, a.xp, a.xp_col, a.y, a.y_col, a.s_k, a.b_k,
+    launch_hv<1>(ctx, model, sec, ncol, 0, a.x, a.x_col, a.xp, a.xp_col, a.y, a.y_col, a.s_k, a.b_k,
                  a.s_km1, a.stride, a.part);
 }
 

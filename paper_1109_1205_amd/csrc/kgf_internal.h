@@ -151,7 +151,31 @@ int64_t binom_host(int n, int k);
 
 // ---- hamiltonian (hamiltonian.hip) ---------------------------------------
 HopTable& hop_table(kgf_model* model, int n);
-void apply_h(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec,
+
+// Parameter sets of several models with one bond topology (same L and bond
+// list), for batches whose columns carry different Hamiltonians: column c
+// of a launch uses member c mod n.  The hopping tables (targets, bonds,
+// signs) depend on the topology only and are shared.
+struct ModelSet {
+    std::vector<kgf_model*> models;
+    bool U_uniform = true;
+    DevBuf t;      // double [n][nb]
+    DevBuf Utab;   // double [n][3 * 256]
+    DevBuf U0;     // double [n]
+    std::map<int, std::unique_ptr<DevBuf>> eu, ed;   // by particle number: double [n][D_n]
+};
+void model_set_init(kgf_ctx* ctx, ModelSet& set);   // checks the topology, uploads t, U
+bool same_topology(const kgf_model* a, const kgf_model* b);
+
+// What H.v needs: one model, or a model set (one member per column).
+struct HModel {
+    kgf_model* m = nullptr;
+    ModelSet* set = nullptr;
+    HModel(kgf_model* mm) : m(mm) {}
+    explicit HModel(ModelSet* s) : m(s->models.at(0)), set(s) {}
+};
+
+void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec,
              const double2* v, double2* w, int nvec, int64_t ld);
 void apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int orbital,
              int dagger, const double2* v, double2* w, int nvec, int64_t ld_src,
@@ -180,7 +204,7 @@ struct LanczosHvArgs {
     double* part;                          // [ncol][nblk]
 };
 int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec);
-void hv_lanczos(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, int ncol,
+void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a);
 
 // ---- krylov (krylov.hip) -------------------------------------------------
@@ -197,18 +221,7 @@ struct SilOpts {
 // re-allocation when a caller grows its batch step by step).
 void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth);
 // Lanczos bases of ncol columns (slot 0 = psi + c*ld), left in the SIL workspace.
-void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
-               int64_t ld, const SilOpts& o);
-// Coefficients of exp(dir i H t) (or exp(-(H - shift) t) for dir 0) applied to
-// column col[r], in the basis of the last sil_build: coef + r * coef_stride.
-void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, const int* dir,
-               double shift, double2* coef, int coef_stride);
-// out + o * out_col = sum_j coef[o][j] v_j(column c), o < nout (one pass over the basis)
-void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_t ld, int ncol, int m,
-                       int c, const double2* coef, int64_t coef_stride, int nout, double2* out,
-                       int64_t out_col);
-// Lanczos bases of ncol columns (slot 0 = psi + c*ld), left in the SIL workspace.
-void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol,
+void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol,
                int64_t ld, const SilOpts& o);
 // Coefficients of exp(dir i H t) (or exp(-(H - shift) t) for dir 0) applied to
 // column col[r], in the basis of the last sil_build: coef + r * coef_stride.
@@ -219,7 +232,7 @@ void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_
                        int c, const double2* coef, int64_t coef_stride, int nout, double2* out,
                        int64_t out_col);
 // Batched short-iterative-Lanczos step(s) on ncol columns psi_c = psi + c*ld.
-void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi,
+void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi,
                    int ncol, int64_t ld, int nsteps, const SilOpts& o);
 
 struct GsResult {

@@ -817,7 +817,7 @@ void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reort
 
 // Lanczos bases of ncol columns psi_c = psi + c * ld (slot 0 = psi itself);
 // leaves the scalars in "sil_scal" and slots 1..m in "sil_X".
-void sil_build(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
                const SilOpts& o) {
     const int64_t D = sec->dim();
     const int m = o.m;
@@ -906,7 +906,7 @@ void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_
     }
 }
 
-void sil_propagate(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
                    int nsteps, const SilOpts& o) {
     const int64_t D = sec->dim();
     const int m = o.m;
