@@ -50,6 +50,13 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16"], default="ladder14",
+                   help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
+                        "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
+                        "short mesh")
+    p.add_argument("--grad-instances", type=int, default=5,
+                   help="batch64: instances (one per L first) whose adjoint gradient is timed")
+    p.add_argument("--nt16", type=int, default=6, help="ladder16: mesh points")
     p.add_argument("--hv", default="",
                    help="H.v micro-benchmark instead of the four-step run: comma-separated ladder sizes "
                         "(14, 16); each is timed for every --hv-passes variant")
@@ -124,6 +131,127 @@ def probe(a):
                       "vector_bytes": 16 * sec.dim}), flush=True)
 
 
+def batch64(a):
+    """The uneven batch: 64 Anderson stars (L from 8..12, U 0 -> 4), G_imp on
+    50 x 50, dt = 0.05, Krylov dim 15.  Times (1) kgf_greens_neq_multi over all
+    instances (each L one batch), (2) kgf_greens_neq instance by instance, and
+    (3) the adjoint (kgf_greens_neq_vjp, loss sum |G - G_target|^2 with the
+    target from the same instance at U = 3) for a few instances, next to the
+    forward pass of the same instances."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    qs = wl.batch_instances()
+    ctx = kgf.Context(0)
+    Hi = [ctx.model(q.H_ini) for q in qs]
+    Hf = [ctx.model(q.H) for q in qs]
+    secs = [ctx.sector(q.H.L, q.n_up, q.n_dn) for q in qs]
+    v0 = [torch.from_numpy(wl.start_vector(s_.dim, 7)).to("cuda:0") for s_ in secs]
+    q0 = qs[0]
+    kw = dict(orbitals=q0.orbitals, nt=q0.nt, steps_per_grid=q0.steps_per_grid, dt=q0.dt, krylov_dim=q0.krylov_dim)
+    vsteps = len(qs) * ((q0.nt - 1) * q0.steps_per_grid + q0.steps_per_grid * q0.nt * (q0.nt - 1))
+    torch.cuda.synchronize()
+    log("batched: 64 instances")
+    t0 = time.perf_counter()
+    outb = ctx.greens_neq_multi(Hi, Hf, secs, v0, **kw)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log(f"batched {tb:.1f} s; per instance:")
+    t0 = time.perf_counter()
+    maxdiff = 0.0
+    for i in range(len(qs)):
+        o = ctx.greens_neq(Hi[i], Hf[i], secs[i], v0[i], schedule=1, **kw)
+        sc = max(np.abs(o["G_lesser"]).max(), np.abs(o["G_greater"]).max())
+        maxdiff = max(maxdiff, np.abs(o["G_lesser"] - outb["G_lesser"][i]).max() / sc,
+                      np.abs(o["G_greater"] - outb["G_greater"][i]).max() / sc)
+        if (i + 1) % 8 == 0:
+            log(f"  {i + 1}/64")
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    # adjoint timings: the first instance of each L, then more
+    order = sorted(range(len(qs)), key=lambda i: (qs[i].H.L, i))
+    pick, seen = [], set()
+    for i in order:
+        if qs[i].H.L not in seen:
+            pick.append(i)
+            seen.add(qs[i].H.L)
+    pick = pick[:max(1, a.grad_instances)]
+    grad_rows = []
+    for i in pick:
+        q = qs[i]
+        tgt_model = q.H.with_U([3.0] + [0.0] * (q.H.L - 1))
+        tgt = ctx.greens_neq(ctx.model(q.H_ini), ctx.model(tgt_model), secs[i], v0[i], schedule=1, **kw)
+        Wl = 2.0 * (outb["G_lesser"][i] - tgt["G_lesser"])
+        Wg = 2.0 * (outb["G_greater"][i] - tgt["G_greater"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = ctx.greens_neq(Hi[i], Hf[i], secs[i], v0[i], schedule=0, **kw)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = ctx.greens_neq_vjp(Hi[i], Hf[i], secs[i], v0[i], q.orbitals, q.nt, q.steps_per_grid, q.dt, Wl, Wg,
+                               krylov_dim=q.krylov_dim, quad_nodes=12)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        grad_rows.append({"instance": q.name, "D": secs[i].dim, "forward_plain_s": round(tf, 2),
+                          "adjoint_s": round(ta, 2), "adjoint_over_forward": round(ta / tf, 2),
+                          "grad_norm": float(np.linalg.norm(r["grad"])), "cg_iters": r["cg_iters"]})
+        log(f"adjoint {q.name}: forward {tf:.1f} s, adjoint {ta:.1f} s")
+    res = {"metric": "G(t,t') contour steps/s, 64 uneven Anderson instances (batched vs per instance)",
+           "value": round(vsteps / tb, 1), "unit": "vector-steps/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batch64: 64 Anderson stars, L 8..12 (seeds 4000+i), U 0->4, eps_imp -2, "
+                                  "G_imp 50x50, t_k=0.2k, dt=0.05, Krylov dim 15",
+                      "vector_steps": vsteps},
+           "batched_s": round(tb, 2), "per_instance_s": round(tp, 2), "speedup": round(tp / tb, 3),
+           "per_instance_value": round(vsteps / tp, 1), "max_rel_diff_batched_vs_per_instance": maxdiff,
+           "adjoint": grad_rows}
+    print(json.dumps(res), flush=True)
+
+
+def ladder16(a):
+    """The 2x8 ladder quench (D = 165,636,900) on a short mesh of --nt16
+    points: restarted ground state, checkpointed forward mesh, sweeps of
+    the c and c+ branches.  Reports contour steps/s and the Lanczos H.v rate."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    q = wl.ladder16()
+    ctx = kgf.Context(0)
+    last = [time.perf_counter()]
+
+    def report(phase, done, total):
+        now = time.perf_counter()
+        if now - last[0] >= 20.0 or done == total:
+            last[0] = now
+            log(f"  {phase} {done}/{total}")
+    ctx.set_progress(report)
+    s = ctx.sector(16, q.n_up, q.n_dn)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, q.gs_seed)).to("cuda:0")
+    nt = a.nt16
+    ctx.profile_begin(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.greens_neq(ctx.model(q.H_ini), ctx.model(q.H), s, v0, orbitals=q.orbitals, nt=nt, steps_per_grid=1,
+                         dt=q.dt, krylov_dim=q.krylov_dim, schedule=1, gs_tol=q.gs_tol, gs_max_iter=2000)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = ctx.profile_end()
+    Gl, Gg = out["G_lesser"][:, :, 0, 0], out["G_greater"][:, :, 0, 0]
+    vsteps = (nt - 1) + nt * (nt - 1)
+    hv = st.get("hv_lanczos", {"sampled_ms": 0, "sampled": 1, "sampled_bytes": 0})
+    res = {"metric": "four-step on the 2x8 ladder (L=16), short mesh", "D": s.dim, "nt": nt,
+           "elapsed_s": round(el, 2), "vector_steps": vsteps,
+           "anticommutator_err": float(np.abs(np.diag(Gg - Gl) + 1j).max()), "E0": out["E0"],
+           "hv_lanczos": {"avg_ms": round(hv["sampled_ms"] / max(hv["sampled"], 1), 3),
+                          "GBps": round(hv["sampled_bytes"] / max(hv["sampled_ms"], 1e-9) / 1e6, 1)},
+           "kernels": {k: {"launches": v["launches"], "total_ms": round(v["sampled_ms"], 1)}
+                       for k, v in sorted(st.items())}}
+    print(json.dumps(res), flush=True)
+
+
 def measured_traffic():
     """HBM bytes per algorithmic byte of the dominant kernel from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each
@@ -169,6 +297,12 @@ def main():
         return
     if a.hv:
         hv_bench(a)
+        return
+    if a.workload == "batch64":
+        batch64(a)
+        return
+    if a.workload == "ladder16":
+        ladder16(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "

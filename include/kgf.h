@@ -302,9 +302,14 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      every K-th state (smallest K whose checkpoints and one
  *                      recomputed segment take at most 30%); n >= 1 fixes K = n.
  *                      Recomputed states are bitwise equal to stored ones.
+ *   KGF_OPT_ADJ_EVERY: 0 = the adjoints (kgf_propagate_vjp, kgf_greens_neq_vjp)
+ *                      store the states of each propagation chain whole if they
+ *                      take at most 30% of free device memory, else keep every
+ *                      K-th state and recompute one segment at a time;
+ *                      n >= 1 fixes K = n (checkpoint every n SIL steps).
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
-enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4 };
+enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

@@ -71,3 +71,56 @@ def greens_neq(kctx: Context, L: int, bonds_ini, bonds, theta_ini: torch.Tensor,
               gs_max_iter=gs_max_iter)
     return _GreensNeq.apply(theta_ini, theta, kctx, L, bonds_ini, bonds, sector, v0, list(orbitals), nt,
                             steps_per_grid, dt, kw)
+
+
+class _GreensNeqBatch(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, meta, *thetas):
+        n = meta["n"]
+        kctx = meta["kctx"]
+        mi = [model_from_theta(kctx, meta["L"][i], meta["bonds_ini"][i], thetas[i].detach().cpu().numpy())
+              for i in range(n)]
+        mf = [model_from_theta(kctx, meta["L"][i], meta["bonds"][i], thetas[n + i].detach().cpu().numpy())
+              for i in range(n)]
+        kw = meta["kw"]
+        out = kctx.greens_neq_multi(mi, mf, meta["sectors"], meta["v0"], meta["orbitals"], meta["nt"], meta["spg"],
+                                    meta["dt"], krylov_dim=kw["krylov_dim"], reorth=kw["reorth"],
+                                    gs_tol=kw["gs_tol"], gs_max_iter=kw["gs_max_iter"])
+        fctx.meta = meta
+        fctx.save_for_backward(*thetas)
+        return torch.from_numpy(out["G_lesser"]), torch.from_numpy(out["G_greater"])
+
+    @staticmethod
+    def backward(fctx, gl, gg):
+        meta = fctx.meta
+        thetas = fctx.saved_tensors
+        n, kctx, kw = meta["n"], meta["kctx"], meta["kw"]
+        grads = [None] * (2 * n)
+        for i in range(n):
+            mi = model_from_theta(kctx, meta["L"][i], meta["bonds_ini"][i], thetas[i].detach().cpu().numpy())
+            mf = model_from_theta(kctx, meta["L"][i], meta["bonds"][i], thetas[n + i].detach().cpu().numpy())
+            Wl = None if gl is None else gl[i].detach().cpu().numpy()
+            Wg = None if gg is None else gg[i].detach().cpu().numpy()
+            r = kctx.greens_neq_vjp(mi, mf, meta["sectors"][i], meta["v0"][i], meta["orbitals"], meta["nt"],
+                                    meta["spg"], meta["dt"], Wl, Wg, krylov_dim=kw["krylov_dim"], reorth=kw["reorth"],
+                                    quad_nodes=kw["quad_nodes"], cg_tol=kw["cg_tol"], gs_tol=kw["gs_tol"],
+                                    gs_max_iter=kw["gs_max_iter"])
+            grads[i] = torch.from_numpy(r["grad_ini"]).to(thetas[i].dtype)
+            grads[n + i] = torch.from_numpy(r["grad"]).to(thetas[n + i].dtype)
+        return (None,) + tuple(grads)
+
+
+def greens_neq_batch(kctx: Context, L: Sequence[int], bonds_ini, bonds, theta_ini: Sequence[torch.Tensor],
+                     theta: Sequence[torch.Tensor], sectors: Sequence[Sector], v0, orbitals: Sequence[Tuple[int, int]],
+                     nt: int, steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0,
+                     quad_nodes: int = 12, cg_tol: float = 1e-12, gs_tol: float = 1e-12, gs_max_iter: int = 300):
+    """Differentiable four-step (G^<, G^>) of n instances, stacked as
+    [n][nt][nt][n_orb][n_orb].  The forward pass runs all instances through
+    kgf_greens_neq_multi (instances with one sector and bond list batched);
+    the backward pass runs kgf_greens_neq_vjp instance by instance."""
+    n = len(theta)
+    meta = dict(n=n, kctx=kctx, L=list(L), bonds_ini=list(bonds_ini), bonds=list(bonds), sectors=list(sectors),
+                v0=list(v0), orbitals=list(orbitals), nt=nt, spg=steps_per_grid, dt=dt,
+                kw=dict(krylov_dim=krylov_dim, reorth=reorth, quad_nodes=quad_nodes, cg_tol=cg_tol, gs_tol=gs_tol,
+                        gs_max_iter=gs_max_iter))
+    return _GreensNeqBatch.apply(meta, *theta_ini, *theta)

@@ -174,22 +174,65 @@ void sil_adjoint_step(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, con
 
 // Adjoint of a chain x_{n+1} = exp(delta i H dt) x_n, n < nsteps, from x_0.
 // lam: in the cotangent of x_nsteps, out the cotangent of x_0.
+// The states x_n are needed in reverse order.  They are stored whole when
+// they take at most 30% of free device memory (or ctx->adj_every == 0 is
+// not forced); otherwise every K-th state is kept and each segment of K
+// states is recomputed forward from its checkpoint just before its adjoint
+// steps (recomputed states are bitwise the stored ones).
 void chain_adjoint(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* x0, int nsteps, double dt,
                    int delta, const SilOpts& o, int nq, double2* lam, double* g) {
     if (nsteps <= 0) return;
     const int64_t D = sec->dim();
-    ensure_device_fits(sizeof(double2) * (size_t)nsteps * D, "adjoint chain states");
-    double2* S = static_cast<double2*>(workspace(ctx, "adj_chain", sizeof(double2) * (size_t)nsteps * D));
-    KGF_HIP(hipMemcpyAsync(S, x0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    const size_t vb = sizeof(double2) * (size_t)D;
     SilOpts so = o;
     so.dt = dt;
     so.direction = delta;
-    for (int n = 1; n < nsteps; ++n) {
-        KGF_HIP(hipMemcpyAsync(S + (size_t)n * D, S + (size_t)(n - 1) * D, sizeof(double2) * D,
-                               hipMemcpyDeviceToDevice, ctx->stream));
-        sil_propagate(ctx, model, sec, S + (size_t)n * D, 1, D, 1, so);
+    int K = ctx->adj_every;
+    if (K <= 0) {
+        size_t free_b = 0, total_b = 0;
+        KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+        K = nsteps;
+        if ((double)vb * nsteps > 0.30 * (double)free_b)
+            for (K = 1; K < nsteps; ++K)
+                if ((double)vb * ((nsteps + K - 1) / K + K) <= 0.30 * (double)free_b) break;
     }
-    for (int n = nsteps - 1; n >= 0; --n) sil_adjoint_step(ctx, model, sec, S + (size_t)n * D, lam, dt, delta, o, nq, g);
+    K = std::max(1, std::min(K, nsteps));
+    if (K >= nsteps) {
+        ensure_device_fits(vb * (size_t)nsteps, "adjoint chain states");
+        double2* S = static_cast<double2*>(workspace(ctx, "adj_chain", vb * (size_t)nsteps));
+        KGF_HIP(hipMemcpyAsync(S, x0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int n = 1; n < nsteps; ++n) {
+            KGF_HIP(hipMemcpyAsync(S + (size_t)n * D, S + (size_t)(n - 1) * D, vb, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+            sil_propagate(ctx, model, sec, S + (size_t)n * D, 1, D, 1, so);
+        }
+        for (int n = nsteps - 1; n >= 0; --n)
+            sil_adjoint_step(ctx, model, sec, S + (size_t)n * D, lam, dt, delta, o, nq, g);
+        return;
+    }
+    // checkpoints C[c] = x_{cK}, then segments of K states
+    const int ncp = (nsteps + K - 1) / K;
+    ensure_device_fits(vb * (size_t)(ncp + K), "adjoint chain checkpoints");
+    double2* Cp = static_cast<double2*>(workspace(ctx, "adj_chain", vb * (size_t)(ncp + K)));
+    double2* Sg = Cp + (size_t)ncp * D;
+    KGF_HIP(hipMemcpyAsync(Cp, x0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(Sg, x0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    for (int n = 1; n < nsteps; ++n) {
+        sil_propagate(ctx, model, sec, Sg, 1, D, 1, so);
+        if (n % K == 0)
+            KGF_HIP(hipMemcpyAsync(Cp + (size_t)(n / K) * D, Sg, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    for (int c = ncp - 1; c >= 0; --c) {
+        const int n0 = c * K, n1 = std::min(nsteps, n0 + K);
+        KGF_HIP(hipMemcpyAsync(Sg, Cp + (size_t)c * D, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int n = n0 + 1; n < n1; ++n) {
+            double2* x = Sg + (size_t)(n - n0) * D;
+            KGF_HIP(hipMemcpyAsync(x, x - D, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            sil_propagate(ctx, model, sec, x, 1, D, 1, so);
+        }
+        for (int n = n1 - 1; n >= n0; --n)
+            sil_adjoint_step(ctx, model, sec, Sg + (size_t)(n - n0) * D, lam, dt, delta, o, nq, g);
+    }
 }
 
 // (H - E0) mu = (1 - P0) r, mu orthogonal to psi0 (unit norm), by projected CG.

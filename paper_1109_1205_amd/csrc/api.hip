@@ -466,6 +466,9 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_PHI_EVERY) {
             KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: PHI_EVERY must be >= 0");
             ctx->phi_every = value;
+        } else if (option == KGF_OPT_ADJ_EVERY) {
+            KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: ADJ_EVERY must be >= 0");
+            ctx->adj_every = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

@@ -93,6 +93,7 @@ struct kgf_ctx {
     int hv_strip = 0;
     int gs_max_basis = 0;                    // 0: as many Lanczos vectors as fit
     int phi_every = 0;                       // 0: forward mesh stored whole when it fits
+    int adj_every = 0;                       // 0: adjoint chains stored whole when they fit
     // progress callback
     kgf_progress_fn progress = nullptr;
     void* progress_user = nullptr;

@@ -141,3 +141,87 @@ def test_greens_neq_vjp_against_finite_differences(ctx):
     fdi = _fd_four_step(H_ini, H, nu, nd, orbs, nt, dtg, spg, m, v0, Wl, Wg, "ini")
     say("grad H_ini max err", np.abs(got["grad_ini"] - fdi).max(), "scale", np.abs(fdi).max(), "cg", got["cg_iters"])
     assert np.abs(got["grad_ini"] - fdi).max() <= 1e-6 * np.abs(fdi).max()
+
+
+def test_checkpointed_chains_are_bitwise_equal(ctx):
+    """The adjoint with chain states kept as checkpoints (recomputed
+    segments) returns exactly the gradient of the stored-chain adjoint."""
+    say("adjoint checkpoints")
+    model = wl.chain_siam(6, 2.0).with_field(0, 0.3)
+    sec = basis.Sector(6, 3, 2)
+    psi0 = to_dev(wl.complex_vector(sec.dim, 3))
+    chi = wl.complex_vector(sec.dim, 4)
+    outs = []
+    for K in (0, 3, 1):
+        ctx.set_option(ctx.ADJ_EVERY, K)
+        try:
+            lam = to_dev(0.5 * chi)
+            g = ctx.propagate_vjp(ctx.model(model), ctx.sector(6, 3, 2), psi0, lam, 7, 0.1, 15, -1, reorth=2,
+                                  quad_nodes=10)
+            outs.append((g, to_host(lam)))
+        finally:
+            ctx.set_option(ctx.ADJ_EVERY, 0)
+    for g, lam in outs[1:]:
+        assert np.array_equal(g, outs[0][0]) and np.array_equal(lam, outs[0][1])
+    H = wl.chain_siam(5, 2.0)
+    Hi = H.with_field(0, 0.4)
+    sec5 = basis.Sector(5, 3, 2)
+    v0 = to_dev(wl.start_vector(sec5.dim, 7))
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((5, 5, 1, 1)) + 1j * rng.standard_normal((5, 5, 1, 1))
+    res = []
+    for K in (0, 2):
+        ctx.set_option(ctx.ADJ_EVERY, K)
+        try:
+            res.append(ctx.greens_neq_vjp(ctx.model(Hi), ctx.model(H), ctx.sector(5, 3, 2), v0, [(0, 0)], 5, 3, 0.05,
+                                          W, W.conj(), krylov_dim=14, quad_nodes=8))
+        finally:
+            ctx.set_option(ctx.ADJ_EVERY, 0)
+    assert np.array_equal(res[0]["grad"], res[1]["grad"])
+    assert np.array_equal(res[0]["grad_ini"], res[1]["grad_ini"])
+
+
+def test_ladder16_hopping_gradient_short_mesh(ctx):
+    """2x8 ladder quench (L = 16, D = 165,636,900), G^< and G^> of site 0 on a
+    3-point mesh, loss Re sum conj(W) G with a seeded complex Gaussian W
+    (seed 5); the 22 bond hoppings are shared by H_ini (U = 4) and H (U = 8),
+    so dL/dt_b = grad[b] + grad_ini[b].  Checked against central differences
+    of the GPU forward pass for two bonds (a leg and a rung), chains
+    checkpointed every step."""
+    import torch
+    q = wl.ladder16()
+    s = ctx.sector(16, 8, 8)
+    say("ladder16 gradient: start vector")
+    v0 = torch.from_numpy(wl.start_vector(s.dim, 7)).to("cuda:0")
+    nt = 3
+    rng = np.random.default_rng(5)
+    Wl = rng.standard_normal((nt, nt, 1, 1)) + 1j * rng.standard_normal((nt, nt, 1, 1))
+    Wg = rng.standard_normal((nt, nt, 1, 1)) + 1j * rng.standard_normal((nt, nt, 1, 1))
+    kw = dict(krylov_dim=20, gs_tol=1e-13, gs_max_iter=2000)
+    ctx.set_option(ctx.ADJ_EVERY, 1)
+    ctx.set_progress(lambda ph, d, t: say("  ", ph, d, t) if d == t else None)
+    try:
+        r = ctx.greens_neq_vjp(ctx.model(q.H_ini), ctx.model(q.H), s, v0, [(0, 0)], nt, 1, q.dt, Wl, Wg,
+                               quad_nodes=12, cg_tol=1e-12, **kw)
+    finally:
+        ctx.set_option(ctx.ADJ_EVERY, 0)
+        ctx.set_progress(None)
+    nb = len(q.H.bonds)
+    g_t = r["grad"][:nb] + r["grad_ini"][:nb]
+    say("grad norm", np.linalg.norm(g_t), "cg", r["cg_iters"])
+
+    def loss(b, h):
+        def bump(m):
+            t = list(m.t)
+            t[b] += h
+            return wl.Model(L=m.L, bonds=m.bonds, t=tuple(t), eps_up=m.eps_up, eps_dn=m.eps_dn, U=m.U, name=m.name)
+        o = ctx.greens_neq(ctx.model(bump(q.H_ini)), ctx.model(bump(q.H)), s, v0, orbitals=[(0, 0)], nt=nt,
+                           steps_per_grid=1, dt=q.dt, schedule=0, **kw)
+        return float((np.sum(np.conj(Wl) * o["G_lesser"]) + np.sum(np.conj(Wg) * o["G_greater"])).real)
+    legs = [b for b, (i, j) in enumerate(q.H.bonds) if j - i == 2]
+    rungs = [b for b, (i, j) in enumerate(q.H.bonds) if j - i == 1]
+    for b in (legs[0], rungs[0]):
+        h = 1e-4
+        fd = (loss(b, h) - loss(b, -h)) / (2 * h)
+        say("bond", q.H.bonds[b], "adjoint", g_t[b], "fd", fd)
+        assert abs(g_t[b] - fd) <= 1e-6 * max(1.0, np.abs(g_t).max())

@@ -82,3 +82,48 @@ def test_anderson_fit_gradient(env, seed):
     ref = np.concatenate([fd_eb, fd_Vb, [fd_U]])
     say("max err", np.abs(got - ref).max(), "scale", np.abs(ref).max())
     assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_batch_gradient_equals_single_instance_gradients(env):
+    """Three Anderson instances (two of L = 5, one of L = 6) through the
+    batched differentiable G: loss and theta-gradients equal the
+    single-instance autograd path (itself checked against differences)."""
+    import torch
+    k, ag, ctx = env
+    insts = []
+    for seed, L in ((4001, 5), (4002, 5), (4005, 6)):
+        rng = np.random.default_rng(seed)
+        eb, Vb = rng.uniform(-2.0, 2.0, L - 1), 0.3 + 0.1 * rng.standard_normal(L - 1)
+        insts.append((L, eb, Vb))
+    nt, spg, dtg, m = 4, 2, 0.2, 14
+    orbs = [(0, 0)]
+    Ls, bl, thi, thf, secs, v0s, tg = [], [], [], [], [], [], []
+    for L, eb, Vb in insts:
+        nu, nd = (L + 1) // 2, L // 2
+        bonds = [(0, j + 1) for j in range(L - 1)]
+        sec = ctx.sector(L, nu, nd)
+        Ls.append(L)
+        bl.append(bonds)
+        thi.append(star_theta(torch, torch.tensor(eb), torch.tensor(Vb), torch.zeros((), dtype=torch.float64),
+                              torch.tensor(-2.0, dtype=torch.float64), L).requires_grad_(True))
+        thf.append(star_theta(torch, torch.tensor(eb), torch.tensor(Vb), torch.tensor(4.0, dtype=torch.float64),
+                              torch.tensor(-2.0, dtype=torch.float64), L).requires_grad_(True))
+        secs.append(sec)
+        v0s.append(to_dev(wl.start_vector(sec.dim, 7)))
+        rng = np.random.default_rng(L)
+        tg.append(torch.from_numpy(rng.standard_normal((nt, nt, 1, 1)) + 1j * rng.standard_normal((nt, nt, 1, 1))))
+    say("batched autograd")
+    Gl, Gg = ag.greens_neq_batch(ctx, Ls, bl, bl, thi, thf, secs, v0s, orbs, nt, spg, dtg / spg, krylov_dim=m,
+                                 reorth=2, quad_nodes=10, cg_tol=1e-13, gs_tol=1e-13)
+    loss = sum(((Gl[i] - tg[i]).abs() ** 2).sum() + ((Gg[i] - tg[i]).abs() ** 2).sum() for i in range(3))
+    loss.backward()
+    for i in range(3):
+        a = thi[i].detach().clone().requires_grad_(True)
+        b = thf[i].detach().clone().requires_grad_(True)
+        gl, gg = ag.greens_neq(ctx, Ls[i], bl[i], bl[i], a, b, secs[i], v0s[i], orbs, nt, spg, dtg / spg,
+                               krylov_dim=m, reorth=2, quad_nodes=10, cg_tol=1e-13, gs_tol=1e-13)
+        li = ((gl - tg[i]).abs() ** 2).sum() + ((gg - tg[i]).abs() ** 2).sum()
+        li.backward()
+        scale = max(float(a.grad.abs().max()), float(b.grad.abs().max()))
+        assert float((thi[i].grad - a.grad).abs().max()) <= 1e-9 * scale
+        assert float((thf[i].grad - b.grad).abs().max()) <= 1e-9 * scale
