@@ -384,7 +384,7 @@ constexpr size_t kSplitLdsMax = 150 * 1024;      // one real component of a row
 constexpr int kRowsJSplit = 16;                  // row elements per thread, split rows (D_dn <= 16,384)
 
 // Pass 1.  One block per row u; threads own d = tid + j * 1024.
-template <bool SPLIT, bool UNIFORM_U>
+template <bool SPLIT, bool UNIFORM_U, int NR>
 __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double2* __restrict__ X, int64_t x_col,
                                                         double2* __restrict__ Y, int64_t y_col) {
     extern __shared__ double2 srow[];
@@ -410,12 +410,34 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
     };
     constexpr int kBatch = 8;
     if (!SPLIT) {
-        for (int64_t d = tid; d < Ddn; d += blockDim.x) srow[d] = xrow[d];
+        // NR consecutive rows per block share every hop-table load
+        const int64_t ub = (int64_t)blockIdx.x * NR;
+        const int nr = (int)min((int64_t)NR, T.Dup - ub);
+        const double2* __restrict__ xr = X + c * x_col + ub * Ddn;
+        double2* __restrict__ yr = Y + c * y_col + ub * Ddn;
+        for (int64_t i = tid; i < (int64_t)nr * Ddn; i += blockDim.x) srow[i] = xr[i];
+        uint32_t mur[NR];
+        double eur[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            mur[r] = r < nr ? T.mu[ub + r] : 0u;
+            eur[r] = r < nr ? T.eu[par_index(T, blockIdx.y) * T.Dup + ub + r] : 0.0;
+        }
         __syncthreads();
         for (int64_t d = tid; d < Ddn; d += blockDim.x) {
-            const double2 xv = srow[d];
-            const double dg = diag(d);
-            double ar = dg * xv.x, ai = dg * xv.y;
+            const uint32_t md = T.md[d];
+            const double edd = T.ed[par_index(T, blockIdx.y) * T.Ddn + d];
+            double ar[NR], ai[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const uint32_t both = mur[r] & md;
+                double dg = eur[r] + edd;
+                if (UNIFORM_U) dg += par_U0(T, par_index(T, blockIdx.y)) * (double)__popc(both);
+                else dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
+                const double2 xv = srow[(int64_t)r * Ddn + d];
+                ar[r] = dg * xv.x;
+                ai[r] = dg * xv.y;
+            }
             const int cd = T.cnt_dn[d];
             for (int k0 = 0; k0 < cd; k0 += kBatch) {
                 uint32_t e[kBatch];
@@ -426,12 +448,17 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
                     if (k0 + j < cd) {
                         double tv = s_negt[(e[j] >> 24) & 127u];
                         tv = (e[j] >> 31) ? -tv : tv;
-                        const double2 z = srow[e[j] & 0xFFFFFFu];
-                        ar = fma(tv, z.x, ar);
-                        ai = fma(tv, z.y, ai);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            const double2 z = srow[(int64_t)r * Ddn + (e[j] & 0xFFFFFFu)];
+                            ar[r] = fma(tv, z.x, ar[r]);
+                            ai[r] = fma(tv, z.y, ai[r]);
+                        }
                     }
             }
-            yrow[d] = make_double2(ar, ai);
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr) yr[(int64_t)r * Ddn + d] = make_double2(ar[r], ai[r]);
         }
         return;
     }
@@ -882,11 +909,16 @@ void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int 
         const size_t lds = P.split ? sizeof(double) * (size_t)sec->d_dn : sizeof(double2) * (size_t)sec->d_dn;
         dim3 rg((unsigned)sec->d_up, (unsigned)ncol);
         if (P.split) {
-            auto rows = uu ? k_hv_rows<true, true> : k_hv_rows<true, false>;
+            auto rows = uu ? k_hv_rows<true, true, 1> : k_hv_rows<true, false, 1>;
             opt_in_lds(ctx, (const void*)rows, 4 + (uu ? 1 : 0), kSplitLdsMax);
             hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
+        } else if (2 * lds <= kSplitLdsMax) {
+            auto rows = uu ? k_hv_rows<false, true, 2> : k_hv_rows<false, false, 2>;
+            opt_in_lds(ctx, (const void*)rows, 8 + (uu ? 1 : 0), kSplitLdsMax);
+            dim3 rg2((unsigned)((sec->d_up + 1) / 2), (unsigned)ncol);
+            hipLaunchKernelGGL(rows, rg2, dim3(kHvThreads), 2 * lds, ctx->stream, T, x, x_col, y, y_col);
         } else {
-            auto rows = uu ? k_hv_rows<false, true> : k_hv_rows<false, false>;
+            auto rows = uu ? k_hv_rows<false, true, 1> : k_hv_rows<false, false, 1>;
             opt_in_lds(ctx, (const void*)rows, 6 + (uu ? 1 : 0), kRowLdsMax);
             hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
         }
