@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--grad-instances", type=int, default=5,
                    help="batch64: instances (one per L first) whose adjoint gradient is timed")
     p.add_argument("--nt16", type=int, default=6, help="ladder16: mesh points")
+    p.add_argument("--plain-baseline", action="store_true",
+                   help="batch64: also time the plain single-vector method (schedule 0) instance by instance")
     p.add_argument("--hv", default="",
                    help="H.v micro-benchmark instead of the four-step run: comma-separated ladder sizes "
                         "(14, 16); each is timed for every --hv-passes variant")
@@ -169,6 +171,16 @@ def batch64(a):
             log(f"  {i + 1}/64")
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    tplain = None
+    if a.plain_baseline:
+        log("plain single-vector schedule, instance by instance:")
+        t0 = time.perf_counter()
+        for i in range(len(qs)):
+            ctx.greens_neq(Hi[i], Hf[i], secs[i], v0[i], schedule=0, **kw)
+            if (i + 1) % 8 == 0:
+                log(f"  {i + 1}/64")
+        torch.cuda.synchronize()
+        tplain = time.perf_counter() - t0
     # adjoint timings: the first instance of each L, then more
     order = sorted(range(len(qs)), key=lambda i: (qs[i].H.L, i))
     pick, seen = [], set()
@@ -206,6 +218,8 @@ def batch64(a):
                       "vector_steps": vsteps},
            "batched_s": round(tb, 2), "per_instance_s": round(tp, 2), "speedup": round(tp / tb, 3),
            "per_instance_value": round(vsteps / tp, 1), "max_rel_diff_batched_vs_per_instance": maxdiff,
+           "plain_single_vector_s": (round(tplain, 2) if tplain else None),
+           "speedup_vs_plain": (round(tplain / tb, 3) if tplain else None),
            "adjoint": grad_rows}
     print(json.dumps(res), flush=True)
 
