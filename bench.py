@@ -55,7 +55,11 @@ def parse():
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
                         "short mesh")
     p.add_argument("--grad-instances", type=int, default=5,
-                   help="batch64: instances (one per L first) whose adjoint gradient is timed")
+                   help="batch64: instances (one per L first) whose per-instance adjoint gradient is timed")
+    p.add_argument("--no-batched-adjoint", action="store_true",
+                   help="batch64: skip the batched adjoint of all 64 instances")
+    p.add_argument("--skip-per-instance", action="store_true",
+                   help="batch64: skip the per-instance forward timing")
     p.add_argument("--nt16", type=int, default=6, help="ladder16: mesh points")
     p.add_argument("--plain-baseline", action="store_true",
                    help="batch64: also time the plain single-vector method (schedule 0) instance by instance")
@@ -146,6 +150,14 @@ def batch64(a):
     import workloads as wl
     qs = wl.batch_instances()
     ctx = kgf.Context(0)
+    last = [time.perf_counter()]
+
+    def report(phase, done, total):
+        now = time.perf_counter()
+        if now - last[0] >= 20.0:
+            last[0] = now
+            log(f"  {phase} {done}/{total}")
+    ctx.set_progress(report)
     Hi = [ctx.model(q.H_ini) for q in qs]
     Hf = [ctx.model(q.H) for q in qs]
     secs = [ctx.sector(q.H.L, q.n_up, q.n_dn) for q in qs]
@@ -162,7 +174,7 @@ def batch64(a):
     log(f"batched {tb:.1f} s; per instance:")
     t0 = time.perf_counter()
     maxdiff = 0.0
-    for i in range(len(qs)):
+    for i in ([] if a.skip_per_instance else range(len(qs))):
         o = ctx.greens_neq(Hi[i], Hf[i], secs[i], v0[i], schedule=1, **kw)
         sc = max(np.abs(o["G_lesser"]).max(), np.abs(o["G_greater"]).max())
         maxdiff = max(maxdiff, np.abs(o["G_lesser"] - outb["G_lesser"][i]).max() / sc,
@@ -170,7 +182,7 @@ def batch64(a):
         if (i + 1) % 8 == 0:
             log(f"  {i + 1}/64")
     torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
+    tp = None if a.skip_per_instance else time.perf_counter() - t0
     tplain = None
     if a.plain_baseline:
         log("plain single-vector schedule, instance by instance:")
@@ -210,17 +222,46 @@ def batch64(a):
                           "adjoint_s": round(ta, 2), "adjoint_over_forward": round(ta / tf, 2),
                           "grad_norm": float(np.linalg.norm(r["grad"])), "cg_iters": r["cg_iters"]})
         log(f"adjoint {q.name}: forward {tf:.1f} s, adjoint {ta:.1f} s")
+    # batched adjoint of all instances (same loss, targets at U = 3)
+    bat_adj = None
+    if not a.no_batched_adjoint:
+        log("targets for the batched adjoint (U = 3)")
+        tg = ctx.greens_neq_multi(Hi, [ctx.model(q.H.with_U([3.0] + [0.0] * (q.H.L - 1))) for q in qs], secs, v0,
+                                  **kw)
+        Wl = [2.0 * (outb["G_lesser"][i] - tg["G_lesser"][i]) for i in range(len(qs))]
+        Wg = [2.0 * (outb["G_greater"][i] - tg["G_greater"][i]) for i in range(len(qs))]
+        log("batched adjoint of 64 instances")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = ctx.greens_neq_vjp_multi(Hi, Hf, secs, v0, q0.orbitals, q0.nt, q0.steps_per_grid, q0.dt, Wl, Wg,
+                                      krylov_dim=q0.krylov_dim, quad_nodes=12)
+        torch.cuda.synchronize()
+        tba = time.perf_counter() - t0
+        # per-instance adjoint time estimated from the sampled instances, per L
+        per_L = {}
+        for r in grad_rows:
+            per_L[int(r["instance"].split("_L")[1])] = r["adjoint_s"]
+        Ls = [q.H.L for q in qs]
+        est = sum(per_L[L] * Ls.count(L) for L in per_L) if len(per_L) == len(set(Ls)) else None
+        bat_adj = {"batched_adjoint_s": round(tba, 2),
+                   "per_instance_adjoint_s_estimated": (round(est, 1) if est else None),
+                   "speedup_estimated": (round(est / tba, 2) if est else None),
+                   "batched_adjoint_over_batched_forward": round(tba / tb, 2),
+                   "grad_norm_sum": float(sum(np.linalg.norm(r["grad"]) for r in rs))}
+        log(f"batched adjoint {tba:.1f} s")
     res = {"metric": "G(t,t') contour steps/s, 64 uneven Anderson instances (batched vs per instance)",
            "value": round(vsteps / tb, 1), "unit": "vector-steps/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "batch64: 64 Anderson stars, L 8..12 (seeds 4000+i), U 0->4, eps_imp -2, "
                                   "G_imp 50x50, t_k=0.2k, dt=0.05, Krylov dim 15",
                       "vector_steps": vsteps},
-           "batched_s": round(tb, 2), "per_instance_s": round(tp, 2), "speedup": round(tp / tb, 3),
-           "per_instance_value": round(vsteps / tp, 1), "max_rel_diff_batched_vs_per_instance": maxdiff,
+           "batched_s": round(tb, 2), "per_instance_s": (round(tp, 2) if tp else None),
+           "speedup": (round(tp / tb, 3) if tp else None),
+           "per_instance_value": (round(vsteps / tp, 1) if tp else None),
+           "max_rel_diff_batched_vs_per_instance": (maxdiff if tp else None),
            "plain_single_vector_s": (round(tplain, 2) if tplain else None),
            "speedup_vs_plain": (round(tplain / tb, 3) if tplain else None),
-           "adjoint": grad_rows}
+           "adjoint": grad_rows, "batched_adjoint": bat_adj}
     print(json.dumps(res), flush=True)
 
 

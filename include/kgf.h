@@ -272,6 +272,27 @@ int  kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H
                         double* host_grad_ini, double* host_grad, kgf_c128* host_G_lesser,
                         kgf_c128* host_G_greater, double* host_E0, int* host_cg_iters);
 
+/* Gradients of kgf_greens_neq_vjp for n_inst instances in one call.
+ * Instances whose sectors have equal (L, N_up, N_dn) and whose H have the
+ * same bond list form a group whose propagations, chain adjoints and adjoint
+ * steps run as one batch (column c carries member c mod n); ground states,
+ * Gram matrices and the ground-state solves are per instance.  Results equal
+ * kgf_greens_neq_vjp on each instance up to rounding.  Per-instance arrays:
+ * H_ini[i], H[i], sectors[i], v0[i] (device), host_W_lesser[i] /
+ * host_W_greater[i] (host [nt][nt][n_orb][n_orb]; the arrays of pointers may
+ * be NULL, entries NULL = zero cotangent), host_grad_ini[i] (n_theta(H_ini[i])
+ * doubles), host_grad[i] (n_theta(H[i]) doubles; NULL entries skip);
+ * host_E0 [n_inst]; host_cg_iters [n_inst] or NULL.  Memory: the plain-
+ * schedule meshes of kgf_greens_neq_vjp times the group size. */
+int  kgf_greens_neq_vjp_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H_ini,
+                              const kgf_model* const* H, const kgf_sector* const* sectors,
+                              const kgf_gs_opts* gs_opts, const kgf_c128* const* v0,
+                              const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
+                              const kgf_prop_opts* opts, const kgf_c128* const* host_W_lesser,
+                              const kgf_c128* const* host_W_greater, int quad_nodes, double cg_tol,
+                              double* const* host_grad_ini, double* const* host_grad,
+                              double* host_E0, int* host_cg_iters);
+
 /* ---- progress reporting ------------------------------------------------------
  * The drivers (kgf_ground_state, kgf_greens_eq, kgf_greens_neq) call
  * fn(user, phase, done, total) on the calling host thread after each mesh

@@ -101,6 +101,8 @@ def load_library():
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
         "kgf_set_option": (I, [P, I, I]),
+        "kgf_greens_neq_vjp_multi": (I, [P, I, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), P, P,
+                                         I, D, P, P, P, P]),
         "kgf_greens_neq_multi": (I, [P, I, P, P, P, P, C.POINTER(_GsOpts), P, I, I, I, C.POINTER(_PropOpts), I, P, P,
                                      P]),
         "kgf_n_theta": (I, [P]),
@@ -125,7 +127,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
-            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_profile_begin",
+            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_profile_begin",
             "kgf_profile_end"]
 
 
@@ -478,6 +480,45 @@ class Context:
                                        _np_ptr(Gl), _np_ptr(Gg), C.byref(E0), C.byref(cgi)))
         return {"grad_ini": gi, "grad": g, "G_lesser": Gl, "G_greater": Gg, "E0": E0.value,
                 "cg_iters": cgi.value}
+
+    def greens_neq_vjp_multi(self, H_ini: Sequence[Model], H: Sequence[Model], secs: Sequence[Sector], v0s, orbitals,
+                             nt: int, steps_per_grid: int, dt: float, W_lesser=None, W_greater=None,
+                             krylov_dim: int = 15, reorth: int = 0, quad_nodes: int = 12, cg_tol: float = 1e-12,
+                             gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1,
+                             gs_reorth: int = 2, breakdown_tol: float = 1e-13):
+        """kgf_greens_neq_vjp_multi: gradients of n instances (same-sector,
+        same-topology instances batched).  W_lesser / W_greater: sequences of
+        [nt][nt][n_orb][n_orb] arrays (or None).  Returns a list of dicts."""
+        n = len(H)
+        for v, s_ in zip(v0s, secs):
+            self._chk(v, s_.dim, "v0")
+        orbs = np.ascontiguousarray([2 * s_ + sp for s_, sp in orbitals], dtype=np.int32)
+        no = len(orbs)
+        shape = (nt, nt, no, no)
+
+        def arrs(W):
+            if W is None:
+                return None, []
+            keep = [None if w is None else np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(shape))
+                    for w in W]
+            return (C.c_void_p * n)(*[(0 if w is None else w.ctypes.data) for w in keep]), keep
+        Wl, keep_l = arrs(W_lesser)
+        Wg, keep_g = arrs(W_greater)
+        gi = [np.zeros(self.n_theta(m), dtype=np.float64) for m in H_ini]
+        g = [np.zeros(self.n_theta(m), dtype=np.float64) for m in H]
+        E0 = np.zeros(n)
+        cgi = np.zeros(n, dtype=np.int32)
+
+        def hv(xs):
+            return (C.c_void_p * n)(*[(x.value if isinstance(x, C.c_void_p) else int(x)) for x in xs])
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        gso = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        _check(_lib.kgf_greens_neq_vjp_multi(self.handle, n, hv(m.handle for m in H_ini), hv(m.handle for m in H),
+                                             hv(s_.handle for s_ in secs), C.byref(gso), hv(_ptr(v) for v in v0s),
+                                             _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), Wl, Wg,
+                                             int(quad_nodes), float(cg_tol), hv(a.ctypes.data for a in gi),
+                                             hv(a.ctypes.data for a in g), _np_ptr(E0), _np_ptr(cgi)))
+        return [{"grad_ini": gi[i], "grad": g[i], "E0": float(E0[i]), "cg_iters": int(cgi[i])} for i in range(n)]
 
     def profile_begin(self, sample_every: int = 1):
         _check(_lib.kgf_profile_begin(self.handle, int(sample_every)))

@@ -95,18 +95,18 @@ class _GreensNeqBatch(torch.autograd.Function):
         meta = fctx.meta
         thetas = fctx.saved_tensors
         n, kctx, kw = meta["n"], meta["kctx"], meta["kw"]
-        grads = [None] * (2 * n)
-        for i in range(n):
-            mi = model_from_theta(kctx, meta["L"][i], meta["bonds_ini"][i], thetas[i].detach().cpu().numpy())
-            mf = model_from_theta(kctx, meta["L"][i], meta["bonds"][i], thetas[n + i].detach().cpu().numpy())
-            Wl = None if gl is None else gl[i].detach().cpu().numpy()
-            Wg = None if gg is None else gg[i].detach().cpu().numpy()
-            r = kctx.greens_neq_vjp(mi, mf, meta["sectors"][i], meta["v0"][i], meta["orbitals"], meta["nt"],
-                                    meta["spg"], meta["dt"], Wl, Wg, krylov_dim=kw["krylov_dim"], reorth=kw["reorth"],
-                                    quad_nodes=kw["quad_nodes"], cg_tol=kw["cg_tol"], gs_tol=kw["gs_tol"],
-                                    gs_max_iter=kw["gs_max_iter"])
-            grads[i] = torch.from_numpy(r["grad_ini"]).to(thetas[i].dtype)
-            grads[n + i] = torch.from_numpy(r["grad"]).to(thetas[n + i].dtype)
+        mi = [model_from_theta(kctx, meta["L"][i], meta["bonds_ini"][i], thetas[i].detach().cpu().numpy())
+              for i in range(n)]
+        mf = [model_from_theta(kctx, meta["L"][i], meta["bonds"][i], thetas[n + i].detach().cpu().numpy())
+              for i in range(n)]
+        Wl = None if gl is None else [gl[i].detach().cpu().numpy() for i in range(n)]
+        Wg = None if gg is None else [gg[i].detach().cpu().numpy() for i in range(n)]
+        rs = kctx.greens_neq_vjp_multi(mi, mf, meta["sectors"], meta["v0"], meta["orbitals"], meta["nt"], meta["spg"],
+                                       meta["dt"], Wl, Wg, krylov_dim=kw["krylov_dim"], reorth=kw["reorth"],
+                                       quad_nodes=kw["quad_nodes"], cg_tol=kw["cg_tol"], gs_tol=kw["gs_tol"],
+                                       gs_max_iter=kw["gs_max_iter"])
+        grads = [torch.from_numpy(rs[i]["grad_ini"]).to(thetas[i].dtype) for i in range(n)]
+        grads += [torch.from_numpy(rs[i]["grad"]).to(thetas[n + i].dtype) for i in range(n)]
         return (None,) + tuple(grads)
 
 
@@ -115,9 +115,9 @@ def greens_neq_batch(kctx: Context, L: Sequence[int], bonds_ini, bonds, theta_in
                      nt: int, steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0,
                      quad_nodes: int = 12, cg_tol: float = 1e-12, gs_tol: float = 1e-12, gs_max_iter: int = 300):
     """Differentiable four-step (G^<, G^>) of n instances, stacked as
-    [n][nt][nt][n_orb][n_orb].  The forward pass runs all instances through
-    kgf_greens_neq_multi (instances with one sector and bond list batched);
-    the backward pass runs kgf_greens_neq_vjp instance by instance."""
+    [n][nt][nt][n_orb][n_orb].  Forward through kgf_greens_neq_multi and
+    backward through kgf_greens_neq_vjp_multi: instances with one sector and
+    bond list run as one batch in both."""
     n = len(theta)
     meta = dict(n=n, kctx=kctx, L=list(L), bonds_ini=list(bonds_ini), bonds=list(bonds), sectors=list(sectors),
                 v0=list(v0), orbitals=list(orbitals), nt=nt, spg=steps_per_grid, dt=dt,

@@ -137,56 +137,80 @@ std::unique_ptr<kgf_sector> adj_sector(kgf_ctx* ctx, int L, int nu, int nd) {
 
 }  // namespace
 
-// One adjoint step of psi_{n+1} = exp(delta i H dt) psi_n (see the file header).
-// lam: on entry psi_bar_{n+1}, on return psi_bar_n.  g (device) accumulates.
-void sil_adjoint_step(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi_n, double2* lam,
-                      double dt, int delta, const SilOpts& o, int nq, double* g) {
+// One adjoint step of psi_{n+1} = exp(delta i H dt) psi_n (see the file header)
+// for nm members at once (member c uses the Hamiltonian of launch column c mod
+// nm: a single model, or a ModelSet).  psi: members at stride psi_ld; lam: on
+// entry psi_bar_{n+1}, on return psi_bar_n (stride lam_ld); g (device) gets
+// member j's gradient at g + j * gstride.
+void sil_adjoint_step(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int nm, const double2* psi, int64_t psi_ld,
+                      double2* lam, int64_t lam_ld, double dt, int delta, const SilOpts& o, int nq, double* g,
+                      int gstride) {
     const int64_t D = sec->dim();
     const int m = o.m;
-    double2* pair = static_cast<double2*>(workspace(ctx, "adj_pair", sizeof(double2) * 2 * D));
-    KGF_HIP(hipMemcpyAsync(pair, psi_n, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
-    KGF_HIP(hipMemcpyAsync(pair + D, lam, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
-    sil_build(ctx, model, sec, pair, 2, D, o);
+    const size_t vb = sizeof(double2) * (size_t)D;
+    double2* pair = static_cast<double2*>(workspace(ctx, "adj_pair", vb * 2 * nm));   // [psi_j][lam_j]
+    for (int j = 0; j < nm; ++j) {
+        KGF_HIP(hipMemcpyAsync(pair + (size_t)j * D, psi + j * psi_ld, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(pair + (size_t)(nm + j) * D, lam + j * lam_ld, vb, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    }
+    sil_build(ctx, model, sec, pair, 2 * nm, D, o);
     std::vector<double> xq, wq;
     gauss_legendre(nq, xq, wq);
-    const int nreq = 2 * nq + 1;
+    const int per = 2 * nq + 1;
+    const int nreq = per * nm;
     std::vector<int> col(nreq), dir(nreq);
     std::vector<double> tt(nreq);
-    for (int q = 0; q < nq; ++q) {
-        const double s = 0.5 * dt * (1.0 + xq[q]);
-        col[q] = 0, dir[q] = delta, tt[q] = s;                       // psi(s)
-        col[nq + q] = 1, dir[nq + q] = -delta, tt[nq + q] = dt - s;  // lam(s)
+    for (int j = 0; j < nm; ++j) {
+        const int r0 = j * per;
+        for (int q = 0; q < nq; ++q) {
+            const double s = 0.5 * dt * (1.0 + xq[q]);
+            col[r0 + q] = j, dir[r0 + q] = delta, tt[r0 + q] = s;                        // psi(s)
+            col[r0 + nq + q] = nm + j, dir[r0 + nq + q] = -delta, tt[r0 + nq + q] = dt - s;  // lam(s)
+        }
+        col[r0 + 2 * nq] = nm + j, dir[r0 + 2 * nq] = -delta, tt[r0 + 2 * nq] = dt;     // new cotangent
     }
-    col[2 * nq] = 1, dir[2 * nq] = -delta, tt[2 * nq] = dt;          // new cotangent
     double2* coef = static_cast<double2*>(workspace(ctx, "adj_coef", sizeof(double2) * nreq * m));
     sil_coefs(ctx, m, nreq, col.data(), tt.data(), dir.data(), 0.0, coef, m);
-    double2* nodes = static_cast<double2*>(workspace(ctx, "adj_nodes", sizeof(double2) * 2 * nq * D));
-    sil_combine_multi(ctx, sec, pair, D, 2, m, 0, coef, m, nq, nodes, D);
-    sil_combine_multi(ctx, sec, pair, D, 2, m, 1, coef + (size_t)nq * m, m, nq, nodes + (size_t)nq * D, D);
-    sil_combine_multi(ctx, sec, pair, D, 2, m, 1, coef + (size_t)2 * nq * m, m, 1, lam, D);
+    double2* nodes = static_cast<double2*>(workspace(ctx, "adj_nodes", vb * 2 * nq * nm));
     std::vector<double2> om(nq);
     for (int q = 0; q < nq; ++q) {
         // 2 Re[delta i (dt/2) w_q <lam|dH|psi>]  ->  weight delta i dt w_q
         om[q] = make_double2(0.0, delta * dt * wq[q]);
     }
-    dH_expect(ctx, model, sec, nodes + (size_t)nq * D, D, nodes, D, nq, om.data(), g);
+    for (int j = 0; j < nm; ++j) {
+        const double2* cj = coef + (size_t)j * per * m;
+        double2* nj = nodes + (size_t)j * 2 * nq * D;
+        sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, j, cj, m, nq, nj, D);
+        sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, nm + j, cj + (size_t)nq * m, m, nq, nj + (size_t)nq * D, D);
+        sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, nm + j, cj + (size_t)2 * nq * m, m, 1, lam + j * lam_ld, D);
+        // dH/dtheta depends on the bond topology only, shared by all members
+        dH_expect(ctx, model.m, sec, nj + (size_t)nq * D, D, nj, D, nq, om.data(), g + (size_t)j * gstride);
+    }
 }
 
-// Adjoint of a chain x_{n+1} = exp(delta i H dt) x_n, n < nsteps, from x_0.
-// lam: in the cotangent of x_nsteps, out the cotangent of x_0.
-// The states x_n are needed in reverse order.  They are stored whole when
-// they take at most 30% of free device memory (or ctx->adj_every == 0 is
-// not forced); otherwise every K-th state is kept and each segment of K
-// states is recomputed forward from its checkpoint just before its adjoint
-// steps (recomputed states are bitwise the stored ones).
-void chain_adjoint(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* x0, int nsteps, double dt,
-                   int delta, const SilOpts& o, int nq, double2* lam, double* g) {
+// Adjoint of nm chains x_{n+1} = exp(delta i H dt) x_n, n < nsteps, from x_0
+// (members at stride x_ld).  lam: in the cotangents of x_nsteps, out those of
+// x_0 (stride lam_ld).  The states x_n are needed in reverse order.  They are
+// stored whole when they take at most 30% of free device memory (unless
+// ctx->adj_every forces checkpoints); otherwise every K-th state is kept and
+// each segment of K states is recomputed forward from its checkpoint just
+// before its adjoint steps (recomputed states are bitwise the stored ones).
+void chain_adjoint(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int nm, const double2* x0, int64_t x_ld,
+                   int nsteps, double dt, int delta, const SilOpts& o, int nq, double2* lam, int64_t lam_ld, double* g,
+                   int gstride) {
     if (nsteps <= 0) return;
     const int64_t D = sec->dim();
-    const size_t vb = sizeof(double2) * (size_t)D;
+    const size_t vb = sizeof(double2) * (size_t)D * nm;   // one state of all members
+    const int64_t sd = D * nm;
     SilOpts so = o;
     so.dt = dt;
     so.direction = delta;
+    auto load = [&](double2* dst) {
+        for (int j = 0; j < nm; ++j)
+            KGF_HIP(hipMemcpyAsync(dst + (size_t)j * D, x0 + j * x_ld, sizeof(double2) * D, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+    };
     int K = ctx->adj_every;
     if (K <= 0) {
         size_t free_b = 0, total_b = 0;
@@ -200,38 +224,39 @@ void chain_adjoint(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const 
     if (K >= nsteps) {
         ensure_device_fits(vb * (size_t)nsteps, "adjoint chain states");
         double2* S = static_cast<double2*>(workspace(ctx, "adj_chain", vb * (size_t)nsteps));
-        KGF_HIP(hipMemcpyAsync(S, x0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        load(S);
         for (int n = 1; n < nsteps; ++n) {
-            KGF_HIP(hipMemcpyAsync(S + (size_t)n * D, S + (size_t)(n - 1) * D, vb, hipMemcpyDeviceToDevice,
+            KGF_HIP(hipMemcpyAsync(S + (size_t)n * sd, S + (size_t)(n - 1) * sd, vb, hipMemcpyDeviceToDevice,
                                    ctx->stream));
-            sil_propagate(ctx, model, sec, S + (size_t)n * D, 1, D, 1, so);
+            sil_propagate(ctx, model, sec, S + (size_t)n * sd, nm, D, 1, so);
         }
         for (int n = nsteps - 1; n >= 0; --n)
-            sil_adjoint_step(ctx, model, sec, S + (size_t)n * D, lam, dt, delta, o, nq, g);
+            sil_adjoint_step(ctx, model, sec, nm, S + (size_t)n * sd, D, lam, lam_ld, dt, delta, o, nq, g, gstride);
         return;
     }
     // checkpoints C[c] = x_{cK}, then segments of K states
     const int ncp = (nsteps + K - 1) / K;
     ensure_device_fits(vb * (size_t)(ncp + K), "adjoint chain checkpoints");
     double2* Cp = static_cast<double2*>(workspace(ctx, "adj_chain", vb * (size_t)(ncp + K)));
-    double2* Sg = Cp + (size_t)ncp * D;
-    KGF_HIP(hipMemcpyAsync(Cp, x0, vb, hipMemcpyDeviceToDevice, ctx->stream));
-    KGF_HIP(hipMemcpyAsync(Sg, x0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    double2* Sg = Cp + (size_t)ncp * sd;
+    load(Cp);
+    load(Sg);
     for (int n = 1; n < nsteps; ++n) {
-        sil_propagate(ctx, model, sec, Sg, 1, D, 1, so);
+        sil_propagate(ctx, model, sec, Sg, nm, D, 1, so);
         if (n % K == 0)
-            KGF_HIP(hipMemcpyAsync(Cp + (size_t)(n / K) * D, Sg, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            KGF_HIP(hipMemcpyAsync(Cp + (size_t)(n / K) * sd, Sg, vb, hipMemcpyDeviceToDevice, ctx->stream));
     }
     for (int c = ncp - 1; c >= 0; --c) {
         const int n0 = c * K, n1 = std::min(nsteps, n0 + K);
-        KGF_HIP(hipMemcpyAsync(Sg, Cp + (size_t)c * D, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(Sg, Cp + (size_t)c * sd, vb, hipMemcpyDeviceToDevice, ctx->stream));
         for (int n = n0 + 1; n < n1; ++n) {
-            double2* x = Sg + (size_t)(n - n0) * D;
-            KGF_HIP(hipMemcpyAsync(x, x - D, vb, hipMemcpyDeviceToDevice, ctx->stream));
-            sil_propagate(ctx, model, sec, x, 1, D, 1, so);
+            double2* x = Sg + (size_t)(n - n0) * sd;
+            KGF_HIP(hipMemcpyAsync(x, x - sd, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            sil_propagate(ctx, model, sec, x, nm, D, 1, so);
         }
         for (int n = n1 - 1; n >= n0; --n)
-            sil_adjoint_step(ctx, model, sec, Sg + (size_t)(n - n0) * D, lam, dt, delta, o, nq, g);
+            sil_adjoint_step(ctx, model, sec, nm, Sg + (size_t)(n - n0) * sd, D, lam, lam_ld, dt, delta, o, nq, g,
+                             gstride);
     }
 }
 
@@ -272,9 +297,23 @@ static int projected_cg(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, c
     return it;
 }
 
+// One instance of a four-step adjoint: its Hamiltonians, start vector,
+// cotangents (host, [nt][nt][n_orb][n_orb] or null) and host outputs.
+struct VjpMember {
+    kgf_model* Hi = nullptr;
+    kgf_model* Hf = nullptr;
+    const double2* v0 = nullptr;
+    const double2* Wl = nullptr;
+    const double2* Wg = nullptr;
+    double* grad_ini = nullptr;
+    double* grad = nullptr;
+    double2* Gl = nullptr;
+    double2* Gg = nullptr;
+    double* E0 = nullptr;
+    int* cg_iters = nullptr;
+};
+
 struct VjpArgs {
-    kgf_model* H_ini;
-    kgf_model* H;
     const kgf_sector* sec;
     const int32_t* orbs;
     int norb, nt, spg;
@@ -284,39 +323,55 @@ struct VjpArgs {
     int cg_maxit;
 };
 
-static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const double2* v0, const kgf_gs_opts* gso,
-                          const double2* Wl, const double2* Wg, double* grad_ini_host, double* grad_host,
-                          double2* Gl_host, double2* Gg_host, double* E0_out, int* cg_iters) {
+// Gradient of the four-step G (plain schedule) for nm members with one sector
+// and one bond topology of H.  Every propagation, chain adjoint and adjoint
+// step runs all members as one batch (column c: member c mod nm); ground
+// states, Gram matrices, cotangent combinations and the ground-state solves
+// are per member.  Mesh states are stored member-fastest: [state][member][D].
+static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const kgf_gs_opts* gso, std::vector<VjpMember>& M) {
     const kgf_sector* sec = A.sec;
+    const int nm = (int)M.size();
     const int64_t D = sec->dim();
     const int nt = A.nt, norb = A.norb, L = sec->L;
     const double dt = A.o.dt;
-    // (i) ground state
-    double2* psi0 = static_cast<double2*>(workspace(ctx, "vjp_psi0", sizeof(double2) * D));
-    GsResult gs = ground_state(ctx, A.H_ini, sec, v0, psi0, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
+    const size_t vb = sizeof(double2) * (size_t)D;
+    ModelSet Sf;
+    for (auto& mb : M) Sf.models.push_back(mb.Hf);
+    if (nm > 1) model_set_init(ctx, Sf);
+    const HModel HF = nm > 1 ? HModel(&Sf) : HModel(M[0].Hf);
+    // (i) ground states
+    double2* psi0 = static_cast<double2*>(workspace(ctx, "vjp_psi0", vb * nm));
+    std::vector<double> E0(nm);
+    for (int j = 0; j < nm; ++j) {
+        GsResult gs = ground_state(ctx, M[j].Hi, sec, M[j].v0, psi0 + (size_t)j * D, gso->tol, gso->max_iter,
+                                   gso->check_every, gso->reorth);
+        KGF_REQUIRE(gs.converged, KGF_ENOCONV, "adjoint: ground state of H_ini did not converge");
+        E0[j] = gs.E0;
+        if (M[j].E0) *M[j].E0 = gs.E0;
+    }
     ctx->ws.erase("gs_V");
-    KGF_REQUIRE(gs.converged, KGF_ENOCONV, "adjoint: ground state of H_ini did not converge");
-    const double E0 = gs.E0;
-    *E0_out = E0;
-    // (ii) forward mesh
-    ensure_device_fits(sizeof(double2) * (size_t)2 * nt * D, "adjoint forward mesh");
-    double2* Phi = static_cast<double2*>(workspace(ctx, "vjp_phi", sizeof(double2) * (size_t)nt * D));
-    double2* Phib = static_cast<double2*>(workspace(ctx, "vjp_phibar", sizeof(double2) * (size_t)nt * D));
-    KGF_HIP(hipMemsetAsync(Phib, 0, sizeof(double2) * (size_t)nt * D, ctx->stream));
-    KGF_HIP(hipMemcpyAsync(Phi, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    // (ii) forward mesh Phi[k][member]
+    const int64_t sd = D * nm;
+    ensure_device_fits(vb * nm * (size_t)2 * nt, "adjoint forward mesh");
+    double2* Phi = static_cast<double2*>(workspace(ctx, "vjp_phi", vb * nm * (size_t)nt));
+    double2* Phib = static_cast<double2*>(workspace(ctx, "vjp_phibar", vb * nm * (size_t)nt));
+    KGF_HIP(hipMemsetAsync(Phib, 0, vb * nm * (size_t)nt, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(Phi, psi0, vb * nm, hipMemcpyDeviceToDevice, ctx->stream));
     SilOpts fo = A.o;
     fo.direction = -1;
     for (int k = 1; k < nt; ++k) {
-        KGF_HIP(hipMemcpyAsync(Phi + (size_t)k * D, Phi + (size_t)(k - 1) * D, sizeof(double2) * D,
-                               hipMemcpyDeviceToDevice, ctx->stream));
-        sil_propagate(ctx, A.H, sec, Phi + (size_t)k * D, 1, D, A.spg, fo);
+        KGF_HIP(hipMemcpyAsync(Phi + (size_t)k * sd, Phi + (size_t)(k - 1) * sd, vb * nm, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+        sil_propagate(ctx, HF, sec, Phi + (size_t)k * sd, nm, D, A.spg, fo);
     }
-    const int nth = n_theta(A.H), nthi = n_theta(A.H_ini);
-    double* g = static_cast<double*>(workspace(ctx, "vjp_g", sizeof(double) * (nth + nthi)));
-    double* gi = g + nth;
-    KGF_HIP(hipMemsetAsync(g, 0, sizeof(double) * (nth + nthi), ctx->stream));
+    const int nth = n_theta(M[0].Hf);
+    int nthi = 0;
+    for (auto& mb : M) nthi = std::max(nthi, n_theta(mb.Hi));
+    double* g = static_cast<double*>(workspace(ctx, "vjp_g", sizeof(double) * (size_t)nm * (nth + nthi)));
+    double* gi = g + (size_t)nm * nth;
+    KGF_HIP(hipMemsetAsync(g, 0, sizeof(double) * (size_t)nm * (nth + nthi), ctx->stream));
     const size_t gsz = (size_t)nt * nt * norb * norb;
-    std::vector<double2> Gl(gsz, make_double2(0, 0)), Gg(gsz, make_double2(0, 0));
+    std::vector<double2> Gl(gsz * nm, make_double2(0, 0)), Gg(gsz * nm, make_double2(0, 0));
     auto Widx = [&](int j, int k, int a, int b) { return (((size_t)j * nt + k) * norb + a) * norb + b; };
     SilOpts bo = A.o;
     bo.direction = +1;
@@ -328,100 +383,119 @@ static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const double2* v0, con
         const int na = (int)loc.size();
         if (!na) continue;
         for (int dagger = 0; dagger < 2; ++dagger) {
-            const double2* W = dagger ? Wg : Wl;
             auto tgt = adj_sector(ctx, L, sec->n_up + (spin == 0 ? (dagger ? 1 : -1) : 0),
                                   sec->n_dn + (spin == 1 ? (dagger ? 1 : -1) : 0));
             if (!tgt || tgt->dim() == 0) continue;
             const int64_t Dt = tgt->dim();
+            const int64_t tsd = Dt * nm;
             const int N = na * nt;
-            ensure_device_fits(sizeof(double2) * (size_t)2 * N * Dt, "adjoint state mesh");
-            double2* Psi = static_cast<double2*>(workspace(ctx, "vjp_psi", sizeof(double2) * (size_t)N * Dt));
-            double2* Psib = static_cast<double2*>(workspace(ctx, "vjp_psibar", sizeof(double2) * (size_t)N * Dt));
+            ensure_device_fits(sizeof(double2) * (size_t)2 * N * tsd, "adjoint state mesh");
+            double2* Psi = static_cast<double2*>(workspace(ctx, "vjp_psi", sizeof(double2) * (size_t)N * tsd));
+            double2* Psib = static_cast<double2*>(workspace(ctx, "vjp_psibar", sizeof(double2) * (size_t)N * tsd));
             for (int q = 0; q < na; ++q)
                 for (int k = 0; k < nt; ++k) {
-                    double2* x = Psi + ((size_t)q * nt + k) * Dt;
-                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, x, 1, D, Dt);
-                    if (k > 0) sil_propagate(ctx, A.H, tgt.get(), x, 1, Dt, k * A.spg, bo);
+                    double2* x = Psi + ((size_t)q * nt + k) * tsd;
+                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * sd, x, nm, D, Dt);
+                    if (k > 0) sil_propagate(ctx, HF, tgt.get(), x, nm, Dt, k * A.spg, bo);
+                    progress(ctx, dagger ? "adjoint_mesh_greater" : "adjoint_mesh_lesser", (int64_t)q * nt + k + 1, N);
                 }
-            // Gram matrix raw[(b,s)][(a,j)] = <Psi_b(s)|Psi_a(j)>, then G on the host side of the ABI
             double2* raw = static_cast<double2*>(workspace(ctx, "vjp_raw", sizeof(double2) * (size_t)N * N));
-            block_dots(ctx, Psi, Dt, N, Psi, Dt, N, Dt, raw);
-            std::vector<double2> rh((size_t)N * N);
-            KGF_HIP(hipMemcpyAsync(rh.data(), raw, sizeof(double2) * rh.size(), hipMemcpyDeviceToHost, ctx->stream));
-            sync(ctx);
-            for (int a = 0; a < na; ++a)
-                for (int b = 0; b < na; ++b)
-                    for (int j = 0; j < nt; ++j)
-                        for (int s = 0; s < nt; ++s) {
-                            // lesser: G[j][s][A][B] = i <Psi_B(s)|Psi_A(j)>; greater: -i <chi_A(j)|chi_B(s)>
-                            const double2 z = rh[((size_t)b * nt + s) * N + (size_t)a * nt + j];
-                            const double2 zg = rh[((size_t)a * nt + j) * N + (size_t)b * nt + s];
-                            if (!dagger) Gl[Widx(j, s, loc[a], loc[b])] = make_double2(-z.y, z.x);
-                            else Gg[Widx(j, s, loc[a], loc[b])] = make_double2(zg.y, -zg.x);
-                        }
-            if (!W) continue;
-            // cotangents of the mesh states: Psi_bar = C Psi (see the file header)
-            std::vector<double2> C((size_t)N * N);
-            for (int x = 0; x < na; ++x)
-                for (int m = 0; m < nt; ++m)
-                    for (int a = 0; a < na; ++a)
-                        for (int j = 0; j < nt; ++j) {
-                            const double2 w1 = W[Widx(j, m, loc[a], loc[x])];
-                            const double2 w2 = W[Widx(m, j, loc[x], loc[a])];
-                            cplx c;
-                            if (!dagger)   // (i/2)[conj(W[j][m][a][x]) - W[m][j][x][a]]
-                                c = cplx(0.0, 0.5) * (std::conj(cplx(w1.x, w1.y)) - cplx(w2.x, w2.y));
-                            else           // (i/2)[W[j][m][a][x] - conj(W[m][j][x][a])]
-                                c = cplx(0.0, 0.5) * (cplx(w1.x, w1.y) - std::conj(cplx(w2.x, w2.y)));
-                            C[((size_t)x * nt + m) * N + (size_t)a * nt + j] = make_double2(c.real(), c.imag());
-                        }
-            double2* Cd = static_cast<double2*>(workspace(ctx, "vjp_C", sizeof(double2) * C.size()));
-            KGF_HIP(hipMemcpy(Cd, C.data(), sizeof(double2) * C.size(), hipMemcpyHostToDevice));
-            for (int y0 = 0; y0 < N; y0 += 65535) {
-                const int ny = std::min(N - y0, 65535);
-                hipLaunchKernelGGL(k_lincomb, dim3(grid_for(Dt), ny), dim3(kThreads), 0, ctx->stream, Psi, Dt, N,
-                                   Cd + (size_t)y0 * N, Psib + (size_t)y0 * Dt, Dt, Dt);
-                check_launch("k_lincomb");
+            double2* Cd = static_cast<double2*>(workspace(ctx, "vjp_C", sizeof(double2) * (size_t)N * N));
+            std::vector<double2> rh((size_t)N * N), C((size_t)N * N);
+            for (int j = 0; j < nm; ++j) {
+                // Gram matrix raw[(b,s)][(a,j)] = <Psi_b(s)|Psi_a(j)> of member j
+                block_dots(ctx, Psi + (size_t)j * Dt, tsd, N, Psi + (size_t)j * Dt, tsd, N, Dt, raw);
+                KGF_HIP(hipMemcpyAsync(rh.data(), raw, sizeof(double2) * rh.size(), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+                sync(ctx);
+                double2* GlJ = Gl.data() + (size_t)j * gsz;
+                double2* GgJ = Gg.data() + (size_t)j * gsz;
+                for (int a = 0; a < na; ++a)
+                    for (int b = 0; b < na; ++b)
+                        for (int jj = 0; jj < nt; ++jj)
+                            for (int s2 = 0; s2 < nt; ++s2) {
+                                // lesser: G[j][s][A][B] = i <Psi_B(s)|Psi_A(j)>; greater: -i <chi_A(j)|chi_B(s)>
+                                const double2 z = rh[((size_t)b * nt + s2) * N + (size_t)a * nt + jj];
+                                const double2 zg = rh[((size_t)a * nt + jj) * N + (size_t)b * nt + s2];
+                                if (!dagger) GlJ[Widx(jj, s2, loc[a], loc[b])] = make_double2(-z.y, z.x);
+                                else GgJ[Widx(jj, s2, loc[a], loc[b])] = make_double2(zg.y, -zg.x);
+                            }
+                // cotangents of the mesh states: Psi_bar = C Psi (see the file header)
+                const double2* W = dagger ? M[j].Wg : M[j].Wl;
+                for (int x = 0; x < na; ++x)
+                    for (int mm = 0; mm < nt; ++mm)
+                        for (int a = 0; a < na; ++a)
+                            for (int jj = 0; jj < nt; ++jj) {
+                                cplx c(0.0, 0.0);
+                                if (W) {
+                                    const double2 w1 = W[Widx(jj, mm, loc[a], loc[x])];
+                                    const double2 w2 = W[Widx(mm, jj, loc[x], loc[a])];
+                                    if (!dagger)   // (i/2)[conj(W[j][m][a][x]) - W[m][j][x][a]]
+                                        c = cplx(0.0, 0.5) * (std::conj(cplx(w1.x, w1.y)) - cplx(w2.x, w2.y));
+                                    else           // (i/2)[W[j][m][a][x] - conj(W[m][j][x][a])]
+                                        c = cplx(0.0, 0.5) * (cplx(w1.x, w1.y) - std::conj(cplx(w2.x, w2.y)));
+                                }
+                                C[((size_t)x * nt + mm) * N + (size_t)a * nt + jj] = make_double2(c.real(), c.imag());
+                            }
+                KGF_HIP(hipMemcpy(Cd, C.data(), sizeof(double2) * C.size(), hipMemcpyHostToDevice));
+                for (int y0 = 0; y0 < N; y0 += 65535) {
+                    const int ny = std::min(N - y0, 65535);
+                    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(Dt), ny), dim3(kThreads), 0, ctx->stream,
+                                       Psi + (size_t)j * Dt, tsd, N, Cd + (size_t)y0 * N,
+                                       Psib + (size_t)y0 * tsd + (size_t)j * Dt, tsd, Dt);
+                    check_launch("k_lincomb");
+                }
+                sync(ctx);   // Cd is reused by the next member
             }
             // back through each chain, then through c_a (adjoint c+_a) or c+_a (adjoint c_a)
-            double2* xs = static_cast<double2*>(workspace(ctx, "vjp_x0", sizeof(double2) * Dt));
-            double2* back = static_cast<double2*>(workspace(ctx, "vjp_back", sizeof(double2) * D));
+            double2* xs = static_cast<double2*>(workspace(ctx, "vjp_x0", sizeof(double2) * (size_t)tsd));
+            double2* back = static_cast<double2*>(workspace(ctx, "vjp_back", vb * nm));
             for (int q = 0; q < na; ++q)
                 for (int k = 0; k < nt; ++k) {
-                    double2* lam = Psib + ((size_t)q * nt + k) * Dt;
+                    double2* lam = Psib + ((size_t)q * nt + k) * tsd;
                     if (k > 0) {
-                        apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * D, xs, 1, D, Dt);
-                        chain_adjoint(ctx, A.H, tgt.get(), xs, k * A.spg, dt, +1, A.o, A.nq, lam, g);
+                        apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi + (size_t)k * sd, xs, nm, D, Dt);
+                        chain_adjoint(ctx, HF, tgt.get(), nm, xs, Dt, k * A.spg, dt, +1, A.o, A.nq, lam, Dt, g, nth);
                     }
-                    apply_c(ctx, tgt.get(), sec, A.orbs[loc[q]], dagger ? 0 : 1, lam, back, 1, Dt, D);
-                    axpy(ctx, Phib + (size_t)k * D, back, cplx(1.0, 0.0), D);
+                    apply_c(ctx, tgt.get(), sec, A.orbs[loc[q]], dagger ? 0 : 1, lam, back, nm, Dt, D);
+                    axpy(ctx, Phib + (size_t)k * sd, back, cplx(1.0, 0.0), sd);
                     progress(ctx, dagger ? "adjoint_greater" : "adjoint_lesser", (int64_t)q * nt + k + 1, N);
                 }
         }
     }
     // adjoint of the forward mesh Phi(t_k) = exp(-iH dt)^(k spg) |0>
-    double2* lam = static_cast<double2*>(workspace(ctx, "vjp_lam", sizeof(double2) * D));
-    KGF_HIP(hipMemcpyAsync(lam, Phib + (size_t)(nt - 1) * D, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    double2* lam = static_cast<double2*>(workspace(ctx, "vjp_lam", vb * nm));
+    KGF_HIP(hipMemcpyAsync(lam, Phib + (size_t)(nt - 1) * sd, vb * nm, hipMemcpyDeviceToDevice, ctx->stream));
     for (int k = nt - 1; k >= 1; --k) {
-        chain_adjoint(ctx, A.H, sec, Phi + (size_t)(k - 1) * D, A.spg, dt, -1, A.o, A.nq, lam, g);
-        axpy(ctx, lam, Phib + (size_t)(k - 1) * D, cplx(1.0, 0.0), D);
+        chain_adjoint(ctx, HF, sec, nm, Phi + (size_t)(k - 1) * sd, D, A.spg, dt, -1, A.o, A.nq, lam, D, g, nth);
+        axpy(ctx, lam, Phib + (size_t)(k - 1) * sd, cplx(1.0, 0.0), sd);
         progress(ctx, "adjoint_forward", nt - k, nt - 1);
     }
-    // ground state of H_ini
-    if (Wl || Wg) {
-        double2* mu = static_cast<double2*>(workspace(ctx, "vjp_mu", sizeof(double2) * D));
-        *cg_iters = projected_cg(ctx, A.H_ini, sec, psi0, E0, lam, mu, A.cg_tol, A.cg_maxit);
-        const double2 wm = make_double2(-2.0, 0.0);
-        dH_expect(ctx, A.H_ini, sec, mu, D, psi0, D, 1, &wm, gi);
+    // ground states of H_ini
+    for (int j = 0; j < nm; ++j) {
+        int it = 0;
+        if (M[j].Wl || M[j].Wg) {
+            double2* mu = static_cast<double2*>(workspace(ctx, "vjp_mu", vb));
+            it = projected_cg(ctx, M[j].Hi, sec, psi0 + (size_t)j * D, E0[j], lam + (size_t)j * D, mu, A.cg_tol,
+                              A.cg_maxit);
+            const double2 wm = make_double2(-2.0, 0.0);
+            dH_expect(ctx, M[j].Hi, sec, mu, D, psi0 + (size_t)j * D, D, 1, &wm, gi + (size_t)j * nthi);
+        }
+        if (M[j].cg_iters) *M[j].cg_iters = it;
     }
-    std::vector<double> gh(nth + nthi);
+    std::vector<double> gh((size_t)nm * (nth + nthi));
     KGF_HIP(hipMemcpyAsync(gh.data(), g, sizeof(double) * gh.size(), hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
-    if (grad_host) std::copy(gh.begin(), gh.begin() + nth, grad_host);
-    if (grad_ini_host) std::copy(gh.begin() + nth, gh.end(), grad_ini_host);
-    if (Gl_host) std::copy(Gl.begin(), Gl.end(), Gl_host);
-    if (Gg_host) std::copy(Gg.begin(), Gg.end(), Gg_host);
-    for (const char* n : {"vjp_phi", "vjp_phibar", "vjp_psi", "vjp_psibar", "adj_chain", "sil_X", "adj_nodes"})
+    for (int j = 0; j < nm; ++j) {
+        if (M[j].grad) std::copy(gh.begin() + (size_t)j * nth, gh.begin() + (size_t)(j + 1) * nth, M[j].grad);
+        if (M[j].grad_ini) {
+            const double* src = gh.data() + (size_t)nm * nth + (size_t)j * nthi;
+            std::copy(src, src + n_theta(M[j].Hi), M[j].grad_ini);
+        }
+        if (M[j].Gl) std::copy(Gl.begin() + (size_t)j * gsz, Gl.begin() + (size_t)(j + 1) * gsz, M[j].Gl);
+        if (M[j].Gg) std::copy(Gg.begin() + (size_t)j * gsz, Gg.begin() + (size_t)(j + 1) * gsz, M[j].Gg);
+    }
+    for (const char* n : {"vjp_phi", "vjp_phibar", "vjp_psi", "vjp_psibar", "adj_chain", "sil_X", "adj_nodes", "adj_pair"})
         ctx->ws.erase(n);
 }
 
@@ -468,8 +542,9 @@ int kgf_propagate_vjp(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* se
         double* g = static_cast<double*>(workspace(ctx, "abi_grad", sizeof(double) * nth));
         KGF_HIP(hipMemsetAsync(g, 0, sizeof(double) * nth, ctx->stream));
         SilOpts o = to_sil_opts(opts);
-        chain_adjoint(ctx, const_cast<kgf_model*>(model), sector, reinterpret_cast<const double2*>(psi0), nsteps, o.dt,
-                      o.direction, o, quad_nodes, reinterpret_cast<double2*>(lam), g);
+        chain_adjoint(ctx, const_cast<kgf_model*>(model), sector, 1, reinterpret_cast<const double2*>(psi0),
+                      sector->dim(), nsteps, o.dt, o.direction, o, quad_nodes, reinterpret_cast<double2*>(lam),
+                      sector->dim(), g, 0);
         KGF_HIP(hipMemcpyAsync(host_grad, g, sizeof(double) * nth, hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
         ctx->ws.erase("adj_chain");
@@ -496,8 +571,6 @@ int kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                         "kgf_greens_neq_vjp: orbital out of range");
         KGF_HIP(hipSetDevice(ctx->device));
         VjpArgs A;
-        A.H_ini = const_cast<kgf_model*>(H_ini);
-        A.H = const_cast<kgf_model*>(H);
         A.sec = sector;
         A.orbs = host_orbs;
         A.norb = n_orb;
@@ -507,12 +580,79 @@ int kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
         A.nq = quad_nodes;
         A.cg_tol = cg_tol;
         A.cg_maxit = 20000;
-        int cgi = 0;
-        four_step_vjp(ctx, A, reinterpret_cast<const double2*>(v0), gs_opts,
-                      reinterpret_cast<const double2*>(host_W_lesser), reinterpret_cast<const double2*>(host_W_greater),
-                      host_grad_ini, host_grad, reinterpret_cast<double2*>(host_G_lesser),
-                      reinterpret_cast<double2*>(host_G_greater), host_E0, &cgi);
-        if (host_cg_iters) *host_cg_iters = cgi;
+        std::vector<VjpMember> M(1);
+        M[0].Hi = const_cast<kgf_model*>(H_ini);
+        M[0].Hf = const_cast<kgf_model*>(H);
+        M[0].v0 = reinterpret_cast<const double2*>(v0);
+        M[0].Wl = reinterpret_cast<const double2*>(host_W_lesser);
+        M[0].Wg = reinterpret_cast<const double2*>(host_W_greater);
+        M[0].grad_ini = host_grad_ini;
+        M[0].grad = host_grad;
+        M[0].Gl = reinterpret_cast<double2*>(host_G_lesser);
+        M[0].Gg = reinterpret_cast<double2*>(host_G_greater);
+        M[0].E0 = host_E0;
+        M[0].cg_iters = host_cg_iters;
+        four_step_vjp(ctx, A, gs_opts, M);
+    });
+}
+
+int kgf_greens_neq_vjp_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H_ini, const kgf_model* const* H,
+                             const kgf_sector* const* sectors, const kgf_gs_opts* gs_opts, const kgf_c128* const* v0,
+                             const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
+                             const kgf_prop_opts* opts, const kgf_c128* const* host_W_lesser,
+                             const kgf_c128* const* host_W_greater, int quad_nodes, double cg_tol,
+                             double* const* host_grad_ini, double* const* host_grad, double* host_E0,
+                             int* host_cg_iters) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && n_inst >= 1 && H_ini && H && sectors && gs_opts && v0 && host_orbs && host_E0, KGF_EINVAL,
+                    "kgf_greens_neq_vjp_multi: NULL argument");
+        check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && quad_nodes >= 1 && quad_nodes <= 31 &&
+                        std::isfinite(cg_tol) && cg_tol > 0.0,
+                    KGF_EINVAL, "kgf_greens_neq_vjp_multi: bad sizes");
+        for (int i = 0; i < n_inst; ++i) {
+            KGF_REQUIRE(H_ini[i] && H[i] && sectors[i] && v0[i], KGF_EINVAL, "kgf_greens_neq_vjp_multi: NULL instance");
+            KGF_REQUIRE(H_ini[i]->L == sectors[i]->L && H[i]->L == sectors[i]->L && sectors[i]->dim() > 0, KGF_EINVAL,
+                        "kgf_greens_neq_vjp_multi: model / sector mismatch or empty sector");
+            for (int a = 0; a < n_orb; ++a)
+                KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sectors[i]->L, KGF_EINVAL,
+                            "kgf_greens_neq_vjp_multi: orbital out of range");
+        }
+        KGF_HIP(hipSetDevice(ctx->device));
+        std::vector<int> done(n_inst, 0);
+        for (int i0 = 0; i0 < n_inst; ++i0) {
+            if (done[i0]) continue;
+            std::vector<VjpMember> M;
+            for (int i = i0; i < n_inst; ++i) {
+                const kgf_sector* a = sectors[i];
+                const kgf_sector* b = sectors[i0];
+                if (done[i] || a->L != b->L || a->n_up != b->n_up || a->n_dn != b->n_dn || !same_topology(H[i], H[i0]))
+                    continue;
+                done[i] = 1;
+                VjpMember mb;
+                mb.Hi = const_cast<kgf_model*>(H_ini[i]);
+                mb.Hf = const_cast<kgf_model*>(H[i]);
+                mb.v0 = reinterpret_cast<const double2*>(v0[i]);
+                mb.Wl = host_W_lesser ? reinterpret_cast<const double2*>(host_W_lesser[i]) : nullptr;
+                mb.Wg = host_W_greater ? reinterpret_cast<const double2*>(host_W_greater[i]) : nullptr;
+                mb.grad_ini = host_grad_ini ? host_grad_ini[i] : nullptr;
+                mb.grad = host_grad ? host_grad[i] : nullptr;
+                mb.E0 = host_E0 + i;
+                mb.cg_iters = host_cg_iters ? host_cg_iters + i : nullptr;
+                M.push_back(mb);
+            }
+            VjpArgs A;
+            A.sec = sectors[i0];
+            A.orbs = host_orbs;
+            A.norb = n_orb;
+            A.nt = nt;
+            A.spg = steps_per_grid;
+            A.o = to_sil_opts(opts);
+            A.nq = quad_nodes;
+            A.cg_tol = cg_tol;
+            A.cg_maxit = 20000;
+            four_step_vjp(ctx, A, gs_opts, M);
+        }
     });
 }
 

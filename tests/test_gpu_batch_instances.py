@@ -93,3 +93,25 @@ def test_full_uneven_batch(ctx):
         ref = ctx.greens_neq(Hi[i], Hf[i], secs[i], v0[i], schedule=1, **kw)
         assert rel_err(out["G_lesser"][i], ref["G_lesser"]) < 1e-12
         assert rel_err(out["G_greater"][i], ref["G_greater"]) < 1e-12
+
+
+def test_batched_adjoint_equals_per_instance(ctx):
+    """kgf_greens_neq_vjp_multi (two L = 8, two L = 9 and one L = 10 instance;
+    same-L instances batched) against kgf_greens_neq_vjp instance by
+    instance, seeded complex cotangents on G^< and G^>."""
+    allq = wl.batch_instances()
+    qs = [q for q in allq if q.H.L == 8][:2] + [q for q in allq if q.H.L == 9][:2] + [q for q in allq if q.H.L == 10][:1]
+    say("batched adjoint:", [q.name for q in qs])
+    Hi, Hf, secs, v0 = _inputs(ctx, qs)
+    nt, spg, dt = 4, 2, 0.05
+    rng = np.random.default_rng(5)
+    Wl = [rng.standard_normal((nt, nt, 1, 1)) + 1j * rng.standard_normal((nt, nt, 1, 1)) for _ in qs]
+    Wg = [rng.standard_normal((nt, nt, 1, 1)) + 1j * rng.standard_normal((nt, nt, 1, 1)) for _ in qs]
+    kw = dict(krylov_dim=15, quad_nodes=8, cg_tol=1e-12)
+    res = ctx.greens_neq_vjp_multi(Hi, Hf, secs, v0, [(0, 0)], nt, spg, dt, Wl, Wg, **kw)
+    for i, q in enumerate(qs):
+        ref = ctx.greens_neq_vjp(Hi[i], Hf[i], secs[i], v0[i], [(0, 0)], nt, spg, dt, Wl[i], Wg[i], **kw)
+        assert res[i]["E0"] == ref["E0"]
+        sc = max(np.abs(ref["grad"]).max(), np.abs(ref["grad_ini"]).max())
+        assert np.abs(res[i]["grad"] - ref["grad"]).max() <= 1e-12 * sc, q.name
+        assert np.abs(res[i]["grad_ini"] - ref["grad_ini"]).max() <= 1e-12 * sc, q.name
