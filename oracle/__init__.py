@@ -17,6 +17,8 @@ Modules
     greens       equilibrium G (Eq. psigreen) and the four-step
                  nonequilibrium G^<, G^>, Matsubara and mixed components
                  (Sec. 4)
+    gradients    dense exact gradients (Frechet derivative of exp, ground-state
+                 perturbation): the reference for the adjoint
     exact        dense references: Jordan-Wigner Fock-space operators,
                  full diagonalisation, matrix exponentials and the U=0
                  closed form used to pin the above

@@ -172,7 +172,9 @@ void sil_adjoint_step(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int nm,
     }
     double2* coef = static_cast<double2*>(workspace(ctx, "adj_coef", sizeof(double2) * nreq * m));
     sil_coefs(ctx, m, nreq, col.data(), tt.data(), dir.data(), 0.0, coef, m);
-    double2* nodes = static_cast<double2*>(workspace(ctx, "adj_nodes", vb * 2 * nq * nm));
+    // per member: nq psi nodes, nq lam nodes, the new cotangent (one slot)
+    const int slots = 2 * nq + 1;
+    double2* nodes = static_cast<double2*>(workspace(ctx, "adj_nodes", vb * slots * nm));
     std::vector<double2> om(nq);
     for (int q = 0; q < nq; ++q) {
         // 2 Re[delta i (dt/2) w_q <lam|dH|psi>]  ->  weight delta i dt w_q
@@ -180,10 +182,11 @@ void sil_adjoint_step(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int nm,
     }
     for (int j = 0; j < nm; ++j) {
         const double2* cj = coef + (size_t)j * per * m;
-        double2* nj = nodes + (size_t)j * 2 * nq * D;
+        double2* nj = nodes + (size_t)j * slots * D;
         sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, j, cj, m, nq, nj, D);
-        sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, nm + j, cj + (size_t)nq * m, m, nq, nj + (size_t)nq * D, D);
-        sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, nm + j, cj + (size_t)2 * nq * m, m, 1, lam + j * lam_ld, D);
+        // lam nodes and the new cotangent in one pass over the lam basis
+        sil_combine_multi(ctx, sec, pair, D, 2 * nm, m, nm + j, cj + (size_t)nq * m, m, nq + 1, nj + (size_t)nq * D, D);
+        KGF_HIP(hipMemcpyAsync(lam + j * lam_ld, nj + (size_t)2 * nq * D, vb, hipMemcpyDeviceToDevice, ctx->stream));
         // dH/dtheta depends on the bond topology only, shared by all members
         dH_expect(ctx, model.m, sec, nj + (size_t)nq * D, D, nj, D, nq, om.data(), g + (size_t)j * gstride);
     }

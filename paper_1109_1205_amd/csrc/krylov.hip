@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_multiaxpy(Slots sl, int ky, int nj
 
 // Several outputs from one pass over the Krylov slots of column c:
 // out_o = sum_j coef[o][j] slot(j, c) for o < nout (nout <= kMaxOut).
-constexpr int kMaxOut = 8;
+constexpr int kMaxOut = 16;
 __global__ __launch_bounds__(kThreads) void k_combine_multi(Slots sl, int c, int n, const double2* __restrict__ coef,
                                                             int64_t coef_stride, int nout, double2* __restrict__ out,
                                                             int64_t out_col, int64_t D) {

@@ -225,3 +225,46 @@ def test_ladder16_hopping_gradient_short_mesh(ctx):
         fd = (loss(b, h) - loss(b, -h)) / (2 * h)
         say("bond", q.H.bonds[b], "adjoint", g_t[b], "fd", fd)
         assert abs(g_t[b] - fd) <= 1e-6 * max(1.0, np.abs(g_t).max())
+
+
+@pytest.mark.parametrize("direction", [-1, +1])
+def test_propagate_vjp_against_dense_frechet_gradient(ctx, direction):
+    """Adjoint of n SIL steps vs the exact gradient of exp(direction i H n dt)
+    (Frechet derivative of the matrix exponential)."""
+    from oracle import gradients
+    model = wl.chain_siam(6, 2.0).with_field(0, 0.3)
+    sec = basis.Sector(6, 3, 2)
+    psi0, chi = wl.complex_vector(sec.dim, 3), wl.complex_vector(sec.dim, 4)
+    n, dt, m = 5, 0.1, 15
+    ref = gradients.propagation_gradient(model, sec, psi0, chi, n * dt, direction)
+    lam = to_dev(0.5 * chi)
+    g = ctx.propagate_vjp(ctx.model(model), ctx.sector(6, 3, 2), to_dev(psi0), lam, n, dt, m, direction, reorth=2,
+                          quad_nodes=10)
+    say("propagate vjp vs dense", np.abs(g - ref).max(), np.abs(ref).max())
+    assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_greens_neq_vjp_against_dense_gradient(ctx):
+    """Four-step gradient (H and H_ini, orbitals of both spins) vs the exact
+    dense gradient: Frechet derivatives of every exponential and the
+    sum-over-states ground-state derivative."""
+    from oracle import gradients
+    H = wl.chain_siam(4, 2.0)
+    Hi = gradients.model_with_theta(H.with_field(0, 0.4), gradients.theta_of(H.with_field(0, 0.4)) * 1.03)
+    orbs = [(0, 0), (1, 1)]
+    nt, spg, dt = 3, 3, 0.1
+    times = [k * spg * dt for k in range(nt)]
+    rng = np.random.default_rng(3)
+    shape = (nt, nt, 2, 2)
+    Wl = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    Wg = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    gi_ref, g_ref, G = gradients.four_step_gradient(Hi, H, 2, 2, orbs, times, Wl, Wg)
+    sec = basis.Sector(4, 2, 2)
+    r = ctx.greens_neq_vjp(ctx.model(Hi), ctx.model(H), ctx.sector(4, 2, 2), to_dev(wl.start_vector(sec.dim, 7)),
+                           orbs, nt, spg, dt, Wl, Wg, krylov_dim=14, reorth=2, quad_nodes=10, cg_tol=1e-13,
+                           gs_tol=1e-13)
+    sc = max(np.abs(g_ref).max(), np.abs(gi_ref).max())
+    say("four-step vjp vs dense", np.abs(r["grad"] - g_ref).max(), np.abs(r["grad_ini"] - gi_ref).max(), sc)
+    assert rel_err(r["G_lesser"], G["G_lesser"]) < 1e-10
+    assert np.abs(r["grad"] - g_ref).max() <= 1e-8 * sc
+    assert np.abs(r["grad_ini"] - gi_ref).max() <= 1e-8 * sc
