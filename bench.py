@@ -66,7 +66,8 @@ def parse():
     p.add_argument("--hv", default="",
                    help="H.v micro-benchmark instead of the four-step run: comma-separated ladder sizes "
                         "(14, 16); each is timed for every --hv-passes variant")
-    p.add_argument("--hv-passes", default="0", help="comma-separated kgf_set_option HV_PASSES values")
+    p.add_argument("--hv-passes", default="0",
+                   help="comma-separated kgf_set_option HV_PASSES values (9: the library's tuner chooses)")
     p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
     p.add_argument("--hv-reps", type=int, default=10)
     return p.parse_args()
@@ -89,8 +90,10 @@ def hv_bench(a):
         y = torch.empty_like(x)
         variants = [(int(p_), int(s_)) for p_ in a.hv_passes.split(",") if p_ for s_ in a.hv_strip.split(",") if s_]
         for passes, strip in variants:
-            ctx.set_option(ctx.HV_PASSES, passes)
-            ctx.set_option(ctx.HV_STRIP, strip)
+            # passes 9: let the library's tuner choose (HV_TUNE)
+            ctx.set_option(ctx.HV_TUNE, 1 if passes == 9 else 0)
+            ctx.set_option(ctx.HV_PASSES, 0 if passes == 9 else passes)
+            ctx.set_option(ctx.HV_STRIP, 0 if passes == 9 else strip)
             ctx.apply_h(m, sec, x, y)      # warm-up (tables, LDS opt-in)
             torch.cuda.synchronize()
             log(f"L={L} D={sec.dim} passes={passes} strip={strip}: timing")
@@ -111,6 +114,7 @@ def hv_bench(a):
             del xs
         ctx.set_option(ctx.HV_PASSES, 0)
         ctx.set_option(ctx.HV_STRIP, 0)
+        ctx.set_option(ctx.HV_TUNE, 0)
         del x, y
         torch.cuda.empty_cache()
 

@@ -328,9 +328,16 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      take at most 30% of free device memory, else keep every
  *                      K-th state and recompute one segment at a time;
  *                      n >= 1 fixes K = n (checkpoint every n SIL steps).
+ *   KGF_OPT_HV_TUNE:   0 (default) = H.v variant by size; 1 = the first H.v of
+ *                      each sector (L, N_up, N_dn) times every equivalent variant
+ *                      (single pass, two pass with strips 16/32/64, split rows)
+ *                      on scratch vectors, separately for the plain and the
+ *                      Lanczos form, and keeps the fastest for that context.
+ *                      HV_PASSES / HV_STRIP, when set, take precedence.
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
-enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5 };
+enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5,
+       KGF_OPT_HV_TUNE = 6 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

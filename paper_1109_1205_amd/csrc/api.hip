@@ -469,6 +469,9 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_ADJ_EVERY) {
             KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: ADJ_EVERY must be >= 0");
             ctx->adj_every = value;
+        } else if (option == KGF_OPT_HV_TUNE) {
+            KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: HV_TUNE must be 0 or 1");
+            ctx->hv_tune = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

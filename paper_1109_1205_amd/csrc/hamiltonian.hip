@@ -11,6 +11,8 @@
 // whole rows V[u', :] (coalesced along d), the down-spin hops gather inside
 // row u (L1/L2 resident), the diagonal is evaluated on the fly from the two
 // masks.  H.v is sparse and memory bound: no matrix cores are involved.
+#include <array>
+
 #include "kgf_internal.h"
 
 namespace kgf {
@@ -832,13 +834,13 @@ struct HvPlan {
 
 constexpr size_t kStripL2Bytes = 6 * 1024 * 1024;   // widest strip up to this slab size (measured)
 
-HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec) {
+// The plan for an explicit request (passes 0..3, strip 0/8..64; 0 = by size).
+HvPlan make_plan(const kgf_sector* sec, int ov, int strip) {
     HvPlan p;
     const int64_t Dup = sec->d_up, Ddn = sec->d_dn;
     const size_t row = sizeof(double2) * (size_t)Ddn;
     const bool fits1 = row <= kRowLdsMax;
     const bool fits_split = sizeof(double) * (size_t)Ddn <= kSplitLdsMax && Ddn <= (int64_t)kRowsJSplit * kHvThreads;
-    const int ov = ctx->hv_passes;
     if (fits1 && (ov == 0 || ov == 1)) p.passes = 1;
     else if (fits1 || fits_split) p.passes = 2;
     else p.passes = 0;
@@ -850,13 +852,25 @@ HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec) {
                 p.C = c;
                 break;
             }
-        if (ctx->hv_strip) p.C = ctx->hv_strip;
+        if (strip) p.C = strip;
         const int R = kUpThreads / p.C;
         p.nstrip = (int)((Ddn + p.C - 1) / p.C);
         p.ntile = (int)((Dup + R - 1) / R);
         p.up_blocks = 8 * (int64_t)((p.nstrip + 7) / 8) * p.ntile;
     }
     return p;
+}
+
+std::array<int, 4> tune_key(const kgf_sector* sec, int mode) { return {sec->L, sec->n_up, sec->n_dn, mode}; }
+
+// Explicit options win; then a tuned choice (kgf_set_option HV_TUNE); then sizes.
+HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec, int mode) {
+    if (ctx->hv_passes || ctx->hv_strip) return make_plan(sec, ctx->hv_passes, ctx->hv_strip);
+    if (ctx->hv_tune) {
+        auto it = ctx->hv_tuned.find(tune_key(sec, mode));
+        if (it != ctx->hv_tuned.end()) return make_plan(sec, it->second.first, it->second.second);
+    }
+    return make_plan(sec, 0, 0);
 }
 
 template <int MODE, int C>
@@ -883,14 +897,14 @@ template <int MODE>
 void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int cbase,
                const double2* x, int64_t x_col, const double2* xp, int64_t xp_col, double2* y,
                int64_t y_col, const double* s_k, const double* b_k, const double* s_km1,
-               int stride, double* part) {
+               int stride, double* part, const HvPlan* force = nullptr) {
     HvTables T = make_tables(model, sec);
     T.cbase = cbase;
     KGF_REQUIRE(sec->d_up <= 0x7ffffff0 && ncol <= 65535, KGF_EUNSUPPORTED, "H.v: grid too large");
     // algorithmic bytes: read x once, write y once, read xp once if present
     const double vec = 16.0 * (double)sec->dim() * ncol;
     Prof pr(ctx, MODE == 0 ? "hv" : "hv_lanczos", vec * (xp ? 3.0 : 2.0));
-    const HvPlan P = hv_plan(ctx, sec);
+    const HvPlan P = force ? *force : hv_plan(ctx, sec, MODE);
     const bool uu = uniform_U(model);
     if (P.passes == 1) {
         const size_t row_bytes = sizeof(double2) * (size_t)sec->d_dn;
@@ -945,8 +959,79 @@ void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int 
 
 }  // namespace
 
+void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
+    if (!ctx->hv_tune || ctx->hv_passes || ctx->hv_strip || sec->dim() == 0) return;
+    const int64_t D = sec->dim();
+    for (int mode = 0; mode < 2; ++mode) {
+        const auto key = tune_key(sec, mode);
+        if (ctx->hv_tuned.count(key)) continue;
+        // candidate requests, one per distinct plan
+        std::vector<std::pair<int, int>> cand;
+        std::vector<HvPlan> plans;
+        const std::pair<int, int> reqs[] = {{1, 0}, {2, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}};
+        for (const auto& rq : reqs) {
+            const HvPlan P = make_plan(sec, rq.first, rq.second);
+            if (P.passes == 0) continue;
+            bool dup = false;
+            for (const auto& q : plans) dup = dup || (q.passes == P.passes && q.split == P.split && q.C == P.C);
+            if (!dup) {
+                plans.push_back(P);
+                cand.push_back(rq);
+            }
+        }
+        if (cand.size() <= 1) {
+            ctx->hv_tuned[key] = cand.empty() ? std::make_pair(0, 0) : cand[0];
+            continue;
+        }
+        int64_t nblk = sec->d_up;
+        for (const auto& P : plans) nblk = std::max<int64_t>(nblk, P.up_blocks);
+        ensure_device_fits(2 * sizeof(double2) * (size_t)D, "H.v tuning vectors");
+        double2* x = static_cast<double2*>(workspace(ctx, "hv_tune_x", 2 * sizeof(double2) * (size_t)D));
+        double2* y = x + D;
+        double* aux = static_cast<double*>(workspace(ctx, "hv_tune_aux", sizeof(double) * (size_t)(nblk + 3)));
+        const double sc[3] = {1.0, 0.5, 1.0};   // s_k, b_k, s_{k-1}
+        KGF_HIP(hipMemsetAsync(x, 0, 2 * sizeof(double2) * (size_t)D, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(aux, sc, sizeof(sc), hipMemcpyHostToDevice, ctx->stream));
+        const bool prof = ctx->prof_on;
+        ctx->prof_on = false;
+        hipEvent_t e0, e1;
+        KGF_HIP(hipEventCreate(&e0));
+        KGF_HIP(hipEventCreate(&e1));
+        int best = 0;
+        float best_ms = 0.0f;
+        for (size_t c = 0; c < plans.size(); ++c) {
+            auto run = [&] {
+                if (mode == 0)
+                    launch_hv<0>(ctx, model, sec, 1, 0, x, D, nullptr, 0, y, D, nullptr, nullptr, nullptr, 0, nullptr,
+                                 &plans[c]);
+                else
+                    launch_hv<1>(ctx, model, sec, 1, 0, x, D, x, D, y, D, aux, aux + 1, aux + 2, 0, aux + 3, &plans[c]);
+            };
+            run();   // first launch: LDS opt-in, caches
+            KGF_HIP(hipEventRecord(e0, ctx->stream));
+            for (int r = 0; r < 3; ++r) run();
+            KGF_HIP(hipEventRecord(e1, ctx->stream));
+            KGF_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            KGF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (c == 0 || ms < best_ms) {
+                best_ms = ms;
+                best = (int)c;
+            }
+        }
+        KGF_HIP(hipEventDestroy(e0));
+        KGF_HIP(hipEventDestroy(e1));
+        ctx->prof_on = prof;
+        ctx->hv_tuned[key] = cand[best];
+        sync(ctx);
+        ctx->ws.erase("hv_tune_x");
+        ctx->ws.erase("hv_tune_aux");
+    }
+}
+
 void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec, const double2* v, double2* w,
              int nvec, int64_t ld) {
+    hv_prepare(ctx, model, sec);
     for (int c0 = 0; c0 < nvec; c0 += 65535) {
         int nc = nvec - c0 < 65535 ? nvec - c0 : 65535;
         launch_hv<0>(ctx, model, sec, nc, c0, v + c0 * ld, ld, nullptr, 0, w + c0 * ld, ld, nullptr,
@@ -955,7 +1040,7 @@ void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec, const double2* v
 }
 
 int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec) {
-    const HvPlan P = hv_plan(ctx, sec);
+    const HvPlan P = hv_plan(ctx, sec, 1);
     return P.passes == 2 ? (int)P.up_blocks : (int)sec->d_up;
 }
 

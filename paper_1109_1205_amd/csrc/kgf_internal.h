@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -94,6 +95,8 @@ struct kgf_ctx {
     int gs_max_basis = 0;                    // 0: as many Lanczos vectors as fit
     int phi_every = 0;                       // 0: forward mesh stored whole when it fits
     int adj_every = 0;                       // 0: adjoint chains stored whole when they fit
+    int hv_tune = 0;                         // 1: time the H.v variants of each sector once
+    std::map<std::array<int, 4>, std::pair<int, int>> hv_tuned;   // (L, N_up, N_dn, mode) -> (passes, strip)
     // progress callback
     kgf_progress_fn progress = nullptr;
     void* progress_user = nullptr;
@@ -178,6 +181,9 @@ struct HModel {
 
 void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec,
              const double2* v, double2* w, int nvec, int64_t ld);
+// With ctx->hv_tune set, times the equivalent H.v variants of the sector once
+// (plain and Lanczos forms) and keeps the fastest; a no-op otherwise.
+void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec);
 void apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int orbital,
              int dagger, const double2* v, double2* w, int nvec, int64_t ld_src,
              int64_t ld_dst);

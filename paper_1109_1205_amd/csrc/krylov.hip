@@ -822,6 +822,7 @@ void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, 
     const int64_t D = sec->dim();
     const int m = o.m;
     KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
+    hv_prepare(ctx, model, sec);
     sil_reserve(ctx, sec, ncol, m, o.reorth);
     const size_t xbytes = sizeof(double2) * (size_t)m * ncol * D;
     double2* X = static_cast<double2*>(workspace(ctx, "sil_X", xbytes));
@@ -938,6 +939,7 @@ void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* p
 static GsResult gs_cycle(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v0,
                          double2* psi0, double tol, int max_iter, int check_every, int reorth) {
     const int64_t D = sec->dim();
+    hv_prepare(ctx, model, sec);
     const int nmax = max_iter + 1;
     const size_t vbytes = sizeof(double2) * (size_t)nmax * D;
     auto& xs = ctx->ws["gs_V"];

@@ -198,3 +198,32 @@ def test_four_step_ladder16_short_run(ctx):
     n0 = float((p * occ).sum())
     say("n0", n0, "G<(0,0)", Gl[0, 0])
     assert abs(Gl[0, 0] - 1j * n0) < 1e-10
+
+
+def test_tuned_hv_choice_keeps_parity(ctx):
+    """With the H.v tuner on, the variant it picks per sector (and form)
+    still matches the oracle: H.v on three sectors, then ground state and
+    SIL steps on the Anderson star (which re-uses the tuned choice)."""
+    ctx.set_option(6, 1)
+    try:
+        for name, mk, nu, nd, nvec in CASES[:3]:
+            model = mk()
+            sec = basis.Sector(model.L, nu, nd)
+            H = hamiltonian.Hamiltonian(model, sec)
+            V = np.stack([wl.complex_vector(sec.dim, 10 + c) for c in range(nvec)])
+            got = to_host(ctx.apply_h(ctx.model(model), ctx.sector(model.L, nu, nd), to_dev(V)))
+            assert rel_err(got, np.stack([H.apply(V[c]) for c in range(nvec)])) < 1e-13, name
+        model = wl.siam10().H_ini
+        sec = basis.Sector(10, 5, 5)
+        H = hamiltonian.Hamiltonian(model, sec)
+        v0 = wl.start_vector(sec.dim, 7)
+        ora = lanczos.ground_state(H.apply, v0, tol=1e-12, max_iter=400)
+        s = ctx.sector(10, 5, 5)
+        E0, psi, info = ctx.ground_state(ctx.model(model), s, to_dev(v0), tol=1e-12, max_iter=400)
+        assert info["converged"] and abs(E0 - ora.E0) <= 1e-12 * abs(ora.E0)
+        X = wl.complex_vector(sec.dim, 30)
+        ref = propagate.propagate(H.apply, X, 0.05, 3, 15, -1, 0.0, "none")
+        got = to_host(ctx.propagate(ctx.model(model), s, to_dev(X[None, :]), 3, 0.05, 15, -1))
+        assert rel_err(got[0], ref) < 1e-12
+    finally:
+        ctx.set_option(6, 0)
