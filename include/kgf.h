@@ -180,6 +180,39 @@ int  kgf_greens_eq(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* secto
                    int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch,
                    kgf_c128* host_G_greater, kgf_c128* host_G_lesser);
 
+/* ---- equilibrium spectra (Sec. 2, Sec. 3) ----------------------------------
+ * kgf_greens_omega: the conventional Lanczos Green's function of Eq. (gapprox)
+ * for orbital a (site*2+spin) from the ground state psi0 (device, in `sector`)
+ * with energy E0, at the n_lanczos-step tridiagonal matrix (reorth 0..2 passes
+ * of Gram-Schmidt), evaluated as the continued fraction on host_omega[nw]:
+ *   host_G_greater[j] = <i0|(omega_j + i eta + E0 - H)^-1|i0>,  i0 = c+_a |0>,
+ *   host_G_lesser[j]  = <i0|(omega_j + i eta - E0 + H)^-1|i0>,  i0 = c_a |0>;
+ * the retarded G_aa(omega) is their sum and A = -Im G / pi.  eta > 0.
+ * host_steps[0..1] (or NULL) receive the Lanczos steps taken (fewer than
+ * n_lanczos when the Krylov space is exhausted).  Either output may be NULL. */
+int  kgf_greens_omega(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                      const kgf_c128* psi0, double E0, int orbital, int n_lanczos, int reorth,
+                      const double* host_omega, int nw, double eta, kgf_c128* host_G_greater,
+                      kgf_c128* host_G_lesser, int* host_steps);
+
+/* kgf_greens_eq_fine: the time-dependent Lanczos G of Eqs. (psit), (psigreen)
+ * for orbital a on a fine grid: nsteps short-iterative-Lanczos steps of
+ * opts->dt (the restarts), each read at nfine equally spaced times from its own
+ * Krylov basis (Eq. (udelta) with the fine time).  host_G[nsteps*nfine + 1] at
+ * t_j = j * opts->dt / nfine receives, as kgf_greens_eq,
+ *   dagger = 1: G^>(t) = -i e^{+i E0 t} <c+_a 0| e^{-iHt} |c+_a 0>,
+ *   dagger = 0: G^<(t) = +i e^{-i E0 t} <c_a 0| e^{+iHt} |c_a 0>
+ * (opts->direction is ignored; the retarded G(t) is G^> - G^<). */
+int  kgf_greens_eq_fine(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                        const kgf_c128* psi0, double E0, int orbital, int dagger, int nsteps,
+                        int nfine, const kgf_prop_opts* opts, kgf_c128* host_G);
+
+/* kgf_fourier: host_out[j] = sum_k w_k e^{(i omega_j - eta) t_k} host_G[k],
+ * t_k = k dt, trapezoid weights (dt, halved at both ends): the damped
+ * transform int_0^T dt e^{i omega t - eta t} G(t) of Sec. 3 (inverse of Eq. (ft)). */
+int  kgf_fourier(kgf_ctx* ctx, const kgf_c128* host_G, int nt, double dt, double eta,
+                 const double* host_omega, int nw, kgf_c128* host_out);
+
 /* ---- nonequilibrium Green's function, four-step procedure (Sec. 4) --------
  * (i)   |0> = ground state of H_ini in `sector` (kgf_ground_state, from v0)
  * (ii)  Phi(t_k) = e^{-iH t_k}|0>, t_k = k*steps_per_grid*opts->dt

@@ -19,6 +19,8 @@ Modules
                  (Sec. 4)
     gradients    dense exact gradients (Frechet derivative of exp, ground-state
                  perturbation): the reference for the adjoint
+    spectral     equilibrium spectra: conventional Lanczos G(omega) (Eq. gapprox),
+                 time-dependent Lanczos G(t) on a fine grid, damped transform
     exact        dense references: Jordan-Wigner Fock-space operators,
                  full diagonalisation, matrix exponentials and the U=0
                  closed form used to pin the above

@@ -101,6 +101,9 @@ def load_library():
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
         "kgf_set_option": (I, [P, I, I]),
+        "kgf_greens_omega": (I, [P, P, P, P, D, I, I, I, P, I, D, P, P, P]),
+        "kgf_greens_eq_fine": (I, [P, P, P, P, D, I, I, I, I, C.POINTER(_PropOpts), P]),
+        "kgf_fourier": (I, [P, P, I, D, D, P, I, P]),
         "kgf_greens_neq_vjp_multi": (I, [P, I, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), P, P,
                                          I, D, P, P, P, P]),
         "kgf_greens_neq_multi": (I, [P, I, P, P, P, P, C.POINTER(_GsOpts), P, I, I, I, C.POINTER(_PropOpts), I, P, P,
@@ -127,7 +130,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
-            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_profile_begin",
+            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_profile_begin",
             "kgf_profile_end"]
 
 
@@ -402,6 +405,41 @@ class Context:
                                          _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(batch),
                                          _np_ptr(Gl), _np_ptr(Gg), _np_ptr(E0)))
         return {"G_lesser": Gl, "G_greater": Gg, "E0": E0}
+
+    # -- equilibrium spectra --------------------------------------------------
+    def greens_omega(self, model: Model, sec: Sector, psi0, E0: float, orbital: Tuple[int, int], n_lanczos: int,
+                     omega, eta: float, reorth: int = 2):
+        """Conventional Lanczos G^(L)(omega) (kgf_greens_omega): particle and hole
+        parts; the retarded G is their sum."""
+        self._chk(psi0, sec.dim, "psi0")
+        w = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(-1))
+        Gg, Gl = _host_c128(w.shape), _host_c128(w.shape)
+        steps = np.zeros(2, dtype=np.int32)
+        _check(_lib.kgf_greens_omega(self.handle, model.handle, sec.handle, _ptr(psi0), float(E0),
+                                     2 * orbital[0] + orbital[1], int(n_lanczos), int(reorth), _np_ptr(w), len(w),
+                                     float(eta), _np_ptr(Gg), _np_ptr(Gl), _np_ptr(steps)))
+        return {"G_greater": Gg, "G_lesser": Gl, "steps": steps}
+
+    def greens_eq_fine(self, model: Model, sec: Sector, psi0, E0: float, orbital: Tuple[int, int], dagger: int,
+                       nsteps: int, nfine: int, dt: float, krylov_dim: int = 15, reorth: int = 0,
+                       breakdown_tol: float = 1e-13):
+        """Time-dependent Lanczos G^> (dagger=1) or G^< (dagger=0) on t_j = j dt / nfine."""
+        self._chk(psi0, sec.dim, "psi0")
+        G = _host_c128(nsteps * nfine + 1)
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        _check(_lib.kgf_greens_eq_fine(self.handle, model.handle, sec.handle, _ptr(psi0), float(E0),
+                                       2 * orbital[0] + orbital[1], int(dagger), int(nsteps), int(nfine), C.byref(o),
+                                       _np_ptr(G)))
+        return G
+
+    def fourier(self, G, dt: float, eta: float, omega):
+        """kgf_fourier: int_0^T dt e^{i omega t - eta t} G(t), trapezoid rule."""
+        g = np.ascontiguousarray(np.asarray(G, dtype=np.complex128).reshape(-1))
+        w = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(-1))
+        out = _host_c128(w.shape)
+        _check(_lib.kgf_fourier(self.handle, _np_ptr(g), len(g), float(dt), float(eta), _np_ptr(w), len(w),
+                                _np_ptr(out)))
+        return out
 
     HV_PASSES, HV_STRIP, GS_MAX_BASIS, PHI_EVERY, ADJ_EVERY, HV_TUNE = 1, 2, 3, 4, 5, 6
 

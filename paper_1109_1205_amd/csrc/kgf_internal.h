@@ -252,6 +252,11 @@ GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec,
                       const double2* v0, double2* psi0, double tol, int max_iter,
                       int check_every, int reorth);
 
+// n Lanczos steps from i0: a[0..n), b[1..n) (host), <i0|i0>; returns the
+// steps taken (fewer when the Krylov space is exhausted).
+int lanczos_tridiag(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* i0, int n, int reorth,
+                    double* a_host, double* b_host, double* norm2_host);
+
 // G[l][r] = <L_l | R_r> for nl left and nr right vectors (complex dots);
 // result in device memory out[l * nr + r] (double2).
 // out[l * out_ld + r]; out_ld = 0 means nr.

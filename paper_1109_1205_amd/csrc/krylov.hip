@@ -1036,6 +1036,75 @@ static GsResult gs_cycle(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, 
     return out;
 }
 
+// The tridiagonal Lanczos matrix of n steps from i0 (Eqs. (recursion),
+// (tmatrix)): a[0..n), b[1..n) on the host (b[k] couples steps k-1 and k),
+// norm2 = <i0|i0>.  The basis is kept for the reorthogonalisation (passes
+// 0..2).  Returns the number of steps taken: fewer than n when the Krylov
+// space is exhausted (b = 0), after which the matrix is exact.
+int lanczos_tridiag(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* i0, int n, int reorth,
+                    double* a_host, double* b_host, double* norm2_host) {
+    const int64_t D = sec->dim();
+    hv_prepare(ctx, model, sec);
+    const size_t vbytes = sizeof(double2) * (size_t)(n + 1) * D;
+    ensure_device_fits(vbytes, "Lanczos basis");
+    double2* V = static_cast<double2*>(workspace(ctx, "lt_V", vbytes));
+    double* a = static_cast<double*>(workspace(ctx, "lt_a", sizeof(double) * (n + 2)));
+    double* b = static_cast<double*>(workspace(ctx, "lt_b", sizeof(double) * (n + 2)));
+    double* s = static_cast<double*>(workspace(ctx, "lt_s", sizeof(double) * (n + 2)));
+    const int NB = red_blocks(D);
+    const int HB = hv_lanczos_blocks(ctx, sec);
+    double* part = static_cast<double*>(workspace(ctx, "lt_part", sizeof(double) * (NB > HB ? NB : HB)));
+    double* part_big = static_cast<double*>(workspace(ctx, "lt_partbig", sizeof(double) * (size_t)NB * 2 * (n + 2)));
+    double2* hvec = static_cast<double2*>(workspace(ctx, "lt_hvec", sizeof(double2) * (n + 2)));
+    Slots sl{V, 0, V + D, D, 0};
+    KGF_HIP(hipMemcpyAsync(V, i0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_norm2, dim3(NB, 1), dim3(kThreads), 0, ctx->stream, V, D, D, part);
+    check_launch("k_norm2");
+    double2* n2dev = static_cast<double2*>(workspace(ctx, "lt_n2", sizeof(double2)));
+    hipLaunchKernelGGL(k_gs_fin, dim3(1), dim3(kThreads), 0, ctx->stream, (int)FIN_INIT, 0, part, NB, a, b, s);
+    check_launch("k_gs_fin");
+    block_dots(ctx, V, D, 1, V, D, 1, D, n2dev);
+    for (int k = 0; k < n; ++k) {
+        LanczosHvArgs ha;
+        ha.x = sl.at(k, 0);
+        ha.x_col = 0;
+        ha.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
+        ha.xp_col = 0;
+        ha.y = sl.at(k + 1, 0);
+        ha.y_col = 0;
+        ha.s_k = s + k;
+        ha.b_k = b + k;
+        ha.s_km1 = s + (k > 0 ? k - 1 : 0);
+        ha.stride = 0;
+        ha.part = part;
+        hv_lanczos(ctx, model, sec, 1, ha);
+        hipLaunchKernelGGL(k_gs_fin, dim3(1), dim3(kThreads), 0, ctx->stream, (int)FIN_A, k, part, HB, a, b, s);
+        check_launch("k_gs_fin");
+        if (k == n - 1) break;
+        hipLaunchKernelGGL(k_update, dim3(NB, 1), dim3(kThreads), 0, ctx->stream, sl, k, a + k, s + k, 0, D, part);
+        check_launch("k_update");
+        if (reorth > 0) reorthogonalise(ctx, sl, k + 1, k + 1, 1, D, reorth, nullptr, s, part, part_big, hvec);
+        hipLaunchKernelGGL(k_gs_fin, dim3(1), dim3(kThreads), 0, ctx->stream, (int)FIN_B, k, part, NB, a, b, s);
+        check_launch("k_gs_fin");
+    }
+    std::vector<double> ha(n + 2), hb(n + 2), hs(n + 2);
+    double2 n2;
+    KGF_HIP(hipMemcpyAsync(ha.data(), a, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(hb.data(), b, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(hs.data(), s, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, ctx->stream));
+    KGF_HIP(hipMemcpyAsync(&n2, n2dev, sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    int taken = 0;
+    while (taken < n && hs[taken] != 0.0) ++taken;   // s_k = 0 once the space is exhausted
+    for (int k = 0; k < n; ++k) {
+        a_host[k] = k < taken ? ha[k] : 0.0;
+        b_host[k] = (k >= 1 && k < taken) ? hb[k] : 0.0;
+    }
+    *norm2_host = n2.x;
+    for (const char* nm : {"lt_V", "lt_partbig"}) ctx->ws.erase(nm);
+    return taken;
+}
+
 // Ground state of H in the sector.  When the Lanczos basis of max_iter + 1
 // vectors does not fit in device memory (large sectors), the recursion is
 // restarted from the current Ritz vector every `cap` vectors (explicit
