@@ -50,10 +50,11 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
-    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16"], default="ladder14",
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1"], default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
-                        "short mesh")
+                        "short mesh; fig1: the equilibrium spectral density of the L=10 ring (Sec. 3) for "
+                        "several restart counts against the conventional Lanczos G")
     p.add_argument("--grad-instances", type=int, default=5,
                    help="batch64: instances (one per L first) whose per-instance adjoint gradient is timed")
     p.add_argument("--no-batched-adjoint", action="store_true",
@@ -311,6 +312,62 @@ def ladder16(a):
     print(json.dumps(res), flush=True)
 
 
+def fig1(a):
+    """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
+    half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
+    grid 0.01, Krylov dimension 64, from the time-dependent Lanczos G(t) with
+    f = 1000, 100 and 1 restarts and a damped transform, and the conventional
+    Lanczos G^(L)(w) of the same dimension (Eq. (gapprox)); f = 1 should
+    reproduce the conventional result (Eq. (res))."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    ctx = kgf.Context(0)
+    model = wl.ring(10, 1.0, 8.0)
+    m = ctx.model(model)
+    s = ctx.sector(10, 5, 5)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, 7)).to("cuda:0")
+    E0, psi0, info = ctx.ground_state(m, s, v0, tol=1e-13, max_iter=600)
+    tmax, dtf, eta, krylov = 1000.0, 0.01, 0.01, 64
+    om = np.linspace(-6.0, 14.0, 8001)
+    A, times = {}, {}
+    for f in (1000, 100, 1):
+        dt = tmax / f
+        nfine = int(round(dt / dtf))
+        t0 = time.perf_counter()
+        gg = ctx.greens_eq_fine(m, s, psi0, E0, (0, 0), 1, f, nfine, dt, krylov_dim=krylov, reorth=2)
+        gl = ctx.greens_eq_fine(m, s, psi0, E0, (0, 0), 0, f, nfine, dt, krylov_dim=krylov, reorth=2)
+        Gw = ctx.fourier(gg - gl, dtf, eta, om)
+        torch.cuda.synchronize()
+        times[f] = round(time.perf_counter() - t0, 2)
+        A[f] = -Gw.imag / np.pi
+        log(f"f={f}: {times[f]} s")
+    t0 = time.perf_counter()
+    conv = ctx.greens_omega(m, s, psi0, E0, (0, 0), krylov, om, eta, reorth=2)
+    times["conventional"] = round(time.perf_counter() - t0, 2)
+    Ac = -(conv["G_greater"] + conv["G_lesser"]).imag / np.pi
+    conv100 = ctx.greens_omega(m, s, psi0, E0, (0, 0), 100, om, eta, reorth=2)
+    A["conv100"] = -(conv100["G_greater"] + conv100["G_lesser"]).imag / np.pi
+    ref = A[1000]
+    sc = np.abs(ref).max()
+    # the bipartite ring is particle-hole symmetric about w = U/2: bins of
+    # w' = w - U/2 >= 0 across the upper Hubbard band
+    wp = om - 4.0
+    wins = {f"{lo}<=w'<{lo + 1}": (wp >= lo) & (wp < lo + 1) for lo in range(0, 9)}
+    dev = {(f"f={f}" if f != "conv100" else "conventional n=100"): {k: round(float(np.abs(A[f][w] - ref[w]).max() / sc), 6) for k, w in wins.items()}
+           for f in (100, 1, "conv100")}
+    res = {"metric": "Sec. 3 spectral density, L=10 ring U=8 (time-dependent vs conventional Lanczos)",
+           "E0": E0, "gs_iters": info["iters"], "times_s": {str(k): v for k, v in times.items()},
+           "deviation_from_f1000_rel_max": dev,
+           "min_A": {f"f={f}": float(A[f].min()) for f in (1000, 100, 1)},
+           "f1_vs_conventional_rel_max": float(np.abs(A[1] - Ac).max() / np.abs(Ac).max()),
+           "sum_rule_f1000": float(np.trapezoid(ref, om) if hasattr(np, "trapezoid") else np.trapz(ref, om)),
+           "config": {"workload": "ring10 U=8 half filling, eta=0.01, t_max=1000, fine dt=0.01, Krylov dim 64",
+                      "omega": [float(om[0]), float(om[-1]), len(om)]}}
+    print(json.dumps(res), flush=True)
+
+
 def measured_traffic():
     """HBM bytes per algorithmic byte of the dominant kernel from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each
@@ -362,6 +419,9 @@ def main():
         return
     if a.workload == "ladder16":
         ladder16(a)
+        return
+    if a.workload == "fig1":
+        fig1(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "
