@@ -50,10 +50,11 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
-    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1"], default="ladder14",
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3"], default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
-                        "short mesh; fig1: the equilibrium spectral density of the L=10 ring (Sec. 3) for "
+                        "short mesh; hub4x3: equilibrium G of the 4x3 cluster, 24 columns batched vs one at a "
+                        "time; fig1: the equilibrium spectral density of the L=10 ring (Sec. 3) for "
                         "several restart counts against the conventional Lanczos G")
     p.add_argument("--grad-instances", type=int, default=5,
                    help="batch64: instances (one per L first) whose per-instance adjoint gradient is timed")
@@ -312,6 +313,43 @@ def ladder16(a):
     print(json.dumps(res), flush=True)
 
 
+def hub4x3(a):
+    """Equilibrium G_ij(t) of the half-filled 4x3 cluster (t' = -0.3, U = 8,
+    D = 853,776): 12 c_i^+ vectors in (7,6) and 12 c_i vectors in (5,6), 400
+    SIL steps of dt = 0.025, Krylov dim 15, all 12 x 12 dots per step.
+    Timed with the columns of each sector in one block (batched) and one
+    column at a time (plain); both give the same G."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    q = wl.hub4x3()
+    ctx = kgf.Context(0)
+    m = ctx.model(q.H)
+    s = ctx.sector(q.H.L, q.n_up, q.n_dn)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, 7)).to("cuda:0")
+    E0, psi0, info = ctx.ground_state(m, s, v0, tol=1e-12, max_iter=400)
+    log(f"hub4x3 ground state E0={E0} ({info['iters']} iterations)")
+    res, G = {}, {}
+    for name, batch in (("batched", 0), ("plain", 1)):
+        ctx.greens_eq(m, s, psi0, E0, q.orbitals, 3, 1, q.dt_grid, krylov_dim=q.krylov_dim, batch=batch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G[name] = ctx.greens_eq(m, s, psi0, E0, q.orbitals, q.nt, q.steps_per_grid, q.dt_grid,
+                                krylov_dim=q.krylov_dim, batch=batch)
+        el = time.perf_counter() - t0
+        vsteps = 2 * len(q.orbitals) * (q.nt - 1) * q.steps_per_grid
+        res[name] = {"s": round(el, 3), "vector_steps_per_s": round(vsteps / el, 1)}
+        log(f"hub4x3 {name}: {el:.2f} s")
+    dG = max(float(np.abs(G["batched"][i] - G["plain"][i]).max()) for i in range(2))
+    out = {"metric": "equilibrium G of the 4x3 cluster, 24 columns, batched vs plain", "D": s.dim,
+           "vector_steps": 2 * len(q.orbitals) * (q.nt - 1) * q.steps_per_grid, **res,
+           "batched_over_plain": round(res["plain"]["s"] / res["batched"]["s"], 2),
+           "max_abs_diff_batched_plain": dG,
+           "anticommutator_err": float(np.abs(np.diagonal(G["batched"][0][0] - G["batched"][1][0]) + 1j).max())}
+    print(json.dumps(out), flush=True)
+
+
 def fig1(a):
     """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
     half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
@@ -422,6 +460,9 @@ def main():
         return
     if a.workload == "fig1":
         fig1(a)
+        return
+    if a.workload == "hub4x3":
+        hub4x3(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "

@@ -454,7 +454,7 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
     return guarded([&] {
         KGF_REQUIRE(ctx, KGF_EINVAL, "kgf_set_option: ctx is NULL");
         if (option == KGF_OPT_HV_PASSES) {
-            KGF_REQUIRE(value >= 0 && value <= 3, KGF_EINVAL, "kgf_set_option: HV_PASSES must be 0..3");
+            KGF_REQUIRE(value >= 0 && value <= 4, KGF_EINVAL, "kgf_set_option: HV_PASSES must be 0..4");
             ctx->hv_passes = value;
         } else if (option == KGF_OPT_HV_STRIP) {
             KGF_REQUIRE(value == 0 || value == 8 || value == 16 || value == 32 || value == 64, KGF_EINVAL,

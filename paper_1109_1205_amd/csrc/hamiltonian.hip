@@ -823,10 +823,13 @@ __global__ void k_dH_fin(const double* __restrict__ part, int64_t nrow, int nthe
 //   passes 0: single pass without LDS staging (anything larger).
 // kgf_set_option can force a variant where the row fits (results agree to
 // rounding): ctx->hv_passes 1 = single pass, 2 = two passes, 3 = two passes
-// with split rows; ctx->hv_strip = strip width of pass 2 (8, 16, 32, 64).
+// with split rows, 4 = two passes with one row per pass-1 block (two blocks
+// per CU instead of two rows sharing the hop-table loads);
+// ctx->hv_strip = strip width of pass 2 (8, 16, 32, 64).
 struct HvPlan {
     int passes = 0;
     bool split = false;
+    int nr = 2;   // rows per pass-1 block when whole rows are staged
     int C = 8;
     int nstrip = 0, ntile = 0;
     int64_t up_blocks = 0;
@@ -846,6 +849,7 @@ HvPlan make_plan(const kgf_sector* sec, int ov, int strip) {
     else p.passes = 0;
     if (p.passes == 2) {
         p.split = !fits1 || (ov == 3 && fits_split);
+        p.nr = ov == 4 ? 1 : 2;
         p.C = 8;
         for (int c : {64, 32, 16})
             if ((size_t)Dup * c * sizeof(double2) <= kStripL2Bytes) {
@@ -926,7 +930,7 @@ void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int 
             auto rows = uu ? k_hv_rows<true, true, 1> : k_hv_rows<true, false, 1>;
             opt_in_lds(ctx, (const void*)rows, 4 + (uu ? 1 : 0), kSplitLdsMax);
             hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
-        } else if (2 * lds <= kSplitLdsMax) {
+        } else if (P.nr == 2 && 2 * lds <= kSplitLdsMax) {
             auto rows = uu ? k_hv_rows<false, true, 2> : k_hv_rows<false, false, 2>;
             opt_in_lds(ctx, (const void*)rows, 8 + (uu ? 1 : 0), kSplitLdsMax);
             dim3 rg2((unsigned)((sec->d_up + 1) / 2), (unsigned)ncol);
@@ -968,12 +972,13 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         // candidate requests, one per distinct plan
         std::vector<std::pair<int, int>> cand;
         std::vector<HvPlan> plans;
-        const std::pair<int, int> reqs[] = {{1, 0}, {2, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}};
+        const std::pair<int, int> reqs[] = {{1, 0}, {2, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}, {4, 0}, {4, 16}, {4, 32}};
         for (const auto& rq : reqs) {
             const HvPlan P = make_plan(sec, rq.first, rq.second);
             if (P.passes == 0) continue;
             bool dup = false;
-            for (const auto& q : plans) dup = dup || (q.passes == P.passes && q.split == P.split && q.C == P.C);
+            for (const auto& q : plans)
+                dup = dup || (q.passes == P.passes && q.split == P.split && q.C == P.C && (P.split || q.nr == P.nr));
             if (!dup) {
                 plans.push_back(P);
                 cand.push_back(rq);

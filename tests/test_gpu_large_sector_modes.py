@@ -44,7 +44,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("passes,strip", [(2, 0), (3, 0), (2, 8), (3, 16), (2, 32), (3, 64)])
+@pytest.mark.parametrize("passes,strip", [(2, 0), (3, 0), (2, 8), (3, 16), (2, 32), (3, 64), (4, 0), (4, 16)])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_apply_h_variants(ctx, case, passes, strip):
     name, mk, nu, nd, nvec = case
@@ -64,7 +64,7 @@ def test_apply_h_variants(ctx, case, passes, strip):
     assert rel_err(got, ref) < 1e-13
 
 
-@pytest.mark.parametrize("passes", [2, 3])
+@pytest.mark.parametrize("passes", [2, 3, 4])
 def test_ground_state_and_sil_through_two_pass(ctx, passes):
     say("Lanczos two-pass", passes)
     model = wl.siam10().H_ini
