@@ -60,6 +60,9 @@ typedef struct kgf_sector kgf_sector;
  * `hip_stream` (a hipStream_t, borrowed, may be NULL for the null stream).
  * All kernels of calls on this context are launched on that stream. */
 int  kgf_create(kgf_ctx** out, int hip_device, void* hip_stream);
+/* kgf_destroy frees the context's workspaces.  Models and sectors created on
+ * it must be destroyed first (their destroy synchronises on the context's
+ * stream); handles still alive afterwards must not be passed to any call. */
 void kgf_destroy(kgf_ctx* ctx);
 int  kgf_set_stream(kgf_ctx* ctx, void* hip_stream);
 const char* kgf_last_error(void);

@@ -183,8 +183,13 @@ class Model:
                    spec.eps_up, spec.eps_dn, spec.U)
 
     def close(self):
+        # The native destroy synchronises on the context's stream, so it must
+        # run while the context exists; at interpreter shutdown (or when a
+        # traceback keeps handles in a reference cycle) finalisers may run in
+        # any order, and a handle whose context is gone is left to the process.
         if getattr(self, "handle", None):
-            _lib.kgf_model_destroy(self.handle)
+            if getattr(self.ctx, "handle", None):
+                _lib.kgf_model_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -226,8 +231,10 @@ class Sector:
         return out
 
     def close(self):
+        # see Model.close: only while the context exists
         if getattr(self, "handle", None):
-            _lib.kgf_sector_destroy(self.handle)
+            if getattr(self.ctx, "handle", None):
+                _lib.kgf_sector_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

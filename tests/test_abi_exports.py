@@ -35,3 +35,27 @@ def test_library_exports_every_declared_symbol():
 def test_binding_signatures_cover_header():
     from paper_1109_1205_amd import _lib
     assert set(_lib.exported_symbols()) == set(declared_functions())
+
+
+def test_handles_skip_native_destroy_once_their_context_is_closed(monkeypatch):
+    """Model and sector destroys synchronise on their context's stream, so
+    the binding calls them only while the context exists (finalisers of a
+    reference cycle run in any order at interpreter shutdown)."""
+    import ctypes
+    from types import SimpleNamespace
+    from paper_1109_1205_amd import _lib as L
+    calls = []
+    stub = SimpleNamespace(kgf_model_destroy=lambda h: calls.append(("model", h.value)),
+                           kgf_sector_destroy=lambda h: calls.append(("sector", h.value)))
+    monkeypatch.setattr(L, "_lib", stub)
+    live = SimpleNamespace(handle=ctypes.c_void_p(0x10))
+    gone = SimpleNamespace(handle=None)
+    for cls, kind in ((L.Model, "model"), (L.Sector, "sector")):
+        for ctx, expect in ((live, [(kind, 0x20)]), (gone, [])):
+            calls.clear()
+            obj = object.__new__(cls)
+            obj.ctx, obj.handle = ctx, ctypes.c_void_p(0x20)
+            obj.close()
+            assert calls == expect and obj.handle is None
+            obj.close()                      # idempotent
+            assert calls == expect

@@ -232,3 +232,50 @@ def test_paper_total_polarisation(key):
     k = c.get("moments_alternate_near_impurity", 0)
     for i in range(k - 1):
         assert m[i] * m[i + 1] < 0
+
+
+def _moments(sec, L, psi):
+    """m_i = <n_i,up> - <n_i,dn> of a sector vector (row-major D_up x D_dn)."""
+    p = np.abs(psi.reshape(sec.d_up, sec.d_dn)) ** 2
+    bu = hamiltonian.occupation_bits(sec.up, L)
+    bd = hamiltonian.occupation_bits(sec.dn, L)
+    return (p.sum(1)[:, None] * bu).sum(0) - (p.sum(0)[:, None] * bd).sum(0)
+
+
+def test_paper_fig4_dynamics():
+    """The time dependence the paper states for the isolated L_c = 8 cluster
+    after the field is switched off, with the oracle's SIL propagation
+    (which equals -i G^<_ii(t,t) of the four-step; tested elsewhere)."""
+    from oracle import lanczos, propagate
+    spec = json.load(open(GOLDEN))["fig4_dynamics"]
+    H, H_ini = _paper_model(spec)
+    nu, nd = spec["sector"]
+    L = H.L
+    sec = basis.Sector(L, nu, nd)
+    Hi, Hf = hamiltonian.Hamiltonian(H_ini, sec), hamiltonian.Hamiltonian(H, sec)
+    gs = lanczos.ground_state(Hi.apply, wl.start_vector(sec.dim, 7), tol=1e-13, max_iter=400)
+    psi = gs.psi.astype(complex)
+    ms = [_moments(sec, L, psi)]
+    for _ in range(110):   # t = 0.1 k, k <= 110
+        psi = propagate.propagate(Hf.apply, psi, 0.1, 1, 15, -1, 0.0, "cgs2")
+        ms.append(_moments(sec, L, psi))
+    ms = np.array(ms)
+    t = 0.1 * np.arange(len(ms))
+    c = spec["claims"]
+    assert np.abs(ms.sum(1)).max() < 1e-12
+    assert ms[t <= c["impurity_half_decay_before"] + 1e-9, 0].min() < 0.5 * ms[0, 0]
+    win = (t >= 1.0) & (t <= 11.0 + 1e-9)
+    k = np.argmax(np.where(win, ms[:, 0], -np.inf))
+    assert c["revival_window"][0] <= t[k] <= c["revival_window"][1] and ms[k, 0] > 0.5 * ms[0, 0]
+    e = c["edge_maximum"]
+    assert np.argmax(ms[int(round(e["t"] / 0.1))]) + 1 == e["site"]
+    # one Krylov space over the whole interval (Eq. (udelta) with dt = t)
+    sk = c["single_krylov_space"]
+    dev = []
+    for n in sk["dims"]:
+        d = 0.0
+        for kk in range(5, 101, 5):
+            p = propagate.sil_step(Hf.apply, gs.psi.astype(complex), 0.1 * kk, n, -1, 0.0, "cgs2")
+            d = max(d, float(np.abs(_moments(sec, L, p) - ms[kk]).max()))
+        dev.append(d)
+    assert all(dev[i + 1] < dev[i] for i in range(len(dev) - 1)) and dev[-1] < sk["converged_tol"]
