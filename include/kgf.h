@@ -153,7 +153,7 @@ int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* se
 /* ---- short-iterative-Lanczos propagation (Sec. 3, Eqs. (newstate), (udelta))
  * Each of nvec vectors psi[c] (at psi + c*ld) is advanced nsteps times by
  *   direction -1: exp(-i H dt);  +1: exp(+i H dt);  0: exp(-(H - shift) dt)
- * using a Krylov space of dimension krylov_dim (<= 64) rebuilt at every
+ * using a Krylov space of dimension krylov_dim (<= 128) rebuilt at every
  * step (restart), T diagonalised by implicit QL in one wavefront.  The
  * vectors of a batch run independent recursions (own a_k, b_k, T).
  * reorth: 0 none, 1 classical GS, 2 classical GS twice.  A recursion

@@ -138,7 +138,7 @@ namespace kgf {
 void check_prop_opts(const kgf_prop_opts* o) {
     KGF_REQUIRE(o, KGF_EINVAL, "propagation options are NULL");
     KGF_REQUIRE(o->krylov_dim >= 1 && o->krylov_dim <= kMaxKrylov, KGF_EUNSUPPORTED,
-                "krylov_dim must be in 1..64");
+                "krylov_dim must be in 1..128");
     KGF_REQUIRE(o->reorth >= 0 && o->reorth <= 2, KGF_EINVAL, "reorth must be 0, 1 or 2");
     KGF_REQUIRE(o->direction >= -1 && o->direction <= 1, KGF_EINVAL, "direction must be -1, 0 or 1");
     KGF_REQUIRE(std::isfinite(o->dt) && std::isfinite(o->shift) && std::isfinite(o->breakdown_tol) &&

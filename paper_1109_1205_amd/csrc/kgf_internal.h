@@ -38,7 +38,7 @@ struct Error {
 
 constexpr int kMaxL = 24;          // masks are uint32; column ranks need 24 bits
 constexpr int kMaxBonds = 127;     // bond index stored in 7 bits
-constexpr int kMaxKrylov = 64;     // SIL Krylov dimension (one wavefront)
+constexpr int kMaxKrylov = 128;    // SIL Krylov dimension (one or two wavefronts per tridiagonal matrix)
 constexpr int kBinomN = 33;        // binomial table C[n][k], n,k < 33
 constexpr int kThreads = 256;      // threads per block of the streaming kernels
 

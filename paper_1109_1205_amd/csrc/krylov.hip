@@ -22,14 +22,14 @@ namespace kgf {
 namespace {
 
 // per-column scalar block (doubles)
-constexpr int kOffA = 0;                   // a[0..63]
-constexpr int kOffB = 64;                  // b[0..64]
-constexpr int kOffS = 130;                 // s[0..64]
-constexpr int kOffBeta0 = 196;
-constexpr int kOffSmax = 197;
-constexpr int kOffCoef = 200;              // complex coef[0..64] (re, im)
-constexpr int kOffH = 332;                 // complex reorth coefficients [0..64]
-constexpr int kScalStride = 464;
+constexpr int kOffA = 0;                   // a[0..127]
+constexpr int kOffB = 128;                 // b[0..128]
+constexpr int kOffS = 258;                 // s[0..128]
+constexpr int kOffBeta0 = 388;
+constexpr int kOffSmax = 389;
+constexpr int kOffCoef = 390;              // complex coef[0..128] (re, im)
+constexpr int kScalStride = 648;
+static_assert(kMaxKrylov <= 128 && kOffCoef % 2 == 0 && kScalStride % 2 == 0, "per-column scalar layout");
 
 constexpr int kDotChunk = 8;               // vectors per multi-dot chunk
 
@@ -311,12 +311,14 @@ __global__ void k_fin_h(const double* __restrict__ part, int nj, int nper, doubl
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal eigen-decomposition and exponential, one wavefront per column
+// tridiagonal eigen-decomposition and exponential, one block per column:
+// one wavefront (NT = 64) for m <= 64, two (NT = 128) up to kMaxKrylov
 // ---------------------------------------------------------------------------
 // Implicit QL iteration with Wilkinson shifts for the symmetric tridiagonal
-// T (diagonal a_0..a_{m-1}, off-diagonal b_1..b_{m-1}).  Lane 0 chases the
-// bulge and records the plane rotations of a sweep; every lane then applies
-// them to its own row of the eigenvector matrix Q held in LDS.  Finally
+// T (diagonal a_0..a_{m-1}, off-diagonal b_1..b_{m-1}).  Thread 0 chases the
+// bulge and records the plane rotations of a sweep; every thread then applies
+// them to its own row of the eigenvector matrix Q held in LDS (dynamic,
+// m x (m+1) doubles).  Finally
 //   coef_k = beta0 * sum_j Q[k][j] f(lambda_j) Q[0][j] * s_k,
 // f = exp(-i lambda dt), exp(+i lambda dt) or exp(-(lambda - shift) dt).
 // Up to kMaxReq coefficient requests per launch: request r evaluates column
@@ -330,13 +332,17 @@ struct CoefReq {
     double t[kMaxReq];
 };
 
-__global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ scal, int m, CoefReq req,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tridiag_exp(const double* __restrict__ scal, int m, CoefReq req,
                                                     double shift, double2* __restrict__ coef_out,
                                                     int coef_stride) {
-    __shared__ double Q[kMaxKrylov][kMaxKrylov + 1];
+    extern __shared__ double Qd[];   // Q[i][j] = Qd[i * (m + 1) + j]
     __shared__ double d[kMaxKrylov], e[kMaxKrylov];
     __shared__ double rc[kMaxKrylov], rs[kMaxKrylov];
+    __shared__ double xr[NT > 64 ? NT : 1], xi[NT > 64 ? NT : 1];   // neighbour exchange (NT > 64)
+    __shared__ double s_red[2][2];
     __shared__ int s_mm, s_lo;
+    const int ld = m + 1;
     const int r = blockIdx.x;
     const int c = req.col[r];
     const double dt = req.t[r];
@@ -363,6 +369,15 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ s
             glo = fmin(glo, __shfl_xor(glo, off, 64));
             ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
         }
+        if (NT > 64) {
+            if ((lane & 63) == 0) {
+                s_red[lane >> 6][0] = glo;
+                s_red[lane >> 6][1] = ghi;
+            }
+            __syncthreads();
+            glo = fmin(s_red[0][0], s_red[1][0]);
+            ghi = fmax(s_red[0][1], s_red[1][1]);
+        }
         const double sigma = 0.5 * (glo + ghi);
         const double x = 0.5 * (ghi - glo) * fabs(dt);
         if (x <= 64.0) {
@@ -385,8 +400,22 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ s
             for (int sub = 0; sub < n_sub; ++sub) {
                 double vr = cr, vi = ci;                     // running term
                 for (int k = 1; k <= K; ++k) {
-                    const double pr = __shfl_up(vr, 1, 64), pi = __shfl_up(vi, 1, 64);
-                    const double nr = __shfl_down(vr, 1, 64), ni = __shfl_down(vi, 1, 64);
+                    double pr, pi, nr, ni;
+                    if (NT == 64) {
+                        pr = __shfl_up(vr, 1, 64);
+                        pi = __shfl_up(vi, 1, 64);
+                        nr = __shfl_down(vr, 1, 64);
+                        ni = __shfl_down(vi, 1, 64);
+                    } else {
+                        xr[lane] = vr;
+                        xi[lane] = vi;
+                        __syncthreads();
+                        pr = lane >= 1 ? xr[lane - 1] : 0.0;
+                        pi = lane >= 1 ? xi[lane - 1] : 0.0;
+                        nr = lane + 1 < NT ? xr[lane + 1] : 0.0;
+                        ni = lane + 1 < NT ? xi[lane + 1] : 0.0;
+                        __syncthreads();
+                    }
                     const double wr = ar * vr + (lane >= 1 ? br * pr : 0.0) + (lane + 1 < m ? bn * nr : 0.0);
                     const double wi = ar * vi + (lane >= 1 ? br * pi : 0.0) + (lane + 1 < m ? bn * ni : 0.0);
                     const double f = h / (double)k;
@@ -427,7 +456,7 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ s
     if (lane < m) {
         d[lane] = sc[kOffA + lane];
         e[lane] = lane + 1 < m ? sc[kOffB + lane + 1] : 0.0;
-        for (int j = 0; j < m; ++j) Q[lane][j] = (j == lane) ? 1.0 : 0.0;
+        for (int j = 0; j < m; ++j) Qd[lane * ld + j] = (j == lane) ? 1.0 : 0.0;
     }
     __syncthreads();
 
@@ -482,11 +511,12 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ s
             const int mm = s_mm;
             if (mm == l) break;
             if (lane < m) {
+                double* Qr = Qd + lane * ld;
                 for (int i = mm - 1; i >= s_lo; --i) {
-                    const double f = Q[lane][i + 1];
-                    const double q = Q[lane][i];
-                    Q[lane][i + 1] = rs[i] * q + rc[i] * f;
-                    Q[lane][i] = rc[i] * q - rs[i] * f;
+                    const double f = Qr[i + 1];
+                    const double q = Qr[i];
+                    Qr[i + 1] = rs[i] * q + rc[i] * f;
+                    Qr[i] = rc[i] * q - rs[i] * f;
                 }
             }
             __syncthreads();
@@ -506,7 +536,7 @@ __global__ __launch_bounds__(64) void k_tridiag_exp(const double* __restrict__ s
                 fr = cs;
                 fi = direction < 0 ? -sn : sn;
             }
-            const double w = Q[lane][j] * Q[0][j];
+            const double w = Qd[lane * ld + j] * Qd[j];
             re = fma(w, fr, re);
             im = fma(w, fi, im);
         }
@@ -885,8 +915,21 @@ void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, c
             q.dir[r] = dir[r0 + r];
         }
         Prof pr(ctx, "tridiag_exp");
-        hipLaunchKernelGGL(k_tridiag_exp, dim3(q.n), dim3(64), 0, ctx->stream, scal, m, q, shift,
-                           coef + (int64_t)r0 * coef_stride, coef_stride);
+        const size_t lds = sizeof(double) * (size_t)m * (m + 1);
+        if (m <= 64) {
+            hipLaunchKernelGGL(k_tridiag_exp<64>, dim3(q.n), dim3(64), lds, ctx->stream, scal, m, q, shift,
+                               coef + (int64_t)r0 * coef_stride, coef_stride);
+        } else {
+            static bool opted[64] = {};
+            if (!opted[ctx->device & 63]) {
+                KGF_HIP(hipFuncSetAttribute((const void*)k_tridiag_exp<128>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(sizeof(double) * kMaxKrylov * (kMaxKrylov + 1))));
+                opted[ctx->device & 63] = true;
+            }
+            hipLaunchKernelGGL(k_tridiag_exp<128>, dim3(q.n), dim3(128), lds, ctx->stream, scal, m, q, shift,
+                               coef + (int64_t)r0 * coef_stride, coef_stride);
+        }
         check_launch("k_tridiag_exp");
     }
 }

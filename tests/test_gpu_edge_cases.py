@@ -63,8 +63,8 @@ def test_invalid_inputs_are_reported(kctx):
         ctx.greens_neq(m5, m5, s4, v, orbitals=[(0, 0)], nt=2, steps_per_grid=1, dt=0.1)
     with pytest.raises(RuntimeError):             # orbital outside the cluster
         ctx.greens_neq(m4, m4, s4, v, orbitals=[(7, 0)], nt=2, steps_per_grid=1, dt=0.1)
-    with pytest.raises(RuntimeError):             # Krylov dimension beyond the supported 64
-        ctx.propagate(m4, s4, v.reshape(1, -1).clone(), 1, 0.1, 80, -1)
+    with pytest.raises(RuntimeError):             # Krylov dimension beyond the supported 128
+        ctx.propagate(m4, s4, v.reshape(1, -1).clone(), 1, 0.1, 129, -1)
     with pytest.raises(RuntimeError):
         ctx.greens_neq_multi([m4, m5], [m4, m5], [s4, s4], [v, v], [(0, 0)], 2, 1, 0.1)
     with pytest.raises(ValueError):               # wrong vector length (binding check)
