@@ -72,6 +72,9 @@ def parse():
                    help="comma-separated kgf_set_option HV_PASSES values (9: the library's tuner chooses)")
     p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
     p.add_argument("--hv-reps", type=int, default=10)
+    p.add_argument("--tune", action="store_true",
+                   help="batch64 / ladder16: let the library time the equivalent H.v variants per sector "
+                        "(kgf_set_option HV_TUNE) and keep the fastest")
     return p.parse_args()
 
 
@@ -156,6 +159,8 @@ def batch64(a):
     import workloads as wl
     qs = wl.batch_instances()
     ctx = kgf.Context(0)
+    if a.tune:
+        ctx.set_option(ctx.HV_TUNE, 1)
     last = [time.perf_counter()]
 
     def report(phase, done, total):
@@ -281,6 +286,8 @@ def ladder16(a):
     import workloads as wl
     q = wl.ladder16()
     ctx = kgf.Context(0)
+    if a.tune:
+        ctx.set_option(ctx.HV_TUNE, 1)
     last = [time.perf_counter()]
 
     def report(phase, done, total):

@@ -150,6 +150,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+    const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(double2* p, double2 a) {
+    dbl2v v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<dbl2v*>(p));
+}
+
 // MODE 0: y = H x.
 // MODE 1: y = s * H x - bp * xp, part = Re <s x, y>   (one Lanczos step)
 template <int MODE, bool UNIFORM_U>
@@ -246,7 +259,9 @@ __global__ __launch_bounds__(kThreads) void k_hv(HvTables T, const double2* __re
 
 // Row-in-LDS variant: the block stages its input row x[u, :] in LDS, so the
 // down-spin gathers (random inside the row) are served by LDS; only the
-// up-spin row reads go to the memory hierarchy.  Blocks are mapped to the
+// up-spin row reads go to the memory hierarchy.  The single-use streams (y
+// written, x_{k-1} read) are nontemporal, so that they do not push the source
+// vector, whose rows the up-spin hops re-read, out of the caches.  Blocks are mapped to the
 // 8 XCDs so that each XCD walks a contiguous range of rows (block b runs on
 // XCD b mod 8): most up-spin hops connect rows less than a few hundred
 // apart, so their source rows stay in that XCD's L2.
@@ -350,14 +365,14 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_
             out.x = sc * ar;
             out.y = sc * ai;
             if (bp != 0.0) {
-                const double2 p = (XP + c * xp_col)[u * Ddn + d];
+                const double2 p = ld_stream(XP + c * xp_col + u * Ddn + d);
                 out.x = fma(-bp, p.x, out.x);
                 out.y = fma(-bp, p.y, out.y);
             }
             dot = fma(sc * xv.x, out.x, dot);
             dot = fma(sc * xv.y, out.y, dot);
         }
-        y[u * Ddn + d] = out;
+        st_stream(y + u * Ddn + d, out);
     }
     if (MODE == 1) {
         double s = block_sum(dot, s_red);
@@ -512,19 +527,6 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
         const int64_t d = tid + (int64_t)j * kHvThreads;
         if (d < Ddn) yrow[d] = make_double2(are[j], gather(d, xim[j]));
     }
-}
-
-typedef double dbl2v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ double2 ld_stream(const double2* p) {
-    const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(p));
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ void st_stream(double2* p, double2 a) {
-    dbl2v v;
-    v.x = a.x;
-    v.y = a.y;
-    __builtin_nontemporal_store(v, reinterpret_cast<dbl2v*>(p));
 }
 
 constexpr int kUpThreads = 256;
