@@ -91,6 +91,13 @@ __global__ __launch_bounds__(kThreads) void k_norm2(const double2* __restrict__ 
 }
 
 // y_c -= a_k s_k x_c ; part = ||y_c||^2   (a_k, s_k at fa/fs + c * stride)
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+// nontemporal load of a value read once (does not displace reused data)
+__device__ __forceinline__ double2 ld_once(const double2* p) {
+    const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(p));
+    return make_double2(v.x, v.y);
+}
+
 __global__ __launch_bounds__(kThreads) void k_update(Slots sl, int k, const double* __restrict__ fa,
                                                      const double* __restrict__ fs, int stride,
                                                      int64_t D, double* __restrict__ part) {
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Slots sl, int k, const doub
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double2 z = x[i], w = y[i];
+        double2 z = ld_once(x + i), w = y[i];
         w.x = fma(-f, z.x, w.x);
         w.y = fma(-f, z.y, w.y);
         y[i] = w;
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(Slots sl, int n, const dou
          i += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
         for (int j = 0; j < n; ++j) {
-            const double2 z = sl.at(j, c)[i];
+            const double2 z = ld_once(sl.at(j, c) + i);
             const double2 h = sc[j];
             re = fma(h.x, z.x, fma(-h.y, z.y, re));
             im = fma(h.x, z.y, fma(h.y, z.x, im));
