@@ -73,7 +73,7 @@ def parse():
     p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
     p.add_argument("--hv-reps", type=int, default=10)
     p.add_argument("--tune", action="store_true",
-                   help="batch64 / ladder16: let the library time the equivalent H.v variants per sector "
+                   help="let the library time the equivalent H.v variants per sector "
                         "(kgf_set_option HV_TUNE) and keep the fastest")
     return p.parse_args()
 
@@ -134,6 +134,8 @@ def probe(a):
     import workloads as wl
     q = wl.ladder14()
     ctx = kgf.Context(0)
+    if a.tune:
+        ctx.set_option(ctx.HV_TUNE, 1)
     m = ctx.model(q.H)
     sec = ctx.sector(14, q.n_up - 1, q.n_dn)
     g = torch.Generator(device="cuda:0").manual_seed(11)

@@ -400,7 +400,8 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_
 constexpr size_t kSplitLdsMax = 150 * 1024;      // one real component of a row
 constexpr int kRowsJSplit = 16;                  // row elements per thread, split rows (D_dn <= 16,384)
 
-// Pass 1.  One block per row u; threads own d = tid + j * 1024.
+// Pass 1.  One block per row u; threads own d = tid + j * 1024.  The row is
+// read and y written once (nontemporal), so the hop tables stay in L2.
 template <bool SPLIT, bool UNIFORM_U, int NR>
 __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double2* __restrict__ X, int64_t x_col,
                                                         double2* __restrict__ Y, int64_t y_col) {
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
         const int nr = (int)min((int64_t)NR, T.Dup - ub);
         const double2* __restrict__ xr = X + c * x_col + ub * Ddn;
         double2* __restrict__ yr = Y + c * y_col + ub * Ddn;
-        for (int64_t i = tid; i < (int64_t)nr * Ddn; i += blockDim.x) srow[i] = xr[i];
+        for (int64_t i = tid; i < (int64_t)nr * Ddn; i += blockDim.x) srow[i] = ld_stream(xr + i);
         uint32_t mur[NR];
         double eur[NR];
 #pragma unroll
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
             }
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                if (r < nr) yr[(int64_t)r * Ddn + d] = make_double2(ar[r], ai[r]);
+                if (r < nr) st_stream(yr + (int64_t)r * Ddn + d, make_double2(ar[r], ai[r]));
         }
         return;
     }
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
         const int64_t d = tid + (int64_t)j * kHvThreads;
         xim[j] = 0.0;
         if (d < Ddn) {
-            const double2 v = xrow[d];
+            const double2 v = ld_stream(xrow + d);
             sh[d] = v.x;
             xim[j] = v.y;
         }
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
 #pragma unroll
     for (int j = 0; j < kRowsJSplit; ++j) {
         const int64_t d = tid + (int64_t)j * kHvThreads;
-        if (d < Ddn) yrow[d] = make_double2(are[j], gather(d, xim[j]));
+        if (d < Ddn) st_stream(yrow + d, make_double2(are[j], gather(d, xim[j])));
     }
 }
 
