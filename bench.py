@@ -134,8 +134,6 @@ def probe(a):
     import workloads as wl
     q = wl.ladder14()
     ctx = kgf.Context(0)
-    if a.tune:
-        ctx.set_option(ctx.HV_TUNE, 1)
     m = ctx.model(q.H)
     sec = ctx.sector(14, q.n_up - 1, q.n_dn)
     g = torch.Generator(device="cuda:0").manual_seed(11)
@@ -485,6 +483,8 @@ def main():
 
     q = wl.ladder14()
     ctx = kgf.Context(0)
+    if a.tune:
+        ctx.set_option(ctx.HV_TUNE, 1)
     last = [time.perf_counter()]
 
     def report(phase, done, total):
