@@ -453,6 +453,10 @@ def cpu_baseline(q):
 
 def main():
     a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): every workload here is a "
+              "single-device run", file=sys.stderr)
+        sys.exit(2)
     if a.probe:
         probe(a)
         return
@@ -471,10 +475,6 @@ def main():
     if a.workload == "hub4x3":
         hub4x3(a)
         return
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the four-step solver is a "
-              "single-device path in this build", file=sys.stderr)
-        sys.exit(2)
     import numpy as np
     import torch
 

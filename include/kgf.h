@@ -154,7 +154,9 @@ int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* se
  * Each of nvec vectors psi[c] (at psi + c*ld) is advanced nsteps times by
  *   direction -1: exp(-i H dt);  +1: exp(+i H dt);  0: exp(-(H - shift) dt)
  * using a Krylov space of dimension krylov_dim (<= 128) rebuilt at every
- * step (restart), T diagonalised by implicit QL in one wavefront.  The
+ * step (restart); exp(-+i T dt) e_1 by Taylor substeps, or by an implicit-QL
+ * eigen-decomposition of T when ||T dt|| is large, in one block of one or two
+ * wavefronts.  The
  * vectors of a batch run independent recursions (own a_k, b_k, T).
  * reorth: 0 none, 1 classical GS, 2 classical GS twice.  A recursion
  * stops early (exactly) when b_{k+1} <= breakdown_tol * max(|a_j|, b_j).

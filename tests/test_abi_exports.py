@@ -59,3 +59,14 @@ def test_handles_skip_native_destroy_once_their_context_is_closed(monkeypatch):
             assert calls == expect and obj.handle is None
             obj.close()                      # idempotent
             assert calls == expect
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus N > 1 exits with a message and
+    touches no device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=root, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
