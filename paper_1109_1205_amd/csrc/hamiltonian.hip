@@ -261,7 +261,9 @@ __global__ __launch_bounds__(kThreads) void k_hv(HvTables T, const double2* __re
 // down-spin gathers (random inside the row) are served by LDS; only the
 // up-spin row reads go to the memory hierarchy.  The single-use streams (y
 // written, x_{k-1} read) are nontemporal, so that they do not push the source
-// vector, whose rows the up-spin hops re-read, out of the caches.  Blocks are mapped to the
+// vector, whose rows the up-spin hops re-read, out of the caches.  Eight
+// waves per SIMD (at most 64 VGPRs) let two 1024-thread blocks share a CU:
+// the Lanczos form otherwise needs 65 and runs one block per CU.  Blocks are mapped to the
 // 8 XCDs so that each XCD walks a contiguous range of rows (block b runs on
 // XCD b mod 8): most up-spin hops connect rows less than a few hundred
 // apart, so their source rows stay in that XCD's L2.
@@ -269,7 +271,7 @@ constexpr int kHvThreads = 1024;
 constexpr size_t kRowLdsMax = 78 * 1024;
 
 template <int MODE, bool UNIFORM_U>
-__global__ __launch_bounds__(kHvThreads) void k_hv_lds(HvTables T, int rows_per_xcd,
+__global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds(HvTables T, int rows_per_xcd,
                                                        const double2* __restrict__ X, int64_t x_col,
                                                        const double2* __restrict__ XP, int64_t xp_col,
                                                        double2* __restrict__ Y, int64_t y_col,
