@@ -321,6 +321,9 @@ __global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds(HvTables T, int rows_p
     // Gathers are issued in predicated batches of kBatch so that many loads
     // are in flight per thread (the hop counts are data dependent).
     constexpr int kBatch = 8;
+    // up-spin row gathers per batch: 4 in the Lanczos form keeps it within the
+    // 64-VGPR budget without spills (measured: 4 and 6 equal, 8 spills)
+    constexpr int kBatchUp = MODE == 1 ? 4 : 8;
     for (int64_t d = tid; d < Ddn; d += blockDim.x) {
         const double2 xv = srow[d];
         const uint32_t both = mu & T.md[d];
@@ -332,13 +335,13 @@ __global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds(HvTables T, int rows_p
             dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
         }
         double ar = dg * xv.x, ai = dg * xv.y;
-        for (int k0 = 0; k0 < cu; k0 += kBatch) {       // up-spin hops: uniform count
-            double2 z[kBatch];
+        for (int k0 = 0; k0 < cu; k0 += kBatchUp) {     // up-spin hops: uniform count
+            double2 z[kBatchUp];
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j)
+            for (int j = 0; j < kBatchUp; ++j)
                 if (k0 + j < cu) z[j] = x[s_uprow[k0 + j] + d];
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j)
+            for (int j = 0; j < kBatchUp; ++j)
                 if (k0 + j < cu) {
                     const double tv = s_upval[k0 + j];
                     ar = fma(tv, z[j].x, ar);
