@@ -708,19 +708,33 @@ __global__ __launch_bounds__(kThreads) void k_apply_c_dn(
 constexpr int kThetaMax = kMaxBonds + 3 * kMaxL;
 constexpr size_t kDhLdsMax = 112 * 1024;
 
-template <bool STAGE>
-__global__ __launch_bounds__(kHvThreads) void k_dH(HvTables T, const uint32_t* __restrict__ bdn, int rpx,
-                                                   int L, const double2* __restrict__ lam,
-                                                   const double2* __restrict__ psi, double wr, double wi,
-                                                   double* __restrict__ part, int ntheta) {
+// Pairs (lam_p, psi_p) with weights w_p run as blockIdx.y = p (up to
+// kDhPairs per launch, weights passed by value); the block size NT is 256
+// for rows up to 2048 elements (several rows per CU), else 1024.
+// part[(p * D_up + u) * ntheta + theta].
+constexpr int kDhPairs = 32;
+struct DhWeights {
+    double2 w[kDhPairs];
+};
+
+template <bool STAGE, int NT>
+__global__ __launch_bounds__(NT) void k_dH(HvTables T, const uint32_t* __restrict__ bdn, int rpx,
+                                           int L, const double2* __restrict__ lam_all, int64_t lam_col,
+                                           const double2* __restrict__ psi_all, int64_t psi_col,
+                                           DhWeights wts, double* __restrict__ part_all, int ntheta) {
     extern __shared__ double2 sm[];
-    __shared__ double s_acc[kHvThreads / 64][kThetaMax];
+    __shared__ double s_acc[NT / 64][kThetaMax];
     __shared__ int64_t s_uprow[kMaxBonds + 1];
     __shared__ int s_upb[kMaxBonds + 1];
     __shared__ double s_ups[kMaxBonds + 1];
     const int blk = blockIdx.x;
     const int64_t u = (int64_t)(blk & 7) * rpx + (blk >> 3);
     if (u >= T.Dup) return;
+    const int pr = blockIdx.y;
+    const double2* __restrict__ lam = lam_all + pr * lam_col;
+    const double2* __restrict__ psi = psi_all + pr * psi_col;
+    const double wr = wts.w[pr].x, wi = wts.w[pr].y;
+    double* __restrict__ part = part_all + (int64_t)pr * T.Dup * ntheta;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nw = blockDim.x >> 6;
     const int64_t Ddn = T.Ddn;
@@ -784,28 +798,50 @@ __global__ __launch_bounds__(kHvThreads) void k_dH(HvTables T, const uint32_t* _
             for (int i = 0; i < L; ++i)
                 if ((mu >> i) & 1u) s_acc[wv][nb + i] += sR;   // eps_up_i
     }
+    // Hops in groups of kG: one sweep of the row serves kG hops (kG
+    // independent loads in flight per element); each hop keeps its own
+    // partial sum, accumulated over d in the same order as one hop at a time.
+    constexpr int kG = 8;
     // up-spin hops of row u
-    for (int k = 0; k < cu; ++k) {
-        const double2* __restrict__ src = psi + s_uprow[k];
-        double acc = 0.0;
+    for (int k0 = 0; k0 < cu; k0 += kG) {
+        double acc[kG];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) acc[j] = 0.0;
         for (int64_t d = tid; d < Ddn; d += blockDim.x) {
-            const double2 z = zval(d), p = src[d];
-            acc += z.x * p.x - z.y * p.y;
-        }
-        wave_add(-s_ups[k] * acc, s_upb[k]);
-    }
-    // down-spin hops, one bond at a time
-    for (int b = 0; b < T.nb; ++b) {
-        double acc = 0.0;
-        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
-            const uint32_t e = bdn[(int64_t)b * Ddn + d];
-            if (e == ~0u) continue;
             const double2 z = zval(d);
-            const double2 p = STAGE ? sm[Ddn + (e & 0x7FFFFFFFu)] : prow[e & 0x7FFFFFFFu];
-            const double v = z.x * p.x - z.y * p.y;
-            acc += (e >> 31) ? -v : v;
+            double2 p[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (k0 + j < cu) p[j] = psi[s_uprow[k0 + j] + d];
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (k0 + j < cu) acc[j] += z.x * p[j].x - z.y * p[j].y;
         }
-        wave_add(-acc, b);
+#pragma unroll
+        for (int j = 0; j < kG; ++j)
+            if (k0 + j < cu) wave_add(-s_ups[k0 + j] * acc[j], s_upb[k0 + j]);
+    }
+    // down-spin hops, kG bonds per sweep
+    for (int b0 = 0; b0 < T.nb; b0 += kG) {
+        double acc[kG];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) acc[j] = 0.0;
+        for (int64_t d = tid; d < Ddn; d += blockDim.x) {
+            uint32_t e[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) e[j] = b0 + j < T.nb ? bdn[(int64_t)(b0 + j) * Ddn + d] : ~0u;
+            const double2 z = zval(d);
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                if (e[j] == ~0u) continue;
+                const double2 p = STAGE ? sm[Ddn + (e[j] & 0x7FFFFFFFu)] : prow[e[j] & 0x7FFFFFFFu];
+                const double v = z.x * p.x - z.y * p.y;
+                acc[j] += (e[j] >> 31) ? -v : v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kG; ++j)
+            if (b0 + j < T.nb) wave_add(-acc[j], b0 + j);
     }
     __syncthreads();
     for (int t = tid; t < ntheta; t += blockDim.x) {
@@ -1065,37 +1101,63 @@ void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
 
 int n_theta(const kgf_model* model) { return model->nb + 3 * model->L; }
 
+namespace {
+
+template <bool STAGE, int NT>
+void launch_dH(kgf_ctx* ctx, const HvTables& T, const uint32_t* bdn, int rpx, int L, const double2* lam,
+               int64_t lam_col, const double2* psi, int64_t psi_col, const DhWeights& w, double* part, int nth,
+               int npair, size_t stage) {
+    if (STAGE) {
+        static bool opted[64] = {};
+        if (!opted[ctx->device & 63]) {
+            KGF_HIP(hipFuncSetAttribute((const void*)k_dH<STAGE, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kDhLdsMax));
+            opted[ctx->device & 63] = true;
+        }
+    }
+    hipLaunchKernelGGL((k_dH<STAGE, NT>), dim3((unsigned)(8 * rpx), (unsigned)npair), dim3(NT), STAGE ? stage : 0,
+                       ctx->stream, T, bdn, rpx, L, lam, lam_col, psi, psi_col, w, part, nth);
+}
+
+}  // namespace
+
+// g[theta] += sum_p Re sum conj(w_p lam_p) dH/dtheta psi_p over npair pairs, one launch
 void dH_expect(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* lam, int64_t lam_col,
                const double2* psi, int64_t psi_col, int npair, const double2* host_w, double* g) {
+    if (npair <= 0) return;
     HvTables T = make_tables(model, sec);
     HopTable& td = hop_table(model, sec->n_dn);
     const int nth = n_theta(model);
     KGF_REQUIRE(nth <= kThetaMax, KGF_EUNSUPPORTED, "dH: too many parameters");
     const int rpx = (int)((sec->d_up + 7) / 8);
-    double* part = static_cast<double*>(workspace(ctx, "dH_part", sizeof(double) * (size_t)sec->d_up * nth));
+    const int pmax = std::min(npair, kDhPairs);
+    double* part = static_cast<double*>(
+        workspace(ctx, "dH_part", sizeof(double) * (size_t)pmax * (size_t)sec->d_up * nth));
     const size_t stage = 2 * sizeof(double2) * (size_t)sec->d_dn;
-    for (int p = 0; p < npair; ++p) {
-        const double2 w = host_w[p];
+    const bool small = sec->d_dn <= 2048;
+    const uint32_t* bdn = td.bond.as<uint32_t>();
+    for (int p0 = 0; p0 < npair; p0 += kDhPairs) {
+        const int np = std::min(kDhPairs, npair - p0);
+        DhWeights w{};
+        for (int q = 0; q < np; ++q) w.w[q] = host_w[p0 + q];
+        const double2* lp = lam + p0 * lam_col;
+        const double2* pp = psi + p0 * psi_col;
         {
-            Prof pr(ctx, "dH_expect", 32.0 * (double)sec->dim());
+            Prof pr(ctx, "dH_expect", 32.0 * (double)sec->dim() * np);
             if (stage <= kDhLdsMax) {
-                static bool opted[64] = {};
-                if (!opted[ctx->device & 63]) {
-                    KGF_HIP(hipFuncSetAttribute((const void*)k_dH<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                (int)kDhLdsMax));
-                    opted[ctx->device & 63] = true;
-                }
-                hipLaunchKernelGGL(k_dH<true>, dim3((unsigned)(8 * rpx)), dim3(kHvThreads), stage, ctx->stream, T,
-                                   td.bond.as<uint32_t>(), rpx, model->L, lam + p * lam_col, psi + p * psi_col, w.x,
-                                   w.y, part, nth);
+                if (small)
+                    launch_dH<true, 256>(ctx, T, bdn, rpx, model->L, lp, lam_col, pp, psi_col, w, part, nth, np, stage);
+                else
+                    launch_dH<true, kHvThreads>(ctx, T, bdn, rpx, model->L, lp, lam_col, pp, psi_col, w, part, nth,
+                                                np, stage);
             } else {
-                hipLaunchKernelGGL(k_dH<false>, dim3((unsigned)(8 * rpx)), dim3(kHvThreads), 0, ctx->stream, T,
-                                   td.bond.as<uint32_t>(), rpx, model->L, lam + p * lam_col, psi + p * psi_col, w.x,
-                                   w.y, part, nth);
+                launch_dH<false, kHvThreads>(ctx, T, bdn, rpx, model->L, lp, lam_col, pp, psi_col, w, part, nth, np,
+                                             stage);
             }
             check_launch("k_dH");
         }
-        hipLaunchKernelGGL(k_dH_fin, dim3(nth), dim3(kThreads), 0, ctx->stream, part, (int64_t)sec->d_up, nth, g);
+        hipLaunchKernelGGL(k_dH_fin, dim3(nth), dim3(kThreads), 0, ctx->stream, part, (int64_t)np * sec->d_up, nth,
+                           g);
         check_launch("k_dH_fin");
     }
 }
