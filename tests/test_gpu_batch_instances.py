@@ -6,7 +6,7 @@ Hamiltonians.
 * batched == per instance (kgf_greens_neq) to rounding, on a short mesh and
   on sampled instances of the full workload;
 * the two L = 8 instances of the workload on the full 50 x 50 mesh against
-  the oracle's four-step (north-star bar 1e-10 relative to max|G|);
+  the oracle's four-step (bar 1e-10 relative to max|G|, the parity tolerance for G);
 * every instance of the full workload: equal-time anticommutator and
   Hermiticity."""
 import time

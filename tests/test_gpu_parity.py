@@ -1,7 +1,7 @@
 """HIP path vs the CPU oracle, element by element, through the C ABI.
 
 Bars: integer tables bit-exact; the ladder operator (a signed copy)
-bit-exact; floating point within the benchmark spec's tolerances (G: 1e-10
+bit-exact; floating point within the parity tolerances (G: 1e-10
 relative to max|G|; E0: 1e-12 relative), tighter where the arithmetic
 allows (H.v: summation-order rounding only)."""
 import math

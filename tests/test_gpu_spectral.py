@@ -47,7 +47,7 @@ def test_greens_omega_against_oracle(ring8):
 @pytest.mark.parametrize("dagger", [1, 0])
 @pytest.mark.parametrize("nsteps,nfine,dt,m,bar", [(6, 8, 0.4, 15, 1e-10), (1, 400, 20.0, 40, 1e-7)])
 def test_greens_eq_fine_against_oracle(ring8, dagger, nsteps, nfine, dt, m, bar):
-    """Restarted propagation (short steps, converged) at the north-star 1e-10;
+    """Restarted propagation (short steps, converged) at the G parity tolerance 1e-10;
     one Krylov space of 40 over t = 20 (f = 1, the conventional method,
     unconverged by design) at 1e-7: there the oracle itself moves by 1e-8
     relative when only the global phase of |0> changes."""
