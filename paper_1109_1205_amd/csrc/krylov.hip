@@ -362,8 +362,9 @@ __global__ __launch_bounds__(NT) void k_tridiag_exp(const double* __restrict__ s
     // ---- moderate ||T dt||: exp(A) e_1 by n_sub Taylor substeps of exp(A/n_sub),
     // with A = -i (T - sigma) dt, +i (T - sigma) dt or -(T - sigma) dt and
     // the scalar factor of the centre sigma of the Gershgorin interval applied
-    // at the end.  Lane r holds row r; the tridiagonal product uses
-    // neighbour-lane shuffles.  Each substep has x = ||A||/n_sub <= 1 and
+    // at the end.  Thread r holds row r; the tridiagonal product takes the
+    // neighbouring rows by lane shuffles (one wavefront) or through LDS (two
+    // wavefronts).  Each substep has x = ||A||/n_sub <= 1 and
     // K terms with x^(K+1)/(K+1)! e^x < 1e-17.  Large ||T dt|| (few long
     // steps) takes the eigen-decomposition below instead.
     {
