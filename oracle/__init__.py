@@ -21,6 +21,8 @@ Modules
                  perturbation): the reference for the adjoint
     spectral     equilibrium spectra: conventional Lanczos G(omega) (Eq. gapprox),
                  time-dependent Lanczos G(t) on a fine grid, damped transform
+    driven       driven H(t) = sum_j f_j(t) H_j by the fourth-order
+                 commutator-free exponential integrator (Sec. 6 outlook)
     exact        dense references: Jordan-Wigner Fock-space operators,
                  full diagonalisation, matrix exponentials and the U=0
                  closed form used to pin the above
