@@ -87,6 +87,14 @@ typedef struct {
 
 int  kgf_model_create(kgf_ctx* ctx, const kgf_model_desc* desc, kgf_model** out);
 void kgf_model_destroy(kgf_model* model);
+/* kgf_model_set_params: replace the parameters (t_bond, eps_up, eps_dn, U) of
+ * a model in place; L and the bond list must equal the model's (KGF_EINVAL
+ * otherwise).  Waits for the context's stream first, so work already issued
+ * uses the old values; hopping tables built for the model are kept (they
+ * depend on the bond topology only) and their on-site energies recomputed.
+ * Instance sets built from the model (kgf_greens_neq_multi) must not run
+ * concurrently with the change. */
+int  kgf_model_set_params(kgf_model* model, const kgf_model_desc* desc);
 
 /* ---- sector basis (Sec. 2 occupation-number basis; Sec. 4 N, S_z) --------
  * kgf_sector_create builds, on the device, the ascending mask tables of
@@ -184,6 +192,24 @@ int  kgf_greens_eq(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* secto
                    const kgf_c128* psi0, double E0, const int32_t* host_orbs, int n_orb,
                    int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch,
                    kgf_c128* host_G_greater, kgf_c128* host_G_lesser);
+
+/* ---- driven Hamiltonians (Sec. 6, outlook) ---------------------------------
+ * kgf_propagate_driven: psi[c] (at psi + c*ld, device, nvec columns) is
+ * advanced nsteps steps of opts->dt under H(t) = sum_j f_j(t) H_j, where H_j
+ * has the parameter vector host_theta[j*n_theta .. ] = (t_b, eps_up, eps_dn,
+ * U) on the bond list of `work`, by the fourth-order commutator-free
+ * exponential integrator with two exponentials per step:
+ *   U(t+h, t) = exp(-i h B_2) exp(-i h B_1),
+ *   B_1 = a_2 H(t_1) + a_1 H(t_2),  B_2 = a_1 H(t_1) + a_2 H(t_2),
+ *   a_1,2 = 1/4 -+ sqrt(3)/6,  t_1,2 = t + (1/2 -+ sqrt(3)/6) h.
+ * host_f[(n*2 + q)*n_terms + j] = f_j(t_q) of step n (the caller evaluates
+ * its drive at the Gauss nodes).  Each exponential is one SIL step
+ * (krylov_dim, reorth, breakdown_tol from opts; direction must be -1);
+ * `work` (same L and bonds) has its parameters replaced per stage and holds
+ * the last stage's on return. */
+int  kgf_propagate_driven(kgf_ctx* ctx, kgf_model* work, const kgf_sector* sector, kgf_c128* psi, int nvec,
+                          int64_t ld, int nsteps, int n_terms, const double* host_theta, const double* host_f,
+                          const kgf_prop_opts* opts);
 
 /* ---- equilibrium spectra (Sec. 2, Sec. 3) ----------------------------------
  * kgf_greens_omega: the conventional Lanczos Green's function of Eq. (gapprox)

@@ -86,6 +86,8 @@ def load_library():
         "kgf_version": (I, []),
         "kgf_model_create": (I, [P, C.POINTER(_ModelDesc), C.POINTER(P)]),
         "kgf_model_destroy": (None, [P]),
+        "kgf_model_set_params": (I, [P, C.POINTER(_ModelDesc)]),
+        "kgf_propagate_driven": (I, [P, P, P, P, I, I64, I, I, P, P, C.POINTER(_PropOpts)]),
         "kgf_sector_create": (I, [P, I, I, I, C.POINTER(P)]),
         "kgf_sector_destroy": (None, [P]),
         "kgf_sector_dims": (I, [P, C.POINTER(I64), C.POINTER(I64)]),
@@ -130,7 +132,8 @@ def exported_symbols() -> Sequence[str]:
             "kgf_sector_dims", "kgf_sector_states", "kgf_sector_rank", "kgf_hop_table",
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
-            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_profile_begin",
+            "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
+            "kgf_propagate_driven", "kgf_profile_begin",
             "kgf_profile_end"]
 
 
@@ -175,6 +178,30 @@ class Model:
         h = C.c_void_p()
         _check(_lib.kgf_model_create(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
+
+    def _desc(self):
+        return _ModelDesc(self.L, len(self._bi),
+                          self._bi.ctypes.data_as(C.POINTER(C.c_int32)), self._bj.ctypes.data_as(C.POINTER(C.c_int32)),
+                          self._t.ctypes.data_as(C.POINTER(C.c_double)), self._eu.ctypes.data_as(C.POINTER(C.c_double)),
+                          self._ed.ctypes.data_as(C.POINTER(C.c_double)), self._U.ctypes.data_as(C.POINTER(C.c_double)))
+
+    @property
+    def theta(self) -> np.ndarray:
+        """The parameter vector (t_b, eps_up, eps_dn, U)."""
+        return np.concatenate([self._t, self._eu, self._ed, self._U])
+
+    def set_params(self, t, eps_up, eps_dn, U) -> None:
+        """kgf_model_set_params: new parameters on the same sites and bonds."""
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1)) for a in (t, eps_up, eps_dn, U)]
+        if len(arrs[0]) != len(self._bi) or any(len(a) != self.L for a in arrs[1:]):
+            raise ValueError("set_params: arrays do not match the model's bonds and sites")
+        old = (self._t, self._eu, self._ed, self._U)
+        self._t, self._eu, self._ed, self._U = arrs
+        try:
+            _check(_lib.kgf_model_set_params(self.handle, C.byref(self._desc())))
+        except Exception:
+            self._t, self._eu, self._ed, self._U = old
+            raise
 
     @classmethod
     def from_spec(cls, ctx: "Context", spec) -> "Model":
@@ -344,6 +371,40 @@ class Context:
         o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
         _check(_lib.kgf_propagate(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
                                   C.byref(o)))
+        return psi
+
+    # Gauss-Legendre nodes of the driven integrator, as fractions of a step
+    DRIVE_NODES = (0.5 - np.sqrt(3.0) / 6.0, 0.5 + np.sqrt(3.0) / 6.0)
+
+    def propagate_driven(self, work: Model, sec: Sector, psi, thetas, f, nsteps: int, dt: float, t0: float = 0.0,
+                         krylov_dim: int = 15, reorth: int = 0, breakdown_tol: float = 1e-13):
+        """kgf_propagate_driven: psi (device, [nvec, D] or [D]) advanced under
+        H(t) = sum_j f(t)[j] H(thetas[j]) from t0 in nsteps steps of dt (fourth-
+        order commutator-free integrator).  thetas: [n_terms, n_theta] parameter
+        vectors on the bonds of `work`; f(t) returns the n_terms drive values;
+        `work` holds the last stage's parameters afterwards."""
+        nvec = self._chk(psi, sec.dim, "psi")
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64))
+        if th.ndim == 1:
+            th = th.reshape(1, -1)
+        n_terms = th.shape[0]
+        if th.shape[1] != len(work._bi) + 3 * work.L:
+            raise ValueError("propagate_driven: thetas must have n_bonds + 3 L columns")
+        fv = np.empty((int(nsteps), 2, n_terms))
+        for n in range(int(nsteps)):
+            for q, c in enumerate(self.DRIVE_NODES):
+                fv[n, q] = np.asarray(f(t0 + (n + c) * dt), dtype=np.float64).reshape(n_terms)
+        fv = np.ascontiguousarray(fv)
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        _check(_lib.kgf_propagate_driven(self.handle, work.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
+                                         n_terms, _np_ptr(th), _np_ptr(fv), C.byref(o)))
+        if nsteps > 0 and nvec > 0 and sec.dim > 0:
+            # the device now holds the last stage's parameters: mirror them on the host
+            a1, a2 = 0.25 - np.sqrt(3.0) / 6.0, 0.25 + np.sqrt(3.0) / 6.0
+            last = (a1 * fv[-1, 0] + a2 * fv[-1, 1]) @ th
+            nb, L = len(work._bi), work.L
+            work._t, work._eu = last[:nb].copy(), last[nb:nb + L].copy()
+            work._ed, work._U = last[nb + L:nb + 2 * L].copy(), last[nb + 2 * L:].copy()
         return psi
 
     def greens_eq(self, model: Model, sec: Sector, psi0, E0: float, orbitals: Sequence[Tuple[int, int]],

@@ -228,25 +228,26 @@ int kgf_model_create(kgf_ctx* ctx, const kgf_model_desc* d, kgf_model** out) {
         KGF_REQUIRE(finite_all(m->t.data(), m->nb) && finite_all(d->eps_up, d->L) &&
                         finite_all(d->eps_dn, d->L) && finite_all(d->U, d->L),
                     KGF_EINVAL, "kgf_model_create: non-finite parameter");
-        m->U_uniform = true;
-        for (int i = 1; i < d->L; ++i)
-            if (m->U[i] != m->U[0]) m->U_uniform = false;
         KGF_HIP(hipSetDevice(ctx->device));
-        m->d_t.reserve(sizeof(double) * (m->nb > 0 ? m->nb : 1));
-        if (m->nb)
-            KGF_HIP(hipMemcpy(m->d_t.p, m->t.data(), sizeof(double) * m->nb, hipMemcpyHostToDevice));
-        // byte tables: Utab[q][x] = sum of U_{8q+i} over the set bits i of x
-        std::vector<double> tab(3 * 256, 0.0);
-        for (int q = 0; q < 3; ++q)
-            for (int x = 0; x < 256; ++x) {
-                double s = 0.0;
-                for (int i = 0; i < 8; ++i)
-                    if (((x >> i) & 1) && 8 * q + i < d->L) s += m->U[8 * q + i];
-                tab[q * 256 + x] = s;
-            }
-        m->d_Utab.reserve(sizeof(double) * tab.size());
-        KGF_HIP(hipMemcpy(m->d_Utab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+        upload_params(m.get());
         *out = m.release();
+    });
+}
+
+int kgf_model_set_params(kgf_model* m, const kgf_model_desc* d) {
+    return guarded([&] {
+        KGF_REQUIRE(m && d, KGF_EINVAL, "kgf_model_set_params: NULL argument");
+        KGF_REQUIRE(d->L == m->L && d->n_bonds == m->nb, KGF_EINVAL,
+                    "kgf_model_set_params: L and the number of bonds must stay the same");
+        KGF_REQUIRE(d->eps_up && d->eps_dn && d->U && (m->nb == 0 || (d->bond_i && d->bond_j && d->t_bond)),
+                    KGF_EINVAL, "kgf_model_set_params: NULL parameter array");
+        for (int b = 0; b < m->nb; ++b)
+            KGF_REQUIRE(d->bond_i[b] == m->bi[b] && d->bond_j[b] == m->bj[b], KGF_EINVAL,
+                        "kgf_model_set_params: bond " + std::to_string(b) + " differs");
+        KGF_REQUIRE(finite_all(d->t_bond, m->nb) && finite_all(d->eps_up, m->L) && finite_all(d->eps_dn, m->L) &&
+                        finite_all(d->U, m->L),
+                    KGF_EINVAL, "kgf_model_set_params: non-finite parameter");
+        model_set_params(m, d->t_bond, d->eps_up, d->eps_dn, d->U);
     });
 }
 

@@ -151,6 +151,63 @@ __global__ void k_onsite(const uint32_t* __restrict__ masks, int64_t D, int L,
     out_dn[r] = sd;
 }
 
+// device copies of a model's parameters: hopping amplitudes and the byte
+// tables Utab[q][x] = sum of U_{8q+i} over the set bits i of x
+void upload_params(kgf_model* m) {
+    m->U_uniform = true;
+    for (int i = 1; i < m->L; ++i)
+        if (m->U[i] != m->U[0]) m->U_uniform = false;
+    m->d_t.reserve(sizeof(double) * (m->nb > 0 ? m->nb : 1));
+    if (m->nb) KGF_HIP(hipMemcpy(m->d_t.p, m->t.data(), sizeof(double) * m->nb, hipMemcpyHostToDevice));
+    std::vector<double> tab(3 * 256, 0.0);
+    for (int q = 0; q < 3; ++q)
+        for (int x = 0; x < 256; ++x) {
+            double s = 0.0;
+            for (int i = 0; i < 8; ++i)
+                if (((x >> i) & 1) && 8 * q + i < m->L) s += m->U[8 * q + i];
+            tab[q * 256 + x] = s;
+        }
+    m->d_Utab.reserve(sizeof(double) * tab.size());
+    KGF_HIP(hipMemcpy(m->d_Utab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+}
+
+void model_set_params(kgf_model* m, const double* t, const double* eps_up, const double* eps_dn,
+                      const double* U) {
+    KGF_HIP(hipSetDevice(m->ctx->device));
+    KGF_HIP(hipStreamSynchronize(m->ctx->stream));   // issued work keeps the old parameters
+    m->t.assign(t, t + m->nb);
+    m->eps_up.assign(eps_up, eps_up + m->L);
+    m->eps_dn.assign(eps_dn, eps_dn + m->L);
+    m->U.assign(U, U + m->L);
+    upload_params(m);
+    refresh_onsite(m);
+}
+
+// Recompute the on-site energies e_up, e_dn of every hopping table already
+// built for the model (after its eps_up / eps_dn changed); the tables'
+// targets, bonds and signs depend on the bond topology only.
+void refresh_onsite(kgf_model* model) {
+    kgf_ctx* ctx = model->ctx;
+    if (model->tables.empty()) return;
+    DevBuf deu, ded;
+    deu.reserve(sizeof(double) * model->L);
+    ded.reserve(sizeof(double) * model->L);
+    KGF_HIP(hipMemcpyAsync(deu.p, model->eps_up.data(), sizeof(double) * model->L, hipMemcpyHostToDevice,
+                           ctx->stream));
+    KGF_HIP(hipMemcpyAsync(ded.p, model->eps_dn.data(), sizeof(double) * model->L, hipMemcpyHostToDevice,
+                           ctx->stream));
+    for (auto& kv : model->tables) {
+        HopTable& t = *kv.second;
+        if (!t.D) continue;
+        const int64_t blocks = (t.D + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_onsite, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream, t.masks.as<uint32_t>(),
+                           t.D, model->L, deu.as<double>(), ded.as<double>(), t.e_up.as<double>(),
+                           t.e_dn.as<double>());
+        check_launch("k_onsite");
+    }
+    sync(ctx);   // the temporaries above are freed on return
+}
+
 HopTable& hop_table(kgf_model* model, int n) {
     auto it = model->tables.find(n);
     if (it != model->tables.end()) return *it->second;

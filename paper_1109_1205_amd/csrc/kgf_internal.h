@@ -155,6 +155,14 @@ int64_t binom_host(int n, int k);
 
 // ---- hamiltonian (hamiltonian.hip) ---------------------------------------
 HopTable& hop_table(kgf_model* model, int n);
+// device copies of a model's hopping amplitudes and U byte tables
+void upload_params(kgf_model* m);
+// after a parameter change: recompute the on-site energies of the built tables
+void refresh_onsite(kgf_model* model);
+// replace a model's parameters in place (same L and bonds); waits for the
+// context's stream first, so that work already issued keeps the old values
+void model_set_params(kgf_model* m, const double* t, const double* eps_up, const double* eps_dn,
+                      const double* U);
 
 // Parameter sets of several models with one bond topology (same L and bond
 // list), for batches whose columns carry different Hamiltonians: column c
