@@ -50,10 +50,12 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
-    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3"], default="ladder14",
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven"],
+                   default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
-                        "short mesh; hub4x3: equilibrium G of the 4x3 cluster, 24 columns batched vs one at a "
+                        "short mesh; driven: the 2x7 ladder under a periodic rung drive (commutator-free "
+                        "integrator) against as many static SIL steps; hub4x3: equilibrium G of the 4x3 cluster, 24 columns batched vs one at a "
                         "time; fig1: the equilibrium spectral density of the L=10 ring (Sec. 3) for "
                         "several restart counts against the conventional Lanczos G")
     p.add_argument("--grad-instances", type=int, default=5,
@@ -357,6 +359,51 @@ def hub4x3(a):
     print(json.dumps(out), flush=True)
 
 
+def driven(a):
+    """Driven 2x7 ladder (7,7), D = 11,778,624: H(t) = H0 + 0.5 sin(2t) K_rung
+    (K_rung: the hopping on the seven rungs), 10 steps of h = 0.05 of the
+    fourth-order commutator-free integrator (two SIL steps of Krylov dim 20
+    per step), timed against 20 static SIL steps of the same size."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    q = wl.ladder14()
+    ctx = kgf.Context(0)
+    H0 = q.H
+    nb, L = len(H0.bonds), H0.L
+    th0 = np.concatenate([np.asarray(H0.t, float), np.asarray(H0.eps_up, float), np.asarray(H0.eps_dn, float),
+                          np.asarray(H0.U, float)])
+    kr = np.zeros(nb + 3 * L)
+    for b, (i, j) in enumerate(H0.bonds):
+        if j == i + 1 and i % 2 == 0:        # rung (2x, 2x+1) in the rung-major numbering
+            kr[b] = 1.0
+    f = lambda t: [1.0, 0.5 * np.sin(2.0 * t)]
+    s = ctx.sector(L, q.n_up, q.n_dn)
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    x = torch.randn(1, s.dim, dtype=torch.complex128, device="cuda:0", generator=g)
+    x /= torch.linalg.vector_norm(x)
+    work, m0 = ctx.model(H0), ctx.model(H0)
+    y = x.clone()
+    ctx.propagate_driven(work, s, y, [th0, kr], f, 1, 0.05, krylov_dim=q.krylov_dim)   # warm-up (tables)
+    ctx.propagate(m0, s, y, 1, 0.05, q.krylov_dim)
+    torch.cuda.synchronize()
+    y = x.clone()
+    t0 = time.perf_counter()
+    ctx.propagate_driven(work, s, y, [th0, kr], f, 10, 0.05, krylov_dim=q.krylov_dim)
+    torch.cuda.synchronize()
+    td = time.perf_counter() - t0
+    z = x.clone()
+    t0 = time.perf_counter()
+    ctx.propagate(m0, s, z, 20, 0.05, q.krylov_dim)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out = {"metric": "driven 2x7 ladder, commutator-free 4th order, 10 steps (20 SIL steps)", "D": s.dim,
+           "driven_s": round(td, 3), "static_20_sil_steps_s": round(ts, 3), "overhead": round(td / ts - 1.0, 3),
+           "norm_err": float(abs(torch.linalg.vector_norm(y).item() - 1.0))}
+    print(json.dumps(out), flush=True)
+
+
 def fig1(a):
     """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
     half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
@@ -474,6 +521,9 @@ def main():
         return
     if a.workload == "hub4x3":
         hub4x3(a)
+        return
+    if a.workload == "driven":
+        driven(a)
         return
     import numpy as np
     import torch
