@@ -90,3 +90,55 @@ def test_krylov_stages_match_exact_and_conserve_norm(reorth):
     kry = driven.cfm4(H0, sec, ths, f, psi, 0.1, 0.05, 10, m=15, reorth=reorth)
     assert np.abs(kry - exact).max() < 1e-12 * np.abs(exact).max()
     assert abs(np.linalg.norm(kry) - np.linalg.norm(psi)) < 1e-12 * np.linalg.norm(psi)
+
+
+def _chain_siam_pair(L=4, U=1.0, h=0.2):
+    H = wl.chain_siam(L, U, 1.0)
+    return H, H.with_field(0, h)
+
+
+def test_driven_four_step_with_constant_drive_is_the_static_four_step():
+    """A constant drive: the driven four-step equals the static one (Sec. 4)
+    with H = sum_j f_j H_j."""
+    from oracle import greens
+    H, H_ini = _chain_siam_pair()
+    L, nb = H.L, len(H.bonds)
+    k0 = np.zeros(nb + 3 * L)
+    k0[1] = 1.0
+    f = lambda t: [1.0, 0.4]
+    orbs = [(0, 0), (1, 0), (0, 1)]
+    sec = basis.Sector(L, 2, 2)
+    v0 = wl.start_vector(sec.dim, 7)
+    got = driven.four_step(H_ini, H, [theta_of(H), k0], f, 2, 2, orbs, 5, 0.2, 2, 15, v0, gs_tol=1e-13)
+    Hs = model_with_theta(H, theta_of(H) + 0.4 * k0)
+    ref = greens.four_step(H_ini, Hs, 2, 2, orbs, 5, 0.2, 2, 15, v0, gs_tol=1e-13)
+    for key in ("G_lesser", "G_greater"):
+        assert np.abs(got[key] - ref[key]).max() < 1e-11 * np.abs(ref[key]).max()
+
+
+def test_driven_four_step_commuting_drive_is_a_phase():
+    """H(t) = H + f(t) N_up with N_up constant on a sector: for up-spin
+    orbitals G^<(t,t') and G^>(t,t') pick up exp(-i (F(t) - F(t'))), F = the
+    integral of f (cubic f: integrated exactly); down-spin ones are unchanged."""
+    from oracle import greens
+    H, H_ini = _chain_siam_pair()
+    L, nb = H.L, len(H.bonds)
+    thN = np.zeros(nb + 3 * L)
+    thN[nb:nb + L] = 1.0
+    f = lambda t: [1.0, 0.5 + t - 0.4 * t ** 2 + 0.2 * t ** 3]
+    F = lambda t: 0.5 * t + 0.5 * t ** 2 - 0.4 / 3 * t ** 3 + 0.05 * t ** 4
+    orbs = [(0, 0), (2, 0), (1, 1)]
+    sec = basis.Sector(L, 2, 2)
+    v0 = wl.start_vector(sec.dim, 7)
+    nt, dtg, spg = 5, 0.25, 2
+    got = driven.four_step(H_ini, H, [theta_of(H), thN], f, 2, 2, orbs, nt, dtg, spg, 15, v0, gs_tol=1e-13)
+    ref = greens.four_step(H_ini, H, 2, 2, orbs, nt, dtg, spg, 15, v0, gs_tol=1e-13)
+    t = dtg * np.arange(nt)
+    ph = np.exp(-1j * (F(t)[:, None] - F(t)[None, :]))
+    for key in ("G_lesser", "G_greater"):
+        r = ref[key].copy()
+        for a, (_, sa) in enumerate(orbs):
+            for b, (_, sb) in enumerate(orbs):
+                if sa == 0 and sb == 0:
+                    r[:, :, a, b] *= ph
+        assert np.abs(got[key] - r).max() < 1e-11 * np.abs(r).max()
