@@ -211,6 +211,29 @@ int  kgf_propagate_driven(kgf_ctx* ctx, kgf_model* work, const kgf_sector* secto
                           int64_t ld, int nsteps, int n_terms, const double* host_theta, const double* host_f,
                           const kgf_prop_opts* opts);
 
+/* kgf_greens_neq_driven: the four-step G^<, G^> (Sec. 4) with the driven final
+ * Hamiltonian of kgf_propagate_driven.  |0> = ground state of H_ini in `sector`
+ * (from v0, gs_opts); Phi(t_k) = U(t_k, 0)|0> by the commutator-free
+ * integrator with steps h = opts->dt from t = 0, t_k = k * steps_per_grid * h,
+ * k = 0..nt-1; host_f holds the (nt-1)*steps_per_grid steps in the layout of
+ * kgf_propagate_driven (step n starts at t = n h).  With U^+ the adjoint stage
+ * exponentials in reverse order,
+ *   G^<_ab(t, t') = +i <Psi_b(t')|Psi_a(t)>,  Psi_a(t) = U(t, 0)^+ c_a Phi(t),
+ *   G^>_ab(t, t') = -i <chi_a(t)|chi_b(t')>,  chi_a(t) = U(t, 0)^+ c+_a Phi(t),
+ * evaluated by one backward sweep per spin and per c / c+ that carries the
+ * columns U(t_j, t_s)^+ c_a Phi(t_j) and dots them with c_b Phi(t_s) at every
+ * mesh time t_s <= t_j (t_j < t_s from G_ab(t, t')* = -G_ba(t', t)).
+ * batch: most columns in one sweep block (0 = as many as fit in memory).
+ * Outputs host [nt][nt][n_orb][n_orb] (zero between orbitals of different
+ * spin; either may be NULL) and E0.  `work` (not H_ini; same L and bonds as
+ * the terms) is left holding the last stage's parameters.  KGF_ENOCONV if the
+ * ground state does not converge. */
+int  kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_model* work, const kgf_sector* sector,
+                           const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
+                           int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch, int n_terms,
+                           const double* host_theta, const double* host_f, kgf_c128* host_G_lesser,
+                           kgf_c128* host_G_greater, double* host_E0);
+
 /* ---- equilibrium spectra (Sec. 2, Sec. 3) ----------------------------------
  * kgf_greens_omega: the conventional Lanczos Green's function of Eq. (gapprox)
  * for orbital a (site*2+spin) from the ground state psi0 (device, in `sector`)

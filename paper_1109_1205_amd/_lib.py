@@ -88,6 +88,8 @@ def load_library():
         "kgf_model_destroy": (None, [P]),
         "kgf_model_set_params": (I, [P, C.POINTER(_ModelDesc)]),
         "kgf_propagate_driven": (I, [P, P, P, P, I, I64, I, I, P, P, C.POINTER(_PropOpts)]),
+        "kgf_greens_neq_driven": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
+                                      P, P, P, P, C.POINTER(D)]),
         "kgf_sector_create": (I, [P, I, I, I, C.POINTER(P)]),
         "kgf_sector_destroy": (None, [P]),
         "kgf_sector_dims": (I, [P, C.POINTER(I64), C.POINTER(I64)]),
@@ -133,7 +135,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
-            "kgf_propagate_driven", "kgf_profile_begin",
+            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_profile_begin",
             "kgf_profile_end"]
 
 
@@ -384,28 +386,67 @@ class Context:
         vectors on the bonds of `work`; f(t) returns the n_terms drive values;
         `work` holds the last stage's parameters afterwards."""
         nvec = self._chk(psi, sec.dim, "psi")
+        th, fv = self._drive_table(work, thetas, f, nsteps, dt, t0)
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        _check(_lib.kgf_propagate_driven(self.handle, work.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
+                                         th.shape[0], _np_ptr(th), _np_ptr(fv), C.byref(o)))
+        if nsteps > 0 and nvec > 0 and sec.dim > 0:
+            self._mirror_last_stage(work, th, fv)
+        return psi
+
+    def _drive_table(self, work: Model, thetas, f, nsteps: int, dt: float, t0: float):
+        """[n_terms, n_theta] parameter vectors and the drive values at the
+        two Gauss nodes of each step, [nsteps, 2, n_terms]."""
         th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64))
         if th.ndim == 1:
             th = th.reshape(1, -1)
         n_terms = th.shape[0]
         if th.shape[1] != len(work._bi) + 3 * work.L:
-            raise ValueError("propagate_driven: thetas must have n_bonds + 3 L columns")
-        fv = np.empty((int(nsteps), 2, n_terms))
+            raise ValueError("driven: thetas must have n_bonds + 3 L columns")
+        fv = np.empty((max(int(nsteps), 1), 2, n_terms))
         for n in range(int(nsteps)):
             for q, c in enumerate(self.DRIVE_NODES):
                 fv[n, q] = np.asarray(f(t0 + (n + c) * dt), dtype=np.float64).reshape(n_terms)
-        fv = np.ascontiguousarray(fv)
+        if nsteps <= 0:
+            fv[:] = 0.0
+        return th, np.ascontiguousarray(fv)
+
+    @staticmethod
+    def _mirror_last_stage(work: Model, th, fv):
+        # the device holds the last stage's parameters: mirror them on the host
+        a1, a2 = 0.25 - np.sqrt(3.0) / 6.0, 0.25 + np.sqrt(3.0) / 6.0
+        last = (a1 * fv[-1, 0] + a2 * fv[-1, 1]) @ th
+        nb, L = len(work._bi), work.L
+        work._t, work._eu = last[:nb].copy(), last[nb:nb + L].copy()
+        work._ed, work._U = last[nb + L:nb + 2 * L].copy(), last[nb + 2 * L:].copy()
+
+    def greens_neq_driven(self, H_ini: Model, work: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]],
+                          thetas, f, nt: int, steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0,
+                          batch: int = 0, gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1,
+                          gs_reorth: int = 2, breakdown_tol: float = 1e-13):
+        """kgf_greens_neq_driven: four-step G^<, G^> [nt, nt, n_orb, n_orb] after
+        the ground state of H_ini, under H(t) = sum_j f(t)[j] H(thetas[j]) from
+        t = 0 (steps of dt, steps_per_grid per mesh interval).  `work` (not
+        H_ini) holds the last stage's parameters afterwards."""
+        self._chk(v0, sec.dim, "v0")
+        if work is H_ini:
+            raise ValueError("greens_neq_driven: work must not be H_ini")
+        nsteps = (int(nt) - 1) * int(steps_per_grid)
+        th, fv = self._drive_table(work, thetas, f, nsteps, dt, 0.0)
+        orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
+        no = len(orbs)
+        Gl = _host_c128((nt, nt, no, no))
+        Gg = _host_c128((nt, nt, no, no))
+        E0 = C.c_double()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        _check(_lib.kgf_propagate_driven(self.handle, work.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
-                                         n_terms, _np_ptr(th), _np_ptr(fv), C.byref(o)))
-        if nsteps > 0 and nvec > 0 and sec.dim > 0:
-            # the device now holds the last stage's parameters: mirror them on the host
-            a1, a2 = 0.25 - np.sqrt(3.0) / 6.0, 0.25 + np.sqrt(3.0) / 6.0
-            last = (a1 * fv[-1, 0] + a2 * fv[-1, 1]) @ th
-            nb, L = len(work._bi), work.L
-            work._t, work._eu = last[:nb].copy(), last[nb:nb + L].copy()
-            work._ed, work._U = last[nb + L:nb + 2 * L].copy(), last[nb + 2 * L:].copy()
-        return psi
+        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        _check(_lib.kgf_greens_neq_driven(self.handle, H_ini.handle, work.handle, sec.handle, C.byref(g), _ptr(v0),
+                                          _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(batch),
+                                          th.shape[0], _np_ptr(th), _np_ptr(fv), _np_ptr(Gl), _np_ptr(Gg),
+                                          C.byref(E0)))
+        if nsteps > 0:
+            self._mirror_last_stage(work, th, fv)
+        return {"G_lesser": Gl, "G_greater": Gg, "E0": E0.value}
 
     def greens_eq(self, model: Model, sec: Sector, psi0, E0: float, orbitals: Sequence[Tuple[int, int]],
                   nt: int, steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0,

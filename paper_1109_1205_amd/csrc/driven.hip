@@ -11,8 +11,27 @@
 // theta_j and each exponential is one short-iterative-Lanczos step of the
 // ordinary kernels on a work model whose parameters are replaced per stage.
 #include <cmath>
+#include <vector>
 
 #include "kgf_internal.h"
+
+namespace kgf {
+
+void driven_stage(kgf_model* work, const DriveTable& drv, int n, int stage) {
+    const double a1 = 0.25 - std::sqrt(3.0) / 6.0, a2 = 0.25 + std::sqrt(3.0) / 6.0;
+    const int nb = work->nb, L = work->L, nth = n_theta(work);
+    const double* f1 = drv.f + (int64_t)n * 2 * drv.n_terms;   // f_j(t_1)
+    const double* f2 = f1 + drv.n_terms;                       // f_j(t_2)
+    std::vector<double> th(nth, 0.0);
+    for (int j = 0; j < drv.n_terms; ++j) {
+        const double g = stage == 0 ? a2 * f1[j] + a1 * f2[j] : a1 * f1[j] + a2 * f2[j];
+        const double* tj = drv.theta + (int64_t)j * nth;
+        for (int q = 0; q < nth; ++q) th[q] += g * tj[q];
+    }
+    model_set_params(work, th.data(), th.data() + nb, th.data() + nb + L, th.data() + nb + 2 * L);
+}
+
+}  // namespace kgf
 
 using namespace kgf;
 
@@ -28,26 +47,17 @@ int kgf_propagate_driven(kgf_ctx* ctx, kgf_model* work, const kgf_sector* s, kgf
                     "kgf_propagate_driven: bad nvec / nsteps / ld / n_terms");
         if (nvec == 0 || nsteps == 0 || s->dim() == 0) return;
         KGF_REQUIRE(psi && host_theta && host_f, KGF_EINVAL, "kgf_propagate_driven: NULL array");
-        const int nb = work->nb, L = work->L, nth = n_theta(work);
+        const int nth = n_theta(work);
         for (int64_t i = 0; i < (int64_t)n_terms * nth; ++i)
             KGF_REQUIRE(std::isfinite(host_theta[i]), KGF_EINVAL, "kgf_propagate_driven: non-finite theta");
         for (int64_t i = 0; i < (int64_t)nsteps * 2 * n_terms; ++i)
             KGF_REQUIRE(std::isfinite(host_f[i]), KGF_EINVAL, "kgf_propagate_driven: non-finite drive value");
         KGF_HIP(hipSetDevice(ctx->device));
-        const double a1 = 0.25 - std::sqrt(3.0) / 6.0, a2 = 0.25 + std::sqrt(3.0) / 6.0;
-        SilOpts o = to_sil_opts(opts);
-        std::vector<double> th(nth);
+        const SilOpts o = to_sil_opts(opts);
+        const DriveTable drv{n_terms, host_theta, host_f};
         for (int n = 0; n < nsteps; ++n) {
-            const double* f1 = host_f + (int64_t)n * 2 * n_terms;   // f_j(t_1)
-            const double* f2 = f1 + n_terms;                       // f_j(t_2)
             for (int stage = 0; stage < 2; ++stage) {
-                std::fill(th.begin(), th.end(), 0.0);
-                for (int j = 0; j < n_terms; ++j) {
-                    const double g = stage == 0 ? a2 * f1[j] + a1 * f2[j] : a1 * f1[j] + a2 * f2[j];
-                    const double* tj = host_theta + (int64_t)j * nth;
-                    for (int q = 0; q < nth; ++q) th[q] += g * tj[q];
-                }
-                model_set_params(work, th.data(), th.data() + nb, th.data() + nb + L, th.data() + nb + 2 * L);
+                driven_stage(work, drv, n, stage);
                 sil_propagate(ctx, work, s, reinterpret_cast<double2*>(psi), nvec, ld, 1, o);
             }
             if ((n + 1) % 16 == 0 || n + 1 == nsteps) progress(ctx, "driven", n + 1, nsteps);

@@ -688,6 +688,119 @@ void greens_neq_multi(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* 
     }
 }
 
+// Four-step with a driven final Hamiltonian H(t) = sum_j f_j(t) H_j (the
+// commutator-free integrator of driven.hip; steps of o.dt from t = 0, spg per
+// mesh interval).  Without time-translation invariance the sweep carries
+// X_{a,j}(s) = U(t_j, t_s)^+ c_a Phi_j: from t_s to t_{s-1} each column takes
+// the adjoint stage exponentials of the steps in between, last step first and
+// B_2 before B_1.  U(t_s, 0) U(t_j, 0)^+ = U(t_j, t_s)^+ for the product of
+// steps, so <c_b Phi_s | X_{a,j}(s)> = <Psi_b(t_s)|Psi_a(t_j)> as in the
+// plain schedule.  `work` takes every stage's parameters in turn.
+void greens_neq_driven(kgf_ctx* ctx, kgf_model* Hi, kgf_model* work, const kgf_sector* sec, const double2* v0,
+                       const kgf_gs_opts* gso, const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o,
+                       int batch, const DriveTable& drv, double2* Gl_host, double2* Gg_host, double* E0_host) {
+    const int64_t D = sec->dim();
+    const size_t vb = sizeof(double2) * (size_t)D;
+    const size_t gsz = (size_t)nt * nt * norb * norb;
+    ensure_device_fits(vb * (size_t)nt, "driven four-step forward mesh");
+    double2* Phi = static_cast<double2*>(workspace(ctx, "dneq_phi", vb * (size_t)nt));
+    GsResult gs = ground_state(ctx, Hi, sec, v0, Phi, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
+    KGF_REQUIRE(gs.converged, KGF_ENOCONV, "driven four-step: the ground state of H_ini did not converge");
+    *E0_host = gs.E0;
+    release(ctx, "gs_V");
+    release(ctx, "gs_partbig");
+    SilOpts fo = o;
+    fo.direction = -1;
+    for (int t = 1; t < nt; ++t) {
+        double2* cur = Phi + (size_t)t * D;
+        KGF_HIP(hipMemcpyAsync(cur, cur - D, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int n = (t - 1) * spg; n < t * spg; ++n)
+            for (int stage = 0; stage < 2; ++stage) {
+                driven_stage(work, drv, n, stage);
+                sil_propagate(ctx, work, sec, cur, 1, D, 1, fo);
+            }
+        progress(ctx, "driven_forward", t, nt - 1);
+    }
+    auto phi = [&](int t) { return Phi + (size_t)t * D; };
+    std::vector<double2> Gl(gsz, make_double2(0, 0)), Gg(gsz, make_double2(0, 0));
+    SilOpts so = o;
+    so.direction = +1;
+    for (int spin = 0; spin < 2; ++spin) {
+        std::vector<int> loc;
+        for (int a = 0; a < norb; ++a)
+            if ((orbs[a] & 1) == spin) loc.push_back(a);
+        const int na = (int)loc.size();
+        if (!na) continue;
+        DevBuf gidx;
+        upload_ints(ctx, gidx, loc);
+        for (int dagger = 0; dagger < 2; ++dagger) {
+            auto tgt = shifted(ctx, sec, spin, dagger ? +1 : -1);
+            if (!tgt || tgt->dim() == 0) continue;
+            const int64_t Dt = tgt->dim();
+            const size_t rsz = (size_t)nt * nt * na * na;
+            double2* raw = static_cast<double2*>(workspace(ctx, "dneq_raw", sizeof(double2) * rsz));
+            KGF_HIP(hipMemsetAsync(raw, 0, sizeof(double2) * rsz, ctx->stream));
+            const size_t per_col = sizeof(double2) * (size_t)(o.m + 1) * Dt;
+            int Bcols = batch;
+            if (Bcols <= 0) {
+                size_t free_b = 0, total_b = 0;
+                KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+                Bcols = (int)std::max<size_t>(1, (size_t)(0.8 * (double)free_b) / per_col);
+            }
+            const int jchunk = std::min(nt, std::max(1, Bcols / na));
+            const int maxcols = jchunk * na;
+            release(ctx, "sil_X");
+            sil_reserve(ctx, tgt.get(), maxcols, o.m, o.reorth);
+            ensure_device_fits(sizeof(double2) * (size_t)maxcols * Dt, "driven four-step sweep block");
+            double2* S = static_cast<double2*>(workspace(ctx, "dneq_cols", sizeof(double2) * (size_t)maxcols * Dt));
+            double2* Lb = static_cast<double2*>(workspace(ctx, "dneq_left", sizeof(double2) * (size_t)na * Dt));
+            double2* tmp = static_cast<double2*>(workspace(ctx, "dneq_tmp", sizeof(double2) * (size_t)na * maxcols));
+            const int64_t ss = (int64_t)na * na * nt, sb = (int64_t)na * nt, sa = nt, sj = 1;
+            for (int jhi = nt - 1; jhi >= 0; jhi -= jchunk) {
+                const int jlo = std::max(0, jhi - jchunk + 1);
+                int ncur = 0;   // column r at S + r * Dt: orbital r % na injected at t_{jhi - r / na}
+                for (int s2 = jhi; s2 >= 0; --s2) {
+                    if (s2 >= jlo) {
+                        for (int q = 0; q < na; ++q)
+                            apply_c(ctx, sec, tgt.get(), orbs[loc[q]], dagger, phi(s2), S + (size_t)(ncur + q) * Dt,
+                                    1, D, Dt);
+                        ncur += na;
+                    }
+                    for (int q = 0; q < na; ++q)
+                        apply_c(ctx, sec, tgt.get(), orbs[loc[q]], dagger, phi(s2), Lb + (size_t)q * Dt, 1, D, Dt);
+                    block_dots(ctx, Lb, Dt, na, S, Dt, ncur, Dt, tmp, ncur);
+                    place(ctx, tmp, na, na, ncur, jhi, raw, s2 * ss, sb, sa, sj);
+                    if (s2 > 0)
+                        for (int n = s2 * spg - 1; n >= (s2 - 1) * spg; --n)
+                            for (int stage = 1; stage >= 0; --stage) {
+                                driven_stage(work, drv, n, stage);
+                                sil_propagate(ctx, work, tgt.get(), S, ncur, Dt, 1, so);
+                            }
+                    progress(ctx, dagger ? "driven_sweep_greater" : "driven_sweep_lesser", jhi - s2 + 1, jhi + 1);
+                }
+            }
+            double2* Gdev = static_cast<double2*>(workspace(ctx, "dneq_G", sizeof(double2) * gsz));
+            KGF_HIP(hipMemsetAsync(Gdev, 0, sizeof(double2) * gsz, ctx->stream));
+            const int64_t total = (int64_t)nt * nt * na * na;
+            hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)),
+                               dim3(kThreads), 0, ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), norb,
+                               dagger, 1, Gdev);
+            check_launch("k_store_neq");
+            std::vector<double2> h(gsz);
+            KGF_HIP(hipMemcpyAsync(h.data(), Gdev, sizeof(double2) * gsz, hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            // only the entries of this spin group were written (the rest are zero)
+            std::vector<double2>& dst = dagger ? Gg : Gl;
+            for (size_t e = 0; e < gsz; ++e)
+                if (h[e].x != 0.0 || h[e].y != 0.0) dst[e] = h[e];
+        }
+    }
+    if (Gl_host) std::copy(Gl.begin(), Gl.end(), Gl_host);
+    if (Gg_host) std::copy(Gg.begin(), Gg.end(), Gg_host);
+    for (const char* nm : {"dneq_phi", "dneq_cols", "dneq_left", "dneq_tmp", "dneq_raw", "dneq_G", "sil_X"})
+        release(ctx, nm);
+}
+
 }  // namespace kgf
 
 using namespace kgf;
@@ -764,5 +877,41 @@ extern "C" int kgf_greens_neq_multi(kgf_ctx* ctx, int n_inst, const kgf_model* c
                          reinterpret_cast<const double2* const*>(v0), gs_opts, host_orbs, n_orb, nt, steps_per_grid,
                          kgf::to_sil_opts(opts), batch, reinterpret_cast<double2*>(host_G_lesser),
                          reinterpret_cast<double2*>(host_G_greater), host_E0);
+    });
+}
+
+extern "C" int kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_model* work,
+                                     const kgf_sector* sector, const kgf_gs_opts* gs_opts, const kgf_c128* v0,
+                                     const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
+                                     const kgf_prop_opts* opts, int batch, int n_terms, const double* host_theta,
+                                     const double* host_f, kgf_c128* host_G_lesser, kgf_c128* host_G_greater,
+                                     double* host_E0) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(ctx && H_ini && work && sector && gs_opts && v0 && host_orbs && host_E0 && host_theta && host_f,
+                    KGF_EINVAL, "kgf_greens_neq_driven: NULL argument");
+        KGF_REQUIRE(H_ini != work, KGF_EINVAL, "kgf_greens_neq_driven: work must not be H_ini");
+        KGF_REQUIRE(H_ini->L == sector->L && work->L == sector->L, KGF_EINVAL,
+                    "kgf_greens_neq_driven: models and sector differ in L");
+        KGF_REQUIRE(sector->dim() > 0, KGF_EINVAL, "kgf_greens_neq_driven: empty sector");
+        kgf::check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && batch >= 0 && n_terms >= 1, KGF_EINVAL,
+                    "kgf_greens_neq_driven: bad sizes");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                    KGF_EINVAL, "kgf_greens_neq_driven: bad ground-state options");
+        for (int a = 0; a < n_orb; ++a)
+            KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
+                        "kgf_greens_neq_driven: orbital out of range");
+        const int nth = kgf::n_theta(work);
+        const int64_t nsteps = (int64_t)(nt - 1) * steps_per_grid;
+        for (int64_t i = 0; i < (int64_t)n_terms * nth; ++i)
+            KGF_REQUIRE(std::isfinite(host_theta[i]), KGF_EINVAL, "kgf_greens_neq_driven: non-finite theta");
+        for (int64_t i = 0; i < nsteps * 2 * n_terms; ++i)
+            KGF_REQUIRE(std::isfinite(host_f[i]), KGF_EINVAL, "kgf_greens_neq_driven: non-finite drive value");
+        KGF_HIP(hipSetDevice(ctx->device));
+        greens_neq_driven(ctx, const_cast<kgf_model*>(H_ini), work, sector, reinterpret_cast<const double2*>(v0),
+                          gs_opts, host_orbs, n_orb, nt, steps_per_grid, kgf::to_sil_opts(opts), batch,
+                          kgf::DriveTable{n_terms, host_theta, host_f}, reinterpret_cast<double2*>(host_G_lesser),
+                          reinterpret_cast<double2*>(host_G_greater), host_E0);
     });
 }

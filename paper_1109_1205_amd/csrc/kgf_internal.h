@@ -164,6 +164,17 @@ void refresh_onsite(kgf_model* model);
 void model_set_params(kgf_model* m, const double* t, const double* eps_up, const double* eps_dn,
                       const double* U);
 
+// Drive of H(t) = sum_j f_j(t) H_j: theta[j * n_theta(work) ..] = parameters
+// of H_j; f[(n * 2 + q) * n_terms + j] = f_j at Gauss node q of step n.
+struct DriveTable {
+    int n_terms;
+    const double* theta;
+    const double* f;
+};
+// set `work` to the Hamiltonian of stage s (0: B_1, 1: B_2) of step n of the
+// fourth-order commutator-free integrator (driven.hip)
+void driven_stage(kgf_model* work, const DriveTable& drv, int n, int stage);
+
 // Parameter sets of several models with one bond topology (same L and bond
 // list), for batches whose columns carry different Hamiltonians: column c
 // of a launch uses member c mod n.  The hopping tables (targets, bonds,

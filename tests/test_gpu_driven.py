@@ -85,3 +85,47 @@ def test_propagate_driven_against_oracle(ctx, name):
     v = wl.complex_vector(sec.dim, 90)
     Hl = hamiltonian.Hamiltonian(model_with_theta(H0, th2), sec)
     assert rel_err(to_host(ctx.apply_h(work, ctx.sector(H0.L, nu, nd), to_dev(v))), Hl.apply(v)) < 1e-13
+
+
+def _ring8_drive():
+    H = wl.ring(8, 1.0, 4.0)
+    nb, L = len(H.bonds), H.L
+    k0 = np.zeros(nb + 3 * L)
+    k0[0] = 1.0
+    fld = np.zeros(nb + 3 * L)
+    fld[nb], fld[nb + L] = -1.0, 1.0
+    return H.with_field(0, 0.3), H, [theta_of(H), k0, fld], (lambda t: [1.0, 0.8 * np.sin(2.0 * t), 0.3 * np.cos(t)])
+
+
+@pytest.fixture(scope="module")
+def driven_four_step_oracle():
+    Hi, H, thetas, f = _ring8_drive()
+    sec = basis.Sector(8, 4, 4)
+    v0 = wl.start_vector(sec.dim, 7)
+    say("driven four-step oracle")
+    return driven.four_step(Hi, H, thetas, f, 4, 4, [(0, 0), (1, 0), (2, 1)], 5, 0.2, 2, 15, v0, gs_tol=1e-12)
+
+
+@pytest.mark.parametrize("batch", [0, 2])
+def test_greens_neq_driven_against_oracle(ctx, driven_four_step_oracle, batch):
+    """Four-step G^<, G^> under a driven hopping and field on the half-filled
+    8-site ring (D = 4900, nt = 5, two steps per mesh interval) against the
+    oracle's plain schedule; batch = 2 splits each sweep into one mesh time
+    per block."""
+    Hi, H, thetas, f = _ring8_drive()
+    ora = driven_four_step_oracle
+    s = ctx.sector(8, 4, 4)
+    v0 = to_dev(wl.start_vector(s.dim, 7))
+    say("driven four-step GPU, batch", batch)
+    work = ctx.model(H)
+    got = ctx.greens_neq_driven(ctx.model(Hi), work, s, v0, [(0, 0), (1, 0), (2, 1)], thetas, f, nt=5,
+                                steps_per_grid=2, dt=0.1, krylov_dim=15, reorth=2, batch=batch, gs_tol=1e-12)
+    assert abs(got["E0"] - ora["E0"]) <= 1e-12 * abs(ora["E0"])
+    for key in ("G_lesser", "G_greater"):
+        e = rel_err(got[key], ora[key])
+        say(key, "rel err", e)
+        assert e < 1e-10, key
+    # zero between orbitals of different spin
+    assert not got["G_lesser"][:, :, 2, :2].any() and not got["G_greater"][:, :, :2, 2].any()
+    with pytest.raises(ValueError):
+        ctx.greens_neq_driven(work, work, s, v0, [(0, 0)], thetas, f, nt=2, steps_per_grid=1, dt=0.1)
