@@ -50,7 +50,7 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
-    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven"],
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4"],
                    default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
@@ -404,6 +404,61 @@ def driven(a):
     print(json.dumps(out), flush=True)
 
 
+def driven4(a):
+    """Four-step G^<_00, G^>_00 of the 2x7 ladder quench (U 4 -> 8, D =
+    11,778,624) with the periodic rung drive of the driven mode added to the
+    final Hamiltonian: 11 mesh times 0.1 apart, one commutator-free step (two
+    SIL steps of Krylov dim 20) per interval, timed against the static
+    four-step with the same number of SIL steps (two of 0.05 per interval)."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    q = wl.ladder14()
+    ctx = kgf.Context(0)
+    H = q.H
+    nb, L = len(H.bonds), H.L
+    th0 = np.concatenate([np.asarray(H.t, float), np.asarray(H.eps_up, float), np.asarray(H.eps_dn, float),
+                          np.asarray(H.U, float)])
+    kr = np.zeros(nb + 3 * L)
+    for b, (i, j) in enumerate(H.bonds):
+        if j == i + 1 and i % 2 == 0:
+            kr[b] = 1.0
+    f = lambda t: [1.0, 0.5 * np.sin(2.0 * t)]
+    s = ctx.sector(L, q.n_up, q.n_dn)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, q.gs_seed)).to("cuda:0")
+    m_ini, m_fin, work = ctx.model(q.H_ini), ctx.model(H), ctx.model(H)
+    res, G = {}, {}
+
+    def run(name, nt):
+        if name == "driven":
+            return ctx.greens_neq_driven(m_ini, work, s, v0, q.orbitals, [th0, kr], f, nt=nt, steps_per_grid=1,
+                                         dt=0.1, krylov_dim=q.krylov_dim, gs_tol=q.gs_tol)
+        return ctx.greens_neq(m_ini, m_fin, s, v0, orbitals=q.orbitals, nt=nt, steps_per_grid=2, dt=0.05,
+                              krylov_dim=q.krylov_dim, schedule=1, gs_tol=q.gs_tol)
+    for name in ("driven", "static"):
+        run(name, 2)      # warm-up: hopping tables of the three sectors, workspaces
+        log(f"driven4 {name}: warm-up done")
+    nt = 11
+    for name in ("driven", "static"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = run(name, nt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Gl, Gg = out["G_lesser"][:, :, 0, 0], out["G_greater"][:, :, 0, 0]
+        G[name] = Gl
+        res[name] = {"s": round(el, 3), "anticommutator_err": float(np.abs(np.diag(Gg - Gl) + 1j).max()),
+                     "E0": out["E0"]}
+        log(f"driven4 {name}: {el:.2f} s")
+    sil = 2 * (nt - 1) + 2 * 2 * nt * (nt - 1) // 2
+    print(json.dumps({"metric": "driven four-step on the 2x7 ladder, 11 mesh times, vs static four-step "
+                                "with equal SIL steps", "D": s.dim, "sil_vector_steps": sil, **res,
+                      "overhead": round(res["driven"]["s"] / res["static"]["s"] - 1.0, 3),
+                      "max_abs_Glesser_driven_minus_static": float(np.abs(G["driven"] - G["static"]).max())}),
+          flush=True)
+
+
 def fig1(a):
     """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
     half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
@@ -524,6 +579,9 @@ def main():
         return
     if a.workload == "driven":
         driven(a)
+        return
+    if a.workload == "driven4":
+        driven4(a)
         return
     import numpy as np
     import torch
