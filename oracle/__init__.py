@@ -23,6 +23,9 @@ Modules
                  time-dependent Lanczos G(t) on a fine grid, damped transform
     driven       driven H(t) = sum_j f_j(t) H_j by the fourth-order
                  commutator-free exponential integrator (Sec. 6 outlook)
+    necpt        nonequilibrium cluster-perturbation theory: the CPT equation
+                 (Eq. cpteq) on the discretised Keldysh contour, bath functions
+                 (Eqs. gb1, gb2), free-fermion references for U = 0
     exact        dense references: Jordan-Wigner Fock-space operators,
                  full diagonalisation, matrix exponentials and the U=0
                  closed form used to pin the above
