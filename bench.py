@@ -50,7 +50,7 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
-    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4"],
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4", "necpt"],
                    default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
@@ -459,6 +459,71 @@ def driven4(a):
           flush=True)
 
 
+def necpt_bench(a):
+    """Sec. 5 setting on the GPU: Anderson chain of L_c = 6 sites (U = T = V = 1,
+    field h = 0.2 on the impurity for t < 0, half filling) linked at its last
+    site to a 1000-site bath, t_max = 10, dt = 0.02 (nt = 501): four-step
+    cluster G^<, G^> of all six sites for both spins, bath functions, and the
+    CPT equation on the Keldysh contour per spin (1002 contour points, 6012
+    right-hand sides).  Reports the time of each part, the kernel split of the
+    contour solve and the net polarisation of the first four sites."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    Lc, Lb, V, dt, tmax = 6, 1000, 1.0, 0.02, 10.0
+    nt = int(round(tmax / dt)) + 1
+    ctx = kgf.Context(0)
+    H = wl.chain_siam(Lc, 1.0, 1.0)
+    Hi = H.with_field(0, 0.2)
+    s = ctx.sector(Lc, Lc // 2, Lc // 2)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, 7)).to("cuda:0")
+    orbs = [(i, sp) for sp in (0, 1) for i in range(Lc)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.greens_neq(ctx.model(Hi), ctx.model(H), s, v0, orbs, nt=nt, steps_per_grid=1, dt=dt, krylov_dim=15,
+                         reorth=2, gs_tol=1e-13)
+    t_fs = time.perf_counter() - t0
+    log(f"necpt: cluster four-step {t_fs:.2f} s")
+    t0 = time.perf_counter()
+    gbl, gbg = ctx.bath_chain(Lb, 1.0, nt, dt)
+    torch.cuda.synchronize()
+    t_bath = time.perf_counter() - t0
+    dens, iso = [], []
+    t_cpt = []
+    ctx.profile_begin(1)
+    for sp in (0, 1):
+        idx = [k for k, (_, q) in enumerate(orbs) if q == sp]
+        cl = np.ascontiguousarray(out["G_lesser"][:, :, idx][:, :, :, idx])
+        cg = np.ascontiguousarray(out["G_greater"][:, :, idx][:, :, :, idx])
+        dl, dg = torch.from_numpy(cl).to("cuda:0"), torch.from_numpy(cg).to("cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gl, gg = ctx.necpt(dl, dg, gbl, gbg, Lc - 1, V, dt)
+        torch.cuda.synchronize()
+        t_cpt.append(time.perf_counter() - t0)
+        log(f"necpt: contour solve, spin {sp}: {t_cpt[-1]:.3f} s")
+        dens.append(np.real(-1j * np.einsum("aaii->ai", gl.cpu().numpy())))
+        iso.append(np.real(-1j * np.einsum("aaii->ai", cl)))
+    stats = ctx.profile_end()
+    m_cpt = (dens[0] - dens[1])[:, :4].sum(axis=1)
+    m_iso = (iso[0] - iso[1])[:, :4].sum(axis=1)
+    marks = [0, 100, 200, 300, 400, 500]
+    kern = {k: {"launches": v["launches"], "total_ms": round(v["sampled_ms"], 2)} for k, v in sorted(stats.items())}
+    n, m = 2 * nt, 2 * nt * Lc
+    gemm_flops = 8.0 * (n * n * n + n * n * m + m * m * n)     # 1 - P K, K X, R (K X)
+    zg = stats.get("k_zgemm", {"sampled_ms": 0.0})
+    print(json.dumps({"metric": "NE-CPT, L_c=6 Anderson chain + 1000-site bath, t_max=10, dt=0.02",
+                      "nt": nt, "contour_points": n, "rhs": m, "cluster_four_step_s": round(t_fs, 3),
+                      "bath_s": round(t_bath, 4), "contour_solve_s": [round(x, 4) for x in t_cpt],
+                      "kernels": kern,
+                      "zgemm_TFLOPs": (round(gemm_flops / (zg["sampled_ms"] / 2 * 1e-3) / 1e12, 2)
+                                       if zg["sampled_ms"] else None),
+                      "net_moment_sites_1_4": {f"t={dt * k:g}": [round(float(m_cpt[k]), 5), round(float(m_iso[k]), 5)]
+                                               for k in marks},
+                      "moment_columns": ["NE-CPT", "isolated cluster"]}), flush=True)
+
+
 def fig1(a):
     """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
     half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
@@ -582,6 +647,9 @@ def main():
         return
     if a.workload == "driven4":
         driven4(a)
+        return
+    if a.workload == "necpt":
+        necpt_bench(a)
         return
     import numpy as np
     import torch

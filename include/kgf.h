@@ -234,6 +234,35 @@ int  kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_model* work
                            const double* host_theta, const double* host_f, kgf_c128* host_G_lesser,
                            kgf_c128* host_G_greater, double* host_E0);
 
+/* ---- nonequilibrium cluster-perturbation theory (Sec. 5, Eq. (cpteq)) -------
+ * Contour: the Keldysh contour on the mesh t_k = k dt, k < nt (forward, then
+ * backward); a contour function is G^> where its first time is later on the
+ * contour, G^< where earlier, their mean on the equal-point diagonal; contour
+ * integrals by the trapezoid rule on each branch.  The initial state is the
+ * ground state of the disconnected system (cluster and bath), the
+ * inter-cluster hopping acts for t > 0.
+ *
+ * kgf_bath_chain: Eqs. (gb1), (gb2) for the first site of an L_b-site chain
+ * with hopping -T_b between neighbours and inverse temperature beta (INFINITY:
+ * the ground state; levels at zero half filled), written to the device meshes
+ * G_lesser, G_greater [nt][nt] (complex128, caller-owned).
+ *
+ * kgf_necpt: the cluster block of G = (G'^-1 - V)^-1 for a cluster linked at
+ * its site `boundary` by the hopping V to bath site 1: with the bath
+ * eliminated, G = G^c + G^c * Sigma * G, Sigma = V^2 G^b_11 on `boundary`.
+ * Inputs (device, complex128): the cluster's Gc_lesser, Gc_greater
+ * [nt][nt][n_c][n_c] (one spin; e.g. kgf_greens_neq) and the bath's
+ * Gb_lesser, Gb_greater [nt][nt]; outputs G_lesser, G_greater
+ * [nt][nt][n_c][n_c] (device, caller-owned, not aliasing the inputs).
+ * Workspace ~16 (2 nt n_c)^2 bytes.  KGF_EUNSUPPORTED if 2 nt n_c > 65536,
+ * KGF_EINVAL for a singular contour matrix.  The error of the scheme is
+ * first order in dt. */
+int  kgf_bath_chain(kgf_ctx* ctx, int L_b, double T_b, double beta, int nt, double dt,
+                    kgf_c128* G_lesser, kgf_c128* G_greater);
+int  kgf_necpt(kgf_ctx* ctx, int nt, int n_c, int boundary, double dt, double V,
+               const kgf_c128* Gc_lesser, const kgf_c128* Gc_greater, const kgf_c128* Gb_lesser,
+               const kgf_c128* Gb_greater, kgf_c128* G_lesser, kgf_c128* G_greater);
+
 /* ---- equilibrium spectra (Sec. 2, Sec. 3) ----------------------------------
  * kgf_greens_omega: the conventional Lanczos Green's function of Eq. (gapprox)
  * for orbital a (site*2+spin) from the ground state psi0 (device, in `sector`)

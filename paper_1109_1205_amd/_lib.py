@@ -88,6 +88,8 @@ def load_library():
         "kgf_model_destroy": (None, [P]),
         "kgf_model_set_params": (I, [P, C.POINTER(_ModelDesc)]),
         "kgf_propagate_driven": (I, [P, P, P, P, I, I64, I, I, P, P, C.POINTER(_PropOpts)]),
+        "kgf_bath_chain": (I, [P, I, D, D, I, D, P, P]),
+        "kgf_necpt": (I, [P, I, I, I, D, D, P, P, P, P, P, P]),
         "kgf_greens_neq_driven": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                       P, P, P, P, C.POINTER(D)]),
         "kgf_sector_create": (I, [P, I, I, I, C.POINTER(P)]),
@@ -135,7 +137,8 @@ def exported_symbols() -> Sequence[str]:
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
-            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_profile_begin",
+            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt",
+            "kgf_profile_begin",
             "kgf_profile_end"]
 
 
@@ -514,6 +517,33 @@ class Context:
                                          _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(batch),
                                          _np_ptr(Gl), _np_ptr(Gg), _np_ptr(E0)))
         return {"G_lesser": Gl, "G_greater": Gg, "E0": E0}
+
+    # -- nonequilibrium cluster-perturbation theory ---------------------------
+    def bath_chain(self, L_b: int, T_b: float, nt: int, dt: float, beta: float = float("inf")):
+        """kgf_bath_chain: (G^<, G^>) [nt, nt] device tensors of the first site
+        of an L_b-site chain with hopping -T_b (Eqs. (gb1), (gb2))."""
+        import torch
+        Gl = torch.empty((nt, nt), dtype=torch.complex128, device=f"cuda:{self.device}")
+        Gg = torch.empty_like(Gl)
+        _check(_lib.kgf_bath_chain(self.handle, int(L_b), float(T_b), float(beta), int(nt), float(dt), _ptr(Gl),
+                                   _ptr(Gg)))
+        return Gl, Gg
+
+    def necpt(self, Gc_lesser, Gc_greater, Gb_lesser, Gb_greater, boundary: int, V: float, dt: float):
+        """kgf_necpt: cluster block (G^<, G^>) [nt, nt, n_c, n_c] of the CPT
+        equation on the Keldysh contour; inputs are contiguous complex128
+        device tensors (cluster [nt, nt, n_c, n_c], bath [nt, nt])."""
+        import torch
+        nt, n_c = int(Gc_lesser.shape[0]), int(Gc_lesser.shape[2])
+        for x, shp in ((Gc_lesser, (nt, nt, n_c, n_c)), (Gc_greater, (nt, nt, n_c, n_c)), (Gb_lesser, (nt, nt)),
+                       (Gb_greater, (nt, nt))):
+            if tuple(x.shape) != shp or x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous():
+                raise ValueError(f"necpt: expected a contiguous complex128 device tensor of shape {shp}")
+        Gl = torch.empty_like(Gc_lesser)
+        Gg = torch.empty_like(Gc_lesser)
+        _check(_lib.kgf_necpt(self.handle, nt, n_c, int(boundary), float(dt), float(V), _ptr(Gc_lesser),
+                              _ptr(Gc_greater), _ptr(Gb_lesser), _ptr(Gb_greater), _ptr(Gl), _ptr(Gg)))
+        return Gl, Gg
 
     # -- equilibrium spectra --------------------------------------------------
     def greens_omega(self, model: Model, sec: Sector, psi0, E0: float, orbital: Tuple[int, int], n_lanczos: int,

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkgf.so")
-SOURCES = ["api.hip", "basis.hip", "hamiltonian.hip", "krylov.hip", "greens.hip", "adjoint.hip", "spectral.hip", "driven.hip"]
+SOURCES = ["api.hip", "basis.hip", "hamiltonian.hip", "krylov.hip", "greens.hip", "adjoint.hip", "spectral.hip", "driven.hip", "necpt.hip"]
 ARCH = os.environ.get("KGF_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions stay disabled in all device code.

@@ -1,0 +1,411 @@
+// Nonequilibrium cluster-perturbation theory (Sec. 5, Eq. (cpteq)) on the
+// Keldysh contour.  The CPT equation G = (G'^-1 - V)^-1 for a cluster whose
+// site b is linked by the hopping V to site 1 of an uncorrelated bath reduces,
+// on the cluster, to G = G^c + G^c * Sigma * G with the embedding function
+// Sigma(z, z') = V^2 G^b_11(z, z') acting on site b only (the bath block is
+// eliminated exactly, also after discretisation).  Row b is solved first,
+//     (1 - G^c_bb K) X_j = G^c_bj,   K(p, q) = w_p Sigma(z_p, z_q) w_q,
+// then G_ij = G^c_ij + G^c_ib K X_j.
+// Contour: the mesh t_k = k dt, k < nt, forward (points p = k) then backward
+// (p = 2nt-1-k); a contour function takes G^> where z is later than z', G^<
+// where earlier and their mean on the equal-point diagonal; the contour
+// integral is the trapezoid rule on each branch (weights +dt forward, -dt
+// backward, halved at the ends of each branch).  Dense complex FP64 algebra:
+// an LDS-tiled GEMM and a right-looking LU with partial pivoting.
+#include <cmath>
+#include <vector>
+
+#include "kgf_internal.h"
+
+namespace kgf {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ int ctime(int p, int nt) { return p < nt ? p : 2 * nt - 1 - p; }
+
+__device__ __forceinline__ double cweight(int p, int nt, double dt) {
+    const int k = ctime(p, nt);
+    double w = (nt > 1) ? ((k == 0 || k == nt - 1) ? 0.5 * dt : dt) : 0.0;
+    return p < nt ? w : -w;
+}
+
+// out[p * ldo + q] = s * (weights ? w_p w_q : 1) * G(z_p, z_q), G from the
+// meshes Gl / Gg (element (a, b) at a * sa + b * sb)
+__global__ void k_to_contour(const double2* __restrict__ Gl, const double2* __restrict__ Gg, int nt, int64_t sa,
+                             int64_t sb, double s, int weights, double dt, double2* __restrict__ out, int64_t ldo) {
+    const int n = 2 * nt;
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(e / n), q = (int)(e % n);
+        const int64_t off = ctime(p, nt) * sa + ctime(q, nt) * sb;
+        double2 v;
+        if (p > q) {
+            v = Gg[off];
+        } else if (p < q) {
+            v = Gl[off];
+        } else {
+            const double2 a = Gg[off], b = Gl[off];
+            v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+        }
+        double f = s;
+        if (weights) f *= cweight(p, nt, dt) * cweight(q, nt, dt);
+        out[p * ldo + q] = make_double2(f * v.x, f * v.y);
+    }
+}
+
+__global__ void k_identity(double2* __restrict__ A, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        A[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
+}
+
+// C = alpha A B + beta C, row-major complex; 64x64 tile per 256-thread block,
+// thread (ty, tx) owns rows ty + 16 r and columns tx + 16 c, r, c < 4.
+constexpr int kGT = 64, kGK = 8;
+
+__global__ void __launch_bounds__(256) k_zgemm(int M, int N, int K, double2 alpha, const double2* __restrict__ A,
+                                               int64_t lda, const double2* __restrict__ B, int64_t ldb, double2 beta,
+                                               double2* __restrict__ C, int64_t ldc) {
+    __shared__ double2 As[kGK][kGT];
+    __shared__ double2 Bs[kGK][kGT];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int row0 = blockIdx.y * kGT, col0 = blockIdx.x * kGT;
+    double2 acc[4][4];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < K; k0 += kGK) {
+        for (int e = tid; e < kGT * kGK; e += 256) {
+            const int r = e / kGK, k = e % kGK;          // A tile: 64 rows x 8
+            const int gr = row0 + r, gk = k0 + k;
+            As[k][r] = (gr < M && gk < K) ? A[gr * lda + gk] : make_double2(0.0, 0.0);
+            const int kb = e / kGT, cb = e % kGT;        // B tile: 8 rows x 64
+            const int gkb = k0 + kb, gc = col0 + cb;
+            Bs[kb][cb] = (gkb < K && gc < N) ? B[gkb * ldb + gc] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int k = 0; k < kGK; ++k) {
+            double2 a[4], b[4];
+            for (int r = 0; r < 4; ++r) a[r] = As[k][ty + 16 * r];
+            for (int c = 0; c < 4; ++c) b[c] = Bs[k][tx + 16 * c];
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    acc[r][c].x = fma(a[r].x, b[c].x, fma(-a[r].y, b[c].y, acc[r][c].x));
+                    acc[r][c].y = fma(a[r].x, b[c].y, fma(a[r].y, b[c].x, acc[r][c].y));
+                }
+        }
+        __syncthreads();
+    }
+    const bool use_c = beta.x != 0.0 || beta.y != 0.0;
+    for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + ty + 16 * r;
+        if (gr >= M) continue;
+        for (int c = 0; c < 4; ++c) {
+            const int gc = col0 + tx + 16 * c;
+            if (gc >= N) continue;
+            double2 v = cmul(alpha, acc[r][c]);
+            if (use_c) {
+                const double2 o = cmul(beta, C[gr * ldc + gc]);
+                v.x += o.x;
+                v.y += o.y;
+            }
+            C[gr * ldc + gc] = v;
+        }
+    }
+}
+
+void zgemm(kgf_ctx* ctx, int M, int N, int K, double2 alpha, const double2* A, int64_t lda, const double2* B,
+           int64_t ldb, double2 beta, double2* C, int64_t ldc) {
+    if (M == 0 || N == 0) return;
+    const dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT));
+    Prof pr(ctx, "k_zgemm");
+    hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, ctx->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    check_launch("k_zgemm");
+}
+
+// LU step k, part 1 (one block): pivot row = argmax_{i >= k} |A[i][k]|,
+// swapped with row k in A (n columns) and B (m columns); |pivot| -> piv[k].
+__global__ void __launch_bounds__(256) k_lu_pivot(double2* __restrict__ A, int n, double2* __restrict__ B, int m,
+                                                  int k, double* __restrict__ piv) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = A[(int64_t)i * n + k];
+        const double v = a.x * a.x + a.y * a.y;
+        if (v > best) {
+            best = v;
+            bi = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = sv[threadIdx.x + s];
+            const int oi = si[threadIdx.x + s];
+            if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                sv[threadIdx.x] = o;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int p = si[0];
+    if (threadIdx.x == 0) piv[k] = sqrt(sv[0] > 0.0 ? sv[0] : 0.0);
+    if (p != k) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const double2 t = A[(int64_t)k * n + j];
+            A[(int64_t)k * n + j] = A[(int64_t)p * n + j];
+            A[(int64_t)p * n + j] = t;
+        }
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const double2 t = B[(int64_t)k * m + j];
+            B[(int64_t)k * m + j] = B[(int64_t)p * m + j];
+            B[(int64_t)p * m + j] = t;
+        }
+    }
+}
+
+// LU step k, part 2: rows i > k of [A | B] minus (A[i][k] / A[k][k]) row k,
+// columns > k of A and all of B (column k and row k are only read).
+__global__ void k_lu_elim(double2* __restrict__ A, int n, double2* __restrict__ B, int m, int k) {
+    const int w = (n - k - 1) + m;
+    const int64_t total = (int64_t)(n - k - 1) * w;
+    const double2 d = A[(int64_t)k * n + k];
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 dinv = make_double2(d.x / dd, -d.y / dd);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = k + 1 + (int)(e / w);
+        const int c = (int)(e % w);
+        const double2 l = cmul(A[(int64_t)i * n + k], dinv);
+        double2* dst;
+        double2 src;
+        if (c < n - k - 1) {
+            const int j = k + 1 + c;
+            dst = A + (int64_t)i * n + j;
+            src = A[(int64_t)k * n + j];
+        } else {
+            const int j = c - (n - k - 1);
+            dst = B + (int64_t)i * m + j;
+            src = B[(int64_t)k * m + j];
+        }
+        const double2 t = cmul(l, src);
+        *dst = make_double2(dst->x - t.x, dst->y - t.y);
+    }
+}
+
+// back substitution step k: rows i < k of B minus A[i][k] x_k, x_k = B[k] / A[k][k]
+__global__ void k_lu_back(const double2* __restrict__ A, int n, double2* __restrict__ B, int m, int k) {
+    const int64_t total = (int64_t)k * m;
+    const double2 d = A[(int64_t)k * n + k];
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 dinv = make_double2(d.x / dd, -d.y / dd);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / m), j = (int)(e % m);
+        const double2 x = cmul(B[(int64_t)k * m + j], dinv);
+        const double2 t = cmul(A[(int64_t)i * n + k], x);
+        B[(int64_t)i * m + j] = make_double2(B[(int64_t)i * m + j].x - t.x, B[(int64_t)i * m + j].y - t.y);
+    }
+}
+
+__global__ void k_lu_scale(const double2* __restrict__ A, int n, double2* __restrict__ B, int m) {
+    const int64_t total = (int64_t)n * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / m);
+        const double2 d = A[(int64_t)i * n + i];
+        const double dd = d.x * d.x + d.y * d.y;
+        B[e] = cmul(B[e], make_double2(d.x / dd, -d.y / dd));
+    }
+}
+
+unsigned grid_for(int64_t total) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kThreads - 1) / kThreads, 8192));
+}
+
+// Solve A X = B in place (A: n x n, B: n x m, row-major); false if a pivot
+// vanishes or is not finite.
+bool lu_solve(kgf_ctx* ctx, double2* A, int n, double2* B, int m, double* piv_dev) {
+    for (int k = 0; k < n; ++k) {
+        {
+            Prof pr(ctx, "k_lu_pivot");
+            hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(256), 0, ctx->stream, A, n, B, m, k, piv_dev);
+            check_launch("k_lu_pivot");
+        }
+        const int64_t total = (int64_t)(n - k - 1) * ((n - k - 1) + m);
+        if (total > 0) {
+            Prof pr(ctx, "k_lu_elim");
+            hipLaunchKernelGGL(k_lu_elim, dim3(grid_for(total)), dim3(kThreads), 0, ctx->stream, A, n, B, m, k);
+            check_launch("k_lu_elim");
+        }
+    }
+    std::vector<double> piv(n);
+    KGF_HIP(hipMemcpyAsync(piv.data(), piv_dev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    for (int k = 0; k < n; ++k)
+        if (!(piv[k] > 0.0) || !std::isfinite(piv[k])) return false;
+    for (int k = n - 1; k > 0; --k) {
+        const int64_t total = (int64_t)k * m;
+        Prof pr(ctx, "k_lu_back");
+        hipLaunchKernelGGL(k_lu_back, dim3(grid_for(total)), dim3(kThreads), 0, ctx->stream, A, n, B, m, k);
+        check_launch("k_lu_back");
+    }
+    hipLaunchKernelGGL(k_lu_scale, dim3(grid_for((int64_t)n * m)), dim3(kThreads), 0, ctx->stream, A, n, B, m);
+    check_launch("k_lu_scale");
+    return true;
+}
+
+// G[a][b][i][j] = Gc[a][b][i][j] + C[(i n + p) * ldc + j n + q] with
+// (p, q) = (a forward, b backward) for G^< and (a backward, b forward) for G^>
+__global__ void k_extract(const double2* __restrict__ Gcl, const double2* __restrict__ Gcg,
+                          const double2* __restrict__ C, int64_t ldc, int nt, int nc, double2* __restrict__ Gl,
+                          double2* __restrict__ Gg) {
+    const int n = 2 * nt;
+    const int64_t total = (int64_t)nt * nt * nc * nc;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e % nc);
+        const int i = (int)((e / nc) % nc);
+        const int b = (int)((e / ((int64_t)nc * nc)) % nt);
+        const int a = (int)(e / ((int64_t)nc * nc * nt));
+        const double2 cl = C[((int64_t)i * n + a) * ldc + (int64_t)j * n + (n - 1 - b)];
+        const double2 cg = C[((int64_t)i * n + (n - 1 - a)) * ldc + (int64_t)j * n + b];
+        Gl[e] = make_double2(Gcl[e].x + cl.x, Gcl[e].y + cl.y);
+        Gg[e] = make_double2(Gcg[e].x + cg.x, Gcg[e].y + cg.y);
+    }
+}
+
+// Eqs. (gb1), (gb2) for site 1 of an L_b-site chain with hopping -T_b between
+// neighbours: levels e_k = -2 T_b cos(k pi / (L_b + 1)), weights
+// u_k^2 = 2 sin^2(k pi / (L_b + 1)) / (L_b + 1), occupations 1 / (e^{beta e} + 1)
+// (beta = inf: 1, 1/2, 0 for e <, =, > 0, |e| <= 1e-12 max(1, 2|T_b|) counting as
+// zero); one thread per time difference d = a - b.
+__global__ void k_bath_chain(int Lb, double Tb, double beta, int nt, double dt, double2* __restrict__ gl_d,
+                             double2* __restrict__ gg_d) {
+    const int nd = 2 * nt - 1;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += gridDim.x * blockDim.x) {
+        const double tau = (double)(e - (nt - 1)) * dt;
+        double lr = 0.0, li = 0.0, gr = 0.0, gi = 0.0;
+        for (int k = 1; k <= Lb; ++k) {
+            const double th = M_PI * k / (Lb + 1);
+            const double ek = -2.0 * Tb * cos(th);
+            const double sn = sin(th);
+            const double u2 = 2.0 * sn * sn / (Lb + 1);
+            const bool zero = fabs(ek) <= 1e-12 * fmax(1.0, 2.0 * fabs(Tb));   // a zero level, up to rounding
+            double f;
+            if (isinf(beta))
+                f = zero ? 0.5 : (ek < 0.0 ? 1.0 : 0.0);
+            else
+                f = 1.0 / (exp(beta * ek) + 1.0);
+            double s, c;
+            sincos(ek * tau, &s, &c);        // e^{-i e tau} = c - i s
+            // G^< = +i u2 f (c - i s) = u2 f (s + i c);  G^> = -i u2 (1-f) (c - i s) = u2 (1-f) (-s - i c)
+            lr += u2 * f * s;
+            li += u2 * f * c;
+            gr -= u2 * (1.0 - f) * s;
+            gi -= u2 * (1.0 - f) * c;
+        }
+        gl_d[e] = make_double2(lr, li);
+        gg_d[e] = make_double2(gr, gi);
+    }
+}
+
+__global__ void k_expand_diff(const double2* __restrict__ gl_d, const double2* __restrict__ gg_d, int nt,
+                              double2* __restrict__ Gl, double2* __restrict__ Gg) {
+    const int64_t total = (int64_t)nt * nt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / nt), b = (int)(e % nt);
+        Gl[e] = gl_d[a - b + nt - 1];
+        Gg[e] = gg_d[a - b + nt - 1];
+    }
+}
+
+}  // namespace
+
+}  // namespace kgf
+
+using namespace kgf;
+
+extern "C" int kgf_bath_chain(kgf_ctx* ctx, int L_b, double T_b, double beta, int nt, double dt,
+                              kgf_c128* G_lesser, kgf_c128* G_greater) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && G_lesser && G_greater, KGF_EINVAL, "kgf_bath_chain: NULL argument");
+        KGF_REQUIRE(L_b >= 1 && nt >= 1 && std::isfinite(T_b) && std::isfinite(dt) && dt >= 0.0 &&
+                        !std::isnan(beta) && beta > 0.0,
+                    KGF_EINVAL, "kgf_bath_chain: bad L_b / nt / T_b / dt / beta");
+        KGF_HIP(hipSetDevice(ctx->device));
+        const int nd = 2 * nt - 1;
+        double2* d = static_cast<double2*>(workspace(ctx, "cpt_bath_d", sizeof(double2) * 2 * (size_t)nd));
+        hipLaunchKernelGGL(k_bath_chain, dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, ctx->stream, L_b, T_b, beta,
+                           nt, dt, d, d + nd);
+        check_launch("k_bath_chain");
+        hipLaunchKernelGGL(k_expand_diff, dim3(grid_for((int64_t)nt * nt)), dim3(kThreads), 0, ctx->stream, d,
+                           d + nd, nt, reinterpret_cast<double2*>(G_lesser), reinterpret_cast<double2*>(G_greater));
+        check_launch("k_expand_diff");
+        sync(ctx);
+    });
+}
+
+extern "C" int kgf_necpt(kgf_ctx* ctx, int nt, int n_c, int boundary, double dt, double V,
+                         const kgf_c128* Gc_lesser, const kgf_c128* Gc_greater, const kgf_c128* Gb_lesser,
+                         const kgf_c128* Gb_greater, kgf_c128* G_lesser, kgf_c128* G_greater) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && Gc_lesser && Gc_greater && Gb_lesser && Gb_greater && G_lesser && G_greater, KGF_EINVAL,
+                    "kgf_necpt: NULL argument");
+        KGF_REQUIRE(nt >= 1 && n_c >= 1 && boundary >= 0 && boundary < n_c, KGF_EINVAL,
+                    "kgf_necpt: bad nt / n_c / boundary");
+        KGF_REQUIRE(std::isfinite(dt) && dt >= 0.0 && std::isfinite(V), KGF_EINVAL, "kgf_necpt: bad dt / V");
+        KGF_REQUIRE((int64_t)2 * nt * n_c <= 65536, KGF_EUNSUPPORTED, "kgf_necpt: 2 nt n_c above 65536");
+        KGF_HIP(hipSetDevice(ctx->device));
+        const int n = 2 * nt, m = n * n_c;
+        const auto* gcl = reinterpret_cast<const double2*>(Gc_lesser);
+        const auto* gcg = reinterpret_cast<const double2*>(Gc_greater);
+        const auto* gbl = reinterpret_cast<const double2*>(Gb_lesser);
+        const auto* gbg = reinterpret_cast<const double2*>(Gb_greater);
+        const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+        ensure_device_fits(sizeof(double2) * (3 * nn + 3 * nm + (size_t)m * m), "NE-CPT contour matrices");
+        auto buf = [&](const char* name, size_t elems) {
+            return static_cast<double2*>(workspace(ctx, name, sizeof(double2) * elems));
+        };
+        double2* P = buf("cpt_P", nn);     // G^c_bb on the contour
+        double2* K = buf("cpt_K", nn);     // w Sigma w
+        double2* A = buf("cpt_A", nn);     // 1 - P K
+        double2* X = buf("cpt_X", nm);     // G^c_bj -> X_j (columns j n + q)
+        double2* Y = buf("cpt_Y", nm);     // K X
+        double2* R = buf("cpt_R", nm);     // G^c_ib stacked by rows (i n + p)
+        double2* C = buf("cpt_C", (size_t)m * m);
+        double* piv = static_cast<double*>(workspace(ctx, "cpt_piv", sizeof(double) * n));
+        const int64_t sa = (int64_t)nt * n_c * n_c, sb = (int64_t)n_c * n_c;   // mesh strides of [a][b][i][j]
+        const unsigned g = grid_for((int64_t)nn);
+        auto contour = [&](const double2* l, const double2* gg, int64_t sa_, int64_t sb_, double s, int wts,
+                           double2* out, int64_t ldo) {
+            hipLaunchKernelGGL(k_to_contour, dim3(g), dim3(kThreads), 0, ctx->stream, l, gg, nt, sa_, sb_, s, wts,
+                               dt, out, ldo);
+            check_launch("k_to_contour");
+        };
+        const int64_t bb = (int64_t)boundary * n_c + boundary;
+        contour(gcl + bb, gcg + bb, sa, sb, 1.0, 0, P, n);
+        contour(gbl, gbg, nt, 1, V * V, 1, K, n);
+        for (int j = 0; j < n_c; ++j) {
+            const int64_t bj = (int64_t)boundary * n_c + j, ib = (int64_t)j * n_c + boundary;
+            contour(gcl + bj, gcg + bj, sa, sb, 1.0, 0, X + (size_t)j * n, m);
+            contour(gcl + ib, gcg + ib, sa, sb, 1.0, 0, R + (size_t)j * nn, n);
+        }
+        hipLaunchKernelGGL(k_identity, dim3(g), dim3(kThreads), 0, ctx->stream, A, n);
+        check_launch("k_identity");
+        zgemm(ctx, n, n, n, make_double2(-1.0, 0.0), P, n, K, n, make_double2(1.0, 0.0), A, n);
+        KGF_REQUIRE(lu_solve(ctx, A, n, X, m, piv), KGF_EINVAL, "kgf_necpt: singular contour matrix 1 - G^c_bb K");
+        zgemm(ctx, n, m, n, make_double2(1.0, 0.0), K, n, X, m, make_double2(0.0, 0.0), Y, m);
+        zgemm(ctx, m, m, n, make_double2(1.0, 0.0), R, n, Y, m, make_double2(0.0, 0.0), C, m);
+        hipLaunchKernelGGL(k_extract, dim3(grid_for((int64_t)nt * nt * n_c * n_c)), dim3(kThreads), 0, ctx->stream,
+                           gcl, gcg, C, (int64_t)m, nt, n_c, reinterpret_cast<double2*>(G_lesser),
+                           reinterpret_cast<double2*>(G_greater));
+        check_launch("k_extract");
+        sync(ctx);
+        progress(ctx, "necpt", 1, 1);
+    });
+}
