@@ -958,9 +958,12 @@ void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int 
         const size_t row_bytes = sizeof(double2) * (size_t)sec->d_dn;
         const int rpx = (int)((sec->d_up + 7) / 8);
         dim3 grid((unsigned)(8 * rpx), (unsigned)ncol);
+        // one lane per row element (whole wavefronts, at most kHvThreads):
+        // short rows of small sectors do not launch 1024 mostly idle threads
+        const int thr = (int)std::min<int64_t>(kHvThreads, std::max<int64_t>(64, (sec->d_dn + 63) / 64 * 64));
         auto kern = uu ? k_hv_lds<MODE, true> : k_hv_lds<MODE, false>;
         opt_in_lds(ctx, (const void*)kern, 2 * MODE + (uu ? 1 : 0), kRowLdsMax);
-        hipLaunchKernelGGL(kern, grid, dim3(kHvThreads), row_bytes, ctx->stream, T, rpx, x, x_col, xp,
+        hipLaunchKernelGGL(kern, grid, dim3(thr), row_bytes, ctx->stream, T, rpx, x, x_col, xp,
                            xp_col, y, y_col, s_k, b_k, s_km1, stride, part);
         check_launch("k_hv_lds");
         return;
