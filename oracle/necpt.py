@@ -15,10 +15,20 @@ beta -> infinity), V acts for t > 0, and the contour is the Keldysh contour
 0 -> t_max -> 0 on the mesh t_k = k dt, k = 0..nt-1: contour point index
 p = 0..nt-1 is t_p on the forward branch, p = nt..2nt-1 is t_{2nt-1-p} on the
 backward branch.  A contour function is G^>(t, t') where z is later than z'
-and G^<(t, t') where z is earlier; on the equal-point diagonal it takes the
-mean (G^> + G^<)/2.  The contour integral is the trapezoid rule on each
-branch: weight +dt on the forward and -dt on the backward branch, halved at
-both ends of each branch.
+and G^<(t, t') where z is earlier.  The contour integral is the trapezoid
+rule on each branch (weight +dt on the forward and -dt on the backward
+branch, halved at both ends of each branch), with every jump of the
+integrand at a node: at an interior node the integrand takes the mean of its
+two one-sided limits, so the equal-point diagonal of G' is (G^> + G^<)/2.
+At the four branch ends (t = 0 forward, t_max forward, t_max backward, t = 0
+backward) only the limit from inside the branch enters, and it differs
+between the two places where G' appears in  (1 - G' W V) G = G':
+as the kernel G'(z, z''), z'' -> z from inside the branch, it is G^< at a
+branch start and G^> at a branch end ("row" values); as the right-hand side
+it fixes the diagonal of the unknown G, which is later used as G(z'', z'),
+z'' -> z' from inside the branch, so there it is G^> at a branch start and
+G^< at a branch end ("rhs" values).  With the mean at the branch ends
+instead, the scheme is only first order in dt.
 """
 from __future__ import annotations
 
@@ -37,12 +47,15 @@ def contour_points(nt: int, dt: float):
     return tix, np.concatenate([w, -w[::-1]])
 
 
-def to_contour(G_lesser: np.ndarray, G_greater: np.ndarray) -> np.ndarray:
+def to_contour(G_lesser: np.ndarray, G_greater: np.ndarray, role: str = "row") -> np.ndarray:
     """[nt, nt, n, n] lesser / greater meshes -> contour matrix
-    [2nt * n, 2nt * n], row (p, i) = p * n + i."""
+    [2nt * n, 2nt * n], row (p, i) = p * n + i; role "row" or "rhs" picks the
+    one-sided diagonal values at the branch ends (module docstring)."""
     nt, n = G_lesser.shape[0], G_lesser.shape[2]
     tix, _ = contour_points(nt, 1.0)
     N = 2 * nt
+    starts = {0, nt} if nt > 1 else set()
+    ends = {nt - 1, N - 1} if nt > 1 else set()
     out = np.zeros((N, n, N, n), dtype=np.complex128)
     for p in range(N):
         for q in range(N):
@@ -51,6 +64,10 @@ def to_contour(G_lesser: np.ndarray, G_greater: np.ndarray) -> np.ndarray:
                 blk = G_greater[a, b]
             elif p < q:
                 blk = G_lesser[a, b]
+            elif p in starts:
+                blk = G_lesser[a, b] if role == "row" else G_greater[a, b]
+            elif p in ends:
+                blk = G_greater[a, b] if role == "row" else G_lesser[a, b]
             else:
                 blk = 0.5 * (G_greater[a, b] + G_lesser[a, b])
             out[p, :, q, :] = blk
@@ -94,16 +111,17 @@ def bath_greens(T: np.ndarray, nt: int, dt: float, beta: float = np.inf, sites=N
 
 def cpt_solve(Gp_lesser: np.ndarray, Gp_greater: np.ndarray, V: np.ndarray, dt: float):
     """The discretised CPT equation on the contour:
-    (1 - G' W V) G = G', with W the diagonal of quadrature weights (V is
-    instantaneous, so the contour integral over z'' carries one weight).
+    (1 - G'_row W V) G = G'_rhs, with W the diagonal of quadrature weights
+    (V is instantaneous, so the contour integral over z'' carries one
+    weight) and G'_row, G'_rhs the contour matrices of G' with the row and
+    rhs values at the branch ends.
     Gp_*: [nt, nt, n, n] meshes of the disconnected system; V: [n, n].
     Returns the (G^<, G^>) meshes of the connected system."""
     nt, n = Gp_lesser.shape[0], Gp_lesser.shape[2]
-    Gz = to_contour(Gp_lesser, Gp_greater)
     _, w = contour_points(nt, dt)
     WV = np.kron(np.diag(w), V)
-    A = np.eye(2 * nt * n) - Gz @ WV
-    G = scipy.linalg.solve(A, Gz)
+    A = np.eye(2 * nt * n) - to_contour(Gp_lesser, Gp_greater, "row") @ WV
+    G = scipy.linalg.solve(A, to_contour(Gp_lesser, Gp_greater, "rhs"))
     return from_contour(G, nt, n)
 
 
