@@ -237,8 +237,9 @@ int  kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_model* work
 /* ---- nonequilibrium cluster-perturbation theory (Sec. 5, Eq. (cpteq)) -------
  * Contour: the Keldysh contour on the mesh t_k = k dt, k < nt (forward, then
  * backward); a contour function is G^> where its first time is later on the
- * contour, G^< where earlier, their mean on the equal-point diagonal; contour
- * integrals by the trapezoid rule on each branch.  The initial state is the
+ * contour, G^< where earlier; contour integrals by the trapezoid rule on each
+ * branch with the integrand's jumps at nodes (mean of the one-sided limits at
+ * interior nodes, the limit from inside the branch at branch ends).  The initial state is the
  * ground state of the disconnected system (cluster and bath), the
  * inter-cluster hopping acts for t > 0.
  *
@@ -256,7 +257,7 @@ int  kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_model* work
  * [nt][nt][n_c][n_c] (device, caller-owned, not aliasing the inputs).
  * Workspace ~16 (2 nt n_c)^2 bytes.  KGF_EUNSUPPORTED if 2 nt n_c > 65536,
  * KGF_EINVAL for a singular contour matrix.  The error of the scheme is
- * first order in dt. */
+ * second order in dt. */
 int  kgf_bath_chain(kgf_ctx* ctx, int L_b, double T_b, double beta, int nt, double dt,
                     kgf_c128* G_lesser, kgf_c128* G_greater);
 int  kgf_necpt(kgf_ctx* ctx, int nt, int n_c, int boundary, double dt, double V,

@@ -8,10 +8,16 @@
 // then G_ij = G^c_ij + G^c_ib K X_j.
 // Contour: the mesh t_k = k dt, k < nt, forward (points p = k) then backward
 // (p = 2nt-1-k); a contour function takes G^> where z is later than z', G^<
-// where earlier and their mean on the equal-point diagonal; the contour
-// integral is the trapezoid rule on each branch (weights +dt forward, -dt
-// backward, halved at the ends of each branch).  Dense complex FP64 algebra:
-// an LDS-tiled GEMM and a right-looking LU with partial pivoting.
+// where earlier; the contour integral is the trapezoid rule on each branch
+// (weights +dt forward, -dt backward, halved at the ends of each branch) with
+// the integrand's jumps at nodes.  On the equal-point diagonal an interior
+// node takes the mean (G^> + G^<)/2; a branch end takes the limit from inside
+// its branch, which depends on where the matrix enters: as the kernel
+// G(z, z'') ("row": G^< at a branch start, G^> at a branch end) or as the
+// right-hand side, whose diagonal becomes the unknown's and is later used
+// as G(z'', z') ("rhs": the other way round).  This makes the scheme second
+// order in dt (first order with the mean at the ends as well).  Dense complex
+// FP64 algebra: an LDS-tiled GEMM and a right-looking LU with partial pivoting.
 #include <cmath>
 #include <vector>
 
@@ -34,9 +40,11 @@ __device__ __forceinline__ double cweight(int p, int nt, double dt) {
 }
 
 // out[p * ldo + q] = s * (weights ? w_p w_q : 1) * G(z_p, z_q), G from the
-// meshes Gl / Gg (element (a, b) at a * sa + b * sb)
+// meshes Gl / Gg (element (a, b) at a * sa + b * sb); rhs = 0: row values at
+// the branch ends, 1: right-hand-side values
 __global__ void k_to_contour(const double2* __restrict__ Gl, const double2* __restrict__ Gg, int nt, int64_t sa,
-                             int64_t sb, double s, int weights, double dt, double2* __restrict__ out, int64_t ldo) {
+                             int64_t sb, double s, int weights, int rhs, double dt, double2* __restrict__ out,
+                             int64_t ldo) {
     const int n = 2 * nt;
     const int64_t total = (int64_t)n * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -47,6 +55,9 @@ __global__ void k_to_contour(const double2* __restrict__ Gl, const double2* __re
             v = Gg[off];
         } else if (p < q) {
             v = Gl[off];
+        } else if (nt > 1 && (p == 0 || p == nt || p == nt - 1 || p == n - 1)) {
+            const bool start = p == 0 || p == nt;                 // first point of its branch
+            v = (start != (rhs != 0)) ? Gl[off] : Gg[off];
         } else {
             const double2 a = Gg[off], b = Gl[off];
             v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
@@ -382,18 +393,19 @@ extern "C" int kgf_necpt(kgf_ctx* ctx, int nt, int n_c, int boundary, double dt,
         const int64_t sa = (int64_t)nt * n_c * n_c, sb = (int64_t)n_c * n_c;   // mesh strides of [a][b][i][j]
         const unsigned g = grid_for((int64_t)nn);
         auto contour = [&](const double2* l, const double2* gg, int64_t sa_, int64_t sb_, double s, int wts,
-                           double2* out, int64_t ldo) {
+                           int rhs, double2* out, int64_t ldo) {
             hipLaunchKernelGGL(k_to_contour, dim3(g), dim3(kThreads), 0, ctx->stream, l, gg, nt, sa_, sb_, s, wts,
-                               dt, out, ldo);
+                               rhs, dt, out, ldo);
             check_launch("k_to_contour");
         };
+        // kernels of the integral (P, K, R): row values; right-hand sides (X): rhs values
         const int64_t bb = (int64_t)boundary * n_c + boundary;
-        contour(gcl + bb, gcg + bb, sa, sb, 1.0, 0, P, n);
-        contour(gbl, gbg, nt, 1, V * V, 1, K, n);
+        contour(gcl + bb, gcg + bb, sa, sb, 1.0, 0, 0, P, n);
+        contour(gbl, gbg, nt, 1, V * V, 1, 0, K, n);
         for (int j = 0; j < n_c; ++j) {
             const int64_t bj = (int64_t)boundary * n_c + j, ib = (int64_t)j * n_c + boundary;
-            contour(gcl + bj, gcg + bj, sa, sb, 1.0, 0, X + (size_t)j * n, m);
-            contour(gcl + ib, gcg + ib, sa, sb, 1.0, 0, R + (size_t)j * nn, n);
+            contour(gcl + bj, gcg + bj, sa, sb, 1.0, 0, 1, X + (size_t)j * n, m);
+            contour(gcl + ib, gcg + ib, sa, sb, 1.0, 0, 0, R + (size_t)j * nn, n);
         }
         hipLaunchKernelGGL(k_identity, dim3(g), dim3(kThreads), 0, ctx->stream, A, n);
         check_launch("k_identity");

@@ -115,8 +115,9 @@ def test_necpt_degenerate_cases(ctx):
 def test_necpt_u0_paper_sizes_property(ctx):
     """1000-site bath, dt = 0.02, t_max = 5, six cluster sites, U = 0: the
     CPT equation is exact there, so the GPU result equals the free-fermion G
-    of the connected 1006-site chain within the scheme's first-order error
-    (measured 0.5% of the coupling's effect)."""
+    of the connected 1006-site chain within the scheme's second-order error
+    (the same scheme evaluated on the CPU: 1.5e-4 of the coupling's effect,
+    equal-time anticommutator off by 1.0e-4)."""
     Lc, Lb, V, dt, nt = 6, 1000, 1.0, 0.02, 251
     hc = _chain(Lc)
     hci = hc.copy()
@@ -141,7 +142,7 @@ def test_necpt_u0_paper_sizes_property(ctx):
     effect = np.abs(El - Gcl).max()
     err = max(np.abs(gl - El).max(), np.abs(gg - Eg).max())
     say("err / effect", err / effect)
-    assert effect > 0.2 and err < 0.01 * effect
+    assert effect > 0.2 and err < 5e-4 * effect
     # equal times: G^> - G^< = -i to the same order
     d = np.einsum("aaij->aij", gg - gl)
-    assert np.abs(d + 1j * np.eye(Lc)).max() < 0.02
+    assert np.abs(d + 1j * np.eye(Lc)).max() < 5e-4
