@@ -537,8 +537,9 @@ class Context:
         nt, n_c = int(Gc_lesser.shape[0]), int(Gc_lesser.shape[2])
         for x, shp in ((Gc_lesser, (nt, nt, n_c, n_c)), (Gc_greater, (nt, nt, n_c, n_c)), (Gb_lesser, (nt, nt)),
                        (Gb_greater, (nt, nt))):
-            if tuple(x.shape) != shp or x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous():
-                raise ValueError(f"necpt: expected a contiguous complex128 device tensor of shape {shp}")
+            if (tuple(x.shape) != shp or x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous()
+                    or x.device.index != self.device):
+                raise ValueError(f"necpt: expected a contiguous complex128 tensor of shape {shp} on cuda:{self.device}")
         Gl = torch.empty_like(Gc_lesser)
         Gg = torch.empty_like(Gc_lesser)
         _check(_lib.kgf_necpt(self.handle, nt, n_c, int(boundary), float(dt), float(V), _ptr(Gc_lesser),
