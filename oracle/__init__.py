@@ -23,6 +23,9 @@ Modules
                  time-dependent Lanczos G(t) on a fine grid, damped transform
     driven       driven H(t) = sum_j f_j(t) H_j by the fourth-order
                  commutator-free exponential integrator (Sec. 6 outlook)
+    greens2      a four-time two-particle Green's function
+                 <c+_a(t1) c+_b(t2) c_c(t3) c_d(t4)> by dense propagation of
+                 two-time states (Sec. 6 outlook: higher-order functions)
     necpt        nonequilibrium cluster-perturbation theory: the CPT equation
                  (Eq. cpteq) on the discretised Keldysh contour, bath functions
                  (Eqs. gb1, gb2), free-fermion references for U = 0
