@@ -801,6 +801,129 @@ void greens_neq_driven(kgf_ctx* ctx, kgf_model* Hi, kgf_model* work, const kgf_s
         release(ctx, nm);
 }
 
+// Four-time two-particle function (the outlook's higher-order Green's
+// functions): chi_abcd(t1,t2,t3,t4) = <0|c+_a(t1) c+_b(t2) c_c(t3) c_d(t4)|0>
+// = <Psi_ba(t2,t1) | Psi_cd(t3,t4)> with the two-time states
+// Psi_xy(s,u) = e^{iHs} c_x e^{-iH(s-u)} c_y Phi(u), Phi(u) = e^{-iHu}|0>.
+// Per spin class (spin of x, spin of y): c_y Phi(u) is carried through the
+// mesh in the N-1 sector (forward from u, then backward from u), c_x applied
+// at every mesh time s; the resulting columns, laid out with s slowest, go
+// back to t = 0 in one sweep (the columns with s >= k form a contiguous tail
+// that takes one mesh interval at step k).  chi is the Gram matrix between
+// the classes that end in the same N-2 sector.  host_chi:
+// [nt][nt][nt][nt][norb][norb][norb][norb], zero where the spins do not match.
+void greens2_neq(kgf_ctx* ctx, kgf_model* Hi, kgf_model* H, const kgf_sector* sec, const double2* v0,
+                 const kgf_gs_opts* gso, const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o,
+                 double2* chi_host, double* E0_host) {
+    const int64_t D = sec->dim();
+    const size_t vb = sizeof(double2) * (size_t)D;
+    ensure_device_fits(vb * (size_t)nt, "four-time function: forward mesh");
+    double2* Phi = static_cast<double2*>(workspace(ctx, "g2_phi", vb * (size_t)nt));
+    GsResult gs = ground_state(ctx, Hi, sec, v0, Phi, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
+    KGF_REQUIRE(gs.converged, KGF_ENOCONV, "four-time function: the ground state of H_ini did not converge");
+    *E0_host = gs.E0;
+    release(ctx, "gs_V");
+    release(ctx, "gs_partbig");
+    SilOpts fo = o, bo = o;
+    fo.direction = -1;
+    bo.direction = +1;
+    for (int t = 1; t < nt; ++t) {
+        double2* cur = Phi + (size_t)t * D;
+        KGF_HIP(hipMemcpyAsync(cur, cur - D, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        sil_propagate(ctx, H, sec, cur, 1, D, spg, fo);
+    }
+    std::vector<int> by_spin[2];
+    for (int a = 0; a < norb; ++a) by_spin[orbs[a] & 1].push_back(a);
+    struct Class {
+        int sx, sy, nx, ny;
+        std::unique_ptr<kgf_sector> s2;
+        double2* Z = nullptr;
+    };
+    std::vector<Class> cls;
+    const int64_t total_chi = (int64_t)nt * nt * nt * nt * norb * norb * norb * norb;
+    std::fill(chi_host, chi_host + total_chi, make_double2(0.0, 0.0));
+    for (int sx = 0; sx < 2; ++sx)
+        for (int sy = 0; sy < 2; ++sy) {
+            const int nx = (int)by_spin[sx].size(), ny = (int)by_spin[sy].size();
+            if (!nx || !ny) continue;
+            auto s1 = shifted(ctx, sec, sy, -1);
+            if (!s1 || s1->dim() == 0) continue;
+            auto s2 = shifted(ctx, s1.get(), sx, -1);
+            if (!s2 || s2->dim() == 0) continue;
+            const int64_t D1 = s1->dim(), D2 = s2->dim();
+            const int blk = nt * nx * ny;                       // columns per mesh time s
+            const size_t zb = sizeof(double2) * (size_t)nt * blk * D2;
+            ensure_device_fits(zb + 2 * sizeof(double2) * (size_t)ny * D1, "four-time function: two-time states");
+            const std::string zname = "g2_Z" + std::to_string(2 * sx + sy);
+            double2* Z = static_cast<double2*>(workspace(ctx, zname, zb));
+            double2* W = static_cast<double2*>(workspace(ctx, "g2_W", sizeof(double2) * (size_t)ny * D1));
+            double2* W0 = static_cast<double2*>(workspace(ctx, "g2_W0", sizeof(double2) * (size_t)ny * D1));
+            // column ((s * nt + u) * nx + i) * ny + j  <->  Psi_{x_i y_j}(t_s, t_u)
+            auto emit = [&](int s_, int u_) {
+                for (int i = 0; i < nx; ++i)
+                    apply_c(ctx, s1.get(), s2.get(), orbs[by_spin[sx][i]], 0, W,
+                            Z + (size_t)(((int64_t)s_ * nt + u_) * nx + i) * ny * D2, ny, D1, D2);
+            };
+            for (int u = 0; u < nt; ++u) {
+                for (int j = 0; j < ny; ++j)
+                    apply_c(ctx, sec, s1.get(), orbs[by_spin[sy][j]], 0, Phi + (size_t)u * D, W0 + (size_t)j * D1, 1,
+                            D, D1);
+                KGF_HIP(hipMemcpyAsync(W, W0, sizeof(double2) * (size_t)ny * D1, hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+                emit(u, u);
+                for (int s_ = u + 1; s_ < nt; ++s_) {              // e^{-iH(t_s - t_u)}, s > u
+                    sil_propagate(ctx, H, s1.get(), W, ny, D1, spg, fo);
+                    emit(s_, u);
+                }
+                KGF_HIP(hipMemcpyAsync(W, W0, sizeof(double2) * (size_t)ny * D1, hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+                for (int s_ = u - 1; s_ >= 0; --s_) {              // s < u
+                    sil_propagate(ctx, H, s1.get(), W, ny, D1, spg, bo);
+                    emit(s_, u);
+                }
+                progress(ctx, "four_time_states", u + 1, nt);
+            }
+            for (int k = nt - 1; k >= 1; --k)                       // e^{iH t_s}: columns s >= k, one interval
+                sil_propagate(ctx, H, s2.get(), Z + (size_t)k * blk * D2, (nt - k) * blk, D2, spg, bo);
+            Class c;
+            c.sx = sx;
+            c.sy = sy;
+            c.nx = nx;
+            c.ny = ny;
+            c.s2 = std::move(s2);
+            c.Z = Z;
+            cls.push_back(std::move(c));
+        }
+    for (const Class& bra : cls)
+        for (const Class& ket : cls) {
+            if (bra.s2->n_up != ket.s2->n_up || bra.s2->n_dn != ket.s2->n_dn) continue;
+            const int nl = nt * nt * bra.nx * bra.ny, nr = nt * nt * ket.nx * ket.ny;
+            double2* gram = static_cast<double2*>(workspace(ctx, "g2_gram", sizeof(double2) * (size_t)nl * nr));
+            block_dots(ctx, bra.Z, bra.s2->dim(), nl, ket.Z, ket.s2->dim(), nr, bra.s2->dim(), gram, nr);
+            std::vector<double2> h((size_t)nl * nr);
+            KGF_HIP(hipMemcpyAsync(h.data(), gram, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            // bra column (s = t2, u = t1, x = b, y = a); ket column (s = t3, u = t4, x = c, y = d)
+            for (int l = 0; l < nl; ++l) {
+                const int jb = l % bra.ny, ib = (l / bra.ny) % bra.nx;
+                const int u1 = (l / (bra.ny * bra.nx)) % nt, s2_ = l / (bra.ny * bra.nx * nt);
+                const int A = by_spin[bra.sy][jb], B = by_spin[bra.sx][ib];
+                for (int r = 0; r < nr; ++r) {
+                    const int jk = r % ket.ny, ik = (r / ket.ny) % ket.nx;
+                    const int u4 = (r / (ket.ny * ket.nx)) % nt, s3 = r / (ket.ny * ket.nx * nt);
+                    const int Cc = by_spin[ket.sx][ik], Dd = by_spin[ket.sy][jk];
+                    const int64_t e =
+                        ((((((((int64_t)u1 * nt + s2_) * nt + s3) * nt + u4) * norb + A) * norb + B) * norb + Cc) *
+                             norb +
+                         Dd);
+                    chi_host[e] = h[(size_t)l * nr + r];
+                }
+            }
+        }
+    for (const char* nm : {"g2_phi", "g2_W", "g2_W0", "g2_gram", "g2_Z0", "g2_Z1", "g2_Z2", "g2_Z3", "sil_X"})
+        release(ctx, nm);
+}
+
 }  // namespace kgf
 
 using namespace kgf;
@@ -913,5 +1036,32 @@ extern "C" int kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_m
                           gs_opts, host_orbs, n_orb, nt, steps_per_grid, kgf::to_sil_opts(opts), batch,
                           kgf::DriveTable{n_terms, host_theta, host_f}, reinterpret_cast<double2*>(host_G_lesser),
                           reinterpret_cast<double2*>(host_G_greater), host_E0);
+    });
+}
+
+extern "C" int kgf_greens2_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
+                               const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
+                               int nt, int steps_per_grid, const kgf_prop_opts* opts, kgf_c128* host_chi,
+                               double* host_E0) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(ctx && H_ini && H && sector && gs_opts && v0 && host_orbs && host_chi && host_E0, KGF_EINVAL,
+                    "kgf_greens2_neq: NULL argument");
+        KGF_REQUIRE(H_ini->L == sector->L && H->L == sector->L, KGF_EINVAL,
+                    "kgf_greens2_neq: models and sector differ in L");
+        KGF_REQUIRE(sector->dim() > 0, KGF_EINVAL, "kgf_greens2_neq: empty sector");
+        kgf::check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1, KGF_EINVAL, "kgf_greens2_neq: bad sizes");
+        const double n4 = (double)nt * nt * nt * nt * n_orb * n_orb * n_orb * n_orb;
+        KGF_REQUIRE(n4 <= (double)(1 << 28), KGF_EUNSUPPORTED, "kgf_greens2_neq: nt^4 n_orb^4 above 2^28");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                    KGF_EINVAL, "kgf_greens2_neq: bad ground-state options");
+        for (int a = 0; a < n_orb; ++a)
+            KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
+                        "kgf_greens2_neq: orbital out of range");
+        KGF_HIP(hipSetDevice(ctx->device));
+        greens2_neq(ctx, const_cast<kgf_model*>(H_ini), const_cast<kgf_model*>(H), sector,
+                    reinterpret_cast<const double2*>(v0), gs_opts, host_orbs, n_orb, nt, steps_per_grid,
+                    kgf::to_sil_opts(opts), reinterpret_cast<double2*>(host_chi), host_E0);
     });
 }
