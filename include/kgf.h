@@ -234,22 +234,25 @@ int  kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_model* work
                            const double* host_theta, const double* host_f, kgf_c128* host_G_lesser,
                            kgf_c128* host_G_greater, double* host_E0);
 
-/* ---- a four-time two-particle Green's function (Sec. 6 outlook) -------------
+/* ---- four-time two-particle Green's functions (Sec. 6 outlook) --------------
  * kgf_greens2_neq: after the ground state |0> of H_ini in `sector` (from v0,
  * gs_opts) and the switch to H at t = 0, on the mesh t_k = k * steps_per_grid
  * * opts->dt, k < nt:
  *   host_chi[k1][k2][k3][k4][a][b][c][d]
- *     = <0| c+_a(t_k1) c+_b(t_k2) c_c(t_k3) c_d(t_k4) |0>,
- * c(t) = e^{iHt} c e^{-iHt}, for the n_orb orbital codes (site*2+spin) in
- * host_orbs; zero where the spins cannot match.  Evaluated from the two-time
- * states c_x(t_s) c_y(t_u)|0> (SIL steps of opts; c_y e^{-iHt_u}|0> carried
- * through the mesh in the N-1 sector, c_x applied at every mesh time, all of
- * them returned to t = 0 in one sweep) and their scalar products.  host_chi
- * (caller-owned, nt^4 n_orb^4 complex128, at most 2^28 entries) and host_E0
- * are host arrays.  KGF_ENOCONV if the ground state does not converge. */
+ *     = <0| O1_a(t_k1) O2_b(t_k2) O3_c(t_k3) O4_d(t_k4) |0>,
+ * O(t) = e^{iHt} O e^{-iHt}, O_m = c+ where bit (4 - m) of `pattern` is set,
+ * else c (pattern 0b1100 = 12: c+ c+ c c; exactly two bits set, KGF_EINVAL
+ * otherwise), for the n_orb orbital codes (site*2+spin) in host_orbs; zero
+ * where the spins cannot match.  Evaluated as the scalar products of the
+ * two-time states O2_b(t2)^+ O1_a(t1)^+ |0> and O3_c(t3) O4_d(t4) |0> (SIL
+ * steps of opts; the inner operator's state carried through the mesh, the
+ * outer operator applied at every mesh time, all states returned to t = 0 in
+ * one sweep).  host_chi (caller-owned, nt^4 n_orb^4 complex128, at most 2^28
+ * entries) and host_E0 are host arrays.  KGF_ENOCONV if the ground state does
+ * not converge. */
 int  kgf_greens2_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
                      const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
-                     int nt, int steps_per_grid, const kgf_prop_opts* opts, kgf_c128* host_chi,
+                     int nt, int steps_per_grid, const kgf_prop_opts* opts, int pattern, kgf_c128* host_chi,
                      double* host_E0);
 
 /* ---- nonequilibrium cluster-perturbation theory (Sec. 5, Eq. (cpteq)) -------

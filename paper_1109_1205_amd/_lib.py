@@ -88,7 +88,7 @@ def load_library():
         "kgf_model_destroy": (None, [P]),
         "kgf_model_set_params": (I, [P, C.POINTER(_ModelDesc)]),
         "kgf_propagate_driven": (I, [P, P, P, P, I, I64, I, I, P, P, C.POINTER(_PropOpts)]),
-        "kgf_greens2_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), P,
+        "kgf_greens2_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, P,
                                 C.POINTER(D)]),
         "kgf_bath_chain": (I, [P, I, D, D, I, D, P, P]),
         "kgf_necpt": (I, [P, I, I, I, D, D, P, P, P, P, P, P]),
@@ -521,13 +521,15 @@ class Context:
         return {"G_lesser": Gl, "G_greater": Gg, "E0": E0}
 
     def greens2_neq(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
-                    steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0, gs_tol: float = 1e-12,
-                    gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                    steps_per_grid: int, dt: float, pattern=(1, 1, 0, 0), krylov_dim: int = 15, reorth: int = 0,
+                    gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
                     breakdown_tol: float = 1e-13):
         """kgf_greens2_neq: chi[k1, k2, k3, k4, a, b, c, d] =
-        <0| c+_a(t_k1) c+_b(t_k2) c_c(t_k3) c_d(t_k4) |0> after the ground
-        state of H_ini, t_k = k * steps_per_grid * dt.  Returns chi and E0."""
+        <0| O1_a(t_k1) O2_b(t_k2) O3_c(t_k3) O4_d(t_k4) |0> after the ground
+        state of H_ini, t_k = k * steps_per_grid * dt, O_m = c+ where
+        pattern[m] else c (default c+ c+ c c).  Returns chi and E0."""
         self._chk(v0, sec.dim, "v0")
+        bits = sum(int(bool(q)) << (3 - m) for m, q in enumerate(pattern))
         orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
         no = len(orbs)
         chi = _host_c128((nt, nt, nt, nt, no, no, no, no))
@@ -535,8 +537,8 @@ class Context:
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
         g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
         _check(_lib.kgf_greens2_neq(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
-                                    _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), _np_ptr(chi),
-                                    C.byref(E0)))
+                                    _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), bits,
+                                    _np_ptr(chi), C.byref(E0)))
         return {"chi": chi, "E0": E0.value}
 
     # -- nonequilibrium cluster-perturbation theory ---------------------------

@@ -801,20 +801,27 @@ void greens_neq_driven(kgf_ctx* ctx, kgf_model* Hi, kgf_model* work, const kgf_s
         release(ctx, nm);
 }
 
-// Four-time two-particle function (the outlook's higher-order Green's
-// functions): chi_abcd(t1,t2,t3,t4) = <0|c+_a(t1) c+_b(t2) c_c(t3) c_d(t4)|0>
-// = <Psi_ba(t2,t1) | Psi_cd(t3,t4)> with the two-time states
-// Psi_xy(s,u) = e^{iHs} c_x e^{-iH(s-u)} c_y Phi(u), Phi(u) = e^{-iHu}|0>.
-// Per spin class (spin of x, spin of y): c_y Phi(u) is carried through the
-// mesh in the N-1 sector (forward from u, then backward from u), c_x applied
-// at every mesh time s; the resulting columns, laid out with s slowest, go
-// back to t = 0 in one sweep (the columns with s >= k form a contiguous tail
-// that takes one mesh interval at step k).  chi is the Gram matrix between
-// the classes that end in the same N-2 sector.  host_chi:
+// Four-time two-particle functions (the outlook's higher-order Green's
+// functions): chi_abcd(t1,t2,t3,t4) = <0| O1_a(t1) O2_b(t2) O3_c(t3) O4_d(t4) |0>,
+// O = c or c+ (two of each), as the scalar product of the two-time states
+// O2_b(t2)^+ O1_a(t1)^+ |0> and O3_c(t3) O4_d(t4) |0>.  A two-time state
+// o_x(s) o_y(u)|0> = e^{iHs} o_x e^{-iH(s-u)} o_y Phi(u), Phi(u) = e^{-iHu}|0>:
+// per spin class (spin of x, spin of y), o_y Phi(u) is carried through the
+// mesh in its sector (forward from u, then backward from u), o_x applied at
+// every mesh time s; the resulting columns, laid out with s slowest, go back
+// to t = 0 in one sweep (the columns with s >= k form a contiguous tail that
+// takes one mesh interval at step k).  chi is the Gram matrix between bra and
+// ket classes that end in the same sector.  host_chi:
 // [nt][nt][nt][nt][norb][norb][norb][norb], zero where the spins do not match.
+struct TwoTimeClass {
+    int sx, sy, nx, ny;
+    std::unique_ptr<kgf_sector> s2;
+    double2* Z = nullptr;
+};
+
 void greens2_neq(kgf_ctx* ctx, kgf_model* Hi, kgf_model* H, const kgf_sector* sec, const double2* v0,
                  const kgf_gs_opts* gso, const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o,
-                 double2* chi_host, double* E0_host) {
+                 const int dag[4], double2* chi_host, double* E0_host) {
     const int64_t D = sec->dim();
     const size_t vb = sizeof(double2) * (size_t)D;
     ensure_device_fits(vb * (size_t)nt, "four-time function: forward mesh");
@@ -834,68 +841,74 @@ void greens2_neq(kgf_ctx* ctx, kgf_model* Hi, kgf_model* H, const kgf_sector* se
     }
     std::vector<int> by_spin[2];
     for (int a = 0; a < norb; ++a) by_spin[orbs[a] & 1].push_back(a);
-    struct Class {
-        int sx, sy, nx, ny;
-        std::unique_ptr<kgf_sector> s2;
-        double2* Z = nullptr;
-    };
-    std::vector<Class> cls;
     const int64_t total_chi = (int64_t)nt * nt * nt * nt * norb * norb * norb * norb;
     std::fill(chi_host, chi_host + total_chi, make_double2(0.0, 0.0));
-    for (int sx = 0; sx < 2; ++sx)
-        for (int sy = 0; sy < 2; ++sy) {
-            const int nx = (int)by_spin[sx].size(), ny = (int)by_spin[sy].size();
-            if (!nx || !ny) continue;
-            auto s1 = shifted(ctx, sec, sy, -1);
-            if (!s1 || s1->dim() == 0) continue;
-            auto s2 = shifted(ctx, s1.get(), sx, -1);
-            if (!s2 || s2->dim() == 0) continue;
-            const int64_t D1 = s1->dim(), D2 = s2->dim();
-            const int blk = nt * nx * ny;                       // columns per mesh time s
-            const size_t zb = sizeof(double2) * (size_t)nt * blk * D2;
-            ensure_device_fits(zb + 2 * sizeof(double2) * (size_t)ny * D1, "four-time function: two-time states");
-            const std::string zname = "g2_Z" + std::to_string(2 * sx + sy);
-            double2* Z = static_cast<double2*>(workspace(ctx, zname, zb));
-            double2* W = static_cast<double2*>(workspace(ctx, "g2_W", sizeof(double2) * (size_t)ny * D1));
-            double2* W0 = static_cast<double2*>(workspace(ctx, "g2_W0", sizeof(double2) * (size_t)ny * D1));
-            // column ((s * nt + u) * nx + i) * ny + j  <->  Psi_{x_i y_j}(t_s, t_u)
-            auto emit = [&](int s_, int u_) {
-                for (int i = 0; i < nx; ++i)
-                    apply_c(ctx, s1.get(), s2.get(), orbs[by_spin[sx][i]], 0, W,
-                            Z + (size_t)(((int64_t)s_ * nt + u_) * nx + i) * ny * D2, ny, D1, D2);
-            };
-            for (int u = 0; u < nt; ++u) {
-                for (int j = 0; j < ny; ++j)
-                    apply_c(ctx, sec, s1.get(), orbs[by_spin[sy][j]], 0, Phi + (size_t)u * D, W0 + (size_t)j * D1, 1,
-                            D, D1);
-                KGF_HIP(hipMemcpyAsync(W, W0, sizeof(double2) * (size_t)ny * D1, hipMemcpyDeviceToDevice,
-                                       ctx->stream));
-                emit(u, u);
-                for (int s_ = u + 1; s_ < nt; ++s_) {              // e^{-iH(t_s - t_u)}, s > u
-                    sil_propagate(ctx, H, s1.get(), W, ny, D1, spg, fo);
-                    emit(s_, u);
+
+    // all states o_x(t_s) o_y(t_u)|0> (o = c+ where the flag is set), class by class
+    auto family = [&](int dx, int dy, const char* tag) {
+        std::vector<TwoTimeClass> cls;
+        for (int sx = 0; sx < 2; ++sx)
+            for (int sy = 0; sy < 2; ++sy) {
+                const int nx = (int)by_spin[sx].size(), ny = (int)by_spin[sy].size();
+                if (!nx || !ny) continue;
+                auto s1 = shifted(ctx, sec, sy, dy ? +1 : -1);
+                if (!s1 || s1->dim() == 0) continue;
+                auto s2 = shifted(ctx, s1.get(), sx, dx ? +1 : -1);
+                if (!s2 || s2->dim() == 0) continue;
+                const int64_t D1 = s1->dim(), D2 = s2->dim();
+                const int blk = nt * nx * ny;                       // columns per mesh time s
+                const size_t zb = sizeof(double2) * (size_t)nt * blk * D2;
+                ensure_device_fits(zb + 2 * sizeof(double2) * (size_t)ny * D1, "four-time function: two-time states");
+                const std::string zname = std::string(tag) + std::to_string(2 * sx + sy);
+                double2* Z = static_cast<double2*>(workspace(ctx, zname, zb));
+                double2* W = static_cast<double2*>(workspace(ctx, "g2_W", sizeof(double2) * (size_t)ny * D1));
+                double2* W0 = static_cast<double2*>(workspace(ctx, "g2_W0", sizeof(double2) * (size_t)ny * D1));
+                // column ((s * nt + u) * nx + i) * ny + j  <->  o_{x_i}(t_s) o_{y_j}(t_u)|0>
+                auto emit = [&](int s_, int u_) {
+                    for (int i = 0; i < nx; ++i)
+                        apply_c(ctx, s1.get(), s2.get(), orbs[by_spin[sx][i]], dx, W,
+                                Z + (size_t)(((int64_t)s_ * nt + u_) * nx + i) * ny * D2, ny, D1, D2);
+                };
+                for (int u = 0; u < nt; ++u) {
+                    for (int j = 0; j < ny; ++j)
+                        apply_c(ctx, sec, s1.get(), orbs[by_spin[sy][j]], dy, Phi + (size_t)u * D,
+                                W0 + (size_t)j * D1, 1, D, D1);
+                    KGF_HIP(hipMemcpyAsync(W, W0, sizeof(double2) * (size_t)ny * D1, hipMemcpyDeviceToDevice,
+                                           ctx->stream));
+                    emit(u, u);
+                    for (int s_ = u + 1; s_ < nt; ++s_) {              // e^{-iH(t_s - t_u)}, s > u
+                        sil_propagate(ctx, H, s1.get(), W, ny, D1, spg, fo);
+                        emit(s_, u);
+                    }
+                    KGF_HIP(hipMemcpyAsync(W, W0, sizeof(double2) * (size_t)ny * D1, hipMemcpyDeviceToDevice,
+                                           ctx->stream));
+                    for (int s_ = u - 1; s_ >= 0; --s_) {              // s < u
+                        sil_propagate(ctx, H, s1.get(), W, ny, D1, spg, bo);
+                        emit(s_, u);
+                    }
+                    progress(ctx, "four_time_states", u + 1, nt);
                 }
-                KGF_HIP(hipMemcpyAsync(W, W0, sizeof(double2) * (size_t)ny * D1, hipMemcpyDeviceToDevice,
-                                       ctx->stream));
-                for (int s_ = u - 1; s_ >= 0; --s_) {              // s < u
-                    sil_propagate(ctx, H, s1.get(), W, ny, D1, spg, bo);
-                    emit(s_, u);
-                }
-                progress(ctx, "four_time_states", u + 1, nt);
+                for (int k = nt - 1; k >= 1; --k)                       // e^{iH t_s}: columns s >= k, one interval
+                    sil_propagate(ctx, H, s2.get(), Z + (size_t)k * blk * D2, (nt - k) * blk, D2, spg, bo);
+                TwoTimeClass c;
+                c.sx = sx;
+                c.sy = sy;
+                c.nx = nx;
+                c.ny = ny;
+                c.s2 = std::move(s2);
+                c.Z = Z;
+                cls.push_back(std::move(c));
             }
-            for (int k = nt - 1; k >= 1; --k)                       // e^{iH t_s}: columns s >= k, one interval
-                sil_propagate(ctx, H, s2.get(), Z + (size_t)k * blk * D2, (nt - k) * blk, D2, spg, bo);
-            Class c;
-            c.sx = sx;
-            c.sy = sy;
-            c.nx = nx;
-            c.ny = ny;
-            c.s2 = std::move(s2);
-            c.Z = Z;
-            cls.push_back(std::move(c));
-        }
-    for (const Class& bra : cls)
-        for (const Class& ket : cls) {
+        return cls;
+    };
+    // kets O3_c(t3) O4_d(t4)|0>; bras O2_b(t2)^+ O1_a(t1)^+ |0>
+    std::vector<TwoTimeClass> kets = family(dag[2], dag[3], "g2k_Z");
+    std::vector<TwoTimeClass> bras_own;
+    const bool same = (1 - dag[1]) == dag[2] && (1 - dag[0]) == dag[3];
+    if (!same) bras_own = family(1 - dag[1], 1 - dag[0], "g2b_Z");
+    const std::vector<TwoTimeClass>& bras = same ? kets : bras_own;
+    for (const TwoTimeClass& bra : bras)
+        for (const TwoTimeClass& ket : kets) {
             if (bra.s2->n_up != ket.s2->n_up || bra.s2->n_dn != ket.s2->n_dn) continue;
             const int nl = nt * nt * bra.nx * bra.ny, nr = nt * nt * ket.nx * ket.ny;
             double2* gram = static_cast<double2*>(workspace(ctx, "g2_gram", sizeof(double2) * (size_t)nl * nr));
@@ -920,7 +933,8 @@ void greens2_neq(kgf_ctx* ctx, kgf_model* Hi, kgf_model* H, const kgf_sector* se
                 }
             }
         }
-    for (const char* nm : {"g2_phi", "g2_W", "g2_W0", "g2_gram", "g2_Z0", "g2_Z1", "g2_Z2", "g2_Z3", "sil_X"})
+    for (const char* nm : {"g2_phi", "g2_W", "g2_W0", "g2_gram", "g2k_Z0", "g2k_Z1", "g2k_Z2", "g2k_Z3", "g2b_Z0",
+                           "g2b_Z1", "g2b_Z2", "g2b_Z3", "sil_X"})
         release(ctx, nm);
 }
 
@@ -1041,8 +1055,8 @@ extern "C" int kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_m
 
 extern "C" int kgf_greens2_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
                                const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
-                               int nt, int steps_per_grid, const kgf_prop_opts* opts, kgf_c128* host_chi,
-                               double* host_E0) {
+                               int nt, int steps_per_grid, const kgf_prop_opts* opts, int pattern,
+                               kgf_c128* host_chi, double* host_E0) {
     return kgf::abi_guard([&] {
         KGF_REQUIRE(ctx && H_ini && H && sector && gs_opts && v0 && host_orbs && host_chi && host_E0, KGF_EINVAL,
                     "kgf_greens2_neq: NULL argument");
@@ -1059,9 +1073,12 @@ extern "C" int kgf_greens2_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_m
         for (int a = 0; a < n_orb; ++a)
             KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
                         "kgf_greens2_neq: orbital out of range");
+        KGF_REQUIRE(pattern >= 0 && pattern < 16 && __builtin_popcount((unsigned)pattern) == 2, KGF_EINVAL,
+                    "kgf_greens2_neq: pattern must hold two c+ and two c");
+        const int dag[4] = {(pattern >> 3) & 1, (pattern >> 2) & 1, (pattern >> 1) & 1, pattern & 1};
         KGF_HIP(hipSetDevice(ctx->device));
         greens2_neq(ctx, const_cast<kgf_model*>(H_ini), const_cast<kgf_model*>(H), sector,
                     reinterpret_cast<const double2*>(v0), gs_opts, host_orbs, n_orb, nt, steps_per_grid,
-                    kgf::to_sil_opts(opts), reinterpret_cast<double2*>(host_chi), host_E0);
+                    kgf::to_sil_opts(opts), dag, reinterpret_cast<double2*>(host_chi), host_E0);
     });
 }
