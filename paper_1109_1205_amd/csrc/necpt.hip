@@ -156,8 +156,8 @@ __global__ void __launch_bounds__(256) k_lu_pivot(double2* __restrict__ A, int n
     sv[threadIdx.x] = best;
     si[threadIdx.x] = bi;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
             const double o = sv[threadIdx.x + s];
             const int oi = si[threadIdx.x + s];
             if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
