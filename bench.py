@@ -50,7 +50,8 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
-    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4", "necpt"],
+    p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4", "necpt",
+                                           "two_particle"],
                    default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
@@ -524,6 +525,39 @@ def necpt_bench(a):
                       "moment_columns": ["NE-CPT", "isolated cluster"]}), flush=True)
 
 
+def two_particle(a):
+    """Four-time function <c+_a(t1) c+_b(t2) c_c(t3) c_d(t4)> of the L = 8
+    Anderson chain (U = 2, field 0.2 on the impurity for t < 0, sector (4,4),
+    D = 4900) for the impurity and the far end, both spins (4 orbitals), on
+    8 mesh times 0.2 apart (4 SIL steps of Krylov dim 15 per interval)."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    ctx = kgf.Context(0)
+    H = wl.chain_siam(8, 2.0, 1.0)
+    Hi = H.with_field(0, 0.2)
+    s = ctx.sector(8, 4, 4)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, 7)).to("cuda:0")
+    orbs = [(0, 0), (7, 0), (0, 1), (7, 1)]
+    nt, spg = 8, 4
+    mi, mh = ctx.model(Hi), ctx.model(H)
+    ctx.greens2_neq(mi, mh, s, v0, orbs, nt=2, steps_per_grid=1, dt=0.05)      # warm-up (tables)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.greens2_neq(mi, mh, s, v0, orbs, nt=nt, steps_per_grid=spg, dt=0.05)
+    el = time.perf_counter() - t0
+    nx = ny = 2
+    per_class = nt * (nt - 1) * spg * ny + sum((nt - k) * nt * nx * ny for k in range(1, nt)) * spg
+    vsteps = 4 * per_class + (nt - 1) * spg
+    chi = out["chi"]
+    print(json.dumps({"metric": "four-time function, L=8 Anderson chain, 4 orbitals, 8x8x8x8 mesh", "D": s.dim,
+                      "elapsed_s": round(el, 3), "sil_vector_steps": vsteps,
+                      "vector_steps_per_s": round(vsteps / el, 1), "E0": out["E0"],
+                      "equal_time_antisymmetry_err": float(max(
+                          np.abs(chi[k, k] + np.swapaxes(chi[k, k], -4, -3)).max() for k in range(nt)))}), flush=True)
+
+
 def fig1(a):
     """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
     half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
@@ -650,6 +684,9 @@ def main():
         return
     if a.workload == "necpt":
         necpt_bench(a)
+        return
+    if a.workload == "two_particle":
+        two_particle(a)
         return
     import numpy as np
     import torch
