@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark: four-step nonequilibrium G(t,t') on the 2x7 Hubbard ladder.
 
-Workload (one "step" = one pass of the whole hot path): half-filled open
-2x7 Hubbard ladder (t=1, D = 3432 x 3432 = 11,778,624), sudden quench
-U: 4 -> 8; (i) ground state of H_ini by Lanczos, (ii) forward SIL
-propagation to t_max = 5 (100 steps of dt = 0.05, Krylov dim 20),
-(iii) backward propagation of c Phi(t_k) and c+ Phi(t_k) for every mesh
-time, (iv) G^<_00(t,t') and G^>_00(t,t') on the 101 x 101 mesh.
+Workload: half-filled open 2x7 Hubbard ladder (t=1, D = 3432 x 3432 =
+11,778,624), sudden quench U: 4 -> 8; (i) ground state of H_ini by Lanczos,
+(ii) forward SIL propagation to t_max = 5 (100 steps of dt = 0.05, Krylov
+dim 20), (iii) backward propagation of c Phi(t_k) and c+ Phi(t_k) for every
+mesh time, (iv) G^<_00(t,t') and G^>_00(t,t') on the 101 x 101 mesh.
 Inputs are synthetic and seeded (start vector seed 7); everything is
 resident in HBM when the timed region starts.
 
-value = contour steps/s: single-vector SIL steps (each Krylov dim H.v
-products) completed per second over the whole four-step run.
+One timed "step" is one mesh interval of the backward sweep (steps (iii)
+and (iv)) at the production block width: the block of columns
+e^{iH(t_j - t_s)} c Phi(t_j) (as many as the free device memory holds) is
+dotted with c Phi(t_s) (step (iv)) and moved from t_s to t_{s-1} by one
+SIL step (Krylov dim 20, batched over the columns).  The ground state, the
+forward mesh and the sweep's growth phase (block narrower than the
+production width) run before the timed region and are timed separately;
+after it the run is finished, so the line also reports the whole four-step
+run (all 10,200 vector-steps) and checks the equal-time anticommutator of
+the full G.
+
+value = contour steps/s: single-column SIL steps (each Krylov dim H.v
+products) completed per second in the timed intervals.
 roofline: the Lanczos-fused H.v kernel (the dominant kernel), algorithmic
 bytes per launch = 16 B x D x columns x (2 or 3 vector passes), divided by
 its launch durations measured with HIP events on the library's stream.
@@ -39,8 +49,13 @@ def log(*a):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=1)
-    p.add_argument("--warmup", type=int, default=0)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--whole", action="store_true",
+                   help="time whole four-step runs per step (kgf_greens_neq; both schedules) instead of "
+                        "sweep intervals")
+    p.add_argument("--no-finish", action="store_true",
+                   help="stop after the timed intervals instead of finishing the four-step run")
     p.add_argument("--schedule", choices=["sweep", "plain"], default="sweep")
     p.add_argument("--batch", type=int, default=0, help="sweep block width cap (0 = from free memory)")
     p.add_argument("--reorth", type=int, default=0)
@@ -636,20 +651,23 @@ def measured_traffic():
 
 def cpu_baseline(q):
     """The oracle as it stands: one SIL step (Krylov dim 20) of a c-sector
-    vector of the same ladder on the host cores."""
-    import numpy as np
+    vector of the same ladder on the host, BLAS/OpenMP pools held to one
+    thread (scipy.sparse products and NumPy elementwise work are
+    single-threaded anyway)."""
     import workloads as wl
     from oracle import basis, hamiltonian, propagate
+    from threadpoolctl import threadpool_limits
     sec = basis.Sector(14, 6, 7)
     H = hamiltonian.Hamiltonian(q.H, sec)
     v = wl.complex_vector(sec.dim, 1)
-    t0 = time.perf_counter()
-    propagate.sil_step(H.apply, v, q.dt, q.krylov_dim, +1, reorth="none")
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "vector-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one SIL step (Krylov dim {q.krylov_dim}, dt={q.dt}) of a random D={sec.dim} "
-                       f"c-sector vector of the 2x7 ladder with the NumPy/SciPy oracle, {dt:.1f} s; "
-                       f"scipy.sparse products are single-threaded (host os.cpu_count()={os.cpu_count()})")}
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        propagate.sil_step(H.apply, v, q.dt, q.krylov_dim, +1, reorth="none")
+        dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "vector-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one SIL step (Krylov dim {q.krylov_dim}, dt={q.dt}, no reorthogonalisation) of a random "
+                       f"D={sec.dim} c-sector vector of the 2x7 ladder with the NumPy/SciPy oracle, {dt:.1f} s on "
+                       f"one thread (host os.cpu_count()={os.cpu_count()})")}
 
 
 def main():
@@ -688,6 +706,143 @@ def main():
     if a.workload == "two_particle":
         two_particle(a)
         return
+    if a.whole:
+        whole_runs(a)
+        return
+    stepwise(a)
+
+
+def roofline_of(stats, kernel="hv_lanczos"):
+    """roofline object of the dominant kernel from the library's HIP-event
+    samples, plus a per-class kernel table."""
+    dom = max(stats.items(), key=lambda kv: kv[1]["sampled_ms"] / max(kv[1]["sampled"], 1) * kv[1]["launches"])
+    hv = stats.get(kernel, dom[1])
+    achieved = hv["sampled_bytes"] / (hv["sampled_ms"] * 1e-3) / 1e9 if hv["sampled_ms"] > 0 else 0.0
+    tb = measured_traffic()
+    avg_launch_bytes = hv["sampled_bytes"] / max(hv["sampled"], 1)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": (round(tb * avg_launch_bytes) if tb is not None else None),
+                "kernel": kernel, "avg_launch_ms": round(hv["sampled_ms"] / max(hv["sampled"], 1), 5),
+                "avg_launch_algorithmic_bytes": round(avg_launch_bytes),
+                "dominant_class": dom[0]}
+    kernels = {k: {"launches": v["launches"], "avg_ms": round(v["sampled_ms"] / max(v["sampled"], 1), 5),
+                   "total_ms": round(v["sampled_ms"] * v["launches"] / max(v["sampled"], 1), 1),
+                   "GBps": (round(v["sampled_bytes"] / (v["sampled_ms"] * 1e-3) / 1e9, 1)
+                            if v["sampled_bytes"] and v["sampled_ms"] else None)}
+               for k, v in sorted(stats.items())}
+    return roofline, kernels
+
+
+WORKLOAD_14 = ("ladder14 quench: 2x7 open Hubbard ladder t=1, half filling, D=11,778,624, U 4->8, "
+               "G^<_00 and G^>_00 on 101x101, Krylov dim 20, dt=0.05")
+
+
+def stepwise(a):
+    """Default mode: the four-step run of the 2x7 ladder through
+    kgf_neq_run_*, one timed step = one backward-sweep mesh interval at the
+    production block width."""
+    import numpy as np
+    import torch
+
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+
+    q = wl.ladder14()
+    ctx = kgf.Context(0)
+    if a.tune:
+        ctx.set_option(ctx.HV_TUNE, 1)
+    m_ini, m_fin = ctx.model(q.H_ini), ctx.model(q.H)
+    sec = ctx.sector(14, q.n_up, q.n_dn)
+    v0 = torch.from_numpy(wl.start_vector(sec.dim, q.gs_seed)).to("cuda:0")
+    vec_total = (q.nt - 1) * q.steps_per_grid + 2 * q.steps_per_grid * q.nt * (q.nt - 1) // 2
+    phases = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = ctx.neq_run(m_ini, m_fin, sec, v0, q.orbitals, nt=q.nt, steps_per_grid=q.steps_per_grid, dt=q.dt,
+                      krylov_dim=q.krylov_dim, reorth=a.reorth, batch=a.batch, gs_tol=q.gs_tol)
+    torch.cuda.synchronize()
+    phases["ground_state_and_forward_mesh_s"] = round(time.perf_counter() - t0, 3)
+    log(f"ground state + forward mesh: {phases['ground_state_and_forward_mesh_s']} s (E0 = {run.E0})")
+    # growth phase: advance until the next interval runs at the chunk's full width
+    # with enough full-width intervals left for warm-up and timed steps
+    t0 = time.perf_counter()
+    info = run.advance(0)
+    grow_steps = 0
+    while not info["done"]:
+        if (info["next_width"] == info["chunk_width"]
+                and info["next_mesh_index"] >= a.warmup + a.steps):
+            break
+        info = run.advance(1)
+        grow_steps += info["vector_steps"]
+    torch.cuda.synchronize()
+    phases["sweep_growth_s"] = round(time.perf_counter() - t0, 3)
+    phases["sweep_growth_vector_steps"] = grow_steps
+    width = info["next_width"]
+    log(f"sweep growth: {phases['sweep_growth_s']} s; production block width {width} columns, "
+        f"{info['next_mesh_index']} full-width intervals left in this chunk")
+    for w in range(a.warmup):
+        run.advance(1)
+    torch.cuda.synchronize()
+    log(f"warm-up: {a.warmup} interval(s)")
+    ctx.profile_begin(a.profile_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timed_steps, widths = 0, []
+    for k in range(a.steps):
+        r = run.advance(1)
+        timed_steps += r["vector_steps"]
+        widths.append(r["width"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.profile_end()
+    elapsed = t1 - t0
+    log(f"timed: {a.steps} interval(s), {timed_steps} vector-steps in {elapsed:.3f} s")
+    roofline, kernels = roofline_of(stats)
+    anti, full = None, None
+    if not a.no_finish:
+        t0 = time.perf_counter()
+        while not run.advance(8)["done"]:
+            pass
+        torch.cuda.synchronize()
+        phases["rest_of_run_s"] = round(time.perf_counter() - t0, 3)
+        out = run.result()
+        Gl, Gg = out["G_lesser"][:, :, 0, 0], out["G_greater"][:, :, 0, 0]
+        anti = float(np.abs(np.diag(Gg - Gl) + 1j).max())
+        tot = (phases["ground_state_and_forward_mesh_s"] + phases["sweep_growth_s"] + phases["rest_of_run_s"])
+        log(f"rest of the run: {phases['rest_of_run_s']} s; anticommutator error {anti:.2e}")
+        full = {"vector_steps": vec_total,
+                "s_excluding_warmup_and_timed": round(tot, 3),
+                "s_including_warmup_and_timed_estimate": round(tot + elapsed * (1 + a.warmup / max(a.steps, 1)), 3)}
+        full["vector_steps_per_s"] = round(vec_total / full["s_including_warmup_and_timed_estimate"], 2)
+    run.close()
+    cpu = None if a.no_cpu_baseline else cpu_baseline(q)
+    res = {
+        "metric": "G(t,t') contour steps/s at L=14 (four-step backward sweep, Lanczos-fused H.v GB/s in roofline)",
+        "value": round(timed_steps / elapsed, 2),
+        "unit": "vector-steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * elapsed / max(a.steps, 1), 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD_14, "D": sec.dim, "nt": q.nt, "krylov_dim": q.krylov_dim,
+                   "step": "one backward-sweep mesh interval (dots with c Phi(t_s), one batched SIL step)",
+                   "block_width": width, "vector_steps_per_step": (timed_steps // max(a.steps, 1)),
+                   "interval_widths": sorted(set(widths)), "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "E0": run.E0,
+        "setup": phases,
+        "full_four_step_run": full,
+        "anticommutator_err": anti,
+        "kernels": kernels,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def whole_runs(a):
+    """--whole: one step = one whole four-step run (kgf_greens_neq), either
+    schedule; for the schedule comparison."""
     import numpy as np
     import torch
 
@@ -736,21 +891,7 @@ def main():
     Gl, Gg = out["G_lesser"][:, :, 0, 0], out["G_greater"][:, :, 0, 0]
     anti = float(np.abs(np.diag(Gg - Gl) + 1j).max())
 
-    dom = max(stats.items(), key=lambda kv: kv[1]["sampled_ms"] / max(kv[1]["sampled"], 1) * kv[1]["launches"])
-    hv = stats.get("hv_lanczos", dom[1])
-    achieved = hv["sampled_bytes"] / (hv["sampled_ms"] * 1e-3) / 1e9 if hv["sampled_ms"] > 0 else 0.0
-    tb = measured_traffic()
-    avg_launch_bytes = hv["sampled_bytes"] / max(hv["sampled"], 1)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": (round(tb * avg_launch_bytes) if tb is not None else None),
-                "kernel": "hv_lanczos", "avg_launch_ms": round(hv["sampled_ms"] / max(hv["sampled"], 1), 5),
-                "avg_launch_algorithmic_bytes": round(avg_launch_bytes)}
-    kernels = {k: {"launches": v["launches"], "avg_ms": round(v["sampled_ms"] / max(v["sampled"], 1), 5),
-                   "total_ms": round(v["sampled_ms"] * v["launches"] / max(v["sampled"], 1), 1),
-                   "GBps": (round(v["sampled_bytes"] / (v["sampled_ms"] * 1e-3) / 1e9, 1)
-                            if v["sampled_bytes"] and v["sampled_ms"] else None)}
-               for k, v in sorted(stats.items())}
+    roofline, kernels = roofline_of(stats)
     cpu = None if a.no_cpu_baseline else cpu_baseline(q)
     res = {
         "metric": "G(t,t') contour steps/s at L=14 (four-step, Lanczos-fused H.v GB/s in roofline)",
@@ -760,9 +901,9 @@ def main():
         "ms_per_step": round(ms_per_step, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": ("ladder14 quench: 2x7 open Hubbard ladder t=1, half filling, D=11,778,624, "
-                                "U 4->8, G^<_00 and G^>_00 on 101x101, Krylov dim 20, dt=0.05"),
+        "config": {"workload": WORKLOAD_14,
                    "D": sec.dim, "nt": q.nt, "krylov_dim": q.krylov_dim, "schedule": a.schedule,
+                   "step": "one whole four-step run",
                    "vector_steps_per_step": vec_steps, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -345,6 +345,50 @@ int  kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                     kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
                     double* host_E0, kgf_c128* psi0_out);
 
+/* ---- step-wise four-step run (Sec. 4, sweep schedule) ------------------------
+ * The four-step G^<, G^> of kgf_greens_neq (schedule 1, no Matsubara branch),
+ * run piecewise so that a caller can interleave, time or stop it.
+ * kgf_neq_run_create: steps (i) and (ii) (ground state of H_ini from v0 with
+ * gs_opts, forward mesh Phi(t_k) = e^{-iH t_k}|0>, t_k = k*steps_per_grid*opts->dt);
+ * arguments and meanings as kgf_greens_neq.  *host_E0 receives E0.
+ * kgf_neq_run_advance: runs up to n_intervals mesh intervals of steps (iii) and
+ * (iv): per spin that has requested orbitals, the c sweep, then the c+ sweep,
+ * each from t_max down to t_0 in chunks of source times (chunk width from
+ * `batch`, else from free device memory).  One interval at mesh time t_s
+ * injects c_a Phi(t_s) (c+_a Phi(t_s)) for the source times of the chunk, dots
+ * every column e^{iH(t_j - t_s)} c_a Phi(t_j) of the block with c_b Phi(t_s)
+ * (Sec. 4 step (iv)) and, for s > 0, moves the block to t_{s-1} by
+ * steps_per_grid short-iterative-Lanczos steps (Sec. 3, Eq. (newstate)).  The
+ * work is enqueued on the context's stream; the call returns once it is
+ * issued (it waits for the device only when a sweep ends).  host_info (or
+ * NULL) describes what ran and what comes next.
+ * kgf_neq_run_result: once done, copies G^<, G^> [nt][nt][n_orb][n_orb] (host;
+ * either may be NULL) -- bitwise the values of kgf_greens_neq with schedule 1
+ * and the same `batch`; KGF_EINVAL while intervals are left.
+ * Memory: the run owns its forward mesh, sweep block and G until
+ * kgf_neq_run_destroy (other calls on the context may run in between and do
+ * not touch them); the context, models and sector must outlive the run.
+ * KGF_ENOCONV from create if the ground state does not converge. */
+typedef struct kgf_neq_run kgf_neq_run;
+typedef struct {
+    int     intervals;           /* mesh intervals run by this call                       */
+    int     width;               /* block columns of the last interval run                */
+    int     done;                /* 1 when every sweep has finished                       */
+    int     next_width;          /* block columns of the next interval (0 when done)      */
+    int     next_mesh_index;     /* mesh index s of the next interval (-1 when done)      */
+    int     chunk_width;         /* full block width of the next interval's chunk         */
+    int     branch;              /* index of the next interval's sweep (order above), -1 when done */
+    int64_t vector_steps;        /* single-column SIL steps run by this call              */
+    int64_t total_vector_steps;  /* single-column SIL steps since creation                */
+} kgf_neq_run_info;
+int  kgf_neq_run_create(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
+                        const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
+                        int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch,
+                        kgf_neq_run** out, double* host_E0);
+int  kgf_neq_run_advance(kgf_neq_run* run, int n_intervals, kgf_neq_run_info* host_info);
+int  kgf_neq_run_result(kgf_neq_run* run, kgf_c128* host_G_lesser, kgf_c128* host_G_greater);
+void kgf_neq_run_destroy(kgf_neq_run* run);
+
 /* Four-step G^< and G^> (Sec. 4 steps (i)-(iv), sweep schedule) of n_inst
  * independent instances in one call.  Instances whose sectors have equal
  * (L, N_up, N_dn) and whose H have the same bond list form a group that runs

@@ -53,6 +53,12 @@ class _PropOpts(C.Structure):
                 ("direction", C.c_int), ("shift", C.c_double), ("breakdown_tol", C.c_double)]
 
 
+class _RunInfo(C.Structure):
+    _fields_ = [("intervals", C.c_int), ("width", C.c_int), ("done", C.c_int), ("next_width", C.c_int),
+                ("next_mesh_index", C.c_int), ("chunk_width", C.c_int), ("branch", C.c_int),
+                ("vector_steps", C.c_int64), ("total_vector_steps", C.c_int64)]
+
+
 class _KStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("sampled", C.c_int64),
                 ("sampled_ms", C.c_double), ("sampled_bytes", C.c_double)]
@@ -107,6 +113,11 @@ def load_library():
         "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
+        "kgf_neq_run_create": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I,
+                                   C.POINTER(P), C.POINTER(D)]),
+        "kgf_neq_run_advance": (I, [P, I, C.POINTER(_RunInfo)]),
+        "kgf_neq_run_result": (I, [P, P, P]),
+        "kgf_neq_run_destroy": (None, [P]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
         "kgf_set_option": (I, [P, I, I]),
         "kgf_greens_omega": (I, [P, P, P, P, D, I, I, I, P, I, D, P, P, P]),
@@ -140,6 +151,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
             "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_greens2_neq",
+            "kgf_neq_run_create", "kgf_neq_run_advance", "kgf_neq_run_result", "kgf_neq_run_destroy",
             "kgf_profile_begin",
             "kgf_profile_end"]
 
@@ -269,6 +281,38 @@ class Sector:
         if getattr(self, "handle", None):
             if getattr(self.ctx, "handle", None):
                 _lib.kgf_sector_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class NeqRun:
+    """Handle of a step-wise four-step run (kgf_neq_run_*): steps (i), (ii) at
+    creation, steps (iii), (iv) one mesh interval per advance()."""
+
+    def __init__(self, ctx: "Context", handle, E0: float, nt: int, n_orb: int):
+        self.ctx, self.handle, self.E0, self.nt, self.n_orb = ctx, handle, E0, nt, n_orb
+
+    def advance(self, n_intervals: int = 1) -> dict:
+        info = _RunInfo()
+        _check(_lib.kgf_neq_run_advance(self.handle, int(n_intervals), C.byref(info)))
+        return {k: getattr(info, k) for k, _ in _RunInfo._fields_}
+
+    def result(self):
+        shape = (self.nt, self.nt, self.n_orb, self.n_orb)
+        Gl, Gg = _host_c128(shape), _host_c128(shape)
+        _check(_lib.kgf_neq_run_result(self.handle, _np_ptr(Gl), _np_ptr(Gg)))
+        return {"G_lesser": Gl, "G_greater": Gg, "E0": self.E0}
+
+    def close(self):
+        # see Model.close: only while the context exists
+        if getattr(self, "handle", None):
+            if getattr(self.ctx, "handle", None):
+                _lib.kgf_neq_run_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -492,6 +536,23 @@ class Context:
             out["G_matsubara"] = GM
             out["G_mixed"] = Gx
         return out
+
+    def neq_run(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
+                steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0, batch: int = 0,
+                gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                breakdown_tol: float = 1e-13) -> NeqRun:
+        """kgf_neq_run_create: ground state and forward mesh of the four-step
+        procedure; the returned run advances the backward sweeps."""
+        self._chk(v0, sec.dim, "v0")
+        orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
+        E0 = C.c_double()
+        h = C.c_void_p()
+        o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
+        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        _check(_lib.kgf_neq_run_create(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
+                                       _np_ptr(orbs), len(orbs), int(nt), int(steps_per_grid), C.byref(o), int(batch),
+                                       C.byref(h), C.byref(E0)))
+        return NeqRun(self, h, E0.value, int(nt), len(orbs))
 
     def greens_neq_multi(self, H_ini: Sequence[Model], H: Sequence[Model], secs: Sequence[Sector], v0s,
                          orbitals: Sequence[Tuple[int, int]], nt: int, steps_per_grid: int, dt: float,

@@ -291,11 +291,152 @@ struct NeqArgs {
     double dtau;
 };
 
+// Step (iii)+(iv) of one spin group and one operator (c or c+) in the sweep
+// schedule, advanced one mesh interval at a time.  Columns are injected in
+// chunks of source times [jlo, jhi] (chunk width from `batch` or free
+// memory); interval() takes the block at t_s: injects c_a Phi(t_s) when
+// s is in the chunk, dots every column with c_b Phi(t_s) and moves the
+// block to t_{s-1} (one SIL step per grid step).  finish() stores G.
+struct SweepBranch {
+    kgf_ctx* ctx = nullptr;
+    const NeqArgs* A = nullptr;
+    std::vector<int> loc;
+    int dagger = 0, na = 0, nt = 0;
+    std::unique_ptr<kgf_sector> tgt;
+    int64_t D = 0, Dt = 0;
+    SilOpts so;
+    DevBuf gidx;
+    double2 *raw = nullptr, *rawm = nullptr, *S = nullptr, *Lb = nullptr, *tmp = nullptr;
+    const double2* hole = nullptr;   // mixed component: hole states on the tau mesh (or null)
+    int jchunk = 1, jhi = -1, jlo = 0, s = 0, ncur = 0;
+    bool in_chunk = false;
+    int64_t ss = 0, sb = 0, sa = 0, sj = 1;
+
+    // false when the operator's target sector is empty (nothing to do)
+    bool begin(kgf_ctx* c, const NeqArgs& args, const std::vector<int>& orbs_loc, int spin, int dag,
+               const double2* hole_states) {
+        ctx = c;
+        A = &args;
+        loc = orbs_loc;
+        dagger = dag;
+        const kgf_sector* sec = A->sec;
+        tgt = shifted(ctx, sec, spin, dagger ? +1 : -1);
+        if (!tgt || tgt->dim() == 0) return false;
+        D = sec->dim();
+        Dt = tgt->dim();
+        na = (int)loc.size();
+        nt = A->nt;
+        so = A->o;
+        so.direction = +1;   // e^{+iH dt}
+        upload_ints(ctx, gidx, loc);
+        raw = static_cast<double2*>(workspace(ctx, "neq_raw", sizeof(double2) * (size_t)nt * nt * na * na));
+        KGF_HIP(hipMemsetAsync(raw, 0, sizeof(double2) * (size_t)nt * nt * na * na, ctx->stream));
+        hole = hole_states;
+        if (hole)
+            rawm = static_cast<double2*>(workspace(ctx, "neq_rawm", sizeof(double2) * (size_t)na * A->ntau * na * nt));
+        const size_t per_col = sizeof(double2) * (size_t)(A->o.m + 1) * Dt;
+        int Bcols = A->batch;
+        if (Bcols <= 0) {
+            size_t free_b = 0, total_b = 0;
+            KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+            const size_t budget = (size_t)(0.80 * (double)free_b);
+            Bcols = (int)std::max<size_t>(1, budget / per_col);
+        }
+        jchunk = std::min(std::max(1, Bcols / na), nt);
+        const int maxcols = jchunk * na;
+        release(ctx, "sil_X");
+        sil_reserve(ctx, tgt.get(), maxcols, A->o.m, A->o.reorth);
+        ensure_device_fits(sizeof(double2) * (size_t)maxcols * Dt, "four-step sweep block");
+        S = static_cast<double2*>(workspace(ctx, "neq_cols", sizeof(double2) * (size_t)maxcols * Dt));
+        Lb = static_cast<double2*>(workspace(ctx, "neq_left", sizeof(double2) * (size_t)na * Dt));
+        tmp = static_cast<double2*>(workspace(ctx, "neq_tmp", sizeof(double2) * (size_t)na * maxcols));
+        // raw layout [s][b][a][j]
+        ss = (int64_t)na * na * nt;
+        sb = (int64_t)na * nt;
+        sa = nt;
+        sj = 1;
+        jhi = nt - 1;
+        in_chunk = false;
+        return true;
+    }
+
+    bool finished() const { return jhi < 0; }
+    // columns the next interval works on (after its injection), its mesh
+    // index s, and the full width of the chunk it belongs to
+    int next_width() const {
+        if (finished()) return 0;
+        if (!in_chunk) return na;
+        return ncur + (s >= jlo ? na : 0);
+    }
+    int next_s() const { return finished() ? -1 : (in_chunk ? s : jhi); }
+    int chunk_width() const {
+        if (finished()) return 0;
+        return (jhi - std::max(0, jhi - jchunk + 1) + 1) * na;
+    }
+
+    // one mesh interval; returns the SIL column-steps it ran
+    int64_t interval(PhiMesh& Phi) {
+        const kgf_sector* sec = A->sec;
+        if (!in_chunk) {
+            jlo = std::max(0, jhi - jchunk + 1);
+            ncur = 0;   // column r = (jhi - j) * na + q holds X_{q, j}
+            s = jhi;
+            in_chunk = true;
+        }
+        if (s >= jlo) {
+            for (int q = 0; q < na; ++q)
+                apply_c(ctx, sec, tgt.get(), A->orbs[loc[q]], dagger, Phi.at(s), S + (size_t)(ncur + q) * Dt, 1, D,
+                        Dt);
+            ncur += na;
+        }
+        for (int q = 0; q < na; ++q)
+            apply_c(ctx, sec, tgt.get(), A->orbs[loc[q]], dagger, Phi.at(s), Lb + (size_t)q * Dt, 1, D, Dt);
+        // tmp[b][r] = <c_b Phi_s | X_r>
+        block_dots(ctx, Lb, Dt, na, S, Dt, ncur, Dt, tmp, ncur);
+        place(ctx, tmp, na, na, ncur, jhi, raw, s * ss, sb, sa, sj);
+        int64_t steps = 0;
+        if (s > 0) {
+            sil_propagate(ctx, A->H, tgt.get(), S, ncur, Dt, A->spg, so);
+            steps = (int64_t)ncur * A->spg;
+        }
+        progress(ctx, dagger ? "sweep_greater" : "sweep_lesser", jhi - s + 1, jhi + 1);
+        if (--s < 0) {   // chunk done: the columns hold Psi_a(t_j), j in [jlo, jhi]
+            if (hole) {
+                double2* tmpm =
+                    static_cast<double2*>(workspace(ctx, "neq_tmpm", sizeof(double2) * (size_t)na * A->ntau * ncur));
+                block_dots(ctx, hole, Dt, na * A->ntau, S, Dt, ncur, Dt, tmpm, ncur);
+                // rawm layout [(b, jt)][a][k]: (b, jt) is the "left" index of place()
+                place(ctx, tmpm, na * A->ntau, na, ncur, jhi, rawm, 0, (int64_t)na * nt, nt, 1);
+            }
+            jhi -= jchunk;
+            in_chunk = false;
+        }
+        return steps;
+    }
+
+    void finish(double2* Gdev, double2* Gmix_dev) {
+        const int64_t total = (int64_t)nt * nt * na * na;
+        hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(kThreads),
+                           0, ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), A->norb, dagger, 1, Gdev);
+        check_launch("k_store_neq");
+        if (hole && Gmix_dev) store_mixed(ctx, rawm, loc, nt, A->ntau, A->norb, Gmix_dev);
+    }
+};
+
 // step (iii)+(iv) for one spin group and one operator (c or c+);
 // also the mixed component when `mixed_dev` is given (lesser only).
 static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& loc, int spin, int dagger,
                        PhiMesh& Phi, double2* Gdev, const double2* hole_states, const kgf_sector* hole_sec,
                        double2* Gmix_dev) {
+    const bool want_mixed = (Gmix_dev != nullptr && !dagger && A.ntau > 0 && hole_states);
+    if (A.schedule == 1) {
+        SweepBranch br;
+        if (!br.begin(ctx, A, loc, spin, dagger, want_mixed ? hole_states : nullptr)) return;
+        while (!br.finished()) br.interval(Phi);
+        br.finish(Gdev, want_mixed ? Gmix_dev : nullptr);
+        sync(ctx);
+        return;
+    }
     const kgf_sector* sec = A.sec;
     auto tgt = shifted(ctx, sec, spin, dagger ? +1 : -1);
     if (!tgt || tgt->dim() == 0) return;
@@ -309,7 +450,6 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
     upload_ints(ctx, gidx, loc);
     double2* raw = static_cast<double2*>(workspace(ctx, "neq_raw", sizeof(double2) * (size_t)nt * nt * na * na));
     KGF_HIP(hipMemsetAsync(raw, 0, sizeof(double2) * (size_t)nt * nt * na * na, ctx->stream));
-    const bool want_mixed = (Gmix_dev != nullptr && !dagger && A.ntau > 0 && hole_states);
     double2* rawm = nullptr;
     if (want_mixed)
         rawm = static_cast<double2*>(workspace(ctx, "neq_rawm", sizeof(double2) * (size_t)na * A.ntau * na * nt));
@@ -341,62 +481,7 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
         }
         sync(ctx);
         release(ctx, "neq_psi");
-        return;
     }
-
-    // sweep schedule
-    const size_t per_col = sizeof(double2) * (size_t)(A.o.m + 1) * Dt;
-    int Bcols = A.batch;
-    if (Bcols <= 0) {
-        size_t free_b = 0, total_b = 0;
-        KGF_HIP(hipMemGetInfo(&free_b, &total_b));
-        size_t budget = (size_t)(0.80 * (double)free_b);
-        Bcols = (int)std::max<size_t>(1, budget / per_col);
-    }
-    int jchunk = std::max(1, Bcols / na);
-    jchunk = std::min(jchunk, nt);
-    const int maxcols = jchunk * na;
-    release(ctx, "sil_X");
-    sil_reserve(ctx, tgt.get(), maxcols, A.o.m, A.o.reorth);
-    ensure_device_fits(sizeof(double2) * (size_t)maxcols * Dt, "four-step sweep block");
-    double2* S = static_cast<double2*>(workspace(ctx, "neq_cols", sizeof(double2) * (size_t)maxcols * Dt));
-    double2* Lb = static_cast<double2*>(workspace(ctx, "neq_left", sizeof(double2) * (size_t)na * Dt));
-    // raw layout [s][b][a][j]
-    const int64_t ss = (int64_t)na * na * nt, sb = (int64_t)na * nt, sa = nt, sj = 1;
-    double2* tmp = static_cast<double2*>(workspace(ctx, "neq_tmp", sizeof(double2) * (size_t)na * maxcols));
-    for (int jhi = nt - 1; jhi >= 0; jhi -= jchunk) {
-        const int jlo = std::max(0, jhi - jchunk + 1);
-        // column r = (jhi - j) * na + q holds X_{q, j}
-        int ncur = 0;
-        for (int s = jhi; s >= 0; --s) {
-            if (s >= jlo) {
-                for (int q = 0; q < na; ++q)
-                    apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi.at(s), S + (size_t)(ncur + q) * Dt,
-                            1, D, Dt);
-                ncur += na;
-            }
-            for (int q = 0; q < na; ++q)
-                apply_c(ctx, sec, tgt.get(), A.orbs[loc[q]], dagger, Phi.at(s), Lb + (size_t)q * Dt, 1, D, Dt);
-            // tmp[b][r] = <c_b Phi_s | X_r>
-            block_dots(ctx, Lb, Dt, na, S, Dt, ncur, Dt, tmp, ncur);
-            place(ctx, tmp, na, na, ncur, jhi, raw, s * ss, sb, sa, sj);
-            if (s > 0) sil_propagate(ctx, A.H, tgt.get(), S, ncur, Dt, A.spg, so);
-            progress(ctx, dagger ? "sweep_greater" : "sweep_lesser", jhi - s + 1, jhi + 1);
-        }
-        if (want_mixed) {
-            // columns now hold Psi_a(t_j) for j in [jlo, jhi]; tmpm[(b, jt)][r]
-            double2* tmpm = static_cast<double2*>(workspace(ctx, "neq_tmpm", sizeof(double2) * (size_t)na * A.ntau * ncur));
-            block_dots(ctx, hole_states, Dt, na * A.ntau, S, Dt, ncur, Dt, tmpm, ncur);
-            // rawm layout [(b, jt)][a][k]: treat (b, jt) as the "left" index of place()
-            place(ctx, tmpm, na * A.ntau, na, ncur, jhi, rawm, 0, (int64_t)na * nt, nt, 1);
-        }
-    }
-    int64_t total = (int64_t)nt * nt * na * na;
-    hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(kThreads), 0,
-                       ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), A.norb, dagger, 1, Gdev);
-    check_launch("k_store_neq");
-    if (want_mixed) store_mixed(ctx, rawm, loc, nt, A.ntau, A.norb, Gmix_dev);
-    sync(ctx);
 }
 
 // Grid points between stored forward states: 1 (store all) when the mesh
@@ -415,23 +500,23 @@ static int phi_checkpoint_interval(kgf_ctx* ctx, int nt, int64_t D) {
     return std::max(nt, 1);
 }
 
-void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso, double* E0_out,
-                double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host) {
+// Steps (i) and (ii): ground state of H_ini (returned, also copied to
+// psi0_out when given) and the forward mesh Phi(t_k), whole or as checkpoints.
+static double2* neq_forward(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso,
+                            double* E0_out, double2* psi0_out, PhiMesh& Phi) {
     const kgf_sector* sec = A.sec;
     const int64_t D = sec->dim();
-    const int nt = A.nt, norb = A.norb;
+    const int nt = A.nt;
     // (i) ground state of H_ini
     double2* psi0 = static_cast<double2*>(workspace(ctx, "neq_psi0", sizeof(double2) * D));
     GsResult gs = ground_state(ctx, A.H_ini, sec, v0, psi0, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
     release(ctx, "gs_V");
     release(ctx, "gs_partbig");
     KGF_REQUIRE(gs.converged, KGF_ENOCONV, "four-step: ground state of H_ini did not converge");
-    const double E0 = gs.E0;
-    *E0_out = E0;
+    *E0_out = gs.E0;
     if (psi0_out)
         KGF_HIP(hipMemcpyAsync(psi0_out, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
     // (ii) forward states on the mesh (whole, or checkpoints every K)
-    PhiMesh Phi;
     Phi.ctx = ctx;
     Phi.H = A.H;
     Phi.sec = sec;
@@ -465,6 +550,17 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
             progress(ctx, "forward", k, nt - 1);
         }
     }
+    return psi0;
+}
+
+void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso, double* E0_out,
+                double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host) {
+    const kgf_sector* sec = A.sec;
+    const int64_t D = sec->dim();
+    const int nt = A.nt, norb = A.norb;
+    PhiMesh Phi;
+    const double2* psi0 = neq_forward(ctx, A, v0, gso, E0_out, psi0_out, Phi);
+    const double E0 = *E0_out;
     const size_t gsz = sizeof(double2) * (size_t)nt * nt * norb * norb;
     double2* Gl = static_cast<double2*>(workspace(ctx, "neq_Gl", gsz));
     double2* Gg = static_cast<double2*>(workspace(ctx, "neq_Gg", gsz));
@@ -985,6 +1081,171 @@ extern "C" int kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_mo
                    reinterpret_cast<double2*>(host_G_greater), reinterpret_cast<double2*>(host_G_matsubara),
                    reinterpret_cast<double2*>(host_G_mixed));
     });
+}
+
+// Step-wise four-step run (sweep schedule): steps (i) and (ii) at creation,
+// then steps (iii) and (iv) one mesh interval per kgf_neq_run_advance call,
+// through the same SweepBranch code as kgf_greens_neq (bitwise the same G).
+// The run keeps its own workspaces: the context's are swapped out while a
+// run call executes, so other calls on the context in between do not touch
+// the run's forward mesh or sweep block.
+struct kgf_neq_run {
+    kgf_ctx* ctx = nullptr;
+    std::map<std::string, std::unique_ptr<kgf::DevBuf>> ws;
+    std::vector<int32_t> orbs;
+    kgf::NeqArgs A;
+    kgf::PhiMesh Phi;
+    double E0 = 0.0;
+    std::vector<std::pair<int, int>> branches;    // (spin, dagger), kgf_greens_neq's order
+    std::vector<std::vector<int>> locs;           // orbital indices of each branch's spin
+    size_t next = 0;
+    std::unique_ptr<kgf::SweepBranch> cur;
+    double2* Gl = nullptr;
+    double2* Gg = nullptr;
+    int64_t vector_steps = 0;
+    bool done = false;
+};
+
+namespace {
+struct RunWorkspaces {
+    kgf_ctx* ctx;
+    std::map<std::string, std::unique_ptr<kgf::DevBuf>>& own;
+    RunWorkspaces(kgf_ctx* c, std::map<std::string, std::unique_ptr<kgf::DevBuf>>& w) : ctx(c), own(w) {
+        std::swap(ctx->ws, own);
+    }
+    ~RunWorkspaces() { std::swap(ctx->ws, own); }
+};
+
+// begin the next branch whose target sector is not empty; false when none is left
+bool run_next_branch(kgf_neq_run* r) {
+    while (r->next < r->branches.size()) {
+        const auto [spin, dagger] = r->branches[r->next];
+        const auto& loc = r->locs[r->next];
+        ++r->next;
+        std::unique_ptr<kgf::SweepBranch> br(new kgf::SweepBranch());
+        if (br->begin(r->ctx, r->A, loc, spin, dagger, nullptr)) {
+            r->cur = std::move(br);
+            return true;
+        }
+    }
+    r->cur.reset();
+    return false;
+}
+}  // namespace
+
+extern "C" int kgf_neq_run_create(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
+                                  const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
+                                  int nt, int steps_per_grid, const kgf_prop_opts* opts, int batch,
+                                  kgf_neq_run** out, double* host_E0) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(ctx && H_ini && H && sector && gs_opts && v0 && host_orbs && out && host_E0, KGF_EINVAL,
+                    "kgf_neq_run_create: NULL argument");
+        KGF_REQUIRE(H_ini->L == sector->L && H->L == sector->L, KGF_EINVAL,
+                    "kgf_neq_run_create: models and sector differ in L");
+        KGF_REQUIRE(sector->dim() > 0, KGF_EINVAL, "kgf_neq_run_create: empty sector");
+        kgf::check_prop_opts(opts);
+        KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && batch >= 0, KGF_EINVAL,
+                    "kgf_neq_run_create: bad sizes");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                    KGF_EINVAL, "kgf_neq_run_create: bad ground-state options");
+        for (int a = 0; a < n_orb; ++a)
+            KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
+                        "kgf_neq_run_create: orbital out of range");
+        KGF_HIP(hipSetDevice(ctx->device));
+        std::unique_ptr<kgf_neq_run> r(new kgf_neq_run());
+        r->ctx = ctx;
+        r->orbs.assign(host_orbs, host_orbs + n_orb);
+        kgf::NeqArgs& A = r->A;
+        A.H_ini = const_cast<kgf_model*>(H_ini);
+        A.H = const_cast<kgf_model*>(H);
+        A.sec = sector;
+        A.orbs = r->orbs.data();
+        A.norb = n_orb;
+        A.nt = nt;
+        A.spg = steps_per_grid;
+        A.o = kgf::to_sil_opts(opts);
+        A.schedule = 1;
+        A.batch = batch;
+        A.ntau = 0;
+        A.tspg = 1;
+        A.dtau = 0.0;
+        RunWorkspaces guard(ctx, r->ws);
+        kgf::neq_forward(ctx, A, reinterpret_cast<const double2*>(v0), gs_opts, &r->E0, nullptr, r->Phi);
+        const size_t gsz = sizeof(double2) * (size_t)nt * nt * n_orb * n_orb;
+        r->Gl = static_cast<double2*>(kgf::workspace(ctx, "run_Gl", gsz));
+        r->Gg = static_cast<double2*>(kgf::workspace(ctx, "run_Gg", gsz));
+        KGF_HIP(hipMemsetAsync(r->Gl, 0, gsz, ctx->stream));
+        KGF_HIP(hipMemsetAsync(r->Gg, 0, gsz, ctx->stream));
+        for (int spin = 0; spin < 2; ++spin) {
+            std::vector<int> loc;
+            for (int a = 0; a < n_orb; ++a)
+                if ((host_orbs[a] & 1) == spin) loc.push_back(a);
+            if (loc.empty()) continue;
+            for (int dagger = 0; dagger < 2; ++dagger) {
+                r->branches.push_back({spin, dagger});
+                r->locs.push_back(loc);
+            }
+        }
+        r->done = !run_next_branch(r.get());
+        kgf::sync(ctx);
+        *host_E0 = r->E0;
+        *out = r.release();
+    });
+}
+
+extern "C" int kgf_neq_run_advance(kgf_neq_run* r, int n_intervals, kgf_neq_run_info* host_info) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(r && n_intervals >= 0, KGF_EINVAL, "kgf_neq_run_advance: bad argument");
+        kgf_ctx* ctx = r->ctx;
+        KGF_HIP(hipSetDevice(ctx->device));
+        RunWorkspaces guard(ctx, r->ws);
+        int64_t steps = 0;
+        int ran = 0, width = 0;
+        while (ran < n_intervals && !r->done) {
+            width = r->cur->next_width();
+            steps += r->cur->interval(r->Phi);
+            ++ran;
+            if (r->cur->finished()) {
+                const int dagger = r->cur->dagger;
+                r->cur->finish(dagger ? r->Gg : r->Gl, nullptr);
+                kgf::sync(ctx);
+                r->done = !run_next_branch(r);
+            }
+        }
+        r->vector_steps += steps;
+        if (host_info) {
+            host_info->intervals = ran;
+            host_info->vector_steps = steps;
+            host_info->width = width;
+            host_info->done = r->done ? 1 : 0;
+            host_info->next_width = r->done ? 0 : r->cur->next_width();
+            host_info->next_mesh_index = r->done ? -1 : r->cur->next_s();
+            host_info->chunk_width = r->done ? 0 : r->cur->chunk_width();
+            host_info->branch = r->done ? -1 : (int)r->next - 1;
+            host_info->total_vector_steps = r->vector_steps;
+        }
+    });
+}
+
+extern "C" int kgf_neq_run_result(kgf_neq_run* r, kgf_c128* host_G_lesser, kgf_c128* host_G_greater) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(r, KGF_EINVAL, "kgf_neq_run_result: NULL run");
+        KGF_REQUIRE(r->done, KGF_EINVAL, "kgf_neq_run_result: the run has intervals left");
+        kgf_ctx* ctx = r->ctx;
+        KGF_HIP(hipSetDevice(ctx->device));
+        const size_t gsz = sizeof(double2) * (size_t)r->A.nt * r->A.nt * r->A.norb * r->A.norb;
+        if (host_G_lesser) KGF_HIP(hipMemcpyAsync(host_G_lesser, r->Gl, gsz, hipMemcpyDeviceToHost, ctx->stream));
+        if (host_G_greater) KGF_HIP(hipMemcpyAsync(host_G_greater, r->Gg, gsz, hipMemcpyDeviceToHost, ctx->stream));
+        kgf::sync(ctx);
+    });
+}
+
+extern "C" void kgf_neq_run_destroy(kgf_neq_run* r) {
+    if (!r) return;
+    (void)hipSetDevice(r->ctx->device);
+    (void)hipStreamSynchronize(r->ctx->stream);
+    delete r;
 }
 
 extern "C" int kgf_greens_neq_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H_ini,
