@@ -180,6 +180,26 @@ typedef struct {
 int  kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
                    kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts);
 
+/* ---- allocation-free propagation ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * kgf_propagate_noalloc does what kgf_propagate does, with the same kernels
+ * and bitwise the same results, but takes every buffer it needs (Krylov
+ * slots, per-column scalars, reduction partials) from a fixed device array
+ * of KGF_NOALLOC_SCRATCH_BYTES per GPU, resolved at kgf_create and held until
+ * the process ends; it calls no allocator.  Limits: the scratch must hold
+ * krylov_dim * nvec * D complex128 plus small per-column arrays, else
+ * KGF_EUNSUPPORTED (e.g. D = 63,504, krylov_dim 15: up to 4 columns); the
+ * model's hopping tables for the sector's particle numbers must already
+ * exist (one kgf_apply_h or kgf_propagate on the sector builds them), else
+ * KGF_EINVAL.  All calls on one GPU share the array: calls that overlap in
+ * time on that GPU (another thread, another stream) race; calls issued in
+ * order on one stream do not.  Nothing in the array has to start at zero:
+ * every value a step reads is written earlier in the same step. */
+#define KGF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int  kgf_propagate_noalloc(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
+                           kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts);
+
 /* ---- equilibrium Green's function (Sec. 3, Eqs. (psit), (psigreen), eta=0)
  *   G^>_{ij}(t_k) = -i e^{+i E0 t_k} <c+_i 0| e^{-iH t_k} |c+_j 0>
  *   G^<_{ij}(t_k) = +i e^{-i E0 t_k} <c_j 0| e^{+iH t_k} |c_i 0>

@@ -110,6 +110,7 @@ def load_library():
         "kgf_apply_c": (I, [P, P, P, I, I, P, P, I, I64, I64]),
         "kgf_ground_state": (I, [P, P, P, C.POINTER(_GsOpts), P, P, C.POINTER(D), C.POINTER(_GsInfo)]),
         "kgf_propagate": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts)]),
+        "kgf_propagate_noalloc": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts)]),
         "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
@@ -152,6 +153,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
             "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_greens2_neq",
             "kgf_neq_run_create", "kgf_neq_run_advance", "kgf_neq_run_result", "kgf_neq_run_destroy",
+            "kgf_propagate_noalloc",
             "kgf_profile_begin",
             "kgf_profile_end"]
 
@@ -422,6 +424,17 @@ class Context:
         o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
         _check(_lib.kgf_propagate(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
                                   C.byref(o)))
+        return psi
+
+    def propagate_noalloc(self, model: Model, sec: Sector, psi, nsteps: int, dt: float, krylov_dim: int = 15,
+                          direction: int = DIRECTION_FORWARD, shift: float = 0.0, reorth: int = 0,
+                          breakdown_tol: float = 1e-13):
+        """kgf_propagate_noalloc: propagate() with every device buffer in the
+        library's fixed per-GPU scratch (no allocation)."""
+        nvec = self._chk(psi, sec.dim, "psi")
+        o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
+        _check(_lib.kgf_propagate_noalloc(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim,
+                                          int(nsteps), C.byref(o)))
         return psi
 
     # Gauss-Legendre nodes of the driven integrator, as fractions of a step

@@ -1,13 +1,34 @@
 // C ABI of libkgf: handles, argument checking, error plumbing, workspace
 // and kernel timing.  The numerical work lives in basis.hip,
 // hamiltonian.hip, krylov.hip and greens.hip.
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "kgf_internal.h"
 
 namespace {
 thread_local std::string g_last_error;
+
+// Device scratch of kgf_propagate_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes the symbol itself to a kernel; it
+// uses the device address resolved per device at kgf_create.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::array<void*, kMaxDevices> g_scratch_addr{};
+std::mutex g_scratch_mu;
+
+// with `device` current
+void resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[device]) return;
+    void* p = nullptr;
+    KGF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    KGF_REQUIRE(p != nullptr, KGF_EHIP, "kgf_create: no device address for the no-allocation scratch");
+    g_scratch_addr[device] = p;
+}
 }
 
 namespace kgf {
@@ -170,7 +191,9 @@ int kgf_create(kgf_ctx** out, int hip_device, void* hip_stream) {
         KGF_HIP(hipGetDeviceCount(&ndev));
         KGF_REQUIRE(hip_device >= 0 && hip_device < ndev, KGF_EINVAL,
                     "kgf_create: device " + std::to_string(hip_device) + " out of range");
+        KGF_REQUIRE(hip_device < kMaxDevices, KGF_EUNSUPPORTED, "kgf_create: device index above 63");
         KGF_HIP(hipSetDevice(hip_device));
+        resolve_scratch(hip_device);
         std::unique_ptr<kgf_ctx> c(new kgf_ctx());
         c->device = hip_device;
         c->stream = static_cast<hipStream_t>(hip_stream);
@@ -389,6 +412,32 @@ int kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, kgf
         KGF_HIP(hipSetDevice(ctx->device));
         sil_propagate(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<double2*>(psi), nvec,
                       ld, nsteps, to_sil_opts(opts));
+    });
+}
+
+int kgf_propagate_noalloc(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, kgf_c128* psi,
+                          int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts) {
+    return guarded([&] {
+        KGF_REQUIRE(ctx && model && s, KGF_EINVAL, "kgf_propagate_noalloc: NULL handle");
+        KGF_REQUIRE(model->L == s->L, KGF_EINVAL, "kgf_propagate_noalloc: model and sector L differ");
+        check_prop_opts(opts);
+        KGF_REQUIRE(nvec >= 0 && nvec <= 65535 && nsteps >= 0 && ld >= s->dim(), KGF_EINVAL,
+                    "kgf_propagate_noalloc: bad nvec / nsteps / ld");
+        if (nvec == 0 || nsteps == 0 || s->dim() == 0) return;
+        KGF_REQUIRE(psi, KGF_EINVAL, "kgf_propagate_noalloc: NULL psi");
+        KGF_REQUIRE(hop_table_ready(model, s->n_up) && hop_table_ready(model, s->n_dn), KGF_EINVAL,
+                    "kgf_propagate_noalloc: the model's hopping tables for this sector are not built yet "
+                    "(one kgf_apply_h or kgf_propagate on the sector builds them)");
+        const size_t need = sil_scratch_bytes(ctx, s, nvec, opts->krylov_dim, opts->reorth);
+        KGF_REQUIRE(need <= kNoAllocScratchBytes, KGF_EUNSUPPORTED,
+                    "kgf_propagate_noalloc: needs " + std::to_string((need + (1 << 20) - 1) >> 20) +
+                        " MiB of scratch (krylov_dim x nvec x D complex128 plus scalars); the limit is " +
+                        std::to_string(kNoAllocScratchBytes >> 20) + " MiB");
+        KGF_HIP(hipSetDevice(ctx->device));
+        void* base = g_scratch_addr[ctx->device];
+        KGF_REQUIRE(base != nullptr, KGF_EHIP, "kgf_propagate_noalloc: scratch address not resolved");
+        sil_propagate_in(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<double2*>(psi), nvec, ld, nsteps,
+                         to_sil_opts(opts), base);
     });
 }
 

@@ -208,6 +208,8 @@ void refresh_onsite(kgf_model* model) {
     sync(ctx);   // the temporaries above are freed on return
 }
 
+bool hop_table_ready(const kgf_model* model, int n) { return model->tables.count(n) != 0; }
+
 HopTable& hop_table(kgf_model* model, int n) {
     auto it = model->tables.find(n);
     if (it != model->tables.end()) return *it->second;

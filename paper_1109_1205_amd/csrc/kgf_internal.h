@@ -261,6 +261,16 @@ void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi,
                    int ncol, int64_t ld, int nsteps, const SilOpts& o);
 
+// Bytes of the one buffer that sil_propagate_in carves its Krylov slots,
+// scalars and partials from, and SIL steps with every device buffer in
+// `scratch` (no allocation; the model's hopping tables for the sector's
+// particle numbers must exist).
+size_t sil_scratch_bytes(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth);
+void sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                      int nsteps, const SilOpts& o, void* scratch);
+// true when the model's hopping table for n particles has been built
+bool hop_table_ready(const kgf_model* model, int n);
+
 struct GsResult {
     double E0;
     int iters;

@@ -853,28 +853,50 @@ void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reort
     }
 }
 
-// Lanczos bases of ncol columns psi_c = psi + c * ld (slot 0 = psi itself);
-// leaves the scalars in "sil_scal" and slots 1..m in "sil_X".
-void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
-               const SilOpts& o) {
+// Device memory of one batched SIL step: the Krylov slots 1..m (slot 0 is
+// the state itself), the per-column scalars, the reduction partials and,
+// with reorthogonalisation, the Gram-Schmidt partials and coefficients.
+struct SilWork {
+    double2* X;
+    double* scal;
+    double* part;
+    double* part_big;
+    double2* hvec;
+};
+
+// Byte layout of a SilWork carved from one buffer (each piece 256-aligned).
+struct SilLayout {
+    size_t x, scal, part, part_big, hvec, total;
+};
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+static SilLayout sil_layout(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth) {
     const int64_t D = sec->dim();
-    const int m = o.m;
-    KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
-    hv_prepare(ctx, model, sec);
-    sil_reserve(ctx, sec, ncol, m, o.reorth);
-    const size_t xbytes = sizeof(double2) * (size_t)m * ncol * D;
-    double2* X = static_cast<double2*>(workspace(ctx, "sil_X", xbytes));
-    double* scal = static_cast<double*>(workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol));
     const int NB = red_blocks(D);
     const int HB = hv_lanczos_blocks(ctx, sec);
     const int nper_max = NB > HB ? NB : HB;
-    double* part = static_cast<double*>(workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol));
-    double* part_big = nullptr;
-    double2* hvec = nullptr;
-    if (o.reorth > 0) {
-        part_big = static_cast<double*>(workspace(ctx, "sil_partbig", sizeof(double) * (size_t)NB * ncol * (m + 1) * 2));
-        hvec = static_cast<double2*>(workspace(ctx, "sil_hvec", sizeof(double2) * (size_t)ncol * (m + 1)));
-    }
+    SilLayout l;
+    l.x = 0;
+    l.scal = l.x + align256(sizeof(double2) * (size_t)m * ncol * D);
+    l.part = l.scal + align256(sizeof(double) * kScalStride * ncol);
+    l.part_big = l.part + align256(sizeof(double) * (size_t)nper_max * ncol);
+    l.hvec = l.part_big + (reorth > 0 ? align256(sizeof(double) * (size_t)NB * ncol * (m + 1) * 2) : 0);
+    l.total = l.hvec + (reorth > 0 ? align256(sizeof(double2) * (size_t)ncol * (m + 1)) : 0);
+    return l;
+}
+
+// Lanczos bases of ncol columns psi_c = psi + c * ld (slot 0 = psi itself)
+// in the memory of w; the scalars are left in w.scal.
+static void sil_build_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                        const SilOpts& o, const SilWork& w) {
+    const int64_t D = sec->dim();
+    const int m = o.m;
+    double2* X = w.X;
+    double* scal = w.scal;
+    const int NB = red_blocks(D);
+    const int HB = hv_lanczos_blocks(ctx, sec);
+    double* part = w.part;
+    double* part_big = w.part_big;
+    double2* hvec = w.hvec;
     Slots sl{psi, ld, X, (int64_t)ncol * D, D};
     {
         Prof pr(ctx, "norm", 16.0 * D * ncol);
@@ -910,6 +932,57 @@ void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, 
     }
 }
 
+// The SIL buffers in the context's workspaces (sil_reserve first).
+static SilWork sil_work_ws(kgf_ctx* ctx, const kgf_sector* sec, int ncol, const SilOpts& o) {
+    const int64_t D = sec->dim();
+    const int NB = red_blocks(D);
+    const int HB = hv_lanczos_blocks(ctx, sec);
+    const int nper_max = NB > HB ? NB : HB;
+    SilWork w;
+    w.X = static_cast<double2*>(workspace(ctx, "sil_X", sizeof(double2) * (size_t)o.m * ncol * D));
+    w.scal = static_cast<double*>(workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol));
+    w.part = static_cast<double*>(workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol));
+    w.part_big = nullptr;
+    w.hvec = nullptr;
+    if (o.reorth > 0) {
+        w.part_big = static_cast<double*>(
+            workspace(ctx, "sil_partbig", sizeof(double) * (size_t)NB * ncol * (o.m + 1) * 2));
+        w.hvec = static_cast<double2*>(workspace(ctx, "sil_hvec", sizeof(double2) * (size_t)ncol * (o.m + 1)));
+    }
+    return w;
+}
+
+// Lanczos bases of ncol columns psi_c = psi + c * ld (slot 0 = psi itself);
+// leaves the scalars in "sil_scal" and slots 1..m in "sil_X".
+void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+               const SilOpts& o) {
+    KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
+    hv_prepare(ctx, model, sec);
+    sil_reserve(ctx, sec, ncol, o.m, o.reorth);
+    sil_build_w(ctx, model, sec, psi, ncol, ld, o, sil_work_ws(ctx, sec, ncol, o));
+}
+
+// exp(T t) e_1 coefficients of up to kMaxReq requests against the scalars at scal
+static void launch_coefs(kgf_ctx* ctx, const double* scal, int m, const CoefReq& q, double shift, double2* coef,
+                         int coef_stride) {
+    Prof pr(ctx, "tridiag_exp");
+    const size_t lds = sizeof(double) * (size_t)m * (m + 1);
+    if (m <= 64) {
+        hipLaunchKernelGGL(k_tridiag_exp<64>, dim3(q.n), dim3(64), lds, ctx->stream, scal, m, q, shift, coef,
+                           coef_stride);
+    } else {
+        static bool opted[64] = {};
+        if (!opted[ctx->device & 63]) {
+            KGF_HIP(hipFuncSetAttribute((const void*)k_tridiag_exp<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)(sizeof(double) * kMaxKrylov * (kMaxKrylov + 1))));
+            opted[ctx->device & 63] = true;
+        }
+        hipLaunchKernelGGL(k_tridiag_exp<128>, dim3(q.n), dim3(128), lds, ctx->stream, scal, m, q, shift, coef,
+                           coef_stride);
+    }
+    check_launch("k_tridiag_exp");
+}
+
 // coefficient requests against the bases left by sil_build
 void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, const int* dir, double shift,
                double2* coef, int coef_stride) {
@@ -922,23 +995,7 @@ void sil_coefs(kgf_ctx* ctx, int m, int nreq, const int* col, const double* t, c
             q.t[r] = t[r0 + r];
             q.dir[r] = dir[r0 + r];
         }
-        Prof pr(ctx, "tridiag_exp");
-        const size_t lds = sizeof(double) * (size_t)m * (m + 1);
-        if (m <= 64) {
-            hipLaunchKernelGGL(k_tridiag_exp<64>, dim3(q.n), dim3(64), lds, ctx->stream, scal, m, q, shift,
-                               coef + (int64_t)r0 * coef_stride, coef_stride);
-        } else {
-            static bool opted[64] = {};
-            if (!opted[ctx->device & 63]) {
-                KGF_HIP(hipFuncSetAttribute((const void*)k_tridiag_exp<128>,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)(sizeof(double) * kMaxKrylov * (kMaxKrylov + 1))));
-                opted[ctx->device & 63] = true;
-            }
-            hipLaunchKernelGGL(k_tridiag_exp<128>, dim3(q.n), dim3(128), lds, ctx->stream, scal, m, q, shift,
-                               coef + (int64_t)r0 * coef_stride, coef_stride);
-        }
-        check_launch("k_tridiag_exp");
+        launch_coefs(ctx, scal, m, q, shift, coef + (int64_t)r0 * coef_stride, coef_stride);
     }
 }
 
@@ -958,29 +1015,63 @@ void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_
     }
 }
 
-void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
-                   int nsteps, const SilOpts& o) {
+// One SIL step of every column in the memory of w: build, exp(-+i T dt) e_1
+// (column c's coefficients into its scalar block), combination into psi.
+static void sil_step_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                       const SilOpts& o, const SilWork& w) {
     const int64_t D = sec->dim();
     const int m = o.m;
-    std::vector<int> col(ncol), dir(ncol, o.direction);
-    std::vector<double> tt(ncol, o.dt);
-    for (int c = 0; c < ncol; ++c) col[c] = c;
-    for (int step = 0; step < nsteps; ++step) {
-        sil_build(ctx, model, sec, psi, ncol, ld, o);
-        double* scal = static_cast<double*>(ctx->ws["sil_scal"]->p);
-        double2* coef = reinterpret_cast<double2*>(scal + kOffCoef);
-        sil_coefs(ctx, m, ncol, col.data(), tt.data(), dir.data(), o.shift, coef, kScalStride / 2);
-        double2* X = static_cast<double2*>(ctx->ws["sil_X"]->p);
-        Slots sl{psi, ld, X, (int64_t)ncol * D, D};
-        const int NB = red_blocks(D);
-        {
-            Prof pr(ctx, "combine", 16.0 * (m + 1) * D * ncol);
-            hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream, sl, m,
-                               reinterpret_cast<const double2*>(coef), (int64_t)(kScalStride / 2), psi, ld, D);
-            check_launch("k_combine");
+    sil_build_w(ctx, model, sec, psi, ncol, ld, o, w);
+    double2* coef = reinterpret_cast<double2*>(w.scal + kOffCoef);
+    for (int r0 = 0; r0 < ncol; r0 += kMaxReq) {
+        CoefReq q;
+        q.n = std::min(kMaxReq, ncol - r0);
+        for (int r = 0; r < q.n; ++r) {
+            q.col[r] = r0 + r;
+            q.t[r] = o.dt;
+            q.dir[r] = o.direction;
         }
+        launch_coefs(ctx, w.scal, m, q, o.shift, coef + (int64_t)r0 * (kScalStride / 2), kScalStride / 2);
+    }
+    Slots sl{psi, ld, w.X, (int64_t)ncol * D, D};
+    const int NB = red_blocks(D);
+    Prof pr(ctx, "combine", 16.0 * (m + 1) * D * ncol);
+    hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream, sl, m,
+                       reinterpret_cast<const double2*>(coef), (int64_t)(kScalStride / 2), psi, ld, D);
+    check_launch("k_combine");
+}
+
+void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                   int nsteps, const SilOpts& o) {
+    for (int step = 0; step < nsteps; ++step) {
+        KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
+        hv_prepare(ctx, model, sec);
+        sil_reserve(ctx, sec, ncol, o.m, o.reorth);
+        sil_step_w(ctx, model, sec, psi, ncol, ld, o, sil_work_ws(ctx, sec, ncol, o));
     }
 }
+
+// Bytes of the single buffer a batched SIL step of ncol columns needs.
+size_t sil_scratch_bytes(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth) {
+    return sil_layout(ctx, sec, ncol, m, reorth).total;
+}
+
+// SIL steps with every device buffer carved from `scratch` (at least
+// sil_scratch_bytes); no allocation.  The hopping tables of the model for the
+// sector's particle numbers must already exist.
+void sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                      int nsteps, const SilOpts& o, void* scratch) {
+    const SilLayout l = sil_layout(ctx, sec, ncol, o.m, o.reorth);
+    char* base = static_cast<char*>(scratch);
+    SilWork w;
+    w.X = reinterpret_cast<double2*>(base + l.x);
+    w.scal = reinterpret_cast<double*>(base + l.scal);
+    w.part = reinterpret_cast<double*>(base + l.part);
+    w.part_big = o.reorth > 0 ? reinterpret_cast<double*>(base + l.part_big) : nullptr;
+    w.hvec = o.reorth > 0 ? reinterpret_cast<double2*>(base + l.hvec) : nullptr;
+    for (int step = 0; step < nsteps; ++step) sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
+}
+
 
 // ---------------------------------------------------------------------------
 // ground state
