@@ -47,6 +47,7 @@ extern "C" {
 #define KGF_EHIP         -3   /* HIP runtime error                          */
 #define KGF_ENOCONV      -4   /* ground-state Lanczos did not converge      */
 #define KGF_EUNSUPPORTED -5   /* size outside the supported range          */
+#define KGF_EDEGENERATE  -6   /* two Lanczos starts reached different ground states */
 
 /* complex128, interleaved (re, im); layout-compatible with torch.complex128 */
 typedef struct { double re, im; } kgf_c128;
@@ -95,6 +96,11 @@ void kgf_model_destroy(kgf_model* model);
  * Instance sets built from the model (kgf_greens_neq_multi) must not run
  * concurrently with the change. */
 int  kgf_model_set_params(kgf_model* model, const kgf_model_desc* desc);
+/* kgf_model_get_params: copy the model's current parameters to host arrays
+ * t [n_bonds], eps_up [L], eps_dn [L], U [L] (any may be NULL) -- after
+ * kgf_propagate_driven / kgf_greens_neq_driven, the last stage's. */
+int  kgf_model_get_params(const kgf_model* model, double* host_t, double* host_eps_up, double* host_eps_dn,
+                          double* host_U);
 
 /* ---- sector basis (Sec. 2 occupation-number basis; Sec. 4 N, S_z) --------
  * kgf_sector_create builds, on the device, the ascending mask tables of
@@ -142,17 +148,31 @@ int  kgf_apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst,
  * b_{k+1}|y_k| <= tol * max(1, |E0|) (checked every check_every steps) or
  * at max_iter.  psi0 (device, D) receives the normalised Ritz vector
  * (Eq. (eigen)).  Returns KGF_ENOCONV (psi0, E0 still written) when not
- * converged.  Workspace: (max_iter + 1) vectors of D complex128. */
+ * converged.  Workspace: (max_iter + 1) vectors of D complex128.
+ * Uniqueness (the method assumes a nondegenerate ground state, Sec. 2 and
+ * Sec. 4 step (i)): with unique_check = 1 a second recursion runs from a
+ * second start vector -- real entries uniform in [-1, 1) from the SplitMix64
+ * generator (Steele, Lea, Flood 2014) at counter i for entry i, seeded with
+ * unique_seed -- and fidelity2 = |<0_a|0_b>|^2 of the two normalised Ritz
+ * vectors is reported; below 1 - unique_tol (0: 1e-10) the call returns
+ * KGF_EDEGENERATE, with psi0 and E0 of the first start written.  The same
+ * options apply to the ground state inside the four-step drivers.
+ * unique_check = 0 (the default of a zeroed struct) skips the second run
+ * (fidelity2 = -1). */
 typedef struct {
-    double tol;
-    int    max_iter;
-    int    check_every;
-    int    reorth;
+    double   tol;
+    int      max_iter;
+    int      check_every;
+    int      reorth;
+    int      unique_check;
+    double   unique_tol;
+    uint64_t unique_seed;
 } kgf_gs_opts;
 typedef struct {
     int    iters;
     int    converged;
     double residual;
+    double fidelity2;
 } kgf_gs_info;
 int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
                       const kgf_gs_opts* opts, const kgf_c128* v0, kgf_c128* psi0,
@@ -168,6 +188,13 @@ int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* se
  * vectors of a batch run independent recursions (own a_k, b_k, T).
  * reorth: 0 none, 1 classical GS, 2 classical GS twice.  A recursion
  * stops early (exactly) when b_{k+1} <= breakdown_tol * max(|a_j|, b_j).
+ * host_err_est (or NULL): the largest, over columns and steps, a-posteriori
+ * estimate of one step's error in the 2-norm,
+ *     beta0 * b_m * |[f(T_m) e_1]_{m-1}|,   f(T) = exp(-+i T dt) or exp(-(T - shift) dt),
+ * the first term of the error of the Krylov approximation of Eq. (udelta)
+ * (b_m: the norm the recursion would carry into a further step; zero after
+ * a breakdown, where the step is exact).  Asking for it costs one more
+ * vector update per step and synchronises the stream.
  * Workspace: krylov_dim * nvec vectors of D complex128. */
 typedef struct {
     int    krylov_dim;
@@ -178,7 +205,8 @@ typedef struct {
     double breakdown_tol;
 } kgf_prop_opts;
 int  kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
-                   kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts);
+                   kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts,
+                   double* host_err_est);
 
 /* ---- allocation-free propagation ---------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
@@ -198,7 +226,8 @@ int  kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* secto
  * every value a step reads is written earlier in the same step. */
 #define KGF_NOALLOC_SCRATCH_BYTES (64ull << 20)
 int  kgf_propagate_noalloc(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
-                           kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts);
+                           kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts,
+                           double* host_err_est);
 
 /* ---- equilibrium Green's function (Sec. 3, Eqs. (psit), (psigreen), eta=0)
  *   G^>_{ij}(t_k) = -i e^{+i E0 t_k} <c+_i 0| e^{-iH t_k} |c+_j 0>
@@ -465,7 +494,11 @@ int  kgf_propagate_vjp(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s
  * cg_tol).  host_W_lesser / host_W_greater: [nt][nt][n_orb][n_orb] or NULL
  * (zero).  Optional outputs: G^<, G^> of the forward pass, E0, the number
  * of CG iterations.  Cost: about four forward passes; memory: the forward
- * mesh, the backward-propagated states of every mesh time and one chain. */
+ * mesh, the backward-propagated states of every mesh time and one chain.
+ * KGF_ENOCONV (outputs still written, host_grad_ini not to be trusted) when
+ * the projected CG stops above cg_tol: at its iteration limit
+ * (KGF_OPT_CG_MAX_ITER) or on a non-positive curvature p^T (H - E0) p, which
+ * a (near-)degenerate ground state produces. */
 int  kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                         const kgf_sector* sector, const kgf_gs_opts* gs_opts, const kgf_c128* v0,
                         const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
@@ -485,7 +518,8 @@ int  kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H
  * be NULL, entries NULL = zero cotangent), host_grad_ini[i] (n_theta(H_ini[i])
  * doubles), host_grad[i] (n_theta(H[i]) doubles; NULL entries skip);
  * host_E0 [n_inst]; host_cg_iters [n_inst] or NULL.  Memory: the plain-
- * schedule meshes of kgf_greens_neq_vjp times the group size. */
+ * schedule meshes of kgf_greens_neq_vjp times the group size.  KGF_ENOCONV
+ * as kgf_greens_neq_vjp when the CG of any instance stops above cg_tol. */
 int  kgf_greens_neq_vjp_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H_ini,
                               const kgf_model* const* H, const kgf_sector* const* sectors,
                               const kgf_gs_opts* gs_opts, const kgf_c128* const* v0,
@@ -537,10 +571,12 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      on scratch vectors, separately for the plain and the
  *                      Lanczos form, and keeps the fastest for that context.
  *                      HV_PASSES / HV_STRIP, when set, take precedence.
+ *   KGF_OPT_CG_MAX_ITER: iteration limit of the projected CG of the four-step
+ *                      adjoints (0 = 20000).
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
 enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5,
-       KGF_OPT_HV_TUNE = 6 };
+       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

@@ -20,7 +20,8 @@ DIRECTION_BACKWARD = +1     # exp(+i H dt)
 DIRECTION_IMAGINARY = 0     # exp(-(H - shift) dt)
 
 KGF_OK = 0
-_CODES = {-1: "KGF_EINVAL", -2: "KGF_ENOMEM", -3: "KGF_EHIP", -4: "KGF_ENOCONV", -5: "KGF_EUNSUPPORTED"}
+_CODES = {-1: "KGF_EINVAL", -2: "KGF_ENOMEM", -3: "KGF_EHIP", -4: "KGF_ENOCONV", -5: "KGF_EUNSUPPORTED",
+          -6: "KGF_EDEGENERATE"}
 
 
 class KgfError(RuntimeError):
@@ -41,11 +42,18 @@ class _ModelDesc(C.Structure):
 
 
 class _GsOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("reorth", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("reorth", C.c_int),
+                ("unique_check", C.c_int), ("unique_tol", C.c_double), ("unique_seed", C.c_uint64)]
 
 
 class _GsInfo(C.Structure):
-    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("residual", C.c_double)]
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("residual", C.c_double), ("fidelity2", C.c_double)]
+
+
+def _gs(tol, max_iter, check_every, reorth, unique_check=False, unique_tol=0.0, unique_seed=8):
+    """kgf_gs_opts; unique_check runs the second-start uniqueness test."""
+    return _GsOpts(float(tol), int(max_iter), int(check_every), int(reorth), int(bool(unique_check)),
+                   float(unique_tol), int(unique_seed))
 
 
 class _PropOpts(C.Structure):
@@ -109,8 +117,9 @@ def load_library():
         "kgf_apply_h": (I, [P, P, P, P, P, I, I64]),
         "kgf_apply_c": (I, [P, P, P, I, I, P, P, I, I64, I64]),
         "kgf_ground_state": (I, [P, P, P, C.POINTER(_GsOpts), P, P, C.POINTER(D), C.POINTER(_GsInfo)]),
-        "kgf_propagate": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts)]),
-        "kgf_propagate_noalloc": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts)]),
+        "kgf_propagate": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts), C.POINTER(D)]),
+        "kgf_propagate_noalloc": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts), C.POINTER(D)]),
+        "kgf_model_get_params": (I, [P, P, P, P, P]),
         "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                I, I, D, P, P, P, P, C.POINTER(D), P]),
@@ -153,7 +162,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
             "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_greens2_neq",
             "kgf_neq_run_create", "kgf_neq_run_advance", "kgf_neq_run_result", "kgf_neq_run_destroy",
-            "kgf_propagate_noalloc",
+            "kgf_propagate_noalloc", "kgf_model_get_params",
             "kgf_profile_begin",
             "kgf_profile_end"]
 
@@ -223,6 +232,18 @@ class Model:
         except Exception:
             self._t, self._eu, self._ed, self._U = old
             raise
+
+    def device_params(self):
+        """kgf_model_get_params: the parameters the library holds (t, eps_up,
+        eps_dn, U) -- after a driven propagation, the last stage's."""
+        nb = len(self._bi)
+        t, eu, ed, U = (np.zeros(max(n, 1)) for n in (nb, self.L, self.L, self.L))
+        _check(_lib.kgf_model_get_params(self.handle, _np_ptr(t), _np_ptr(eu), _np_ptr(ed), _np_ptr(U)))
+        return t[:nb], eu, ed, U
+
+    def _sync_params(self):
+        # mirror the library's copy after calls that replace the parameters in place
+        self._t, self._eu, self._ed, self._U = (np.ascontiguousarray(a.copy()) for a in self.device_params())
 
     @classmethod
     def from_spec(cls, ctx: "Context", spec) -> "Model":
@@ -403,28 +424,36 @@ class Context:
         return out
 
     def ground_state(self, model: Model, sec: Sector, v0, tol=1e-12, max_iter=300, check_every=1, reorth=2,
-                     out=None, allow_unconverged=False):
+                     out=None, allow_unconverged=False, unique_check=False, unique_tol=0.0, unique_seed=8):
+        """kgf_ground_state; with unique_check a second start (SplitMix64,
+        unique_seed) tests the uniqueness of |0> (KgfError KGF_EDEGENERATE
+        when the two Ritz vectors differ)."""
         self._chk(v0, sec.dim, "v0")
         out = self.empty(sec.dim) if out is None else out
         E0 = C.c_double()
         info = _GsInfo()
         rc = _lib.kgf_ground_state(self.handle, model.handle, sec.handle,
-                                   C.byref(_GsOpts(float(tol), int(max_iter), int(check_every), int(reorth))),
+                                   C.byref(_gs(tol, max_iter, check_every, reorth, unique_check, unique_tol,
+                                               unique_seed)),
                                    _ptr(v0), _ptr(out), C.byref(E0), C.byref(info))
         if rc == -4 and allow_unconverged:
             pass
         else:
             _check(rc)
-        return E0.value, out, {"iters": info.iters, "converged": bool(info.converged), "residual": info.residual}
+        return E0.value, out, {"iters": info.iters, "converged": bool(info.converged), "residual": info.residual,
+                               "fidelity2": info.fidelity2}
 
     def propagate(self, model: Model, sec: Sector, psi, nsteps: int, dt: float, krylov_dim: int = 15,
                   direction: int = DIRECTION_FORWARD, shift: float = 0.0, reorth: int = 0,
-                  breakdown_tol: float = 1e-13):
+                  breakdown_tol: float = 1e-13, return_err: bool = False):
+        """kgf_propagate; with return_err also the largest per-step a-posteriori
+        error estimate (returns (psi, err))."""
         nvec = self._chk(psi, sec.dim, "psi")
         o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
+        err = C.c_double()
         _check(_lib.kgf_propagate(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
-                                  C.byref(o)))
-        return psi
+                                  C.byref(o), C.byref(err) if return_err else None))
+        return (psi, err.value) if return_err else psi
 
     def propagate_noalloc(self, model: Model, sec: Sector, psi, nsteps: int, dt: float, krylov_dim: int = 15,
                           direction: int = DIRECTION_FORWARD, shift: float = 0.0, reorth: int = 0,
@@ -434,7 +463,7 @@ class Context:
         nvec = self._chk(psi, sec.dim, "psi")
         o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
         _check(_lib.kgf_propagate_noalloc(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim,
-                                          int(nsteps), C.byref(o)))
+                                          int(nsteps), C.byref(o), None))
         return psi
 
     # Gauss-Legendre nodes of the driven integrator, as fractions of a step
@@ -452,8 +481,7 @@ class Context:
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
         _check(_lib.kgf_propagate_driven(self.handle, work.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
                                          th.shape[0], _np_ptr(th), _np_ptr(fv), C.byref(o)))
-        if nsteps > 0 and nvec > 0 and sec.dim > 0:
-            self._mirror_last_stage(work, th, fv)
+        work._sync_params()
         return psi
 
     def _drive_table(self, work: Model, thetas, f, nsteps: int, dt: float, t0: float):
@@ -473,19 +501,10 @@ class Context:
             fv[:] = 0.0
         return th, np.ascontiguousarray(fv)
 
-    @staticmethod
-    def _mirror_last_stage(work: Model, th, fv):
-        # the device holds the last stage's parameters: mirror them on the host
-        a1, a2 = 0.25 - np.sqrt(3.0) / 6.0, 0.25 + np.sqrt(3.0) / 6.0
-        last = (a1 * fv[-1, 0] + a2 * fv[-1, 1]) @ th
-        nb, L = len(work._bi), work.L
-        work._t, work._eu = last[:nb].copy(), last[nb:nb + L].copy()
-        work._ed, work._U = last[nb + L:nb + 2 * L].copy(), last[nb + 2 * L:].copy()
-
     def greens_neq_driven(self, H_ini: Model, work: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]],
                           thetas, f, nt: int, steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0,
                           batch: int = 0, gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1,
-                          gs_reorth: int = 2, breakdown_tol: float = 1e-13):
+                          gs_reorth: int = 2, gs_unique_check: bool = False, breakdown_tol: float = 1e-13):
         """kgf_greens_neq_driven: four-step G^<, G^> [nt, nt, n_orb, n_orb] after
         the ground state of H_ini, under H(t) = sum_j f(t)[j] H(thetas[j]) from
         t = 0 (steps of dt, steps_per_grid per mesh interval).  `work` (not
@@ -501,13 +520,12 @@ class Context:
         Gg = _host_c128((nt, nt, no, no))
         E0 = C.c_double()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        g = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens_neq_driven(self.handle, H_ini.handle, work.handle, sec.handle, C.byref(g), _ptr(v0),
                                           _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(batch),
                                           th.shape[0], _np_ptr(th), _np_ptr(fv), _np_ptr(Gl), _np_ptr(Gg),
                                           C.byref(E0)))
-        if nsteps > 0:
-            self._mirror_last_stage(work, th, fv)
+        work._sync_params()
         return {"G_lesser": Gl, "G_greater": Gg, "E0": E0.value}
 
     def greens_eq(self, model: Model, sec: Sector, psi0, E0: float, orbitals: Sequence[Tuple[int, int]],
@@ -526,7 +544,7 @@ class Context:
     def greens_neq(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
                    steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0, schedule: int = 1,
                    batch: int = 0, ntau: int = 0, tau_steps_per_grid: int = 1, dtau: float = 0.0,
-                   gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                   gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2, gs_unique_check: bool = False,
                    breakdown_tol: float = 1e-13, psi0_out=None):
         self._chk(v0, sec.dim, "v0")
         if psi0_out is not None:
@@ -539,7 +557,7 @@ class Context:
         Gx = _host_c128((nt, ntau, no, no)) if ntau > 0 else None
         E0 = C.c_double()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        g = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens_neq(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
                                    _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(schedule),
                                    int(batch), int(ntau), int(tau_steps_per_grid), float(dtau), _np_ptr(Gl),
@@ -552,7 +570,7 @@ class Context:
 
     def neq_run(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
                 steps_per_grid: int, dt: float, krylov_dim: int = 15, reorth: int = 0, batch: int = 0,
-                gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2, gs_unique_check: bool = False,
                 breakdown_tol: float = 1e-13) -> NeqRun:
         """kgf_neq_run_create: ground state and forward mesh of the four-step
         procedure; the returned run advances the backward sweeps."""
@@ -561,7 +579,7 @@ class Context:
         E0 = C.c_double()
         h = C.c_void_p()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        g = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_neq_run_create(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
                                        _np_ptr(orbs), len(orbs), int(nt), int(steps_per_grid), C.byref(o), int(batch),
                                        C.byref(h), C.byref(E0)))
@@ -570,7 +588,7 @@ class Context:
     def greens_neq_multi(self, H_ini: Sequence[Model], H: Sequence[Model], secs: Sequence[Sector], v0s,
                          orbitals: Sequence[Tuple[int, int]], nt: int, steps_per_grid: int, dt: float,
                          krylov_dim: int = 15, reorth: int = 0, batch: int = 0, gs_tol: float = 1e-12,
-                         gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                         gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2, gs_unique_check: bool = False,
                          breakdown_tol: float = 1e-13):
         """kgf_greens_neq_multi: four-step G^<, G^> of many instances in one call
         (same-sector, same-topology instances batched).  Returns G_lesser,
@@ -587,7 +605,7 @@ class Context:
         def arr(xs):
             return (C.c_void_p * n)(*[(x.value if isinstance(x, C.c_void_p) else int(x)) for x in xs])
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        g = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens_neq_multi(self.handle, n, arr(m.handle for m in H_ini), arr(m.handle for m in H),
                                          arr(s_.handle for s_ in secs), arr(_ptr(v) for v in v0s), C.byref(g),
                                          _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(batch),
@@ -596,7 +614,7 @@ class Context:
 
     def greens2_neq(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
                     steps_per_grid: int, dt: float, pattern=(1, 1, 0, 0), krylov_dim: int = 15, reorth: int = 0,
-                    gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2,
+                    gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1, gs_reorth: int = 2, gs_unique_check: bool = False,
                     breakdown_tol: float = 1e-13):
         """kgf_greens2_neq: chi[k1, k2, k3, k4, a, b, c, d] =
         <0| O1_a(t_k1) O2_b(t_k2) O3_c(t_k3) O4_d(t_k4) |0> after the ground
@@ -609,7 +627,7 @@ class Context:
         chi = _host_c128((nt, nt, nt, nt, no, no, no, no))
         E0 = C.c_double()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        g = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        g = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens2_neq(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
                                     _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), bits,
                                     _np_ptr(chi), C.byref(E0)))
@@ -678,11 +696,11 @@ class Context:
                                 _np_ptr(out)))
         return out
 
-    HV_PASSES, HV_STRIP, GS_MAX_BASIS, PHI_EVERY, ADJ_EVERY, HV_TUNE = 1, 2, 3, 4, 5, 6
+    HV_PASSES, HV_STRIP, GS_MAX_BASIS, PHI_EVERY, ADJ_EVERY, HV_TUNE, CG_MAX_ITER = 1, 2, 3, 4, 5, 6, 7
 
     def set_option(self, option: int, value: int) -> None:
         """kgf_set_option: HV_PASSES 0..4, HV_STRIP 0/8/16/32/64, GS_MAX_BASIS 0 or >= 8, PHI_EVERY >= 0,
-        ADJ_EVERY >= 0, HV_TUNE 0/1."""
+        ADJ_EVERY >= 0, HV_TUNE 0/1, CG_MAX_ITER >= 0."""
         _check(_lib.kgf_set_option(self.handle, int(option), int(value)))
 
     def set_progress(self, fn=None):
@@ -733,7 +751,7 @@ class Context:
     def greens_neq_vjp(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals, nt: int, steps_per_grid: int,
                        dt: float, W_lesser=None, W_greater=None, krylov_dim: int = 15, reorth: int = 0,
                        quad_nodes: int = 12, cg_tol: float = 1e-12, gs_tol: float = 1e-12, gs_max_iter: int = 300,
-                       gs_check_every: int = 1, gs_reorth: int = 2, breakdown_tol: float = 1e-13):
+                       gs_check_every: int = 1, gs_reorth: int = 2, gs_unique_check: bool = False, breakdown_tol: float = 1e-13):
         """dL/dtheta_ini and dL/dtheta for L = Re sum conj(W^<) G^< + Re sum conj(W^>) G^>."""
         self._chk(v0, sec.dim, "v0")
         orbs = np.ascontiguousarray([2 * s + sp for s, sp in orbitals], dtype=np.int32)
@@ -748,7 +766,7 @@ class Context:
         E0 = C.c_double()
         cgi = C.c_int()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        gso = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        gso = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens_neq_vjp(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(gso), _ptr(v0),
                                        _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), _np_ptr(Wl),
                                        _np_ptr(Wg), int(quad_nodes), float(cg_tol), _np_ptr(gi), _np_ptr(g),
@@ -760,7 +778,7 @@ class Context:
                              nt: int, steps_per_grid: int, dt: float, W_lesser=None, W_greater=None,
                              krylov_dim: int = 15, reorth: int = 0, quad_nodes: int = 12, cg_tol: float = 1e-12,
                              gs_tol: float = 1e-12, gs_max_iter: int = 300, gs_check_every: int = 1,
-                             gs_reorth: int = 2, breakdown_tol: float = 1e-13):
+                             gs_reorth: int = 2, gs_unique_check: bool = False, breakdown_tol: float = 1e-13):
         """kgf_greens_neq_vjp_multi: gradients of n instances (same-sector,
         same-topology instances batched).  W_lesser / W_greater: sequences of
         [nt][nt][n_orb][n_orb] arrays (or None).  Returns a list of dicts."""
@@ -787,7 +805,7 @@ class Context:
         def hv(xs):
             return (C.c_void_p * n)(*[(x.value if isinstance(x, C.c_void_p) else int(x)) for x in xs])
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
-        gso = _GsOpts(float(gs_tol), int(gs_max_iter), int(gs_check_every), int(gs_reorth))
+        gso = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens_neq_vjp_multi(self.handle, n, hv(m.handle for m in H_ini), hv(m.handle for m in H),
                                              hv(s_.handle for s_ in secs), C.byref(gso), hv(_ptr(v) for v in v0s),
                                              _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), Wl, Wg,

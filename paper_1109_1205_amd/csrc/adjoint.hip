@@ -264,8 +264,11 @@ void chain_adjoint(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int nm, co
 }
 
 // (H - E0) mu = (1 - P0) r, mu orthogonal to psi0 (unit norm), by projected CG.
+// *converged: the residual reached tol (false after maxit iterations or a
+// non-positive curvature p^T (H - E0) p).
 static int projected_cg(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0, double E0,
-                        const double2* rhs, double2* mu, double tol, int maxit) {
+                        const double2* rhs, double2* mu, double tol, int maxit, bool* converged) {
+    *converged = false;
     const int64_t D = sec->dim();
     double2* r = static_cast<double2*>(workspace(ctx, "cg_r", sizeof(double2) * D));
     double2* p = static_cast<double2*>(workspace(ctx, "cg_p", sizeof(double2) * D));
@@ -276,7 +279,10 @@ static int projected_cg(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, c
     KGF_HIP(hipMemcpyAsync(p, r, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
     double rr = dot(ctx, r, r, D).real();
     const double bnorm = std::sqrt(rr);
-    if (bnorm == 0.0) return 0;
+    if (bnorm == 0.0) {
+        *converged = true;
+        return 0;
+    }
     int it = 0;
     for (; it < maxit; ++it) {
         apply_h(ctx, model, sec, p, Ap, 1, D);
@@ -290,6 +296,7 @@ static int projected_cg(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, c
         const double rr2 = dot(ctx, r, r, D).real();
         if (std::sqrt(rr2) <= tol * bnorm) {
             ++it;
+            *converged = true;
             break;
         }
         hipLaunchKernelGGL(k_xpby, dim3(grid_for(D)), dim3(kThreads), 0, ctx->stream, p, r, rr2 / rr, D);
@@ -314,6 +321,7 @@ struct VjpMember {
     double2* Gg = nullptr;
     double* E0 = nullptr;
     int* cg_iters = nullptr;
+    bool cg_failed = false;
 };
 
 struct VjpArgs {
@@ -349,6 +357,7 @@ static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const kgf_gs_opts* gso
         GsResult gs = ground_state(ctx, M[j].Hi, sec, M[j].v0, psi0 + (size_t)j * D, gso->tol, gso->max_iter,
                                    gso->check_every, gso->reorth);
         KGF_REQUIRE(gs.converged, KGF_ENOCONV, "adjoint: ground state of H_ini did not converge");
+        require_unique_ground_state(ctx, M[j].Hi, sec, psi0 + (size_t)j * D, gso, "adjoint");
         E0[j] = gs.E0;
         if (M[j].E0) *M[j].E0 = gs.E0;
     }
@@ -479,8 +488,10 @@ static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const kgf_gs_opts* gso
         int it = 0;
         if (M[j].Wl || M[j].Wg) {
             double2* mu = static_cast<double2*>(workspace(ctx, "vjp_mu", vb));
+            bool conv = false;
             it = projected_cg(ctx, M[j].Hi, sec, psi0 + (size_t)j * D, E0[j], lam + (size_t)j * D, mu, A.cg_tol,
-                              A.cg_maxit);
+                              A.cg_maxit, &conv);
+            M[j].cg_failed = !conv;
             const double2 wm = make_double2(-2.0, 0.0);
             dH_expect(ctx, M[j].Hi, sec, mu, D, psi0 + (size_t)j * D, D, 1, &wm, gi + (size_t)j * nthi);
         }
@@ -569,6 +580,10 @@ int kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
         KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && quad_nodes >= 1 && quad_nodes <= 31 &&
                         std::isfinite(cg_tol) && cg_tol > 0.0,
                     KGF_EINVAL, "kgf_greens_neq_vjp: bad sizes");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        gs_unique_opts_ok(gs_opts),
+                    KGF_EINVAL, "kgf_greens_neq_vjp: bad ground-state options");
         for (int a = 0; a < n_orb; ++a)
             KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
                         "kgf_greens_neq_vjp: orbital out of range");
@@ -582,7 +597,7 @@ int kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
         A.o = to_sil_opts(opts);
         A.nq = quad_nodes;
         A.cg_tol = cg_tol;
-        A.cg_maxit = 20000;
+        A.cg_maxit = ctx->cg_max_iter > 0 ? ctx->cg_max_iter : 20000;
         std::vector<VjpMember> M(1);
         M[0].Hi = const_cast<kgf_model*>(H_ini);
         M[0].Hf = const_cast<kgf_model*>(H);
@@ -596,6 +611,9 @@ int kgf_greens_neq_vjp(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
         M[0].E0 = host_E0;
         M[0].cg_iters = host_cg_iters;
         four_step_vjp(ctx, A, gs_opts, M);
+        KGF_REQUIRE(!M[0].cg_failed, KGF_ENOCONV,
+                    "kgf_greens_neq_vjp: the projected CG of the ground-state term stopped above cg_tol "
+                    "(iteration limit or non-positive curvature); host_grad_ini is not reliable");
     });
 }
 
@@ -613,6 +631,10 @@ int kgf_greens_neq_vjp_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H
         KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && quad_nodes >= 1 && quad_nodes <= 31 &&
                         std::isfinite(cg_tol) && cg_tol > 0.0,
                     KGF_EINVAL, "kgf_greens_neq_vjp_multi: bad sizes");
+        KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        gs_unique_opts_ok(gs_opts),
+                    KGF_EINVAL, "kgf_greens_neq_vjp_multi: bad ground-state options");
         for (int i = 0; i < n_inst; ++i) {
             KGF_REQUIRE(H_ini[i] && H[i] && sectors[i] && v0[i], KGF_EINVAL, "kgf_greens_neq_vjp_multi: NULL instance");
             KGF_REQUIRE(H_ini[i]->L == sectors[i]->L && H[i]->L == sectors[i]->L && sectors[i]->dim() > 0, KGF_EINVAL,
@@ -623,6 +645,7 @@ int kgf_greens_neq_vjp_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H
         }
         KGF_HIP(hipSetDevice(ctx->device));
         std::vector<int> done(n_inst, 0);
+        bool cg_failed = false;
         for (int i0 = 0; i0 < n_inst; ++i0) {
             if (done[i0]) continue;
             std::vector<VjpMember> M;
@@ -653,9 +676,13 @@ int kgf_greens_neq_vjp_multi(kgf_ctx* ctx, int n_inst, const kgf_model* const* H
             A.o = to_sil_opts(opts);
             A.nq = quad_nodes;
             A.cg_tol = cg_tol;
-            A.cg_maxit = 20000;
+            A.cg_maxit = ctx->cg_max_iter > 0 ? ctx->cg_max_iter : 20000;
             four_step_vjp(ctx, A, gs_opts, M);
+            for (const VjpMember& mb : M) cg_failed = cg_failed || mb.cg_failed;
         }
+        KGF_REQUIRE(!cg_failed, KGF_ENOCONV,
+                    "kgf_greens_neq_vjp_multi: the projected CG of a ground-state term stopped above cg_tol "
+                    "(iteration limit or non-positive curvature); that instance's host_grad_ini is not reliable");
     });
 }
 

@@ -4,7 +4,9 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "kgf_internal.h"
 
@@ -167,6 +169,11 @@ void check_prop_opts(const kgf_prop_opts* o) {
                 KGF_EINVAL, "non-finite propagation option");
 }
 
+bool gs_unique_opts_ok(const kgf_gs_opts* o) {
+    return (o->unique_check == 0 || o->unique_check == 1) && std::isfinite(o->unique_tol) && o->unique_tol >= 0.0 &&
+           o->unique_tol < 1.0;
+}
+
 SilOpts to_sil_opts(const kgf_prop_opts* o) {
     SilOpts s;
     s.m = o->krylov_dim;
@@ -271,6 +278,17 @@ int kgf_model_set_params(kgf_model* m, const kgf_model_desc* d) {
                         finite_all(d->U, m->L),
                     KGF_EINVAL, "kgf_model_set_params: non-finite parameter");
         model_set_params(m, d->t_bond, d->eps_up, d->eps_dn, d->U);
+    });
+}
+
+int kgf_model_get_params(const kgf_model* m, double* host_t, double* host_eps_up, double* host_eps_dn,
+                         double* host_U) {
+    return guarded([&] {
+        KGF_REQUIRE(m, KGF_EINVAL, "kgf_model_get_params: NULL model");
+        if (host_t) std::copy(m->t.begin(), m->t.end(), host_t);
+        if (host_eps_up) std::copy(m->eps_up.begin(), m->eps_up.end(), host_eps_up);
+        if (host_eps_dn) std::copy(m->eps_dn.begin(), m->eps_dn.end(), host_eps_dn);
+        if (host_U) std::copy(m->U.begin(), m->U.end(), host_U);
     });
 }
 
@@ -399,30 +417,44 @@ int kgf_apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int 
 }
 
 
+// largest of n device doubles (n small: the per-column error estimates)
+static double host_max(kgf_ctx* ctx, const double* dev, int n) {
+    std::vector<double> h((size_t)n);
+    KGF_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    double m = 0.0;
+    for (double v : h) m = std::fmax(m, v);
+    return m;
+}
+
 int kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, kgf_c128* psi,
-                  int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts) {
+                  int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts, double* host_err_est) {
     return guarded([&] {
         KGF_REQUIRE(ctx && model && s, KGF_EINVAL, "kgf_propagate: NULL handle");
         KGF_REQUIRE(model->L == s->L, KGF_EINVAL, "kgf_propagate: model and sector L differ");
         check_prop_opts(opts);
         KGF_REQUIRE(nvec >= 0 && nsteps >= 0 && ld >= s->dim(), KGF_EINVAL,
                     "kgf_propagate: bad nvec / nsteps / ld");
+        if (host_err_est) *host_err_est = 0.0;
         if (nvec == 0 || nsteps == 0 || s->dim() == 0) return;
         KGF_REQUIRE(psi, KGF_EINVAL, "kgf_propagate: NULL psi");
         KGF_HIP(hipSetDevice(ctx->device));
+        double* err = host_err_est ? static_cast<double*>(workspace(ctx, "sil_err", sizeof(double) * nvec)) : nullptr;
         sil_propagate(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<double2*>(psi), nvec,
-                      ld, nsteps, to_sil_opts(opts));
+                      ld, nsteps, to_sil_opts(opts), err);
+        if (host_err_est) *host_err_est = host_max(ctx, err, nvec);
     });
 }
 
 int kgf_propagate_noalloc(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, kgf_c128* psi,
-                          int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts) {
+                          int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts, double* host_err_est) {
     return guarded([&] {
         KGF_REQUIRE(ctx && model && s, KGF_EINVAL, "kgf_propagate_noalloc: NULL handle");
         KGF_REQUIRE(model->L == s->L, KGF_EINVAL, "kgf_propagate_noalloc: model and sector L differ");
         check_prop_opts(opts);
         KGF_REQUIRE(nvec >= 0 && nvec <= 65535 && nsteps >= 0 && ld >= s->dim(), KGF_EINVAL,
                     "kgf_propagate_noalloc: bad nvec / nsteps / ld");
+        if (host_err_est) *host_err_est = 0.0;
         if (nvec == 0 || nsteps == 0 || s->dim() == 0) return;
         KGF_REQUIRE(psi, KGF_EINVAL, "kgf_propagate_noalloc: NULL psi");
         KGF_REQUIRE(hop_table_ready(model, s->n_up) && hop_table_ready(model, s->n_dn), KGF_EINVAL,
@@ -436,8 +468,19 @@ int kgf_propagate_noalloc(kgf_ctx* ctx, const kgf_model* model, const kgf_sector
         KGF_HIP(hipSetDevice(ctx->device));
         void* base = g_scratch_addr[ctx->device];
         KGF_REQUIRE(base != nullptr, KGF_EHIP, "kgf_propagate_noalloc: scratch address not resolved");
-        sil_propagate_in(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<double2*>(psi), nvec, ld, nsteps,
-                         to_sil_opts(opts), base);
+        double* err = sil_propagate_in(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<double2*>(psi), nvec,
+                                       ld, nsteps, to_sil_opts(opts), base, host_err_est != nullptr);
+        if (host_err_est) {   // a fixed-size host copy: no allocation on either side
+            double h[64];
+            double mx = 0.0;
+            for (int c0 = 0; c0 < nvec; c0 += 64) {
+                const int n = std::min(64, nvec - c0);
+                KGF_HIP(hipMemcpyAsync(h, err + c0, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+                sync(ctx);
+                for (int i = 0; i < n; ++i) mx = std::fmax(mx, h[i]);
+            }
+            *host_err_est = mx;
+        }
     });
 }
 
@@ -451,7 +494,9 @@ int kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s,
         KGF_REQUIRE(s->dim() > 0, KGF_EINVAL, "kgf_ground_state: empty sector");
         KGF_REQUIRE(v0 && psi0, KGF_EINVAL, "kgf_ground_state: NULL vector");
         KGF_REQUIRE(o->max_iter >= 1 && o->max_iter <= 4000 && o->check_every >= 1 &&
-                        std::isfinite(o->tol) && o->tol >= 0.0 && o->reorth >= 0 && o->reorth <= 2,
+                        std::isfinite(o->tol) && o->tol >= 0.0 && o->reorth >= 0 && o->reorth <= 2 &&
+                        (o->unique_check == 0 || o->unique_check == 1) && std::isfinite(o->unique_tol) &&
+                        o->unique_tol >= 0.0 && o->unique_tol < 1.0,
                     KGF_EINVAL, "kgf_ground_state: bad options");
         KGF_HIP(hipSetDevice(ctx->device));
         GsResult r = ground_state(ctx, const_cast<kgf_model*>(model), s,
@@ -459,14 +504,21 @@ int kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s,
                                   reinterpret_cast<double2*>(psi0), o->tol, o->max_iter,
                                   o->check_every, o->reorth);
         *host_E0 = r.E0;
+        double f2 = -1.0;
+        if (o->unique_check && r.converged)
+            f2 = gs_fidelity2(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<const double2*>(psi0), o);
         if (info) {
             info->iters = r.iters;
             info->converged = r.converged ? 1 : 0;
             info->residual = r.residual;
+            info->fidelity2 = f2;
         }
         if (!r.converged) {
             g_last_error = "ground-state Lanczos did not converge within max_iter";
             conv_code = KGF_ENOCONV;
+        } else if (o->unique_check && !(f2 >= 1.0 - (o->unique_tol > 0.0 ? o->unique_tol : 1e-10))) {
+            g_last_error = "the ground state is not unique: two Lanczos starts give |<0_a|0_b>|^2 = " + std::to_string(f2);
+            conv_code = KGF_EDEGENERATE;
         }
     });
     return rc != KGF_OK ? rc : conv_code;
@@ -522,6 +574,9 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_HV_TUNE) {
             KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: HV_TUNE must be 0 or 1");
             ctx->hv_tune = value;
+        } else if (option == KGF_OPT_CG_MAX_ITER) {
+            KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: CG_MAX_ITER must be >= 0");
+            ctx->cg_max_iter = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

@@ -513,6 +513,7 @@ static double2* neq_forward(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, c
     release(ctx, "gs_V");
     release(ctx, "gs_partbig");
     KGF_REQUIRE(gs.converged, KGF_ENOCONV, "four-step: ground state of H_ini did not converge");
+    require_unique_ground_state(ctx, A.H_ini, sec, psi0, gso, "four-step");
     *E0_out = gs.E0;
     if (psi0_out)
         KGF_HIP(hipMemcpyAsync(psi0_out, psi0, sizeof(double2) * D, hipMemcpyDeviceToDevice, ctx->stream));
@@ -686,6 +687,7 @@ void greens_neq_multi(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* 
             GsResult gs = ground_state(ctx, Hi[mem[k]], sec, v0[mem[k]], Phi + (size_t)k * D, gso->tol, gso->max_iter,
                                        gso->check_every, gso->reorth);
             KGF_REQUIRE(gs.converged, KGF_ENOCONV, "batched four-step: a ground state of H_ini did not converge");
+            require_unique_ground_state(ctx, Hi[mem[k]], sec, Phi + (size_t)k * D, gso, "batched four-step");
             E0_host[mem[k]] = gs.E0;
             progress(ctx, "ground_states", k + 1, n);
         }
@@ -802,6 +804,7 @@ void greens_neq_driven(kgf_ctx* ctx, kgf_model* Hi, kgf_model* work, const kgf_s
     double2* Phi = static_cast<double2*>(workspace(ctx, "dneq_phi", vb * (size_t)nt));
     GsResult gs = ground_state(ctx, Hi, sec, v0, Phi, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
     KGF_REQUIRE(gs.converged, KGF_ENOCONV, "driven four-step: the ground state of H_ini did not converge");
+    require_unique_ground_state(ctx, Hi, sec, Phi, gso, "driven four-step");
     *E0_host = gs.E0;
     release(ctx, "gs_V");
     release(ctx, "gs_partbig");
@@ -924,6 +927,7 @@ void greens2_neq(kgf_ctx* ctx, kgf_model* Hi, kgf_model* H, const kgf_sector* se
     double2* Phi = static_cast<double2*>(workspace(ctx, "g2_phi", vb * (size_t)nt));
     GsResult gs = ground_state(ctx, Hi, sec, v0, Phi, gso->tol, gso->max_iter, gso->check_every, gso->reorth);
     KGF_REQUIRE(gs.converged, KGF_ENOCONV, "four-time function: the ground state of H_ini did not converge");
+    require_unique_ground_state(ctx, Hi, sec, Phi, gso, "four-time function");
     *E0_host = gs.E0;
     release(ctx, "gs_V");
     release(ctx, "gs_partbig");
@@ -1056,7 +1060,8 @@ extern "C" int kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_mo
         KGF_REQUIRE(ntau >= 0 && (ntau == 0 || (tau_steps_per_grid >= 1 && std::isfinite(dtau) && dtau >= 0.0)),
                     KGF_EINVAL, "kgf_greens_neq: bad Matsubara mesh");
         KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
-                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        kgf::gs_unique_opts_ok(gs_opts),
                     KGF_EINVAL, "kgf_greens_neq: bad ground-state options");
         for (int a = 0; a < n_orb; ++a)
             KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
@@ -1147,7 +1152,8 @@ extern "C" int kgf_neq_run_create(kgf_ctx* ctx, const kgf_model* H_ini, const kg
         KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && batch >= 0, KGF_EINVAL,
                     "kgf_neq_run_create: bad sizes");
         KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
-                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        kgf::gs_unique_opts_ok(gs_opts),
                     KGF_EINVAL, "kgf_neq_run_create: bad ground-state options");
         for (int a = 0; a < n_orb; ++a)
             KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
@@ -1260,7 +1266,8 @@ extern "C" int kgf_greens_neq_multi(kgf_ctx* ctx, int n_inst, const kgf_model* c
         KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && batch >= 0, KGF_EINVAL,
                     "kgf_greens_neq_multi: bad sizes");
         KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
-                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        kgf::gs_unique_opts_ok(gs_opts),
                     KGF_EINVAL, "kgf_greens_neq_multi: bad ground-state options");
         for (int i = 0; i < n_inst; ++i) {
             KGF_REQUIRE(H_ini[i] && H[i] && sectors[i] && v0[i], KGF_EINVAL, "kgf_greens_neq_multi: NULL instance");
@@ -1295,7 +1302,8 @@ extern "C" int kgf_greens_neq_driven(kgf_ctx* ctx, const kgf_model* H_ini, kgf_m
         KGF_REQUIRE(n_orb >= 1 && nt >= 1 && steps_per_grid >= 1 && batch >= 0 && n_terms >= 1, KGF_EINVAL,
                     "kgf_greens_neq_driven: bad sizes");
         KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
-                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        kgf::gs_unique_opts_ok(gs_opts),
                     KGF_EINVAL, "kgf_greens_neq_driven: bad ground-state options");
         for (int a = 0; a < n_orb; ++a)
             KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,
@@ -1329,7 +1337,8 @@ extern "C" int kgf_greens2_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_m
         const double n4 = (double)nt * nt * nt * nt * n_orb * n_orb * n_orb * n_orb;
         KGF_REQUIRE(n4 <= (double)(1 << 28), KGF_EUNSUPPORTED, "kgf_greens2_neq: nt^4 n_orb^4 above 2^28");
         KGF_REQUIRE(gs_opts->max_iter >= 1 && gs_opts->max_iter <= 4000 && gs_opts->check_every >= 1 &&
-                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol),
+                        gs_opts->reorth >= 0 && gs_opts->reorth <= 2 && std::isfinite(gs_opts->tol) &&
+                        kgf::gs_unique_opts_ok(gs_opts),
                     KGF_EINVAL, "kgf_greens2_neq: bad ground-state options");
         for (int a = 0; a < n_orb; ++a)
             KGF_REQUIRE(host_orbs[a] >= 0 && (host_orbs[a] >> 1) < sector->L, KGF_EINVAL,

@@ -96,6 +96,7 @@ struct kgf_ctx {
     int phi_every = 0;                       // 0: forward mesh stored whole when it fits
     int adj_every = 0;                       // 0: adjoint chains stored whole when they fit
     int hv_tune = 0;                         // 1: time the H.v variants of each sector once
+    int cg_max_iter = 0;                     // 0: 20000 (projected CG of the adjoints)
     std::map<std::array<int, 4>, std::pair<int, int>> hv_tuned;   // (L, N_up, N_dn, mode) -> (passes, strip)
     // progress callback
     kgf_progress_fn progress = nullptr;
@@ -258,16 +259,20 @@ void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_
                        int c, const double2* coef, int64_t coef_stride, int nout, double2* out,
                        int64_t out_col);
 // Batched short-iterative-Lanczos step(s) on ncol columns psi_c = psi + c*ld.
+// err (device, ncol doubles, or null): the largest a-posteriori step error
+// estimate of each column over the steps.
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi,
-                   int ncol, int64_t ld, int nsteps, const SilOpts& o);
+                   int ncol, int64_t ld, int nsteps, const SilOpts& o, double* err = nullptr);
 
 // Bytes of the one buffer that sil_propagate_in carves its Krylov slots,
 // scalars and partials from, and SIL steps with every device buffer in
 // `scratch` (no allocation; the model's hopping tables for the sector's
 // particle numbers must exist).
 size_t sil_scratch_bytes(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth);
-void sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
-                      int nsteps, const SilOpts& o, void* scratch);
+// Returns the device address of the per-column error estimates when
+// want_err (inside the scratch), else null.
+double* sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                         int nsteps, const SilOpts& o, void* scratch, bool want_err);
 // true when the model's hopping table for n particles has been built
 bool hop_table_ready(const kgf_model* model, int n);
 
@@ -280,6 +285,14 @@ struct GsResult {
 GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec,
                       const double2* v0, double2* psi0, double tol, int max_iter,
                       int check_every, int reorth);
+
+// |<psi0|psi_b>|^2 for psi_b the ground state from a second (SplitMix64) start
+// vector, and the check that raises KGF_EDEGENERATE below 1 - unique_tol
+// (no-op unless o->unique_check).
+double gs_fidelity2(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,
+                    const kgf_gs_opts* o);
+void require_unique_ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,
+                                 const kgf_gs_opts* o, const char* who);
 
 // n Lanczos steps from i0: a[0..n), b[1..n) (host), <i0|i0>; returns the
 // steps taken (fewer when the Krylov space is exhausted).
@@ -302,6 +315,8 @@ int abi_guard(F&& f) {
     return abi_guard_impl(&f, [](void* p) { (*static_cast<F*>(p))(); });
 }
 void check_prop_opts(const kgf_prop_opts* o);
+// the uniqueness fields of ground-state options are valid
+bool gs_unique_opts_ok(const kgf_gs_opts* o);
 SilOpts to_sil_opts(const kgf_prop_opts* o);
 
 // ---- greens (greens.hip) -------------------------------------------------

@@ -853,6 +853,76 @@ void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reort
     }
 }
 
+// A-posteriori estimate of one SIL step's error.  The Krylov state
+// u(t) = beta0 V_m f(t T_m) e_1 leaves the residual r(t) = A u - u' =
+// beta0 b_m [f(t T_m) e_1]_{m-1} v_m (A = -+iH, or -(H - shift)), and the
+// error of the step is int_0^dt e^{(dt - t) A} r(t) dt, so
+//     err <= beta0 b_m int_0^dt |[f(t T_m) e_1]_{m-1}| dt
+// (with the norm of e^{(dt - t) A} at most 1: real time, or imaginary time
+// with the shift at or below the spectrum).  The integral is taken with a
+// kErrNodes-point Gauss-Legendre rule on [0, dt]; the coefficients at the
+// nodes are coef_k = beta0 u_k s_k, so beta0 |u_{m-1}| = |coef_{m-1}| / s_{m-1}.
+// err[c] keeps the largest value over the steps.
+constexpr int kErrNodes = 16;
+struct GlRule {
+    double x[kErrNodes];   // nodes on [0, 1]
+    double w[kErrNodes];   // weights, summing to 1
+};
+
+// Gauss-Legendre rule on [0, 1]: the roots of P_n by Newton's method from
+// the Chebyshev-like first guesses, weights 2 / ((1 - z^2) P_n'(z)^2) halved.
+static GlRule make_gl_rule() {
+    GlRule g;
+    const int n = kErrNodes;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        g.x[i] = 0.5 * (1.0 - z);
+        g.w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return g;
+}
+
+static const GlRule& gl_rule() {
+    static const GlRule g = make_gl_rule();
+    return g;
+}
+
+__global__ void k_err_est(const double* __restrict__ scal, int m, int ncol, const double2* __restrict__ nodec,
+                          GlRule g, double dt, double* __restrict__ err) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    const double* sc = scal + (int64_t)c * kScalStride;
+    const double s = sc[kOffS + m - 1];
+    double e = 0.0;
+    if (s != 0.0) {
+        double acc = 0.0;
+        for (int i = 0; i < kErrNodes; ++i) {
+            const double2 cf = nodec[((int64_t)c * kErrNodes + i) * m + m - 1];
+            acc += g.w[i] * hypot(cf.x, cf.y);
+        }
+        e = fabs(dt) * sc[kOffB + m] * acc / s;
+    }
+    err[c] = fmax(err[c], e);
+}
+
+__global__ void k_fill_zero(double* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
 // Device memory of one batched SIL step: the Krylov slots 1..m (slot 0 is
 // the state itself), the per-column scalars, the reduction partials and,
 // with reorthogonalisation, the Gram-Schmidt partials and coefficients.
@@ -862,11 +932,13 @@ struct SilWork {
     double* part;
     double* part_big;
     double2* hvec;
+    double* err;      // per-column running maximum of the step error estimate, or null
+    double2* errc;    // [ncol][kErrNodes][m] coefficients at the estimate's quadrature nodes (with err)
 };
 
 // Byte layout of a SilWork carved from one buffer (each piece 256-aligned).
 struct SilLayout {
-    size_t x, scal, part, part_big, hvec, total;
+    size_t x, scal, part, part_big, hvec, err, errc, total;
 };
 static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 static SilLayout sil_layout(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth) {
@@ -880,7 +952,9 @@ static SilLayout sil_layout(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m
     l.part = l.scal + align256(sizeof(double) * kScalStride * ncol);
     l.part_big = l.part + align256(sizeof(double) * (size_t)nper_max * ncol);
     l.hvec = l.part_big + (reorth > 0 ? align256(sizeof(double) * (size_t)NB * ncol * (m + 1) * 2) : 0);
-    l.total = l.hvec + (reorth > 0 ? align256(sizeof(double2) * (size_t)ncol * (m + 1)) : 0);
+    l.err = l.hvec + (reorth > 0 ? align256(sizeof(double2) * (size_t)ncol * (m + 1)) : 0);
+    l.errc = l.err + align256(sizeof(double) * (size_t)ncol);
+    l.total = l.errc + align256(sizeof(double2) * (size_t)ncol * kErrNodes * m);
     return l;
 }
 
@@ -919,14 +993,14 @@ static void sil_build_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, doubl
         a.part = part;
         hv_lanczos(ctx, model, sec, ncol, a);
         launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
-        if (k == m - 1) break;
+        if (k == m - 1 && !w.err) break;   // b_m only for the error estimate
         {
             Prof pr(ctx, "lanczos_update", 48.0 * D * ncol);
             hipLaunchKernelGGL(k_update, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, sl, k,
                                scal + kOffA + k, scal + kOffS + k, kScalStride, D, part);
             check_launch("k_update");
         }
-        if (o.reorth > 0)
+        if (o.reorth > 0 && k < m - 1)
             reorthogonalise(ctx, sl, k + 1, k + 1, ncol, D, o.reorth, scal, nullptr, part, part_big, hvec);
         launch_fin(ctx, FIN_B, k, part, NB, scal, ncol, o.breakdown_tol);
     }
@@ -949,6 +1023,8 @@ static SilWork sil_work_ws(kgf_ctx* ctx, const kgf_sector* sec, int ncol, const 
             workspace(ctx, "sil_partbig", sizeof(double) * (size_t)NB * ncol * (o.m + 1) * 2));
         w.hvec = static_cast<double2*>(workspace(ctx, "sil_hvec", sizeof(double2) * (size_t)ncol * (o.m + 1)));
     }
+    w.err = nullptr;
+    w.errc = nullptr;
     return w;
 }
 
@@ -1033,6 +1109,23 @@ static void sil_step_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double
         }
         launch_coefs(ctx, w.scal, m, q, o.shift, coef + (int64_t)r0 * (kScalStride / 2), kScalStride / 2);
     }
+    if (w.err) {
+        const GlRule& g = gl_rule();
+        const int nreq = ncol * kErrNodes;
+        for (int r0 = 0; r0 < nreq; r0 += kMaxReq) {
+            CoefReq q;
+            q.n = std::min(kMaxReq, nreq - r0);
+            for (int r = 0; r < q.n; ++r) {
+                q.col[r] = (r0 + r) / kErrNodes;
+                q.t[r] = o.dt * g.x[(r0 + r) % kErrNodes];
+                q.dir[r] = o.direction;
+            }
+            launch_coefs(ctx, w.scal, m, q, o.shift, w.errc + (int64_t)r0 * m, m);
+        }
+        hipLaunchKernelGGL(k_err_est, dim3((ncol + 63) / 64), dim3(64), 0, ctx->stream, w.scal, m, ncol, w.errc, g,
+                           o.dt, w.err);
+        check_launch("k_err_est");
+    }
     Slots sl{psi, ld, w.X, (int64_t)ncol * D, D};
     const int NB = red_blocks(D);
     Prof pr(ctx, "combine", 16.0 * (m + 1) * D * ncol);
@@ -1042,12 +1135,21 @@ static void sil_step_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double
 }
 
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
-                   int nsteps, const SilOpts& o) {
+                   int nsteps, const SilOpts& o, double* err) {
+    if (err && nsteps > 0) {
+        hipLaunchKernelGGL(k_fill_zero, dim3((ncol + 255) / 256), dim3(256), 0, ctx->stream, err, ncol);
+        check_launch("k_fill_zero");
+    }
     for (int step = 0; step < nsteps; ++step) {
         KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
         hv_prepare(ctx, model, sec);
         sil_reserve(ctx, sec, ncol, o.m, o.reorth);
-        sil_step_w(ctx, model, sec, psi, ncol, ld, o, sil_work_ws(ctx, sec, ncol, o));
+        SilWork w = sil_work_ws(ctx, sec, ncol, o);
+        w.err = err;
+        if (err)
+            w.errc = static_cast<double2*>(
+                workspace(ctx, "sil_errc", sizeof(double2) * (size_t)ncol * kErrNodes * o.m));
+        sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
     }
 }
 
@@ -1059,8 +1161,8 @@ size_t sil_scratch_bytes(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, i
 // SIL steps with every device buffer carved from `scratch` (at least
 // sil_scratch_bytes); no allocation.  The hopping tables of the model for the
 // sector's particle numbers must already exist.
-void sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
-                      int nsteps, const SilOpts& o, void* scratch) {
+double* sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                         int nsteps, const SilOpts& o, void* scratch, bool want_err) {
     const SilLayout l = sil_layout(ctx, sec, ncol, o.m, o.reorth);
     char* base = static_cast<char*>(scratch);
     SilWork w;
@@ -1069,7 +1171,57 @@ void sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, dou
     w.part = reinterpret_cast<double*>(base + l.part);
     w.part_big = o.reorth > 0 ? reinterpret_cast<double*>(base + l.part_big) : nullptr;
     w.hvec = o.reorth > 0 ? reinterpret_cast<double2*>(base + l.hvec) : nullptr;
+    w.err = want_err ? reinterpret_cast<double*>(base + l.err) : nullptr;
+    w.errc = want_err ? reinterpret_cast<double2*>(base + l.errc) : nullptr;
+    if (w.err) {
+        hipLaunchKernelGGL(k_fill_zero, dim3((ncol + 255) / 256), dim3(256), 0, ctx->stream, w.err, ncol);
+        check_launch("k_fill_zero");
+    }
     for (int step = 0; step < nsteps; ++step) sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
+    return w.err;
+}
+
+// Uniqueness of a ground state: a second recursion from a SplitMix64 start
+// vector (entry i: output i of the generator seeded with `seed`, mapped to
+// [-1, 1)), and |<psi0|psi_b>|^2 of the two normalised Ritz vectors.
+__global__ void k_splitmix_fill(double2* __restrict__ v, int64_t D, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double u = (double)(z >> 11) * 0x1.0p-53;
+        v[i] = make_double2(2.0 * u - 1.0, 0.0);
+    }
+}
+
+double gs_fidelity2(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,
+                    const kgf_gs_opts* o) {
+    const int64_t D = sec->dim();
+    double2* v = static_cast<double2*>(workspace(ctx, "gs_chk_v", sizeof(double2) * (size_t)D));
+    const int64_t blocks = std::min<int64_t>((D + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_splitmix_fill, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0,
+                       ctx->stream, v, D, o->unique_seed);
+    check_launch("k_splitmix_fill");
+    ground_state(ctx, model, sec, v, v, o->tol, o->max_iter, o->check_every, o->reorth);   // psi_b over its start
+    double2* dd = static_cast<double2*>(workspace(ctx, "gs_chk_dot", sizeof(double2)));
+    block_dots(ctx, psi0, D, 1, v, D, 1, D, dd);
+    double2 h;
+    KGF_HIP(hipMemcpyAsync(&h, dd, sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    ctx->ws.erase("gs_chk_v");
+    ctx->ws.erase("gs_V");
+    return h.x * h.x + h.y * h.y;
+}
+
+void require_unique_ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,
+                                 const kgf_gs_opts* o, const char* who) {
+    if (!o || !o->unique_check) return;
+    const double f2 = gs_fidelity2(ctx, model, sec, psi0, o);
+    const double tol = o->unique_tol > 0.0 ? o->unique_tol : 1e-10;
+    if (!(f2 >= 1.0 - tol))
+        fail(KGF_EDEGENERATE, std::string(who) + ": the ground state of H_ini is not unique (two Lanczos starts give "
+                                                 "|<0_a|0_b>|^2 = " + std::to_string(f2) + ")");
 }
 
 

@@ -1,7 +1,7 @@
 """Host logic of the driven entry points (no GPU): the binding samples the
-drive at the two Gauss nodes of every commutator-free step and mirrors the
-last stage's parameters on the host; both must agree with the oracle's
-independent definition of the stages."""
+drive at the two Gauss nodes of every commutator-free step; the stage
+parameters built from that table must agree with the oracle's independent
+definition of the stages."""
 from types import SimpleNamespace
 
 import numpy as np
@@ -11,7 +11,7 @@ from oracle import driven
 from oracle.gradients import theta_of
 
 
-def test_drive_table_and_last_stage_match_the_oracle_stages():
+def test_drive_table_matches_the_oracle_stages():
     from paper_1109_1205_amd._lib import Context
     H0 = wl.ring(6, 1.0, 2.0)
     nb, L = len(H0.bonds), H0.L
@@ -29,10 +29,6 @@ def test_drive_table_and_last_stage_match_the_oracle_stages():
         b1, b2 = driven.stage_thetas(thetas, f, t0 + n * h, h)
         np.testing.assert_allclose((a2 * fv[n, 0] + a1 * fv[n, 1]) @ th, b1, rtol=1e-14, atol=1e-15)
         np.testing.assert_allclose((a1 * fv[n, 0] + a2 * fv[n, 1]) @ th, b2, rtol=1e-14, atol=1e-15)
-    Context._mirror_last_stage(work, th, fv)
-    last = np.concatenate([work._t, work._eu, work._ed, work._U])
-    np.testing.assert_allclose(last, driven.stage_thetas(thetas, f, t0 + (nsteps - 1) * h, h)[1], rtol=1e-14,
-                               atol=1e-15)
     # no steps: a zero placeholder row, never read
     _, fz = Context._drive_table(me, work, thetas, f, 0, h, t0)
     assert fz.shape == (1, 2, 2) and not fz.any()
