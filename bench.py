@@ -66,7 +66,7 @@ def parse():
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
     p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4", "necpt",
-                                           "two_particle"],
+                                           "two_particle", "graphs"],
                    default="ladder14",
                    help="ladder14: the four-step benchmark (default); batch64: the 64-instance uneven Anderson "
                         "batch, batched vs per instance, plus adjoint timings; ladder16: the 2x8 ladder on a "
@@ -573,6 +573,54 @@ def two_particle(a):
                           np.abs(chi[k, k] + np.swapaxes(chi[k, k], -4, -3)).max() for k in range(nt)))}), flush=True)
 
 
+def graphs(a):
+    """Launch-bound small sectors with and without captured SIL steps
+    (KGF_OPT_GRAPHS): the equilibrium G of the half-filled 8-site ring
+    (D = 4,900; all 8 sites, 200 SIL steps of dt = 0.05, Krylov dim 15) and
+    the four-step G of a 10-site Anderson star; both runs give bitwise the
+    same G."""
+    import numpy as np
+    import torch
+    import paper_1109_1205_amd as kgf
+    import workloads as wl
+    ctx = kgf.Context(0)
+    q = wl.ring8()
+    m = ctx.model(q.H)
+    s = ctx.sector(8, 4, 4)
+    v0 = torch.from_numpy(wl.start_vector(s.dim, 7)).to("cuda:0")
+    E0, psi0, _ = ctx.ground_state(m, s, v0, tol=1e-12, max_iter=400)
+    q10 = wl.siam10()
+    s10 = ctx.sector(10, 5, 5)
+    v10 = torch.from_numpy(wl.start_vector(s10.dim, 7)).to("cuda:0")
+    mi10, mf10 = ctx.model(q10.H_ini), ctx.model(q10.H)
+    res = {}
+    for on in (0, 1, 0, 1):
+        ctx.set_option(8, on)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = ctx.greens_eq(m, s, psi0, E0, q.orbitals, q.nt, q.steps_per_grid, q.dt_grid, krylov_dim=q.krylov_dim)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        G4 = ctx.greens_neq(mi10, mf10, s10, v10, q10.orbitals, nt=21, steps_per_grid=q10.steps_per_grid,
+                            dt=q10.dt, krylov_dim=q10.krylov_dim)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[on] = {"ring8_greens_eq_s": round(t1 - t0, 4), "siam10_four_step_nt21_s": round(t2 - t1, 4),
+                   "G": G, "G4": G4["G_lesser"]}
+        log(f"graphs={on}: ring8 {t1 - t0:.3f} s, siam10 {t2 - t1:.3f} s")
+    same = all(np.array_equal(res[0]["G"][i], res[1]["G"][i]) for i in range(2)) and np.array_equal(
+        res[0]["G4"], res[1]["G4"])
+    vsteps = 2 * len(q.orbitals) * (q.nt - 1) * q.steps_per_grid
+    print(json.dumps({"metric": "captured SIL steps vs eager launches, small sectors",
+                      "ring8_eq_vector_steps": vsteps,
+                      "eager": {k: v for k, v in res[0].items() if k.endswith("_s")},
+                      "graphs": {k: v for k, v in res[1].items() if k.endswith("_s")},
+                      "ring8_speedup": round(res[0]["ring8_greens_eq_s"] / res[1]["ring8_greens_eq_s"], 2),
+                      "siam10_speedup": round(res[0]["siam10_four_step_nt21_s"] / res[1]["siam10_four_step_nt21_s"],
+                                              2),
+                      "bitwise_equal": bool(same)}), flush=True)
+
+
 def fig1(a):
     """Sec. 3 on the GPU: local spectral density A(w) = -Im G_00(w) / pi of the
     half-filled L=10 Hubbard ring at U=8 (T=1), eta = 0.01, t_max = 1000, fine
@@ -705,6 +753,9 @@ def main():
         return
     if a.workload == "two_particle":
         two_particle(a)
+        return
+    if a.workload == "graphs":
+        graphs(a)
         return
     if a.whole:
         whole_runs(a)

@@ -573,10 +573,17 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      HV_PASSES / HV_STRIP, when set, take precedence.
  *   KGF_OPT_CG_MAX_ITER: iteration limit of the projected CG of the four-step
  *                      adjoints (0 = 20000).
+ *   KGF_OPT_GRAPHS:    1 (default) = a batched SIL step that recurs with the same
+ *                      model parameters, sector, state buffer, batch width and
+ *                      options (the steps of one kgf_propagate call, the intervals
+ *                      of a four-step sweep) is captured once in a hipGraph and
+ *                      replayed (the same kernels and arguments: bitwise the eager
+ *                      results); not while kgf_profile_begin is active.  0 = eager.
+ *                      Changing any option drops the captured steps.
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
 enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5,
-       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7 };
+       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7, KGF_OPT_GRAPHS = 8 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -76,6 +77,19 @@ void* host_scratch(kgf_ctx* ctx, size_t bytes) {
 }
 
 void sync(kgf_ctx* ctx) { KGF_HIP(hipStreamSynchronize(ctx->stream)); }
+
+uint64_t next_version() {
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
+
+void drop_graphs(kgf_ctx* ctx) {
+    if (ctx->sil_graphs.empty()) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& g : ctx->sil_graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    ctx->sil_graphs.clear();
+}
 
 void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
@@ -219,6 +233,8 @@ void kgf_destroy(kgf_ctx* ctx) {
     }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
+    drop_graphs(ctx);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
 }
 
@@ -260,6 +276,7 @@ int kgf_model_create(kgf_ctx* ctx, const kgf_model_desc* d, kgf_model** out) {
                     KGF_EINVAL, "kgf_model_create: non-finite parameter");
         KGF_HIP(hipSetDevice(ctx->device));
         upload_params(m.get());
+        m->version = next_version();
         *out = m.release();
     });
 }
@@ -555,6 +572,7 @@ int kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user) {
 int kgf_set_option(kgf_ctx* ctx, int option, int value) {
     return guarded([&] {
         KGF_REQUIRE(ctx, KGF_EINVAL, "kgf_set_option: ctx is NULL");
+        drop_graphs(ctx);   // captured steps follow the kernel choices in force when captured
         if (option == KGF_OPT_HV_PASSES) {
             KGF_REQUIRE(value >= 0 && value <= 4, KGF_EINVAL, "kgf_set_option: HV_PASSES must be 0..4");
             ctx->hv_passes = value;
@@ -577,6 +595,9 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_CG_MAX_ITER) {
             KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: CG_MAX_ITER must be >= 0");
             ctx->cg_max_iter = value;
+        } else if (option == KGF_OPT_GRAPHS) {
+            KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: GRAPHS must be 0 or 1");
+            ctx->use_graphs = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

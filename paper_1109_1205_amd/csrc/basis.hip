@@ -181,6 +181,7 @@ void model_set_params(kgf_model* m, const double* t, const double* eps_up, const
     m->U.assign(U, U + m->L);
     upload_params(m);
     refresh_onsite(m);
+    m->version = next_version();
 }
 
 // Recompute the on-site energies e_up, e_dn of every hopping table already

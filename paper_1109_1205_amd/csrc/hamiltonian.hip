@@ -49,6 +49,7 @@ bool same_topology(const kgf_model* a, const kgf_model* b) {
 }
 
 void model_set_init(kgf_ctx* ctx, ModelSet& S) {
+    S.version = next_version();
     const int n = (int)S.models.size();
     KGF_REQUIRE(n >= 1, KGF_EINVAL, "model set: no models");
     kgf_model* m0 = S.models[0];

@@ -97,6 +97,16 @@ struct kgf_ctx {
     int adj_every = 0;                       // 0: adjoint chains stored whole when they fit
     int hv_tune = 0;                         // 1: time the H.v variants of each sector once
     int cg_max_iter = 0;                     // 0: 20000 (projected CG of the adjoints)
+    // captured SIL steps (hipGraph), replayed when the same step recurs
+    int use_graphs = 1;
+    struct SilGraph {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec = nullptr;
+        uint64_t last_use = 0;
+    };
+    std::vector<SilGraph> sil_graphs;
+    uint64_t graph_clock = 0;
+    hipStream_t capture_stream = nullptr;
     std::map<std::array<int, 4>, std::pair<int, int>> hv_tuned;   // (L, N_up, N_dn, mode) -> (passes, strip)
     // progress callback
     kgf_progress_fn progress = nullptr;
@@ -108,6 +118,7 @@ struct kgf_ctx {
 
 struct kgf_model {
     kgf_ctx* ctx = nullptr;
+    uint64_t version = 0;  // unique per creation and per parameter change (keys of captured steps)
     int L = 0;
     int nb = 0;
     std::vector<int32_t> bi, bj;
@@ -148,6 +159,11 @@ struct Prof {
     ~Prof();
 };
 
+// unique version stamps of models and model sets
+uint64_t next_version();
+// forget every captured SIL step of the context (waits for the stream)
+void drop_graphs(kgf_ctx* ctx);
+
 // ---- basis (basis.hip) ----------------------------------------------------
 void build_binomials(kgf_ctx* ctx);
 void build_masks(kgf_ctx* ctx, int L, int n, uint32_t* masks, int64_t D);
@@ -181,6 +197,7 @@ void driven_stage(kgf_model* work, const DriveTable& drv, int n, int stage);
 // of a launch uses member c mod n.  The hopping tables (targets, bonds,
 // signs) depend on the topology only and are shared.
 struct ModelSet {
+    uint64_t version = 0;  // unique per model_set_init
     std::vector<kgf_model*> models;
     bool U_uniform = true;
     DevBuf t;      // double [n][nb]

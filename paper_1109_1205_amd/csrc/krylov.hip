@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstring>
 
 #include "kgf_internal.h"
 
@@ -1134,6 +1135,101 @@ static void sil_step_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double
     check_launch("k_combine");
 }
 
+// Identity of a batched SIL step for graph replay: everything its launches
+// take as arguments (model parameters by version, sector, state buffer,
+// batch, options, work buffers).
+struct SilStepKey {
+    uint64_t model_version;
+    int L, n_up, n_dn, ncol;
+    const double2* psi;
+    int64_t ld;
+    int m, reorth, direction;
+    double dt, shift, breakdown_tol;
+    const void* bufs[5];
+};
+
+static std::vector<unsigned char> step_key(HModel model, const kgf_sector* sec, const double2* psi, int ncol,
+                                           int64_t ld, const SilOpts& o, const SilWork& w) {
+    SilStepKey k;
+    std::memset(&k, 0, sizeof(k));
+    k.model_version = model.set ? model.set->version : model.m->version;
+    k.L = sec->L;
+    k.n_up = sec->n_up;
+    k.n_dn = sec->n_dn;
+    k.ncol = ncol;
+    k.psi = psi;
+    k.ld = ld;
+    k.m = o.m;
+    k.reorth = o.reorth;
+    k.direction = o.direction;
+    k.dt = o.dt;
+    k.shift = o.shift;
+    k.breakdown_tol = o.breakdown_tol;
+    k.bufs[0] = w.X;
+    k.bufs[1] = w.scal;
+    k.bufs[2] = w.part;
+    k.bufs[3] = w.part_big;
+    k.bufs[4] = w.hvec;
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&k);
+    return std::vector<unsigned char>(b, b + sizeof(k));
+}
+
+constexpr size_t kMaxGraphs = 32;
+
+// One SIL step, eager on the first sighting of its key, captured into a
+// hipGraph (on a private stream, launched on the context's stream) on the
+// second, replayed from then on.  The first eager step also builds any
+// tables the launches read, so nothing is allocated or copied synchronously
+// during a capture.
+static void sil_step_graph(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
+                           const SilOpts& o, const SilWork& w) {
+    std::vector<unsigned char> key = step_key(model, sec, psi, ncol, ld, o, w);
+    auto& G = ctx->sil_graphs;
+    auto it = std::find_if(G.begin(), G.end(), [&](const kgf_ctx::SilGraph& g) { return g.key == key; });
+    if (it == G.end()) {
+        sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
+        if (G.size() >= kMaxGraphs) {
+            auto old = std::min_element(G.begin(), G.end(), [](const kgf_ctx::SilGraph& a, const kgf_ctx::SilGraph& b) {
+                return a.last_use < b.last_use;
+            });
+            if (old->exec) {
+                sync(ctx);
+                (void)hipGraphExecDestroy(old->exec);
+            }
+            G.erase(old);
+        }
+        kgf_ctx::SilGraph g;
+        g.key = std::move(key);
+        g.last_use = ++ctx->graph_clock;
+        G.push_back(std::move(g));
+        return;
+    }
+    it->last_use = ++ctx->graph_clock;
+    if (!it->exec) {
+        if (!ctx->capture_stream) KGF_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        KGF_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipStream_t saved = ctx->stream;
+        ctx->stream = ctx->capture_stream;
+        hipGraph_t graph = nullptr;
+        try {
+            sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
+        } catch (...) {
+            ctx->stream = saved;
+            (void)hipStreamEndCapture(ctx->capture_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        ctx->stream = saved;
+        KGF_HIP(hipStreamEndCapture(ctx->capture_stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        KGF_HIP(e);
+        it->exec = exec;
+    }
+    KGF_HIP(hipGraphLaunch(it->exec, ctx->stream));
+}
+
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
                    int nsteps, const SilOpts& o, double* err) {
     if (err && nsteps > 0) {
@@ -1149,7 +1245,10 @@ void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* p
         if (err)
             w.errc = static_cast<double2*>(
                 workspace(ctx, "sil_errc", sizeof(double2) * (size_t)ncol * kErrNodes * o.m));
-        sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
+        if (ctx->use_graphs && !ctx->prof_on && !err)
+            sil_step_graph(ctx, model, sec, psi, ncol, ld, o, w);
+        else
+            sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
     }
 }
 
