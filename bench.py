@@ -195,12 +195,21 @@ def batch64(a):
     kw = dict(orbitals=q0.orbitals, nt=q0.nt, steps_per_grid=q0.steps_per_grid, dt=q0.dt, krylov_dim=q0.krylov_dim)
     vsteps = len(qs) * ((q0.nt - 1) * q0.steps_per_grid + q0.steps_per_grid * q0.nt * (q0.nt - 1))
     torch.cuda.synchronize()
-    log("batched: 64 instances")
+    log("batched: 64 instances (small-sector groups in lockstep)")
     t0 = time.perf_counter()
     outb = ctx.greens_neq_multi(Hi, Hf, secs, v0, **kw)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    log(f"batched {tb:.1f} s; per instance:")
+    log(f"batched {tb:.1f} s; group by group:")
+    ctx.set_option(ctx.LOCKSTEP, 0)
+    t0 = time.perf_counter()
+    outg = ctx.greens_neq_multi(Hi, Hf, secs, v0, **kw)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    ctx.set_option(ctx.LOCKSTEP, 1)
+    same_g = bool(np.array_equal(outg["G_lesser"], outb["G_lesser"]) and np.array_equal(outg["G_greater"],
+                                                                                          outb["G_greater"]))
+    log(f"group by group {tg:.1f} s (bitwise equal: {same_g}); per instance:")
     t0 = time.perf_counter()
     maxdiff = 0.0
     for i in ([] if a.skip_per_instance else range(len(qs))):
@@ -284,7 +293,9 @@ def batch64(a):
            "config": {"workload": "batch64: 64 Anderson stars, L 8..12 (seeds 4000+i), U 0->4, eps_imp -2, "
                                   "G_imp 50x50, t_k=0.2k, dt=0.05, Krylov dim 15",
                       "vector_steps": vsteps},
-           "batched_s": round(tb, 2), "per_instance_s": (round(tp, 2) if tp else None),
+           "batched_s": round(tb, 2), "group_by_group_s": round(tg, 2),
+           "lockstep_speedup_vs_group_by_group": round(tg / tb, 3), "lockstep_bitwise_equal": same_g,
+           "per_instance_s": (round(tp, 2) if tp else None),
            "speedup": (round(tp / tb, 3) if tp else None),
            "per_instance_value": (round(vsteps / tp, 1) if tp else None),
            "max_rel_diff_batched_vs_per_instance": (maxdiff if tp else None),

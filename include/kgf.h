@@ -444,6 +444,8 @@ void kgf_neq_run_destroy(kgf_neq_run* run);
  * as one batch: every Lanczos / SIL launch of the forward meshes and the
  * backward sweeps serves all members, column c carrying the parameters of
  * member c mod n (different hoppings, on-site energies and U per instance);
+ * with KGF_OPT_LOCKSTEP (default) the groups themselves advance together,
+ * each kernel of a SIL step one launch over every group's columns;
  * ground states are found one instance at a time.  Results equal
  * kgf_greens_neq on each instance up to rounding.
  * Per-instance inputs: H_ini[i], H[i], sectors[i], v0[i] (device, D_i).
@@ -580,10 +582,20 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      replayed (the same kernels and arguments: bitwise the eager
  *                      results); not while kgf_profile_begin is active.  0 = eager.
  *                      Changing any option drops the captured steps.
+ *   KGF_OPT_LOCKSTEP:  1 (default) = kgf_greens_neq_multi advances the groups of
+ *                      instances with small sectors (at most 2^17 states) together:
+ *                      every kernel of a SIL step is one launch over the columns of
+ *                      all of them (sectors of different size, a Hamiltonian per
+ *                      column; the H.v one launch per row block size), the sweeps
+ *                      share one chunk of source times; larger sectors fill the GPU
+ *                      alone and run group by group.  Same results as group by group
+ *                      (per group the same element owners and reduction orders).
+ *                      Used when reorth = 0 and those sectors' H.v is the single
+ *                      pass; 0 = every group alone.
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
 enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5,
-       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7, KGF_OPT_GRAPHS = 8 };
+       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7, KGF_OPT_GRAPHS = 8, KGF_OPT_LOCKSTEP = 9 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

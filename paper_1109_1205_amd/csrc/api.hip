@@ -78,6 +78,26 @@ void* host_scratch(kgf_ctx* ctx, size_t bytes) {
 
 void sync(kgf_ctx* ctx) { KGF_HIP(hipStreamSynchronize(ctx->stream)); }
 
+void* upload_table(kgf_ctx* ctx, const std::string& name, const void* host, size_t n) {
+    auto it = ctx->ws.find(name);
+    if (it == ctx->ws.end() || !it->second || it->second->bytes < n) sync(ctx);   // growing frees the old buffer
+    void* dev = workspace(ctx, name, n);
+    const int i = ctx->stage_next;
+    ctx->stage_next = (i + 1) % kgf_ctx::kStageSlots;
+    if (ctx->stage_ev[i]) KGF_HIP(hipEventSynchronize(ctx->stage_ev[i]));   // the slot's previous copy is done
+    if (ctx->stage_bytes[i] < n) {
+        if (ctx->stage[i]) KGF_HIP(hipHostFree(ctx->stage[i]));
+        ctx->stage[i] = nullptr;
+        KGF_HIP(hipHostMalloc(&ctx->stage[i], n, hipHostMallocDefault));
+        ctx->stage_bytes[i] = n;
+    }
+    std::memcpy(ctx->stage[i], host, n);
+    KGF_HIP(hipMemcpyAsync(dev, ctx->stage[i], n, hipMemcpyHostToDevice, ctx->stream));
+    if (!ctx->stage_ev[i]) KGF_HIP(hipEventCreateWithFlags(&ctx->stage_ev[i], hipEventDisableTiming));
+    KGF_HIP(hipEventRecord(ctx->stage_ev[i], ctx->stream));
+    return dev;
+}
+
 uint64_t next_version() {
     static std::atomic<uint64_t> counter{0};
     return ++counter;
@@ -235,6 +255,10 @@ void kgf_destroy(kgf_ctx* ctx) {
     if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
     drop_graphs(ctx);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    for (int i = 0; i < kgf_ctx::kStageSlots; ++i) {
+        if (ctx->stage_ev[i]) (void)hipEventDestroy(ctx->stage_ev[i]);
+        if (ctx->stage[i]) (void)hipHostFree(ctx->stage[i]);
+    }
     delete ctx;
 }
 
@@ -595,6 +619,9 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_CG_MAX_ITER) {
             KGF_REQUIRE(value >= 0, KGF_EINVAL, "kgf_set_option: CG_MAX_ITER must be >= 0");
             ctx->cg_max_iter = value;
+        } else if (option == KGF_OPT_LOCKSTEP) {
+            KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: LOCKSTEP must be 0 or 1");
+            ctx->lockstep = value;
         } else if (option == KGF_OPT_GRAPHS) {
             KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: GRAPHS must be 0 or 1");
             ctx->use_graphs = value;

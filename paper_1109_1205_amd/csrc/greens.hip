@@ -658,10 +658,337 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
 // column c carries the Hamiltonian of member c mod n (ModelSet), so every
 // launch serves all members.  Ground states are found per instance.
 // Gl_host / Gg_host: [ninst][nt][nt][norb][norb]; E0_host: [ninst].
+// Lockstep form of the same computation: every group's ground states first,
+// then the forward meshes and the backward sweeps of all groups advance
+// together, each SIL step one grouped launch per kernel over the columns of
+// every group (sectors of different size, a Hamiltonian per column).  The
+// sweeps share one chunk of source times sized for all groups.  Per group
+// the kernels, element owners and reduction orders are those of the
+// group-by-group path, so the results are the same.
+struct LockGroup {
+    std::vector<int> mem;                  // instance indices
+    const kgf_sector* sec = nullptr;
+    std::unique_ptr<ModelSet> set;
+    double2* Phi = nullptr;                // [nt][n][D]
+    std::unique_ptr<kgf_sector> tgt;       // target sector of the current branch
+    double2 *raw = nullptr, *S = nullptr, *Lb = nullptr, *tmp = nullptr;
+    std::vector<double2> Gl, Gg;           // host [n][nt][nt][norb][norb]
+};
+
+static bool lockstep_possible(kgf_ctx* ctx, int ninst, kgf_model* const* Hf, const kgf_sector* const* secs,
+                              const SilOpts& o) {
+    if (o.reorth != 0) return false;
+    std::vector<GroupSpec> probe;
+    std::vector<std::unique_ptr<kgf_sector>> keep;
+    for (int i = 0; i < ninst; ++i) {
+        probe.push_back(GroupSpec{HModel(Hf[i]), secs[i], 0, 1});
+        for (int spin = 0; spin < 2; ++spin)
+            for (int d = -1; d <= 1; d += 2) {
+                auto t = shifted(ctx, secs[i], spin, d);
+                if (t && t->dim() > 0) {
+                    probe.push_back(GroupSpec{HModel(Hf[i]), t.get(), 0, 1});
+                    keep.push_back(std::move(t));
+                }
+            }
+    }
+    return hv_groups_supported(ctx, probe);
+}
+
+static void greens_neq_multi_lockstep(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* const* Hf,
+                                      const kgf_sector* const* secs, const double2* const* v0,
+                                      const kgf_gs_opts* gso, const int32_t* orbs, int norb, int nt, int spg,
+                                      const SilOpts& o, int batch, double2* Gl_host, double2* Gg_host,
+                                      double* E0_host) {
+    std::vector<int> done(ninst, 0);
+    std::vector<LockGroup> G;
+    for (int i0 = 0; i0 < ninst; ++i0) {
+        if (done[i0]) continue;
+        LockGroup g;
+        for (int i = i0; i < ninst; ++i)
+            if (!done[i] && secs[i]->L == secs[i0]->L && secs[i]->n_up == secs[i0]->n_up &&
+                secs[i]->n_dn == secs[i0]->n_dn && same_topology(Hf[i], Hf[i0])) {
+                g.mem.push_back(i);
+                done[i] = 1;
+            }
+        g.sec = secs[i0];
+        g.set.reset(new ModelSet());
+        for (int i : g.mem) g.set->models.push_back(Hf[i]);
+        model_set_init(ctx, *g.set);
+        G.push_back(std::move(g));
+    }
+    const size_t gsz = (size_t)nt * nt * norb * norb;
+    // (i) ground states, one instance at a time, into the first mesh slot
+    size_t phi_bytes = 0;
+    for (auto& g : G) phi_bytes += sizeof(double2) * (size_t)nt * g.mem.size() * g.sec->dim();
+    ensure_device_fits(phi_bytes, "batched four-step forward meshes");
+    for (size_t gi = 0; gi < G.size(); ++gi) {
+        LockGroup& g = G[gi];
+        const int n = (int)g.mem.size();
+        const int64_t D = g.sec->dim();
+        g.Phi = static_cast<double2*>(workspace(ctx, "lneq_phi" + std::to_string(gi),
+                                                sizeof(double2) * (size_t)nt * n * D));
+        for (int k = 0; k < n; ++k) {
+            GsResult gs = ground_state(ctx, Hi[g.mem[k]], g.sec, v0[g.mem[k]], g.Phi + (size_t)k * D, gso->tol,
+                                       gso->max_iter, gso->check_every, gso->reorth);
+            KGF_REQUIRE(gs.converged, KGF_ENOCONV, "batched four-step: a ground state of H_ini did not converge");
+            require_unique_ground_state(ctx, Hi[g.mem[k]], g.sec, g.Phi + (size_t)k * D, gso, "batched four-step");
+            E0_host[g.mem[k]] = gs.E0;
+        }
+        progress(ctx, "ground_states", gi + 1, G.size());
+        g.Gl.assign((size_t)n * gsz, make_double2(0, 0));
+        g.Gg.assign((size_t)n * gsz, make_double2(0, 0));
+    }
+    release(ctx, "gs_V");
+    release(ctx, "gs_partbig");
+    // (ii) forward meshes of all groups in lockstep
+    SilOpts fo = o;
+    fo.direction = -1;
+    std::vector<GroupSpec> specs;
+    std::vector<double2*> ptrs;
+    std::vector<int64_t> lds;
+    {
+        int col = 0;
+        for (auto& g : G) {
+            specs.push_back(GroupSpec{HModel(g.set.get()), g.sec, col, (int)g.mem.size()});
+            col += (int)g.mem.size();
+        }
+        sil_groups_reserve(ctx, specs, o.m);
+    }
+    for (int t = 1; t < nt; ++t) {
+        specs.clear();
+        ptrs.clear();
+        lds.clear();
+        int col = 0;
+        for (auto& g : G) {
+            const int n = (int)g.mem.size();
+            const int64_t D = g.sec->dim();
+            double2* cur = g.Phi + (size_t)t * n * D;
+            KGF_HIP(hipMemcpyAsync(cur, cur - (size_t)n * D, sizeof(double2) * (size_t)n * D, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+            specs.push_back(GroupSpec{HModel(g.set.get()), g.sec, col, n});
+            ptrs.push_back(cur);
+            lds.push_back(D);
+            col += n;
+        }
+        for (int r = 0; r < spg; ++r) sil_step_groups(ctx, specs, ptrs, lds, fo);
+        progress(ctx, "forward", t, nt - 1);
+    }
+    // (iii)+(iv) backward sweeps of all groups in lockstep
+    SilOpts so = o;
+    so.direction = +1;
+    for (int spin = 0; spin < 2; ++spin) {
+        std::vector<int> loc;
+        for (int a = 0; a < norb; ++a)
+            if ((orbs[a] & 1) == spin) loc.push_back(a);
+        const int na = (int)loc.size();
+        if (!na) continue;
+        DevBuf gidx;
+        upload_ints(ctx, gidx, loc);
+        for (int dagger = 0; dagger < 2; ++dagger) {
+            const size_t rsz = (size_t)nt * nt * na * na;
+            size_t per_j = 0;    // device bytes per source time (all groups' columns with their Krylov slots)
+            for (size_t gi = 0; gi < G.size(); ++gi) {
+                LockGroup& g = G[gi];
+                g.tgt = shifted(ctx, g.sec, spin, dagger ? +1 : -1);
+                if (!g.tgt || g.tgt->dim() == 0) {
+                    g.tgt.reset();
+                    continue;
+                }
+                per_j += sizeof(double2) * (size_t)(o.m + 1) * na * g.mem.size() * g.tgt->dim();
+                g.raw = static_cast<double2*>(workspace(ctx, "lneq_raw" + std::to_string(gi),
+                                                        sizeof(double2) * rsz * g.mem.size()));
+                KGF_HIP(hipMemsetAsync(g.raw, 0, sizeof(double2) * rsz * g.mem.size(), ctx->stream));
+            }
+            if (per_j == 0) continue;
+            int jchunk = nt;
+            if (batch > 0) {
+                size_t cols_per_j = 0;
+                for (auto& g : G)
+                    if (g.tgt) cols_per_j += (size_t)na * g.mem.size();
+                jchunk = std::max<int>(1, (int)(batch / std::max<size_t>(cols_per_j, 1)));
+            } else {
+                size_t free_b = 0, total_b = 0;
+                KGF_HIP(hipMemGetInfo(&free_b, &total_b));
+                jchunk = (int)std::max<size_t>(1, (size_t)(0.8 * (double)free_b) / per_j);
+            }
+            jchunk = std::min(jchunk, nt);
+            release(ctx, "sg_X");
+            for (size_t gi = 0; gi < G.size(); ++gi) {
+                LockGroup& g = G[gi];
+                if (!g.tgt) continue;
+                const size_t n = g.mem.size();
+                const int64_t Dt = g.tgt->dim();
+                const size_t maxcols = (size_t)jchunk * na * n;
+                ensure_device_fits(sizeof(double2) * maxcols * Dt, "batched four-step sweep block");
+                g.S = static_cast<double2*>(workspace(ctx, "lneq_cols" + std::to_string(gi),
+                                                      sizeof(double2) * maxcols * Dt));
+                g.Lb = static_cast<double2*>(workspace(ctx, "lneq_left" + std::to_string(gi),
+                                                       sizeof(double2) * (size_t)na * n * Dt));
+                g.tmp = static_cast<double2*>(workspace(ctx, "lneq_tmp" + std::to_string(gi),
+                                                        sizeof(double2) * (size_t)na * jchunk * na));
+            }
+            {   // the widest step of the sweep: a full chunk of every group
+                specs.clear();
+                int col = 0;
+                for (auto& g : G) {
+                    if (!g.tgt) continue;
+                    const int nc = jchunk * na * (int)g.mem.size();
+                    specs.push_back(GroupSpec{HModel(g.set.get()), g.tgt.get(), col, nc});
+                    col += nc;
+                }
+                sil_groups_reserve(ctx, specs, o.m);
+            }
+            const int64_t ss = (int64_t)na * na * nt, sb = (int64_t)na * nt, sa = nt, sj = 1;
+            for (int jhi = nt - 1; jhi >= 0; jhi -= jchunk) {
+                const int jlo = std::max(0, jhi - jchunk + 1);
+                int ncur = 0;   // columns per member; column (r, member) at S + (r * n + member) * Dt
+                for (int s2 = jhi; s2 >= 0; --s2) {
+                    const bool inject = s2 >= jlo;
+                    for (auto& g : G) {
+                        if (!g.tgt) continue;
+                        const int n = (int)g.mem.size();
+                        const int64_t D = g.sec->dim(), Dt = g.tgt->dim();
+                        const double2* phi = g.Phi + (size_t)s2 * n * D;
+                        if (inject)
+                            for (int q = 0; q < na; ++q)
+                                apply_c(ctx, g.sec, g.tgt.get(), orbs[loc[q]], dagger, phi,
+                                        g.S + (size_t)(ncur + q) * n * Dt, n, D, Dt);
+                        for (int q = 0; q < na; ++q)
+                            apply_c(ctx, g.sec, g.tgt.get(), orbs[loc[q]], dagger, phi, g.Lb + (size_t)q * n * Dt, n,
+                                    D, Dt);
+                        const int nc = ncur + (inject ? na : 0);
+                        for (int k = 0; k < n; ++k) {
+                            block_dots(ctx, g.Lb + (size_t)k * Dt, (int64_t)n * Dt, na, g.S + (size_t)k * Dt,
+                                       (int64_t)n * Dt, nc, Dt, g.tmp, nc);
+                            place(ctx, g.tmp, na, na, nc, jhi, g.raw + (size_t)k * rsz, s2 * ss, sb, sa, sj);
+                        }
+                    }
+                    if (inject) ncur += na;
+                    if (s2 > 0) {
+                        specs.clear();
+                        ptrs.clear();
+                        lds.clear();
+                        int col = 0;
+                        for (auto& g : G) {
+                            if (!g.tgt) continue;
+                            const int nc = ncur * (int)g.mem.size();
+                            specs.push_back(GroupSpec{HModel(g.set.get()), g.tgt.get(), col, nc});
+                            ptrs.push_back(g.S);
+                            lds.push_back(g.tgt->dim());
+                            col += nc;
+                        }
+                        for (int r = 0; r < spg; ++r) sil_step_groups(ctx, specs, ptrs, lds, so);
+                    }
+                    progress(ctx, dagger ? "batch_sweep_greater" : "batch_sweep_lesser", jhi - s2 + 1, jhi + 1);
+                }
+            }
+            for (size_t gi = 0; gi < G.size(); ++gi) {
+                LockGroup& g = G[gi];
+                if (!g.tgt) continue;
+                const int n = (int)g.mem.size();
+                double2* Gdev = static_cast<double2*>(workspace(ctx, "mneq_G", sizeof(double2) * gsz * n));
+                KGF_HIP(hipMemsetAsync(Gdev, 0, sizeof(double2) * gsz * n, ctx->stream));
+                const int64_t total = (int64_t)nt * nt * na * na;
+                for (int k = 0; k < n; ++k) {
+                    hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)),
+                                       dim3(kThreads), 0, ctx->stream, g.raw + (size_t)k * rsz, ss, sb, sa, sj, nt, na,
+                                       gidx.as<int>(), norb, dagger, 1, Gdev + (size_t)k * gsz);
+                    check_launch("k_store_neq");
+                }
+                std::vector<double2> h((size_t)n * gsz);
+                KGF_HIP(hipMemcpyAsync(h.data(), Gdev, sizeof(double2) * h.size(), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+                sync(ctx);
+                std::vector<double2>& dst = dagger ? g.Gg : g.Gl;
+                for (size_t e = 0; e < h.size(); ++e)
+                    if (h[e].x != 0.0 || h[e].y != 0.0) dst[e] = h[e];
+            }
+            for (size_t gi = 0; gi < G.size(); ++gi)
+                for (const char* nm : {"lneq_cols", "lneq_left", "lneq_tmp"})
+                    release(ctx, (std::string(nm) + std::to_string(gi)).c_str());
+            release(ctx, "sg_X");
+        }
+    }
+    for (auto& g : G) {
+        const int n = (int)g.mem.size();
+        for (int k = 0; k < n; ++k) {
+            if (Gl_host) std::copy(g.Gl.begin() + (size_t)k * gsz, g.Gl.begin() + (size_t)(k + 1) * gsz,
+                                   Gl_host + (size_t)g.mem[k] * gsz);
+            if (Gg_host) std::copy(g.Gg.begin() + (size_t)k * gsz, g.Gg.begin() + (size_t)(k + 1) * gsz,
+                                   Gg_host + (size_t)g.mem[k] * gsz);
+        }
+    }
+    for (size_t gi = 0; gi < G.size(); ++gi)
+        for (const char* nm : {"lneq_phi", "lneq_raw"}) release(ctx, (std::string(nm) + std::to_string(gi)).c_str());
+    for (const char* nm : {"mneq_G", "sg_part", "sg_scal"}) release(ctx, nm);
+}
+
+static void greens_neq_multi_groups(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* const* Hf,
+                                    const kgf_sector* const* secs, const double2* const* v0, const kgf_gs_opts* gso,
+                                    const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch,
+                                    double2* Gl_host, double2* Gg_host, double* E0_host);
+
+// Instances whose sector has at most this many states run their groups in
+// lockstep (their per-group launches are too small to fill the GPU); larger
+// ones run group by group with the single-group kernels, whose arguments the
+// hardware preloads (the grouped kernels read a descriptor per block, about
+// 5% slower per launch when the launch alone fills the GPU).
+constexpr int64_t kLockstepMaxDim = int64_t(1) << 17;
+
 void greens_neq_multi(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* const* Hf,
                       const kgf_sector* const* secs, const double2* const* v0, const kgf_gs_opts* gso,
                       const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch, double2* Gl_host,
                       double2* Gg_host, double* E0_host) {
+    std::vector<int> small, large;
+    for (int i = 0; i < ninst; ++i) (secs[i]->dim() <= kLockstepMaxDim ? small : large).push_back(i);
+    std::vector<kgf_model*> small_h;
+    std::vector<const kgf_sector*> small_s;
+    for (int i : small) {
+        small_h.push_back(Hf[i]);
+        small_s.push_back(secs[i]);
+    }
+    if (!ctx->lockstep || small.size() < 2 ||
+        !lockstep_possible(ctx, (int)small.size(), small_h.data(), small_s.data(), o)) {
+        greens_neq_multi_groups(ctx, ninst, Hi, Hf, secs, v0, gso, orbs, norb, nt, spg, o, batch, Gl_host, Gg_host,
+                                E0_host);
+        return;
+    }
+    const size_t gsz = (size_t)nt * nt * norb * norb;
+    for (int part = 0; part < 2; ++part) {
+        const std::vector<int>& idx = part == 0 ? small : large;
+        if (idx.empty()) continue;
+        const int n = (int)idx.size();
+        std::vector<kgf_model*> hi(n), hf(n);
+        std::vector<const kgf_sector*> sc(n);
+        std::vector<const double2*> v(n);
+        std::vector<double2> gl(Gl_host ? (size_t)n * gsz : 0), gg(Gg_host ? (size_t)n * gsz : 0);
+        std::vector<double> e0(n);
+        for (int k = 0; k < n; ++k) {
+            hi[k] = Hi[idx[k]];
+            hf[k] = Hf[idx[k]];
+            sc[k] = secs[idx[k]];
+            v[k] = v0[idx[k]];
+        }
+        if (part == 0)
+            greens_neq_multi_lockstep(ctx, n, hi.data(), hf.data(), sc.data(), v.data(), gso, orbs, norb, nt, spg, o,
+                                      batch, Gl_host ? gl.data() : nullptr, Gg_host ? gg.data() : nullptr, e0.data());
+        else
+            greens_neq_multi_groups(ctx, n, hi.data(), hf.data(), sc.data(), v.data(), gso, orbs, norb, nt, spg, o,
+                                    batch, Gl_host ? gl.data() : nullptr, Gg_host ? gg.data() : nullptr, e0.data());
+        for (int k = 0; k < n; ++k) {
+            E0_host[idx[k]] = e0[k];
+            if (Gl_host) std::copy(gl.begin() + (size_t)k * gsz, gl.begin() + (size_t)(k + 1) * gsz,
+                                   Gl_host + (size_t)idx[k] * gsz);
+            if (Gg_host) std::copy(gg.begin() + (size_t)k * gsz, gg.begin() + (size_t)(k + 1) * gsz,
+                                   Gg_host + (size_t)idx[k] * gsz);
+        }
+    }
+}
+
+static void greens_neq_multi_groups(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* const* Hf,
+                                    const kgf_sector* const* secs, const double2* const* v0, const kgf_gs_opts* gso,
+                                    const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch,
+                                    double2* Gl_host, double2* Gg_host, double* E0_host) {
     std::vector<int> done(ninst, 0);
     const size_t gsz = (size_t)nt * nt * norb * norb;
     for (int i0 = 0; i0 < ninst; ++i0) {

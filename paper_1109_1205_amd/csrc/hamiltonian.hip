@@ -12,6 +12,9 @@
 // row u (L1/L2 resident), the diagonal is evaluated on the fly from the two
 // masks.  H.v is sparse and memory bound: no matrix cores are involved.
 #include <array>
+#include <map>
+#include <cstdlib>
+#include <cstring>
 
 #include "kgf_internal.h"
 
@@ -271,6 +274,117 @@ __global__ __launch_bounds__(kThreads) void k_hv(HvTables T, const double2* __re
 constexpr int kHvThreads = 1024;
 constexpr size_t kRowLdsMax = 78 * 1024;
 
+// One instance group of a grouped single-pass launch (device copy).
+struct HvGroupDev {
+    HvTables T;
+    int64_t blk0;  // first flattened block of the group (8 * rpx blocks per column)
+    int rpx;       // rows per XCD
+    int thr;       // threads owning row elements (the group's own block size)
+    int col0;      // first global column of the group
+    int uniform;   // diagonal U by popcount (one U for all sites)
+};
+
+// Body of the single-pass kernel for output row u of one column: the block
+// stages x[u, :] in LDS (srow), threads tid < nthr own the row elements
+// d = tid, tid + nthr, ...  (the others only join the barriers and add zero
+// to the block's Lanczos dot).  par: parameter-set index of the column.
+template <int MODE, bool UNIFORM_U>
+__device__ __forceinline__ void hv_lds_row(const HvTables& T, int64_t u, int par, int nthr,
+                                           const double2* __restrict__ x, const double2* __restrict__ xp,
+                                           double2* __restrict__ y, double sc, double bp, double* __restrict__ part_out,
+                                           double2* srow, double* s_negt, double* s_U, double* s_upval,
+                                           int64_t* s_uprow, double* s_red) {
+    const int tid = threadIdx.x;
+    const bool owner = tid < nthr;
+    const int64_t Ddn = T.Ddn;
+    const double2* __restrict__ xrow = x + u * Ddn;
+
+    if (owner)
+        for (int64_t d = tid; d < Ddn; d += nthr) srow[d] = xrow[d];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par * T.nb + b];
+    if (!UNIFORM_U)
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par * 768 + i];
+    __syncthreads();
+    const int cu = T.cnt_up[u];
+    for (int k = tid; k < cu; k += blockDim.x) {
+        uint32_t e = T.ent_up[(int64_t)k * T.Dup + u];
+        double v = s_negt[(e >> 24) & 127u];
+        s_upval[k] = (e >> 31) ? -v : v;
+        s_uprow[k] = (int64_t)(e & 0xFFFFFFu) * Ddn;
+    }
+    __syncthreads();
+
+    const uint32_t mu = T.mu[u];
+    const double eu = T.eu[par * T.Dup + u];
+    double dot = 0.0;
+    // Gathers are issued in predicated batches of kBatch so that many loads
+    // are in flight per thread (the hop counts are data dependent).
+    constexpr int kBatch = 8;
+    // up-spin row gathers per batch: 4 in the Lanczos form keeps it within the
+    // 64-VGPR budget without spills (measured: 4 and 6 equal, 8 spills)
+    constexpr int kBatchUp = MODE == 1 ? 4 : 8;
+    if (owner)
+        for (int64_t d = tid; d < Ddn; d += nthr) {
+            const double2 xv = srow[d];
+            const uint32_t both = mu & T.md[d];
+            const int cd = T.cnt_dn[d];
+            double dg = eu + T.ed[par * T.Ddn + d];
+            if (UNIFORM_U) {
+                dg += par_U0(T, par) * (double)__popc(both);
+            } else {
+                dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
+            }
+            double ar = dg * xv.x, ai = dg * xv.y;
+            for (int k0 = 0; k0 < cu; k0 += kBatchUp) {     // up-spin hops: uniform count
+                double2 z[kBatchUp];
+#pragma unroll
+                for (int j = 0; j < kBatchUp; ++j)
+                    if (k0 + j < cu) z[j] = x[s_uprow[k0 + j] + d];
+#pragma unroll
+                for (int j = 0; j < kBatchUp; ++j)
+                    if (k0 + j < cu) {
+                        const double tv = s_upval[k0 + j];
+                        ar = fma(tv, z[j].x, ar);
+                        ai = fma(tv, z[j].y, ai);
+                    }
+            }
+            for (int k0 = 0; k0 < cd; k0 += kBatch) {       // down-spin hops: per-lane count
+                uint32_t e[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) e[j] = (k0 + j < cd) ? T.ent_dn[(int64_t)(k0 + j) * Ddn + d] : 0u;
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    if (k0 + j < cd) {
+                        double tv = s_negt[(e[j] >> 24) & 127u];
+                        tv = (e[j] >> 31) ? -tv : tv;
+                        const double2 zz = srow[e[j] & 0xFFFFFFu];
+                        ar = fma(tv, zz.x, ar);
+                        ai = fma(tv, zz.y, ai);
+                    }
+            }
+            double2 out;
+            if (MODE == 0) {
+                out.x = ar;
+                out.y = ai;
+            } else {
+                out.x = sc * ar;
+                out.y = sc * ai;
+                if (bp != 0.0) {
+                    const double2 p = ld_stream(xp + u * Ddn + d);
+                    out.x = fma(-bp, p.x, out.x);
+                    out.y = fma(-bp, p.y, out.y);
+                }
+                dot = fma(sc * xv.x, out.x, dot);
+                dot = fma(sc * xv.y, out.y, dot);
+            }
+            st_stream(y + u * Ddn + d, out);
+        }
+    if (MODE == 1) {
+        double sum = block_sum(dot, s_red);
+        if (tid == 0) *part_out = sum;
+    }
+}
+
 template <int MODE, bool UNIFORM_U>
 __global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds(HvTables T, int rows_per_xcd,
                                                        const double2* __restrict__ X, int64_t x_col,
@@ -291,99 +405,51 @@ __global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds(HvTables T, int rows_p
     const int64_t u = (int64_t)(blk & 7) * rows_per_xcd + (blk >> 3);
     if (u >= T.Dup) return;   // uniform over the block
     const int c = blockIdx.y;
-    const int tid = threadIdx.x;
-    const int64_t Ddn = T.Ddn;
-    const double2* __restrict__ x = X + c * x_col;
-    double2* __restrict__ y = Y + c * y_col;
-    const double2* __restrict__ xrow = x + u * Ddn;
-
-    for (int64_t d = tid; d < Ddn; d += blockDim.x) srow[d] = xrow[d];
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
-    if (!UNIFORM_U)
-        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par_index(T, blockIdx.y) * 768 + i];
-    __syncthreads();
-    const int cu = T.cnt_up[u];
-    for (int k = tid; k < cu; k += blockDim.x) {
-        uint32_t e = T.ent_up[(int64_t)k * T.Dup + u];
-        double v = s_negt[(e >> 24) & 127u];
-        s_upval[k] = (e >> 31) ? -v : v;
-        s_uprow[k] = (int64_t)(e & 0xFFFFFFu) * Ddn;
-    }
-    __syncthreads();
-
     double sc = 1.0, bp = 0.0;
     if (MODE == 1) {
         sc = s_k[c * stride];
         if (XP) bp = b_k[c * stride] * s_km1[c * stride];
     }
-    const uint32_t mu = T.mu[u];
-    const double eu = T.eu[par_index(T, blockIdx.y) * T.Dup + u];
-    double dot = 0.0;
-    // Gathers are issued in predicated batches of kBatch so that many loads
-    // are in flight per thread (the hop counts are data dependent).
-    constexpr int kBatch = 8;
-    // up-spin row gathers per batch: 4 in the Lanczos form keeps it within the
-    // 64-VGPR budget without spills (measured: 4 and 6 equal, 8 spills)
-    constexpr int kBatchUp = MODE == 1 ? 4 : 8;
-    for (int64_t d = tid; d < Ddn; d += blockDim.x) {
-        const double2 xv = srow[d];
-        const uint32_t both = mu & T.md[d];
-        const int cd = T.cnt_dn[d];
-        double dg = eu + T.ed[par_index(T, blockIdx.y) * T.Ddn + d];
-        if (UNIFORM_U) {
-            dg += par_U0(T, par_index(T, blockIdx.y)) * (double)__popc(both);
-        } else {
-            dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
-        }
-        double ar = dg * xv.x, ai = dg * xv.y;
-        for (int k0 = 0; k0 < cu; k0 += kBatchUp) {     // up-spin hops: uniform count
-            double2 z[kBatchUp];
-#pragma unroll
-            for (int j = 0; j < kBatchUp; ++j)
-                if (k0 + j < cu) z[j] = x[s_uprow[k0 + j] + d];
-#pragma unroll
-            for (int j = 0; j < kBatchUp; ++j)
-                if (k0 + j < cu) {
-                    const double tv = s_upval[k0 + j];
-                    ar = fma(tv, z[j].x, ar);
-                    ai = fma(tv, z[j].y, ai);
-                }
-        }
-        for (int k0 = 0; k0 < cd; k0 += kBatch) {       // down-spin hops: per-lane count
-            uint32_t e[kBatch];
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) e[j] = (k0 + j < cd) ? T.ent_dn[(int64_t)(k0 + j) * Ddn + d] : 0u;
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j)
-                if (k0 + j < cd) {
-                    double tv = s_negt[(e[j] >> 24) & 127u];
-                    tv = (e[j] >> 31) ? -tv : tv;
-                    const double2 zz = srow[e[j] & 0xFFFFFFu];
-                    ar = fma(tv, zz.x, ar);
-                    ai = fma(tv, zz.y, ai);
-                }
-        }
-        double2 out;
-        if (MODE == 0) {
-            out.x = ar;
-            out.y = ai;
-        } else {
-            out.x = sc * ar;
-            out.y = sc * ai;
-            if (bp != 0.0) {
-                const double2 p = ld_stream(XP + c * xp_col + u * Ddn + d);
-                out.x = fma(-bp, p.x, out.x);
-                out.y = fma(-bp, p.y, out.y);
-            }
-            dot = fma(sc * xv.x, out.x, dot);
-            dot = fma(sc * xv.y, out.y, dot);
-        }
-        st_stream(y + u * Ddn + d, out);
-    }
-    if (MODE == 1) {
-        double s = block_sum(dot, s_red);
-        if (tid == 0) part[(int64_t)c * T.Dup + u] = s;
-    }
+    hv_lds_row<MODE, UNIFORM_U>(T, u, par_index(T, c), blockDim.x, X + c * x_col, XP ? XP + c * xp_col : nullptr,
+                                Y + c * y_col, sc, bp, MODE == 1 ? part + (int64_t)c * T.Dup + u : nullptr, srow,
+                                s_negt, s_U, s_upval, s_uprow, s_red);
+}
+
+// The Lanczos-fused single pass for the columns of several instance groups
+// (different sectors and Hamiltonians) in one launch: block (b, c) serves
+// global column c, whose group supplies the tables, the row mapping and the
+// number of row-element owners; every group's arithmetic is that of its own
+// single-group launch (same element owners, same reduction order).
+template <bool UNIFORM_U>
+__global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds_groups(const HvGroupDev* __restrict__ groups, int ngroups,
+                                                                 int64_t nblocks, const GroupCol* __restrict__ cols,
+                                                                 int k, const double* __restrict__ scal, int stride) {
+    extern __shared__ double2 srow[];
+    __shared__ double s_negt[kMaxBonds + 1];
+    __shared__ double s_U[UNIFORM_U ? 1 : 3 * 256];
+    __shared__ double s_upval[kMaxBonds + 1];
+    __shared__ int64_t s_uprow[kMaxBonds + 1];
+    __shared__ double s_red[kHvThreads / 64];
+    // flattened grid: group by block prefix, then column and row block
+    const int64_t b = flat_block();
+    if (b >= nblocks) return;
+    int g = 0;
+    while (g + 1 < ngroups && b >= groups[g + 1].blk0) ++g;
+    const HvGroupDev G = groups[g];   // by value: the tables stay in registers like kernel arguments
+    const int64_t lb = b - G.blk0;
+    const int c = G.col0 + (int)(lb / (8 * G.rpx));
+    const int blk = (int)(lb % (8 * G.rpx));
+    const GroupCol C = cols[c];
+    const int64_t u = (int64_t)(blk & 7) * G.rpx + (blk >> 3);
+    if (u >= G.T.Dup) return;
+    const double* sc_c = scal + (int64_t)c * stride;
+    const double sc = sc_c[kScalOffS + k];
+    const double bp = k > 0 ? sc_c[kScalOffB + k] * sc_c[kScalOffS + k - 1] : 0.0;
+    const double2* x = C.at(k);
+    const double2* xp = k > 0 ? C.at(k - 1) : nullptr;
+    double2* y = C.at(k + 1);
+    hv_lds_row<1, UNIFORM_U>(G.T, u, par_index(G.T, c - G.col0), G.thr, x, xp, y, sc, bp, C.part + u, srow, s_negt,
+                             s_U, s_upval, s_uprow, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1009,7 +1075,90 @@ void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int 
     check_launch("k_hv");
 }
 
+// threads of a single-pass block for rows of ddn elements: one lane per row
+// element in whole wavefronts, at most kHvThreads
+int hv_row_threads(int64_t ddn) {
+    return (int)std::min<int64_t>(kHvThreads, std::max<int64_t>(64, (ddn + 63) / 64 * 64));
+}
+
 }  // namespace
+
+bool hv_groups_supported(kgf_ctx* ctx, const std::vector<GroupSpec>& groups) {
+    for (const GroupSpec& g : groups) {
+        if (g.sec->dim() == 0) return false;
+        if (hv_plan(ctx, g.sec, 1).passes != 1) return false;
+        if (g.sec->d_up > 0x7ffffff0) return false;
+    }
+    return !groups.empty();
+}
+
+void hv_lanczos_groups(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, const GroupCol* cols, int ncol_total,
+                       int k, const double* scal, int stride) {
+    (void)ncol_total;
+    // One launch per (diagonal form, block size): the groups whose rows take
+    // the same number of threads share a launch, each with the flattened
+    // block prefix of its groups, so no block carries idle wavefronts.
+    std::map<std::pair<int, int>, std::vector<HvGroupDev>> parts;
+    int64_t max_ddn = 0;
+    double bytes = 0.0;
+    for (const GroupSpec& G : groups) {
+        if (G.ncol == 0) continue;
+        HvGroupDev h;
+        h.T = make_tables(G.model, G.sec);
+        h.rpx = (int)((G.sec->d_up + 7) / 8);
+        h.thr = hv_row_threads(G.sec->d_dn);
+        h.col0 = G.col0;
+        h.uniform = uniform_U(G.model) ? 1 : 0;
+        h.blk0 = 0;   // set per part below
+        parts[{h.uniform, h.thr}].push_back(h);
+        max_ddn = std::max<int64_t>(max_ddn, G.sec->d_dn);
+        bytes += 16.0 * (double)G.sec->dim() * G.ncol * (k > 0 ? 3.0 : 2.0);
+    }
+    // block prefixes per part (the column count of each group is needed)
+    std::map<int, int> ncol_of;   // col0 -> ncol
+    for (const GroupSpec& G : groups) ncol_of[G.col0] = G.ncol;
+    std::vector<unsigned char> hb;
+    std::vector<std::pair<size_t, int64_t>> launch;   // (first entry, blocks) per part
+    std::vector<std::pair<int, int>> keys;
+    for (auto& kv : parts) {
+        int64_t nblk = 0;
+        for (HvGroupDev& h : kv.second) {
+            h.blk0 = nblk;
+            nblk += (int64_t)8 * h.rpx * ncol_of[h.col0];
+        }
+        launch.push_back({hb.size() / sizeof(HvGroupDev), nblk});
+        keys.push_back(kv.first);
+        const unsigned char* b = reinterpret_cast<const unsigned char*>(kv.second.data());
+        hb.insert(hb.end(), b, b + sizeof(HvGroupDev) * kv.second.size());
+    }
+    // the tables change only with the groups: upload when they differ
+    if (!ctx->ws.count("hvg_groups") || ctx->hvg_table != hb) {
+        upload_table(ctx, "hvg_groups", hb.data(), hb.size());
+        ctx->hvg_table = std::move(hb);
+    }
+    const HvGroupDev* dg = static_cast<const HvGroupDev*>(ctx->ws["hvg_groups"]->p);
+    Prof pr(ctx, "hv_lanczos", bytes);
+    const size_t row_bytes = sizeof(double2) * (size_t)max_ddn;
+    size_t pi = 0;
+    for (auto& kv : parts) {
+        const int uniform = kv.first.first, thr = kv.first.second;
+        const HvGroupDev* tab = dg + launch[pi].first;
+        const int64_t nblk = launch[pi].second;
+        const int ng = (int)kv.second.size();
+        ++pi;
+        if (nblk == 0) continue;
+        if (uniform) {
+            opt_in_lds(ctx, (const void*)k_hv_lds_groups<true>, 10, kRowLdsMax);
+            hipLaunchKernelGGL(k_hv_lds_groups<true>, flat_grid(nblk), dim3(thr), row_bytes, ctx->stream, tab, ng,
+                               nblk, cols, k, scal, stride);
+        } else {
+            opt_in_lds(ctx, (const void*)k_hv_lds_groups<false>, 11, kRowLdsMax);
+            hipLaunchKernelGGL(k_hv_lds_groups<false>, flat_grid(nblk), dim3(thr), row_bytes, ctx->stream, tab, ng,
+                               nblk, cols, k, scal, stride);
+        }
+        check_launch("k_hv_lds_groups");
+    }
+}
 
 void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
     if (!ctx->hv_tune || ctx->hv_passes || ctx->hv_strip || sec->dim() == 0) return;

@@ -99,6 +99,7 @@ struct kgf_ctx {
     int cg_max_iter = 0;                     // 0: 20000 (projected CG of the adjoints)
     // captured SIL steps (hipGraph), replayed when the same step recurs
     int use_graphs = 1;
+    int lockstep = 1;                        // 1: uneven instance groups advance together (grouped launches)
     struct SilGraph {
         std::vector<unsigned char> key;
         hipGraphExec_t exec = nullptr;
@@ -107,6 +108,14 @@ struct kgf_ctx {
     std::vector<SilGraph> sil_graphs;
     uint64_t graph_clock = 0;
     hipStream_t capture_stream = nullptr;
+    // host copies of the device tables of the last grouped launch
+    std::vector<unsigned char> hvg_table, gcol_table;
+    // pinned staging ring for small table uploads (stream-ordered, no host wait)
+    static constexpr int kStageSlots = 4;
+    void* stage[kStageSlots] = {};
+    size_t stage_bytes[kStageSlots] = {};
+    hipEvent_t stage_ev[kStageSlots] = {};
+    int stage_next = 0;
     std::map<std::array<int, 4>, std::pair<int, int>> hv_tuned;   // (L, N_up, N_dn, mode) -> (passes, strip)
     // progress callback
     kgf_progress_fn progress = nullptr;
@@ -158,6 +167,11 @@ struct Prof {
     Prof(kgf_ctx* c, const char* n, double bytes = 0.0);
     ~Prof();
 };
+
+// copy n bytes of host data into the device workspace `name` in stream
+// order through the pinned staging ring (the host does not wait for the
+// stream); returns the device pointer
+void* upload_table(kgf_ctx* ctx, const std::string& name, const void* host, size_t n);
 
 // unique version stamps of models and model sets
 uint64_t next_version();
@@ -252,6 +266,60 @@ void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a);
 
 // ---- krylov (krylov.hip) -------------------------------------------------
+// Per-column scalar block of the SIL recursion (doubles): offsets of b_k and
+// s_k (the full layout lives in krylov.hip).
+constexpr int kScalOffB = 128;
+constexpr int kScalOffS = 258;
+
+// One column of a launch that serves several instance groups: its Krylov
+// slots (slot 0 is the state), dimension, partial-sum area and group.
+struct GroupCol {
+    double2* s0;
+    double2* X1;
+    int64_t x_slot;
+    int64_t D;
+    double* part;
+    int group;
+    int nb;            // blocks per column of the streaming kernels
+    int nrow;          // rows (D_up): partials of the Lanczos H.v
+    __host__ __device__ double2* at(int k) const { return k == 0 ? s0 : X1 + (int64_t)(k - 1) * x_slot; }
+};
+
+// Block range of one group in a flattened grouped launch: global blocks
+// [blk0, blk0 + nb * ncol) serve columns col0.. with nb blocks each.
+struct GroupRange {
+    int64_t blk0;
+    int nb;
+    int col0;
+};
+// group, column and block within the column of flattened block b
+__device__ __forceinline__ int group_of_block(const GroupRange* r, int ng, int64_t b) {
+    int g = 0;
+    while (g + 1 < ng && b >= r[g + 1].blk0) ++g;
+    return g;
+}
+
+// An instance group of a grouped launch: its model (or model set), sector
+// and global columns [col0, col0 + ncol).
+struct GroupSpec {
+    HModel model;
+    const kgf_sector* sec;
+    int col0;
+    int ncol;
+};
+// true when every group's Lanczos H.v is the single pass (rows in LDS)
+bool hv_groups_supported(kgf_ctx* ctx, const std::vector<GroupSpec>& groups);
+// Lanczos-fused H.v of step k for every column of every group in one launch
+// (cols: device descriptors, scal: per-column scalar blocks of stride stride)
+void hv_lanczos_groups(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, const GroupCol* cols, int ncol_total,
+                       int k, const double* scal, int stride);
+// flattened grid of 1D blocks over n blocks (x up to 2^31 - 1, then y)
+inline dim3 flat_grid(int64_t n) {
+    const int64_t x = n < 0x7fffffff ? n : 0x7fffffff;
+    return dim3((unsigned)(x > 0 ? x : 1), (unsigned)((n + x - 1) / (x > 0 ? x : 1)));
+}
+__device__ __forceinline__ int64_t flat_block() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+
 struct SilOpts {
     int m;
     int reorth;
@@ -335,6 +403,15 @@ void check_prop_opts(const kgf_prop_opts* o);
 // the uniqueness fields of ground-state options are valid
 bool gs_unique_opts_ok(const kgf_gs_opts* o);
 SilOpts to_sil_opts(const kgf_prop_opts* o);
+
+// One SIL step of every column of every group (reorth 0, single-pass H.v),
+// each kernel launched once for all of them.  Results equal those of
+// sil_propagate on each group separately (bitwise: same kernels per group).
+void sil_step_groups(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, const std::vector<double2*>& psi,
+                     const std::vector<int64_t>& ld, const SilOpts& o);
+// reserve the workspaces of the largest grouped step a caller will run
+// (avoids growing them step by step)
+void sil_groups_reserve(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, int m);
 
 // ---- greens (greens.hip) -------------------------------------------------
 void greens_eq(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,

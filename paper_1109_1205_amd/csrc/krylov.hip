@@ -31,6 +31,7 @@ constexpr int kOffSmax = 389;
 constexpr int kOffCoef = 390;              // complex coef[0..128] (re, im)
 constexpr int kScalStride = 648;
 static_assert(kMaxKrylov <= 128 && kOffCoef % 2 == 0 && kScalStride % 2 == 0, "per-column scalar layout");
+static_assert(kOffB == kScalOffB && kOffS == kScalOffS, "scalar offsets shared with the H.v kernels");
 
 constexpr int kDotChunk = 8;               // vectors per multi-dot chunk
 
@@ -276,13 +277,30 @@ __device__ double fixed_sum(const double* p, int n, double* sh) {
 
 enum FinMode { FIN_INIT = 0, FIN_A = 1, FIN_B = 2 };
 
+__device__ __forceinline__ void fin_body(int mode, int k, double v, double* sc, double tol);
+
 __global__ void k_fin(int mode, int k, const double* __restrict__ part, int nper,
                       double* __restrict__ scal, double tol) {
     __shared__ double sh[kThreads / 64];
     const int c = blockIdx.x;
     double v = fixed_sum(part + (int64_t)c * nper, nper, sh);
     if (threadIdx.x != 0) return;
-    double* sc = scal + (int64_t)c * kScalStride;
+    fin_body(mode, k, v, scal + (int64_t)c * kScalStride, tol);
+}
+
+// finaliser of a grouped launch: column c's partials (rows = 1: one per H.v
+// row, else one per streaming block)
+__global__ void k_fin_groups(int mode, int k, const GroupCol* __restrict__ cols, int rows,
+                             double* __restrict__ scal, double tol) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.x;
+    const GroupCol C = cols[c];
+    double v = fixed_sum(C.part, rows ? C.nrow : C.nb, sh);
+    if (threadIdx.x != 0) return;
+    fin_body(mode, k, v, scal + (int64_t)c * kScalStride, tol);
+}
+
+__device__ __forceinline__ void fin_body(int mode, int k, double v, double* sc, double tol) {
     if (mode == FIN_INIT) {
         double b0 = sqrt(v);
         sc[kOffBeta0] = b0;
@@ -1278,6 +1296,221 @@ double* sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, 
     }
     for (int step = 0; step < nsteps; ++step) sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
     return w.err;
+}
+
+// ---------------------------------------------------------------------------
+// grouped launches: the columns of several instance groups (sectors of
+// different size, a Hamiltonian per column) in every launch of a SIL step.
+// Column c (blockIdx.y) reads its slots, dimension and partial area from
+// cols[c]; per column the element-to-thread mapping, block count and
+// reduction order are those of the single-group kernels above.
+// ---------------------------------------------------------------------------
+// column and block-within-column of a flattened streaming launch
+__device__ __forceinline__ bool stream_block(const GroupRange* r, int ng, int64_t nblocks, int* c, int* bx) {
+    const int64_t b = flat_block();
+    if (b >= nblocks) return false;
+    const int g = group_of_block(r, ng, b);
+    const int64_t lb = b - r[g].blk0;
+    *c = r[g].col0 + (int)(lb / r[g].nb);
+    *bx = (int)(lb % r[g].nb);
+    return true;
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm2_groups(const GroupCol* __restrict__ cols,
+                                                           const GroupRange* __restrict__ rg, int ng, int64_t nblocks) {
+    __shared__ double sh[kThreads / 64];
+    int c, bx;
+    if (!stream_block(rg, ng, nblocks, &c, &bx)) return;
+    const GroupCol C = cols[c];
+    const double2* x = C.s0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)bx * blockDim.x + threadIdx.x; i < C.D; i += (int64_t)C.nb * blockDim.x) {
+        double2 z = x[i];
+        acc = fma(z.x, z.x, acc);
+        acc = fma(z.y, z.y, acc);
+    }
+    double v = block_sum(acc, sh);
+    if (threadIdx.x == 0) C.part[bx] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_update_groups(const GroupCol* __restrict__ cols,
+                                                            const GroupRange* __restrict__ rg, int ng,
+                                                            int64_t nblocks, int k, const double* __restrict__ scal) {
+    __shared__ double sh[kThreads / 64];
+    int c, bx;
+    if (!stream_block(rg, ng, nblocks, &c, &bx)) return;
+    const GroupCol C = cols[c];
+    const double* sc = scal + (int64_t)c * kScalStride;
+    const double f = sc[kOffA + k] * sc[kOffS + k];
+    const double2* x = C.at(k);
+    double2* y = C.at(k + 1);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)bx * blockDim.x + threadIdx.x; i < C.D; i += (int64_t)C.nb * blockDim.x) {
+        double2 z = ld_once(x + i), w = y[i];
+        w.x = fma(-f, z.x, w.x);
+        w.y = fma(-f, z.y, w.y);
+        y[i] = w;
+        acc = fma(w.x, w.x, acc);
+        acc = fma(w.y, w.y, acc);
+    }
+    double v = block_sum(acc, sh);
+    if (threadIdx.x == 0) C.part[bx] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_combine_groups(const GroupCol* __restrict__ cols,
+                                                             const GroupRange* __restrict__ rg, int ng,
+                                                             int64_t nblocks, int n, const double* __restrict__ scal) {
+    extern __shared__ double2 cf[];
+    int c, bx;
+    if (!stream_block(rg, ng, nblocks, &c, &bx)) return;
+    const GroupCol C = cols[c];
+    const double2* coef = reinterpret_cast<const double2*>(scal + (int64_t)c * kScalStride + kOffCoef);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) cf[j] = coef[j];
+    __syncthreads();
+    double2* o = C.s0;
+    for (int64_t i = (int64_t)bx * blockDim.x + threadIdx.x; i < C.D; i += (int64_t)C.nb * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double2 z = ld_once(C.at(j) + i);
+            const double2 h = cf[j];
+            re = fma(h.x, z.x, fma(-h.y, z.y, re));
+            im = fma(h.x, z.y, fma(h.y, z.x, im));
+        }
+        o[i] = make_double2(re, im);
+    }
+}
+
+// workspace sizes of a grouped SIL step: Krylov slots, partials
+static void group_sizes(const std::vector<GroupSpec>& groups, int m, size_t* xbytes, size_t* pbytes, int* ncol) {
+    *xbytes = *pbytes = 0;
+    *ncol = 0;
+    for (const GroupSpec& g : groups) {
+        const int64_t D = g.sec->dim();
+        *ncol += g.ncol;
+        *xbytes += sizeof(double2) * (size_t)m * g.ncol * D;
+        *pbytes += sizeof(double) * (size_t)g.ncol * std::max<int64_t>(red_blocks(D), g.sec->d_up);
+    }
+}
+
+void sil_groups_reserve(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, int m) {
+    size_t xbytes, pbytes;
+    int ncol;
+    group_sizes(groups, m, &xbytes, &pbytes, &ncol);
+    auto& xs = ctx->ws["sg_X"];
+    if (!xs || xs->bytes < xbytes) {
+        if (xs) {
+            sync(ctx);
+            xs.reset();
+        }
+        ensure_device_fits(xbytes, "grouped SIL Krylov basis");
+        workspace(ctx, "sg_X", xbytes);
+    }
+    workspace(ctx, "sg_part", pbytes);
+    workspace(ctx, "sg_scal", sizeof(double) * kScalStride * (size_t)std::max(ncol, 1));
+}
+
+void sil_step_groups(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, const std::vector<double2*>& psi,
+                     const std::vector<int64_t>& ld, const SilOpts& o) {
+    KGF_REQUIRE(o.reorth == 0, KGF_EUNSUPPORTED, "grouped SIL step: no reorthogonalisation");
+    const int m = o.m;
+    int ncol = 0;
+    for (const GroupSpec& g : groups) {
+        KGF_REQUIRE(g.col0 == ncol, KGF_EINVAL, "grouped SIL step: groups must take consecutive columns");
+        ncol += g.ncol;
+    }
+    if (ncol == 0) return;
+    KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "grouped SIL step: at most 65535 columns");
+    size_t xbytes, pbytes;
+    group_sizes(groups, m, &xbytes, &pbytes, &ncol);
+    sil_groups_reserve(ctx, groups, m);   // a no-op when the caller reserved the largest step beforehand
+    char* X = static_cast<char*>(workspace(ctx, "sg_X", xbytes));
+    double* part = static_cast<double*>(workspace(ctx, "sg_part", pbytes));
+    double* scal = static_cast<double*>(workspace(ctx, "sg_scal", sizeof(double) * kScalStride * (size_t)ncol));
+    std::vector<GroupCol> cols((size_t)ncol);
+    size_t xo = 0, po = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const GroupSpec& g = groups[gi];
+        const int64_t D = g.sec->dim();
+        double2* Xg = reinterpret_cast<double2*>(X + xo);
+        for (int lc = 0; lc < g.ncol; ++lc) {
+            GroupCol& C = cols[(size_t)g.col0 + lc];
+            C.s0 = psi[gi] + (int64_t)lc * ld[gi];
+            C.X1 = Xg + (int64_t)lc * D;
+            C.x_slot = (int64_t)g.ncol * D;
+            C.D = D;
+            C.part = part + po;
+            C.group = (int)gi;
+            C.nb = red_blocks(D);
+            C.nrow = (int)g.sec->d_up;
+            po += (size_t)std::max<int64_t>(C.nb, g.sec->d_up);
+        }
+        xo += sizeof(double2) * (size_t)m * g.ncol * D;
+    }
+    // block ranges of the flattened streaming launches (nb blocks per column)
+    std::vector<GroupRange> ranges;
+    int64_t nstream = 0;
+    for (const GroupSpec& g : groups) {
+        if (g.ncol == 0) continue;
+        GroupRange r;
+        r.blk0 = nstream;
+        r.nb = red_blocks(g.sec->dim());
+        r.col0 = g.col0;
+        nstream += (int64_t)r.nb * g.ncol;
+        ranges.push_back(r);
+    }
+    const int ng = (int)ranges.size();
+    // upload the column and range tables when they changed (a sweep keeps them for many steps)
+    const size_t cb = sizeof(GroupCol) * cols.size(), rb = sizeof(GroupRange) * ranges.size();
+    std::vector<unsigned char> hb(cb + rb);
+    std::memcpy(hb.data(), cols.data(), cb);
+    std::memcpy(hb.data() + cb, ranges.data(), rb);
+    if (!ctx->ws.count("sg_cols") || ctx->gcol_table != hb) {
+        upload_table(ctx, "sg_cols", hb.data(), hb.size());
+        ctx->gcol_table = std::move(hb);
+    }
+    const GroupCol* dcols = static_cast<const GroupCol*>(ctx->ws["sg_cols"]->p);
+    const GroupRange* drng = reinterpret_cast<const GroupRange*>(static_cast<char*>(ctx->ws["sg_cols"]->p) + cb);
+    static_assert(sizeof(GroupCol) % alignof(GroupRange) == 0, "range table alignment");
+    double vec = 0.0;
+    for (const GroupSpec& g : groups) vec += 16.0 * (double)g.sec->dim() * g.ncol;
+    {
+        Prof pr(ctx, "norm", vec);
+        hipLaunchKernelGGL(k_norm2_groups, flat_grid(nstream), dim3(kThreads), 0, ctx->stream, dcols, drng, ng, nstream);
+        check_launch("k_norm2_groups");
+    }
+    auto fin = [&](int mode, int k, int rows, double tol) {
+        Prof pr(ctx, "fin");
+        hipLaunchKernelGGL(k_fin_groups, dim3(ncol), dim3(kThreads), 0, ctx->stream, mode, k, dcols, rows, scal, tol);
+        check_launch("k_fin_groups");
+    };
+    fin(FIN_INIT, 0, 0, 0.0);
+    for (int k = 0; k < m; ++k) {
+        hv_lanczos_groups(ctx, groups, dcols, ncol, k, scal, kScalStride);
+        fin(FIN_A, k, 1, 0.0);
+        if (k == m - 1) break;
+        {
+            Prof pr(ctx, "lanczos_update", 3.0 * vec);
+            hipLaunchKernelGGL(k_update_groups, flat_grid(nstream), dim3(kThreads), 0, ctx->stream, dcols, drng, ng,
+                               nstream, k, scal);
+            check_launch("k_update_groups");
+        }
+        fin(FIN_B, k, 0, o.breakdown_tol);
+    }
+    double2* coef = reinterpret_cast<double2*>(scal + kOffCoef);
+    for (int r0 = 0; r0 < ncol; r0 += kMaxReq) {
+        CoefReq q;
+        q.n = std::min(kMaxReq, ncol - r0);
+        for (int r = 0; r < q.n; ++r) {
+            q.col[r] = r0 + r;
+            q.t[r] = o.dt;
+            q.dir[r] = o.direction;
+        }
+        launch_coefs(ctx, scal, m, q, o.shift, coef + (int64_t)r0 * (kScalStride / 2), kScalStride / 2);
+    }
+    Prof pr(ctx, "combine", (m + 1) * vec);
+    hipLaunchKernelGGL(k_combine_groups, flat_grid(nstream), dim3(kThreads), sizeof(double2) * m, ctx->stream, dcols,
+                       drng, ng, nstream, m, scal);
+    check_launch("k_combine_groups");
 }
 
 // Uniqueness of a ground state: a second recursion from a SplitMix64 start

@@ -50,6 +50,27 @@ def test_multi_equals_per_instance_short_mesh(ctx):
         assert rel_err(out["G_greater"][i], ref["G_greater"]) < 1e-12
 
 
+@pytest.mark.parametrize("batch", [0, 7])
+def test_lockstep_equals_group_by_group(ctx, batch):
+    """All groups (L = 8..12) advancing together, each SIL kernel one launch
+    over every group's columns, equal the group-by-group batches bitwise;
+    batch = 7 cuts the sweeps into several chunks of source times."""
+    qs = wl.batch_instances()[:12]
+    say("lockstep vs group by group, L =", sorted({q.H.L for q in qs}), "batch", batch)
+    Hi, Hf, secs, v0 = _inputs(ctx, qs)
+    kw = dict(orbitals=[(0, 0), (1, 1)], nt=5, steps_per_grid=2, dt=0.05, krylov_dim=12, batch=batch)
+    LOCKSTEP = 9
+    ctx.set_option(LOCKSTEP, 0)
+    try:
+        ref = ctx.greens_neq_multi(Hi, Hf, secs, v0, **kw)
+    finally:
+        ctx.set_option(LOCKSTEP, 1)
+    got = ctx.greens_neq_multi(Hi, Hf, secs, v0, **kw)
+    assert np.array_equal(got["E0"], ref["E0"])
+    for key in ("G_lesser", "G_greater"):
+        assert np.array_equal(got[key], ref[key]), key
+
+
 def test_multi_l8_instances_full_mesh_against_oracle(ctx):
     qs = [q for q in wl.batch_instances() if q.H.L == 8][:2]
     assert len(qs) == 2
@@ -75,7 +96,14 @@ def test_full_uneven_batch(ctx):
     Hi, Hf, secs, v0 = _inputs(ctx, qs)
     q0 = qs[0]
     kw = dict(orbitals=q0.orbitals, nt=q0.nt, steps_per_grid=q0.steps_per_grid, dt=q0.dt, krylov_dim=q0.krylov_dim)
-    ctx.set_progress(lambda ph, d, t: say("  ", ph, d, t) if d == t else None)
+    last = [time.perf_counter()]
+
+    def report(ph, d, t):
+        now = time.perf_counter()
+        if d == t or now - last[0] > 20.0:
+            last[0] = now
+            say("  ", ph, d, t)
+    ctx.set_progress(report)
     t0 = time.perf_counter()
     try:
         out = ctx.greens_neq_multi(Hi, Hf, secs, v0, **kw)
