@@ -571,8 +571,13 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      each sector (L, N_up, N_dn) times every equivalent variant
  *                      (single pass, two pass with strips 16/32/64, split rows)
  *                      on scratch vectors, separately for the plain and the
- *                      Lanczos form, and keeps the fastest for that context.
- *                      HV_PASSES / HV_STRIP, when set, take precedence.
+ *                      Lanczos form, and keeps the fastest for that context;
+ *                      and the four-step sweeps with batch = 0 time one SIL
+ *                      step per block width (the widest that fits, 32, 16, 8, 4
+ *                      columns) on scratch columns of the target sector and keep
+ *                      the width with the most column-steps per second (cached
+ *                      per sector and Krylov options; columns do not depend on
+ *                      the width).  HV_PASSES / HV_STRIP, when set, take precedence.
  *   KGF_OPT_CG_MAX_ITER: iteration limit of the projected CG of the four-step
  *                      adjoints (0 = 20000).
  *   KGF_OPT_GRAPHS:    1 (default) = a batched SIL step that recurs with the same

@@ -66,6 +66,14 @@ void* workspace(kgf_ctx* ctx, const std::string& name, size_t bytes) {
     return slot->p;
 }
 
+void release_ws(kgf_ctx* ctx, const char* name) {
+    auto it = ctx->ws.find(name);
+    if (it != ctx->ws.end()) {
+        sync(ctx);
+        ctx->ws.erase(it);
+    }
+}
+
 void* host_scratch(kgf_ctx* ctx, size_t bytes) {
     if (bytes > ctx->host_scratch_bytes) {
         if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);

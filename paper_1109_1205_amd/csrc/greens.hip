@@ -342,6 +342,11 @@ struct SweepBranch {
             const size_t budget = (size_t)(0.80 * (double)free_b);
             Bcols = (int)std::max<size_t>(1, budget / per_col);
         }
+        if (A->batch <= 0 && ctx->hv_tune) {
+            // widths as multiples of the spin group: the block of one source time
+            const int w = tuned_sweep_width(ctx, A->H, tgt.get(), std::min(Bcols, nt * na), so);
+            Bcols = std::max(na, (w / na) * na);
+        }
         jchunk = std::min(std::max(1, Bcols / na), nt);
         const int maxcols = jchunk * na;
         release(ctx, "sil_X");

@@ -117,6 +117,7 @@ struct kgf_ctx {
     hipEvent_t stage_ev[kStageSlots] = {};
     int stage_next = 0;
     std::map<std::array<int, 4>, std::pair<int, int>> hv_tuned;   // (L, N_up, N_dn, mode) -> (passes, strip)
+    std::map<std::array<int, 4>, int> sweep_tuned;                // (L, 64 N_up + N_dn, m, reorth) -> columns
     // progress callback
     kgf_progress_fn progress = nullptr;
     void* progress_user = nullptr;
@@ -370,6 +371,14 @@ struct GsResult {
 GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec,
                       const double2* v0, double2* psi0, double tol, int max_iter,
                       int check_every, int reorth);
+
+// v[i] = SplitMix64 output i of `seed` mapped to [-1, 1) (real), i < n
+void fill_splitmix(kgf_ctx* ctx, double2* v, int64_t n, uint64_t seed);
+// sweep block width chosen by timing one SIL step per candidate width (cached
+// per sector shape and Krylov options; at most max_cols)
+int tuned_sweep_width(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int max_cols, const SilOpts& o);
+// drop a workspace (waits for the stream first)
+void release_ws(kgf_ctx* ctx, const char* name);
 
 // |<psi0|psi_b>|^2 for psi_b the ground state from a second (SplitMix64) start
 // vector, and the check that raises KGF_EDEGENERATE below 1 - unique_tol

@@ -1527,6 +1527,68 @@ __global__ void k_splitmix_fill(double2* __restrict__ v, int64_t D, uint64_t see
     }
 }
 
+void fill_splitmix(kgf_ctx* ctx, double2* v, int64_t n, uint64_t seed) {
+    const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_splitmix_fill, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, ctx->stream,
+                       v, n, seed);
+    check_launch("k_splitmix_fill");
+}
+
+// Sweep block width by measurement (KGF_OPT_HV_TUNE): one batched SIL step
+// on scratch columns at each candidate width up to max_cols (the widest that
+// fits, then 32, 16, 8, 4), timed with HIP events after a warm-up step.  The
+// widest candidate within 5% of the best column-steps per second is kept for
+// the sector shape and Krylov options: a narrower block means more chunks,
+// each starting with a growth phase of narrow blocks, which one step does not
+// see.  Column results do not depend on the width.
+int tuned_sweep_width(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int max_cols, const SilOpts& o) {
+    const std::array<int, 4> key = {sec->L, sec->n_up * 64 + sec->n_dn, o.m, o.reorth};
+    auto it = ctx->sweep_tuned.find(key);
+    if (it != ctx->sweep_tuned.end()) return std::min(it->second, max_cols);
+    const int64_t D = sec->dim();
+    std::vector<int> cand;
+    for (int c : {max_cols, 32, 16, 8, 4})
+        if (c >= 1 && c <= max_cols && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    if (cand.size() <= 1 || D == 0) {
+        ctx->sweep_tuned[key] = max_cols;
+        return max_cols;
+    }
+    ensure_device_fits(sizeof(double2) * (size_t)max_cols * D, "sweep width tuning columns");
+    double2* X = static_cast<double2*>(workspace(ctx, "tune_cols", sizeof(double2) * (size_t)max_cols * D));
+    fill_splitmix(ctx, X, (int64_t)max_cols * D, 0x5eedULL);
+    const bool prof = ctx->prof_on;
+    ctx->prof_on = false;
+    hipEvent_t e0, e1;
+    KGF_HIP(hipEventCreate(&e0));
+    KGF_HIP(hipEventCreate(&e1));
+    std::vector<double> rate(cand.size());
+    double best_rate = 0.0;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        const int c = cand[i];
+        sil_propagate(ctx, model, sec, X, c, D, 1, o);   // warm-up (tables, workspaces, graph bookkeeping)
+        KGF_HIP(hipEventRecord(e0, ctx->stream));
+        sil_propagate(ctx, model, sec, X, c, D, 1, o);
+        KGF_HIP(hipEventRecord(e1, ctx->stream));
+        KGF_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        KGF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        rate[i] = c / std::max(1e-6, (double)ms);
+        best_rate = std::max(best_rate, rate[i]);
+    }
+    int best = cand.back();
+    for (size_t i = 0; i < cand.size(); ++i)   // candidates run from the widest down
+        if (rate[i] >= 0.95 * best_rate) {
+            best = cand[i];
+            break;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->prof_on = prof;
+    release_ws(ctx, "tune_cols");
+    ctx->sweep_tuned[key] = best;
+    return best;
+}
+
 double gs_fidelity2(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0,
                     const kgf_gs_opts* o) {
     const int64_t D = sec->dim();

@@ -124,3 +124,22 @@ def test_run_rejects_bad_input(ctx):
     with pytest.raises(RuntimeError):
         run.advance(-1)
     run.close()
+
+
+def test_tuned_sweep_matches_oracle(ctx):
+    """KGF_OPT_HV_TUNE picks the H.v variant and the sweep block width by
+    timing; the tuned four-step still matches the oracle."""
+    H = wl.chain_siam(6, 2.0)
+    Hi = H.with_field(0, 0.4)
+    orbs = [(0, 0), (2, 0), (1, 1)]
+    s = ctx.sector(6, 3, 3)
+    v0 = wl.start_vector(s.dim, 7)
+    ctx.set_option(ctx.HV_TUNE, 1)
+    try:
+        got = ctx.greens_neq(ctx.model(Hi), ctx.model(H), s, to_dev(v0), orbs, nt=7, steps_per_grid=2, dt=0.1,
+                             krylov_dim=15, schedule=1)
+    finally:
+        ctx.set_option(ctx.HV_TUNE, 0)
+    ref = greens.four_step(Hi, H, 3, 3, orbs, 7, 0.2, 2, 15, v0, reorth="none")
+    for key in ("G_lesser", "G_greater"):
+        assert rel_err(got[key], ref[key]) < 1e-10, key
