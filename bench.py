@@ -65,6 +65,8 @@ def parse():
                    help="short run for hardware counters: one SIL step of a batch of backward-sweep "
                         "columns of the same workload, then a plain copy of one vector (calibration)")
     p.add_argument("--probe-cols", type=int, default=8)
+    p.add_argument("--probe-L", type=int, choices=[14, 16], default=14,
+                   help="probe: ladder size (16: the two-pass H.v of the 2x8 ladder)")
     p.add_argument("--workload", choices=["ladder14", "batch64", "ladder16", "fig1", "hub4x3", "driven", "driven4", "necpt",
                                            "two_particle", "graphs"],
                    default="ladder14",
@@ -90,6 +92,9 @@ def parse():
                    help="comma-separated kgf_set_option HV_PASSES values (9: the library's tuner chooses)")
     p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
     p.add_argument("--hv-reps", type=int, default=10)
+    p.add_argument("--no-graphs", action="store_true",
+                   help="run every SIL step eagerly (kgf_set_option GRAPHS 0) instead of replaying captured "
+                        "steps; for kernel traces")
     p.add_argument("--tune", action="store_true",
                    help="let the library time the equivalent H.v variants per sector "
                         "(kgf_set_option HV_TUNE) and keep the fastest")
@@ -145,22 +150,24 @@ def hv_bench(a):
 def probe(a):
     """Launch the dominant kernel in its bench configuration a few times
     (one SIL step, Krylov dim 20, on --probe-cols c-sector columns of the
-    ladder), then one plain vector copy y = 2x whose FETCH_SIZE/WRITE_SIZE
-    calibrate the counters (16 B x D read, 16 B x D written)."""
+    2x7 ladder, or of the 2x8 ladder with --probe-L 16), then one plain
+    vector copy y = 2x whose FETCH_SIZE/WRITE_SIZE calibrate the counters
+    (16 B x D read, 16 B x D written)."""
     import torch
     import paper_1109_1205_amd as kgf
     import workloads as wl
-    q = wl.ladder14()
+    q = wl.ladder14() if a.probe_L == 14 else wl.ladder16()
     ctx = kgf.Context(0)
     m = ctx.model(q.H)
-    sec = ctx.sector(14, q.n_up - 1, q.n_dn)
+    sec = ctx.sector(a.probe_L, q.n_up - 1, q.n_dn)
+    log(f"probe: L={a.probe_L} D={sec.dim} cols={a.probe_cols}")
     g = torch.Generator(device="cuda:0").manual_seed(11)
     X = torch.randn(a.probe_cols, sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
     ctx.propagate(m, sec, X, 1, q.dt, q.krylov_dim, +1)
     y = torch.empty_like(X[0])
     torch.mul(X[0], 2.0, out=y)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "hv_lanczos", "D": sec.dim, "cols": a.probe_cols,
+    print(json.dumps({"probe": "hv_lanczos", "L": a.probe_L, "D": sec.dim, "cols": a.probe_cols,
                       "vector_bytes": 16 * sec.dim}), flush=True)
 
 
@@ -606,7 +613,7 @@ def graphs(a):
     mi10, mf10 = ctx.model(q10.H_ini), ctx.model(q10.H)
     res = {}
     for on in (0, 1, 0, 1):
-        ctx.set_option(8, on)
+        ctx.set_option(ctx.GRAPHS, on)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         G = ctx.greens_eq(m, s, psi0, E0, q.orbitals, q.nt, q.steps_per_grid, q.dt_grid, krylov_dim=q.krylov_dim)
@@ -814,6 +821,8 @@ def stepwise(a):
     ctx = kgf.Context(0)
     if a.tune:
         ctx.set_option(ctx.HV_TUNE, 1)
+    if a.no_graphs:
+        ctx.set_option(ctx.GRAPHS, 0)
     m_ini, m_fin = ctx.model(q.H_ini), ctx.model(q.H)
     sec = ctx.sector(14, q.n_up, q.n_dn)
     v0 = torch.from_numpy(wl.start_vector(sec.dim, q.gs_seed)).to("cuda:0")
@@ -915,6 +924,8 @@ def whole_runs(a):
     ctx = kgf.Context(0)
     if a.tune:
         ctx.set_option(ctx.HV_TUNE, 1)
+    if a.no_graphs:
+        ctx.set_option(ctx.GRAPHS, 0)
     last = [time.perf_counter()]
 
     def report(phase, done, total):
