@@ -93,8 +93,8 @@ def parse():
     p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
     p.add_argument("--hv-reps", type=int, default=10)
     p.add_argument("--no-graphs", action="store_true",
-                   help="run every SIL step eagerly (kgf_set_option GRAPHS 0) instead of replaying captured "
-                        "steps; for kernel traces")
+                   help="state GRAPHS 0 explicitly (every SIL step eager, the library default); kernel traces "
+                        "are taken this way")
     p.add_argument("--tune", action="store_true",
                    help="let the library time the equivalent H.v variants per sector "
                         "(kgf_set_option HV_TUNE) and keep the fastest")

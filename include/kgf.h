@@ -580,12 +580,14 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      the width).  HV_PASSES / HV_STRIP, when set, take precedence.
  *   KGF_OPT_CG_MAX_ITER: iteration limit of the projected CG of the four-step
  *                      adjoints (0 = 20000).
- *   KGF_OPT_GRAPHS:    1 (default) = a batched SIL step that recurs with the same
- *                      model parameters, sector, state buffer, batch width and
- *                      options (the steps of one kgf_propagate call, the intervals
- *                      of a four-step sweep) is captured once in a hipGraph and
+ *   KGF_OPT_GRAPHS:    1 = a batched SIL step that recurs with the same model
+ *                      parameters, sector, state buffer, batch width and options
+ *                      (the steps of one kgf_propagate call, the intervals of a
+ *                      four-step sweep) is captured once in a hipGraph and
  *                      replayed (the same kernels and arguments: bitwise the eager
- *                      results); not while kgf_profile_begin is active.  0 = eager.
+ *                      results); not while kgf_profile_begin is active.  0
+ *                      (default) = eager: a SIL step is a few dozen launches of
+ *                      0.1-15 ms, whose launch cost the stream already hides.
  *                      Changing any option drops the captured steps.
  *   KGF_OPT_LOCKSTEP:  1 (default) = kgf_greens_neq_multi advances the groups of
  *                      instances with small sectors (at most 2^17 states) together:

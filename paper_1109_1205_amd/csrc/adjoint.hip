@@ -340,6 +340,7 @@ struct VjpArgs {
 // states, Gram matrices, cotangent combinations and the ground-state solves
 // are per member.  Mesh states are stored member-fastest: [state][member][D].
 static void four_step_vjp(kgf_ctx* ctx, const VjpArgs& A, const kgf_gs_opts* gso, std::vector<VjpMember>& M) {
+    TraceRange range_("kgf four-step adjoint");
     const kgf_sector* sec = A.sec;
     const int nm = (int)M.size();
     const int64_t D = sec->dim();

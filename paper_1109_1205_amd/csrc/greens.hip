@@ -196,6 +196,7 @@ void release(kgf_ctx* ctx, const char* name) {
 void greens_eq(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* psi0, double E0,
                const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch,
                double2* Gg_host, double2* Gl_host) {
+    TraceRange range_("kgf equilibrium G");
     const size_t gsz = sizeof(double2) * (size_t)nt * norb * norb;
     double2* Gdev = static_cast<double2*>(workspace(ctx, "geq_G", 2 * gsz));
     KGF_HIP(hipMemsetAsync(Gdev, 0, 2 * gsz, ctx->stream));
@@ -381,6 +382,7 @@ struct SweepBranch {
 
     // one mesh interval; returns the SIL column-steps it ran
     int64_t interval(PhiMesh& Phi) {
+        TraceRange range_("kgf sweep interval");
         const kgf_sector* sec = A->sec;
         if (!in_chunk) {
             jlo = std::max(0, jhi - jchunk + 1);
@@ -509,6 +511,7 @@ static int phi_checkpoint_interval(kgf_ctx* ctx, int nt, int64_t D) {
 // psi0_out when given) and the forward mesh Phi(t_k), whole or as checkpoints.
 static double2* neq_forward(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso,
                             double* E0_out, double2* psi0_out, PhiMesh& Phi) {
+    TraceRange range_("kgf forward mesh");
     const kgf_sector* sec = A.sec;
     const int64_t D = sec->dim();
     const int nt = A.nt;
@@ -561,6 +564,7 @@ static double2* neq_forward(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, c
 
 void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso, double* E0_out,
                 double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host) {
+    TraceRange range_("kgf four-step");
     const kgf_sector* sec = A.sec;
     const int64_t D = sec->dim();
     const int nt = A.nt, norb = A.norb;
@@ -944,6 +948,7 @@ void greens_neq_multi(kgf_ctx* ctx, int ninst, kgf_model* const* Hi, kgf_model* 
                       const kgf_sector* const* secs, const double2* const* v0, const kgf_gs_opts* gso,
                       const int32_t* orbs, int norb, int nt, int spg, const SilOpts& o, int batch, double2* Gl_host,
                       double2* Gg_host, double* E0_host) {
+    TraceRange range_("kgf four-step, many instances");
     std::vector<int> small, large;
     for (int i = 0; i < ninst; ++i) (secs[i]->dim() <= kLockstepMaxDim ? small : large).push_back(i);
     std::vector<kgf_model*> small_h;

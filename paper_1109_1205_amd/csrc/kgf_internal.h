@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <array>
 #include <cstdint>
@@ -98,7 +99,7 @@ struct kgf_ctx {
     int hv_tune = 0;                         // 1: time the H.v variants of each sector once
     int cg_max_iter = 0;                     // 0: 20000 (projected CG of the adjoints)
     // captured SIL steps (hipGraph), replayed when the same step recurs
-    int use_graphs = 1;
+    int use_graphs = 0;
     int lockstep = 1;                        // 1: uneven instance groups advance together (grouped launches)
     struct SilGraph {
         std::vector<unsigned char> key;
@@ -403,6 +404,16 @@ void block_dots(kgf_ctx* ctx, const double2* Lv, int64_t l_col, int nl,
 // ---- ABI helpers (api.hip) -------------------------------------------------
 // Runs f, turning kgf::Error and other exceptions into a return code and the
 // thread-local message of kgf_last_error.
+// Named host range around a phase of the path, seen by tracers
+// (rocprofv3 --marker-trace); a no-op when no tool is attached.  Popped on
+// every exit, exceptions included.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
 int abi_guard_impl(void* state, void (*call)(void*));
 template <class F>
 int abi_guard(F&& f) {

@@ -1250,6 +1250,7 @@ static void sil_step_graph(kgf_ctx* ctx, HModel model, const kgf_sector* sec, do
 
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
                    int nsteps, const SilOpts& o, double* err) {
+    TraceRange range_("kgf SIL steps");
     if (err && nsteps > 0) {
         hipLaunchKernelGGL(k_fill_zero, dim3((ncol + 255) / 256), dim3(256), 0, ctx->stream, err, ncol);
         check_launch("k_fill_zero");
@@ -1799,6 +1800,7 @@ int lanczos_tridiag(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const
 // restart); the iteration count and the stopping rule are unchanged.
 GsResult ground_state(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, const double2* v0,
                       double2* psi0, double tol, int max_iter, int check_every, int reorth) {
+    TraceRange range_("kgf ground state");
     const int64_t D = sec->dim();
     const size_t vbytes = sizeof(double2) * (size_t)D;
     size_t free_b = 0, total_b = 0;

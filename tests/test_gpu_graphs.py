@@ -22,7 +22,7 @@ def ctx():
     import paper_1109_1205_amd as k
     c = k.Context(0)
     yield c
-    c.set_option(GRAPHS, 1)
+    c.set_option(GRAPHS, 0)
 
 
 def _eager_then_graph(ctx, fn):
