@@ -189,12 +189,15 @@ int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* se
  * reorth: 0 none, 1 classical GS, 2 classical GS twice.  A recursion
  * stops early (exactly) when b_{k+1} <= breakdown_tol * max(|a_j|, b_j).
  * host_err_est (or NULL): the largest, over columns and steps, a-posteriori
- * estimate of one step's error in the 2-norm,
- *     beta0 * b_m * |[f(T_m) e_1]_{m-1}|,   f(T) = exp(-+i T dt) or exp(-(T - shift) dt),
- * the first term of the error of the Krylov approximation of Eq. (udelta)
+ * estimate of one step's error in the 2-norm, the Krylov residual of the
+ * approximation of Eq. (udelta) integrated over the step,
+ *     beta0 * b_m * int_0^dt |[f_tau(T_m) e_1]_{m-1}| dtau   (16-point Gauss-Legendre),
+ *     f_tau(T) = exp(-+i T tau) or exp(-(T - shift) tau)
  * (b_m: the norm the recursion would carry into a further step; zero after
- * a breakdown, where the step is exact).  Asking for it costs one more
- * vector update per step and synchronises the stream.
+ * a breakdown, where the step is exact).  For the real-time directions the
+ * propagator is unitary and this bounds the step's error up to the
+ * quadrature.  Asking for it costs the tridiagonal exponential at the 16
+ * nodes, one more vector update per step, and synchronises the stream.
  * Workspace: krylov_dim * nvec vectors of D complex128. */
 typedef struct {
     int    krylov_dim;
