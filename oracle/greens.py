@@ -135,7 +135,9 @@ def four_step(H_ini_model, H_model, n_up: int, n_dn: int,
     Returns G_lesser[k, k', a, a'] = G^<_{aa'}(t_k, t_k') and
     G_greater[k, k', a, a'] (both nt x nt x n_orb x n_orb), optionally
     G_matsubara[2, ntau, a, a'] (+tau and -tau parts) and
-    G_mixed[k, j, a, a'] = G^|_{aa'}(t_k, tau_j).
+    G_mixed[k, j, a, a'] = G^|_{aa'}(t_k, tau_j) = G^<_{aa'}(t_k, -i tau_j) and
+    G_mixed_left[j, k, a, a'] = G^|_{aa'}(tau_j, t_k) = G^>_{aa'}(-i tau_j, t_k)
+    (the contour functions with one argument on the imaginary branch).
     `times` restricts step (iii)/(iv) to a subset of mesh indices (entries
     outside the subset are left at zero); the forward sweep (ii) still runs
     to the largest requested time."""
@@ -181,6 +183,7 @@ def four_step(H_ini_model, H_model, n_up: int, n_dn: int,
         dtau = dtau_grid / tau_steps_per_grid
         GM = np.zeros((2, ntau, no, no), dtype=np.complex128)
         Gmix = np.zeros((nt, ntau, no, no), dtype=np.complex128)
+        Gmixl = np.zeros((ntau, nt, no, no), dtype=np.complex128)
         part, hole = {}, {}
         for a, (site, spin) in enumerate(orbitals):
             w, tgt = apply_ladder(sec, site, spin, True, psi0)
@@ -202,8 +205,13 @@ def four_step(H_ini_model, H_model, n_up: int, n_dn: int,
                         GM[1, j, a, b] = vdot(hole[b][1], hole[a][0][j])
                 for j in range(ntau):
                     for k in idx:
+                        # G^<(t_k, -i tau_j) = i <e^{-(H_ini-E0) tau_j} c_b 0 | Psi_a(t_k)>
                         if (a, k) in psi_l and b in hole and psi_l[(a, k)][1] == hole[b][2]:
                             Gmix[k, j, a, b] = 1j * vdot(hole[b][0][j], psi_l[(a, k)][0])
+                        # G^>(-i tau_j, t_k) = -i <e^{-(H_ini-E0) tau_j} c+_a 0 | chi_b(t_k)>
+                        if (b, k) in psi_g and a in part and psi_g[(b, k)][1] == part[a][2]:
+                            Gmixl[j, k, a, b] = -1j * vdot(part[a][0][j], psi_g[(b, k)][0])
         out["G_matsubara"] = GM
         out["G_mixed"] = Gmix
+        out["G_mixed_left"] = Gmixl
     return out

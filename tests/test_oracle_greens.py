@@ -57,6 +57,7 @@ def _exact_four_step(H_ini, H, nu, nd, orbitals, times, taus=()):
         cache = {}
         GM = np.zeros((2, len(taus), no, no), complex)
         Gmix = np.zeros((nt, len(taus), no, no), complex)
+        Gmixl = np.zeros((len(taus), nt, no, no), complex)
         for a, (sa, spa) in enumerate(orbitals):
             for b, (sb, spb) in enumerate(orbitals):
                 if spa != spb:
@@ -70,10 +71,14 @@ def _exact_four_step(H_ini, H, nu, nd, orbitals, times, taus=()):
                     GM[0, j, a, b] = -np.exp(E0 * tau) * np.vdot(ca_d, Dp.apply_exp(cb_d, -1j * tau))
                     GM[1, j, a, b] = np.exp(E0 * tau) * np.vdot(cb, Dh.apply_exp(ca, -1j * tau))
                     phi_b = np.exp(E0 * tau) * Dh.apply_exp(cb, -1j * tau)
+                    phi_a = np.exp(E0 * tau) * Dp.apply_exp(ca_d, -1j * tau)
                     for k in range(nt):
                         Gmix[k, j, a, b] = 1j * np.vdot(phi_b, Psi[a, k][0])
+                        # -i <0| c_a e^{-(H_ini-E0) tau} e^{iHt} c+_b e^{-iHt} |0>
+                        Gmixl[j, k, a, b] = -1j * np.vdot(phi_a, Chi[b, k][0])
         out["G_matsubara"] = GM
         out["G_mixed"] = Gmix
+        out["G_mixed_left"] = Gmixl
     return out
 
 
@@ -120,7 +125,7 @@ def quench_small():
 def test_four_step_against_full_diagonalisation(quench_small):
     ora, ref, _ = quench_small
     assert abs(ora["E0"] - ref["E0"]) < 1e-12 * abs(ref["E0"])
-    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed"):
+    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed", "G_mixed_left"):
         err = np.abs(ora[key] - ref[key]).max()
         assert err < 1e-11, (key, err)
 

@@ -14,8 +14,27 @@ against facts that do not depend on it:
   G' * V * G has no equal-time jump), is met to second order in dt;
 * the oracle's four-step cluster G at U = 0 equals the free-fermion G of the
   cluster's one-particle Hamiltonian after the field quench (the object the
-  CPT equation takes as G^c, with its conventions of sign and order)."""
+  CPT equation takes as G^c, with its conventions of sign and order).
+
+On the Keldysh-Matsubara (L-shaped) contour, with the imaginary branch of
+length beta through which the connected initial state enters:
+
+* the thermal free-fermion components (overflow-free eigenbasis forms)
+  equal the plain matrix-exponential definitions;
+* thermal functions are antiperiodic between the contour's first point
+  (t = 0) and its last (tau = beta), for the free functions and for the
+  bath of Eqs. (gb1), (gb2) on complex times;
+* the bath functions equal the free functions of the unquenched bath, at
+  finite beta and beta -> infinity;
+* at U = 0 the CPT equation on the L-shaped contour converges to the
+  connected system's exact thermal functions at second order in the mesh
+  step on every component, and its t = 0 densities are the connected
+  system's (not the isolated cluster's);
+* V = 0 returns G' on every component;
+* the four-step components (G^M(+-tau), both mixed functions) at U = 0 are
+  the zero-temperature free-fermion functions of the L-shaped contour."""
 import numpy as np
+import scipy.linalg
 import pytest
 
 import workloads as wl
@@ -152,3 +171,156 @@ def test_interacting_anticommutator_converges_second_order():
         dev.append(np.abs(np.einsum("aaij->aij", Gg - Gl) + 1j * np.eye(L)).max())
         assert effect > 0.2 and dev[-1] < 0.02 * effect
     assert 3.6 < dev[0] / dev[1] < 4.4, dev
+
+
+# ---- the Keldysh-Matsubara (L-shaped) contour ------------------------------
+
+def _chain_h(L, t=1.0, eps=None):
+    h = np.zeros((L, L))
+    for i in range(L - 1):
+        h[i, i + 1] = h[i + 1, i] = -t
+    if eps is not None:
+        h += np.diag(eps)
+    return h
+
+
+def test_free_greens_l_against_matrix_functions():
+    """Components of the thermal free-fermion contour functions against the
+    definitions with plain matrix exponentials and inverses (beta small
+    enough that e^{beta h} is harmless)."""
+    rng = np.random.default_rng(11)
+    h_ini = _chain_h(4, 1.0, rng.uniform(-1, 1, 4))
+    h = _chain_h(4, 1.0, rng.uniform(-1, 1, 4))
+    beta, nt, dt, ntau, dtau = 2.0, 3, 0.3, 5, 0.5
+    fn = necpt.free_greens_l(h_ini, h, beta, nt, dt, ntau, dtau)
+    I = np.eye(4)
+    f = np.linalg.inv(scipy.linalg.expm(beta * h_ini) + I)
+    U = [scipy.linalg.expm(-1j * h * dt * k) for k in range(nt)]
+    E = lambda x: scipy.linalg.expm(x * h_ini)
+    for a in range(nt):
+        for b in range(nt):
+            np.testing.assert_allclose(fn["lesser"][a, b], 1j * U[a] @ f @ U[b].conj().T, atol=1e-13)
+            np.testing.assert_allclose(fn["greater"][a, b], -1j * U[a] @ (I - f) @ U[b].conj().T, atol=1e-13)
+        for j in range(ntau):
+            tau = j * dtau
+            np.testing.assert_allclose(fn["mixed"][a, j], 1j * U[a] @ f @ E(tau), atol=1e-12)
+            np.testing.assert_allclose(fn["mixed_left"][j, a], -1j * E(-tau) @ (I - f) @ U[a].conj().T, atol=1e-12)
+    for d in range(ntau):
+        tau = d * dtau
+        np.testing.assert_allclose(fn["vert_greater"][d], -1j * E(-tau) @ (I - f), atol=1e-12)
+        np.testing.assert_allclose(fn["vert_lesser"][d], 1j * f @ E(tau), atol=1e-12)
+
+
+def test_thermal_functions_are_antiperiodic():
+    """KMS: the contour's first point (t = 0, forward) and last point
+    (tau = beta) are one, up to the fermion sign: G(0, z') = -G(-i beta, z');
+    checked for the free functions and for the bath of Eqs. (gb1), (gb2)."""
+    h_ini = _chain_h(5, 1.0, [0.3, -0.2, 0.1, 0.0, 0.4])
+    beta, nt, dt, ntau = 3.0, 4, 0.25, 31
+    dtau = beta / (ntau - 1)
+    for fn in (necpt.free_greens_l(h_ini, _chain_h(5), beta, nt, dt, ntau, dtau),
+               necpt.bath_greens_l(h_ini, nt, dt, ntau, dtau, beta)):
+        for b in range(nt):
+            np.testing.assert_allclose(fn["lesser"][0, b], -fn["mixed_left"][ntau - 1, b], atol=1e-13)
+        for j in range(ntau):
+            np.testing.assert_allclose(fn["mixed"][0, j], -fn["vert_greater"][ntau - 1 - j], atol=1e-13)
+
+
+def test_bath_l_matches_free_functions():
+    """Eqs. (gb1), (gb2) on the L-shaped contour (eigenbasis of T) equal the
+    free-fermion functions of the unquenched bath (matrix exponentials),
+    at finite beta and at beta -> infinity."""
+    T = _chain_h(7, 1.0)
+    for beta in (4.0, np.inf):
+        nt, dt, ntau, dtau = 5, 0.2, 21, 0.2
+        a = necpt.bath_greens_l(T, nt, dt, ntau, dtau, beta, sites=[0, 1])
+        b = necpt.free_greens_l(T, T, beta, nt, dt, ntau, dtau)
+        for key in a:
+            np.testing.assert_allclose(a[key], b[key][..., :2, :2], atol=1e-12, err_msg=key)
+
+
+def _u0_quench_l(dt, beta=3.0, t_max=1.2, nb=5, V=0.7):
+    """U = 0 cluster (3-site chain, field 0.4 on site 0 switched off at
+    t = 0) linked at site 2 to a 5-site bath chain; everything thermal at
+    beta, with the imaginary branch of length beta on the mesh dt."""
+    nc = 3
+    hc_ini = _chain_h(nc, 1.0, [0.4, 0.0, 0.0])
+    hc = _chain_h(nc, 1.0)
+    Tb = _chain_h(nb, 1.0)
+    nt = int(round(t_max / dt)) + 1
+    ntau = int(round(beta / dt)) + 1
+    Gc = necpt.free_greens_l(hc_ini, hc, beta, nt, dt, ntau, dt)
+    Gb = necpt.bath_greens_l(Tb, nt, dt, ntau, dt, beta, sites=[0])
+    got = necpt.necpt_l(Gc, Gb, 2, V, dt, dt)
+    # the connected system, exactly: bond -V between cluster site 2 and bath site 0
+    n = nc + nb
+    def full(hcl):
+        h = np.zeros((n, n))
+        h[:nc, :nc] = hcl
+        h[nc:, nc:] = Tb
+        h[2, nc] = h[nc, 2] = -V
+        return h
+    ref = necpt.free_greens_l(full(hc_ini), full(hc), beta, nt, dt, ntau, dt)
+    return got, ref, nc
+
+
+def test_lcontour_cpt_exact_at_u0_second_order():
+    """At U = 0 the CPT equation on the L-shaped contour is exact: the
+    discretised solution converges to the connected system's functions
+    (prepared in its own thermal state by the imaginary branch) at second
+    order in the mesh step, the t = 0 densities included."""
+    errs = []
+    for dt in (0.2, 0.1):
+        got, ref, nc = _u0_quench_l(dt)
+        e = max(np.abs(got[k] - ref[k][..., :nc, :nc]).max() for k in ref)
+        errs.append(e)
+    assert errs[1] < 5e-3, errs
+    ratio = errs[0] / errs[1]
+    assert 3.3 < ratio < 4.8, (errs, ratio)
+    # initial densities: the connected equilibrium, not the isolated cluster's
+    got, ref, nc = _u0_quench_l(0.1)
+    n_got = np.real(-1j * np.diag(got["lesser"][0, 0]))
+    n_ref = np.real(-1j * np.diag(ref["lesser"][0, 0][:nc, :nc]))
+    hc_ini = _chain_h(nc, 1.0, [0.4, 0.0, 0.0])
+    n_iso = np.real(np.diag(necpt.free_greens_l(hc_ini, hc_ini, 3.0, 1, 0.1, 2, 0.1)["lesser"][0, 0] * -1j))
+    assert np.abs(n_got - n_ref).max() < 1e-4
+    assert np.abs(n_ref - n_iso).max() > 3e-3
+
+
+def test_lcontour_reduces_to_keldysh_without_imaginary_branch_coupling():
+    """V = 0: the solution is G' itself on every component."""
+    got, _, nc = _u0_quench_l(0.2, V=0.0)
+    hc_ini = _chain_h(nc, 1.0, [0.4, 0.0, 0.0])
+    nt, ntau = got["lesser"].shape[0], got["vert_greater"].shape[0]
+    Gc = necpt.free_greens_l(hc_ini, _chain_h(nc), 3.0, nt, 0.2, ntau, 0.2)
+    for key in got:
+        np.testing.assert_allclose(got[key], Gc[key], atol=1e-12, err_msg=key)
+
+
+def test_four_step_cluster_components_at_u0_are_free_fermions():
+    """The contour components the L-shaped CPT takes from the four-step
+    (G^<, G^>, G^M(+-tau), both mixed functions) equal, at U = 0, the
+    zero-temperature free-fermion functions of the one-particle Hamiltonian
+    (H_ini on the imaginary branch, H on the real ones): the conventions of
+    sign, order and branch of cluster_fn."""
+    L = 4
+    H = wl.chain_siam(L, 0.0, 1.0)
+    Hi = H.with_field(0, 0.2)
+    sec = basis.Sector(L, 2, 2)
+    orbs = [(i, 0) for i in range(L)]
+    nt, dtg, ntau, dtau = 5, 0.2, 6, 0.3
+    out = greens.four_step(Hi, H, 2, 2, orbs, nt, dtg, 2, 15, wl.start_vector(sec.dim, 7), gs_tol=1e-13,
+                           ntau=ntau, dtau_grid=dtau, tau_steps_per_grid=3)
+
+    def one_particle(M):
+        h = np.diag(np.asarray(M.eps_up, float))
+        for (i, j), t in zip(M.bonds, M.t):
+            h[i, j] -= t
+            h[j, i] -= t
+        return h
+    e = np.linalg.eigvalsh(one_particle(Hi))
+    assert (e < 0).sum() == 2 and np.abs(e).min() > 0.1          # two occupied levels, no zero level
+    ref = necpt.free_greens_l(one_particle(Hi), one_particle(H), np.inf, nt, dtg, ntau, dtau)
+    got = necpt.cluster_fn(out)
+    for key in ref:
+        assert np.abs(got[key] - ref[key]).max() < 1e-10, key
