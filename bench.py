@@ -500,7 +500,9 @@ def necpt_bench(a):
     cluster G^<, G^> of all six sites for both spins, bath functions, and the
     CPT equation on the Keldysh contour per spin (1002 contour points, 6012
     right-hand sides).  Reports the time of each part, the kernel split of the
-    contour solve and the net polarisation of the first four sites."""
+    contour solve and the net polarisation of the first four sites; then the
+    same with the imaginary branch (beta = 15, dtau = 0.02: 751 more contour
+    points), through which the connected system's initial state enters."""
     import numpy as np
     import torch
     import paper_1109_1205_amd as kgf
@@ -543,6 +545,39 @@ def necpt_bench(a):
     m_cpt = (dens[0] - dens[1])[:, :4].sum(axis=1)
     m_iso = (iso[0] - iso[1])[:, :4].sum(axis=1)
     marks = [0, 100, 200, 300, 400, 500]
+    # the same with the imaginary branch (beta = 15, dtau = 0.02): the
+    # connected system's initial state enters through the CPT equation
+    beta, dtau = 15.0, 0.02
+    ntau = int(round(beta / dtau)) + 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outm = ctx.greens_neq(ctx.model(Hi), ctx.model(H), s, v0, orbs, nt=nt, steps_per_grid=1, dt=dt, krylov_dim=15,
+                          reorth=2, gs_tol=1e-13, ntau=ntau, tau_steps_per_grid=1, dtau=dtau)
+    t_fsm = time.perf_counter() - t0
+    log(f"necpt: cluster four-step with the Matsubara branch ({ntau} tau points) {t_fsm:.2f} s")
+    t0 = time.perf_counter()
+    gb = ctx.bath_chain_contour(Lb, 1.0, nt, dt, ntau, dtau, beta)
+    torch.cuda.synchronize()
+    t_bathm = time.perf_counter() - t0
+    densm, t_cptm = [], []
+    for sp in (0, 1):
+        idx = [k for k, (_, q) in enumerate(orbs) if q == sp]
+        sel = lambda x: np.ascontiguousarray(x[..., idx, :][..., idx])
+        gc = {"lesser": sel(outm["G_lesser"]), "greater": sel(outm["G_greater"]), "mixed": sel(outm["G_mixed"]),
+              "mixed_left": sel(outm["G_mixed_left"]), "vert_greater": 1j * sel(outm["G_matsubara"][0]),
+              "vert_lesser": 1j * sel(outm["G_matsubara"][1])}
+        gcd = {k: torch.from_numpy(v).to("cuda:0") for k, v in gc.items()}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.necpt_contour(gcd, gb, Lc - 1, V, dt, dtau)
+        torch.cuda.synchronize()
+        t_cptm.append(time.perf_counter() - t0)
+        log(f"necpt: contour solve with the Matsubara branch, spin {sp}: {t_cptm[-1]:.3f} s")
+        densm.append(np.real(-1j * np.einsum("aaii->ai", res["G_lesser"].cpu().numpy())))
+        del gcd, res
+        torch.cuda.empty_cache()
+    m_m = (densm[0] - densm[1])[:, :4].sum(axis=1)
+    m1 = densm[0][:, 0] - densm[1][:, 0]
     kern = {k: {"launches": v["launches"], "total_ms": round(v["sampled_ms"], 2)} for k, v in sorted(stats.items())}
     n, m = 2 * nt, 2 * nt * Lc
     gemm_flops = 8.0 * (n * n * n + n * n * m + m * m * n)     # 1 - P K, K X, R (K X)
@@ -553,9 +588,17 @@ def necpt_bench(a):
                       "kernels": kern,
                       "zgemm_TFLOPs": (round(gemm_flops / (zg["sampled_ms"] / 2 * 1e-3) / 1e12, 2)
                                        if zg["sampled_ms"] else None),
-                      "net_moment_sites_1_4": {f"t={dt * k:g}": [round(float(m_cpt[k]), 5), round(float(m_iso[k]), 5)]
+                      "net_moment_sites_1_4": {f"t={dt * k:g}": [round(float(m_cpt[k]), 5), round(float(m_iso[k]), 5),
+                                                                 round(float(m_m[k]), 5)]
                                                for k in marks},
-                      "moment_columns": ["NE-CPT", "isolated cluster"]}), flush=True)
+                      "moment_columns": ["NE-CPT (Keldysh contour, disconnected initial state)", "isolated cluster",
+                                         "NE-CPT with the Matsubara branch (beta = 15)"],
+                      "matsubara_branch": {"beta": beta, "dtau": dtau, "ntau": ntau, "contour_points": 2 * nt + ntau,
+                                           "rhs": (2 * nt + ntau) * Lc, "cluster_four_step_s": round(t_fsm, 3),
+                                           "bath_s": round(t_bathm, 4),
+                                           "contour_solve_s": [round(x, 4) for x in t_cptm],
+                                           "impurity_moment_m1": {f"t={dt * k:g}": round(float(m1[k]), 5)
+                                                                  for k in marks}}}), flush=True)
 
 
 def two_particle(a):

@@ -337,6 +337,48 @@ int  kgf_necpt(kgf_ctx* ctx, int nt, int n_c, int boundary, double dt, double V,
                const kgf_c128* Gc_lesser, const kgf_c128* Gc_greater, const kgf_c128* Gb_lesser,
                const kgf_c128* Gb_greater, kgf_c128* G_lesser, kgf_c128* G_greater);
 
+/* ---- NE-CPT on the Keldysh-Matsubara contour (Sec. 5, Eq. (cpteq)) ----------
+ * The contour 0 -> t_max -> 0 -> -i beta: nt real mesh points t_k = k dt on
+ * each real branch, then ntau >= 2 points z = -i tau_j, tau_j = j dtau,
+ * (ntau-1) dtau = beta, later than both real branches.  The hopping V acts on
+ * every branch, so the connected system's initial state is its equilibrium
+ * state at beta, built by the CPT equation itself (Sec. 5 treats the initial
+ * state by CPT through a Matsubara branch).  The imaginary branch enters the
+ * contour integral with the weight -i dtau (trapezoid, halved at its ends)
+ * and the equal-point rules of kgf_necpt; second order in dt and dtau.
+ * A contour function is passed by its components (device, complex128, over
+ * the orbitals [..][n][n]; n = n_c for the cluster, 1 for the bath's site 1):
+ *   lesser, greater [nt][nt] = G^<, G^>(t_a, t_b);
+ *   mixed [nt][ntau] = G^<(t_a, -i tau_j) (kgf_greens_neq's G_mixed);
+ *   mixed_left [ntau][nt] = G^>(-i tau_j, t_b) (G_mixed_left);
+ *   vert_greater [ntau] = G^>(-i tau_d, -i 0) = i G^M(+tau_d);
+ *   vert_lesser [ntau] = G^<(-i 0, -i tau_d) = i G^M(-tau_d).
+ * The members are read only by kgf_necpt_contour.
+ * kgf_bath_chain_contour: Eqs. (gb1), (gb2) on complex contour times for
+ * site 1 of an L_b-site chain (hopping -T_b, no quench) at inverse
+ * temperature beta (INFINITY: the ground state), written to every member of
+ * *out (n = 1; caller-owned device memory).
+ * kgf_necpt_contour: the cluster block of G = (G'^-1 - V)^-1 for a cluster
+ * linked at site `boundary` by V to bath site 1 (bath eliminated: Sigma =
+ * V^2 G^b_11 on `boundary`).  Outputs (device, caller-owned): G_lesser,
+ * G_greater [nt][nt][n_c][n_c]; G_mixed [nt][ntau][n_c][n_c] and
+ * G_mixed_left [ntau][nt][n_c][n_c] or NULL.  Workspace
+ * ~16 ((2 nt + ntau) n_c)^2 bytes.  KGF_EUNSUPPORTED if (2 nt + ntau) n_c >
+ * 65536, KGF_EINVAL for a singular contour matrix or an incomplete function. */
+typedef struct {
+    kgf_c128* lesser;
+    kgf_c128* greater;
+    kgf_c128* mixed;
+    kgf_c128* mixed_left;
+    kgf_c128* vert_greater;
+    kgf_c128* vert_lesser;
+} kgf_contour_fn;
+int  kgf_bath_chain_contour(kgf_ctx* ctx, int L_b, double T_b, double beta, int nt, double dt, int ntau,
+                            double dtau, const kgf_contour_fn* out);
+int  kgf_necpt_contour(kgf_ctx* ctx, int nt, int ntau, int n_c, int boundary, double dt, double dtau, double V,
+                       const kgf_contour_fn* Gc, const kgf_contour_fn* Gb, kgf_c128* G_lesser,
+                       kgf_c128* G_greater, kgf_c128* G_mixed, kgf_c128* G_mixed_left);
+
 /* ---- equilibrium spectra (Sec. 2, Sec. 3) ----------------------------------
  * kgf_greens_omega: the conventional Lanczos Green's function of Eq. (gapprox)
  * for orbital a (site*2+spin) from the ground state psi0 (device, in `sector`)
@@ -382,19 +424,21 @@ int  kgf_fourier(kgf_ctx* ctx, const kgf_c128* host_G, int nt, double dt, double
  * Optional zero-temperature Matsubara branch (ntau > 0) with H_ini:
  *   G^M_{ab}(+tau_j) = -<c+_a 0|e^{-(H_ini-E0)tau_j}|c+_b 0>,
  *   G^M_{ab}(-tau_j) = +<c_b 0|e^{-(H_ini-E0)tau_j}|c_a 0>,
- *   G^|_{ab}(t_k, tau_j) = i <e^{-(H_ini-E0)tau_j} c_b 0 | Psi_a(t_k)>,
+ *   G^|_{ab}(t_k, tau_j) = i <e^{-(H_ini-E0)tau_j} c_b 0 | Psi_a(t_k)>   (= G^<(t_k, -i tau_j)),
+ *   G^|_{ab}(tau_j, t_k) = -i <e^{-(H_ini-E0)tau_j} c+_a 0 | chi_b(t_k)>  (= G^>(-i tau_j, t_k)),
  *   tau_j = j * tau_steps_per_grid * dtau.
  * Outputs (host): G_lesser, G_greater [nt][nt][n_orb][n_orb] indexed (t, t');
  * G_matsubara [2][ntau][n_orb][n_orb] (+tau, -tau) or NULL; G_mixed
- * [nt][ntau][n_orb][n_orb] or NULL; *host_E0.  If host_psi0_out is not NULL
- * the device pointer psi0_out (D) receives |0>. */
+ * [nt][ntau][n_orb][n_orb] (t, tau) or NULL; G_mixed_left [ntau][nt][n_orb][n_orb]
+ * (tau, t) or NULL; *host_E0.  If host_psi0_out is not NULL the device pointer
+ * psi0_out (D) receives |0>. */
 int  kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H,
                     const kgf_sector* sector, const kgf_gs_opts* gs_opts, const kgf_c128* v0,
                     const int32_t* host_orbs, int n_orb, int nt, int steps_per_grid,
                     const kgf_prop_opts* opts, int schedule, int batch,
                     int ntau, int tau_steps_per_grid, double dtau,
                     kgf_c128* host_G_lesser, kgf_c128* host_G_greater,
-                    kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
+                    kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed, kgf_c128* host_G_mixed_left,
                     double* host_E0, kgf_c128* psi0_out);
 
 /* ---- step-wise four-step run (Sec. 4, sweep schedule) ------------------------

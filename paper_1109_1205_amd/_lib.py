@@ -41,6 +41,15 @@ class _ModelDesc(C.Structure):
                 ("eps_dn", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double))]
 
 
+class _ContourFn(C.Structure):
+    """kgf_contour_fn: device pointers of the components of a contour function."""
+    _fields_ = [("lesser", C.c_void_p), ("greater", C.c_void_p), ("mixed", C.c_void_p), ("mixed_left", C.c_void_p),
+                ("vert_greater", C.c_void_p), ("vert_lesser", C.c_void_p)]
+
+
+CONTOUR_KEYS = ("lesser", "greater", "mixed", "mixed_left", "vert_greater", "vert_lesser")
+
+
 class _GsOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("reorth", C.c_int),
                 ("unique_check", C.c_int), ("unique_tol", C.c_double), ("unique_seed", C.c_uint64)]
@@ -106,6 +115,9 @@ def load_library():
                                 C.POINTER(D)]),
         "kgf_bath_chain": (I, [P, I, D, D, I, D, P, P]),
         "kgf_necpt": (I, [P, I, I, I, D, D, P, P, P, P, P, P]),
+        "kgf_bath_chain_contour": (I, [P, I, D, D, I, D, I, D, C.POINTER(_ContourFn)]),
+        "kgf_necpt_contour": (I, [P, I, I, I, I, D, D, D, C.POINTER(_ContourFn), C.POINTER(_ContourFn), P, P, P,
+                                  P]),
         "kgf_greens_neq_driven": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                       P, P, P, P, C.POINTER(D)]),
         "kgf_sector_create": (I, [P, I, I, I, C.POINTER(P)]),
@@ -122,7 +134,7 @@ def load_library():
         "kgf_model_get_params": (I, [P, P, P, P, P]),
         "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
         "kgf_greens_neq": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
-                               I, I, D, P, P, P, P, C.POINTER(D), P]),
+                               I, I, D, P, P, P, P, P, C.POINTER(D), P]),
         "kgf_neq_run_create": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I,
                                    C.POINTER(P), C.POINTER(D)]),
         "kgf_neq_run_advance": (I, [P, I, C.POINTER(_RunInfo)]),
@@ -160,7 +172,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
-            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_greens2_neq",
+            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_bath_chain_contour", "kgf_necpt_contour", "kgf_greens2_neq",
             "kgf_neq_run_create", "kgf_neq_run_advance", "kgf_neq_run_result", "kgf_neq_run_destroy",
             "kgf_propagate_noalloc", "kgf_model_get_params",
             "kgf_profile_begin",
@@ -555,17 +567,20 @@ class Context:
         Gg = _host_c128((nt, nt, no, no))
         GM = _host_c128((2, ntau, no, no)) if ntau > 0 else None
         Gx = _host_c128((nt, ntau, no, no)) if ntau > 0 else None
+        Gxl = _host_c128((ntau, nt, no, no)) if ntau > 0 else None
         E0 = C.c_double()
         o = _prop(krylov_dim, reorth, dt, DIRECTION_FORWARD, 0.0, breakdown_tol)
         g = _gs(gs_tol, gs_max_iter, gs_check_every, gs_reorth, gs_unique_check)
         _check(_lib.kgf_greens_neq(self.handle, H_ini.handle, H.handle, sec.handle, C.byref(g), _ptr(v0),
                                    _np_ptr(orbs), no, int(nt), int(steps_per_grid), C.byref(o), int(schedule),
                                    int(batch), int(ntau), int(tau_steps_per_grid), float(dtau), _np_ptr(Gl),
-                                   _np_ptr(Gg), _np_ptr(GM), _np_ptr(Gx), C.byref(E0), _ptr(psi0_out)))
+                                   _np_ptr(Gg), _np_ptr(GM), _np_ptr(Gx), _np_ptr(Gxl), C.byref(E0),
+                                   _ptr(psi0_out)))
         out = {"G_lesser": Gl, "G_greater": Gg, "E0": E0.value}
         if ntau > 0:
             out["G_matsubara"] = GM
             out["G_mixed"] = Gx
+            out["G_mixed_left"] = Gxl
         return out
 
     def neq_run(self, H_ini: Model, H: Model, sec: Sector, v0, orbitals: Sequence[Tuple[int, int]], nt: int,
@@ -660,6 +675,56 @@ class Context:
         _check(_lib.kgf_necpt(self.handle, nt, n_c, int(boundary), float(dt), float(V), _ptr(Gc_lesser),
                               _ptr(Gc_greater), _ptr(Gb_lesser), _ptr(Gb_greater), _ptr(Gl), _ptr(Gg)))
         return Gl, Gg
+
+    def _contour_fn(self, fn: dict, nt: int, ntau: int, n: int):
+        import torch
+        shapes = {"lesser": (nt, nt), "greater": (nt, nt), "mixed": (nt, ntau), "mixed_left": (ntau, nt),
+                  "vert_greater": (ntau,), "vert_lesser": (ntau,)}
+        for k in CONTOUR_KEYS:
+            x = fn[k]
+            shp = shapes[k] + ((n, n) if n > 1 else ())
+            if (tuple(x.shape) != shp or x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous()
+                    or x.device.index != self.device):
+                raise ValueError(f"contour function: {k} must be a contiguous complex128 tensor of shape {shp} "
+                                 f"on cuda:{self.device}")
+        return _ContourFn(*[_ptr(fn[k]) for k in CONTOUR_KEYS])
+
+    def bath_chain_contour(self, L_b: int, T_b: float, nt: int, dt: float, ntau: int, dtau: float,
+                           beta: float = float("inf")):
+        """kgf_bath_chain_contour: the components (device tensors; keys
+        CONTOUR_KEYS) of the first site of an L_b-site chain on the contour with
+        an imaginary branch of ntau points dtau apart."""
+        import torch
+        dev = f"cuda:{self.device}"
+        out = {"lesser": torch.empty((nt, nt), dtype=torch.complex128, device=dev),
+               "greater": torch.empty((nt, nt), dtype=torch.complex128, device=dev),
+               "mixed": torch.empty((nt, ntau), dtype=torch.complex128, device=dev),
+               "mixed_left": torch.empty((ntau, nt), dtype=torch.complex128, device=dev),
+               "vert_greater": torch.empty((ntau,), dtype=torch.complex128, device=dev),
+               "vert_lesser": torch.empty((ntau,), dtype=torch.complex128, device=dev)}
+        f = self._contour_fn(out, nt, ntau, 1)
+        _check(_lib.kgf_bath_chain_contour(self.handle, int(L_b), float(T_b), float(beta), int(nt), float(dt),
+                                           int(ntau), float(dtau), C.byref(f)))
+        return out
+
+    def necpt_contour(self, Gc: dict, Gb: dict, boundary: int, V: float, dt: float, dtau: float):
+        """kgf_necpt_contour: cluster block of the CPT equation on the contour
+        with its imaginary branch; Gc, Gb: components (CONTOUR_KEYS) as
+        contiguous complex128 device tensors (cluster [..., n_c, n_c], bath
+        site 1 [...]).  Returns G_lesser, G_greater, G_mixed, G_mixed_left."""
+        import torch
+        nt, n_c = int(Gc["lesser"].shape[0]), int(Gc["lesser"].shape[2])
+        ntau = int(Gc["vert_greater"].shape[0])
+        fc = self._contour_fn(Gc, nt, ntau, n_c)
+        fb = self._contour_fn(Gb, nt, ntau, 1)
+        dev = Gc["lesser"].device
+        out = {"G_lesser": torch.empty_like(Gc["lesser"]), "G_greater": torch.empty_like(Gc["lesser"]),
+               "G_mixed": torch.empty((nt, ntau, n_c, n_c), dtype=torch.complex128, device=dev),
+               "G_mixed_left": torch.empty((ntau, nt, n_c, n_c), dtype=torch.complex128, device=dev)}
+        _check(_lib.kgf_necpt_contour(self.handle, nt, ntau, n_c, int(boundary), float(dt), float(dtau), float(V),
+                                      C.byref(fc), C.byref(fb), _ptr(out["G_lesser"]), _ptr(out["G_greater"]),
+                                      _ptr(out["G_mixed"]), _ptr(out["G_mixed_left"])))
+        return out
 
     # -- equilibrium spectra --------------------------------------------------
     def greens_omega(self, model: Model, sec: Sector, psi0, E0: float, orbital: Tuple[int, int], n_lanczos: int,

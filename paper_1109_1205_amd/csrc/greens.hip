@@ -158,6 +158,23 @@ void store_mixed(kgf_ctx* ctx, const double2* rawm, const std::vector<int>& loc,
         }
 }
 
+// left mixed component: rawm[(b * ntau + jt) * (na * nt) + a * nt + k] = <P_b(tau_jt) | chi_a(t_k)>
+// -> Gmixl[jt][k][A = b][B = a] = -i rawm
+void store_mixed_left(kgf_ctx* ctx, const double2* rawm, const std::vector<int>& loc, int nt, int ntau, int norb,
+                      double2* Gmixl) {
+    const int na = (int)loc.size();
+    for (int b = 0; b < na; ++b)
+        for (int a = 0; a < na; ++a) {
+            Map4 m2;
+            m2.n[0] = 1; m2.n[1] = ntau; m2.n[2] = 1; m2.n[3] = nt;
+            m2.is[0] = 0; m2.is[1] = (int64_t)na * nt; m2.is[2] = 0; m2.is[3] = 1;
+            m2.os[0] = 0; m2.os[1] = (int64_t)nt * norb * norb; m2.os[2] = 0; m2.os[3] = (int64_t)norb * norb;
+            const double2* in = rawm + (int64_t)b * ntau * na * nt + (int64_t)a * nt;
+            double2* out = Gmixl + (int64_t)loc[b] * norb + loc[a];
+            scatter4(ctx, in, out, m2, 0.0, -1.0, false);
+        }
+}
+
 std::unique_ptr<kgf_sector> make_sector(kgf_ctx* ctx, int L, int nu, int nd) {
     if (nu < 0 || nu > L || nd < 0 || nd > L) return nullptr;
     std::unique_ptr<kgf_sector> s(new kgf_sector());
@@ -308,7 +325,9 @@ struct SweepBranch {
     SilOpts so;
     DevBuf gidx;
     double2 *raw = nullptr, *rawm = nullptr, *S = nullptr, *Lb = nullptr, *tmp = nullptr;
-    const double2* hole = nullptr;   // mixed component: hole states on the tau mesh (or null)
+    // mixed component: states on the tau mesh (or null) -- e^{-(H_ini-E0) tau} c_b |0> for the c
+    // sweep (G^|(t, tau)), e^{-(H_ini-E0) tau} c+_b |0> for the c+ sweep (G^|(tau, t))
+    const double2* hole = nullptr;
     int jchunk = 1, jhi = -1, jlo = 0, s = 0, ncur = 0;
     bool in_chunk = false;
     int64_t ss = 0, sb = 0, sa = 0, sj = 1;
@@ -426,16 +445,21 @@ struct SweepBranch {
         hipLaunchKernelGGL(k_store_neq, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(kThreads),
                            0, ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), A->norb, dagger, 1, Gdev);
         check_launch("k_store_neq");
-        if (hole && Gmix_dev) store_mixed(ctx, rawm, loc, nt, A->ntau, A->norb, Gmix_dev);
+        if (hole && Gmix_dev) {
+            if (dagger) store_mixed_left(ctx, rawm, loc, nt, A->ntau, A->norb, Gmix_dev);
+            else store_mixed(ctx, rawm, loc, nt, A->ntau, A->norb, Gmix_dev);
+        }
     }
 };
 
-// step (iii)+(iv) for one spin group and one operator (c or c+);
-// also the mixed component when `mixed_dev` is given (lesser only).
+// step (iii)+(iv) for one spin group and one operator (c or c+); also a
+// mixed component when `Gmix_dev` is given: G^|(t, tau) from the c sweep
+// with the hole states, G^|(tau, t) from the c+ sweep with the particle
+// states (`tau_states`, on the tau mesh).
 static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& loc, int spin, int dagger,
-                       PhiMesh& Phi, double2* Gdev, const double2* hole_states, const kgf_sector* hole_sec,
-                       double2* Gmix_dev) {
-    const bool want_mixed = (Gmix_dev != nullptr && !dagger && A.ntau > 0 && hole_states);
+                       PhiMesh& Phi, double2* Gdev, const double2* tau_states, double2* Gmix_dev) {
+    const bool want_mixed = (Gmix_dev != nullptr && A.ntau > 0 && tau_states);
+    const double2* hole_states = tau_states;
     if (A.schedule == 1) {
         SweepBranch br;
         if (!br.begin(ctx, A, loc, spin, dagger, want_mixed ? hole_states : nullptr)) return;
@@ -482,9 +506,10 @@ static void neq_branch(kgf_ctx* ctx, const NeqArgs& A, const std::vector<int>& l
                            ctx->stream, raw, ss, sb, sa, sj, nt, na, gidx.as<int>(), A.norb, dagger, 0, Gdev);
         check_launch("k_store_neq");
         if (want_mixed) {
-            // rawm[(b, jt)][(a, k)] = <hole_b(tau_jt) | Psi_a(t_k)>
+            // rawm[(b, jt)][(a, k)] = <state_b(tau_jt) | Psi_a(t_k)> (chi_a(t_k) for c+)
             block_dots(ctx, hole_states, Dt, na * A.ntau, Psi, Dt, na * nt, Dt, rawm, (int64_t)na * nt);
-            store_mixed(ctx, rawm, loc, nt, A.ntau, A.norb, Gmix_dev);
+            if (dagger) store_mixed_left(ctx, rawm, loc, nt, A.ntau, A.norb, Gmix_dev);
+            else store_mixed(ctx, rawm, loc, nt, A.ntau, A.norb, Gmix_dev);
         }
         sync(ctx);
         release(ctx, "neq_psi");
@@ -563,7 +588,8 @@ static double2* neq_forward(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, c
 }
 
 void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_opts* gso, double* E0_out,
-                double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host) {
+                double2* psi0_out, double2* Gl_host, double2* Gg_host, double2* GM_host, double2* Gmix_host,
+                double2* Gmixl_host) {
     TraceRange range_("kgf four-step");
     const kgf_sector* sec = A.sec;
     const int64_t D = sec->dim();
@@ -576,13 +602,15 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
     double2* Gg = static_cast<double2*>(workspace(ctx, "neq_Gg", gsz));
     KGF_HIP(hipMemsetAsync(Gl, 0, gsz, ctx->stream));
     KGF_HIP(hipMemsetAsync(Gg, 0, gsz, ctx->stream));
-    const bool matsubara = A.ntau > 0 && (GM_host || Gmix_host);
+    const bool matsubara = A.ntau > 0 && (GM_host || Gmix_host || Gmixl_host);
     const size_t gmsz = sizeof(double2) * 2 * (size_t)std::max(A.ntau, 1) * norb * norb;
     const size_t gxsz = sizeof(double2) * (size_t)nt * std::max(A.ntau, 1) * norb * norb;
     double2* GM = static_cast<double2*>(workspace(ctx, "neq_GM", gmsz));
     double2* Gx = static_cast<double2*>(workspace(ctx, "neq_Gx", gxsz));
+    double2* Gxl = static_cast<double2*>(workspace(ctx, "neq_Gxl", gxsz));
     KGF_HIP(hipMemsetAsync(GM, 0, gmsz, ctx->stream));
     KGF_HIP(hipMemsetAsync(Gx, 0, gxsz, ctx->stream));
+    KGF_HIP(hipMemsetAsync(Gxl, 0, gxsz, ctx->stream));
     SilOpts io = A.o;
     io.direction = 0;
     io.shift = E0;
@@ -594,8 +622,8 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
         const int na = (int)loc.size();
         if (!na) continue;
         // Matsubara branch with H_ini: particle (c+) and hole (c) states on the tau mesh
-        std::unique_ptr<kgf_sector> hole_sec;
         double2* hole = nullptr;
+        double2* particle = nullptr;
         if (matsubara) {
             for (int part = 0; part < 2; ++part) {   // part 0: particle (c+), 1: hole (c)
                 auto ts = shifted(ctx, sec, spin, part == 0 ? +1 : -1);
@@ -634,15 +662,15 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
                         }
                     }
                 sync(ctx);
-                if (part == 1) {
-                    hole = P;
-                    hole_sec = std::move(ts);
-                }
+                (part == 0 ? particle : hole) = P;
             }
         }
-        for (int dagger = 0; dagger < 2; ++dagger)
-            neq_branch(ctx, A, loc, spin, dagger, Phi, dagger ? Gg : Gl, hole, hole_sec.get(),
-                       (matsubara && Gmix_host) ? Gx : nullptr);
+        for (int dagger = 0; dagger < 2; ++dagger) {
+            // G^|(t, tau) from the c sweep, G^|(tau, t) from the c+ sweep
+            double2* mix = nullptr;
+            if (matsubara) mix = dagger ? (Gmixl_host ? Gxl : nullptr) : (Gmix_host ? Gx : nullptr);
+            neq_branch(ctx, A, loc, spin, dagger, Phi, dagger ? Gg : Gl, dagger ? particle : hole, mix);
+        }
         release(ctx, "neq_mats_p");
         release(ctx, "neq_mats_h");
     }
@@ -654,7 +682,11 @@ void greens_neq(kgf_ctx* ctx, const NeqArgs& A, const double2* v0, const kgf_gs_
     if (matsubara && Gmix_host)
         KGF_HIP(hipMemcpyAsync(Gmix_host, Gx, sizeof(double2) * (size_t)nt * A.ntau * norb * norb,
                                hipMemcpyDeviceToHost, ctx->stream));
+    if (matsubara && Gmixl_host)
+        KGF_HIP(hipMemcpyAsync(Gmixl_host, Gxl, sizeof(double2) * (size_t)nt * A.ntau * norb * norb,
+                               hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
+    release(ctx, "neq_Gxl");
     release(ctx, "neq_phi");
     release(ctx, "neq_phiseg");
     release(ctx, "neq_cols");
@@ -1384,7 +1416,7 @@ extern "C" int kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_mo
                               int nt, int steps_per_grid, const kgf_prop_opts* opts, int schedule, int batch,
                               int ntau, int tau_steps_per_grid, double dtau, kgf_c128* host_G_lesser,
                               kgf_c128* host_G_greater, kgf_c128* host_G_matsubara, kgf_c128* host_G_mixed,
-                              double* host_E0, kgf_c128* psi0_out) {
+                              kgf_c128* host_G_mixed_left, double* host_E0, kgf_c128* psi0_out) {
     return kgf::abi_guard([&] {
         KGF_REQUIRE(ctx && H_ini && H && sector && gs_opts && v0 && host_orbs && host_E0, KGF_EINVAL,
                     "kgf_greens_neq: NULL argument");
@@ -1421,7 +1453,7 @@ extern "C" int kgf_greens_neq(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_mo
         greens_neq(ctx, A, reinterpret_cast<const double2*>(v0), gs_opts, host_E0,
                    reinterpret_cast<double2*>(psi0_out), reinterpret_cast<double2*>(host_G_lesser),
                    reinterpret_cast<double2*>(host_G_greater), reinterpret_cast<double2*>(host_G_matsubara),
-                   reinterpret_cast<double2*>(host_G_mixed));
+                   reinterpret_cast<double2*>(host_G_mixed), reinterpret_cast<double2*>(host_G_mixed_left));
     });
 }
 

@@ -18,6 +18,14 @@
 // as G(z'', z') ("rhs": the other way round).  This makes the scheme second
 // order in dt (first order with the mean at the ends as well).  Dense complex
 // FP64 algebra: an LDS-tiled GEMM and a right-looking LU with partial pivoting.
+//
+// With an imaginary branch (Sec. 5: the initial state of the connected
+// system is treated by CPT too, through a Matsubara branch of length beta)
+// the contour gets ntau more points z = -i tau_j, tau_j = j dtau, later than
+// both real branches, with the weight -i dtau (halved at its ends) and the
+// same equal-point rules; a contour function then also takes its mixed
+// components G^<(t, -i tau) (real point earlier), G^>(-i tau, t) and its
+// imaginary-branch functions of tau - tau'.
 #include <cmath>
 #include <vector>
 
@@ -31,40 +39,73 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__device__ __forceinline__ int ctime(int p, int nt) { return p < nt ? p : 2 * nt - 1 - p; }
+// contour point p: branch 0 forward (t_p), 1 backward (t_{2nt-1-p}), 2 imaginary (tau_{p-2nt})
+__device__ __forceinline__ int cbranch(int p, int nt) { return p < nt ? 0 : (p < 2 * nt ? 1 : 2); }
+__device__ __forceinline__ int cindex(int p, int nt) { return p < nt ? p : (p < 2 * nt ? 2 * nt - 1 - p : p - 2 * nt); }
 
-__device__ __forceinline__ double cweight(int p, int nt, double dt) {
-    const int k = ctime(p, nt);
-    double w = (nt > 1) ? ((k == 0 || k == nt - 1) ? 0.5 * dt : dt) : 0.0;
-    return p < nt ? w : -w;
+// quadrature weight: +-dt on the real branches, -i dtau on the imaginary one,
+// halved at the ends of each branch
+__device__ __forceinline__ double2 cweight(int p, int nt, int ntau, double dt, double dtau) {
+    const int b = cbranch(p, nt), k = cindex(p, nt);
+    if (b < 2) {
+        const double w = (nt > 1) ? ((k == 0 || k == nt - 1) ? 0.5 * dt : dt) : 0.0;
+        return make_double2(b == 0 ? w : -w, 0.0);
+    }
+    const double w = (ntau > 1) ? ((k == 0 || k == ntau - 1) ? 0.5 * dtau : dtau) : 0.0;
+    return make_double2(0.0, -w);
 }
 
-// out[p * ldo + q] = s * (weights ? w_p w_q : 1) * G(z_p, z_q), G from the
-// meshes Gl / Gg (element (a, b) at a * sa + b * sb); rhs = 0: row values at
-// the branch ends, 1: right-hand-side values
-__global__ void k_to_contour(const double2* __restrict__ Gl, const double2* __restrict__ Gg, int nt, int64_t sa,
-                             int64_t sb, double s, int weights, int rhs, double dt, double2* __restrict__ out,
-                             int64_t ldo) {
-    const int n = 2 * nt;
+// One orbital pair of a contour function: element pointers and mesh strides
+// (lesser / greater [a][b], mixed [a][j] = G^<(t_a, -i tau_j), mixed_left
+// [j][b] = G^>(-i tau_j, t_b), vertical [d]: G^>(-i tau_{j+d}, -i tau_j) and
+// G^<(-i tau_j, -i tau_{j+d})).  The imaginary parts are null without a
+// Matsubara branch.
+struct CFn {
+    const double2 *l, *g, *mx, *mxl, *vg, *vl;
+    int64_t la, lb, ma, mj, xj, xb, vd;
+};
+
+// out[p * ldo + q] = s * (weights ? w_p w_q : 1) * G(z_p, z_q); rhs = 0: row
+// values at the branch ends, 1: right-hand-side values
+__global__ void k_to_contour(CFn f, int nt, int ntau, double s, int weights, int rhs, double dt, double dtau,
+                             double2* __restrict__ out, int64_t ldo) {
+    const int n = 2 * nt + ntau;
     const int64_t total = (int64_t)n * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int p = (int)(e / n), q = (int)(e % n);
-        const int64_t off = ctime(p, nt) * sa + ctime(q, nt) * sb;
+        const int bp = cbranch(p, nt), bq = cbranch(q, nt);
+        const int a = cindex(p, nt), b = cindex(q, nt);
         double2 v;
-        if (p > q) {
-            v = Gg[off];
-        } else if (p < q) {
-            v = Gl[off];
-        } else if (nt > 1 && (p == 0 || p == nt || p == nt - 1 || p == n - 1)) {
-            const bool start = p == 0 || p == nt;                 // first point of its branch
-            v = (start != (rhs != 0)) ? Gl[off] : Gg[off];
+        if (bp == 2 && bq < 2) {
+            v = f.mxl[a * f.xj + b * f.xb];
+        } else if (bp < 2 && bq == 2) {
+            v = f.mx[a * f.ma + b * f.mj];
         } else {
-            const double2 a = Gg[off], b = Gl[off];
-            v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+            double2 gg, gl;   // the two orderings at (p, q); only the valid one is read
+            if (bp < 2) {
+                const int64_t off = a * f.la + b * f.lb;
+                if (p >= q) gg = f.g[off];
+                if (p <= q) gl = f.l[off];
+            } else {
+                if (a >= b) gg = f.vg[(a - b) * f.vd];
+                if (a <= b) gl = f.vl[(b - a) * f.vd];
+            }
+            const bool real_end = nt > 1 && (p == 0 || p == nt || p == nt - 1 || p == 2 * nt - 1);
+            const bool tau_end = ntau > 1 && (p == 2 * nt || p == n - 1);
+            if (p > q) {
+                v = gg;
+            } else if (p < q) {
+                v = gl;
+            } else if (real_end || tau_end) {
+                const bool start = p == 0 || p == nt || p == 2 * nt;   // first point of its branch
+                v = (start != (rhs != 0)) ? gl : gg;
+            } else {
+                v = make_double2(0.5 * (gg.x + gl.x), 0.5 * (gg.y + gl.y));
+            }
         }
-        double f = s;
-        if (weights) f *= cweight(p, nt, dt) * cweight(q, nt, dt);
-        out[p * ldo + q] = make_double2(f * v.x, f * v.y);
+        double2 fct = make_double2(s, 0.0);
+        if (weights) fct = cmul(fct, cmul(cweight(p, nt, ntau, dt, dtau), cweight(q, nt, ntau, dt, dtau)));
+        out[p * ldo + q] = cmul(fct, v);
     }
 }
 
@@ -271,22 +312,47 @@ bool lu_solve(kgf_ctx* ctx, double2* A, int n, double2* B, int m, double* piv_de
     return true;
 }
 
-// G[a][b][i][j] = Gc[a][b][i][j] + C[(i n + p) * ldc + j n + q] with
+// G[a][b][i][j] = Gc[a][b][i][j] + C[(i N + p) * ldc + j N + q] with
 // (p, q) = (a forward, b backward) for G^< and (a backward, b forward) for G^>
+// (N = 2 nt + ntau contour points; backward point of t_b: 2 nt - 1 - b)
 __global__ void k_extract(const double2* __restrict__ Gcl, const double2* __restrict__ Gcg,
-                          const double2* __restrict__ C, int64_t ldc, int nt, int nc, double2* __restrict__ Gl,
-                          double2* __restrict__ Gg) {
-    const int n = 2 * nt;
+                          const double2* __restrict__ C, int64_t ldc, int nt, int ntau, int nc,
+                          double2* __restrict__ Gl, double2* __restrict__ Gg) {
+    const int N = 2 * nt + ntau;
     const int64_t total = (int64_t)nt * nt * nc * nc;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int j = (int)(e % nc);
         const int i = (int)((e / nc) % nc);
         const int b = (int)((e / ((int64_t)nc * nc)) % nt);
         const int a = (int)(e / ((int64_t)nc * nc * nt));
-        const double2 cl = C[((int64_t)i * n + a) * ldc + (int64_t)j * n + (n - 1 - b)];
-        const double2 cg = C[((int64_t)i * n + (n - 1 - a)) * ldc + (int64_t)j * n + b];
+        const double2 cl = C[((int64_t)i * N + a) * ldc + (int64_t)j * N + (2 * nt - 1 - b)];
+        const double2 cg = C[((int64_t)i * N + (2 * nt - 1 - a)) * ldc + (int64_t)j * N + b];
         Gl[e] = make_double2(Gcl[e].x + cl.x, Gcl[e].y + cl.y);
         Gg[e] = make_double2(Gcg[e].x + cg.x, Gcg[e].y + cg.y);
+    }
+}
+
+// the mixed components: Gmx[a][jt][i][j] (forward t_a, imaginary tau_jt) and
+// Gmxl[jt][b][i][j] (imaginary tau_jt, forward t_b); either output may be null
+__global__ void k_extract_mixed(const double2* __restrict__ Gcmx, const double2* __restrict__ Gcmxl,
+                                const double2* __restrict__ C, int64_t ldc, int nt, int ntau, int nc,
+                                double2* __restrict__ Gmx, double2* __restrict__ Gmxl) {
+    const int N = 2 * nt + ntau;
+    const int64_t total = (int64_t)nt * ntau * nc * nc;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e % nc);
+        const int i = (int)((e / nc) % nc);
+        const int64_t r = e / ((int64_t)nc * nc);
+        if (Gmx) {   // e indexes [a][jt][i][j]
+            const int jt = (int)(r % ntau), a = (int)(r / ntau);
+            const double2 c = C[((int64_t)i * N + a) * ldc + (int64_t)j * N + 2 * nt + jt];
+            Gmx[e] = make_double2(Gcmx[e].x + c.x, Gcmx[e].y + c.y);
+        }
+        if (Gmxl) {  // e indexes [jt][b][i][j]
+            const int b = (int)(r % nt), jt = (int)(r / nt);
+            const double2 c = C[((int64_t)i * N + 2 * nt + jt) * ldc + (int64_t)j * N + b];
+            Gmxl[e] = make_double2(Gcmxl[e].x + c.x, Gcmxl[e].y + c.y);
+        }
     }
 }
 
@@ -335,6 +401,151 @@ __global__ void k_expand_diff(const double2* __restrict__ gl_d, const double2* _
     }
 }
 
+// f(e) e^{e x} and (1 - f(e)) e^{-e x} for 0 <= x <= beta without overflow
+// (beta = inf: occupation 1, 1/2, 0 for a negative, zero, positive level)
+__device__ __forceinline__ double fermi_exp(double e, double x, double beta, bool zero) {
+    if (isinf(beta)) return zero ? 0.5 : (e < 0.0 ? exp(e * x) : 0.0);
+    if (e <= 0.0) return exp(e * x) / (exp(beta * e) + 1.0);
+    return exp(-e * (beta - x)) / (1.0 + exp(-beta * e));
+}
+__device__ __forceinline__ double hole_exp(double e, double x, double beta, bool zero) {
+    return fermi_exp(-e, x, beta, zero);
+}
+
+// Eqs. (gb1), (gb2) on complex contour times for site 1 of the chain (levels
+// and weights as k_bath_chain): mixed [a][j] = i sum u2 f e^{e tau_j} e^{-i e t_a},
+// mixed_left [j][b] = -i sum u2 (1-f) e^{-e tau_j} e^{+i e t_b},
+// vertical [d]: G^> = -i sum u2 (1-f) e^{-e tau_d}, G^< = i sum u2 f e^{e tau_d}.
+// One thread per (a, j) of the nt x ntau mesh (a < nt also writes mixed_left
+// [j][a]); threads with a == nt write the vertical functions at d = j.
+__global__ void k_bath_chain_tau(int Lb, double Tb, double beta, int nt, double dt, int ntau, double dtau,
+                                 double2* __restrict__ mx, double2* __restrict__ mxl, double2* __restrict__ vg,
+                                 double2* __restrict__ vl) {
+    const int64_t total = (int64_t)(nt + 1) * ntau;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / ntau), j = (int)(e % ntau);
+        const double tau = j * dtau;
+        double mr = 0.0, mi = 0.0, xr = 0.0, xi = 0.0;   // mixed, mixed_left (or vertical G^>, G^<)
+        for (int k = 1; k <= Lb; ++k) {
+            const double th = M_PI * k / (Lb + 1);
+            const double ek = -2.0 * Tb * cos(th);
+            const double sn = sin(th);
+            const double u2 = 2.0 * sn * sn / (Lb + 1);
+            const bool zero = fabs(ek) <= 1e-12 * fmax(1.0, 2.0 * fabs(Tb));
+            const double fe = u2 * fermi_exp(ek, tau, beta, zero);
+            const double he = u2 * hole_exp(ek, tau, beta, zero);
+            if (a < nt) {
+                double sa, ca;
+                sincos(ek * a * dt, &sa, &ca);   // e^{-i e t} = ca - i sa
+                // i fe (ca - i sa) = fe (sa + i ca);  -i he (ca + i sa) = he (sa - i ca)
+                mr += fe * sa;
+                mi += fe * ca;
+                xr += he * sa;
+                xi -= he * ca;
+            } else {
+                xi -= he;   // vertical G^>: -i he
+                mi += fe;   // vertical G^<: +i fe
+            }
+        }
+        if (a < nt) {
+            mx[(int64_t)a * ntau + j] = make_double2(mr, mi);
+            mxl[(int64_t)j * nt + a] = make_double2(xr, xi);
+        } else {
+            vg[j] = make_double2(0.0, xi);
+            vl[j] = make_double2(0.0, mi);
+        }
+    }
+}
+
+// The cluster block of the CPT equation on the contour of nt real and ntau
+// imaginary mesh points (ntau = 0: the Keldysh contour alone), bath
+// eliminated; see the file comment.  Gc: the cluster's components
+// [..][n_c][n_c]; Gb: the bath's site-1 components.  Outputs G^<, G^>
+// [nt][nt][n_c][n_c] and, when given, the mixed components.
+struct CompPtrs {
+    const double2 *l, *g, *mx, *mxl, *vg, *vl;
+};
+
+void necpt_solve(kgf_ctx* ctx, int nt, int ntau, int n_c, int boundary, double dt, double dtau, double V,
+                 const CompPtrs& gc, const CompPtrs& gb, double2* G_lesser, double2* G_greater, double2* G_mixed,
+                 double2* G_mixed_left) {
+    const int n = 2 * nt + ntau, m = n * n_c;
+    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+    ensure_device_fits(sizeof(double2) * (3 * nn + 3 * nm + (size_t)m * m), "NE-CPT contour matrices");
+    auto buf = [&](const char* name, size_t elems) {
+        return static_cast<double2*>(workspace(ctx, name, sizeof(double2) * elems));
+    };
+    double2* P = buf("cpt_P", nn);     // G^c_bb on the contour
+    double2* K = buf("cpt_K", nn);     // w Sigma w
+    double2* A = buf("cpt_A", nn);     // 1 - P K
+    double2* X = buf("cpt_X", nm);     // G^c_bj -> X_j (columns j n + q)
+    double2* Y = buf("cpt_Y", nm);     // K X
+    double2* R = buf("cpt_R", nm);     // G^c_ib stacked by rows (i n + p)
+    double2* C = buf("cpt_C", (size_t)m * m);
+    double* piv = static_cast<double*>(workspace(ctx, "cpt_piv", sizeof(double) * n));
+    const int64_t q2 = (int64_t)n_c * n_c;
+    auto cluster = [&](int i, int j) {   // orbital pair (i, j) of the cluster components
+        const int64_t o = (int64_t)i * n_c + j;
+        CFn f;
+        f.l = gc.l + o;
+        f.g = gc.g + o;
+        f.mx = gc.mx ? gc.mx + o : nullptr;
+        f.mxl = gc.mxl ? gc.mxl + o : nullptr;
+        f.vg = gc.vg ? gc.vg + o : nullptr;
+        f.vl = gc.vl ? gc.vl + o : nullptr;
+        f.la = (int64_t)nt * q2;
+        f.lb = q2;
+        f.ma = (int64_t)ntau * q2;
+        f.mj = q2;
+        f.xj = (int64_t)nt * q2;
+        f.xb = q2;
+        f.vd = q2;
+        return f;
+    };
+    CFn fb;
+    fb.l = gb.l;
+    fb.g = gb.g;
+    fb.mx = gb.mx;
+    fb.mxl = gb.mxl;
+    fb.vg = gb.vg;
+    fb.vl = gb.vl;
+    fb.la = nt;
+    fb.lb = 1;
+    fb.ma = ntau;
+    fb.mj = 1;
+    fb.xj = nt;
+    fb.xb = 1;
+    fb.vd = 1;
+    const unsigned g = grid_for((int64_t)nn);
+    auto contour = [&](const CFn& f, double s, int wts, int rhs, double2* out, int64_t ldo) {
+        hipLaunchKernelGGL(k_to_contour, dim3(g), dim3(kThreads), 0, ctx->stream, f, nt, ntau, s, wts, rhs, dt, dtau,
+                           out, ldo);
+        check_launch("k_to_contour");
+    };
+    // kernels of the integral (P, K, R): row values; right-hand sides (X): rhs values
+    contour(cluster(boundary, boundary), 1.0, 0, 0, P, n);
+    contour(fb, V * V, 1, 0, K, n);
+    for (int j = 0; j < n_c; ++j) {
+        contour(cluster(boundary, j), 1.0, 0, 1, X + (size_t)j * n, m);
+        contour(cluster(j, boundary), 1.0, 0, 0, R + (size_t)j * nn, n);
+    }
+    hipLaunchKernelGGL(k_identity, dim3(g), dim3(kThreads), 0, ctx->stream, A, n);
+    check_launch("k_identity");
+    zgemm(ctx, n, n, n, make_double2(-1.0, 0.0), P, n, K, n, make_double2(1.0, 0.0), A, n);
+    KGF_REQUIRE(lu_solve(ctx, A, n, X, m, piv), KGF_EINVAL, "NE-CPT: singular contour matrix 1 - G^c_bb K");
+    zgemm(ctx, n, m, n, make_double2(1.0, 0.0), K, n, X, m, make_double2(0.0, 0.0), Y, m);
+    zgemm(ctx, m, m, n, make_double2(1.0, 0.0), R, n, Y, m, make_double2(0.0, 0.0), C, m);
+    hipLaunchKernelGGL(k_extract, dim3(grid_for((int64_t)nt * nt * n_c * n_c)), dim3(kThreads), 0, ctx->stream,
+                       gc.l, gc.g, C, (int64_t)m, nt, ntau, n_c, G_lesser, G_greater);
+    check_launch("k_extract");
+    if (ntau > 0 && (G_mixed || G_mixed_left)) {
+        hipLaunchKernelGGL(k_extract_mixed, dim3(grid_for((int64_t)nt * ntau * n_c * n_c)), dim3(kThreads), 0,
+                           ctx->stream, gc.mx, gc.mxl, C, (int64_t)m, nt, ntau, n_c, G_mixed, G_mixed_left);
+        check_launch("k_extract_mixed");
+    }
+    sync(ctx);
+}
+
 }  // namespace
 
 }  // namespace kgf
@@ -372,52 +583,69 @@ extern "C" int kgf_necpt(kgf_ctx* ctx, int nt, int n_c, int boundary, double dt,
         KGF_REQUIRE(std::isfinite(dt) && dt >= 0.0 && std::isfinite(V), KGF_EINVAL, "kgf_necpt: bad dt / V");
         KGF_REQUIRE((int64_t)2 * nt * n_c <= 65536, KGF_EUNSUPPORTED, "kgf_necpt: 2 nt n_c above 65536");
         KGF_HIP(hipSetDevice(ctx->device));
-        const int n = 2 * nt, m = n * n_c;
-        const auto* gcl = reinterpret_cast<const double2*>(Gc_lesser);
-        const auto* gcg = reinterpret_cast<const double2*>(Gc_greater);
-        const auto* gbl = reinterpret_cast<const double2*>(Gb_lesser);
-        const auto* gbg = reinterpret_cast<const double2*>(Gb_greater);
-        const size_t nn = (size_t)n * n, nm = (size_t)n * m;
-        ensure_device_fits(sizeof(double2) * (3 * nn + 3 * nm + (size_t)m * m), "NE-CPT contour matrices");
-        auto buf = [&](const char* name, size_t elems) {
-            return static_cast<double2*>(workspace(ctx, name, sizeof(double2) * elems));
-        };
-        double2* P = buf("cpt_P", nn);     // G^c_bb on the contour
-        double2* K = buf("cpt_K", nn);     // w Sigma w
-        double2* A = buf("cpt_A", nn);     // 1 - P K
-        double2* X = buf("cpt_X", nm);     // G^c_bj -> X_j (columns j n + q)
-        double2* Y = buf("cpt_Y", nm);     // K X
-        double2* R = buf("cpt_R", nm);     // G^c_ib stacked by rows (i n + p)
-        double2* C = buf("cpt_C", (size_t)m * m);
-        double* piv = static_cast<double*>(workspace(ctx, "cpt_piv", sizeof(double) * n));
-        const int64_t sa = (int64_t)nt * n_c * n_c, sb = (int64_t)n_c * n_c;   // mesh strides of [a][b][i][j]
-        const unsigned g = grid_for((int64_t)nn);
-        auto contour = [&](const double2* l, const double2* gg, int64_t sa_, int64_t sb_, double s, int wts,
-                           int rhs, double2* out, int64_t ldo) {
-            hipLaunchKernelGGL(k_to_contour, dim3(g), dim3(kThreads), 0, ctx->stream, l, gg, nt, sa_, sb_, s, wts,
-                               rhs, dt, out, ldo);
-            check_launch("k_to_contour");
-        };
-        // kernels of the integral (P, K, R): row values; right-hand sides (X): rhs values
-        const int64_t bb = (int64_t)boundary * n_c + boundary;
-        contour(gcl + bb, gcg + bb, sa, sb, 1.0, 0, 0, P, n);
-        contour(gbl, gbg, nt, 1, V * V, 1, 0, K, n);
-        for (int j = 0; j < n_c; ++j) {
-            const int64_t bj = (int64_t)boundary * n_c + j, ib = (int64_t)j * n_c + boundary;
-            contour(gcl + bj, gcg + bj, sa, sb, 1.0, 0, 1, X + (size_t)j * n, m);
-            contour(gcl + ib, gcg + ib, sa, sb, 1.0, 0, 0, R + (size_t)j * nn, n);
-        }
-        hipLaunchKernelGGL(k_identity, dim3(g), dim3(kThreads), 0, ctx->stream, A, n);
-        check_launch("k_identity");
-        zgemm(ctx, n, n, n, make_double2(-1.0, 0.0), P, n, K, n, make_double2(1.0, 0.0), A, n);
-        KGF_REQUIRE(lu_solve(ctx, A, n, X, m, piv), KGF_EINVAL, "kgf_necpt: singular contour matrix 1 - G^c_bb K");
-        zgemm(ctx, n, m, n, make_double2(1.0, 0.0), K, n, X, m, make_double2(0.0, 0.0), Y, m);
-        zgemm(ctx, m, m, n, make_double2(1.0, 0.0), R, n, Y, m, make_double2(0.0, 0.0), C, m);
-        hipLaunchKernelGGL(k_extract, dim3(grid_for((int64_t)nt * nt * n_c * n_c)), dim3(kThreads), 0, ctx->stream,
-                           gcl, gcg, C, (int64_t)m, nt, n_c, reinterpret_cast<double2*>(G_lesser),
-                           reinterpret_cast<double2*>(G_greater));
-        check_launch("k_extract");
+        CompPtrs gc{reinterpret_cast<const double2*>(Gc_lesser), reinterpret_cast<const double2*>(Gc_greater),
+                    nullptr, nullptr, nullptr, nullptr};
+        CompPtrs gb{reinterpret_cast<const double2*>(Gb_lesser), reinterpret_cast<const double2*>(Gb_greater),
+                    nullptr, nullptr, nullptr, nullptr};
+        necpt_solve(ctx, nt, 0, n_c, boundary, dt, 0.0, V, gc, gb, reinterpret_cast<double2*>(G_lesser),
+                    reinterpret_cast<double2*>(G_greater), nullptr, nullptr);
+        progress(ctx, "necpt", 1, 1);
+    });
+}
+
+static bool contour_fn_complete(const kgf_contour_fn* f) {
+    return f && f->lesser && f->greater && f->mixed && f->mixed_left && f->vert_greater && f->vert_lesser;
+}
+
+static CompPtrs comp_ptrs(const kgf_contour_fn* f) {
+    return CompPtrs{reinterpret_cast<const double2*>(f->lesser), reinterpret_cast<const double2*>(f->greater),
+                    reinterpret_cast<const double2*>(f->mixed), reinterpret_cast<const double2*>(f->mixed_left),
+                    reinterpret_cast<const double2*>(f->vert_greater), reinterpret_cast<const double2*>(f->vert_lesser)};
+}
+
+extern "C" int kgf_bath_chain_contour(kgf_ctx* ctx, int L_b, double T_b, double beta, int nt, double dt, int ntau,
+                                      double dtau, const kgf_contour_fn* out) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && contour_fn_complete(out), KGF_EINVAL, "kgf_bath_chain_contour: NULL argument");
+        KGF_REQUIRE(L_b >= 1 && nt >= 1 && ntau >= 1 && std::isfinite(T_b) && std::isfinite(dt) && dt >= 0.0 &&
+                        std::isfinite(dtau) && dtau >= 0.0 && !std::isnan(beta) && beta > 0.0 &&
+                        (std::isinf(beta) || (ntau - 1) * dtau <= beta * (1.0 + 1e-12)),
+                    KGF_EINVAL, "kgf_bath_chain_contour: bad L_b / nt / ntau / T_b / dt / dtau / beta");
+        KGF_HIP(hipSetDevice(ctx->device));
+        const int nd = 2 * nt - 1;
+        double2* d = static_cast<double2*>(workspace(ctx, "cpt_bath_d", sizeof(double2) * 2 * (size_t)nd));
+        hipLaunchKernelGGL(k_bath_chain, dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, ctx->stream, L_b, T_b, beta,
+                           nt, dt, d, d + nd);
+        check_launch("k_bath_chain");
+        hipLaunchKernelGGL(k_expand_diff, dim3(grid_for((int64_t)nt * nt)), dim3(kThreads), 0, ctx->stream, d,
+                           d + nd, nt, reinterpret_cast<double2*>(out->lesser), reinterpret_cast<double2*>(out->greater));
+        check_launch("k_expand_diff");
+        const int64_t tot = (int64_t)(nt + 1) * ntau;
+        hipLaunchKernelGGL(k_bath_chain_tau, dim3(grid_for(tot)), dim3(kThreads), 0, ctx->stream, L_b, T_b, beta, nt,
+                           dt, ntau, dtau, reinterpret_cast<double2*>(out->mixed),
+                           reinterpret_cast<double2*>(out->mixed_left), reinterpret_cast<double2*>(out->vert_greater),
+                           reinterpret_cast<double2*>(out->vert_lesser));
+        check_launch("k_bath_chain_tau");
         sync(ctx);
+    });
+}
+
+extern "C" int kgf_necpt_contour(kgf_ctx* ctx, int nt, int ntau, int n_c, int boundary, double dt, double dtau,
+                                 double V, const kgf_contour_fn* Gc, const kgf_contour_fn* Gb, kgf_c128* G_lesser,
+                                 kgf_c128* G_greater, kgf_c128* G_mixed, kgf_c128* G_mixed_left) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && contour_fn_complete(Gc) && contour_fn_complete(Gb) && G_lesser && G_greater, KGF_EINVAL,
+                    "kgf_necpt_contour: NULL argument");
+        KGF_REQUIRE(nt >= 1 && ntau >= 2 && n_c >= 1 && boundary >= 0 && boundary < n_c, KGF_EINVAL,
+                    "kgf_necpt_contour: bad nt / ntau / n_c / boundary");
+        KGF_REQUIRE(std::isfinite(dt) && dt >= 0.0 && std::isfinite(dtau) && dtau > 0.0 && std::isfinite(V),
+                    KGF_EINVAL, "kgf_necpt_contour: bad dt / dtau / V");
+        KGF_REQUIRE((int64_t)(2 * nt + ntau) * n_c <= 65536, KGF_EUNSUPPORTED,
+                    "kgf_necpt_contour: (2 nt + ntau) n_c above 65536");
+        KGF_HIP(hipSetDevice(ctx->device));
+        necpt_solve(ctx, nt, ntau, n_c, boundary, dt, dtau, V, comp_ptrs(Gc), comp_ptrs(Gb),
+                    reinterpret_cast<double2*>(G_lesser), reinterpret_cast<double2*>(G_greater),
+                    reinterpret_cast<double2*>(G_mixed), reinterpret_cast<double2*>(G_mixed_left));
         progress(ctx, "necpt", 1, 1);
     });
 }

@@ -144,7 +144,7 @@ int main() {
     std::vector<kgf_c128> Gl(ng), Gg(ng), Gl2(ng), Gg2(ng);
     double E0i = 0.0, E0r = 0.0;
     KGF_OK_(kgf_greens_neq(ctx, Hi, H, sec, &g4, v0, orbs, norb, nt, spg, &p4, 1, 3, 0, 0, 0.0, Gl.data(),
-                           Gg.data(), nullptr, nullptr, &E0i, nullptr));
+                           Gg.data(), nullptr, nullptr, nullptr, &E0i, nullptr));
     kgf_neq_run* run = nullptr;
     KGF_OK_(kgf_neq_run_create(ctx, Hi, H, sec, &g4, v0, orbs, norb, nt, spg, &p4, 3, &run, &E0r));
     EXPECT(kgf_neq_run_result(run, Gl2.data(), Gg2.data()) == KGF_EINVAL);   // intervals left

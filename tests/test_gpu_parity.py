@@ -239,7 +239,7 @@ def test_greens_eq_ring8_full(ctx):
 @pytest.mark.parametrize("schedule", [0, 1])
 def test_greens_neq_siam10_reduced_grid(ctx, schedule):
     """Anderson-impurity quench (impurity + 9 bath sites, field switched
-    off), four-step G^<, G^>, Matsubara and mixed components on a reduced
+    off), four-step G^<, G^>, Matsubara and both mixed components on a reduced
     mesh, both step-(iii) schedules, vs the oracle's literal four-step."""
     q = wl.siam10()
     say("G neq siam10 reduced", schedule)
@@ -253,7 +253,7 @@ def test_greens_neq_siam10_reduced_grid(ctx, schedule):
                          dt, q.krylov_dim, reorth=0, schedule=schedule, ntau=ntau, tau_steps_per_grid=tspg,
                          dtau=dtau, gs_tol=q.gs_tol)
     assert abs(got["E0"] - ora["E0"]) <= 1e-12 * abs(ora["E0"])
-    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed"):
+    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed", "G_mixed_left"):
         e = rel_err(got[key], ora[key])
         say(key, e)
         assert e < 1e-10, key
@@ -271,11 +271,11 @@ def test_greens_neq_schedules_agree_multi_orbital(ctx):
     kw = dict(nt=9, steps_per_grid=2, dt=0.1, krylov_dim=12, ntau=4, tau_steps_per_grid=2, dtau=0.1)
     a = ctx.greens_neq(ctx.model(H_ini), ctx.model(H), ctx.sector(6, 3, 3), v0, orbs, schedule=0, **kw)
     b = ctx.greens_neq(ctx.model(H_ini), ctx.model(H), ctx.sector(6, 3, 3), v0, orbs, schedule=1, batch=4, **kw)
-    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed"):
+    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed", "G_mixed_left"):
         assert rel_err(b[key], a[key]) < 1e-12, key
     ora = greens.four_step(H_ini, H, 3, 3, orbs, 9, 0.2, 2, 12, wl.start_vector(sec.dim, 7), reorth="none",
                            ntau=4, dtau_grid=0.2, tau_steps_per_grid=2)
-    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed"):
+    for key in ("G_lesser", "G_greater", "G_matsubara", "G_mixed", "G_mixed_left"):
         assert rel_err(a[key], ora[key]) < 1e-10, key
 
 
@@ -350,4 +350,5 @@ def test_siam10_full_grid_sampled_against_oracle():
             assert abs(got["G_lesser"][k, kp] - ora["G_lesser"][k, kp]).max() < 1e-10 * scale
             assert abs(got["G_greater"][k, kp] - ora["G_greater"][k, kp]).max() < 1e-10 * scale
         assert rel_err(got["G_mixed"][k], ora["G_mixed"][k]) < 1e-10
+        assert rel_err(got["G_mixed_left"][:, k], ora["G_mixed_left"][:, k]) < 1e-10
     assert rel_err(got["G_matsubara"], ora["G_matsubara"]) < 1e-10
