@@ -378,3 +378,32 @@ def cluster_fn(four_step_out: dict) -> dict:
     return {"lesser": four_step_out["G_lesser"], "greater": four_step_out["G_greater"],
             "mixed": four_step_out["G_mixed"], "mixed_left": four_step_out["G_mixed_left"],
             "vert_greater": 1j * GM[0], "vert_lesser": 1j * GM[1]}
+
+
+def cluster_fn_kms(four_step_out: dict) -> dict:
+    """The cluster's contour components on an imaginary branch of length
+    beta = (ntau - 1) dtau from its ground state |0> (N particles), in the
+    limit of a grand-canonical equilibrium dominated by |0> (reading of
+    Sec. 5's Matsubara branch at beta = 15): besides the ground-state terms
+    of cluster_fn, the states of N -+ 1 particles reached from |0> by c, c+
+    enter near the far end of the branch with the weight
+    e^{-(beta - tau)(E_n - E0)}, and, with e^{-tau (H_ini - E0)} projecting
+    onto |0> there, those terms are the same ground-state scalar products
+    read at beta - tau (the functions then obey the boundary condition
+    G(-i beta, z') = -G(0, z') up to terms e^{-beta Delta}):
+        G^>(-i tau, -i tau') = i G^M(+d) - i G^M(-(beta - d)),  d = tau - tau' >= 0
+        G^<(-i tau, -i tau') = i G^M(-d) - i G^M(+(beta - d)),  d = tau' - tau >= 0
+        G^<_ab(t, -i tau)    = G^|_ab(t, tau) + conj(G^|_ba(beta - tau, t))
+        G^>_ab(-i tau, t)    = G^|_ab(tau, t) + conj(G^|_ba(t, beta - tau))
+    (G^| with a real first argument: the c sweep; with an imaginary first
+    argument: the c+ sweep).  The real-time components are unchanged (their
+    corrections are of order e^{-beta Delta})."""
+    fn = cluster_fn(four_step_out)
+    vg0, vl0 = fn["vert_greater"], fn["vert_lesser"]
+    mx, mxl = fn["mixed"], fn["mixed_left"]
+    out = dict(fn)
+    out["vert_greater"] = vg0 - vl0[::-1]
+    out["vert_lesser"] = vl0 - vg0[::-1]
+    out["mixed"] = mx + np.conj(np.transpose(mxl[::-1], (1, 0, 3, 2)))
+    out["mixed_left"] = mxl + np.conj(np.transpose(mx[:, ::-1], (1, 0, 3, 2)))
+    return out

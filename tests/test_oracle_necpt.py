@@ -324,3 +324,41 @@ def test_four_step_cluster_components_at_u0_are_free_fermions():
     got = necpt.cluster_fn(out)
     for key in ref:
         assert np.abs(got[key] - ref[key]).max() < 1e-10, key
+
+
+def test_kms_completed_ground_state_functions_are_thermal():
+    """The cluster's zero-temperature components completed for an imaginary
+    branch of length beta (cluster_fn_kms) equal the thermal functions at
+    beta up to terms e^{-beta Delta}: at U = 0 (free fermions: the four-step
+    replaced by the exact zero-temperature components) the difference falls
+    from 1e-3 at beta = 15 to below 1e-5 at beta = 30; and the CPT equation
+    fed with them reproduces the connected system's thermal densities."""
+    nc, nb, V, dt, nt = 6, 12, 1.0, 0.1, 2
+    eps = np.zeros(nc)
+    eps[0] = -0.2
+    hc_ini, hc, Tb = _chain_h(nc, 1.0, eps), _chain_h(nc), _chain_h(nb)
+    for beta, bound in ((15.0, 2e-3), (30.0, 1e-5)):
+        dtau = 0.1
+        ntau = int(round(beta / dtau)) + 1
+        t0 = necpt.free_greens_l(hc_ini, hc, np.inf, nt, dt, ntau, dtau)
+        GM = np.stack([-1j * t0["vert_greater"], -1j * t0["vert_lesser"]])
+        fake = {"G_lesser": t0["lesser"], "G_greater": t0["greater"], "G_mixed": t0["mixed"],
+                "G_mixed_left": t0["mixed_left"], "G_matsubara": GM}
+        got = necpt.cluster_fn_kms(fake)
+        ref = necpt.free_greens_l(hc_ini, hc, beta, nt, dt, ntau, dtau)
+        err = max(np.abs(got[k] - ref[k]).max() for k in ref)
+        assert err < bound, (beta, err)
+        plain = necpt.cluster_fn(fake)
+        assert max(np.abs(plain[k] - ref[k]).max() for k in ("vert_greater", "mixed")) > 0.1   # the completion matters
+    # the connected densities through the CPT equation (beta = 30)
+    Gb = necpt.bath_greens_l(Tb, nt, dt, ntau, dtau, beta, sites=[0])
+    res = necpt.necpt_l(got, Gb, nc - 1, V, dt, dtau)
+    h = np.zeros((nc + nb, nc + nb))
+    h[:nc, :nc], h[nc:, nc:] = hc_ini, Tb
+    h[nc - 1, nc] = h[nc, nc - 1] = -V
+    hf = h.copy()
+    hf[:nc, :nc] = hc
+    ex = necpt.free_greens_l(h, hf, beta, nt, dt, 2, dtau)
+    n_got = np.real(-1j * np.diag(res["lesser"][0, 0]))
+    n_ex = np.real(-1j * np.diag(ex["lesser"][0, 0]))[:nc]
+    assert np.abs(n_got - n_ex).max() < 2e-4
