@@ -91,6 +91,11 @@ def parse():
     p.add_argument("--hv-passes", default="0",
                    help="comma-separated kgf_set_option HV_PASSES values (9: the library's tuner chooses)")
     p.add_argument("--hv-strip", default="0", help="comma-separated kgf_set_option HV_STRIP values")
+    p.add_argument("--hv-fuse", default="1",
+                   help="comma-separated kgf_set_option HV_FUSE values (two-pass Lanczos step with the update "
+                        "folded into the row pass)")
+    p.add_argument("--hv-seg", default="1",
+                   help="comma-separated kgf_set_option HV_SEG values (row pass with the segment hop tables)")
     p.add_argument("--hv-reps", type=int, default=10)
     p.add_argument("--no-graphs", action="store_true",
                    help="state GRAPHS 0 explicitly (every SIL step eager, the library default); kernel traces "
@@ -116,15 +121,19 @@ def hv_bench(a):
         g = torch.Generator(device="cuda:0").manual_seed(11)
         x = torch.randn(sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
         y = torch.empty_like(x)
-        variants = [(int(p_), int(s_)) for p_ in a.hv_passes.split(",") if p_ for s_ in a.hv_strip.split(",") if s_]
-        for passes, strip in variants:
+        variants = [(int(p_), int(s_), int(f_), int(g_)) for p_ in a.hv_passes.split(",") if p_
+                    for s_ in a.hv_strip.split(",") if s_ for f_ in a.hv_fuse.split(",") if f_
+                    for g_ in a.hv_seg.split(",") if g_]
+        for passes, strip, fuse, seg in variants:
             # passes 9: let the library's tuner choose (HV_TUNE)
             ctx.set_option(ctx.HV_TUNE, 1 if passes == 9 else 0)
             ctx.set_option(ctx.HV_PASSES, 0 if passes == 9 else passes)
             ctx.set_option(ctx.HV_STRIP, 0 if passes == 9 else strip)
+            ctx.set_option(ctx.HV_FUSE, fuse)
+            ctx.set_option(ctx.HV_SEG, seg)
             ctx.apply_h(m, sec, x, y)      # warm-up (tables, LDS opt-in)
             torch.cuda.synchronize()
-            log(f"L={L} D={sec.dim} passes={passes} strip={strip}: timing")
+            log(f"L={L} D={sec.dim} passes={passes} strip={strip} fuse={fuse} seg={seg}: timing")
             ctx.profile_begin(1)
             for _ in range(a.hv_reps):
                 ctx.apply_h(m, sec, x, y)
@@ -132,8 +141,8 @@ def hv_bench(a):
             ctx.propagate(m, sec, xs, 1, q.dt, q.krylov_dim, +1)
             torch.cuda.synchronize()
             st = ctx.profile_end()
-            out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip}
-            for k in ("hv", "hv_lanczos", "lanczos_update", "combine"):
+            out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip, "fuse": fuse, "seg": seg}
+            for k in ("hv", "hv_lanczos", "hv_rows_lanczos", "hv_up_lanczos", "lanczos_update", "combine"):
                 if k in st and st[k]["sampled"]:
                     ms = st[k]["sampled_ms"] / st[k]["sampled"]
                     gbs = st[k]["sampled_bytes"] / (st[k]["sampled_ms"] * 1e-3) / 1e9
@@ -143,6 +152,8 @@ def hv_bench(a):
         ctx.set_option(ctx.HV_PASSES, 0)
         ctx.set_option(ctx.HV_STRIP, 0)
         ctx.set_option(ctx.HV_TUNE, 0)
+        ctx.set_option(ctx.HV_FUSE, 1)
+        ctx.set_option(ctx.HV_SEG, 1)
         del x, y
         torch.cuda.empty_cache()
 

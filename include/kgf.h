@@ -646,10 +646,26 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      (per group the same element owners and reduction orders).
  *                      Used when reorth = 0 and those sectors' H.v is the single
  *                      pass; 0 = every group alone.
+ *   KGF_OPT_HV_FUSE:   1 (default) = where a sector's H.v is two-pass and
+ *                      reorth = 0, a Lanczos step (Eq. (recursion)) is the two
+ *                      passes alone: the update y - a_k v_k of step k and the
+ *                      norm giving b_{k+1} are done by the row pass of step k+1
+ *                      while it stages those rows (no separate update pass);
+ *                      0 = the update as a pass of its own.  Results agree to
+ *                      rounding.
+ *   KGF_OPT_HV_SEG:    1 (default) = pass 1 of the two-pass H.v finds the
+ *                      down-spin hops from segment tables: the masks split into
+ *                      a high and a low half, a hop inside one half moves the
+ *                      rank by an offset that depends on that half alone (tens
+ *                      of KB of tables in LDS instead of one table entry per
+ *                      state and hop); used when at most 8 bonds cross the
+ *                      split and the row and tables fit in LDS.  0 = the
+ *                      per-state tables.  Results agree to rounding.
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
 enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5,
-       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7, KGF_OPT_GRAPHS = 8, KGF_OPT_LOCKSTEP = 9 };
+       KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7, KGF_OPT_GRAPHS = 8, KGF_OPT_LOCKSTEP = 9,
+       KGF_OPT_HV_FUSE = 10, KGF_OPT_HV_SEG = 11 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

@@ -633,6 +633,12 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_GRAPHS) {
             KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: GRAPHS must be 0 or 1");
             ctx->use_graphs = value;
+        } else if (option == KGF_OPT_HV_FUSE) {
+            KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: HV_FUSE must be 0 or 1");
+            ctx->hv_fuse = value;
+        } else if (option == KGF_OPT_HV_SEG) {
+            KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: HV_SEG must be 0 or 1");
+            ctx->hv_seg = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

@@ -260,6 +260,7 @@ HopTable& hop_table(kgf_model* model, int n) {
         check_launch("k_onsite");
         sync(ctx);   // the temporaries above are freed on return
     }
+    build_seg_table(model, *t);
     HopTable& ref = *t;
     model->tables[n] = std::move(t);
     return ref;

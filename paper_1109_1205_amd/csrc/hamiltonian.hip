@@ -11,6 +11,7 @@
 // whole rows V[u', :] (coalesced along d), the down-spin hops gather inside
 // row u (L1/L2 resident), the diagonal is evaluated on the fly from the two
 // masks.  H.v is sparse and memory bound: no matrix cores are involved.
+#include <algorithm>
 #include <array>
 #include <map>
 #include <cstdlib>
@@ -77,6 +78,120 @@ void model_set_init(kgf_ctx* ctx, ModelSet& S) {
                           hipMemcpyDeviceToDevice));
     S.eu.clear();
     S.ed.clear();
+}
+
+// Segment tables of a spin species (SegInfo), built with its hopping table.
+// The split bit is the one near L/2 with the fewest bonds across it; more
+// than 8 bonds across any split leave the tables unusable (S = 0).
+const SegInfo& seg_table(kgf_model* model, int n) { return hop_table(model, n).seg; }
+
+void build_seg_table(kgf_model* model, HopTable& ht) {
+    const int n = ht.n;
+    const int L = model->L;
+    SegInfo g;
+    g.S = 0;
+    int best = -1, best_cross = 1 << 30;
+    for (int S = 1; S < L; ++S) {
+        if (S > 11 || L - S > 11) continue;
+        int nc = 0;
+        for (int b = 0; b < model->nb; ++b) {
+            const int a = std::min(model->bi[b], model->bj[b]), c = std::max(model->bi[b], model->bj[b]);
+            nc += (a < S && c >= S) ? 1 : 0;
+        }
+        if (nc < best_cross || (nc == best_cross && std::abs(2 * S - L) < std::abs(2 * best - L))) {
+            best = S;
+            best_cross = nc;
+        }
+    }
+    if (best < 0 || best_cross > 8) {
+        ht.seg = g;
+        return;
+    }
+    const int S = best, nl = 1 << S, nh = 1 << (L - S);
+    // colex rank of every low part among the low parts of its popcount
+    std::vector<uint16_t> rank(nl);
+    {
+        std::vector<int> seen(S + 1, 0);
+        for (int l = 0; l < nl; ++l) rank[l] = (uint16_t)seen[__builtin_popcount(l)]++;
+    }
+    std::vector<int32_t> seg(nh, -1);
+    {
+        int64_t off = 0;
+        for (int H = 0; H < nh; ++H) {
+            const int k = n - __builtin_popcount(H);
+            if (k < 0 || k > S) continue;
+            seg[H] = (int32_t)off;
+            off += binom_host(S, k);
+        }
+    }
+    auto between = [](int a, int c) -> uint32_t { return ((1u << c) - 1u) & ~((2u << a) - 1u); };
+    std::vector<std::vector<uint32_t>> lo(nl), hi(nh);
+    std::vector<uint32_t> cross;
+    for (int b = 0; b < model->nb; ++b) {
+        const int a = std::min(model->bi[b], model->bj[b]), c = std::max(model->bi[b], model->bj[b]);
+        if (c < S) {
+            for (int l = 0; l < nl; ++l) {
+                if ((((l >> a) ^ (l >> c)) & 1) == 0) continue;
+                const int l2 = l ^ (1 << a) ^ (1 << c);
+                const uint32_t sg = (uint32_t)(__builtin_popcount(l & between(a, c)) & 1);
+                const int32_t dl = (int32_t)rank[l2] - (int32_t)rank[l];
+                lo[l].push_back(((uint32_t)dl & 0xFFFFFFu) | ((uint32_t)b << 24) | (sg << 31));
+            }
+        } else if (a >= S) {
+            const int a2 = a - S, c2 = c - S;
+            for (int H = 0; H < nh; ++H) {
+                if (seg[H] < 0 || (((H >> a2) ^ (H >> c2)) & 1) == 0) continue;
+                const int H2 = H ^ (1 << a2) ^ (1 << c2);
+                const uint32_t sg = (uint32_t)(__builtin_popcount(H & between(a2, c2)) & 1);
+                const int32_t dl = seg[H2] - seg[H];
+                hi[H].push_back(((uint32_t)dl & 0xFFFFFFu) | ((uint32_t)b << 24) | (sg << 31));
+            }
+        } else {
+            cross.push_back((uint32_t)a | ((uint32_t)(c - S) << 8) | ((uint32_t)b << 16));
+            cross.push_back(((uint32_t)nl - 1u) & ~((2u << a) - 1u));   // low sites above a
+            cross.push_back((1u << (c - S)) - 1u);                      // high sites below c
+            cross.push_back(0u);
+        }
+    }
+    for (auto& v : lo) g.wlo = std::max(g.wlo, (int)v.size());
+    for (auto& v : hi) g.whi = std::max(g.whi, (int)v.size());
+    g.S = S;
+    g.nl = nl;
+    g.nh = nh;
+    g.ncross = (int)cross.size() / 4;
+    int w = 0;
+    g.o_lo = w;
+    w += g.wlo * nl;
+    g.o_hi = w;
+    w += g.whi * nh;
+    g.o_clo = w;
+    w += (nl + 3) / 4;
+    g.o_chi = w;
+    w += (nh + 3) / 4;
+    g.o_seg = w;
+    w += nh;
+    g.o_rank = w;
+    w += (nl + 1) / 2;
+    g.o_cross = w;
+    w += 4 * g.ncross;
+    g.words = w;
+    std::vector<uint32_t> tab((size_t)w, 0u);
+    uint8_t* clo = reinterpret_cast<uint8_t*>(tab.data() + g.o_clo);
+    uint8_t* chi = reinterpret_cast<uint8_t*>(tab.data() + g.o_chi);
+    for (int l = 0; l < nl; ++l) {
+        for (size_t k = 0; k < lo[l].size(); ++k) tab[g.o_lo + k * nl + l] = lo[l][k];
+        clo[l] = (uint8_t)lo[l].size();
+    }
+    for (int H = 0; H < nh; ++H) {
+        for (size_t k = 0; k < hi[H].size(); ++k) tab[g.o_hi + k * nh + H] = hi[H][k];
+        chi[H] = (uint8_t)hi[H].size();
+    }
+    std::memcpy(tab.data() + g.o_seg, seg.data(), sizeof(int32_t) * nh);
+    std::memcpy(tab.data() + g.o_rank, rank.data(), sizeof(uint16_t) * nl);
+    std::copy(cross.begin(), cross.end(), tab.begin() + g.o_cross);
+    ht.segtab.reserve(sizeof(uint32_t) * tab.size());
+    KGF_HIP(hipMemcpy(ht.segtab.p, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice));
+    ht.seg = g;
 }
 
 namespace {
@@ -472,20 +587,56 @@ __global__ __launch_bounds__(kHvThreads, 8) void k_hv_lds_groups(const HvGroupDe
 constexpr size_t kSplitLdsMax = 150 * 1024;      // one real component of a row
 constexpr int kRowsJSplit = 16;                  // row elements per thread, split rows (D_dn <= 16,384)
 
+// The Lanczos update of the previous step folded into pass 1 (UPD): the
+// rows of x_k are formed on the fly as x_k = y - a_{k-1} s_{k-1} x_{k-1}
+// from y (the raw output of the previous step's pass 2, in slot k) and
+// x_{k-1}, written back over y, and their squared norms summed per block
+// (one partial per block: b_k = ||x_k||).  Pass 1 is row local, so the
+// update needs no pass of its own: the rows it reads are the rows it stages.
+struct RowUpd {
+    const double2* xp;        // x_{k-1} (column c at xp + c * xp_col)
+    int64_t xp_col;
+    const double* fa;         // a_{k-1} (column c at fa[c * stride])
+    const double* fs;         // s_{k-1}
+    int stride;
+    double* part;             // [ncol][gridDim.x] partials of ||x_k||^2
+};
+
+// x_k element i of a row: y - f x_{k-1}, written back over y (UPD)
+template <bool UPD>
+__device__ __forceinline__ double2 upd_load(double2* __restrict__ xr, const double2* __restrict__ pr, int64_t i,
+                                            double f, double& nrm) {
+    double2 v = ld_stream(xr + i);
+    if (UPD) {
+        const double2 p = ld_stream(pr + i);
+        v.x = fma(-f, p.x, v.x);
+        v.y = fma(-f, p.y, v.y);
+        xr[i] = v;
+        nrm = fma(v.x, v.x, nrm);
+        nrm = fma(v.y, v.y, nrm);
+    }
+    return v;
+}
+
 // Pass 1.  One block per row u; threads own d = tid + j * 1024.  The row is
 // read and y written once (nontemporal), so the hop tables stay in L2.
-template <bool SPLIT, bool UNIFORM_U, int NR>
-__global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double2* __restrict__ X, int64_t x_col,
-                                                        double2* __restrict__ Y, int64_t y_col) {
+// With UPD the row is x_k formed from the pending update (RowUpd); X is
+// then written (x_k back over y).
+template <bool SPLIT, bool UNIFORM_U, int NR, bool UPD = false>
+__global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, double2* __restrict__ X, int64_t x_col,
+                                                        double2* __restrict__ Y, int64_t y_col, RowUpd up) {
     extern __shared__ double2 srow[];
     __shared__ double s_negt[kMaxBonds + 1];
     __shared__ double s_U[UNIFORM_U ? 1 : 3 * 256];
+    __shared__ double s_red[kHvThreads / 64];
     const int64_t u = blockIdx.x;
     const int c = blockIdx.y;
     const int tid = threadIdx.x;
     const int64_t Ddn = T.Ddn;
-    const double2* __restrict__ xrow = X + c * x_col + u * Ddn;
+    double2* __restrict__ xrow = X + c * x_col + u * Ddn;
     double2* __restrict__ yrow = Y + c * y_col + u * Ddn;
+    const double fup = UPD ? up.fa[(int64_t)c * up.stride] * up.fs[(int64_t)c * up.stride] : 0.0;
+    double nrm = 0.0;
     for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
     if (!UNIFORM_U)
         for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par_index(T, blockIdx.y) * 768 + i];
@@ -503,9 +654,14 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
         // NR consecutive rows per block share every hop-table load
         const int64_t ub = (int64_t)blockIdx.x * NR;
         const int nr = (int)min((int64_t)NR, T.Dup - ub);
-        const double2* __restrict__ xr = X + c * x_col + ub * Ddn;
+        double2* __restrict__ xr = X + c * x_col + ub * Ddn;
         double2* __restrict__ yr = Y + c * y_col + ub * Ddn;
-        for (int64_t i = tid; i < (int64_t)nr * Ddn; i += blockDim.x) srow[i] = ld_stream(xr + i);
+        const double2* __restrict__ pr = UPD ? up.xp + c * up.xp_col + ub * Ddn : nullptr;
+        for (int64_t i = tid; i < (int64_t)nr * Ddn; i += blockDim.x) srow[i] = upd_load<UPD>(xr, pr, i, fup, nrm);
+        if (UPD) {
+            const double sum = block_sum(nrm, s_red);
+            if (tid == 0) up.part[(int64_t)c * gridDim.x + blockIdx.x] = sum;
+        }
         uint32_t mur[NR];
         double eur[NR];
 #pragma unroll
@@ -555,15 +711,20 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
     // split: real parts in LDS while the imaginary parts wait in registers
     double* sh = reinterpret_cast<double*>(srow);
     double xim[kRowsJSplit], are[kRowsJSplit];
+    const double2* __restrict__ prow = UPD ? up.xp + c * up.xp_col + u * Ddn : nullptr;
 #pragma unroll
     for (int j = 0; j < kRowsJSplit; ++j) {
         const int64_t d = tid + (int64_t)j * kHvThreads;
         xim[j] = 0.0;
         if (d < Ddn) {
-            const double2 v = ld_stream(xrow + d);
+            const double2 v = upd_load<UPD>(xrow, prow, d, fup, nrm);
             sh[d] = v.x;
             xim[j] = v.y;
         }
+    }
+    if (UPD) {
+        const double sum = block_sum(nrm, s_red);   // its barriers also order the LDS row
+        if (tid == 0) up.part[(int64_t)c * gridDim.x + blockIdx.x] = sum;
     }
     __syncthreads();
     auto gather = [&](int64_t d, double self) -> double {
@@ -599,6 +760,198 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, const double
     for (int j = 0; j < kRowsJSplit; ++j) {
         const int64_t d = tid + (int64_t)j * kHvThreads;
         if (d < Ddn) st_stream(yrow + d, make_double2(are[j], gather(d, xim[j])));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1 with the segment tables (SegInfo) in LDS, for rows up to 16 K
+// elements.  Blocks are persistent over rows (row u = blockIdx.x, +gridDim.x)
+// so the tables are staged once per block.  Each hop of row element d reads
+// the staged row at d + delta, where delta comes from the low part's or the
+// high part's table entry (the high part is shared by the consecutive
+// elements of a segment, so those reads are broadcasts and the row reads are
+// consecutive), or, for a bond across the split, from seg_off and rank_lo.
+// SPLIT: the row's real parts in LDS while the imaginary parts wait in
+// registers, then the other way round (rows above 78 KB).
+// ---------------------------------------------------------------------------
+struct SegDev {
+    const uint32_t* tab;
+    int words, S, nl, nh, ncross;
+    int o_lo, o_hi, o_clo, o_chi, o_seg, o_rank, o_cross;
+};
+
+struct SegView {
+    const uint32_t* lo;
+    const uint32_t* hi;
+    const uint8_t* clo;
+    const uint8_t* chi;
+    const int32_t* seg;
+    const uint16_t* rank;
+    const uint32_t* cross;
+    int S, nl, nh, ncross;
+};
+
+__device__ __forceinline__ int seg_delta(uint32_t e) { return ((int)(e << 8)) >> 8; }
+
+__device__ __forceinline__ void fma_acc(double& acc, double t, double z) { acc = fma(t, z, acc); }
+__device__ __forceinline__ void fma_acc(double2& acc, double t, double2 z) {
+    acc.x = fma(t, z.x, acc.x);
+    acc.y = fma(t, z.y, acc.y);
+}
+
+
+// sum over the hops of row element d (mask s) of -t_b (-1)^sign x[target];
+// rd(i) reads the staged row (a double or a double2)
+template <typename V, typename RD>
+__device__ __forceinline__ void seg_hops(V& acc, int d, uint32_t s, const SegView& G, const double* negt, RD rd) {
+    const uint32_t l = s & (uint32_t)(G.nl - 1), H = s >> G.S;
+    const int nlo = G.clo[l];
+#pragma unroll 1
+    for (int k = 0; k < nlo; ++k) {
+        const uint32_t e = G.lo[k * G.nl + (int)l];
+        const double v = negt[(e >> 24) & 127u];
+        fma_acc(acc, (e >> 31) ? -v : v, rd(d + seg_delta(e)));
+    }
+    const int nhi = G.chi[H];
+#pragma unroll 1
+    for (int k = 0; k < nhi; ++k) {
+        const uint32_t e = G.hi[k * G.nh + (int)H];
+        const double v = negt[(e >> 24) & 127u];
+        fma_acc(acc, (e >> 31) ? -v : v, rd(d + seg_delta(e)));
+    }
+#pragma unroll 1
+    for (int k = 0; k < G.ncross; ++k) {
+        const uint32_t w0 = G.cross[4 * k];
+        const uint32_t a = w0 & 255u, ch = (w0 >> 8) & 255u;
+        if ((((l >> a) ^ (H >> ch)) & 1u) == 0u) continue;
+        const uint32_t l2 = l ^ (1u << a), H2 = H ^ (1u << ch);
+        const int sg = (__popc(l & G.cross[4 * k + 1]) + __popc(H & G.cross[4 * k + 2])) & 1;
+        const double v = negt[(w0 >> 16) & 127u];
+        fma_acc(acc, sg ? -v : v, rd(G.seg[H2] + (int)G.rank[l2]));
+    }
+}
+
+constexpr size_t kSegLdsMax = 160 * 1024 - 8 * 1024;   // dynamic LDS of the segment row kernel
+
+// bytes of the staged row, rounded to 16
+__host__ __device__ __forceinline__ size_t seg_row_bytes(int64_t Ddn, bool split) {
+    return ((split ? 8 : 16) * (size_t)Ddn + 15) & ~(size_t)15;
+}
+
+template <bool SPLIT, bool UNIFORM_U, bool UPD, int J, int NT>
+__global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double2* __restrict__ X,
+                                                            int64_t x_col, double2* __restrict__ Y, int64_t y_col,
+                                                            RowUpd up) {
+    extern __shared__ double2 srow[];
+    __shared__ double s_negt[kMaxBonds + 1];
+    __shared__ double s_U[UNIFORM_U ? 1 : 3 * 256];
+    __shared__ double s_red[NT / 64];
+    const int c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int Ddn = (int)T.Ddn;
+    const int par = par_index(T, c);
+    uint32_t* stab = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(srow) + seg_row_bytes(Ddn, SPLIT));
+    for (int i = tid; i < G.words; i += blockDim.x) stab[i] = G.tab[i];
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par * T.nb + b];
+    if (!UNIFORM_U)
+        for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par * 768 + i];
+    SegView V;
+    V.lo = stab + G.o_lo;
+    V.hi = stab + G.o_hi;
+    V.clo = reinterpret_cast<const uint8_t*>(stab + G.o_clo);
+    V.chi = reinterpret_cast<const uint8_t*>(stab + G.o_chi);
+    V.seg = reinterpret_cast<const int32_t*>(stab + G.o_seg);
+    V.rank = reinterpret_cast<const uint16_t*>(stab + G.o_rank);
+    V.cross = stab + G.o_cross;
+    V.S = G.S;
+    V.nl = G.nl;
+    V.nh = G.nh;
+    V.ncross = G.ncross;
+    const double fup = UPD ? up.fa[(int64_t)c * up.stride] * up.fs[(int64_t)c * up.stride] : 0.0;
+    const double U0 = par_U0(T, par);
+    const double* __restrict__ ed = T.ed + (int64_t)par * Ddn;
+    double nrm = 0.0;
+    __syncthreads();
+    for (int64_t u = blockIdx.x; u < T.Dup; u += gridDim.x) {
+        double2* __restrict__ xrow = X + c * x_col + u * Ddn;
+        double2* __restrict__ yrow = Y + c * y_col + u * Ddn;
+        const double2* __restrict__ prow = UPD ? up.xp + c * up.xp_col + u * Ddn : nullptr;
+        const uint32_t mu = T.mu[u];
+        const double eu = T.eu[(int64_t)par * T.Dup + u];
+        auto diag = [&](double edd, uint32_t md) -> double {
+            const uint32_t both = mu & md;
+            double dg = eu + edd;
+            if (UNIFORM_U) dg += U0 * (double)__popc(both);
+            else dg += s_U[both & 255u] + s_U[256 + ((both >> 8) & 255u)] + s_U[512 + ((both >> 16) & 255u)];
+            return dg;
+        };
+        if (SPLIT) {
+            double* sh = reinterpret_cast<double*>(srow);
+            // an opaque row-variant copy of tid: otherwise the per-element
+            // addresses are hoisted out of the row loop and the kernel spills
+            int tb = tid;
+            asm volatile("" : "+v"(tb));
+            double xim[J], are[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int d = tb + j * NT;
+                xim[j] = 0.0;
+                if (d < Ddn) {
+                    const double2 v = upd_load<UPD>(xrow, prow, d, fup, nrm);
+                    sh[d] = v.x;
+                    xim[j] = v.y;
+                }
+            }
+            __syncthreads();
+            auto rd = [&](int i) -> double { return sh[i]; };
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int d = tb + j * NT;
+                are[j] = 0.0;
+                if (d < Ddn) {
+                    const uint32_t md = T.md[d];
+                    double acc = diag(ed[d], md) * sh[d];
+                    seg_hops(acc, d, md, V, s_negt, rd);
+                    are[j] = acc;
+                }
+
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int d = tb + j * NT;
+                if (d < Ddn) sh[d] = xim[j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int d = tb + j * NT;
+                if (d < Ddn) {
+                    const uint32_t md = T.md[d];
+                    double acc = diag(ed[d], md) * xim[j];
+                    seg_hops(acc, d, md, V, s_negt, rd);
+                    st_stream(yrow + d, make_double2(are[j], acc));
+                }
+            }
+            __syncthreads();
+        } else {
+            for (int d = tid; d < Ddn; d += blockDim.x) srow[d] = upd_load<UPD>(xrow, prow, d, fup, nrm);
+            __syncthreads();
+            auto rd = [&](int i) -> double2 { return srow[i]; };
+            for (int d = tid; d < Ddn; d += blockDim.x) {
+                const uint32_t md = T.md[d];
+                const double2 xv = srow[d];
+                const double dg = diag(ed[d], md);
+                double2 acc = make_double2(dg * xv.x, dg * xv.y);
+                seg_hops(acc, d, md, V, s_negt, rd);
+                st_stream(yrow + d, acc);
+            }
+            __syncthreads();
+        }
+    }
+    if (UPD) {
+        const double sum = block_sum(nrm, s_red);
+        if (tid == 0) up.part[(int64_t)c * gridDim.x + blockIdx.x] = sum;
     }
 }
 
@@ -940,6 +1293,7 @@ __global__ void k_dH_fin(const double* __restrict__ part, int64_t nrow, int nthe
 struct HvPlan {
     int passes = 0;
     bool split = false;
+    bool seg = false;   // pass 1 with the segment tables (set by plan_seg)
     int nr = 2;   // rows per pass-1 block when whole rows are staged
     int C = 8;
     int nstrip = 0, ntile = 0;
@@ -998,14 +1352,118 @@ void launch_up(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int width, int 
                        stride, part);
 }
 
+template <int MODE>
+void launch_up_plan(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int w, int ncol, const double2* x,
+                    int64_t x_col, const double2* xp, int64_t xp_col, double2* y, int64_t y_col, const double* s_k,
+                    const double* b_k, const double* s_km1, int stride, double* part) {
+    switch (P.C) {
+        case 64: launch_up<MODE, 64>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+        case 32: launch_up<MODE, 32>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+        case 16: launch_up<MODE, 16>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+        default: launch_up<MODE, 8>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+    }
+    check_launch("k_hv_up");
+}
+
 // opt in to more than 64 KB of dynamic LDS once per device and kernel
 void opt_in_lds(kgf_ctx* ctx, const void* kern, int slot, size_t bytes) {
-    static bool opted[16][64] = {};
+    static bool opted[48][64] = {};
     const int dev = ctx->device & 63;
     if (!opted[slot][dev]) {
         KGF_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
         opted[slot][dev] = true;
     }
+}
+
+constexpr int kSegBlocks = 512;   // persistent pass-1 blocks per column (segment tables)
+
+// The segment tables of the sector's down-spin species when pass 1 can use
+// them (two-pass plan, rows staged in LDS beside the tables), else null.
+const SegInfo* plan_seg(kgf_ctx* ctx, HModel model, const kgf_sector* sec, const HvPlan& P) {
+    if (P.passes != 2 || !ctx->hv_seg || sec->d_dn > (int64_t)kRowsJSplit * kHvThreads) return nullptr;
+    const SegInfo& g = seg_table(model.m, sec->n_dn);
+    if (g.S <= 0) return nullptr;
+    if (seg_row_bytes(sec->d_dn, P.split) + sizeof(uint32_t) * (size_t)g.words > kSegLdsMax) return nullptr;
+    return &g;
+}
+
+// pass-1 blocks per column of a two-pass plan (one norm partial each with UPD)
+int64_t rows_blocks(const HvPlan& P, const kgf_sector* sec) {
+    if (P.seg) return std::min<int64_t>(sec->d_up, kSegBlocks);
+    const size_t lds = sizeof(double2) * (size_t)sec->d_dn;
+    return (!P.split && P.nr == 2 && 2 * lds <= kSplitLdsMax) ? (sec->d_up + 1) / 2 : sec->d_up;
+}
+
+// Pass 1 of a two-pass plan: y = (down-spin hops + diagonal) x; with upd the
+// row is x_k formed from the pending Lanczos update (written back over x).
+template <bool UPD>
+void launch_rows_t(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, bool uu, int ncol, double2* x, int64_t x_col,
+                   double2* y, int64_t y_col, const RowUpd& up, const SegInfo* sg, const void* segtab) {
+    const int64_t Dup = T.Dup, Ddn = T.Ddn;
+    const size_t lds = P.split ? sizeof(double) * (size_t)Ddn : sizeof(double2) * (size_t)Ddn;
+    const int slot = 2 * (UPD ? 8 : 0);
+    dim3 rg((unsigned)Dup, (unsigned)ncol);
+    if (P.seg) {
+        SegDev G;
+        G.tab = static_cast<const uint32_t*>(segtab);
+        G.words = sg->words;
+        G.S = sg->S;
+        G.nl = sg->nl;
+        G.nh = sg->nh;
+        G.ncross = sg->ncross;
+        G.o_lo = sg->o_lo;
+        G.o_hi = sg->o_hi;
+        G.o_clo = sg->o_clo;
+        G.o_chi = sg->o_chi;
+        G.o_seg = sg->o_seg;
+        G.o_rank = sg->o_rank;
+        G.o_cross = sg->o_cross;
+        const size_t dyn = seg_row_bytes(Ddn, P.split) + sizeof(uint32_t) * (size_t)sg->words;
+        dim3 sgrid((unsigned)std::min<int64_t>(Dup, kSegBlocks), (unsigned)ncol);
+        // split form: 13 row elements per thread cover the 2x8 ladder's 12,870
+        const bool j13 = Ddn <= 13 * kHvThreads;
+        auto kern = !P.split ? (uu ? k_hv_rows_seg<false, true, UPD, 1, kHvThreads>
+                                   : k_hv_rows_seg<false, false, UPD, 1, kHvThreads>)
+                    : j13    ? (uu ? k_hv_rows_seg<true, true, UPD, 13, kHvThreads>
+                                   : k_hv_rows_seg<true, false, UPD, 13, kHvThreads>)
+                             : (uu ? k_hv_rows_seg<true, true, UPD, kRowsJSplit, kHvThreads>
+                                   : k_hv_rows_seg<true, false, UPD, kRowsJSplit, kHvThreads>);
+        const int nthr = kHvThreads;
+        const int sslot = 30 + (UPD ? 6 : 0) + (P.split ? (j13 ? 2 : 4) : 0) + (uu ? 1 : 0);
+        opt_in_lds(ctx, (const void*)kern, sslot, kSegLdsMax);
+        hipLaunchKernelGGL(kern, sgrid, dim3(nthr), dyn, ctx->stream, T, G, x, x_col, y, y_col, up);
+        check_launch("k_hv_rows_seg");
+        return;
+    }
+    if (P.split) {
+        auto rows = uu ? k_hv_rows<true, true, 1, UPD> : k_hv_rows<true, false, 1, UPD>;
+        opt_in_lds(ctx, (const void*)rows, slot + 4 + (uu ? 1 : 0), kSplitLdsMax);
+        hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col, up);
+    } else if (P.nr == 2 && 2 * lds <= kSplitLdsMax) {
+        auto rows = uu ? k_hv_rows<false, true, 2, UPD> : k_hv_rows<false, false, 2, UPD>;
+        opt_in_lds(ctx, (const void*)rows, slot + 8 + (uu ? 1 : 0), kSplitLdsMax);
+        dim3 rg2((unsigned)((Dup + 1) / 2), (unsigned)ncol);
+        hipLaunchKernelGGL(rows, rg2, dim3(kHvThreads), 2 * lds, ctx->stream, T, x, x_col, y, y_col, up);
+    } else {
+        auto rows = uu ? k_hv_rows<false, true, 1, UPD> : k_hv_rows<false, false, 1, UPD>;
+        opt_in_lds(ctx, (const void*)rows, slot + 6 + (uu ? 1 : 0), kRowLdsMax);
+        hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col, up);
+    }
+    check_launch("k_hv_rows");
+}
+
+void launch_rows(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, bool uu, int ncol, double2* x, int64_t x_col,
+                 double2* y, int64_t y_col, const RowUpd* up, const SegInfo* sg, const void* segtab) {
+    if (up) launch_rows_t<true>(ctx, P, T, uu, ncol, x, x_col, y, y_col, *up, sg, segtab);
+    else launch_rows_t<false>(ctx, P, T, uu, ncol, x, x_col, y, y_col, RowUpd{}, sg, segtab);
+}
+
+// the plan of a two-pass launch with its segment choice filled in
+HvPlan with_seg(kgf_ctx* ctx, HModel model, const kgf_sector* sec, HvPlan P, const SegInfo** sg, const void** tab) {
+    *sg = plan_seg(ctx, model, sec, P);
+    P.seg = *sg != nullptr;
+    *tab = P.seg ? hop_table(model.m, sec->n_dn).segtab.p : nullptr;
+    return P;
 }
 
 template <int MODE>
@@ -1038,31 +1496,12 @@ void launch_hv(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int 
     if (P.passes == 2) {
         KGF_REQUIRE(P.up_blocks <= 0x7fffffff && (int64_t)model.m->nb * sec->d_dn < ((int64_t)1 << 32),
                     KGF_EUNSUPPORTED, "H.v: strip grid or hop table too large");
-        const size_t lds = P.split ? sizeof(double) * (size_t)sec->d_dn : sizeof(double2) * (size_t)sec->d_dn;
-        dim3 rg((unsigned)sec->d_up, (unsigned)ncol);
-        if (P.split) {
-            auto rows = uu ? k_hv_rows<true, true, 1> : k_hv_rows<true, false, 1>;
-            opt_in_lds(ctx, (const void*)rows, 4 + (uu ? 1 : 0), kSplitLdsMax);
-            hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
-        } else if (P.nr == 2 && 2 * lds <= kSplitLdsMax) {
-            auto rows = uu ? k_hv_rows<false, true, 2> : k_hv_rows<false, false, 2>;
-            opt_in_lds(ctx, (const void*)rows, 8 + (uu ? 1 : 0), kSplitLdsMax);
-            dim3 rg2((unsigned)((sec->d_up + 1) / 2), (unsigned)ncol);
-            hipLaunchKernelGGL(rows, rg2, dim3(kHvThreads), 2 * lds, ctx->stream, T, x, x_col, y, y_col);
-        } else {
-            auto rows = uu ? k_hv_rows<false, true, 1> : k_hv_rows<false, false, 1>;
-            opt_in_lds(ctx, (const void*)rows, 6 + (uu ? 1 : 0), kRowLdsMax);
-            hipLaunchKernelGGL(rows, rg, dim3(kHvThreads), lds, ctx->stream, T, x, x_col, y, y_col);
-        }
-        check_launch("k_hv_rows");
-        const int w = model.m->nb;
-        switch (P.C) {
-            case 64: launch_up<MODE, 64>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
-            case 32: launch_up<MODE, 32>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
-            case 16: launch_up<MODE, 16>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
-            default: launch_up<MODE, 8>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
-        }
-        check_launch("k_hv_up");
+        const SegInfo* sg;
+        const void* stab;
+        const HvPlan P1 = with_seg(ctx, model, sec, P, &sg, &stab);
+        launch_rows(ctx, P1, T, uu, ncol, const_cast<double2*>(x), x_col, y, y_col, nullptr, sg, stab);
+        launch_up_plan<MODE>(ctx, P, T, model.m->nb, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride,
+                             part);
         return;
     }
     dim3 grid((unsigned)sec->d_up, (unsigned)ncol);
@@ -1241,6 +1680,11 @@ void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec, const double2* v
     }
 }
 
+int hv_part_capacity(kgf_ctx* ctx, const kgf_sector* sec) {
+    // pass 1 of the fused step writes at most one partial per row
+    return (int)std::max<int64_t>(hv_lanczos_blocks(ctx, sec), sec->d_up);
+}
+
 int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec) {
     const HvPlan P = hv_plan(ctx, sec, 1);
     return P.passes == 2 ? (int)P.up_blocks : (int)sec->d_up;
@@ -1250,6 +1694,46 @@ void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a) {
     launch_hv<1>(ctx, model, sec, ncol, 0, a.x, a.x_col, a.xp, a.xp_col, a.y, a.y_col, a.s_k, a.b_k,
                  a.s_km1, a.stride, a.part);
+}
+
+int hv_lanczos_rows_blocks(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
+    const SegInfo* sg;
+    const void* stab;
+    const HvPlan P = hv_plan(ctx, sec, 1);
+    if (P.passes != 2) return 0;
+    return (int)rows_blocks(with_seg(ctx, model, sec, P, &sg, &stab), sec);
+}
+
+void hv_lanczos_rows(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosRowsArgs& a) {
+    const HvPlan P = hv_plan(ctx, sec, 1);
+    KGF_REQUIRE(P.passes == 2, KGF_EINVAL, "fused Lanczos step: the sector's H.v is not two-pass");
+    KGF_REQUIRE(sec->d_up <= 0x7ffffff0 && ncol <= 65535, KGF_EUNSUPPORTED, "H.v: grid too large");
+    HvTables T = make_tables(model, sec);
+    const SegInfo* sg;
+    const void* stab;
+    const HvPlan P1 = with_seg(ctx, model, sec, P, &sg, &stab);
+    // read y (and x_{k-1}), write x_k back and the pass-1 output
+    const double vec = 16.0 * (double)sec->dim() * ncol;
+    Prof pr(ctx, "hv_rows_lanczos", vec * (a.xp ? 4.0 : 2.0));
+    if (a.xp) {
+        const RowUpd up{a.xp, a.xp_col, a.fa, a.fs, a.stride, a.part};
+        launch_rows(ctx, P1, T, uniform_U(model), ncol, a.x, a.x_col, a.z, a.z_col, &up, sg, stab);
+    } else {
+        launch_rows(ctx, P1, T, uniform_U(model), ncol, a.x, a.x_col, a.z, a.z_col, nullptr, sg, stab);
+    }
+}
+
+void hv_lanczos_up(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosHvArgs& a) {
+    const HvPlan P = hv_plan(ctx, sec, 1);
+    KGF_REQUIRE(P.passes == 2, KGF_EINVAL, "fused Lanczos step: the sector's H.v is not two-pass");
+    KGF_REQUIRE(P.up_blocks <= 0x7fffffff && (int64_t)model.m->nb * sec->d_dn < ((int64_t)1 << 32),
+                KGF_EUNSUPPORTED, "H.v: strip grid or hop table too large");
+    HvTables T = make_tables(model, sec);
+    // read x (strips), the pass-1 output and x_{k-1}, write y
+    const double vec = 16.0 * (double)sec->dim() * ncol;
+    Prof pr(ctx, "hv_up_lanczos", vec * (a.xp ? 4.0 : 3.0));
+    launch_up_plan<1>(ctx, P, T, model.m->nb, ncol, a.x, a.x_col, a.xp, a.xp_col, a.y, a.y_col, a.s_k, a.b_k,
+                      a.s_km1, a.stride, a.part);
 }
 
 int n_theta(const kgf_model* model) { return model->nb + 3 * model->L; }

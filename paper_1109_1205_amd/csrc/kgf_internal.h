@@ -55,6 +55,29 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Segment form of one spin species' hopping for n particles (built on the
+// host by seg_table, hamiltonian.hip).  A mask s is split at bit S into its
+// high part H = s >> S and low part l = s & (2^S - 1); in ascending mask
+// order the states with one H are contiguous (a segment of C(S, n - |H|)
+// states, ascending in l).  A hop on a bond inside the low part moves the
+// rank by rank_lo(l') - rank_lo(l), a function of l alone; a hop inside the
+// high part by seg_off(H') - seg_off(H), a function of H alone; the few bonds
+// across the split are evaluated from seg_off and rank_lo.  One packed table
+// of 32-bit words (tens of KB) replaces the per-state ELL entries.
+struct SegInfo {
+    int S = -1;            // split bit; -1 = not built, 0 = not usable
+    int nl = 0, nh = 0;    // 2^S, 2^(L-S)
+    int wlo = 0, whi = 0;  // entry slots per low / high part
+    int ncross = 0;        // bonds across the split
+    int words = 0;         // packed table size (32-bit words)
+    // word offsets: lo [wlo][nl], hi [whi][nh] (delta | bond << 24 | sign << 31,
+    // delta a signed 24-bit rank offset); cnt_lo [nl] and cnt_hi [nh] (bytes);
+    // seg_off [nh] (int32, -1 where H has no segment); rank_lo [nl] (uint16);
+    // cross [ncross][4]: low bit | (high bit - S) << 8 | bond << 16, the low and
+    // the high mask of the sites strictly between, unused
+    int o_lo = 0, o_hi = 0, o_clo = 0, o_chi = 0, o_seg = 0, o_rank = 0, o_cross = 0;
+};
+
 // Per-spin tables of one particle number n for one model (hopping matrix
 // in ELL layout plus the on-site energy of each mask for either spin).
 struct HopTable {
@@ -67,6 +90,8 @@ struct HopTable {
     DevBuf e_up;     // double [D]  sum_i eps_up[i] bit_i
     DevBuf e_dn;     // double [D]  sum_i eps_dn[i] bit_i
     DevBuf bond;     // uint32 [nb * D] per bond: target rank | sign << 31, or ~0u
+    SegInfo seg;     // segment form (seg_table)
+    DevBuf segtab;   // its packed words
 };
 
 struct KernelStat {
@@ -101,6 +126,8 @@ struct kgf_ctx {
     // captured SIL steps (hipGraph), replayed when the same step recurs
     int use_graphs = 0;
     int lockstep = 1;                        // 1: uneven instance groups advance together (grouped launches)
+    int hv_fuse = 1;                         // 1: two-pass Lanczos steps fold the update into pass 1
+    int hv_seg = 1;                          // 1: pass 1 of the two-pass H.v uses the segment hop tables
     struct SilGraph {
         std::vector<unsigned char> key;
         hipGraphExec_t exec = nullptr;
@@ -192,6 +219,9 @@ HopTable& hop_table(kgf_model* model, int n);
 void upload_params(kgf_model* m);
 // after a parameter change: recompute the on-site energies of the built tables
 void refresh_onsite(kgf_model* model);
+// segment form of a spin species' hopping (built with its hopping table)
+const SegInfo& seg_table(kgf_model* model, int n);
+void build_seg_table(kgf_model* model, HopTable& ht);
 // replace a model's parameters in place (same L and bonds); waits for the
 // context's stream first, so that work already issued keeps the old values
 void model_set_params(kgf_model* m, const double* t, const double* eps_up, const double* eps_dn,
@@ -264,8 +294,34 @@ struct LanczosHvArgs {
     double* part;                          // [ncol][nblk]
 };
 int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec);
+// partials per column a Lanczos step may write (either pass of a fused step)
+int hv_part_capacity(kgf_ctx* ctx, const kgf_sector* sec);
 void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
                 const LanczosHvArgs& a);
+
+// Two-pass Lanczos step with the update of the previous step folded into
+// pass 1 (sectors whose H.v plan is two-pass).  Step k is
+//   rows: x_k = y - a_{k-1} s_{k-1} x_{k-1} written back over y (slot k),
+//         part[c][blk] = partials of ||x_k||^2 (-> b_k, s_k), and
+//         z = (down-spin hops + diagonal) x_k;  for k = 0 (xp null) x_0 is
+//         the state itself, read only;
+//   up:   y = s_k (z + T_up x_k) - b_k s_{k-1} x_{k-1} in place of z,
+//         part = Re <s_k x_k, y> (-> a_k)   (hv_lanczos_up with y = z).
+// The separate update pass (y -= a_k v_k, ||y||^2) is not needed: the rows
+// pass reads the rows it would touch anyway.
+struct LanczosRowsArgs {
+    double2* x; int64_t x_col;             // slot k (y in, x_k out when xp is set)
+    double2* z; int64_t z_col;             // pass-1 output (slot k + 1)
+    const double2* xp; int64_t xp_col;     // x_{k-1}, null for k = 0
+    const double* fa;                      // a_{k-1} (per column, * stride)
+    const double* fs;                      // s_{k-1}
+    int stride;
+    double* part;                          // [ncol][hv_lanczos_rows_blocks]
+};
+// pass-1 blocks (norm partials) per column; 0 when the plan is not two-pass
+int hv_lanczos_rows_blocks(kgf_ctx* ctx, HModel model, const kgf_sector* sec);
+void hv_lanczos_rows(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosRowsArgs& a);
+void hv_lanczos_up(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosHvArgs& a);
 
 // ---- krylov (krylov.hip) -------------------------------------------------
 // Per-column scalar block of the SIL recursion (doubles): offsets of b_k and

@@ -862,7 +862,7 @@ void sil_reserve(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reort
         workspace(ctx, "sil_X", xbytes);
     }
     const int NB = red_blocks(D);
-    const int HB = hv_lanczos_blocks(ctx, sec);
+    const int HB = hv_part_capacity(ctx, sec);   // partials of either H.v pass
     const int nper_max = NB > HB ? NB : HB;
     workspace(ctx, "sil_scal", sizeof(double) * kScalStride * ncol);
     workspace(ctx, "sil_part", sizeof(double) * (size_t)nper_max * ncol);
@@ -963,7 +963,7 @@ static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 static SilLayout sil_layout(kgf_ctx* ctx, const kgf_sector* sec, int ncol, int m, int reorth) {
     const int64_t D = sec->dim();
     const int NB = red_blocks(D);
-    const int HB = hv_lanczos_blocks(ctx, sec);
+    const int HB = hv_part_capacity(ctx, sec);   // partials of either H.v pass
     const int nper_max = NB > HB ? NB : HB;
     SilLayout l;
     l.x = 0;
@@ -997,6 +997,49 @@ static void sil_build_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, doubl
         check_launch("k_norm2");
     }
     launch_fin(ctx, FIN_INIT, 0, part, NB, scal, ncol, 0.0);
+    const int RB = (o.reorth == 0 && ctx->hv_fuse) ? hv_lanczos_rows_blocks(ctx, model, sec) : 0;
+    if (RB > 0) {
+        // two-pass H.v: the update of step k - 1 rides in the row pass of step k
+        for (int k = 0; k < m; ++k) {
+            LanczosRowsArgs r;
+            r.x = sl.at(k, 0);
+            r.x_col = k == 0 ? ld : D;
+            r.z = sl.at(k + 1, 0);
+            r.z_col = D;
+            r.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
+            r.xp_col = k - 1 == 0 ? ld : D;
+            r.fa = scal + kOffA + (k > 0 ? k - 1 : 0);
+            r.fs = scal + kOffS + (k > 0 ? k - 1 : 0);
+            r.stride = kScalStride;
+            r.part = part;
+            hv_lanczos_rows(ctx, model, sec, ncol, r);
+            if (k > 0) launch_fin(ctx, FIN_B, k - 1, part, RB, scal, ncol, o.breakdown_tol);
+            LanczosHvArgs a;
+            a.x = sl.at(k, 0);
+            a.x_col = k == 0 ? ld : D;
+            a.xp = k > 0 ? sl.at(k - 1, 0) : nullptr;
+            a.xp_col = k - 1 == 0 ? ld : D;
+            a.y = sl.at(k + 1, 0);
+            a.y_col = D;
+            a.s_k = scal + kOffS + k;
+            a.b_k = scal + kOffB + k;
+            a.s_km1 = scal + kOffS + (k > 0 ? k - 1 : 0);
+            a.stride = kScalStride;
+            a.part = part;
+            hv_lanczos_up(ctx, model, sec, ncol, a);
+            launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
+        }
+        if (w.err) {   // b_m for the error estimate
+            {
+                Prof pr(ctx, "lanczos_update", 48.0 * D * ncol);
+                hipLaunchKernelGGL(k_update, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, sl, m - 1,
+                                   scal + kOffA + m - 1, scal + kOffS + m - 1, kScalStride, D, part);
+                check_launch("k_update");
+            }
+            launch_fin(ctx, FIN_B, m - 1, part, NB, scal, ncol, o.breakdown_tol);
+        }
+        return;
+    }
     for (int k = 0; k < m; ++k) {
         LanczosHvArgs a;
         a.x = sl.at(k, 0);
@@ -1029,7 +1072,7 @@ static void sil_build_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, doubl
 static SilWork sil_work_ws(kgf_ctx* ctx, const kgf_sector* sec, int ncol, const SilOpts& o) {
     const int64_t D = sec->dim();
     const int NB = red_blocks(D);
-    const int HB = hv_lanczos_blocks(ctx, sec);
+    const int HB = hv_part_capacity(ctx, sec);   // partials of either H.v pass
     const int nper_max = NB > HB ? NB : HB;
     SilWork w;
     w.X = static_cast<double2*>(workspace(ctx, "sil_X", sizeof(double2) * (size_t)o.m * ncol * D));

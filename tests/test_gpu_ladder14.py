@@ -12,7 +12,9 @@ the launch shapes the benchmark times.
   Krylov dimension 20, dt = 0.05, backward direction as in step (iii)) on
   two columns in one batch -- the Lanczos-fused H.v, the three-term update,
   the tridiagonal exponential and the combination -- against the oracle's
-  sil_step element by element, <= 1e-12.
+  sil_step element by element, <= 1e-12; once through the single pass with
+  the update pass, once through the two passes with the update folded into
+  the row pass.
 Inputs are seeded host vectors (workloads.complex_vector)."""
 import numpy as np
 import pytest
@@ -63,13 +65,29 @@ def test_apply_h_ladder14_sampled_rows(ctx, oracle_h, passes):
         assert rel_err(got[c], ref) < 1e-13, c
 
 
-def test_sil_step_ladder14(ctx, oracle_h):
+@pytest.fixture(scope="module")
+def sil_ref(oracle_h):
     q, sec, H = oracle_h
     X = np.stack([wl.complex_vector(sec.dim, 150 + c) for c in range(2)])
-    say("ladder14 SIL step: GPU")
-    got = to_host(ctx.propagate(ctx.model(q.H), ctx.sector(14, 6, 7), to_dev(X), 1, q.dt, q.krylov_dim, +1))
+    refs = []
     for c in range(2):
         say("ladder14 SIL step: oracle column", c)
-        ref = propagate.sil_step(H.apply, X[c], q.dt, q.krylov_dim, +1, reorth="none")
-        assert rel_err(got[c], ref) < 1e-12, c
+        refs.append(propagate.sil_step(H.apply, X[c], q.dt, q.krylov_dim, +1, reorth="none"))
+    return X, np.stack(refs)
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_sil_step_ladder14(ctx, oracle_h, sil_ref, passes):
+    """passes 1: the single pass plus the update pass; passes 2: the two
+    passes with the update folded into the row pass (the fused step)."""
+    q, sec, H = oracle_h
+    X, ref = sil_ref
+    say("ladder14 SIL step: GPU, passes", passes)
+    ctx.set_option(PASSES, passes)
+    try:
+        got = to_host(ctx.propagate(ctx.model(q.H), ctx.sector(14, 6, 7), to_dev(X), 1, q.dt, q.krylov_dim, +1))
+    finally:
+        ctx.set_option(PASSES, 0)
+    for c in range(2):
+        assert rel_err(got[c], ref[c]) < 1e-12, c
 

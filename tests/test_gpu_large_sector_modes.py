@@ -20,7 +20,7 @@ from oracle import basis, hamiltonian, lanczos, propagate
 
 pytestmark = pytest.mark.gpu
 
-PASSES, STRIP, GS_MAX_BASIS, PHI_EVERY = 1, 2, 3, 4
+PASSES, STRIP, GS_MAX_BASIS, PHI_EVERY, HV_SEG = 1, 2, 3, 4, 11
 
 
 @pytest.fixture(scope="module")
@@ -44,23 +44,27 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("passes,strip", [(2, 0), (3, 0), (2, 8), (3, 16), (2, 32), (3, 64), (4, 0), (4, 16)])
+# seg 1: the row pass with the segment hop tables (the default); 0: per-state tables
+@pytest.mark.parametrize("passes,strip,seg", [(2, 0, 1), (3, 0, 1), (2, 8, 1), (3, 16, 1), (2, 32, 1), (3, 64, 1),
+                                              (4, 0, 1), (4, 16, 1), (2, 0, 0), (3, 0, 0), (4, 0, 0)])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_apply_h_variants(ctx, case, passes, strip):
+def test_apply_h_variants(ctx, case, passes, strip, seg):
     name, mk, nu, nd, nvec = case
     model = mk()
-    say("H.v variant", name, passes, strip)
+    say("H.v variant", name, passes, strip, seg)
     sec = basis.Sector(model.L, nu, nd)
     H = hamiltonian.Hamiltonian(model, sec)
     V = np.stack([wl.complex_vector(sec.dim, 10 + c) for c in range(nvec)])
     ref = np.stack([H.apply(V[c]) for c in range(nvec)])
     ctx.set_option(PASSES, passes)
     ctx.set_option(STRIP, strip)
+    ctx.set_option(HV_SEG, seg)
     try:
         got = to_host(ctx.apply_h(ctx.model(model), ctx.sector(model.L, nu, nd), to_dev(V)))
     finally:
         ctx.set_option(PASSES, 0)
         ctx.set_option(STRIP, 0)
+        ctx.set_option(HV_SEG, 1)
     assert rel_err(got, ref) < 1e-13
 
 
