@@ -108,11 +108,16 @@ void build_seg_table(kgf_model* model, HopTable& ht) {
         return;
     }
     const int S = best, nl = 1 << S, nh = 1 << (L - S);
-    // colex rank of every low part among the low parts of its popcount
-    std::vector<uint16_t> rank(nl);
+    // colex rank of every low part among the low parts of its popcount, and
+    // its position when the low parts are ordered by (popcount, rank): the
+    // low part tables are indexed by that position, so the consecutive
+    // elements of a segment read consecutive words
+    std::vector<int32_t> rank(nl), pos(nl), cls(S + 2, 0);
     {
         std::vector<int> seen(S + 1, 0);
-        for (int l = 0; l < nl; ++l) rank[l] = (uint16_t)seen[__builtin_popcount(l)]++;
+        for (int l = 0; l < nl; ++l) rank[l] = seen[__builtin_popcount(l)]++;
+        for (int k = 0; k <= S; ++k) cls[k + 1] = cls[k] + (int32_t)binom_host(S, k);
+        for (int l = 0; l < nl; ++l) pos[l] = cls[__builtin_popcount(l)] + rank[l];
     }
     std::vector<int32_t> seg(nh, -1);
     {
@@ -125,8 +130,11 @@ void build_seg_table(kgf_model* model, HopTable& ht) {
         }
     }
     auto between = [](int a, int c) -> uint32_t { return ((1u << c) - 1u) & ~((2u << a) - 1u); };
-    std::vector<std::vector<uint32_t>> lo(nl), hi(nh);
-    std::vector<uint32_t> cross;
+    auto entry = [](int32_t delta, int b, uint32_t sg) -> uint32_t {
+        return ((uint32_t)delta << 9) | (uint32_t)(2 * b) | sg;
+    };
+    std::vector<std::vector<uint32_t>> lo(nl), hi(nh), cl, ch;
+    std::vector<uint32_t> cbond;
     for (int b = 0; b < model->nb; ++b) {
         const int a = std::min(model->bi[b], model->bj[b]), c = std::max(model->bi[b], model->bj[b]);
         if (c < S) {
@@ -134,8 +142,7 @@ void build_seg_table(kgf_model* model, HopTable& ht) {
                 if ((((l >> a) ^ (l >> c)) & 1) == 0) continue;
                 const int l2 = l ^ (1 << a) ^ (1 << c);
                 const uint32_t sg = (uint32_t)(__builtin_popcount(l & between(a, c)) & 1);
-                const int32_t dl = (int32_t)rank[l2] - (int32_t)rank[l];
-                lo[l].push_back(((uint32_t)dl & 0xFFFFFFu) | ((uint32_t)b << 24) | (sg << 31));
+                lo[pos[l]].push_back(entry(rank[l2] - rank[l], b, sg));
             }
         } else if (a >= S) {
             const int a2 = a - S, c2 = c - S;
@@ -143,14 +150,31 @@ void build_seg_table(kgf_model* model, HopTable& ht) {
                 if (seg[H] < 0 || (((H >> a2) ^ (H >> c2)) & 1) == 0) continue;
                 const int H2 = H ^ (1 << a2) ^ (1 << c2);
                 const uint32_t sg = (uint32_t)(__builtin_popcount(H & between(a2, c2)) & 1);
-                const int32_t dl = seg[H2] - seg[H];
-                hi[H].push_back(((uint32_t)dl & 0xFFFFFFu) | ((uint32_t)b << 24) | (sg << 31));
+                hi[H].push_back(entry(seg[H2] - seg[H], b, sg));
             }
         } else {
-            cross.push_back((uint32_t)a | ((uint32_t)(c - S) << 8) | ((uint32_t)b << 16));
-            cross.push_back(((uint32_t)nl - 1u) & ~((2u << a) - 1u));   // low sites above a
-            cross.push_back((1u << (c - S)) - 1u);                      // high sites below c
-            cross.push_back(0u);
+            // across the split: low site a, high site c; the hop is there when
+            // exactly one of them is occupied, its offset is the sum of a low and
+            // a high part, its sign the parity of the occupied sites between
+            const int c2 = c - S;
+            const uint32_t mlo = ((uint32_t)nl - 1u) & ~((2u << a) - 1u), mhi = (1u << c2) - 1u;
+            std::vector<uint32_t> vl(nl, 0u), vh(nh, 0u);
+            for (int l = 0; l < nl; ++l) {
+                const int l2 = l ^ (1 << a);
+                const int32_t dl = rank[l2] - rank[l];
+                const uint32_t bit = (uint32_t)((l >> a) & 1), sg = (uint32_t)(__builtin_popcount(l & mlo) & 1);
+                vl[pos[l]] = ((uint32_t)dl << 2) | (bit << 1) | sg;
+            }
+            for (int H = 0; H < nh; ++H) {
+                const int H2 = H ^ (1 << c2);
+                const bool ok = seg[H] >= 0 && seg[H2] >= 0;
+                const int32_t dh = ok ? seg[H2] - seg[H] : 0;
+                const uint32_t bit = (uint32_t)((H >> c2) & 1), sg = (uint32_t)(__builtin_popcount(H & mhi) & 1);
+                vh[H] = ((uint32_t)dh << 2) | (bit << 1) | sg;
+            }
+            cl.push_back(vl);
+            ch.push_back(vh);
+            cbond.push_back((uint32_t)b);
         }
     }
     for (auto& v : lo) g.wlo = std::max(g.wlo, (int)v.size());
@@ -158,37 +182,38 @@ void build_seg_table(kgf_model* model, HopTable& ht) {
     g.S = S;
     g.nl = nl;
     g.nh = nh;
-    g.ncross = (int)cross.size() / 4;
+    g.ncross = (int)cbond.size();
     int w = 0;
     g.o_lo = w;
     w += g.wlo * nl;
     g.o_hi = w;
     w += g.whi * nh;
-    g.o_clo = w;
-    w += (nl + 3) / 4;
-    g.o_chi = w;
-    w += (nh + 3) / 4;
+    g.o_cl = w;
+    w += g.ncross * nl;
+    g.o_ch = w;
+    w += g.ncross * nh;
     g.o_seg = w;
     w += nh;
-    g.o_rank = w;
-    w += (nl + 1) / 2;
-    g.o_cross = w;
-    w += 4 * g.ncross;
+    g.o_cls = w;
+    w += S + 2;
+    g.o_cbond = w;
+    w += g.ncross;
     g.words = w;
+    const uint32_t pad = entry(0, 128, 0);   // amplitude slot 256: zero
     std::vector<uint32_t> tab((size_t)w, 0u);
-    uint8_t* clo = reinterpret_cast<uint8_t*>(tab.data() + g.o_clo);
-    uint8_t* chi = reinterpret_cast<uint8_t*>(tab.data() + g.o_chi);
-    for (int l = 0; l < nl; ++l) {
-        for (size_t k = 0; k < lo[l].size(); ++k) tab[g.o_lo + k * nl + l] = lo[l][k];
-        clo[l] = (uint8_t)lo[l].size();
-    }
-    for (int H = 0; H < nh; ++H) {
-        for (size_t k = 0; k < hi[H].size(); ++k) tab[g.o_hi + k * nh + H] = hi[H][k];
-        chi[H] = (uint8_t)hi[H].size();
+    for (int p = 0; p < nl; ++p)
+        for (int k = 0; k < g.wlo; ++k)
+            tab[g.o_lo + (size_t)k * nl + p] = k < (int)lo[p].size() ? lo[p][k] : pad;
+    for (int H = 0; H < nh; ++H)
+        for (int k = 0; k < g.whi; ++k)
+            tab[g.o_hi + (size_t)k * nh + H] = k < (int)hi[H].size() ? hi[H][k] : pad;
+    for (int q = 0; q < g.ncross; ++q) {
+        std::copy(cl[q].begin(), cl[q].end(), tab.begin() + g.o_cl + (size_t)q * nl);
+        std::copy(ch[q].begin(), ch[q].end(), tab.begin() + g.o_ch + (size_t)q * nh);
+        tab[g.o_cbond + q] = cbond[q];
     }
     std::memcpy(tab.data() + g.o_seg, seg.data(), sizeof(int32_t) * nh);
-    std::memcpy(tab.data() + g.o_rank, rank.data(), sizeof(uint16_t) * nl);
-    std::copy(cross.begin(), cross.end(), tab.begin() + g.o_cross);
+    std::memcpy(tab.data() + g.o_cls, cls.data(), sizeof(int32_t) * (S + 2));
     ht.segtab.reserve(sizeof(uint32_t) * tab.size());
     KGF_HIP(hipMemcpy(ht.segtab.p, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice));
     ht.seg = g;
@@ -776,22 +801,21 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_rows(HvTables T, double2* __r
 // ---------------------------------------------------------------------------
 struct SegDev {
     const uint32_t* tab;
-    int words, S, nl, nh, ncross;
-    int o_lo, o_hi, o_clo, o_chi, o_seg, o_rank, o_cross;
+    int words, S, nl, nh, wlo, whi, ncross;
+    int o_lo, o_hi, o_cl, o_ch, o_seg, o_cls, o_cbond;
 };
 
 struct SegView {
     const uint32_t* lo;
     const uint32_t* hi;
-    const uint8_t* clo;
-    const uint8_t* chi;
+    const uint32_t* cl;
+    const uint32_t* ch;
     const int32_t* seg;
-    const uint16_t* rank;
-    const uint32_t* cross;
-    int S, nl, nh, ncross;
+    const int32_t* cls;
+    const uint32_t* cbond;
+    const double* amp;     // [257]: 2 b -> -t_b, 2 b + 1 -> +t_b, 256 -> 0
+    int S, nl, nh, wlo, whi, ncross;
 };
-
-__device__ __forceinline__ int seg_delta(uint32_t e) { return ((int)(e << 8)) >> 8; }
 
 __device__ __forceinline__ void fma_acc(double& acc, double t, double z) { acc = fma(t, z, acc); }
 __device__ __forceinline__ void fma_acc(double2& acc, double t, double2 z) {
@@ -799,39 +823,35 @@ __device__ __forceinline__ void fma_acc(double2& acc, double t, double2 z) {
     acc.y = fma(t, z.y, acc.y);
 }
 
-
 // sum over the hops of row element d (mask s) of -t_b (-1)^sign x[target];
-// rd(i) reads the staged row (a double or a double2)
+// rd(i) reads the staged row (a double or a double2).  The loops run over
+// the padded table widths (uniform over the wavefront: no divergent trip
+// counts; a padding entry reads the element itself with amplitude zero).
 template <typename V, typename RD>
-__device__ __forceinline__ void seg_hops(V& acc, int d, uint32_t s, const SegView& G, const double* negt, RD rd) {
-    const uint32_t l = s & (uint32_t)(G.nl - 1), H = s >> G.S;
-    const int nlo = G.clo[l];
-#pragma unroll 1
-    for (int k = 0; k < nlo; ++k) {
-        const uint32_t e = G.lo[k * G.nl + (int)l];
-        const double v = negt[(e >> 24) & 127u];
-        fma_acc(acc, (e >> 31) ? -v : v, rd(d + seg_delta(e)));
+__device__ __forceinline__ void seg_hops(V& acc, int d, uint32_t s, const SegView& G, RD rd) {
+    const int l = (int)(s & (uint32_t)(G.nl - 1)), H = (int)(s >> G.S);
+    const int p = d - G.seg[H] + G.cls[__popc((uint32_t)l)];
+    for (int k = 0; k < G.wlo; ++k) {
+        const uint32_t e = G.lo[k * G.nl + p];
+        fma_acc(acc, G.amp[e & 511u], rd(d + ((int)e >> 9)));
     }
-    const int nhi = G.chi[H];
-#pragma unroll 1
-    for (int k = 0; k < nhi; ++k) {
-        const uint32_t e = G.hi[k * G.nh + (int)H];
-        const double v = negt[(e >> 24) & 127u];
-        fma_acc(acc, (e >> 31) ? -v : v, rd(d + seg_delta(e)));
+    for (int k = 0; k < G.whi; ++k) {
+        const uint32_t e = G.hi[k * G.nh + H];
+        fma_acc(acc, G.amp[e & 511u], rd(d + ((int)e >> 9)));
     }
-#pragma unroll 1
     for (int k = 0; k < G.ncross; ++k) {
-        const uint32_t w0 = G.cross[4 * k];
-        const uint32_t a = w0 & 255u, ch = (w0 >> 8) & 255u;
-        if ((((l >> a) ^ (H >> ch)) & 1u) == 0u) continue;
-        const uint32_t l2 = l ^ (1u << a), H2 = H ^ (1u << ch);
-        const int sg = (__popc(l & G.cross[4 * k + 1]) + __popc(H & G.cross[4 * k + 2])) & 1;
-        const double v = negt[(w0 >> 16) & 127u];
-        fma_acc(acc, sg ? -v : v, rd(G.seg[H2] + (int)G.rank[l2]));
+        const uint32_t a = G.cl[k * G.nl + p], b = G.ch[k * G.nh + H];
+        const uint32_t x = a ^ b;
+        const bool on = (x & 2u) != 0u;
+        const int slot = on ? (int)(2u * G.cbond[k] + (x & 1u)) : 256;
+        const int delta = on ? ((int)a >> 2) + ((int)b >> 2) : 0;
+        fma_acc(acc, G.amp[slot], rd(d + delta));
     }
 }
 
-constexpr size_t kSegLdsMax = 160 * 1024 - 8 * 1024;   // dynamic LDS of the segment row kernel
+// dynamic LDS of the segment row kernel: 160 KB less its static arrays
+// (amplitudes 2 KB, U byte tables 6 KB, partial sums)
+constexpr size_t kSegLdsMax = 160 * 1024 - 9 * 1024;
 
 // bytes of the staged row, rounded to 16
 __host__ __device__ __forceinline__ size_t seg_row_bytes(int64_t Ddn, bool split) {
@@ -843,7 +863,7 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
                                                             int64_t x_col, double2* __restrict__ Y, int64_t y_col,
                                                             RowUpd up) {
     extern __shared__ double2 srow[];
-    __shared__ double s_negt[kMaxBonds + 1];
+    __shared__ double s_amp[257];
     __shared__ double s_U[UNIFORM_U ? 1 : 3 * 256];
     __shared__ double s_red[NT / 64];
     const int c = blockIdx.y;
@@ -852,20 +872,27 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
     const int par = par_index(T, c);
     uint32_t* stab = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(srow) + seg_row_bytes(Ddn, SPLIT));
     for (int i = tid; i < G.words; i += blockDim.x) stab[i] = G.tab[i];
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par * T.nb + b];
+    for (int i = tid; i < 257; i += blockDim.x) {
+        const int b = i >> 1;
+        const double t = (i < 256 && b < T.nb) ? T.t[par * T.nb + b] : 0.0;
+        s_amp[i] = (i & 1) ? t : -t;
+    }
     if (!UNIFORM_U)
         for (int i = tid; i < 3 * 256; i += blockDim.x) s_U[i] = T.Utab[par * 768 + i];
     SegView V;
     V.lo = stab + G.o_lo;
     V.hi = stab + G.o_hi;
-    V.clo = reinterpret_cast<const uint8_t*>(stab + G.o_clo);
-    V.chi = reinterpret_cast<const uint8_t*>(stab + G.o_chi);
+    V.cl = stab + G.o_cl;
+    V.ch = stab + G.o_ch;
     V.seg = reinterpret_cast<const int32_t*>(stab + G.o_seg);
-    V.rank = reinterpret_cast<const uint16_t*>(stab + G.o_rank);
-    V.cross = stab + G.o_cross;
+    V.cls = reinterpret_cast<const int32_t*>(stab + G.o_cls);
+    V.cbond = stab + G.o_cbond;
+    V.amp = s_amp;
     V.S = G.S;
     V.nl = G.nl;
     V.nh = G.nh;
+    V.wlo = G.wlo;
+    V.whi = G.whi;
     V.ncross = G.ncross;
     const double fup = UPD ? up.fa[(int64_t)c * up.stride] * up.fs[(int64_t)c * up.stride] : 0.0;
     const double U0 = par_U0(T, par);
@@ -911,7 +938,7 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
                 if (d < Ddn) {
                     const uint32_t md = T.md[d];
                     double acc = diag(ed[d], md) * sh[d];
-                    seg_hops(acc, d, md, V, s_negt, rd);
+                    seg_hops(acc, d, md, V, rd);
                     are[j] = acc;
                 }
 
@@ -929,7 +956,7 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
                 if (d < Ddn) {
                     const uint32_t md = T.md[d];
                     double acc = diag(ed[d], md) * xim[j];
-                    seg_hops(acc, d, md, V, s_negt, rd);
+                    seg_hops(acc, d, md, V, rd);
                     st_stream(yrow + d, make_double2(are[j], acc));
                 }
             }
@@ -943,7 +970,7 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
                 const double2 xv = srow[d];
                 const double dg = diag(ed[d], md);
                 double2 acc = make_double2(dg * xv.x, dg * xv.y);
-                seg_hops(acc, d, md, V, s_negt, rd);
+                seg_hops(acc, d, md, V, rd);
                 st_stream(yrow + d, acc);
             }
             __syncthreads();
@@ -1410,14 +1437,16 @@ void launch_rows_t(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, bool uu, in
         G.S = sg->S;
         G.nl = sg->nl;
         G.nh = sg->nh;
+        G.wlo = sg->wlo;
+        G.whi = sg->whi;
         G.ncross = sg->ncross;
         G.o_lo = sg->o_lo;
         G.o_hi = sg->o_hi;
-        G.o_clo = sg->o_clo;
-        G.o_chi = sg->o_chi;
+        G.o_cl = sg->o_cl;
+        G.o_ch = sg->o_ch;
         G.o_seg = sg->o_seg;
-        G.o_rank = sg->o_rank;
-        G.o_cross = sg->o_cross;
+        G.o_cls = sg->o_cls;
+        G.o_cbond = sg->o_cbond;
         const size_t dyn = seg_row_bytes(Ddn, P.split) + sizeof(uint32_t) * (size_t)sg->words;
         dim3 sgrid((unsigned)std::min<int64_t>(Dup, kSegBlocks), (unsigned)ncol);
         // split form: 13 row elements per thread cover the 2x8 ladder's 12,870

@@ -56,26 +56,29 @@ struct DevBuf {
 };
 
 // Segment form of one spin species' hopping for n particles (built on the
-// host by seg_table, hamiltonian.hip).  A mask s is split at bit S into its
-// high part H = s >> S and low part l = s & (2^S - 1); in ascending mask
-// order the states with one H are contiguous (a segment of C(S, n - |H|)
-// states, ascending in l).  A hop on a bond inside the low part moves the
-// rank by rank_lo(l') - rank_lo(l), a function of l alone; a hop inside the
-// high part by seg_off(H') - seg_off(H), a function of H alone; the few bonds
-// across the split are evaluated from seg_off and rank_lo.  One packed table
-// of 32-bit words (tens of KB) replaces the per-state ELL entries.
+// host with the hopping table, hamiltonian.hip build_seg_table).  A mask s
+// is split at bit S into its high part H = s >> S and low part l = s &
+// (2^S - 1); in ascending mask order the states with one H are contiguous
+// (a segment of C(S, n - |H|) states, ascending in l).  A hop on a bond
+// inside the low part moves the rank by rank_lo(l') - rank_lo(l), a function
+// of l alone; a hop inside the high part by seg_off(H') - seg_off(H), a
+// function of H alone; a hop on a bond across the split by the sum of one
+// low and one high part.  One packed table of 32-bit words (tens of KB)
+// replaces the per-state ELL entries.
 struct SegInfo {
     int S = -1;            // split bit; -1 = not built, 0 = not usable
     int nl = 0, nh = 0;    // 2^S, 2^(L-S)
-    int wlo = 0, whi = 0;  // entry slots per low / high part
+    int wlo = 0, whi = 0;  // entry slots per low / high part (padded)
     int ncross = 0;        // bonds across the split
     int words = 0;         // packed table size (32-bit words)
-    // word offsets: lo [wlo][nl], hi [whi][nh] (delta | bond << 24 | sign << 31,
-    // delta a signed 24-bit rank offset); cnt_lo [nl] and cnt_hi [nh] (bytes);
-    // seg_off [nh] (int32, -1 where H has no segment); rank_lo [nl] (uint16);
-    // cross [ncross][4]: low bit | (high bit - S) << 8 | bond << 16, the low and
-    // the high mask of the sites strictly between, unused
-    int o_lo = 0, o_hi = 0, o_clo = 0, o_chi = 0, o_seg = 0, o_rank = 0, o_cross = 0;
+    // word offsets.  lo [wlo][nl] (indexed by the low part's position p in
+    // (popcount, rank) order) and hi [whi][nh]: delta << 9 | amplitude slot,
+    // delta a signed rank offset, slot 2 bond + sign (256: padding, zero);
+    // cl [ncross][nl] (by p) and ch [ncross][nh]: delta << 2 | occupied << 1 |
+    // parity of the occupied sites between; seg [nh] (int32 segment offsets,
+    // -1 where H has no segment); cls [S + 2] (first position of each
+    // popcount); cbond [ncross] (bond index)
+    int o_lo = 0, o_hi = 0, o_cl = 0, o_ch = 0, o_seg = 0, o_cls = 0, o_cbond = 0;
 };
 
 // Per-spin tables of one particle number n for one model (hopping matrix
