@@ -96,6 +96,8 @@ def parse():
                         "folded into the row pass)")
     p.add_argument("--hv-seg", default="1",
                    help="comma-separated kgf_set_option HV_SEG values (row pass with the segment hop tables)")
+    p.add_argument("--hv-up-threads", default="1024",
+                   help="comma-separated kgf_set_option HV_UP_THREADS values (pass-2 block size)")
     p.add_argument("--hv-reps", type=int, default=10)
     p.add_argument("--no-graphs", action="store_true",
                    help="state GRAPHS 0 explicitly (every SIL step eager, the library default); kernel traces "
@@ -121,19 +123,20 @@ def hv_bench(a):
         g = torch.Generator(device="cuda:0").manual_seed(11)
         x = torch.randn(sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
         y = torch.empty_like(x)
-        variants = [(int(p_), int(s_), int(f_), int(g_)) for p_ in a.hv_passes.split(",") if p_
+        variants = [(int(p_), int(s_), int(f_), int(g_), int(q_)) for p_ in a.hv_passes.split(",") if p_
                     for s_ in a.hv_strip.split(",") if s_ for f_ in a.hv_fuse.split(",") if f_
-                    for g_ in a.hv_seg.split(",") if g_]
-        for passes, strip, fuse, seg in variants:
+                    for g_ in a.hv_seg.split(",") if g_ for q_ in a.hv_up_threads.split(",") if q_]
+        for passes, strip, fuse, seg, uthr in variants:
             # passes 9: let the library's tuner choose (HV_TUNE)
             ctx.set_option(ctx.HV_TUNE, 1 if passes == 9 else 0)
             ctx.set_option(ctx.HV_PASSES, 0 if passes == 9 else passes)
             ctx.set_option(ctx.HV_STRIP, 0 if passes == 9 else strip)
             ctx.set_option(ctx.HV_FUSE, fuse)
             ctx.set_option(ctx.HV_SEG, seg)
+            ctx.set_option(ctx.HV_UP_THREADS, uthr)
             ctx.apply_h(m, sec, x, y)      # warm-up (tables, LDS opt-in)
             torch.cuda.synchronize()
-            log(f"L={L} D={sec.dim} passes={passes} strip={strip} fuse={fuse} seg={seg}: timing")
+            log(f"L={L} D={sec.dim} passes={passes} strip={strip} fuse={fuse} seg={seg} up_threads={uthr}: timing")
             ctx.profile_begin(1)
             for _ in range(a.hv_reps):
                 ctx.apply_h(m, sec, x, y)
@@ -141,7 +144,8 @@ def hv_bench(a):
             ctx.propagate(m, sec, xs, 1, q.dt, q.krylov_dim, +1)
             torch.cuda.synchronize()
             st = ctx.profile_end()
-            out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip, "fuse": fuse, "seg": seg}
+            out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip, "fuse": fuse, "seg": seg,
+                   "up_threads": uthr}
             for k in ("hv", "hv_lanczos", "hv_rows_lanczos", "hv_up_lanczos", "lanczos_update", "combine"):
                 if k in st and st[k]["sampled"]:
                     ms = st[k]["sampled_ms"] / st[k]["sampled"]
@@ -154,6 +158,7 @@ def hv_bench(a):
         ctx.set_option(ctx.HV_TUNE, 0)
         ctx.set_option(ctx.HV_FUSE, 1)
         ctx.set_option(ctx.HV_SEG, 1)
+        ctx.set_option(ctx.HV_UP_THREADS, 1024)
         del x, y
         torch.cuda.empty_cache()
 

@@ -661,11 +661,14 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      state and hop); used when at most 8 bonds cross the
  *                      split and the row and tables fit in LDS.  0 = the
  *                      per-state tables.  Results agree to rounding.
+ *   KGF_OPT_HV_UP_THREADS: threads per block of pass 2 of the two-pass H.v
+ *                      (256, 512 or 1024 = default; a block covers threads / C
+ *                      rows of one strip).  Results are independent of it.
  * Returns KGF_EINVAL for an unknown option or value.  Not to be changed while
  * work issued by this context is in flight. */
 enum { KGF_OPT_HV_PASSES = 1, KGF_OPT_HV_STRIP = 2, KGF_OPT_GS_MAX_BASIS = 3, KGF_OPT_PHI_EVERY = 4, KGF_OPT_ADJ_EVERY = 5,
        KGF_OPT_HV_TUNE = 6, KGF_OPT_CG_MAX_ITER = 7, KGF_OPT_GRAPHS = 8, KGF_OPT_LOCKSTEP = 9,
-       KGF_OPT_HV_FUSE = 10, KGF_OPT_HV_SEG = 11 };
+       KGF_OPT_HV_FUSE = 10, KGF_OPT_HV_SEG = 11, KGF_OPT_HV_UP_THREADS = 12 };
 int  kgf_set_option(kgf_ctx* ctx, int option, int value);
 
 /* ---- device-side timing of the library's kernels --------------------------

@@ -639,6 +639,10 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
         } else if (option == KGF_OPT_HV_SEG) {
             KGF_REQUIRE(value == 0 || value == 1, KGF_EINVAL, "kgf_set_option: HV_SEG must be 0 or 1");
             ctx->hv_seg = value;
+        } else if (option == KGF_OPT_HV_UP_THREADS) {
+            KGF_REQUIRE(value == 256 || value == 512 || value == 1024, KGF_EINVAL,
+                        "kgf_set_option: HV_UP_THREADS must be 256, 512 or 1024");
+            ctx->hv_up_threads = value;
         } else {
             fail(KGF_EINVAL, "kgf_set_option: unknown option");
         }

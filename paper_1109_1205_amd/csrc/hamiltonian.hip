@@ -982,26 +982,25 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
     }
 }
 
-constexpr int kUpThreads = 256;
 
 // Pass 2.  A block covers R = 256 / C rows of one strip; the packed hop
 // entries of its rows are staged in LDS first, so that each thread's source
 // gathers (rows x[u', strip]) are issued back to back.  With one row group
 // per block, the blocks an XCD holds at a time span about one strip.
 // MODE 0: y += T_up x.   MODE 1: y = s (y + T_up x) - bp xp, part = Re <s x, y>.
-template <int MODE, int C>
-__global__ __launch_bounds__(kUpThreads) void k_hv_up(HvTables T, int nstrip, int ntile, int width,
-                                                      const double2* __restrict__ X, int64_t x_col,
-                                                      const double2* __restrict__ XP, int64_t xp_col,
-                                                      double2* __restrict__ Y, int64_t y_col,
-                                                      const double* __restrict__ s_k, const double* __restrict__ b_k,
-                                                      const double* __restrict__ s_km1, int stride,
-                                                      double* __restrict__ part) {
-    constexpr int R = kUpThreads / C;
+template <int MODE, int C, int NT>
+__global__ __launch_bounds__(NT) void k_hv_up(HvTables T, int nstrip, int ntile, int width,
+                                              const double2* __restrict__ X, int64_t x_col,
+                                              const double2* __restrict__ XP, int64_t xp_col,
+                                              double2* __restrict__ Y, int64_t y_col,
+                                              const double* __restrict__ s_k, const double* __restrict__ b_k,
+                                              const double* __restrict__ s_km1, int stride,
+                                              double* __restrict__ part) {
+    constexpr int R = NT / C;
     extern __shared__ uint32_t s_ent[];            // [R][width]
     __shared__ int s_cnt[R];
     __shared__ double s_negt[kMaxBonds + 1];
-    __shared__ double s_red[kUpThreads / 64];
+    __shared__ double s_red[NT / 64];
     const int blk = blockIdx.x;
     const int q = blk >> 3;
     const int strip = (q / ntile) * 8 + (blk & 7);
@@ -1010,27 +1009,39 @@ __global__ __launch_bounds__(kUpThreads) void k_hv_up(HvTables T, int nstrip, in
     const int tid = threadIdx.x;
     const int64_t Ddn = T.Ddn, Dup = T.Dup;
     const int64_t u0 = (int64_t)tile * R;
-    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
-    for (int i = tid; i < R * width; i += blockDim.x) {
-        const int r = i % R, k = i / R;
-        const int64_t u = u0 + r;
-        s_ent[r * width + k] = u < Dup ? T.ent_up[(int64_t)k * Dup + u] : 0u;
-    }
-    if (tid < R) s_cnt[tid] = u0 + tid < Dup ? T.cnt_up[u0 + tid] : 0;
-    __syncthreads();
+    const int r = tid / C;
+    const int64_t u = u0 + r;
+    const int64_t d = (int64_t)strip * C + (tid % C);
+    const bool live = strip < nstrip && u < Dup && d < Ddn;
+    const double2* __restrict__ x = X + c * x_col;
+    double2* __restrict__ y = Y + c * y_col;
+    const int64_t ix = u * Ddn + d;
+    // the element's own single-use streams first, so that they are in flight
+    // while the hop entries are staged and the source rows gathered
+    double2 w = make_double2(0.0, 0.0), p = make_double2(0.0, 0.0), xv = make_double2(0.0, 0.0);
     double sc = 1.0, bp = 0.0;
     if (MODE == 1) {
         sc = s_k[c * stride];
         if (XP) bp = b_k[c * stride] * s_km1[c * stride];
     }
-    const int r = tid / C;
-    const int64_t u = u0 + r;
-    const int64_t d = (int64_t)strip * C + (tid % C);
-    const double2* __restrict__ x = X + c * x_col;
-    double2* __restrict__ y = Y + c * y_col;
+    if (live) {
+        w = ld_stream(y + ix);
+        if (MODE == 1) {
+            xv = x[ix];
+            if (bp != 0.0) p = ld_stream(XP + c * xp_col + ix);
+        }
+    }
+    for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
+    for (int i = tid; i < R * width; i += blockDim.x) {
+        const int rr = i % R, k = i / R;
+        const int64_t uu = u0 + rr;
+        s_ent[rr * width + k] = uu < Dup ? T.ent_up[(int64_t)k * Dup + uu] : 0u;
+    }
+    if (tid < R) s_cnt[tid] = u0 + tid < Dup ? T.cnt_up[u0 + tid] : 0;
+    __syncthreads();
     double dot = 0.0;
     constexpr int kBatch = 8;
-    if (strip < nstrip && u < Dup && d < Ddn) {
+    if (live) {
         const int cu = s_cnt[r];
         const uint32_t* er = s_ent + r * width;
         double ar = 0.0, ai = 0.0;
@@ -1049,27 +1060,23 @@ __global__ __launch_bounds__(kUpThreads) void k_hv_up(HvTables T, int nstrip, in
                     ai = fma(tv, z[j].y, ai);
                 }
         }
-        const int64_t i = u * Ddn + d;
-        double2 w = ld_stream(y + i);
         w.x += ar;
         w.y += ai;
         if (MODE == 1) {
             w.x *= sc;
             w.y *= sc;
             if (bp != 0.0) {
-                const double2 p = ld_stream(XP + c * xp_col + i);
                 w.x = fma(-bp, p.x, w.x);
                 w.y = fma(-bp, p.y, w.y);
             }
-            const double2 xv = x[i];
             dot = fma(sc * xv.x, w.x, dot);
             dot = fma(sc * xv.y, w.y, dot);
         }
-        st_stream(y + i, w);
+        st_stream(y + ix, w);
     }
     if (MODE == 1) {
-        const double s = block_sum(dot, s_red);
-        if (tid == 0) part[(int64_t)c * gridDim.x + blk] = s;
+        const double sum = block_sum(dot, s_red);
+        if (tid == 0) part[(int64_t)c * gridDim.x + blk] = sum;
     }
 }
 
@@ -1325,12 +1332,13 @@ struct HvPlan {
     int C = 8;
     int nstrip = 0, ntile = 0;
     int64_t up_blocks = 0;
+    int up_threads = 256;   // pass-2 block size (R = up_threads / C rows per block)
 };
 
 constexpr size_t kStripL2Bytes = 6 * 1024 * 1024;   // widest strip up to this slab size (measured)
 
 // The plan for an explicit request (passes 0..3, strip 0/8..64; 0 = by size).
-HvPlan make_plan(const kgf_sector* sec, int ov, int strip) {
+HvPlan make_plan(const kgf_sector* sec, int ov, int strip, int up_threads) {
     HvPlan p;
     const int64_t Dup = sec->d_up, Ddn = sec->d_dn;
     const size_t row = sizeof(double2) * (size_t)Ddn;
@@ -1349,7 +1357,8 @@ HvPlan make_plan(const kgf_sector* sec, int ov, int strip) {
                 break;
             }
         if (strip) p.C = strip;
-        const int R = kUpThreads / p.C;
+        p.up_threads = up_threads;
+        const int R = p.up_threads / p.C;
         p.nstrip = (int)((Ddn + p.C - 1) / p.C);
         p.ntile = (int)((Dup + R - 1) / R);
         p.up_blocks = 8 * (int64_t)((p.nstrip + 7) / 8) * p.ntile;
@@ -1361,22 +1370,34 @@ std::array<int, 4> tune_key(const kgf_sector* sec, int mode) { return {sec->L, s
 
 // Explicit options win; then a tuned choice (kgf_set_option HV_TUNE); then sizes.
 HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec, int mode) {
-    if (ctx->hv_passes || ctx->hv_strip) return make_plan(sec, ctx->hv_passes, ctx->hv_strip);
+    const int ut = ctx->hv_up_threads;
+    if (ctx->hv_passes || ctx->hv_strip) return make_plan(sec, ctx->hv_passes, ctx->hv_strip, ut);
     if (ctx->hv_tune) {
         auto it = ctx->hv_tuned.find(tune_key(sec, mode));
-        if (it != ctx->hv_tuned.end()) return make_plan(sec, it->second.first, it->second.second);
+        if (it != ctx->hv_tuned.end()) return make_plan(sec, it->second.first, it->second.second, ut);
     }
-    return make_plan(sec, 0, 0);
+    return make_plan(sec, 0, 0, ut);
+}
+
+template <int MODE, int C, int NT>
+void launch_up_nt(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int width, int ncol, const double2* x,
+                  int64_t x_col, const double2* xp, int64_t xp_col, double2* y, int64_t y_col, const double* s_k,
+                  const double* b_k, const double* s_km1, int stride, double* part) {
+    const size_t lds = sizeof(uint32_t) * (size_t)(NT / C) * width;
+    hipLaunchKernelGGL((k_hv_up<MODE, C, NT>), dim3((unsigned)P.up_blocks, (unsigned)ncol), dim3(NT), lds,
+                       ctx->stream, T, P.nstrip, P.ntile, width, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1,
+                       stride, part);
 }
 
 template <int MODE, int C>
 void launch_up(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int width, int ncol, const double2* x,
                int64_t x_col, const double2* xp, int64_t xp_col, double2* y, int64_t y_col, const double* s_k,
                const double* b_k, const double* s_km1, int stride, double* part) {
-    const size_t lds = sizeof(uint32_t) * (size_t)(kUpThreads / C) * width;
-    hipLaunchKernelGGL((k_hv_up<MODE, C>), dim3((unsigned)P.up_blocks, (unsigned)ncol), dim3(kUpThreads), lds,
-                       ctx->stream, T, P.nstrip, P.ntile, width, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1,
-                       stride, part);
+    switch (P.up_threads) {
+        case 1024: launch_up_nt<MODE, C, 1024>(ctx, P, T, width, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+        case 512: launch_up_nt<MODE, C, 512>(ctx, P, T, width, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+        default: launch_up_nt<MODE, C, 256>(ctx, P, T, width, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
+    }
 }
 
 template <int MODE>
@@ -1639,7 +1660,7 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         std::vector<HvPlan> plans;
         const std::pair<int, int> reqs[] = {{1, 0}, {2, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}, {4, 0}, {4, 16}, {4, 32}};
         for (const auto& rq : reqs) {
-            const HvPlan P = make_plan(sec, rq.first, rq.second);
+            const HvPlan P = make_plan(sec, rq.first, rq.second, ctx->hv_up_threads);
             if (P.passes == 0) continue;
             bool dup = false;
             for (const auto& q : plans)

@@ -131,6 +131,7 @@ struct kgf_ctx {
     int lockstep = 1;                        // 1: uneven instance groups advance together (grouped launches)
     int hv_fuse = 1;                         // 1: two-pass Lanczos steps fold the update into pass 1
     int hv_seg = 1;                          // 1: pass 1 of the two-pass H.v uses the segment hop tables
+    int hv_up_threads = 1024;                // block size of pass 2 of the two-pass H.v (256, 512, 1024)
     struct SilGraph {
         std::vector<unsigned char> key;
         hipGraphExec_t exec = nullptr;

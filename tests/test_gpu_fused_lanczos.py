@@ -18,7 +18,7 @@ from oracle import basis, hamiltonian, propagate
 
 pytestmark = pytest.mark.gpu
 
-PASSES, STRIP, HV_FUSE = 1, 2, 10
+PASSES, STRIP, HV_FUSE, HV_UP_THREADS = 1, 2, 10, 12
 
 CASES = [
     ("ring8", lambda: wl.ring8().H, 4, 4, 2),
@@ -40,12 +40,14 @@ def ctx():
     c.set_option(PASSES, 0)
     c.set_option(STRIP, 0)
     c.set_option(HV_FUSE, 1)
+    c.set_option(HV_UP_THREADS, 1024)
 
 
-def _run(ctx, model, nu, nd, X, passes, strip, fuse, nsteps, m, err=False):
+def _run(ctx, model, nu, nd, X, passes, strip, fuse, nsteps, m, err=False, up_threads=256):
     ctx.set_option(PASSES, passes)
     ctx.set_option(STRIP, strip)
     ctx.set_option(HV_FUSE, fuse)
+    ctx.set_option(HV_UP_THREADS, up_threads)
     try:
         out = ctx.propagate(ctx.model(model), ctx.sector(model.L, nu, nd), to_dev(X), nsteps, 0.07, m, -1, 0.0, 0,
                             return_err=err)
@@ -53,25 +55,28 @@ def _run(ctx, model, nu, nd, X, passes, strip, fuse, nsteps, m, err=False):
         ctx.set_option(PASSES, 0)
         ctx.set_option(STRIP, 0)
         ctx.set_option(HV_FUSE, 1)
+        ctx.set_option(HV_UP_THREADS, 1024)
     if err:
         return to_host(out[0]), out[1]
     return to_host(out)
 
 
-@pytest.mark.parametrize("passes,strip", [(2, 0), (3, 0), (4, 16), (2, 8)])
+# up_threads: pass-2 block size
+@pytest.mark.parametrize("passes,strip,up_threads", [(2, 0, 256), (3, 0, 256), (4, 16, 256), (2, 8, 256),
+                                                     (2, 0, 1024), (3, 16, 512)])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_fused_sil_matches_oracle(ctx, case, passes, strip):
+def test_fused_sil_matches_oracle(ctx, case, passes, strip, up_threads):
     name, mk, nu, nd, ncol = case
     model = mk()
     sec = basis.Sector(model.L, nu, nd)
     H = hamiltonian.Hamiltonian(model, sec)
     m = min(12, max(sec.dim, 1))
     X = np.stack([wl.complex_vector(sec.dim, 60 + c) for c in range(ncol)])
-    say("fused SIL", name, passes, strip)
+    say("fused SIL", name, passes, strip, up_threads)
     ref = np.stack([propagate.propagate(H.apply, X[c], 0.07, 2, m, -1, 0.0, "none") for c in range(ncol)])
-    got = _run(ctx, model, nu, nd, X, passes, strip, 1, 2, m)
+    got = _run(ctx, model, nu, nd, X, passes, strip, 1, 2, m, up_threads=up_threads)
     assert rel_err(got, ref) < 1e-12
-    unfused = _run(ctx, model, nu, nd, X, passes, strip, 0, 2, m)
+    unfused = _run(ctx, model, nu, nd, X, passes, strip, 0, 2, m, up_threads=up_threads)
     assert rel_err(got, unfused) < 1e-13
 
 
