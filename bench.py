@@ -83,6 +83,10 @@ def parse():
     p.add_argument("--skip-per-instance", action="store_true",
                    help="batch64: skip the per-instance forward timing")
     p.add_argument("--nt16", type=int, default=6, help="ladder16: mesh points")
+    p.add_argument("--spg16", type=int, default=1, help="ladder16: SIL steps of dt = 0.05 per mesh interval")
+    p.add_argument("--adj16", type=int, default=0,
+                   help="ladder16: also the adjoint gradient (all hoppings, U, fields) of a loss of G_00 on a mesh "
+                        "of this many points (0: none), chains checkpointed every 10 SIL steps")
     p.add_argument("--plain-baseline", action="store_true",
                    help="batch64: also time the plain single-vector method (schedule 0) instance by instance")
     p.add_argument("--hv", default="",
@@ -354,22 +358,55 @@ def ladder16(a):
     ctx.profile_begin(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = ctx.greens_neq(ctx.model(q.H_ini), ctx.model(q.H), s, v0, orbitals=q.orbitals, nt=nt, steps_per_grid=1,
+    spg = a.spg16
+    out = ctx.greens_neq(ctx.model(q.H_ini), ctx.model(q.H), s, v0, orbitals=q.orbitals, nt=nt, steps_per_grid=spg,
                          dt=q.dt, krylov_dim=q.krylov_dim, schedule=1, gs_tol=q.gs_tol, gs_max_iter=2000)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     st = ctx.profile_end()
     Gl, Gg = out["G_lesser"][:, :, 0, 0], out["G_greater"][:, :, 0, 0]
-    vsteps = (nt - 1) + nt * (nt - 1)
-    hv = st.get("hv_lanczos", {"sampled_ms": 0, "sampled": 1, "sampled_bytes": 0})
-    res = {"metric": "four-step on the 2x8 ladder (L=16), short mesh", "D": s.dim, "nt": nt,
-           "elapsed_s": round(el, 2), "vector_steps": vsteps,
+    vsteps = ((nt - 1) + nt * (nt - 1)) * spg
+    step = {}
+    for k in ("hv_lanczos", "hv_rows_lanczos", "hv_up_lanczos", "lanczos_update"):
+        if k in st and st[k]["sampled"]:
+            step[k] = {"avg_ms": round(st[k]["sampled_ms"] / st[k]["sampled"], 3),
+                       "GBps": round(st[k]["sampled_bytes"] / max(st[k]["sampled_ms"], 1e-9) / 1e6, 1)}
+    res = {"metric": "four-step on the 2x8 ladder (L=16)", "D": s.dim, "nt": nt, "steps_per_interval": spg,
+           "dt": q.dt, "t_max": round((nt - 1) * spg * q.dt, 6), "elapsed_s": round(el, 2), "vector_steps": vsteps,
            "anticommutator_err": float(np.abs(np.diag(Gg - Gl) + 1j).max()), "E0": out["E0"],
-           "hv_lanczos": {"avg_ms": round(hv["sampled_ms"] / max(hv["sampled"], 1), 3),
-                          "GBps": round(hv["sampled_bytes"] / max(hv["sampled_ms"], 1e-9) / 1e6, 1)},
+           "hermiticity_err": float(np.abs(Gl + np.conj(Gl.T)).max()),
+           "n0_up": float(np.real(-1j * Gl[0, 0])), "lanczos_kernels": step,
            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["sampled_ms"], 1)}
                        for k, v in sorted(st.items())}}
     print(json.dumps(res), flush=True)
+    if a.adj16:
+        # the adjoint of Re sum conj(W) G^< on a mesh of adj16 points (W seeded
+        # by 5), chains checkpointed every 10 SIL steps
+        nta = a.adj16
+        rng = np.random.default_rng(5)
+        W = (rng.standard_normal((nta, nta, 1, 1)) + 1j * rng.standard_normal((nta, nta, 1, 1))) / nta
+        ctx.set_option(ctx.ADJ_EVERY, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fw = ctx.greens_neq(ctx.model(q.H_ini), ctx.model(q.H), s, v0, orbitals=q.orbitals, nt=nta,
+                            steps_per_grid=spg, dt=q.dt, krylov_dim=q.krylov_dim, schedule=0, gs_tol=q.gs_tol,
+                            gs_max_iter=2000)
+        torch.cuda.synchronize()
+        t_fw = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g = ctx.greens_neq_vjp(ctx.model(q.H_ini), ctx.model(q.H), s, v0, q.orbitals, nta, spg, q.dt, W_lesser=W,
+                               krylov_dim=q.krylov_dim, gs_tol=q.gs_tol, gs_max_iter=2000)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        ctx.set_option(ctx.ADJ_EVERY, 0)
+        nb = len(q.H.bonds)
+        print(json.dumps({"metric": "adjoint gradient on the 2x8 ladder (L=16)", "nt": nta, "steps_per_interval": spg,
+                          "checkpoint_every": 10, "forward_plain_schedule_s": round(t_fw, 2),
+                          "vjp_s": round(t_adj, 2), "cg_iters": g["cg_iters"],
+                          "loss": float(np.real(np.sum(np.conj(W) * g["G_lesser"]))),
+                          "forward_G_matches": float(np.abs(g["G_lesser"] - fw["G_lesser"]).max()),
+                          "grad_hoppings_first4": [round(float(x), 10) for x in g["grad"][:4]],
+                          "grad_U_site0": float(g["grad"][nb + 32])}), flush=True)
 
 
 def hub4x3(a):
@@ -575,25 +612,28 @@ def necpt_bench(a):
     gb = ctx.bath_chain_contour(Lb, 1.0, nt, dt, ntau, dtau, beta)
     torch.cuda.synchronize()
     t_bathm = time.perf_counter() - t0
-    densm, t_cptm = [], []
+    # cluster functions on the contour (kgf_cluster_contour): as the ground
+    # state gives them (kms 0), and completed for the finite branch (kms 1)
+    densm, dens0, t_cptm = [], [], []
     for sp in (0, 1):
         idx = [k for k, (_, q) in enumerate(orbs) if q == sp]
-        sel = lambda x: np.ascontiguousarray(x[..., idx, :][..., idx])
-        gc = {"lesser": sel(outm["G_lesser"]), "greater": sel(outm["G_greater"]), "mixed": sel(outm["G_mixed"]),
-              "mixed_left": sel(outm["G_mixed_left"]), "vert_greater": 1j * sel(outm["G_matsubara"][0]),
-              "vert_lesser": 1j * sel(outm["G_matsubara"][1])}
-        gcd = {k: torch.from_numpy(v).to("cuda:0") for k, v in gc.items()}
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ctx.necpt_contour(gcd, gb, Lc - 1, V, dt, dtau)
-        torch.cuda.synchronize()
-        t_cptm.append(time.perf_counter() - t0)
-        log(f"necpt: contour solve with the Matsubara branch, spin {sp}: {t_cptm[-1]:.3f} s")
-        densm.append(np.real(-1j * np.einsum("aaii->ai", res["G_lesser"].cpu().numpy())))
-        del gcd, res
-        torch.cuda.empty_cache()
+        for kms in (1, 0):
+            gcd = ctx.cluster_contour(outm, orbitals=idx, kms=bool(kms))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.necpt_contour(gcd, gb, Lc - 1, V, dt, dtau)
+            torch.cuda.synchronize()
+            if kms:
+                t_cptm.append(time.perf_counter() - t0)
+                log(f"necpt: contour solve with the Matsubara branch, spin {sp}: {t_cptm[-1]:.3f} s")
+            (densm if kms else dens0).append(np.real(-1j * np.einsum("aaii->ai", res["G_lesser"].cpu().numpy())))
+            del gcd, res
+            torch.cuda.empty_cache()
     m_m = (densm[0] - densm[1])[:, :4].sum(axis=1)
     m1 = densm[0][:, 0] - densm[1][:, 0]
+    m_sites0 = [round(float(densm[0][0, i] - densm[1][0, i]), 5) for i in range(4)]
+    m_sites0_plain = [round(float(dens0[0][0, i] - dens0[1][0, i]), 5) for i in range(4)]
+    m_sites0_iso = [round(float(iso[0][0, i] - iso[1][0, i]), 5) for i in range(4)]
     kern = {k: {"launches": v["launches"], "total_ms": round(v["sampled_ms"], 2)} for k, v in sorted(stats.items())}
     n, m = 2 * nt, 2 * nt * Lc
     gemm_flops = 8.0 * (n * n * n + n * n * m + m * m * n)     # 1 - P K, K X, R (K X)
@@ -614,7 +654,11 @@ def necpt_bench(a):
                                            "bath_s": round(t_bathm, 4),
                                            "contour_solve_s": [round(x, 4) for x in t_cptm],
                                            "impurity_moment_m1": {f"t={dt * k:g}": round(float(m1[k]), 5)
-                                                                  for k in marks}}}), flush=True)
+                                                                  for k in marks},
+                                           "t0_moments_sites_1_4": {
+                                               "cpt_completed_cluster_functions": m_sites0,
+                                               "cpt_ground_state_cluster_functions": m_sites0_plain,
+                                               "isolated_cluster": m_sites0_iso}}}), flush=True)
 
 
 def two_particle(a):

@@ -375,6 +375,31 @@ typedef struct {
 } kgf_contour_fn;
 int  kgf_bath_chain_contour(kgf_ctx* ctx, int L_b, double T_b, double beta, int nt, double dt, int ntau,
                             double dtau, const kgf_contour_fn* out);
+/* kgf_cluster_contour: a cluster's contour function (the members of *out,
+ * device, caller-owned, shapes as above with n = n_c) from the host outputs
+ * of kgf_greens_neq with ntau >= 2 (G_lesser, G_greater [nt][nt][n_orb][n_orb],
+ * G_matsubara [2][ntau][..], G_mixed [nt][ntau][..], G_mixed_left [ntau][nt][..]),
+ * for the orbitals host_sel[0..n_c) (NULL: all, n_c = n_orb): lesser, greater,
+ * mixed, mixed_left as given, vert_greater = i G^M(+tau), vert_lesser =
+ * i G^M(-tau) (Sec. 4 mixed and Matsubara functions, Sec. 5 Eq. (cpteq)).
+ * kms = 1 completes these ground-state functions for an imaginary branch of
+ * finite length beta = (ntau - 1) dtau: in an equilibrium at beta dominated
+ * by the ground state, the states of N -+ 1 particles reached by c, c+ enter
+ * near the far end of the branch, where they are the same ground-state
+ * products read at beta - tau:
+ *   vert_greater(tau) = i G^M(+tau) - i G^M(-(beta - tau)),
+ *   vert_lesser(tau)  = i G^M(-tau) - i G^M(+(beta - tau)),
+ *   mixed_ab(t, tau)  = G^|_ab(t, tau) + conj(G^|_ba(beta - tau, t)),
+ *   mixed_left_ab(tau, t) = G^|_ab(tau, t) + conj(G^|_ba(t, beta - tau))
+ * (G(-i beta, z') = -G(0, z') then holds up to terms of order e^{-beta Delta},
+ * Delta the cluster's lowest excitation energy in the sectors involved);
+ * kms = 0 leaves them as the ground state gives them.  Synchronises before
+ * returning (the host arrays are read on the stream).  KGF_EINVAL for a NULL
+ * member, an orbital index outside [0, n_orb) or kms not 0 / 1. */
+int  kgf_cluster_contour(kgf_ctx* ctx, int nt, int ntau, int n_orb, const kgf_c128* host_G_lesser,
+                         const kgf_c128* host_G_greater, const kgf_c128* host_G_matsubara,
+                         const kgf_c128* host_G_mixed, const kgf_c128* host_G_mixed_left, const int* host_sel,
+                         int n_c, int kms, const kgf_contour_fn* out);
 int  kgf_necpt_contour(kgf_ctx* ctx, int nt, int ntau, int n_c, int boundary, double dt, double dtau, double V,
                        const kgf_contour_fn* Gc, const kgf_contour_fn* Gb, kgf_c128* G_lesser,
                        kgf_c128* G_greater, kgf_c128* G_mixed, kgf_c128* G_mixed_left);

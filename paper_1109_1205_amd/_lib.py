@@ -118,6 +118,7 @@ def load_library():
         "kgf_bath_chain_contour": (I, [P, I, D, D, I, D, I, D, C.POINTER(_ContourFn)]),
         "kgf_necpt_contour": (I, [P, I, I, I, I, D, D, D, C.POINTER(_ContourFn), C.POINTER(_ContourFn), P, P, P,
                                   P]),
+        "kgf_cluster_contour": (I, [P, I, I, I, P, P, P, P, P, P, I, I, C.POINTER(_ContourFn)]),
         "kgf_greens_neq_driven": (I, [P, P, P, P, C.POINTER(_GsOpts), P, P, I, I, I, C.POINTER(_PropOpts), I, I,
                                       P, P, P, P, C.POINTER(D)]),
         "kgf_sector_create": (I, [P, I, I, I, C.POINTER(P)]),
@@ -172,7 +173,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_apply_h", "kgf_apply_c", "kgf_ground_state", "kgf_propagate", "kgf_greens_eq",
             "kgf_greens_neq", "kgf_set_progress", "kgf_n_theta", "kgf_dH_expect", "kgf_propagate_vjp",
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
-            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_bath_chain_contour", "kgf_necpt_contour", "kgf_greens2_neq",
+            "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_bath_chain_contour", "kgf_necpt_contour", "kgf_cluster_contour", "kgf_greens2_neq",
             "kgf_neq_run_create", "kgf_neq_run_advance", "kgf_neq_run_result", "kgf_neq_run_destroy",
             "kgf_propagate_noalloc", "kgf_model_get_params",
             "kgf_profile_begin",
@@ -705,6 +706,35 @@ class Context:
         f = self._contour_fn(out, nt, ntau, 1)
         _check(_lib.kgf_bath_chain_contour(self.handle, int(L_b), float(T_b), float(beta), int(nt), float(dt),
                                            int(ntau), float(dtau), C.byref(f)))
+        return out
+
+    def cluster_contour(self, four_step: dict, orbitals=None, kms: bool = True):
+        """kgf_cluster_contour: a cluster's contour components (device tensors;
+        keys CONTOUR_KEYS) from the output of greens_neq with ntau >= 2, for the
+        orbital indices `orbitals` (positions in its orbital list; None: all);
+        kms completes them for the imaginary branch of finite length."""
+        import torch
+        Gl = np.ascontiguousarray(four_step["G_lesser"], dtype=np.complex128)
+        nt, n_orb = int(Gl.shape[0]), int(Gl.shape[2])
+        GM = np.ascontiguousarray(four_step["G_matsubara"], dtype=np.complex128)
+        ntau = int(GM.shape[1])
+        arrs = [Gl, np.ascontiguousarray(four_step["G_greater"], dtype=np.complex128), GM,
+                np.ascontiguousarray(four_step["G_mixed"], dtype=np.complex128),
+                np.ascontiguousarray(four_step["G_mixed_left"], dtype=np.complex128)]
+        shapes = [(nt, nt, n_orb, n_orb), (nt, nt, n_orb, n_orb), (2, ntau, n_orb, n_orb), (nt, ntau, n_orb, n_orb),
+                  (ntau, nt, n_orb, n_orb)]
+        for x, shp in zip(arrs, shapes):
+            if tuple(x.shape) != shp:
+                raise ValueError(f"cluster_contour: expected four-step components of shape {shp}")
+        sel = np.ascontiguousarray(range(n_orb) if orbitals is None else orbitals, dtype=np.int32)
+        n_c = int(sel.shape[0])
+        dev = f"cuda:{self.device}"
+        shp = {"lesser": (nt, nt), "greater": (nt, nt), "mixed": (nt, ntau), "mixed_left": (ntau, nt),
+               "vert_greater": (ntau,), "vert_lesser": (ntau,)}
+        out = {k: torch.empty(shp[k] + (n_c, n_c), dtype=torch.complex128, device=dev) for k in CONTOUR_KEYS}
+        f = self._contour_fn(out, nt, ntau, n_c) if n_c > 1 else _ContourFn(*[_ptr(out[k]) for k in CONTOUR_KEYS])
+        _check(_lib.kgf_cluster_contour(self.handle, nt, ntau, n_orb, *[_np_ptr(x) for x in arrs], _np_ptr(sel), n_c,
+                                        1 if kms else 0, C.byref(f)))
         return out
 
     def necpt_contour(self, Gc: dict, Gb: dict, boundary: int, V: float, dt: float, dtau: float):

@@ -630,6 +630,127 @@ extern "C" int kgf_bath_chain_contour(kgf_ctx* ctx, int L_b, double T_b, double 
     });
 }
 
+// A cluster's contour function from the four-step outputs (orbitals
+// selected by sel), optionally completed for a finite imaginary branch.
+struct ClusterIn {
+    const double2* gl;
+    const double2* gg;
+    const double2* gm;     // [2][ntau][no][no]
+    const double2* mx;     // [nt][ntau][no][no]
+    const double2* mxl;    // [ntau][nt][no][no]
+};
+struct ClusterOut {
+    double2* gl;
+    double2* gg;
+    double2* mx;
+    double2* mxl;
+    double2* vg;
+    double2* vl;
+};
+
+__device__ __forceinline__ double2 times_i(double2 z) { return make_double2(-z.y, z.x); }
+
+__global__ void k_cluster_contour(int nt, int ntau, int no, const int* __restrict__ sel, int nc, int kms,
+                                  ClusterIn in, ClusterOut out) {
+    const int64_t q = (int64_t)nc * nc;
+    const int64_t n_gl = (int64_t)nt * nt * q, n_mx = (int64_t)nt * ntau * q, n_v = (int64_t)ntau * q;
+    const int64_t total = 2 * n_gl + 2 * n_mx + 2 * n_v;
+    auto at = [&](int64_t outer, int a, int b) -> int64_t { return outer * no * no + (int64_t)sel[a] * no + sel[b]; };
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        // output array and element index within it
+        int64_t r = i;
+        int which;
+        if (r < n_gl) which = 0;
+        else if ((r -= n_gl) < n_gl) which = 1;
+        else if ((r -= n_gl) < n_mx) which = 2;
+        else if ((r -= n_mx) < n_mx) which = 3;
+        else if ((r -= n_mx) < n_v) which = 4;
+        else {
+            r -= n_v;
+            which = 5;
+        }
+        const int a = (int)((r / nc) % nc), b = (int)(r % nc);
+        const int64_t outer = r / q;
+        if (which <= 1) {
+            (which == 0 ? out.gl : out.gg)[r] = (which == 0 ? in.gl : in.gg)[at(outer, a, b)];
+        } else if (which == 2) {                       // G^|(t, tau): outer = t * ntau + j
+            const int t = (int)(outer / ntau), j = (int)(outer % ntau);
+            double2 v = in.mx[at(outer, a, b)];
+            if (kms) {
+                const double2 w = in.mxl[at((int64_t)(ntau - 1 - j) * nt + t, b, a)];
+                v.x += w.x;
+                v.y -= w.y;
+            }
+            out.mx[r] = v;
+        } else if (which == 3) {                       // G^|(tau, t): outer = j * nt + t
+            const int j = (int)(outer / nt), t = (int)(outer % nt);
+            double2 v = in.mxl[at(outer, a, b)];
+            if (kms) {
+                const double2 w = in.mx[at((int64_t)t * ntau + (ntau - 1 - j), b, a)];
+                v.x += w.x;
+                v.y -= w.y;
+            }
+            out.mxl[r] = v;
+        } else {                                       // vertical: outer = j
+            const int j = (int)outer;
+            const double2* g0 = in.gm + (which == 4 ? 0 : (int64_t)ntau * no * no);   // +tau (4) or -tau (5)
+            const double2* g1 = in.gm + (which == 4 ? (int64_t)ntau * no * no : 0);
+            double2 v = times_i(g0[at(j, a, b)]);
+            if (kms) {
+                const double2 w = times_i(g1[at(ntau - 1 - j, a, b)]);
+                v.x -= w.x;
+                v.y -= w.y;
+            }
+            (which == 4 ? out.vg : out.vl)[r] = v;
+        }
+    }
+}
+
+extern "C" int kgf_cluster_contour(kgf_ctx* ctx, int nt, int ntau, int n_orb, const kgf_c128* host_G_lesser,
+                                   const kgf_c128* host_G_greater, const kgf_c128* host_G_matsubara,
+                                   const kgf_c128* host_G_mixed, const kgf_c128* host_G_mixed_left,
+                                   const int* host_sel, int n_c, int kms, const kgf_contour_fn* out) {
+    return abi_guard([&] {
+        KGF_REQUIRE(ctx && host_G_lesser && host_G_greater && host_G_matsubara && host_G_mixed && host_G_mixed_left &&
+                        contour_fn_complete(out),
+                    KGF_EINVAL, "kgf_cluster_contour: NULL argument");
+        KGF_REQUIRE(nt >= 1 && ntau >= 2 && n_orb >= 1 && n_c >= 1 && (host_sel || n_c == n_orb) &&
+                        (kms == 0 || kms == 1),
+                    KGF_EINVAL, "kgf_cluster_contour: bad nt / ntau / n_orb / n_c / kms");
+        std::vector<int> sel((size_t)n_c);
+        for (int a = 0; a < n_c; ++a) {
+            sel[a] = host_sel ? host_sel[a] : a;
+            KGF_REQUIRE(sel[a] >= 0 && sel[a] < n_orb, KGF_EINVAL, "kgf_cluster_contour: orbital index out of range");
+        }
+        KGF_HIP(hipSetDevice(ctx->device));
+        const size_t oo = (size_t)n_orb * n_orb;
+        const size_t b_gl = sizeof(double2) * (size_t)nt * nt * oo, b_gm = sizeof(double2) * 2 * (size_t)ntau * oo,
+                     b_mx = sizeof(double2) * (size_t)nt * ntau * oo;
+        char* w = static_cast<char*>(workspace(ctx, "cpt_cluster_in", 2 * b_gl + b_gm + 2 * b_mx + sizeof(int) * n_c));
+        ClusterIn in;
+        in.gl = reinterpret_cast<const double2*>(w);
+        in.gg = reinterpret_cast<const double2*>(w + b_gl);
+        in.gm = reinterpret_cast<const double2*>(w + 2 * b_gl);
+        in.mx = reinterpret_cast<const double2*>(w + 2 * b_gl + b_gm);
+        in.mxl = reinterpret_cast<const double2*>(w + 2 * b_gl + b_gm + b_mx);
+        int* dsel = reinterpret_cast<int*>(w + 2 * b_gl + b_gm + 2 * b_mx);
+        KGF_HIP(hipMemcpyAsync(w, host_G_lesser, b_gl, hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(w + b_gl, host_G_greater, b_gl, hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(w + 2 * b_gl, host_G_matsubara, b_gm, hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(w + 2 * b_gl + b_gm, host_G_mixed, b_mx, hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(w + 2 * b_gl + b_gm + b_mx, host_G_mixed_left, b_mx, hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(dsel, sel.data(), sizeof(int) * n_c, hipMemcpyHostToDevice, ctx->stream));
+        ClusterOut o{reinterpret_cast<double2*>(out->lesser), reinterpret_cast<double2*>(out->greater),
+                     reinterpret_cast<double2*>(out->mixed), reinterpret_cast<double2*>(out->mixed_left),
+                     reinterpret_cast<double2*>(out->vert_greater), reinterpret_cast<double2*>(out->vert_lesser)};
+        const int64_t total = (int64_t)n_c * n_c * (2 * (int64_t)nt * nt + 2 * (int64_t)nt * ntau + 2 * (int64_t)ntau);
+        hipLaunchKernelGGL(k_cluster_contour, dim3(grid_for(total)), dim3(kThreads), 0, ctx->stream, nt, ntau, n_orb,
+                           dsel, n_c, kms, in, o);
+        check_launch("k_cluster_contour");
+        sync(ctx);   // the host arrays may go away on return
+    });
+}
+
 extern "C" int kgf_necpt_contour(kgf_ctx* ctx, int nt, int ntau, int n_c, int boundary, double dt, double dtau,
                                  double V, const kgf_contour_fn* Gc, const kgf_contour_fn* Gb, kgf_c128* G_lesser,
                                  kgf_c128* G_greater, kgf_c128* G_mixed, kgf_c128* G_mixed_left) {

@@ -117,3 +117,74 @@ def test_pipeline_against_oracle(ctx):
     assert abs(n_cpt - n_iso) > 1e-3
     for k in range(nt):
         assert np.abs(Gg[k, k] - Gl[k, k] + 1j * np.eye(Lc)).max() < 1e-2
+
+
+def test_cluster_contour_assembly_against_oracle(ctx):
+    """kgf_cluster_contour on the oracle's four-step output (both spins, one
+    spin selected): the plain assembly equals the oracle's cluster_fn and the
+    completion for the finite imaginary branch its cluster_fn_kms, element
+    by element (the same additions and conjugations on both sides)."""
+    Lc, nt, spg, dtg, ntau, tspg, beta = 4, 7, 2, 0.1, 21, 2, 2.0
+    dtau = beta / (ntau - 1)
+    H = wl.chain_siam(Lc, 1.0, 1.0)
+    Hi = H.with_field(0, 0.2)
+    sec = basis.Sector(Lc, 2, 2)
+    orbs = [(i, sp) for sp in (0, 1) for i in range(Lc)]
+    ora = greens.four_step(Hi, H, 2, 2, orbs, nt, dtg, spg, 15, wl.start_vector(sec.dim, 7), gs_tol=1e-13,
+                           reorth="none", ntau=ntau, dtau_grid=dtau, tau_steps_per_grid=tspg)
+    for sp in (0, 1):
+        idx = [k for k, (_, q) in enumerate(orbs) if q == sp]
+        sub = {k: np.ascontiguousarray(ora[k][..., idx, :][..., idx])
+               for k in ("G_lesser", "G_greater", "G_matsubara", "G_mixed", "G_mixed_left")}
+        for kms, fn in ((False, necpt.cluster_fn), (True, necpt.cluster_fn_kms)):
+            ref = fn(sub)
+            got = ctx.cluster_contour(ora, orbitals=idx, kms=kms)
+            for key in KEYS:
+                assert np.abs(got[key].cpu().numpy() - ref[key]).max() <= 1e-15 * np.abs(ref[key]).max(), (sp, kms, key)
+
+
+def test_pipeline_kms_moments_against_oracle(ctx):
+    """The pipeline with the cluster functions completed for the finite
+    imaginary branch (the reading of Sec. 5's Matsubara branch at finite beta
+    for a zero-temperature cluster): GPU four-step of both spins ->
+    kgf_cluster_contour (kms) -> GPU bath -> contour solve per spin, against
+    the oracle's four-step -> cluster_fn_kms -> bath -> CPT equation.  The
+    t = 0 local moments m_i = n_i,up - n_i,down of the connected system differ
+    from the isolated cluster's: the isolated cluster's ground state has
+    S_z = 0, so its net moment over the cluster vanishes (as Sec. 5 notes for
+    the smallest cluster), the connected system's does not."""
+    Lc, Lb, V, beta = 4, 8, 1.0, 3.0
+    nt, spg, dtg = 9, 2, 0.1
+    ntau, tspg = 31, 2
+    dtau = beta / (ntau - 1)
+    H = wl.chain_siam(Lc, 1.0, 1.0)
+    Hi = H.with_field(0, 0.2)
+    sec = basis.Sector(Lc, 2, 2)
+    orbs = [(i, sp) for sp in (0, 1) for i in range(Lc)]
+    v0 = wl.start_vector(sec.dim, 7)
+    ora = greens.four_step(Hi, H, 2, 2, orbs, nt, dtg, spg, 15, v0, gs_tol=1e-13, reorth="none", ntau=ntau,
+                           dtau_grid=dtau, tau_steps_per_grid=tspg)
+    Gb_ref = necpt.bath_greens_l(_chain(Lb), nt, dtg, ntau, dtau, beta, sites=[0])
+    say("pipeline kms: GPU four-step, both spins")
+    g4 = ctx.greens_neq(ctx.model(Hi), ctx.model(H), ctx.sector(Lc, 2, 2), _dev(v0), orbs, nt, spg, dtg / spg,
+                        krylov_dim=15, reorth=0, schedule=1, ntau=ntau, tau_steps_per_grid=tspg, dtau=dtau / tspg,
+                        gs_tol=1e-13)
+    Gb = ctx.bath_chain_contour(Lb, 1.0, nt, dtg, ntau, dtau, beta)
+    n_cpt, n_iso = [], []
+    for sp in (0, 1):
+        idx = [k for k, (_, q) in enumerate(orbs) if q == sp]
+        sub = {k: np.ascontiguousarray(ora[k][..., idx, :][..., idx])
+               for k in ("G_lesser", "G_greater", "G_matsubara", "G_mixed", "G_mixed_left")}
+        ref = necpt.necpt_l(necpt.cluster_fn_kms(sub), Gb_ref, Lc - 1, V, dtg, dtau)
+        got = ctx.necpt_contour(ctx.cluster_contour(g4, orbitals=idx, kms=True), Gb, Lc - 1, V, dtg, dtau)
+        for key in ("lesser", "greater", "mixed", "mixed_left"):
+            e = rel_err(got["G_" + key].cpu().numpy(), ref[key])
+            say("pipeline kms spin", sp, key, e)
+            assert e < 1e-10, (sp, key)
+        n_cpt.append(np.real(-1j * np.diag(got["G_lesser"][0, 0].cpu().numpy())))
+        n_iso.append(np.real(-1j * np.diag(g4["G_lesser"][0, 0][idx][:, idx])))
+    m_cpt, m_iso = n_cpt[0] - n_cpt[1], n_iso[0] - n_iso[1]
+    say("t = 0 moments: connected", m_cpt, "isolated", m_iso)
+    assert abs(m_iso.sum()) < 1e-12
+    assert abs(m_cpt.sum()) > 1e-3
+    assert np.abs(m_cpt - m_iso).max() > 1e-3
