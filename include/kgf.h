@@ -642,8 +642,11 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *   KGF_OPT_HV_TUNE:   0 (default) = H.v variant by size; 1 = the first H.v of
  *                      each sector (L, N_up, N_dn) times every equivalent variant
  *                      (single pass, two pass with strips 16/32/64, split rows)
- *                      on scratch vectors, separately for the plain and the
- *                      Lanczos form, and keeps the fastest for that context;
+ *                      on scratch vectors, separately for the plain form (three
+ *                      H.v) and the Lanczos form (one SIL step of Krylov
+ *                      dimension 20 on one column, the update pass or the
+ *                      folded update included), and keeps the fastest for that
+ *                      context;
  *                      and the four-step sweeps with batch = 0 time one SIL
  *                      step per block width (the widest that fits, 32, 16, 8, 4
  *                      columns) on scratch columns of the target sector and keep

@@ -1680,27 +1680,39 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         double2* x = static_cast<double2*>(workspace(ctx, "hv_tune_x", 2 * sizeof(double2) * (size_t)D));
         double2* y = x + D;
         double* aux = static_cast<double*>(workspace(ctx, "hv_tune_aux", sizeof(double) * (size_t)(nblk + 3)));
-        const double sc[3] = {1.0, 0.5, 1.0};   // s_k, b_k, s_{k-1}
-        KGF_HIP(hipMemsetAsync(x, 0, 2 * sizeof(double2) * (size_t)D, ctx->stream));
-        KGF_HIP(hipMemcpyAsync(aux, sc, sizeof(sc), hipMemcpyHostToDevice, ctx->stream));
+        (void)aux;
+        if (mode == 0) KGF_HIP(hipMemsetAsync(x, 0, 2 * sizeof(double2) * (size_t)D, ctx->stream));
+        else fill_splitmix(ctx, x, D, 0x7e57ULL);
         const bool prof = ctx->prof_on;
+        const int graphs = ctx->use_graphs;
         ctx->prof_on = false;
+        ctx->use_graphs = 0;
         hipEvent_t e0, e1;
         KGF_HIP(hipEventCreate(&e0));
         KGF_HIP(hipEventCreate(&e1));
         int best = 0;
         float best_ms = 0.0f;
+        // The Lanczos form is timed as one SIL step (Krylov dimension 20, one
+        // column) with the candidate plan in force, so that the update is part
+        // of the comparison: a pass of its own after a single-pass H.v, folded
+        // into the row pass of a two-pass plan.
+        const SilOpts so{20, 0, 0.05, 1, 0.0, 1e-13};
         for (size_t c = 0; c < plans.size(); ++c) {
             auto run = [&] {
-                if (mode == 0)
+                if (mode == 0) {
                     launch_hv<0>(ctx, model, sec, 1, 0, x, D, nullptr, 0, y, D, nullptr, nullptr, nullptr, 0, nullptr,
                                  &plans[c]);
-                else
-                    launch_hv<1>(ctx, model, sec, 1, 0, x, D, x, D, y, D, aux, aux + 1, aux + 2, 0, aux + 3, &plans[c]);
+                } else {
+                    ctx->hv_passes = cand[c].first;
+                    ctx->hv_strip = cand[c].second;
+                    sil_propagate(ctx, model, sec, x, 1, D, 1, so);
+                    ctx->hv_passes = 0;
+                    ctx->hv_strip = 0;
+                }
             };
-            run();   // first launch: LDS opt-in, caches
+            run();   // first launch: LDS opt-in, caches, workspaces
             KGF_HIP(hipEventRecord(e0, ctx->stream));
-            for (int r = 0; r < 3; ++r) run();
+            for (int r = 0; r < (mode == 0 ? 3 : 1); ++r) run();
             KGF_HIP(hipEventRecord(e1, ctx->stream));
             KGF_HIP(hipEventSynchronize(e1));
             float ms = 0.0f;
@@ -1713,6 +1725,7 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         KGF_HIP(hipEventDestroy(e0));
         KGF_HIP(hipEventDestroy(e1));
         ctx->prof_on = prof;
+        ctx->use_graphs = graphs;
         ctx->hv_tuned[key] = cand[best];
         sync(ctx);
         ctx->ws.erase("hv_tune_x");
