@@ -198,6 +198,13 @@ int  kgf_ground_state(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* se
  * propagator is unitary and this bounds the step's error up to the
  * quadrature.  Asking for it costs the tridiagonal exponential at the 16
  * nodes, one more vector update per step, and synchronises the stream.
+ * host_norm_drift (or NULL): the largest, over columns and steps, of
+ * | ||psi after the step|| / ||psi before it|| - 1 |.  The real-time steps are
+ * unitary (Sec. 3), so this measures the loss of orthogonality of the Krylov
+ * basis and rounding; a value far above 1e-14 flags a step the caller should
+ * rerun with reorthogonalisation or a smaller dt (for direction 0 the norm is
+ * not conserved and the value is the decay itself).  Costs one norm pass per
+ * step and synchronises the stream.
  * Workspace: krylov_dim * nvec vectors of D complex128. */
 typedef struct {
     int    krylov_dim;
@@ -209,7 +216,7 @@ typedef struct {
 } kgf_prop_opts;
 int  kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* sector,
                    kgf_c128* psi, int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts,
-                   double* host_err_est);
+                   double* host_err_est, double* host_norm_drift);
 
 /* ---- allocation-free propagation ---------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph

@@ -130,7 +130,7 @@ def load_library():
         "kgf_apply_h": (I, [P, P, P, P, P, I, I64]),
         "kgf_apply_c": (I, [P, P, P, I, I, P, P, I, I64, I64]),
         "kgf_ground_state": (I, [P, P, P, C.POINTER(_GsOpts), P, P, C.POINTER(D), C.POINTER(_GsInfo)]),
-        "kgf_propagate": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts), C.POINTER(D)]),
+        "kgf_propagate": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts), C.POINTER(D), C.POINTER(D)]),
         "kgf_propagate_noalloc": (I, [P, P, P, P, I, I64, I, C.POINTER(_PropOpts), C.POINTER(D)]),
         "kgf_model_get_params": (I, [P, P, P, P, P]),
         "kgf_greens_eq": (I, [P, P, P, P, D, P, I, I, I, C.POINTER(_PropOpts), I, P, P]),
@@ -458,15 +458,20 @@ class Context:
 
     def propagate(self, model: Model, sec: Sector, psi, nsteps: int, dt: float, krylov_dim: int = 15,
                   direction: int = DIRECTION_FORWARD, shift: float = 0.0, reorth: int = 0,
-                  breakdown_tol: float = 1e-13, return_err: bool = False):
+                  breakdown_tol: float = 1e-13, return_err: bool = False, return_drift: bool = False):
         """kgf_propagate; with return_err also the largest per-step a-posteriori
-        error estimate (returns (psi, err))."""
+        error estimate, with return_drift the largest per-step norm drift
+        | ||psi after|| / ||psi before|| - 1 | (returns (psi, err), (psi, drift)
+        or (psi, err, drift))."""
         nvec = self._chk(psi, sec.dim, "psi")
         o = _prop(krylov_dim, reorth, dt, direction, shift, breakdown_tol)
         err = C.c_double()
+        drift = C.c_double()
         _check(_lib.kgf_propagate(self.handle, model.handle, sec.handle, _ptr(psi), nvec, sec.dim, int(nsteps),
-                                  C.byref(o), C.byref(err) if return_err else None))
-        return (psi, err.value) if return_err else psi
+                                  C.byref(o), C.byref(err) if return_err else None,
+                                  C.byref(drift) if return_drift else None))
+        extra = ([err.value] if return_err else []) + ([drift.value] if return_drift else [])
+        return (psi, *extra) if extra else psi
 
     def propagate_noalloc(self, model: Model, sec: Sector, psi, nsteps: int, dt: float, krylov_dim: int = 15,
                           direction: int = DIRECTION_FORWARD, shift: float = 0.0, reorth: int = 0,

@@ -477,7 +477,8 @@ static double host_max(kgf_ctx* ctx, const double* dev, int n) {
 }
 
 int kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, kgf_c128* psi,
-                  int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts, double* host_err_est) {
+                  int nvec, int64_t ld, int nsteps, const kgf_prop_opts* opts, double* host_err_est,
+                  double* host_norm_drift) {
     return guarded([&] {
         KGF_REQUIRE(ctx && model && s, KGF_EINVAL, "kgf_propagate: NULL handle");
         KGF_REQUIRE(model->L == s->L, KGF_EINVAL, "kgf_propagate: model and sector L differ");
@@ -485,13 +486,17 @@ int kgf_propagate(kgf_ctx* ctx, const kgf_model* model, const kgf_sector* s, kgf
         KGF_REQUIRE(nvec >= 0 && nsteps >= 0 && ld >= s->dim(), KGF_EINVAL,
                     "kgf_propagate: bad nvec / nsteps / ld");
         if (host_err_est) *host_err_est = 0.0;
+        if (host_norm_drift) *host_norm_drift = 0.0;
         if (nvec == 0 || nsteps == 0 || s->dim() == 0) return;
         KGF_REQUIRE(psi, KGF_EINVAL, "kgf_propagate: NULL psi");
         KGF_HIP(hipSetDevice(ctx->device));
         double* err = host_err_est ? static_cast<double*>(workspace(ctx, "sil_err", sizeof(double) * nvec)) : nullptr;
+        double* drift =
+            host_norm_drift ? static_cast<double*>(workspace(ctx, "sil_drift", sizeof(double) * nvec)) : nullptr;
         sil_propagate(ctx, const_cast<kgf_model*>(model), s, reinterpret_cast<double2*>(psi), nvec,
-                      ld, nsteps, to_sil_opts(opts), err);
+                      ld, nsteps, to_sil_opts(opts), err, drift);
         if (host_err_est) *host_err_est = host_max(ctx, err, nvec);
+        if (host_norm_drift) *host_norm_drift = host_max(ctx, drift, nvec);
     });
 }
 

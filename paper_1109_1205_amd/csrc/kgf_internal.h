@@ -407,9 +407,12 @@ void sil_combine_multi(kgf_ctx* ctx, const kgf_sector* sec, double2* psi, int64_
                        int64_t out_col);
 // Batched short-iterative-Lanczos step(s) on ncol columns psi_c = psi + c*ld.
 // err (device, ncol doubles, or null): the largest a-posteriori step error
-// estimate of each column over the steps.
+// estimate of each column over the steps; drift (device, ncol doubles, or
+// null): the largest | ||psi after|| / ||psi before|| - 1 | of each column
+// over the steps (one norm pass per step).
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi,
-                   int ncol, int64_t ld, int nsteps, const SilOpts& o, double* err = nullptr);
+                   int ncol, int64_t ld, int nsteps, const SilOpts& o, double* err = nullptr,
+                   double* drift = nullptr);
 
 // Bytes of the one buffer that sil_propagate_in carves its Krylov slots,
 // scalars and partials from, and SIL steps with every device buffer in

@@ -323,6 +323,18 @@ __device__ __forceinline__ void fin_body(int mode, int k, double v, double* sc, 
     }
 }
 
+// drift[c] = max(drift[c], | sqrt(sum of column c's partials) / beta0 - 1 |)
+__global__ void k_drift_fin(const double* __restrict__ part, int nper, const double* __restrict__ scal,
+                            double* __restrict__ drift) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.x;
+    const double v = fixed_sum(part + (int64_t)c * nper, nper, sh);
+    if (threadIdx.x != 0) return;
+    const double b0 = scal[(int64_t)c * kScalStride + kOffBeta0];
+    const double d = b0 > 0.0 ? fabs(sqrt(v) / b0 - 1.0) : 0.0;
+    drift[c] = fmax(drift[c], d);
+}
+
 // sum the multi-dot partials: hvec[c][j] (complex) for j < nj
 __global__ void k_fin_h(const double* __restrict__ part, int nj, int nper, double2* __restrict__ hvec) {
     __shared__ double sh[kThreads / 64];
@@ -952,6 +964,7 @@ struct SilWork {
     double* part_big;
     double2* hvec;
     double* err;      // per-column running maximum of the step error estimate, or null
+    double* drift;    // per-column running maximum of | ||psi_after|| / ||psi_before|| - 1 |, or null
     double2* errc;    // [ncol][kErrNodes][m] coefficients at the estimate's quadrature nodes (with err)
 };
 
@@ -1087,6 +1100,7 @@ static SilWork sil_work_ws(kgf_ctx* ctx, const kgf_sector* sec, int ncol, const 
     }
     w.err = nullptr;
     w.errc = nullptr;
+    w.drift = nullptr;
     return w;
 }
 
@@ -1194,6 +1208,15 @@ static void sil_step_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double
     hipLaunchKernelGGL(k_combine, dim3(NB, ncol), dim3(kThreads), sizeof(double2) * m, ctx->stream, sl, m,
                        reinterpret_cast<const double2*>(coef), (int64_t)(kScalStride / 2), psi, ld, D);
     check_launch("k_combine");
+    if (w.drift) {   // norm after the step against beta0, the norm before it
+        {
+            Prof pn(ctx, "norm", 16.0 * D * ncol);
+            hipLaunchKernelGGL(k_norm2, dim3(NB, ncol), dim3(kThreads), 0, ctx->stream, psi, ld, D, w.part);
+            check_launch("k_norm2");
+        }
+        hipLaunchKernelGGL(k_drift_fin, dim3(ncol), dim3(kThreads), 0, ctx->stream, w.part, NB, w.scal, w.drift);
+        check_launch("k_drift_fin");
+    }
 }
 
 // Identity of a batched SIL step for graph replay: everything its launches
@@ -1292,22 +1315,24 @@ static void sil_step_graph(kgf_ctx* ctx, HModel model, const kgf_sector* sec, do
 }
 
 void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
-                   int nsteps, const SilOpts& o, double* err) {
+                   int nsteps, const SilOpts& o, double* err, double* drift) {
     TraceRange range_("kgf SIL steps");
-    if (err && nsteps > 0) {
-        hipLaunchKernelGGL(k_fill_zero, dim3((ncol + 255) / 256), dim3(256), 0, ctx->stream, err, ncol);
-        check_launch("k_fill_zero");
-    }
+    for (double* p : {err, drift})
+        if (p && nsteps > 0) {
+            hipLaunchKernelGGL(k_fill_zero, dim3((ncol + 255) / 256), dim3(256), 0, ctx->stream, p, ncol);
+            check_launch("k_fill_zero");
+        }
     for (int step = 0; step < nsteps; ++step) {
         KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
         hv_prepare(ctx, model, sec);
         sil_reserve(ctx, sec, ncol, o.m, o.reorth);
         SilWork w = sil_work_ws(ctx, sec, ncol, o);
         w.err = err;
+        w.drift = drift;
         if (err)
             w.errc = static_cast<double2*>(
                 workspace(ctx, "sil_errc", sizeof(double2) * (size_t)ncol * kErrNodes * o.m));
-        if (ctx->use_graphs && !ctx->prof_on && !err)
+        if (ctx->use_graphs && !ctx->prof_on && !err && !drift)
             sil_step_graph(ctx, model, sec, psi, ncol, ld, o, w);
         else
             sil_step_w(ctx, model, sec, psi, ncol, ld, o, w);
@@ -1334,6 +1359,7 @@ double* sil_propagate_in(kgf_ctx* ctx, kgf_model* model, const kgf_sector* sec, 
     w.hvec = o.reorth > 0 ? reinterpret_cast<double2*>(base + l.hvec) : nullptr;
     w.err = want_err ? reinterpret_cast<double*>(base + l.err) : nullptr;
     w.errc = want_err ? reinterpret_cast<double2*>(base + l.errc) : nullptr;
+    w.drift = nullptr;
     if (w.err) {
         hipLaunchKernelGGL(k_fill_zero, dim3((ncol + 255) / 256), dim3(256), 0, ctx->stream, w.err, ncol);
         check_launch("k_fill_zero");

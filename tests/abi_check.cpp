@@ -106,7 +106,7 @@ int main() {
     HIP_OK(hipMemcpy(work + D, v0, sizeof(kgf_c128) * D, hipMemcpyDeviceToDevice));
     HIP_OK(hipMemcpy(w2, work, sizeof(kgf_c128) * 2 * D, hipMemcpyDeviceToDevice));
     kgf_prop_opts po{15, 0, 0.05, -1, 0.0, 1e-13};
-    KGF_OK_(kgf_propagate(ctx, H, sec, work, 2, D, 10, &po, nullptr));
+    KGF_OK_(kgf_propagate(ctx, H, sec, work, 2, D, 10, &po, nullptr, nullptr));
     std::vector<kgf_c128> q(2 * D);
     HIP_OK(hipMemcpy(q.data(), work, sizeof(kgf_c128) * 2 * D, hipMemcpyDeviceToHost));
     double ov_re = 0.0, ov_im = 0.0;
@@ -116,11 +116,11 @@ int main() {
     }
     kgf_prop_opts bad_po = po;
     bad_po.krylov_dim = 0;   // outside 1..128
-    EXPECT(kgf_propagate(ctx, H, sec, work, 2, D, 1, &bad_po, nullptr) == KGF_EUNSUPPORTED);
+    EXPECT(kgf_propagate(ctx, H, sec, work, 2, D, 1, &bad_po, nullptr, nullptr) == KGF_EUNSUPPORTED);
     bad_po = po;
     bad_po.dt = std::nan("");
-    EXPECT(kgf_propagate(ctx, H, sec, work, 2, D, 1, &bad_po, nullptr) == KGF_EINVAL);
-    EXPECT(kgf_propagate(ctx, H, sec, work, 2, D, 1, nullptr, nullptr) == KGF_EINVAL);
+    EXPECT(kgf_propagate(ctx, H, sec, work, 2, D, 1, &bad_po, nullptr, nullptr) == KGF_EINVAL);
+    EXPECT(kgf_propagate(ctx, H, sec, work, 2, D, 1, nullptr, nullptr, nullptr) == KGF_EINVAL);
 
     // allocation-free propagation: bitwise the same states
     KGF_OK_(kgf_propagate_noalloc(ctx, H, sec, w2, 2, D, 10, &po, nullptr));
@@ -132,7 +132,7 @@ int main() {
     HIP_OK(hipMemcpy(w2, psi0, sizeof(kgf_c128) * D, hipMemcpyDeviceToDevice));
     HIP_OK(hipMemcpy(w2 + D, v0, sizeof(kgf_c128) * D, hipMemcpyDeviceToDevice));
     double err = -1.0;
-    KGF_OK_(kgf_propagate(ctx, H, sec, w2, 2, D, 10, &po, &err));
+    KGF_OK_(kgf_propagate(ctx, H, sec, w2, 2, D, 10, &po, &err, nullptr));
     EXPECT(err >= 0.0 && err < 1e-6);
 
     // four-step G after the quench: one call, then step by step

@@ -12,7 +12,12 @@
   true error of the step (measured with the oracle's dense
   eigendecomposition of H, D = 4,900) and stays within a factor 10 of it;
 * the projected CG of the adjoint's ground-state term reports KGF_ENOCONV
-  when held below convergence from the host (iteration limit 1)."""
+  when held below convergence from the host (iteration limit 1);
+* the per-step norm drift | ||psi after|| / ||psi before|| - 1 | of SIL
+  propagation: at rounding level for the unitary real-time steps (Sec. 3),
+  and for the imaginary-time direction equal to the decay of the norm that
+  the oracle's dense exponential gives (so the measurement itself is
+  pinned)."""
 import numpy as np
 import pytest
 
@@ -98,3 +103,27 @@ def test_adjoint_cg_failure_reported(ctx):
         assert e.value.code == -4
     finally:
         ctx.set_option(ctx.CG_MAX_ITER, 0)
+
+
+def test_norm_drift_reported(ctx):
+    q = wl.ring8()
+    sec = basis.Sector(8, 4, 4)
+    H = hamiltonian.Hamiltonian(q.H, sec)
+    X = np.stack([wl.complex_vector(sec.dim, 50 + c) for c in range(2)])
+    say("norm drift: real-time steps")
+    got, est, drift = ctx.propagate(ctx.model(q.H), ctx.sector(8, 4, 4), to_dev(X), 3, 0.05, 15, -1,
+                                    return_err=True, return_drift=True)
+    assert 0.0 <= drift < 1e-13 and est > 0.0
+    _, drift0 = ctx.propagate(ctx.model(q.H), ctx.sector(8, 4, 4), to_dev(X), 0, 0.05, 15, -1, return_drift=True)
+    assert drift0 == 0.0
+    say("norm drift: imaginary-time step against the dense exponential")
+    lam, Q = np.linalg.eigh(H.dense())
+    shift, dt = float(lam[0]) + 1.0, 0.05
+    ratio = []
+    for c in range(2):
+        y = Q @ (np.exp(-(lam - shift) * dt) * (Q.conj().T @ X[c]))
+        ratio.append(abs(np.linalg.norm(y) / np.linalg.norm(X[c]) - 1.0))
+    _, drift_im = ctx.propagate(ctx.model(q.H), ctx.sector(8, 4, 4), to_dev(X), 1, dt, 15, 0, shift,
+                                return_drift=True)
+    assert max(ratio) > 1e-3
+    assert abs(drift_im - max(ratio)) <= 1e-10 * max(ratio)
