@@ -630,7 +630,8 @@ int  kgf_set_progress(kgf_ctx* ctx, kgf_progress_fn fn, void* user);
  *                      real and imaginary halves (the mode used for rows above
  *                      78 KB); 4 two-pass with one whole row per pass-1 block
  *                      (2 and 3 stage two rows per block where they fit).
- *   KGF_OPT_HV_STRIP:  0 by size, or 8, 16, 32, 64 columns per strip (pass 2).
+ *   KGF_OPT_HV_STRIP:  0 by size (the widest of 64, 32, 16, 8 that the rows
+ *                      fill), or 8, 16, 32, 64, 128 columns per strip (pass 2).
  *   KGF_OPT_GS_MAX_BASIS: 0 = the ground-state Lanczos basis holds up to
  *                      max_iter + 1 vectors if they fit in 70% of free device
  *                      memory; n >= 8 caps it at n vectors.  Below max_iter + 1

@@ -800,7 +800,7 @@ class Context:
      HV_SEG, HV_UP_THREADS) = range(1, 13)
 
     def set_option(self, option: int, value: int) -> None:
-        """kgf_set_option: HV_PASSES 0..4, HV_STRIP 0/8/16/32/64, GS_MAX_BASIS 0 or >= 8, PHI_EVERY >= 0,
+        """kgf_set_option: HV_PASSES 0..4, HV_STRIP 0/8/16/32/64/128, GS_MAX_BASIS 0 or >= 8, PHI_EVERY >= 0,
         ADJ_EVERY >= 0, HV_TUNE 0/1, CG_MAX_ITER >= 0, GRAPHS 0/1, LOCKSTEP 0/1, HV_FUSE 0/1,
         HV_SEG 0/1, HV_UP_THREADS 256/512/1024."""
         _check(_lib.kgf_set_option(self.handle, int(option), int(value)))

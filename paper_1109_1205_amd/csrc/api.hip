@@ -614,8 +614,8 @@ int kgf_set_option(kgf_ctx* ctx, int option, int value) {
             KGF_REQUIRE(value >= 0 && value <= 4, KGF_EINVAL, "kgf_set_option: HV_PASSES must be 0..4");
             ctx->hv_passes = value;
         } else if (option == KGF_OPT_HV_STRIP) {
-            KGF_REQUIRE(value == 0 || value == 8 || value == 16 || value == 32 || value == 64, KGF_EINVAL,
-                        "kgf_set_option: HV_STRIP must be 0, 8, 16, 32 or 64");
+            KGF_REQUIRE(value == 0 || value == 8 || value == 16 || value == 32 || value == 64 || value == 128,
+                        KGF_EINVAL, "kgf_set_option: HV_STRIP must be 0, 8, 16, 32, 64 or 128");
             ctx->hv_strip = value;
         } else if (option == KGF_OPT_GS_MAX_BASIS) {
             KGF_REQUIRE(value == 0 || value >= 8, KGF_EINVAL, "kgf_set_option: GS_MAX_BASIS must be 0 or >= 8");

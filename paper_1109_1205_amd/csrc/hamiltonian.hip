@@ -1335,7 +1335,6 @@ struct HvPlan {
     int up_threads = 256;   // pass-2 block size (R = up_threads / C rows per block)
 };
 
-constexpr size_t kStripL2Bytes = 6 * 1024 * 1024;   // widest strip up to this slab size (measured)
 
 // The plan for an explicit request (passes 0..3, strip 0/8..64; 0 = by size).
 HvPlan make_plan(const kgf_sector* sec, int ov, int strip, int up_threads) {
@@ -1350,9 +1349,14 @@ HvPlan make_plan(const kgf_sector* sec, int ov, int strip, int up_threads) {
     if (p.passes == 2) {
         p.split = !fits1 || (ov == 3 && fits_split);
         p.nr = ov == 4 ? 1 : 2;
+        // the widest strip up to 64 columns that the rows fill: wide strips give
+        // the gathers long contiguous row segments, and what the slab loses to
+        // L2 (5.9 MB at 32 columns, 11.7 MB at 64 at L = 16) is served by the
+        // Infinity Cache (L = 16 strip pass: 3.36 / 2.99 / 2.87 / 2.86 ms at
+        // 16 / 32 / 64 / 128 columns; L = 14: 0.174 ms at 64, 0.193 at 128)
         p.C = 8;
         for (int c : {64, 32, 16})
-            if ((size_t)Dup * c * sizeof(double2) <= kStripL2Bytes) {
+            if (Ddn >= c) {
                 p.C = c;
                 break;
             }
@@ -1405,6 +1409,7 @@ void launch_up_plan(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int w, int
                     int64_t x_col, const double2* xp, int64_t xp_col, double2* y, int64_t y_col, const double* s_k,
                     const double* b_k, const double* s_km1, int stride, double* part) {
     switch (P.C) {
+        case 128: launch_up<MODE, 128>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
         case 64: launch_up<MODE, 64>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
         case 32: launch_up<MODE, 32>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
         case 16: launch_up<MODE, 16>(ctx, P, T, w, ncol, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1, stride, part); break;
@@ -1658,7 +1663,8 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         // candidate requests, one per distinct plan
         std::vector<std::pair<int, int>> cand;
         std::vector<HvPlan> plans;
-        const std::pair<int, int> reqs[] = {{1, 0}, {2, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}, {4, 0}, {4, 16}, {4, 32}};
+        const std::pair<int, int> reqs[] = {{1, 0}, {2, 0}, {2, 16}, {2, 32}, {2, 64}, {2, 128}, {3, 0}, {4, 0},
+                                            {4, 32}, {4, 64}};
         for (const auto& rq : reqs) {
             const HvPlan P = make_plan(sec, rq.first, rq.second, ctx->hv_up_threads);
             if (P.passes == 0) continue;

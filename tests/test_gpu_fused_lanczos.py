@@ -63,7 +63,7 @@ def _run(ctx, model, nu, nd, X, passes, strip, fuse, nsteps, m, err=False, up_th
 
 # up_threads: pass-2 block size
 @pytest.mark.parametrize("passes,strip,up_threads", [(2, 0, 256), (3, 0, 256), (4, 16, 256), (2, 8, 256),
-                                                     (2, 0, 1024), (3, 16, 512)])
+                                                     (2, 0, 1024), (3, 16, 512), (2, 128, 1024), (3, 64, 256)])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_fused_sil_matches_oracle(ctx, case, passes, strip, up_threads):
     name, mk, nu, nd, ncol = case

@@ -46,7 +46,7 @@ CASES = [
 
 # seg 1: the row pass with the segment hop tables (the default); 0: per-state tables
 @pytest.mark.parametrize("passes,strip,seg", [(2, 0, 1), (3, 0, 1), (2, 8, 1), (3, 16, 1), (2, 32, 1), (3, 64, 1),
-                                              (4, 0, 1), (4, 16, 1), (2, 0, 0), (3, 0, 0), (4, 0, 0)])
+                                              (2, 128, 1), (4, 0, 1), (4, 16, 1), (2, 0, 0), (3, 0, 0), (4, 0, 0)])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_apply_h_variants(ctx, case, passes, strip, seg):
     name, mk, nu, nd, nvec = case
