@@ -36,6 +36,6 @@ def test_four_time_functions_against_oracle():
         err = np.abs(out["chi"] - ref["chi"]).max()
         say("max abs err", err)
         assert np.abs(ref["chi"]).max() > 0.05, pat
-        assert err < 1e-9, pat
+        assert err < 1e-10 * np.abs(ref["chi"]).max(), pat      # the parity bar for G (measured ~1e-14)
     with pytest.raises(k.KgfError):
         ctx.greens2_neq(mi, mh, s, v0, orbs, nt=2, steps_per_grid=1, dt=0.1, pattern=(1, 1, 1, 0))
