@@ -39,7 +39,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hv_lanczos_ladder14_traffic.md")
+# committed rocprofv3 counter summaries of the L=14 H.v kernels, per profiled class
+TRAFFIC_FILES = {
+    "hv_lanczos": os.path.join(ROOT, "profiles", "hv_lanczos_ladder14_traffic.md"),
+    "hv_rows_lanczos": os.path.join(ROOT, "profiles", "hv_fused_ladder14_traffic.md"),
+    "hv_up_lanczos": os.path.join(ROOT, "profiles", "hv_fused_ladder14_traffic.md"),
+}
 
 
 def log(*a):
@@ -103,9 +108,15 @@ def parse():
     p.add_argument("--hv-up-threads", default="1024",
                    help="comma-separated kgf_set_option HV_UP_THREADS values (pass-2 block size)")
     p.add_argument("--hv-reps", type=int, default=10)
+    p.add_argument("--hv-cols", default="1",
+                   help="comma-separated column counts of the timed SIL step (the Lanczos form); the plain "
+                        "H.v is timed once per variant on one column")
     p.add_argument("--no-graphs", action="store_true",
                    help="state GRAPHS 0 explicitly (every SIL step eager, the library default); kernel traces "
                         "are taken this way")
+    p.add_argument("--hv-plan", type=int, default=0,
+                   help="ladder14 run and --probe: kgf_set_option HV_PASSES for every H.v of the run (0: the "
+                        "library's choice by size and column count, 1: single pass, 2: two pass)")
     p.add_argument("--tune", action="store_true",
                    help="let the library time the equivalent H.v variants per sector "
                         "(kgf_set_option HV_TUNE) and keep the fastest")
@@ -141,22 +152,32 @@ def hv_bench(a):
             ctx.apply_h(m, sec, x, y)      # warm-up (tables, LDS opt-in)
             torch.cuda.synchronize()
             log(f"L={L} D={sec.dim} passes={passes} strip={strip} fuse={fuse} seg={seg} up_threads={uthr}: timing")
-            ctx.profile_begin(1)
-            for _ in range(a.hv_reps):
-                ctx.apply_h(m, sec, x, y)
-            xs = x.clone().reshape(1, -1)
-            ctx.propagate(m, sec, xs, 1, q.dt, q.krylov_dim, +1)
-            torch.cuda.synchronize()
-            st = ctx.profile_end()
-            out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip, "fuse": fuse, "seg": seg,
-                   "up_threads": uthr}
-            for k in ("hv", "hv_lanczos", "hv_rows_lanczos", "hv_up_lanczos", "lanczos_update", "combine"):
-                if k in st and st[k]["sampled"]:
-                    ms = st[k]["sampled_ms"] / st[k]["sampled"]
-                    gbs = st[k]["sampled_bytes"] / (st[k]["sampled_ms"] * 1e-3) / 1e9
-                    out[k] = {"avg_ms": round(ms, 4), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBPS, 4)}
-            print(json.dumps(out), flush=True)
-            del xs
+            for ci, ncols in enumerate(int(v) for v in a.hv_cols.split(",") if v):
+                xs = x.clone().reshape(1, -1).repeat(ncols, 1)
+                ctx.propagate(m, sec, xs, 1, q.dt, q.krylov_dim, +1)    # warm-up at this width (tuner, workspaces)
+                torch.cuda.synchronize()
+                ctx.profile_begin(1)
+                if ci == 0:
+                    for _ in range(a.hv_reps):
+                        ctx.apply_h(m, sec, x, y)
+                ctx.propagate(m, sec, xs, 1, q.dt, q.krylov_dim, +1)
+                torch.cuda.synchronize()
+                st = ctx.profile_end()
+                out = {"hv_bench": L, "D": sec.dim, "passes": passes, "strip": strip, "fuse": fuse, "seg": seg,
+                       "up_threads": uthr, "cols": ncols}
+                step_ms = 0.0
+                for k in ("hv", "hv_lanczos", "hv_rows_lanczos", "hv_up_lanczos", "lanczos_update", "combine"):
+                    if k in st and st[k]["sampled"]:
+                        ms = st[k]["sampled_ms"] / st[k]["sampled"]
+                        gbs = st[k]["sampled_bytes"] / (st[k]["sampled_ms"] * 1e-3) / 1e9
+                        out[k] = {"avg_ms": round(ms, 4), "GBps": round(gbs, 1),
+                                  "frac": round(gbs / HBM_PEAK_GBPS, 4)}
+                        if k != "hv":
+                            step_ms += st[k]["sampled_ms"]
+                out["sil_step_ms_per_column"] = round(step_ms / ncols, 4)
+                print(json.dumps(out), flush=True)
+                del xs
+                torch.cuda.empty_cache()
         ctx.set_option(ctx.HV_PASSES, 0)
         ctx.set_option(ctx.HV_STRIP, 0)
         ctx.set_option(ctx.HV_TUNE, 0)
@@ -178,9 +199,11 @@ def probe(a):
     import workloads as wl
     q = wl.ladder14() if a.probe_L == 14 else wl.ladder16()
     ctx = kgf.Context(0)
+    if a.hv_plan:
+        ctx.set_option(ctx.HV_PASSES, a.hv_plan)
     m = ctx.model(q.H)
     sec = ctx.sector(a.probe_L, q.n_up - 1, q.n_dn)
-    log(f"probe: L={a.probe_L} D={sec.dim} cols={a.probe_cols}")
+    log(f"probe: L={a.probe_L} D={sec.dim} cols={a.probe_cols} hv_plan={a.hv_plan}")
     g = torch.Generator(device="cuda:0").manual_seed(11)
     X = torch.randn(a.probe_cols, sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
     ctx.propagate(m, sec, X, 1, q.dt, q.krylov_dim, +1)
@@ -798,18 +821,21 @@ def fig1(a):
     print(json.dumps(res), flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per algorithmic byte of the dominant kernel from the
-    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each
-    scaled by the plain-copy calibration).  None when the kernel source has
-    changed since the counters were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per algorithmic byte of a kernel class from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    plain-copy calibration).  None when there is no summary for the class or
+    the kernel source has changed since the counters were taken."""
     import hashlib
+    if kernel not in TRAFFIC_FILES:
+        return None
     src = os.path.join(ROOT, "paper_1109_1205_amd", "csrc", "hamiltonian.hip")
     cur = hashlib.sha1(open(src, "rb").read()).hexdigest()
     ratio, sha = None, None
+    keys = ("traffic_bytes_per_algorithmic_byte:", f"traffic_bytes_per_algorithmic_byte.{kernel}:")
     try:
-        for line in open(TRAFFIC_FILE):
-            if line.startswith("traffic_bytes_per_algorithmic_byte:"):
+        for line in open(TRAFFIC_FILES[kernel]):
+            if line.startswith(keys):
                 ratio = float(line.split(":", 1)[1].strip())
             if line.startswith("kernel_source_sha1:"):
                 sha = line.split(":", 1)[1].split()[0]
@@ -884,13 +910,22 @@ def main():
     stepwise(a)
 
 
-def roofline_of(stats, kernel="hv_lanczos"):
-    """roofline object of the dominant kernel from the library's HIP-event
-    samples, plus a per-class kernel table."""
-    dom = max(stats.items(), key=lambda kv: kv[1]["sampled_ms"] / max(kv[1]["sampled"], 1) * kv[1]["launches"])
-    hv = stats.get(kernel, dom[1])
+HV_CLASSES = ("hv_lanczos", "hv_up_lanczos", "hv_rows_lanczos")
+
+
+def roofline_of(stats):
+    """roofline object of the dominant H.v kernel (the Lanczos-form H.v class
+    with the most time: the single pass, or the strip or row pass of the
+    fused two-pass step) from the library's HIP-event samples, plus a
+    per-class kernel table."""
+    def total(v):
+        return v["sampled_ms"] / max(v["sampled"], 1) * v["launches"]
+    dom = max(stats.items(), key=lambda kv: total(kv[1]))
+    present = [k for k in HV_CLASSES if k in stats and stats[k]["sampled"]]
+    kernel = max(present, key=lambda k: total(stats[k])) if present else dom[0]
+    hv = stats[kernel]
     achieved = hv["sampled_bytes"] / (hv["sampled_ms"] * 1e-3) / 1e9 if hv["sampled_ms"] > 0 else 0.0
-    tb = measured_traffic()
+    tb = measured_traffic(kernel)
     avg_launch_bytes = hv["sampled_bytes"] / max(hv["sampled"], 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -924,6 +959,8 @@ def stepwise(a):
     ctx = kgf.Context(0)
     if a.tune:
         ctx.set_option(ctx.HV_TUNE, 1)
+    if a.hv_plan:
+        ctx.set_option(ctx.HV_PASSES, a.hv_plan)
     if a.no_graphs:
         ctx.set_option(ctx.GRAPHS, 0)
     m_ini, m_fin = ctx.model(q.H_ini), ctx.model(q.H)

@@ -1373,6 +1373,8 @@ HvPlan make_plan(const kgf_sector* sec, int ov, int strip, int up_threads) {
 std::array<int, 4> tune_key(const kgf_sector* sec, int mode) { return {sec->L, sec->n_up, sec->n_dn, mode}; }
 
 // Explicit options win; then a tuned choice (kgf_set_option HV_TUNE); then sizes.
+// mode 0: plain H.v; 1: Lanczos form of one column (and any unfused one);
+// 2: the fused Lanczos step over several columns (hv_fused_plan).
 HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec, int mode) {
     const int ut = ctx->hv_up_threads;
     if (ctx->hv_passes || ctx->hv_strip) return make_plan(sec, ctx->hv_passes, ctx->hv_strip, ut);
@@ -1381,6 +1383,31 @@ HvPlan hv_plan(const kgf_ctx* ctx, const kgf_sector* sec, int mode) {
         if (it != ctx->hv_tuned.end()) return make_plan(sec, it->second.first, it->second.second, ut);
     }
     return make_plan(sec, 0, 0, ut);
+}
+
+// Bytes of the Infinity Cache (MALL) in front of HBM.
+constexpr double kMallBytes = 256.0 * 1024 * 1024;
+
+// The plan of a fused Lanczos step over ncol columns (two-pass when it is
+// one).  By size, rows that fit the single pass keep it for one column; for
+// several columns of at least 64 MB each that together exceed the Infinity
+// Cache, the fused two-pass step is taken instead: the single pass's update
+// pass (48 B per element) then streams from HBM rather than from the cache
+// that still holds the vector it has just written, and the two-pass step
+// needs no update pass.  2x7 ladder, ms per Lanczos step and column, single
+// pass + update against two-pass: 0.300 / 0.310 at one column, 0.306 /
+// 0.301 at two, 0.311 / 0.301 at four, 0.324 / 0.297 at 65.
+HvPlan hv_fused_plan(const kgf_ctx* ctx, const kgf_sector* sec, int ncol) {
+    const int ut = ctx->hv_up_threads;
+    if (ctx->hv_passes || ctx->hv_strip || ncol <= 1) return hv_plan(ctx, sec, 1);
+    if (ctx->hv_tune) {
+        auto it = ctx->hv_tuned.find(tune_key(sec, 2));
+        if (it != ctx->hv_tuned.end()) return make_plan(sec, it->second.first, it->second.second, ut);
+    }
+    HvPlan p = make_plan(sec, 0, 0, ut);
+    const double col = 16.0 * (double)sec->dim();
+    if (p.passes == 1 && col >= 64.0 * 1024 * 1024 && col * ncol > kMallBytes) p = make_plan(sec, 2, 0, ut);
+    return p;
 }
 
 template <int MODE, int C, int NT>
@@ -1654,10 +1681,11 @@ void hv_lanczos_groups(kgf_ctx* ctx, const std::vector<GroupSpec>& groups, const
     }
 }
 
-void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
+void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol) {
     if (!ctx->hv_tune || ctx->hv_passes || ctx->hv_strip || sec->dim() == 0) return;
     const int64_t D = sec->dim();
-    for (int mode = 0; mode < 2; ++mode) {
+    constexpr int so_m_tune = 20;   // Krylov dimension of the timed SIL step
+    for (int mode = 0; mode < (ncol > 1 ? 3 : 2); ++mode) {
         const auto key = tune_key(sec, mode);
         if (ctx->hv_tuned.count(key)) continue;
         // candidate requests, one per distinct plan
@@ -1682,13 +1710,23 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         }
         int64_t nblk = sec->d_up;
         for (const auto& P : plans) nblk = std::max<int64_t>(nblk, P.up_blocks);
-        ensure_device_fits(2 * sizeof(double2) * (size_t)D, "H.v tuning vectors");
-        double2* x = static_cast<double2*>(workspace(ctx, "hv_tune_x", 2 * sizeof(double2) * (size_t)D));
+        // mode 2 times up to 8 columns (as many as the launches have, within a
+        // quarter of the free memory with their Krylov bases), at least two
+        int ntc = mode == 2 ? std::min(ncol, 8) : 1;
+        if (mode == 2) {
+            size_t fr = 0, tot = 0;
+            KGF_HIP(hipMemGetInfo(&fr, &tot));
+            const double per_col = sizeof(double2) * (double)D * (so_m_tune + 2);
+            while (ntc > 2 && ntc * per_col > 0.25 * (double)fr) --ntc;
+        }
+        const int64_t nxv = std::max<int64_t>(2, ntc);
+        ensure_device_fits(nxv * sizeof(double2) * (size_t)D, "H.v tuning vectors");
+        double2* x = static_cast<double2*>(workspace(ctx, "hv_tune_x", nxv * sizeof(double2) * (size_t)D));
         double2* y = x + D;
         double* aux = static_cast<double*>(workspace(ctx, "hv_tune_aux", sizeof(double) * (size_t)(nblk + 3)));
         (void)aux;
         if (mode == 0) KGF_HIP(hipMemsetAsync(x, 0, 2 * sizeof(double2) * (size_t)D, ctx->stream));
-        else fill_splitmix(ctx, x, D, 0x7e57ULL);
+        else fill_splitmix(ctx, x, ntc * D, 0x7e57ULL);
         const bool prof = ctx->prof_on;
         const int graphs = ctx->use_graphs;
         ctx->prof_on = false;
@@ -1698,11 +1736,12 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
         KGF_HIP(hipEventCreate(&e1));
         int best = 0;
         float best_ms = 0.0f;
-        // The Lanczos form is timed as one SIL step (Krylov dimension 20, one
-        // column) with the candidate plan in force, so that the update is part
-        // of the comparison: a pass of its own after a single-pass H.v, folded
-        // into the row pass of a two-pass plan.
-        const SilOpts so{20, 0, 0.05, 1, 0.0, 1e-13};
+        // The Lanczos form is timed as one SIL step (Krylov dimension 20; one
+        // column in mode 1, ntc in mode 2, the choice for launches of several
+        // columns) with the candidate plan in force, so that the update is
+        // part of the comparison: a pass of its own after a single-pass H.v,
+        // folded into the row pass of a two-pass plan.
+        const SilOpts so{so_m_tune, 0, 0.05, 1, 0.0, 1e-13};
         for (size_t c = 0; c < plans.size(); ++c) {
             auto run = [&] {
                 if (mode == 0) {
@@ -1711,7 +1750,7 @@ void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
                 } else {
                     ctx->hv_passes = cand[c].first;
                     ctx->hv_strip = cand[c].second;
-                    sil_propagate(ctx, model, sec, x, 1, D, 1, so);
+                    sil_propagate(ctx, model, sec, x, ntc, D, 1, so);
                     ctx->hv_passes = 0;
                     ctx->hv_strip = 0;
                 }
@@ -1750,8 +1789,20 @@ void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec, const double2* v
 }
 
 int hv_part_capacity(kgf_ctx* ctx, const kgf_sector* sec) {
-    // pass 1 of the fused step writes at most one partial per row
-    return (int)std::max<int64_t>(hv_lanczos_blocks(ctx, sec), sec->d_up);
+    // pass 1 of the fused step writes at most one partial per row; pass 2 of
+    // a fused step over several columns may be two-pass where the
+    // one-column plan is not
+    int64_t n = std::max<int64_t>(hv_lanczos_blocks(ctx, sec), sec->d_up);
+    const HvPlan P2 = make_plan(sec, 2, 0, ctx->hv_up_threads);
+    if (P2.passes == 2) n = std::max<int64_t>(n, P2.up_blocks);
+    if (ctx->hv_tune) {
+        auto it = ctx->hv_tuned.find(tune_key(sec, 2));
+        if (it != ctx->hv_tuned.end()) {
+            const HvPlan Pt = make_plan(sec, it->second.first, it->second.second, ctx->hv_up_threads);
+            if (Pt.passes == 2) n = std::max<int64_t>(n, Pt.up_blocks);
+        }
+    }
+    return (int)n;
 }
 
 int hv_lanczos_blocks(kgf_ctx* ctx, const kgf_sector* sec) {
@@ -1765,16 +1816,17 @@ void hv_lanczos(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol,
                  a.s_km1, a.stride, a.part);
 }
 
-int hv_lanczos_rows_blocks(kgf_ctx* ctx, HModel model, const kgf_sector* sec) {
+int hv_lanczos_rows_blocks(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int* up_blocks) {
     const SegInfo* sg;
     const void* stab;
-    const HvPlan P = hv_plan(ctx, sec, 1);
+    const HvPlan P = hv_fused_plan(ctx, sec, ncol);
     if (P.passes != 2) return 0;
+    if (up_blocks) *up_blocks = (int)P.up_blocks;
     return (int)rows_blocks(with_seg(ctx, model, sec, P, &sg, &stab), sec);
 }
 
 void hv_lanczos_rows(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosRowsArgs& a) {
-    const HvPlan P = hv_plan(ctx, sec, 1);
+    const HvPlan P = hv_fused_plan(ctx, sec, ncol);
     KGF_REQUIRE(P.passes == 2, KGF_EINVAL, "fused Lanczos step: the sector's H.v is not two-pass");
     KGF_REQUIRE(sec->d_up <= 0x7ffffff0 && ncol <= 65535, KGF_EUNSUPPORTED, "H.v: grid too large");
     HvTables T = make_tables(model, sec);
@@ -1793,7 +1845,7 @@ void hv_lanczos_rows(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol
 }
 
 void hv_lanczos_up(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosHvArgs& a) {
-    const HvPlan P = hv_plan(ctx, sec, 1);
+    const HvPlan P = hv_fused_plan(ctx, sec, ncol);
     KGF_REQUIRE(P.passes == 2, KGF_EINVAL, "fused Lanczos step: the sector's H.v is not two-pass");
     KGF_REQUIRE(P.up_blocks <= 0x7fffffff && (int64_t)model.m->nb * sec->d_dn < ((int64_t)1 << 32),
                 KGF_EUNSUPPORTED, "H.v: strip grid or hop table too large");

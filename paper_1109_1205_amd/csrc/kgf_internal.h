@@ -269,8 +269,9 @@ struct HModel {
 void apply_h(kgf_ctx* ctx, HModel model, const kgf_sector* sec,
              const double2* v, double2* w, int nvec, int64_t ld);
 // With ctx->hv_tune set, times the equivalent H.v variants of the sector once
-// (plain and Lanczos forms) and keeps the fastest; a no-op otherwise.
-void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec);
+// (plain and Lanczos forms; the Lanczos form separately for one column and,
+// when ncol > 1, for several) and keeps the fastest; a no-op otherwise.
+void hv_prepare(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol = 1);
 void apply_c(kgf_ctx* ctx, const kgf_sector* src, const kgf_sector* dst, int orbital,
              int dagger, const double2* v, double2* w, int nvec, int64_t ld_src,
              int64_t ld_dst);
@@ -322,8 +323,13 @@ struct LanczosRowsArgs {
     int stride;
     double* part;                          // [ncol][hv_lanczos_rows_blocks]
 };
-// pass-1 blocks (norm partials) per column; 0 when the plan is not two-pass
-int hv_lanczos_rows_blocks(kgf_ctx* ctx, HModel model, const kgf_sector* sec);
+// Pass-1 blocks (norm partials) per column of a fused step over ncol
+// columns; 0 when that step is not two-pass.  up_blocks (if given) receives
+// the pass-2 partials per column.  Where the rows fit the single pass, the
+// fused two-pass step is chosen for launches whose columns together exceed
+// the Infinity Cache: the single pass's separate update pass then streams
+// from HBM instead of finding the vector it just wrote in that cache.
+int hv_lanczos_rows_blocks(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, int* up_blocks = nullptr);
 void hv_lanczos_rows(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosRowsArgs& a);
 void hv_lanczos_up(kgf_ctx* ctx, HModel model, const kgf_sector* sec, int ncol, const LanczosHvArgs& a);
 

@@ -1010,7 +1010,8 @@ static void sil_build_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, doubl
         check_launch("k_norm2");
     }
     launch_fin(ctx, FIN_INIT, 0, part, NB, scal, ncol, 0.0);
-    const int RB = (o.reorth == 0 && ctx->hv_fuse) ? hv_lanczos_rows_blocks(ctx, model, sec) : 0;
+    int UB = 0;   // pass-2 partials of a fused step
+    const int RB = (o.reorth == 0 && ctx->hv_fuse) ? hv_lanczos_rows_blocks(ctx, model, sec, ncol, &UB) : 0;
     if (RB > 0) {
         // two-pass H.v: the update of step k - 1 rides in the row pass of step k
         for (int k = 0; k < m; ++k) {
@@ -1040,7 +1041,7 @@ static void sil_build_w(kgf_ctx* ctx, HModel model, const kgf_sector* sec, doubl
             a.stride = kScalStride;
             a.part = part;
             hv_lanczos_up(ctx, model, sec, ncol, a);
-            launch_fin(ctx, FIN_A, k, part, HB, scal, ncol, 0.0);
+            launch_fin(ctx, FIN_A, k, part, UB, scal, ncol, 0.0);
         }
         if (w.err) {   // b_m for the error estimate
             {
@@ -1109,7 +1110,7 @@ static SilWork sil_work_ws(kgf_ctx* ctx, const kgf_sector* sec, int ncol, const 
 void sil_build(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* psi, int ncol, int64_t ld,
                const SilOpts& o) {
     KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
-    hv_prepare(ctx, model, sec);
+    hv_prepare(ctx, model, sec, ncol);
     sil_reserve(ctx, sec, ncol, o.m, o.reorth);
     sil_build_w(ctx, model, sec, psi, ncol, ld, o, sil_work_ws(ctx, sec, ncol, o));
 }
@@ -1324,7 +1325,7 @@ void sil_propagate(kgf_ctx* ctx, HModel model, const kgf_sector* sec, double2* p
         }
     for (int step = 0; step < nsteps; ++step) {
         KGF_REQUIRE(ncol <= 65535, KGF_EUNSUPPORTED, "SIL: at most 65535 columns per batch");
-        hv_prepare(ctx, model, sec);
+        hv_prepare(ctx, model, sec, ncol);
         sil_reserve(ctx, sec, ncol, o.m, o.reorth);
         SilWork w = sil_work_ws(ctx, sec, ncol, o);
         w.err = err;

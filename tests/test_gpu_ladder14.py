@@ -91,3 +91,23 @@ def test_sil_step_ladder14(ctx, oracle_h, sil_ref, passes):
     for c in range(2):
         assert rel_err(got[c], ref[c]) < 1e-12, c
 
+
+
+def test_sil_step_ladder14_default_plan_by_width(ctx, oracle_h, sil_ref):
+    """The library's own choice (no option set): one column (165 MB) keeps
+    the single pass plus the update pass; two and three columns (330 and
+    495 MB, beyond the 256 MB Infinity Cache) take the fused two-pass step.
+    All against the oracle's SIL step, <= 1e-12."""
+    q, sec, H = oracle_h
+    X, ref = sil_ref
+    m, s = ctx.model(q.H), ctx.sector(14, 6, 7)
+    for cols, fused in ((1, False), (2, True), (3, True)):
+        idx = [c % 2 for c in range(cols)]
+        say("ladder14 SIL step: default plan,", cols, "columns")
+        ctx.profile_begin(1)
+        got = to_host(ctx.propagate(m, s, to_dev(X[idx]), 1, q.dt, q.krylov_dim, +1))
+        st = ctx.profile_end()
+        assert ("hv_up_lanczos" in st) == fused and ("hv_lanczos" in st) == (not fused), sorted(st)
+        assert ("lanczos_update" in st) == (not fused), sorted(st)
+        for c in range(cols):
+            assert rel_err(got[c], ref[idx[c]]) < 1e-12, (cols, c)
