@@ -1080,6 +1080,96 @@ __global__ __launch_bounds__(NT) void k_hv_up(HvTables T, int nstrip, int ntile,
     }
 }
 
+// Pass 2 for strips of 64 columns: one wavefront per row, so that the row's
+// hop count, its packed hop entries, the bond amplitudes and the source-row
+// addresses are uniform over the wavefront and live in scalar registers
+// (scalar loads, scalar branches); the vector unit issues only the gathers,
+// each a 1 KB row piece at a scalar base plus the lane's column offset, and
+// the two FMAs per hop.  No LDS staging and no barrier before the final
+// reduction.  Same tiles, block order and partials as k_hv_up<MODE, 64, NT>.
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_hv_up_w(HvTables T, int nstrip, int ntile,
+                                                const double2* __restrict__ X, int64_t x_col,
+                                                const double2* __restrict__ XP, int64_t xp_col,
+                                                double2* __restrict__ Y, int64_t y_col,
+                                                const double* __restrict__ s_k, const double* __restrict__ b_k,
+                                                const double* __restrict__ s_km1, int stride,
+                                                double* __restrict__ part) {
+    constexpr int R = NT / 64;
+    __shared__ double s_red[NT / 64];
+    const int blk = blockIdx.x;
+    const int q = blk >> 3;
+    const int strip = (q / ntile) * 8 + (blk & 7);
+    const int tile = q % ntile;
+    const int c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t Ddn = T.Ddn, Dup = T.Dup;
+    // the wavefront's row: uniform by construction
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t u = (int64_t)tile * R + wv;
+    const int dcol = strip * 64 + (tid & 63);
+    const bool live = strip < nstrip && u < Dup && dcol < Ddn;
+    const double2* __restrict__ x = X + c * x_col;
+    double2* __restrict__ y = Y + c * y_col;
+    double sc = 1.0, bp = 0.0;
+    if (MODE == 1) {
+        sc = s_k[c * stride];
+        if (XP) bp = b_k[c * stride] * s_km1[c * stride];
+    }
+    const int64_t ix = u * Ddn + dcol;
+    double2 w = make_double2(0.0, 0.0), p = w, xv = w;
+    if (live) {
+        w = ld_stream(y + ix);
+        if (MODE == 1) {
+            xv = x[ix];
+            if (bp != 0.0) p = ld_stream(XP + c * xp_col + ix);
+        }
+    }
+    double dot = 0.0;
+    if (live) {
+        const double* __restrict__ tb = T.t + par_index(T, c) * T.nb;
+        const int cu = T.cnt_up[u];
+        const uint32_t* __restrict__ eu = T.ent_up + u;
+        double ar = 0.0, ai = 0.0;
+        constexpr int kBatch = 8;
+        for (int k0 = 0; k0 < cu; k0 += kBatch) {
+            double2 z[kBatch];
+            uint32_t e[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) e[j] = __builtin_amdgcn_readfirstlane(eu[(int64_t)(k0 + j) * Dup]);
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) z[j] = (x + (int64_t)(e[j] & 0xFFFFFFu) * Ddn)[dcol];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (k0 + j < cu) {
+                    const double v = tb[(e[j] >> 24) & 127u];
+                    const double tv = (e[j] >> 31) ? v : -v;   // amplitude -t, negated by the sign bit
+                    ar = fma(tv, z[j].x, ar);
+                    ai = fma(tv, z[j].y, ai);
+                }
+        }
+        w.x += ar;
+        w.y += ai;
+        if (MODE == 1) {
+            w.x *= sc;
+            w.y *= sc;
+            if (bp != 0.0) {
+                w.x = fma(-bp, p.x, w.x);
+                w.y = fma(-bp, p.y, w.y);
+            }
+            dot = fma(sc * xv.x, w.x, dot);
+            dot = fma(sc * xv.y, w.y, dot);
+        }
+        st_stream(y + ix, w);
+    }
+    if (MODE == 1) {
+        const double sum = block_sum(dot, s_red);
+        if (tid == 0) part[(int64_t)c * gridDim.x + blk] = sum;
+    }
+}
+
 // c_alpha / c+_alpha between sectors.  For an up-spin orbital the map is a
 // gather of whole rows, for a down-spin orbital a gather inside each row.
 __device__ __forceinline__ int64_t rank_of(uint32_t m, const uint64_t* C) {
@@ -1414,6 +1504,12 @@ template <int MODE, int C, int NT>
 void launch_up_nt(kgf_ctx* ctx, const HvPlan& P, const HvTables& T, int width, int ncol, const double2* x,
                   int64_t x_col, const double2* xp, int64_t xp_col, double2* y, int64_t y_col, const double* s_k,
                   const double* b_k, const double* s_km1, int stride, double* part) {
+    if (C == 64) {   // one wavefront per row: the row's hop data in scalar registers
+        hipLaunchKernelGGL((k_hv_up_w<MODE, NT>), dim3((unsigned)P.up_blocks, (unsigned)ncol), dim3(NT), 0,
+                           ctx->stream, T, P.nstrip, P.ntile, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1,
+                           stride, part);
+        return;
+    }
     const size_t lds = sizeof(uint32_t) * (size_t)(NT / C) * width;
     hipLaunchKernelGGL((k_hv_up<MODE, C, NT>), dim3((unsigned)P.up_blocks, (unsigned)ncol), dim3(NT), lds,
                        ctx->stream, T, P.nstrip, P.ntile, width, x, x_col, xp, xp_col, y, y_col, s_k, b_k, s_km1,
