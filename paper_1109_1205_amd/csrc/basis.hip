@@ -260,6 +260,32 @@ HopTable& hop_table(kgf_model* model, int n) {
         check_launch("k_onsite");
         sync(ctx);   // the temporaries above are freed on return
     }
+    // Row order of the strip pass: a hop inside either half of the lattice
+    // keeps the upper half's particle count, so the rows of one count draw
+    // their up-spin sources (all but the few hops across the halves) from the
+    // same group, whose strip stays in L2 while it is swept.  Stable counting
+    // sort of the ascending masks by that count.
+    {
+        t->order.reserve(sizeof(int32_t) * (D ? D : 1));
+        if (D) {
+            const int half = model->L / 2;
+            std::vector<int> key((size_t)D);
+            std::vector<int64_t> start(model->L + 2, 0);
+            uint64_t m = n ? ((uint64_t)1 << n) - 1 : 0;
+            for (int64_t r = 0; r < D; ++r) {
+                key[(size_t)r] = __builtin_popcountll(m >> half);
+                ++start[(size_t)key[(size_t)r] + 1];
+                if (m) {   // next mask of the same popcount (ascending)
+                    const uint64_t c = m & (~m + 1), rr = m + c;
+                    m = (((rr ^ m) >> 2) / c) | rr;
+                }
+            }
+            for (int k = 0; k <= model->L; ++k) start[(size_t)k + 1] += start[(size_t)k];
+            std::vector<int32_t> ord((size_t)D);
+            for (int64_t r = 0; r < D; ++r) ord[(size_t)start[(size_t)key[(size_t)r]]++] = (int32_t)r;
+            KGF_HIP(hipMemcpy(t->order.p, ord.data(), sizeof(int32_t) * (size_t)D, hipMemcpyHostToDevice));
+        }
+    }
     build_seg_table(model, *t);
     HopTable& ref = *t;
     model->tables[n] = std::move(t);

@@ -41,6 +41,7 @@ struct HvTables {
     int npar;
     int cbase;
     const double* U0s;    // [npar] or null (then U0)
+    const int32_t* up_order;   // [Dup] row order of the strip pass (HopTable::order)
 };
 
 __device__ __forceinline__ int par_index(const HvTables& T, int c) { return T.npar > 1 ? (T.cbase + c) % T.npar : 0; }
@@ -251,6 +252,7 @@ HvTables make_tables(HModel hm, const kgf_sector* sec) {
     T.md = td.masks.as<uint32_t>();
     T.cnt_up = tu.count.as<int32_t>();
     T.ent_up = tu.ent.as<uint32_t>();
+    T.up_order = tu.order.as<int32_t>();
     T.cnt_dn = td.count.as<int32_t>();
     T.ent_dn = td.ent.as<uint32_t>();
     T.eu = tu.e_up.as<double>();
@@ -983,8 +985,9 @@ __global__ __launch_bounds__(NT) void k_hv_rows_seg(HvTables T, SegDev G, double
 }
 
 
-// Pass 2.  A block covers R = 256 / C rows of one strip; the packed hop
-// entries of its rows are staged in LDS first, so that each thread's source
+// Pass 2.  A block covers R = NT / C rows of one strip (consecutive slots of
+// the row order T.up_order); the packed hop entries of its rows are staged
+// in LDS first, so that each thread's source
 // gathers (rows x[u', strip]) are issued back to back.  With one row group
 // per block, the blocks an XCD holds at a time span about one strip.
 // MODE 0: y += T_up x.   MODE 1: y = s (y + T_up x) - bp xp, part = Re <s x, y>.
@@ -1008,9 +1011,10 @@ __global__ __launch_bounds__(NT) void k_hv_up(HvTables T, int nstrip, int ntile,
     const int c = blockIdx.y;
     const int tid = threadIdx.x;
     const int64_t Ddn = T.Ddn, Dup = T.Dup;
+    // the tile's rows are slots u0 .. u0 + R - 1 of the strip's row order
     const int64_t u0 = (int64_t)tile * R;
     const int r = tid / C;
-    const int64_t u = u0 + r;
+    const int64_t u = u0 + r < Dup ? (int64_t)T.up_order[u0 + r] : Dup;
     const int64_t d = (int64_t)strip * C + (tid % C);
     const bool live = strip < nstrip && u < Dup && d < Ddn;
     const double2* __restrict__ x = X + c * x_col;
@@ -1034,10 +1038,9 @@ __global__ __launch_bounds__(NT) void k_hv_up(HvTables T, int nstrip, int ntile,
     for (int b = tid; b < T.nb; b += blockDim.x) s_negt[b] = -T.t[par_index(T, blockIdx.y) * T.nb + b];
     for (int i = tid; i < R * width; i += blockDim.x) {
         const int rr = i % R, k = i / R;
-        const int64_t uu = u0 + rr;
-        s_ent[rr * width + k] = uu < Dup ? T.ent_up[(int64_t)k * Dup + uu] : 0u;
+        s_ent[rr * width + k] = u0 + rr < Dup ? T.ent_up[(int64_t)k * Dup + T.up_order[u0 + rr]] : 0u;
     }
-    if (tid < R) s_cnt[tid] = u0 + tid < Dup ? T.cnt_up[u0 + tid] : 0;
+    if (tid < R) s_cnt[tid] = u0 + tid < Dup ? T.cnt_up[T.up_order[u0 + tid]] : 0;
     __syncthreads();
     double dot = 0.0;
     constexpr int kBatch = 8;
@@ -1086,7 +1089,10 @@ __global__ __launch_bounds__(NT) void k_hv_up(HvTables T, int nstrip, int ntile,
 // (scalar loads, scalar branches); the vector unit issues only the gathers,
 // each a 1 KB row piece at a scalar base plus the lane's column offset, and
 // the two FMAs per hop.  No LDS staging and no barrier before the final
-// reduction.  Same tiles, block order and partials as k_hv_up<MODE, 64, NT>.
+// reduction.  Same tiles, block order and partials as k_hv_up<MODE, 64, NT>;
+// the rows of a strip are taken in the order T.up_order (grouped by the
+// upper half's particle count), so that the rows an XCD holds at a time
+// draw their sources from one group of the strip.
 template <int MODE, int NT>
 __global__ __launch_bounds__(NT) void k_hv_up_w(HvTables T, int nstrip, int ntile,
                                                 const double2* __restrict__ X, int64_t x_col,
@@ -1104,9 +1110,11 @@ __global__ __launch_bounds__(NT) void k_hv_up_w(HvTables T, int nstrip, int ntil
     const int c = blockIdx.y;
     const int tid = threadIdx.x;
     const int64_t Ddn = T.Ddn, Dup = T.Dup;
-    // the wavefront's row: uniform by construction
+    // the wavefront's row (uniform by construction): slot tile * R + wave of
+    // the strip's row order
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t u = (int64_t)tile * R + wv;
+    const int64_t slot = (int64_t)tile * R + wv;
+    const int64_t u = slot < Dup ? (int64_t)T.up_order[slot] : Dup;
     const int dcol = strip * 64 + (tid & 63);
     const bool live = strip < nstrip && u < Dup && dcol < Ddn;
     const double2* __restrict__ x = X + c * x_col;

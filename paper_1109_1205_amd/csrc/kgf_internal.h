@@ -93,6 +93,9 @@ struct HopTable {
     DevBuf e_up;     // double [D]  sum_i eps_up[i] bit_i
     DevBuf e_dn;     // double [D]  sum_i eps_dn[i] bit_i
     DevBuf bond;     // uint32 [nb * D] per bond: target rank | sign << 31, or ~0u
+    DevBuf order;    // int32  [D] ranks grouped by the popcount of the mask's upper
+                     // half (L/2 and up), ascending within a group: the row order
+                     // of the up-spin strip pass of the two-pass H.v
     SegInfo seg;     // segment form (seg_table)
     DevBuf segtab;   // its packed words
 };
