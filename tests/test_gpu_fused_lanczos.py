@@ -88,3 +88,26 @@ def test_fused_sil_error_estimate(ctx):
     ref, e0 = _run(ctx, model, 5, 5, X, 2, 0, 0, 2, 10, err=True)
     assert rel_err(got, ref) < 1e-13
     assert e0 > 0 and abs(e1 - e0) <= 1e-8 * e0
+
+
+@pytest.fixture(scope="module")
+def wide_up_case():
+    """2x8 ladder with 7 up and 2 down electrons: D = 11,440 x 120 =
+    1,372,800; a strip of 64 (32) columns of x is 11.7 (5.9) MB, more than
+    one XCD's 4 MB L2, so the strip pass walks its rows grouped by the upper
+    half's particle count; strips of 16 (2.9 MB) keep rank order."""
+    model = wl.ladder(8, 1.0, 4.0).with_field(3, 0.2)
+    sec = basis.Sector(16, 7, 2)
+    H = hamiltonian.Hamiltonian(model, sec)
+    X = np.stack([wl.complex_vector(sec.dim, 90 + c) for c in range(2)])
+    say("grouped strip rows: oracle SIL steps")
+    ref = np.stack([propagate.propagate(H.apply, X[c], 0.07, 2, 12, -1, 0.0, "none") for c in range(2)])
+    return model, X, ref
+
+
+@pytest.mark.parametrize("strip", [64, 32, 16])
+def test_fused_sil_grouped_strip_rows(ctx, wide_up_case, strip):
+    model, X, ref = wide_up_case
+    say("grouped strip rows: fused SIL, strip", strip)
+    got = _run(ctx, model, 7, 2, X, 2, strip, 1, 2, 12, up_threads=1024)
+    assert rel_err(got, ref) < 1e-12

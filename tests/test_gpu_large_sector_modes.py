@@ -99,28 +99,44 @@ def test_option_rejects_bad_values(ctx):
         ctx.set_option(99, 0)
 
 
-def test_apply_h_ladder16_sampled_rows(ctx):
-    """2x8 ladder, c-sector (7, 8): D = 11,440 x 12,870 = 147,232,800
-    (2.36 GB per vector). Rows sampled across the matrix (first, last,
-    ragged tail of the strip grid, random) against the oracle row by row."""
-    import torch
+@pytest.fixture(scope="module")
+def ladder16_rows():
     q = wl.ladder16()
     sec = basis.Sector(16, 7, 8)
     say("H.v ladder16 sampled rows: building oracle tables")
     H = hamiltonian.Hamiltonian(q.H, sec)
     rng = np.random.default_rng(16)
     rows = sorted({0, 1, 2, sec.d_up // 2, sec.d_up - 2, sec.d_up - 1, *rng.integers(0, sec.d_up, 6).tolist()})
+    return q, sec, H, rows, {}
+
+
+# strip 0: the default (64 columns, one wavefront per row, rows grouped by
+# the upper half's particle count: a 64-column strip is 11.7 MB); 32: the
+# general strip kernel with grouped rows (5.9 MB strips); 16: rank order
+# (2.9 MB strips fit one XCD's L2)
+@pytest.mark.parametrize("strip", [0, 32, 16])
+def test_apply_h_ladder16_sampled_rows(ctx, ladder16_rows, strip):
+    """2x8 ladder, c-sector (7, 8): D = 11,440 x 12,870 = 147,232,800
+    (2.36 GB per vector). Rows sampled across the matrix (first, last,
+    ragged tail of the strip grid, random) against the oracle row by row."""
+    import torch
+    q, sec, H, rows, memo = ladder16_rows
     g = torch.Generator(device="cuda:0").manual_seed(5)
     x = torch.randn(sec.dim, dtype=torch.complex128, device="cuda:0", generator=g)
-    say("H.v ladder16: GPU product")
-    y = ctx.apply_h(ctx.model(q.H), ctx.sector(16, 7, 8), x)
+    say("H.v ladder16: GPU product, strip", strip)
+    ctx.set_option(STRIP, strip)
+    try:
+        y = ctx.apply_h(ctx.model(q.H), ctx.sector(16, 7, 8), x)
+    finally:
+        ctx.set_option(STRIP, 0)
     xh = x.cpu().numpy()
     yh = y.reshape(sec.d_up, sec.d_dn)[rows].cpu().numpy()
     del x, y
     torch.cuda.empty_cache()
-    say("H.v ladder16: oracle rows", rows)
-    ref = H.apply_rows(xh, rows)
-    assert rel_err(yh, ref) < 1e-13
+    if "ref" not in memo:   # the same seeded x for every strip width
+        say("H.v ladder16: oracle rows", rows)
+        memo["ref"] = H.apply_rows(xh, rows)
+    assert rel_err(yh, memo["ref"]) < 1e-13
 
 
 @pytest.mark.parametrize("cap", [12, 40])
