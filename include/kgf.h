@@ -508,6 +508,8 @@ typedef struct {
     int     branch;              /* index of the next interval's sweep (order above), -1 when done */
     int64_t vector_steps;        /* single-column SIL steps run by this call              */
     int64_t total_vector_steps;  /* single-column SIL steps since creation                */
+    int     chunk_start;         /* 1 when the next interval begins a chunk, or when done
+                                    (where kgf_neq_run_checkpoint may be called)          */
 } kgf_neq_run_info;
 int  kgf_neq_run_create(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H, const kgf_sector* sector,
                         const kgf_gs_opts* gs_opts, const kgf_c128* v0, const int32_t* host_orbs, int n_orb,
@@ -516,6 +518,29 @@ int  kgf_neq_run_create(kgf_ctx* ctx, const kgf_model* H_ini, const kgf_model* H
 int  kgf_neq_run_advance(kgf_neq_run* run, int n_intervals, kgf_neq_run_info* host_info);
 int  kgf_neq_run_result(kgf_neq_run* run, kgf_c128* host_G_lesser, kgf_c128* host_G_greater);
 void kgf_neq_run_destroy(kgf_neq_run* run);
+
+/* Checkpoint and resume of a step-wise run (host spill).  The forward mesh
+ * Phi(t_k) of Sec. 4 step (ii) is recomputed from the same inputs, so an
+ * image holds only the progress of steps (iii)-(iv): the position of the
+ * backward sweeps, the dot products of Sec. 4 step (iv) placed so far for the
+ * current sweep and G^<, G^> of the finished sweeps (nt^2 n_orb^2 complex
+ * numbers each, plus nt^2 n^2 for the current sweep's n orbitals).
+ * kgf_neq_run_checkpoint: writes the image into host_buf (host memory of
+ * `bytes` bytes, owned by the caller) and its size into *host_bytes_needed
+ * (may be NULL); with host_buf NULL only the size is reported.  Valid between
+ * chunks, i.e. when the next interval starts a chunk or the run is done
+ * (kgf_neq_run_info::chunk_start == 1); KGF_EINVAL inside a chunk or for a
+ * short buffer.  The call waits for the run's device work.
+ * kgf_neq_run_restore: on a run just created (no kgf_neq_run_advance yet) from
+ * the same models, sector, v0, orbitals and options, loads an image; the run
+ * then continues where the saved one stopped, the current sweep with the
+ * saved chunk length, so that its result equals the uninterrupted run's
+ * bitwise when `batch` is given (otherwise later sweeps size their chunks
+ * from the free memory of this run).  KGF_EINVAL for an image of another run
+ * (sizes, or a ground-state energy that differs by more than 1e-12
+ * relative), a run that has advanced, or a damaged image. */
+int  kgf_neq_run_checkpoint(kgf_neq_run* run, void* host_buf, size_t bytes, size_t* host_bytes_needed);
+int  kgf_neq_run_restore(kgf_neq_run* run, const void* host_buf, size_t bytes);
 
 /* Four-step G^< and G^> (Sec. 4 steps (i)-(iv), sweep schedule) of n_inst
  * independent instances in one call.  Instances whose sectors have equal

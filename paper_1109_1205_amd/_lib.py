@@ -73,7 +73,7 @@ class _PropOpts(C.Structure):
 class _RunInfo(C.Structure):
     _fields_ = [("intervals", C.c_int), ("width", C.c_int), ("done", C.c_int), ("next_width", C.c_int),
                 ("next_mesh_index", C.c_int), ("chunk_width", C.c_int), ("branch", C.c_int),
-                ("vector_steps", C.c_int64), ("total_vector_steps", C.c_int64)]
+                ("vector_steps", C.c_int64), ("total_vector_steps", C.c_int64), ("chunk_start", C.c_int)]
 
 
 class _KStat(C.Structure):
@@ -141,6 +141,8 @@ def load_library():
         "kgf_neq_run_advance": (I, [P, I, C.POINTER(_RunInfo)]),
         "kgf_neq_run_result": (I, [P, P, P]),
         "kgf_neq_run_destroy": (None, [P]),
+        "kgf_neq_run_checkpoint": (I, [P, P, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "kgf_neq_run_restore": (I, [P, P, C.c_size_t]),
         "kgf_set_progress": (I, [P, _PROGRESS_FN, P]),
         "kgf_set_option": (I, [P, I, I]),
         "kgf_greens_omega": (I, [P, P, P, P, D, I, I, I, P, I, D, P, P, P]),
@@ -175,6 +177,7 @@ def exported_symbols() -> Sequence[str]:
             "kgf_greens_neq_vjp", "kgf_set_option", "kgf_greens_neq_multi", "kgf_greens_neq_vjp_multi", "kgf_greens_omega", "kgf_greens_eq_fine", "kgf_fourier", "kgf_model_set_params",
             "kgf_propagate_driven", "kgf_greens_neq_driven", "kgf_bath_chain", "kgf_necpt", "kgf_bath_chain_contour", "kgf_necpt_contour", "kgf_cluster_contour", "kgf_greens2_neq",
             "kgf_neq_run_create", "kgf_neq_run_advance", "kgf_neq_run_result", "kgf_neq_run_destroy",
+            "kgf_neq_run_checkpoint", "kgf_neq_run_restore",
             "kgf_propagate_noalloc", "kgf_model_get_params",
             "kgf_profile_begin",
             "kgf_profile_end"]
@@ -343,6 +346,20 @@ class NeqRun:
         Gl, Gg = _host_c128(shape), _host_c128(shape)
         _check(_lib.kgf_neq_run_result(self.handle, _np_ptr(Gl), _np_ptr(Gg)))
         return {"G_lesser": Gl, "G_greater": Gg, "E0": self.E0}
+
+    def checkpoint(self) -> bytes:
+        """kgf_neq_run_checkpoint: the run's progress as bytes (between chunks)."""
+        need = C.c_size_t(0)
+        _check(_lib.kgf_neq_run_checkpoint(self.handle, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check(_lib.kgf_neq_run_checkpoint(self.handle, buf, need.value, C.byref(need)))
+        return buf.raw[:need.value]
+
+    def restore(self, image: bytes) -> None:
+        """kgf_neq_run_restore: continue a saved run (on a run just created
+        from the same inputs)."""
+        buf = C.create_string_buffer(bytes(image), len(image))
+        _check(_lib.kgf_neq_run_restore(self.handle, buf, len(image)))
 
     def close(self):
         # see Model.close: only while the context exists

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include <cstring>
 #include "kgf_internal.h"
 
 namespace kgf {
@@ -1478,6 +1479,7 @@ struct kgf_neq_run {
     double2* Gg = nullptr;
     int64_t vector_steps = 0;
     bool done = false;
+    bool touched = false;   // advanced or restored since creation
 };
 
 namespace {
@@ -1589,6 +1591,7 @@ extern "C" int kgf_neq_run_advance(kgf_neq_run* r, int n_intervals, kgf_neq_run_
             }
         }
         r->vector_steps += steps;
+        if (ran > 0) r->touched = true;
         if (host_info) {
             host_info->intervals = ran;
             host_info->vector_steps = steps;
@@ -1599,7 +1602,116 @@ extern "C" int kgf_neq_run_advance(kgf_neq_run* r, int n_intervals, kgf_neq_run_
             host_info->chunk_width = r->done ? 0 : r->cur->chunk_width();
             host_info->branch = r->done ? -1 : (int)r->next - 1;
             host_info->total_vector_steps = r->vector_steps;
+            host_info->chunk_start = (r->done || !r->cur->in_chunk) ? 1 : 0;
         }
+    });
+}
+
+namespace {
+// Byte image of a run between chunks: header, G^<, G^> as accumulated so
+// far, and the current branch's placed dot products.
+struct RunImageHeader {
+    uint64_t magic;          // kRunImageMagic
+    int64_t D;               // sector dimension
+    int32_t nt, norb;
+    int32_t branch;          // index into kgf_neq_run::branches of the current branch, -1 when done
+    int32_t jhi, jchunk, na; // next chunk's top mesh index, chunk length, orbitals of the branch
+    int64_t vector_steps;
+    double E0;
+};
+constexpr uint64_t kRunImageMagic = 0x6b67666e72756e31ULL;   // "kgfnrun1"
+
+size_t run_image_bytes(const kgf_neq_run* r) {
+    const size_t g = sizeof(double2) * (size_t)r->A.nt * r->A.nt * r->A.norb * r->A.norb;
+    size_t raw = 0;
+    if (!r->done && r->cur) raw = sizeof(double2) * (size_t)r->A.nt * r->A.nt * r->cur->na * r->cur->na;
+    return sizeof(RunImageHeader) + 2 * g + raw;
+}
+}  // namespace
+
+extern "C" int kgf_neq_run_checkpoint(kgf_neq_run* r, void* host_buf, size_t bytes, size_t* host_bytes_needed) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(r, KGF_EINVAL, "kgf_neq_run_checkpoint: NULL run");
+        const size_t need = run_image_bytes(r);
+        if (host_bytes_needed) *host_bytes_needed = need;
+        if (!host_buf) return;   // size query
+        KGF_REQUIRE(bytes >= need, KGF_EINVAL, "kgf_neq_run_checkpoint: buffer too small");
+        KGF_REQUIRE(r->done || !r->cur->in_chunk, KGF_EINVAL,
+                    "kgf_neq_run_checkpoint: the run is inside a chunk (checkpoint where next_width == chunk_width)");
+        kgf_ctx* ctx = r->ctx;
+        KGF_HIP(hipSetDevice(ctx->device));
+        RunImageHeader h{};
+        h.magic = kRunImageMagic;
+        h.D = r->A.sec->dim();
+        h.nt = r->A.nt;
+        h.norb = r->A.norb;
+        h.branch = r->done ? -1 : (int32_t)r->next - 1;
+        h.jhi = r->done ? -1 : r->cur->jhi;
+        h.jchunk = r->done ? 0 : r->cur->jchunk;
+        h.na = r->done ? 0 : r->cur->na;
+        h.vector_steps = r->vector_steps;
+        h.E0 = r->E0;
+        char* out = static_cast<char*>(host_buf);
+        std::memcpy(out, &h, sizeof h);
+        const size_t g = sizeof(double2) * (size_t)r->A.nt * r->A.nt * r->A.norb * r->A.norb;
+        char* p = out + sizeof h;
+        KGF_HIP(hipMemcpyAsync(p, r->Gl, g, hipMemcpyDeviceToHost, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(p + g, r->Gg, g, hipMemcpyDeviceToHost, ctx->stream));
+        if (!r->done)
+            KGF_HIP(hipMemcpyAsync(p + 2 * g, r->cur->raw, need - sizeof h - 2 * g, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        kgf::sync(ctx);
+    });
+}
+
+extern "C" int kgf_neq_run_restore(kgf_neq_run* r, const void* host_buf, size_t bytes) {
+    return kgf::abi_guard([&] {
+        KGF_REQUIRE(r && host_buf, KGF_EINVAL, "kgf_neq_run_restore: NULL argument");
+        KGF_REQUIRE(bytes >= sizeof(RunImageHeader), KGF_EINVAL, "kgf_neq_run_restore: image too short");
+        RunImageHeader h;
+        std::memcpy(&h, host_buf, sizeof h);
+        KGF_REQUIRE(h.magic == kRunImageMagic, KGF_EINVAL, "kgf_neq_run_restore: not a run image");
+        KGF_REQUIRE(h.D == r->A.sec->dim() && h.nt == r->A.nt && h.norb == r->A.norb, KGF_EINVAL,
+                    "kgf_neq_run_restore: image of a run with other sizes");
+        KGF_REQUIRE(std::abs(h.E0 - r->E0) <= 1e-12 * std::max(1.0, std::abs(r->E0)), KGF_EINVAL,
+                    "kgf_neq_run_restore: image of a run with another ground state");
+        KGF_REQUIRE(!r->touched, KGF_EINVAL,
+                    "kgf_neq_run_restore: the run has already advanced or been restored (restore into a new run)");
+        KGF_REQUIRE(h.branch >= -1 && h.branch < (int32_t)r->branches.size(), KGF_EINVAL,
+                    "kgf_neq_run_restore: branch out of range");
+        const size_t g = sizeof(double2) * (size_t)r->A.nt * r->A.nt * r->A.norb * r->A.norb;
+        const size_t raw = h.branch >= 0 ? sizeof(double2) * (size_t)r->A.nt * r->A.nt * h.na * h.na : 0;
+        KGF_REQUIRE(bytes >= sizeof h + 2 * g + raw, KGF_EINVAL, "kgf_neq_run_restore: image too short");
+        kgf_ctx* ctx = r->ctx;
+        KGF_HIP(hipSetDevice(ctx->device));
+        RunWorkspaces guard(ctx, r->ws);
+        const char* p = static_cast<const char*>(host_buf) + sizeof h;
+        KGF_HIP(hipMemcpyAsync(r->Gl, p, g, hipMemcpyHostToDevice, ctx->stream));
+        KGF_HIP(hipMemcpyAsync(r->Gg, p + g, g, hipMemcpyHostToDevice, ctx->stream));
+        if (h.branch < 0) {
+            r->cur.reset();
+            r->next = r->branches.size();
+            r->done = true;
+        } else {
+            // begin the saved branch with the saved chunk length, so that its
+            // blocks (and their rounding) are those of the run that was saved
+            KGF_REQUIRE(h.na == (int32_t)r->locs[(size_t)h.branch].size() && h.jchunk >= 1 && h.jhi >= 0 &&
+                            h.jhi < r->A.nt,
+                        KGF_EINVAL, "kgf_neq_run_restore: inconsistent branch state");
+            r->cur.reset();
+            r->next = (size_t)h.branch;
+            const int batch = r->A.batch;
+            r->A.batch = h.jchunk * h.na;
+            const bool ok = run_next_branch(r);
+            r->A.batch = batch;
+            KGF_REQUIRE(ok && (int32_t)r->next - 1 == h.branch, KGF_EINVAL,
+                        "kgf_neq_run_restore: the saved branch has no work in this run");
+            r->cur->jhi = h.jhi;
+            KGF_HIP(hipMemcpyAsync(r->cur->raw, p + 2 * g, raw, hipMemcpyHostToDevice, ctx->stream));
+        }
+        r->vector_steps = h.vector_steps;
+        r->touched = true;
+        kgf::sync(ctx);
     });
 }
 

@@ -11,6 +11,7 @@
 // Hamiltonian.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -157,6 +158,33 @@ int main() {
     KGF_OK_(kgf_neq_run_result(run, Gl2.data(), Gg2.data()));
     kgf_neq_run_destroy(run);
     EXPECT(E0r == E0i);
+    EXPECT(std::memcmp(Gl.data(), Gl2.data(), sizeof(kgf_c128) * ng) == 0);
+    EXPECT(std::memcmp(Gg.data(), Gg2.data(), sizeof(kgf_c128) * ng) == 0);
+
+    // checkpoint between chunks, resume in a new run: the same G bitwise
+    KGF_OK_(kgf_neq_run_create(ctx, Hi, H, sec, &g4, v0, orbs, norb, nt, spg, &p4, 3, &run, &E0r));
+    int moved = 0;
+    do {
+        KGF_OK_(kgf_neq_run_advance(run, 1, &ri));
+        ++moved;
+    } while (!(ri.chunk_start && moved >= 5) && ++guard < 2000);
+    size_t nimg = 0;
+    KGF_OK_(kgf_neq_run_checkpoint(run, nullptr, 0, &nimg));
+    std::vector<char> img(nimg);
+    EXPECT(kgf_neq_run_checkpoint(run, img.data(), nimg - 1, nullptr) == KGF_EINVAL);   // short buffer
+    KGF_OK_(kgf_neq_run_checkpoint(run, img.data(), nimg, &nimg));
+    kgf_neq_run_destroy(run);
+    KGF_OK_(kgf_neq_run_create(ctx, Hi, H, sec, &g4, v0, orbs, norb, nt, spg, &p4, 3, &run, &E0r));
+    EXPECT(kgf_neq_run_restore(run, img.data(), sizeof(int)) == KGF_EINVAL);            // truncated image
+    KGF_OK_(kgf_neq_run_restore(run, img.data(), nimg));
+    EXPECT(kgf_neq_run_restore(run, img.data(), nimg) == KGF_EINVAL);                   // not a new run
+    do {
+        KGF_OK_(kgf_neq_run_advance(run, 1, &ri));
+    } while (!ri.done && ++guard < 3000);
+    std::fill(Gl2.begin(), Gl2.end(), kgf_c128{0.0, 0.0});
+    std::fill(Gg2.begin(), Gg2.end(), kgf_c128{0.0, 0.0});
+    KGF_OK_(kgf_neq_run_result(run, Gl2.data(), Gg2.data()));
+    kgf_neq_run_destroy(run);
     EXPECT(std::memcmp(Gl.data(), Gl2.data(), sizeof(kgf_c128) * ng) == 0);
     EXPECT(std::memcmp(Gg.data(), Gg2.data(), sizeof(kgf_c128) * ng) == 0);
 

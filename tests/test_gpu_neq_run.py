@@ -143,3 +143,62 @@ def test_tuned_sweep_matches_oracle(ctx):
     ref = greens.four_step(Hi, H, 3, 3, orbs, 7, 0.2, 2, 15, v0, reorth="none")
     for key in ("G_lesser", "G_greater"):
         assert rel_err(got[key], ref[key]) < 1e-10, key
+
+
+@pytest.mark.parametrize("batch,stop_after", [(4, 3), (3, 9), (4, 1000), (0, 4)])
+def test_checkpoint_resume_equals_uninterrupted(ctx, batch, stop_after):
+    """Host-spill checkpoint of a run between chunks (after at least
+    `stop_after` intervals, or at the end), resumed in a run created afresh
+    from the same inputs: G^< and G^> bitwise those of the uninterrupted run
+    (which equals kgf_greens_neq and the oracle above); the image is refused
+    inside a chunk, by a run that has advanced and by a run of other sizes."""
+    import paper_1109_1205_amd as k
+    H = wl.chain_siam(6, 2.0)
+    Hi = H.with_field(0, 0.4)
+    orbs = [(0, 0), (2, 0), (1, 1)]
+    nt, spg, dt, m = 7, 2, 0.1, 15
+    s = ctx.sector(6, 3, 3)
+    v0 = to_dev(wl.start_vector(s.dim, 7))
+    mi, mf = ctx.model(Hi), ctx.model(H)
+
+    def new_run(n=nt):
+        return ctx.neq_run(mi, mf, s, v0, orbs, nt=n, steps_per_grid=spg, dt=dt, krylov_dim=m, batch=batch)
+
+    say("checkpoint/resume: uninterrupted run, batch", batch)
+    ref = new_run()
+    while not ref.advance(1)["done"]:
+        pass
+    want = ref.result()
+    ref.close()
+
+    say("checkpoint/resume: saved run")
+    run = new_run()
+    moved, info = 0, {"chunk_start": 1, "done": 0}
+    refused_inside = False
+    while not info["done"]:
+        if not info["chunk_start"] and not refused_inside:
+            with pytest.raises(k.KgfError):
+                run.checkpoint()
+            refused_inside = True
+        if moved >= stop_after and info["chunk_start"]:
+            break
+        info = run.advance(1)
+        moved += 1
+    image = run.checkpoint()
+    run.close()
+
+    say("checkpoint/resume: resumed run after", moved, "intervals,", len(image), "bytes")
+    other = new_run(nt - 1)
+    with pytest.raises(k.KgfError):
+        other.restore(image)
+    other.close()
+    res = new_run()
+    res.restore(image)
+    with pytest.raises(k.KgfError):
+        res.restore(image)
+    while not res.advance(1)["done"]:
+        pass
+    got = res.result()
+    res.close()
+    assert np.array_equal(got["G_lesser"], want["G_lesser"])
+    assert np.array_equal(got["G_greater"], want["G_greater"])
