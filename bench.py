@@ -408,6 +408,15 @@ def ladder16(a):
         nta = a.adj16
         rng = np.random.default_rng(5)
         W = (rng.standard_normal((nta, nta, 1, 1)) + 1j * rng.standard_normal((nta, nta, 1, 1))) / nta
+        # a fresh context: the forward's sweep blocks (sized from free memory)
+        # stay cached in the first one's workspaces
+        ctx.close()
+        torch.cuda.empty_cache()
+        ctx = kgf.Context(0)
+        if a.tune:
+            ctx.set_option(ctx.HV_TUNE, 1)
+        ctx.set_progress(report)
+        s = ctx.sector(16, q.n_up, q.n_dn)
         ctx.set_option(ctx.ADJ_EVERY, 10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -416,6 +425,14 @@ def ladder16(a):
                             gs_max_iter=2000)
         torch.cuda.synchronize()
         t_fw = time.perf_counter() - t0
+        ctx.close()   # again: the plain forward's blocks are sized from free memory too
+        torch.cuda.empty_cache()
+        ctx = kgf.Context(0)
+        if a.tune:
+            ctx.set_option(ctx.HV_TUNE, 1)
+        ctx.set_progress(report)
+        s = ctx.sector(16, q.n_up, q.n_dn)
+        ctx.set_option(ctx.ADJ_EVERY, 10)
         t0 = time.perf_counter()
         g = ctx.greens_neq_vjp(ctx.model(q.H_ini), ctx.model(q.H), s, v0, q.orbitals, nta, spg, q.dt, W_lesser=W,
                                krylov_dim=q.krylov_dim, gs_tol=q.gs_tol, gs_max_iter=2000)
