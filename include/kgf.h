@@ -67,6 +67,11 @@ int  kgf_create(kgf_ctx** out, int hip_device, void* hip_stream);
 void kgf_destroy(kgf_ctx* ctx);
 int  kgf_set_stream(kgf_ctx* ctx, void* hip_stream);
 const char* kgf_last_error(void);
+/* ABI version of this header: incremented whenever a declaration, a struct
+ * layout or the meaning of an argument changes.  kgf_version returns the
+ * version the library was built with; a caller compiled against this header
+ * compares it with KGF_ABI_VERSION before any other call. */
+#define KGF_ABI_VERSION 2
 int  kgf_version(void);
 
 /* ---- model ----------------------------------------------------------------

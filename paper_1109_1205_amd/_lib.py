@@ -14,6 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libkgf.so"
+ABI_VERSION = 2   # KGF_ABI_VERSION of include/kgf.h that the signatures below follow
 
 DIRECTION_FORWARD = -1      # exp(-i H dt)
 DIRECTION_BACKWARD = +1     # exp(+i H dt)
@@ -164,6 +165,9 @@ def load_library():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if L.kgf_version() != ABI_VERSION:
+        raise ImportError(f"{path} has ABI version {L.kgf_version()}, this binding expects {ABI_VERSION}: "
+                          "rebuild it with `python -m paper_1109_1205_amd.build`")
     _lib = L
     return L
 

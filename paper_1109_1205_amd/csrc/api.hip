@@ -231,7 +231,7 @@ SilOpts to_sil_opts(const kgf_prop_opts* o) {
 extern "C" {
 
 const char* kgf_last_error(void) { return g_last_error.c_str(); }
-int kgf_version(void) { return 1; }
+int kgf_version(void) { return KGF_ABI_VERSION; }
 
 int kgf_create(kgf_ctx** out, int hip_device, void* hip_stream) {
     return guarded([&] {

@@ -52,6 +52,7 @@ int main() {
         bj[i] = (i + 1) % L;
     }
     eps_f[0] = 0.3;
+    EXPECT(kgf_version() == KGF_ABI_VERSION);
 
     kgf_ctx* ctx = nullptr;
     KGF_OK_(kgf_create(&ctx, 0, nullptr));

@@ -32,6 +32,17 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libkgf.so not built")
+def test_abi_version_matches_header_and_binding():
+    """kgf_version (no device needed) reports the header's KGF_ABI_VERSION,
+    and the binding loads only a library of the version it was written for."""
+    from paper_1109_1205_amd import _lib
+    m = re.search(r"#define\s+KGF_ABI_VERSION\s+(\d+)", open(HEADER).read())
+    assert m
+    lib = ctypes.CDLL(LIB)
+    assert lib.kgf_version() == int(m.group(1)) == _lib.ABI_VERSION
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libkgf.so not built")
 def test_binding_signatures_cover_header():
     from paper_1109_1205_amd import _lib
     assert set(_lib.exported_symbols()) == set(declared_functions())
