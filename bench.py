@@ -22,9 +22,13 @@ the full G.
 
 value = contour steps/s: single-column SIL steps (each Krylov dim H.v
 products) completed per second in the timed intervals.
-roofline: the Lanczos-fused H.v kernel (the dominant kernel), algorithmic
-bytes per launch = 16 B x D x columns x (2 or 3 vector passes), divided by
-its launch durations measured with HIP events on the library's stream.
+roofline: the Lanczos-form H.v class with the most time (at the production
+width the strip pass of the fused two-pass step, whose algorithmic bytes
+per launch are 16 B x D x columns x (3 or 4 vectors: x_k, z, x_(k-1) in,
+y out); the single pass, 2 or 3 vectors, where one-column launches
+dominate), divided by its launch durations measured with HIP events on the
+library's stream; `traffic` scales those bytes by the committed counter
+summary of that class when it matches the kernel source.
 """
 from __future__ import annotations
 
