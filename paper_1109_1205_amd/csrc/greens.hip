@@ -1695,8 +1695,8 @@ extern "C" int kgf_neq_run_restore(kgf_neq_run* r, const void* host_buf, size_t 
         } else {
             // begin the saved branch with the saved chunk length, so that its
             // blocks (and their rounding) are those of the run that was saved
-            KGF_REQUIRE(h.na == (int32_t)r->locs[(size_t)h.branch].size() && h.jchunk >= 1 && h.jhi >= 0 &&
-                            h.jhi < r->A.nt,
+            KGF_REQUIRE(h.na == (int32_t)r->locs[(size_t)h.branch].size() && h.jchunk >= 1 &&
+                            h.jchunk <= r->A.nt && h.jhi >= 0 && h.jhi < r->A.nt,
                         KGF_EINVAL, "kgf_neq_run_restore: inconsistent branch state");
             r->cur.reset();
             r->next = (size_t)h.branch;
